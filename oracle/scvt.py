@@ -1,0 +1,160 @@
+"""SCVT energy, gradient, Lloyd preconditioner and the preconditioned LBFGS
+loop (oracle).
+
+Test infrastructure only.
+
+Per generator (sections 2.2.1 and 3.1):
+    m_i  = int rho,  mu_i = int y rho  (the paper's c_i),  e_i = int |y-z_i|^2 rho
+    F    = sum_i e_i                                             (CCVT energy)
+    g_i  = 2 (mu_i . z_i) z_i - 2 mu_i          tangential gradient, section 3.1
+    h_i  = 1 / (2 mu_i . z_i)                   spherical Lloyd preconditioner
+    l_i  = mu_i/|mu_i| - z_i                    Lloyd step: the constrained
+                                                centroid (radial projection of
+                                                the mass centroid) minus z_i
+The P-LBFGS direction is the LBFGS two-loop recursion (section 2.2.2) with
+the initial inverse Hessian replaced by diag(h_i) applied to all three
+coordinates of generator i (section 3.1, eq. precStep and the spherical form
+of eq. loyInit).  The line search is the documented reading: Armijo
+backtracking from alpha = 1 (the Lloyd step length, section 3.1), factor 1/2,
+c1 = 1e-4, at most ten evaluations (section 4: ten evaluations, M = 7 by
+default); every trial point is projected back to the sphere (section 3.1).
+"""
+import numpy as np
+
+from . import _clib
+from .voronoi import cells as _cells
+
+
+def dot(a, b):
+    """Dot product of two flattened arrays with numpy's pairwise summation."""
+    return float(np.sum(np.ravel(a) * np.ravel(b)))
+
+
+def normalize_rows(X):
+    return X / np.linalg.norm(X, axis=1)[:, None]
+
+
+def cell_integrals(C, density, levels=2):
+    """m (n,), mu (n,3), e (n,) for the cells C (oracle.voronoi.Cells)."""
+    L = _clib.lib()
+    n = C.n
+    Z = np.ascontiguousarray(C.Z, dtype=np.float64)
+    V = np.ascontiguousarray(C.verts, dtype=np.float64)
+    ptr = np.ascontiguousarray(C.ptr, dtype=np.int64)
+    m = np.zeros(n)
+    mu = np.zeros((n, 3))
+    e = np.zeros(n)
+    D = _clib.cdensity(density)
+    import ctypes
+    rc = L.oracle_cell_integrals(n, _clib.ptr(Z), ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 _clib.ptr(V), ctypes.byref(D), int(levels), _clib.ptr(m),
+                                 _clib.ptr(mu), _clib.ptr(e))
+    assert rc == 0
+    return m, mu, e
+
+
+class Evaluation:
+    """Everything one evaluation at Z produces."""
+
+    def __init__(self, Z, C, m, mu, e):
+        self.Z, self.cells, self.m, self.mu, self.e = Z, C, m, mu, e
+        mz = np.einsum("ij,ij->i", mu, Z)
+        self.F = float(np.sum(e))
+        self.g = 2.0 * mz[:, None] * Z - 2.0 * mu
+        self.h = 1.0 / (2.0 * mz)
+        self.lloyd = mu / np.linalg.norm(mu, axis=1)[:, None] - Z
+        self.step_inf = float(np.max(np.abs(self.lloyd)))
+        self.centroid = mu / m[:, None]
+
+
+def evaluate(Z, density, levels=2):
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    C = _cells(Z)
+    m, mu, e = cell_integrals(C, density, levels)
+    return Evaluation(Z, C, m, mu, e)
+
+
+def two_loop(g, h, hist):
+    """P-LBFGS direction q = -H g (section 2.2.2 two-loop recursion with the
+    initial inverse Hessian replaced by diag(h), section 3.1).
+
+    hist: list of (s, y, r) oldest first, r = 1/(y.s)."""
+    q = -np.array(g, dtype=np.float64)
+    a = [0.0] * len(hist)
+    for j in range(len(hist) - 1, -1, -1):       # backward: newest to oldest
+        s, y, r = hist[j]
+        a[j] = r * dot(s, q)
+        q = q - a[j] * y
+    q = h[:, None] * q                            # q <- H0 q, H0 = diag(h)
+    for j in range(len(hist)):                    # forward: oldest to newest
+        s, y, r = hist[j]
+        b = r * dot(y, q)
+        q = q + (a[j] - b) * s
+    return q
+
+
+class Solver:
+    """Lloyd-preconditioned LBFGS (state machine written out plainly)."""
+
+    def __init__(self, Z0, density, m_hist=7, levels=2, ls_max_evals=10, c1=1e-4,
+                 curv_eps=1e-10):
+        self.density, self.M, self.levels = density, int(m_hist), levels
+        self.ls_max_evals, self.c1, self.curv_eps = ls_max_evals, c1, curv_eps
+        self.cur = evaluate(normalize_rows(np.asarray(Z0, dtype=np.float64)), density, levels)
+        self.hist = []
+        self.iter = 0
+        self.n_evals = 1
+        self.last_alpha = 0.0
+        self.history_F = [self.cur.F]
+
+    @property
+    def Z(self):
+        return self.cur.Z
+
+    def direction(self):
+        return two_loop(self.cur.g, self.cur.h, self.hist)
+
+    def _line_search(self, q, gq):
+        alpha = 1.0
+        for _ in range(self.ls_max_evals):
+            Zt = normalize_rows(self.cur.Z + alpha * q)
+            ev = evaluate(Zt, self.density, self.levels)
+            self.n_evals += 1
+            if ev.F <= self.cur.F + self.c1 * alpha * gq:
+                return alpha, ev
+            alpha *= 0.5
+        return None, None
+
+    def step(self):
+        cur = self.cur
+        q = self.direction()
+        gq = dot(cur.g, q)
+        if gq >= 0.0:                                  # not a descent direction
+            self.hist = []
+            q = -cur.h[:, None] * cur.g
+            gq = dot(cur.g, q)
+        alpha, ev = self._line_search(q, gq)
+        if ev is None and self.hist:                   # reset to the Lloyd step
+            self.hist = []
+            q = -cur.h[:, None] * cur.g
+            gq = dot(cur.g, q)
+            alpha, ev = self._line_search(q, gq)
+        if ev is None:
+            raise RuntimeError("line search failed")
+        s = ev.Z - cur.Z
+        y = ev.g - cur.g
+        ys = dot(y, s)
+        if ys > self.curv_eps * np.sqrt(dot(y, y) * dot(s, s)):
+            self.hist.append((s, y, 1.0 / ys))
+            if len(self.hist) > self.M:
+                self.hist.pop(0)
+        self.cur = ev
+        self.iter += 1
+        self.last_alpha = alpha
+        self.history_F.append(ev.F)
+        return ev
+
+    def solve(self, max_iter, tol):
+        while self.cur.step_inf >= tol and self.iter < max_iter:
+            self.step()
+        return self.cur

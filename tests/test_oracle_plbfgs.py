@@ -1,0 +1,142 @@
+"""Pins for the oracle's optimizer (not the GPU path).
+
+  * the two-loop recursion with H0 = diag(h) equals the dense BFGS matrix
+    built by the product-form update (section 2.2.2; the printed factor
+    S_i = I - rho_i s_i s_i^T is read as the standard I - rho_i y_i s_i^T,
+    the only form that satisfies the secant equation also printed there);
+  * the secant equation H y_newest = s_newest holds;
+  * with no history (M = 0, or the first step) the step is exactly the
+    Lloyd step mu/|mu| (section 3.1: Lloyd direction with step 1);
+  * the analytic gradient 2 m z - 2 mu matches central differences of F
+    along tangent directions (section 2.2.1, dF/dV = 0);
+  * F decreases monotonically under the Armijo line search;
+  * converged uniform-density energy matches the hexagonal (Gersho) constant
+    5/(18 sqrt 3) (int rho^1/2)^2 / n, and the X3 energy matches the paper's
+    Table 1 value within the spread of local minima.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1709_06924_amd.inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense_bfgs(h3, hist):
+    H = np.diag(h3)
+    for s, y, r in hist:                       # oldest to newest
+        V = np.eye(len(s)) - r * np.outer(y, s)
+        H = V.T @ H @ V + r * np.outer(s, s)
+    return H
+
+
+@pytest.mark.parametrize("ngen,M,seed", [(4, 3, 0), (17, 7, 1), (50, 10, 2)])
+def test_two_loop_equals_dense_bfgs(ngen, M, seed):
+    rng = np.random.default_rng(seed)
+    d = 3 * ngen
+    A = rng.standard_normal((d, d))
+    A = A @ A.T + d * np.eye(d)                # SPD model Hessian
+    hist = []
+    for _ in range(M):
+        s = rng.standard_normal(d)
+        y = A @ s
+        hist.append((s.reshape(ngen, 3), y.reshape(ngen, 3), 1.0 / np.dot(y, s)))
+    h = rng.uniform(0.5, 2.0, ngen)
+    g = rng.standard_normal((ngen, 3))
+    q = oracle.two_loop(g, h, hist)
+    H = dense_bfgs(np.repeat(h, 3), [(s.ravel(), y.ravel(), r) for s, y, r in hist])
+    ref = -(H @ g.ravel())
+    assert np.linalg.norm(q.ravel() - ref) <= 1e-13 * np.linalg.norm(ref) * d
+    s, y, r = hist[-1]
+    assert np.allclose(H @ y.ravel(), s.ravel(), rtol=1e-10, atol=1e-12)
+
+
+def test_no_history_is_lloyd_step():
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    Z = I.uniform_sphere(500, 4)
+    for M in (0, 7):
+        S = oracle.Solver(Z, d, m_hist=M)
+        ev0 = S.cur
+        S.step()
+        assert S.last_alpha == 1.0
+        target = ev0.mu / np.linalg.norm(ev0.mu, axis=1)[:, None]
+        assert np.max(np.abs(S.Z - target)) < 1e-14
+        assert np.max(np.abs(S.Z - (ev0.Z + ev0.lloyd))) < 1e-14
+
+
+def test_gradient_matches_finite_differences():
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 4, 0.4, 4)
+    Z = I.uniform_sphere(80, 6)
+    ev = oracle.evaluate(Z, d)
+    rng = np.random.default_rng(0)
+    eps = 1e-5
+    for i in rng.choice(80, 6, replace=False):
+        t = np.cross(Z[i], rng.standard_normal(3))
+        t /= np.linalg.norm(t)
+        Fp = oracle.evaluate(np.vstack([Z[:i], (Z[i] + eps * t) / np.linalg.norm(Z[i] + eps * t), Z[i + 1:]]), d).F
+        Fm = oracle.evaluate(np.vstack([Z[:i], (Z[i] - eps * t) / np.linalg.norm(Z[i] - eps * t), Z[i + 1:]]), d).F
+        fd = (Fp - Fm) / (2 * eps)
+        an = np.dot(ev.g[i], t)
+        assert abs(fd - an) <= 1e-6 * np.linalg.norm(ev.g[i]) + 1e-9 * ev.F
+
+
+def test_tangential_gradient_and_preconditioner_algebra():
+    Z = I.uniform_sphere(300, 8)
+    ev = oracle.evaluate(Z, I.density_x3())
+    # tangential: g_i . z_i = 0; ambient gradient 2 m z - 2 mu projected
+    assert np.max(np.abs(np.einsum("ij,ij->i", ev.g, Z))) < 1e-15
+    G = 2 * ev.m[:, None] * Z - 2 * ev.mu
+    Gt = G - np.einsum("ij,ij->i", G, Z)[:, None] * Z
+    assert np.max(np.abs(Gt - ev.g)) < 1e-15
+    # z - h g = mu / (mu.z), whose projection is the constrained centroid
+    d = Z - ev.h[:, None] * ev.g
+    mz = np.einsum("ij,ij->i", ev.mu, Z)
+    assert np.max(np.abs(d - ev.mu / mz[:, None])) < 1e-12
+
+
+@pytest.mark.parametrize("density", ["const", "tanh"])
+def test_energy_monotone(density):
+    d = {"kind": "const"} if density == "const" else I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    S = oracle.Solver(I.uniform_sphere(400, 9), d, m_hist=7)
+    for _ in range(25):
+        S.step()
+    F = np.array(S.history_F)
+    assert np.all(np.diff(F) <= 0)
+    assert F[-1] < F[0]
+    assert S.n_evals >= S.iter + 1
+
+
+@pytest.mark.slow
+def test_gersho_magnitude_uniform():
+    n = 2562
+    S = oracle.Solver(I.uniform_sphere(n, 1), {"kind": "const"}, m_hist=7)
+    ev = S.solve(250, 1e-10)
+    gersho = 5 / (18 * math.sqrt(3)) * (4 * math.pi) ** 2 / n
+    # Fejes Toth's bound: no n-point configuration beats the hexagonal
+    # constant; a converged SCVT (12 pentagons) sits a little above it
+    assert 1.0 <= ev.F / gersho < 1.012
+    assert ev.step_inf < 1e-3
+
+
+@pytest.mark.slow
+def test_x3_energy_near_paper_table():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_table1_x3.txt"))
+            if l.strip() and not l.startswith("#")][1:]
+    paper = {int(a): float(b) for a, b in rows}
+    n = 2562
+    S = oracle.Solver(I.uniform_sphere(n, 1), I.density_x3(), m_hist=7)
+    ev = S.solve(200, 5e-6)
+    # The printed value sits 2.6% below the hexagonal bound
+    # 5/(18 sqrt 3) (int rho^1/2)^2 / n (a systematic offset of the paper's
+    # numbers, same ratio at both n); our converged energy sits 0.8% above
+    # that bound, as for rho = 1.  The pin is therefore a 5% band.
+    assert abs(ev.F - paper[n]) / paper[n] < 0.05
+    sqrt_mass = 2 * math.pi * sum(  # int rho^1/2 over the sphere, z = cos(theta)
+        math.sqrt((1 - 3.0 ** -4) * z ** 4 + 3.0 ** -4) * w
+        for z, w in zip(*np.polynomial.legendre.leggauss(200)))
+    bound = 5 / (18 * math.sqrt(3)) * sqrt_mass ** 2 / n
+    assert 1.0 <= ev.F / bound < 1.015
