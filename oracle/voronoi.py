@@ -23,23 +23,31 @@ EPS = np.finfo(np.float64).eps
 
 def delaunay(Z):
     """Facets (T,3) of the hull, each oriented counter-clockwise seen from
-    outside: det(z_a, z_b, z_c) > 0."""
+    outside the hull: (z_b - z_a) x (z_c - z_a) is the facet's outward normal
+    (Qhull's facet equations give the outward direction)."""
     Z = np.ascontiguousarray(Z, dtype=np.float64)
     hull = ConvexHull(Z)
     F = hull.simplices.astype(np.int64)
-    d = np.einsum("ij,ij->i", Z[F[:, 0]], np.cross(Z[F[:, 1]], Z[F[:, 2]]))
-    swap = d < 0
+    nrm = np.cross(Z[F[:, 1]] - Z[F[:, 0]], Z[F[:, 2]] - Z[F[:, 0]])
+    swap = np.einsum("ij,ij->i", nrm, hull.equations[:, :3]) < 0
     F[swap, 1], F[swap, 2] = F[swap, 2].copy(), F[swap, 1].copy()
     return F
 
 
 def circumcentres(Z, F):
-    """Voronoi vertex of every facet from its sorted index triple."""
+    """Voronoi vertex of every facet: the circumcentre on the sphere on the
+    empty side of the facet, i.e. along its outward normal.  Computed from the
+    sorted index triple, normalize((z_b-z_a) x (z_c-z_a)) with a<b<c, and
+    signed to agree with the oriented facet's outward normal.  (When the origin
+    is inside the hull this is the sign with v . z_a > 0; when all generators
+    lie in one hemisphere the vertex of the far facet is more than 90 degrees
+    from its generators.)"""
     S = np.sort(F, axis=1)
     za, zb, zc = Z[S[:, 0]], Z[S[:, 1]], Z[S[:, 2]]
     w = np.cross(zb - za, zc - za)
     w /= np.linalg.norm(w, axis=1)[:, None]
-    sgn = np.sign(np.einsum("ij,ij->i", w, za))
+    out = np.cross(Z[F[:, 1]] - Z[F[:, 0]], Z[F[:, 2]] - Z[F[:, 0]])
+    sgn = np.sign(np.einsum("ij,ij->i", w, out))
     sgn[sgn == 0] = 1.0
     return w * sgn[:, None]
 

@@ -41,9 +41,18 @@ def stokes_moment(verts):
     return mu
 
 
-@pytest.mark.parametrize("n,seed", [(5, 0), (9, 1), (17, 2), (31, 3)])
-def test_cells_match_bruteforce_definition(n, seed):
+def hemisphere_points(n, seed):
+    """n points all inside one open hemisphere (origin outside the hull)."""
     Z = I.uniform_sphere(n, seed)
+    Z[:, 2] = np.abs(Z[:, 2]) + 0.05
+    return Z / np.linalg.norm(Z, axis=1)[:, None]
+
+
+@pytest.mark.parametrize("n,seed,hemi", [(5, 0, False), (9, 1, False), (17, 2, False),
+                                         (31, 3, False), (5, 1, False), (6, 4, True),
+                                         (10, 5, True)])
+def test_cells_match_bruteforce_definition(n, seed, hemi):
+    Z = hemisphere_points(n, seed) if hemi else I.uniform_sphere(n, seed)
     C = oracle.cells(Z)
     for i in range(n):
         found = []
