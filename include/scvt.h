@@ -1,0 +1,186 @@
+/*
+ * scvt.h -- C ABI of libscvt.so: the per-iteration hot path of the
+ * Lloyd-preconditioned LBFGS construction of spherical centroidal Voronoi
+ * tessellations (Yang, Gunzburger & Ju, "Fast spherical centroidal Voronoi
+ * mesh generation: a Lloyd-preconditioned LBFGS method in parallel").
+ *
+ * Problem (section 2.1): given generators Z = {z_i} on the unit sphere and a
+ * density rho > 0, minimise the CCVT energy
+ *     F(Z) = sum_i int_{V_i} |y - z_i|^2 rho(y) dsigma(y)
+ * over the spherical Voronoi cells V_i of Z (eq. viInS, Euclidean metric).
+ * One iteration (section 3.1 and the parallel algorithm of section 3.3 on a
+ * single domain):
+ *   1. Voronoi cells of Z (cube-map bucketing, bisector clipping with a
+ *      security-radius certificate, sequential fallback);
+ *   2. per cell: m_i = int rho, mu_i = int y rho (the paper's c_i),
+ *      e_i = int |y - z_i|^2 rho  (fan triangles, geodesic subdivision,
+ *      7-point rule through the radial-projection Jacobian);
+ *   3. g_i = 2 (mu_i . z_i) z_i - 2 mu_i   (tangential gradient),
+ *      h_i = 1 / (2 mu_i . z_i)            (spherical Lloyd preconditioner),
+ *      l_i = mu_i/|mu_i| - z_i             (Lloyd step);
+ *   4. LBFGS two-loop with the initial inverse Hessian diag(h) (section
+ *      2.2.2 with eq. precStep);
+ *   5. Armijo backtracking from alpha = 1 (the Lloyd step length), trial
+ *      points projected back to the sphere; the pair (s, y) is stored when
+ *      y.s > curv_eps |y||s|; at most M pairs are kept (section 4: M = 7).
+ *
+ * Conventions for every call:
+ *   - Arrays of points are row-major n x 3 doubles (x, y, z per generator).
+ *   - A pointer flagged "on_device" is a HIP device pointer on the current
+ *     device; otherwise host memory.  The caller owns every buffer it passes;
+ *     the library copies inputs and never returns memory it allocated.
+ *   - Every call returns an int: 0 = success, > 0 = informational status,
+ *     < 0 = error (see SCVT_E_*).  No C++ exception crosses the ABI.
+ *   - A handle is not thread-safe; separate handles are independent.
+ *   - All device work is ordered on the stream given in scvt_config
+ *     (NULL: the library creates its own stream); calls return after the
+ *     results they report are complete.
+ */
+#ifndef SCVT_H
+#define SCVT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status and error codes */
+#define SCVT_OK 0
+#define SCVT_NOT_CONVERGED 1   /* scvt_solve stopped at max_iter */
+#define SCVT_PENDING 2         /* serving: request not finished yet */
+#define SCVT_E_INVALID -1      /* bad argument (n < 4, non-finite input, ...) */
+#define SCVT_E_OOM -2          /* device allocation failed or over budget */
+#define SCVT_E_DEGENERATE -3   /* duplicate or zero generators */
+#define SCVT_E_CERT -4         /* a Voronoi cell could not be built */
+#define SCVT_E_LINESEARCH -5   /* no sufficient decrease, also after reset */
+#define SCVT_E_NUMERIC -6      /* NaN, or mu_i . z_i <= 0 (h undefined) */
+#define SCVT_E_HIP -7          /* a HIP runtime call failed */
+
+typedef struct scvt_handle scvt_handle;
+
+typedef enum { SCVT_FP64 = 0, SCVT_MIXED = 1 } scvt_precision;
+
+typedef enum {
+  SCVT_RHO_CONST = 0, /* rho = 1 */
+  SCVT_RHO_TANH = 1,  /* rho = gamma + sum_k amp_k (tanh((beta_k - d_k)/alpha_k) + 1)/2 */
+  SCVT_RHO_X3 = 2,    /* rho = (1 - gamma) z^4 + gamma */
+  SCVT_RHO_X16 = 3    /* tanh bump over the anisotropic distance of section 4 */
+} scvt_rho_kind;
+
+/* Density of section 4.  For SCVT_RHO_TANH, d_k = |y - xc_k| (chord) or the
+ * geodesic angle when geodesic != 0; nbumps is 1 or 2.  The printed
+ * prefactor 1/(2(1-gamma)) is read as (1-gamma)/2: pass amp = 1 - gamma for
+ * the paper's single bump.  SCVT_RHO_X16 uses xc[0], beta[0], alpha[0],
+ * amp[0], gamma, w_lon, w_lat. */
+typedef struct {
+  int32_t kind;
+  int32_t geodesic;
+  int32_t nbumps;
+  int32_t reserved;
+  double xc[2][3];
+  double beta[2];
+  double alpha[2];
+  double amp[2];
+  double gamma;
+  double w_lon, w_lat;
+} scvt_density;
+
+typedef struct {
+  int64_t n;            /* number of generators (>= 4) */
+  int32_t m_hist;       /* M, stored LBFGS pairs (0 = Lloyd iteration) */
+  int32_t precision;    /* scvt_precision */
+  scvt_density rho;
+  int32_t quad_levels;  /* geodesic subdivision levels per fan triangle (0..3, default 2) */
+  int32_t ls_max_evals; /* energy evaluations per line search (default 10) */
+  double ls_c1;         /* Armijo constant (default 1e-4) */
+  double curv_eps;      /* store (s,y) only if y.s > curv_eps |y||s| (default 1e-10) */
+  int32_t keep_cells;   /* 1: keep a copy of every cell for scvt_get_cells */
+  int32_t reserved;
+  void* hip_stream;     /* hipStream_t to order work on, or NULL */
+} scvt_config;
+
+/* Per-iteration record; the columns of the paper's tables (section 4). */
+typedef struct {
+  int64_t iter;         /* iterations done */
+  int64_t n_evals;      /* energy evaluations done (incl. the initial one) */
+  double F;             /* energy at the current generators */
+  double grad_norm2;    /* |g|_2 */
+  double step_inf;      /* max_i,k |l_ik| (Lloyd step, the stopping measure) */
+  double alpha;         /* accepted step length of the last iteration */
+  int64_t n_fallback;   /* cells built by the fallback clipper, last evaluation */
+  int64_t n_degenerate; /* cells with a predicate inside its error bound */
+  int32_t status;       /* last return code */
+  int32_t hist_len;     /* stored pairs */
+} scvt_info;
+
+/* Fill *cfg with defaults for n generators: M = 7, FP64, rho = 1,
+ * 2 subdivision levels, 10 evaluations per line search, c1 = 1e-4,
+ * curv_eps = 1e-10, no cell copy, NULL stream. */
+int scvt_config_init(scvt_config* cfg, int64_t n);
+
+/* Create a solver.  z0: n x 3 (host, or device if z0_on_device); rows are
+ * normalised to the unit sphere.  Allocates all device state, builds the
+ * cells of z0 and evaluates F, g, h and the Lloyd step (iteration 0 ready).
+ * Errors: SCVT_E_INVALID (n < 4, bad config, non-finite z0), SCVT_E_OOM,
+ * SCVT_E_DEGENERATE (zero row), SCVT_E_CERT, SCVT_E_NUMERIC, SCVT_E_HIP.
+ * *out is NULL on error. */
+int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt_handle** out);
+
+/* One P-LBFGS iteration (two-loop direction, descent check with reset to the
+ * Lloyd direction, Armijo line search, history update).  info may be NULL. */
+int scvt_step(scvt_handle* h, scvt_info* info);
+
+/* Iterate until step_inf < tol_step_inf or max_iter iterations in total.
+ * Returns SCVT_OK when converged, SCVT_NOT_CONVERGED at the cap, or an error. */
+int scvt_solve(scvt_handle* h, int64_t max_iter, double tol_step_inf, scvt_info* info);
+
+/* Cached results at the current generators (no recomputation): F, and
+ * optionally per cell mass (n), centroid mu_i/m_i (n x 3) and energy e_i (n).
+ * Any output pointer may be NULL. */
+int scvt_energy(scvt_handle* h, double* F, double* mass, double* centroid, double* e_cell,
+                int out_on_device);
+
+/* Current generators, n x 3. */
+int scvt_get_generators(scvt_handle* h, double* z, int on_device);
+
+/* Per-generator vectors at the current generators (parity and debugging):
+ * which = 0 gradient g (n x 3), 1 preconditioner h (n), 2 Lloyd step l
+ * (n x 3), 3 first moment mu (n x 3), 4 the last search direction q (n x 3),
+ * 5 cell circumradius (n). */
+int scvt_get_vectors(scvt_handle* h, int which, double* out, int on_device);
+
+/* Compute the P-LBFGS direction at the current state into out (n x 3),
+ * without stepping; *gq receives g . q (may be NULL). */
+int scvt_direction(scvt_handle* h, double* out, int on_device, double* gq);
+
+/* Voronoi cells at the current generators (requires keep_cells = 1).
+ * max_deg must be 32.  nbr: n x 32 neighbour ids sorted ascending, -1 padded;
+ * deg: n; verts: n x 32 x 6, edge k of cell i runs counter-clockwise (seen
+ * from outside) from verts[i][k][0:3] to verts[i][k][3:6] on the bisector of
+ * i and nbr[i][k]; flags: n, bit 1 fallback-built, 2 near-degenerate,
+ * 4 error, 8 brute-force search.  Any output may be NULL.  Host memory. */
+int scvt_get_cells(scvt_handle* h, int32_t max_deg, int32_t* nbr, int32_t* deg, double* verts,
+                   uint8_t* flags);
+
+/* Checkpoint: serialise (Z, history ring, counters) into buf.  With buf ==
+ * NULL, *bytes receives the size needed.  scvt_set_state restores a state
+ * produced by a handle with the same n and M and re-evaluates at Z. */
+int scvt_get_state(scvt_handle* h, void* buf, size_t* bytes);
+int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes);
+
+/* Kernel timing (HIP events on the handle's stream, enabled by
+ * scvt_set_timing): kernel 0 = cell kernel (certified path), 1 = fallback
+ * kernel, 2 = grid build, 3 = two-loop passes, 4 = whole evaluation.
+ * Returns accumulated milliseconds and launch count since enabling. */
+int scvt_set_timing(scvt_handle* h, int enable);
+int scvt_kernel_time(scvt_handle* h, int kernel, double* total_ms, int64_t* launches);
+
+void scvt_destroy(scvt_handle* h);
+const char* scvt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCVT_H */

@@ -18,5 +18,6 @@ fixes; both sides implement the same ones.  Converged meshes beyond the
 energy statistics are unpinned too (the energy has many local minima).
 """
 from ._clib import build  # noqa: F401
-from .scvt import Evaluation, Solver, cell_integrals, dot, evaluate, normalize_rows, two_loop  # noqa: F401
+from .scvt import (Evaluation, Solver, cell_integrals, dot, evaluate, local_cell,  # noqa: F401
+                   normalize_rows, two_loop)
 from .voronoi import cells, circumcentres, delaunay, neighbour_sets  # noqa: F401

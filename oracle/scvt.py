@@ -37,7 +37,7 @@ def normalize_rows(X):
 def cell_integrals(C, density, levels=2):
     """m (n,), mu (n,3), e (n,) for the cells C (oracle.voronoi.Cells)."""
     L = _clib.lib()
-    n = C.n
+    n = len(C.ptr) - 1
     Z = np.ascontiguousarray(C.Z, dtype=np.float64)
     V = np.ascontiguousarray(C.verts, dtype=np.float64)
     ptr = np.ascontiguousarray(C.ptr, dtype=np.int64)
@@ -158,3 +158,35 @@ class Solver:
         while self.cur.step_inf >= tol and self.iter < max_iter:
             self.step()
         return self.cur
+
+
+def local_cell(Z, i, density, radius, levels=2):
+    """Cell i and its integrals from the generators within chord `radius` of
+    z_i only (for sampled checks at sizes where the global hull is slow).
+
+    The cell of z_i is decided by the generators closer than 2R_i (R_i its
+    circumradius): a generator farther than that cannot be nearer than z_i
+    to any point of the cell.  Raises if 2R_i >= radius.  Returns
+    (neighbour ids, vertices (deg,3) counter-clockwise, m, mu, e)."""
+    from .voronoi import cells as _c
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    d = np.linalg.norm(Z - Z[i], axis=1)
+    sub = np.where(d < radius)[0]
+    C = _c(Z[sub])
+    k = int(np.where(sub == i)[0][0])
+    verts = C.verts[C.ptr[k]:C.ptr[k + 1]]
+    R = np.max(np.linalg.norm(verts - Z[i], axis=1))
+    if not 2 * R < radius:
+        raise ValueError("radius too small for cell %d" % i)
+    # neighbour on the edge from vertex t to t+1: the facet pair's common index
+    fac = C.fac[C.ptr[k]:C.ptr[k + 1]]
+    nb = []
+    for t in range(len(fac)):
+        common = (set(C.F[fac[t]]) & set(C.F[fac[(t + 1) % len(fac)]])) - {k}
+        nb.append(int(sub[common.pop()]))
+    one = type(C).__new__(type(C))
+    one.Z = Z[i:i + 1]
+    one.ptr = np.array([0, len(verts)], dtype=np.int64)
+    one.verts = np.ascontiguousarray(verts)
+    m, mu, e = cell_integrals(one, density, levels)
+    return nb, verts, m[0], mu[0], e[0]

@@ -1,0 +1,597 @@
+// Geometry, predicates, density and quadrature shared by the HIP kernels.
+//
+// Everything here is __host__ __device__ so that the same code can be run on
+// the host for the library's CPU self-checks; the kernels in cells.hip call it
+// from wave-level drivers.
+//
+// Problem (Yang, Gunzburger & Ju, section 2.1): the spherical Voronoi cell of
+// generator z is {x on S^2 : |x - z| < |x - p| for every other generator p}
+// (eq. viInS, Euclidean metric).  On the unit sphere the condition for one p is
+// the half-space x . (z - p) >= 0 bounded by a great circle (the bisector).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#define SCVT_HD __host__ __device__ inline
+
+namespace scvt {
+
+// ------------------------------------------------------------------ vectors
+struct V3 {
+  double x, y, z;
+};
+SCVT_HD V3 mk(double x, double y, double z) { return V3{x, y, z}; }
+SCVT_HD V3 operator+(V3 a, V3 b) { return V3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+SCVT_HD V3 operator-(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+SCVT_HD V3 operator-(V3 a) { return V3{-a.x, -a.y, -a.z}; }
+SCVT_HD V3 operator*(double s, V3 a) { return V3{s * a.x, s * a.y, s * a.z}; }
+SCVT_HD double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+SCVT_HD V3 cross(V3 a, V3 b) {
+  return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+SCVT_HD V3 normalized(V3 a) {
+  double r = sqrt(dot(a, a));
+  return V3{a.x / r, a.y / r, a.z / r};
+}
+
+// unit round-off of binary64
+constexpr double kU = 1.1102230246251565e-16;
+
+// ------------------------------------------------------------- predicates
+// det(a, b, c) with a first-order forward error bound.  The inputs are
+// themselves rounded differences of generator positions (one rounding each);
+// the 2x2 products, minor subtractions, outer products and the final sum add
+// at most six more roundings relative to the permanent (same expression with
+// absolute values).  Nine roundings; the bound uses 16u.
+struct Pred {
+  double v, err;
+};
+SCVT_HD Pred det_pred(V3 a, V3 b, V3 c) {
+  double m0 = b.y * c.z - b.z * c.y;
+  double m1 = b.z * c.x - b.x * c.z;
+  double m2 = b.x * c.y - b.y * c.x;
+  double p0 = fabs(b.y * c.z) + fabs(b.z * c.y);
+  double p1 = fabs(b.z * c.x) + fabs(b.x * c.z);
+  double p2 = fabs(b.x * c.y) + fabs(b.y * c.x);
+  Pred r;
+  r.v = a.x * m0 + a.y * m1 + a.z * m2;
+  r.err = 16.0 * kU * (fabs(a.x) * p0 + fabs(a.y) * p1 + fabs(a.z) * p2);
+  return r;
+}
+
+// Cached cross product d_j x d_b with its minor permanents, so that
+// det(d_j, d_b, d_l) = d_l . c costs three multiply-adds per candidate l.
+struct CrossCache {
+  V3 c, perm;
+};
+SCVT_HD CrossCache make_cross(V3 a, V3 b) {
+  CrossCache k;
+  k.c = cross(a, b);
+  k.perm = V3{fabs(a.y * b.z) + fabs(a.z * b.y), fabs(a.z * b.x) + fabs(a.x * b.z),
+              fabs(a.x * b.y) + fabs(a.y * b.x)};
+  return k;
+}
+SCVT_HD Pred det_cached(const CrossCache& k, V3 l) {
+  Pred r;
+  r.v = dot(l, k.c);
+  r.err = 16.0 * kU * (fabs(l.x) * k.perm.x + fabs(l.y) * k.perm.y + fabs(l.z) * k.perm.z);
+  return r;
+}
+
+// --------------------------------------------------- circumcentre (vertex)
+// Voronoi vertex shared by generators a, b, c: the point of the sphere
+// equidistant from all three, on their side.  Computed from the triple in
+// increasing index order so that every cell that meets at the vertex gets the
+// same bits: normalize((p_b - p_a) x (p_c - p_a)), signed so that v . p_a > 0.
+SCVT_HD V3 circumcentre(int ia, V3 pa, int ib, V3 pb, int ic, V3 pc) {
+  if (ia > ib) {
+    int t = ia; ia = ib; ib = t;
+    V3 s = pa; pa = pb; pb = s;
+  }
+  if (ib > ic) {
+    int t = ib; ib = ic; ic = t;
+    V3 s = pb; pb = pc; pc = s;
+  }
+  if (ia > ib) {
+    int t = ia; ia = ib; ib = t;
+    V3 s = pa; pa = pb; pb = s;
+  }
+  V3 w = normalized(cross(pb - pa, pc - pa));
+  if (dot(w, pa) < 0.0) w = -w;
+  return w;
+}
+
+// ------------------------------------------ edge of the cell on one bisector
+// Candidate set S (positions p_l and differences d_l = p_l - z).  In the
+// gnomonic chart at z every bisector is a straight line and the cell is the
+// convex polygon of the half-planes containing z.  For the line of candidate
+// j, every other candidate l bounds it from one side; the sign of
+// sigma_jl = det(z, d_j, d_l) says which (> 0: an upper bound in the
+// counter-clockwise direction).  Two bounds l, m of the same kind are ordered
+// by the in-circle determinant det(d_j, d_l, d_m) (its sign says whether the
+// vertex (j,l) lies inside the half-space of m).  The edge on line j runs from
+// the tightest lower bound `lo` to the tightest upper bound `hi`, counter-
+// clockwise seen from outside the sphere, and exists if lo < hi.
+enum EdgeStatus { kEdgeNone = 0, kEdgeYes = 1, kEdgeUnbounded = 2, kEdgeDegenerate = 3 };
+struct EdgeRes {
+  int status, lo, hi;
+};
+
+struct CandView {  // structure-of-arrays view (LDS on the device)
+  const double *px, *py, *pz, *dx, *dy, *dz;
+  SCVT_HD V3 p(int l) const { return V3{px[l], py[l], pz[l]}; }
+  SCVT_HD V3 d(int l) const { return V3{dx[l], dy[l], dz[l]}; }
+};
+
+SCVT_HD EdgeRes edge_on_bisector(int j, int ns, V3 z, const CandView& S) {
+  const V3 dj = S.d(j), pj = S.p(j);
+  int lo = -1, hi = -1;
+  CrossCache clo{}, chi{};
+  bool degenerate = false;
+  for (int l = 0; l < ns; l++) {
+    if (l == j) continue;
+    const V3 dl = S.d(l);
+    Pred sg = det_pred(z, dj, dl);
+    if (fabs(sg.v) <= sg.err) {
+      // lines (nearly) parallel in the chart: line l either leaves all of
+      // line j feasible or none of it; decided at the foot of line j by the
+      // sign of d_l . (p_l - p_j)
+      V3 pl = S.p(l), dd = pl - pj;
+      double s = dot(dl, dd);
+      double se = 16.0 * kU * (fabs(dl.x * dd.x) + fabs(dl.y * dd.y) + fabs(dl.z * dd.z));
+      if (s > se) continue;
+      if (s < -se) return EdgeRes{kEdgeNone, -1, -1};
+      degenerate = true;
+      continue;
+    }
+    if (sg.v > 0.0) {
+      if (hi < 0) {
+        hi = l;
+        chi = make_cross(dj, dl);
+      } else {
+        Pred o = det_cached(chi, dl);  // det(d_j, d_hi, d_l)
+        if (fabs(o.v) <= o.err) {
+          degenerate = true;
+        } else if (o.v > 0.0) {  // vertex (j,hi) violates l: l is tighter
+          hi = l;
+          chi = make_cross(dj, dl);
+        }
+      }
+    } else {
+      if (lo < 0) {
+        lo = l;
+        clo = make_cross(dj, dl);
+      } else {
+        Pred o = det_cached(clo, dl);  // det(d_j, d_lo, d_l)
+        if (fabs(o.v) <= o.err) {
+          degenerate = true;
+        } else if (o.v < 0.0) {
+          lo = l;
+          clo = make_cross(dj, dl);
+        }
+      }
+    }
+  }
+  if (degenerate) return EdgeRes{kEdgeDegenerate, lo, hi};
+  if (lo < 0 || hi < 0) return EdgeRes{kEdgeUnbounded, lo, hi};
+  Pred o = det_cached(clo, S.d(hi));  // det(d_j, d_lo, d_hi) > 0  <=>  lo < hi
+  if (fabs(o.v) <= o.err) return EdgeRes{kEdgeDegenerate, lo, hi};
+  return EdgeRes{o.v > 0.0 ? kEdgeYes : kEdgeNone, lo, hi};
+}
+
+// ------------------------------------------------------------- densities
+enum RhoKind { kRhoConst = 0, kRhoTanh = 1, kRhoX3 = 2, kRhoX16 = 3 };
+struct DensityP {
+  int32_t kind, geodesic, nbumps, pad;
+  double xc[2][3];
+  double beta[2], alpha[2], amp[2];
+  double gamma, w_lon, w_lat;
+};
+
+SCVT_HD double chord_to_angle(double ch) {
+  double s = 0.5 * ch;
+  return 2.0 * asin(s > 1.0 ? 1.0 : s);
+}
+
+// Densities of section 4: constant; tanh bumps
+//   rho = gamma + sum_k amp_k (tanh((beta_k - d_k)/alpha_k) + 1)/2
+// (the printed prefactor 1/(2(1-gamma)) is read as (1-gamma)/2 so that rho
+// spans [gamma, 1]); X3 = (1-gamma) z^4 + gamma; X16 with the anisotropic
+// distance built from the latitude/longitude-swapped points.
+SCVT_HD double rho_eval(const DensityP& D, V3 y) {
+  if (D.kind == kRhoConst) return 1.0;
+  if (D.kind == kRhoTanh) {
+    double rho = D.gamma;
+    for (int k = 0; k < D.nbumps; k++) {
+      V3 c = V3{D.xc[k][0], D.xc[k][1], D.xc[k][2]};
+      V3 t = y - c;
+      double d = sqrt(dot(t, t));
+      if (D.geodesic) d = chord_to_angle(d);
+      rho += D.amp[k] * 0.5 * (tanh((D.beta[k] - d) / D.alpha[k]) + 1.0);
+    }
+    return rho;
+  }
+  if (D.kind == kRhoX3) {
+    double z2 = y.z * y.z;
+    return (1.0 - D.gamma) * z2 * z2 + D.gamma;
+  }
+  // X16
+  double sz = y.z > 1.0 ? 1.0 : (y.z < -1.0 ? -1.0 : y.z);
+  double la = asin(sz), lo = atan2(y.y, y.x);
+  double czc = D.xc[0][2] > 1.0 ? 1.0 : (D.xc[0][2] < -1.0 ? -1.0 : D.xc[0][2]);
+  double lac = asin(czc), loc = atan2(D.xc[0][1], D.xc[0][0]);
+  V3 zic = V3{cos(la) * cos(loc), cos(la) * sin(loc), sin(la)};
+  V3 zci = V3{cos(lac) * cos(lo), cos(lac) * sin(lo), sin(lac)};
+  V3 t1 = y - zic, t2 = y - zci;
+  double d1 = chord_to_angle(sqrt(dot(t1, t1)));
+  double d2 = chord_to_angle(sqrt(dot(t2, t2)));
+  double d = sqrt(d1 * d1 / (D.w_lon * D.w_lon) + d2 * d2 / (D.w_lat * D.w_lat));
+  return D.amp[0] * 0.5 * (tanh((D.beta[0] - d) / D.alpha[0]) + 1.0) + D.gamma;
+}
+
+// ------------------------------------------------------------- quadrature
+// Radon's 7-point degree-5 rule (Stroud T2:5-1), barycentric, weights sum to 1.
+struct Rule7 {
+  double l[7][3], w[7];
+};
+SCVT_HD Rule7 rule7() {
+  const double a1 = 0.10128650732345634, a2 = 0.4701420641051151;
+  const double w1 = 0.12593918054482714, w2 = 0.1323941527885062;
+  const double b1 = 1.0 - 2.0 * a1, b2 = 1.0 - 2.0 * a2, t = 1.0 / 3.0;
+  Rule7 r = {{{t, t, t}, {b1, a1, a1}, {a1, b1, a1}, {a1, a1, b1},
+              {b2, a2, a2}, {a2, b2, a2}, {a2, a2, b2}},
+             {9.0 / 40.0, w1, w1, w1, w2, w2, w2}};
+  return r;
+}
+
+struct Acc5 {
+  double m, mx, my, mz, e;
+};
+
+// Radial projection of the flat triangle (A,B,C) onto the sphere has Jacobian
+// (n.p)/|p|^3 with n.p constant = det(A,B,C)/(2 area), so
+//   int_sph f dsigma = det(A,B,C)/2 * sum_q w_q f(p_q/|p_q|) / |p_q|^3.
+SCVT_HD void quad_tri(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
+  const Rule7 R = rule7();
+  const double hd = 0.5 * dot(A, cross(B, C));
+  for (int q = 0; q < 7; q++) {
+    V3 p = R.l[q][0] * A + R.l[q][1] * B + R.l[q][2] * C;
+    double r2 = dot(p, p);
+    double r = sqrt(r2);
+    double ri = 1.0 / r;
+    V3 y = ri * p;
+    double jac = ri * ri * ri;
+    double wt = hd * R.w[q] * jac * rho_eval(D, y);
+    V3 dy = y - z;
+    acc.m += wt;
+    acc.mx += wt * y.x;
+    acc.my += wt * y.y;
+    acc.mz += wt * y.z;
+    acc.e += wt * dot(dy, dy);
+  }
+}
+
+// Leaf `s` (base-4 digits, most significant first) of `levels` geodesic
+// midpoint subdivisions of (A,B,C): children (A,ab,ca), (ab,B,bc), (ca,bc,C),
+// (ab,bc,ca), midpoints normalize(a+b).
+SCVT_HD void subtriangle(V3& A, V3& B, V3& C, int s, int levels) {
+  for (int lv = levels - 1; lv >= 0; lv--) {
+    int k = (s >> (2 * lv)) & 3;
+    V3 ab = normalized(A + B), bc = normalized(B + C), ca = normalized(C + A);
+    if (k == 0) {
+      B = ab; C = ca;
+    } else if (k == 1) {
+      A = ab; C = bc;
+    } else if (k == 2) {
+      A = ca; B = bc;
+    } else {
+      A = ab; B = bc; C = ca;
+    }
+  }
+}
+
+// ------------------------------------------------------------ cube-map grid
+// Each face f = 2k + (sign<0) of the cube [-1,1]^3 carries an equiangular
+// W x W grid, W = G + 2B: G cells span the face proper, B extra cells on each
+// side hold copies ("ghosts") of generators of the neighbouring faces, so
+// that a search window around any generator stays on its own face.
+struct GridP {
+  int G, B, W;
+  int pad;
+  double delta, inv_delta, a0;  // cell angle, its inverse, angle of column 0
+  int64_t ncells;               // 6 W^2
+};
+
+SCVT_HD int home_face(V3 p) {
+  double ax = fabs(p.x), ay = fabs(p.y), az = fabs(p.z);
+  if (ax >= ay && ax >= az) return p.x >= 0.0 ? 0 : 1;
+  if (ay >= az) return p.y >= 0.0 ? 2 : 3;
+  return p.z >= 0.0 ? 4 : 5;
+}
+
+// depth along the face normal and the two in-face coordinates (unscaled)
+SCVT_HD void face_local(V3 p, int f, double& n, double& u, double& v) {
+  int k = f >> 1;
+  double s = (f & 1) ? -1.0 : 1.0;
+  double c[3] = {p.x, p.y, p.z};
+  n = s * c[k];
+  u = c[(k + 1) % 3];
+  v = c[(k + 2) % 3];
+}
+
+SCVT_HD int64_t cell_of(const GridP& g, int f, int ia, int ib) {
+  return (int64_t)f * g.W * g.W + (int64_t)ib * g.W + ia;
+}
+
+// cell of p on face f, or -1 if p is outside that face's extended grid
+SCVT_HD int64_t cell_on_face(const GridP& g, V3 p, int f) {
+  double n, u, v;
+  face_local(p, f, n, u, v);
+  if (!(n > 0.0)) return -1;
+  double a = atan(u / n), b = atan(v / n);
+  double fa = floor((a - g.a0) * g.inv_delta), fb = floor((b - g.a0) * g.inv_delta);
+  if (fa < 0.0 || fb < 0.0 || fa >= (double)g.W || fb >= (double)g.W) return -1;
+  return cell_of(g, f, (int)fa, (int)fb);
+}
+
+// A rectangle of cells on face f and the chord radius D around z inside
+// which every generator of the sphere is stored in the rectangle.
+struct Window {
+  int f, ia_lo, ia_hi, ib_lo, ib_hi;
+  double D;
+};
+
+// Smallest window around z (face f = home face) that covers the chord
+// radius rt (clamped to the grid and to at most maxw cells a side), and the
+// certified radius D of the window actually chosen.  The window's sides are
+// great circles (planes through the origin containing a face axis), so the
+// angular distance from z to a side is asin of z's signed distance to that
+// plane; points outside the face's extended grid lie beyond its outer sides
+// or behind the face (distance asin(depth)).
+SCVT_HD Window make_window(const GridP& g, V3 z, int f, double rt, int maxw) {
+  double n, u, v;
+  face_local(z, f, n, u, v);
+  double az = atan(u / n), bz = atan(v / n);
+  double half = 0.5 * rt;
+  double th = 2.0 * asin(half > 1.0 ? 1.0 : half);
+  double sth = th >= 1.5707963267948966 ? 1.0 : sin(th);
+  double ru = sqrt(n * n + u * u), rv = sqrt(n * n + v * v);
+  double da = sth >= ru ? 1.5707963267948966 : asin(sth / ru);
+  double db = sth >= rv ? 1.5707963267948966 : asin(sth / rv);
+  int ca = (int)floor((az - g.a0) * g.inv_delta), cb = (int)floor((bz - g.a0) * g.inv_delta);
+  ca = ca < 0 ? 0 : (ca >= g.W ? g.W - 1 : ca);
+  cb = cb < 0 ? 0 : (cb >= g.W ? g.W - 1 : cb);
+  double fl = floor((az - da - g.a0) * g.inv_delta), fh = floor((az + da - g.a0) * g.inv_delta);
+  double gl = floor((bz - db - g.a0) * g.inv_delta), gh = floor((bz + db - g.a0) * g.inv_delta);
+  const int half_max = (maxw - 1) / 2;
+  int ia_lo = fl < (double)(ca - half_max) ? ca - half_max : (int)fl;
+  int ia_hi = fh > (double)(ca + half_max) ? ca + half_max : (int)fh;
+  int ib_lo = gl < (double)(cb - half_max) ? cb - half_max : (int)gl;
+  int ib_hi = gh > (double)(cb + half_max) ? cb + half_max : (int)gh;
+  if (ia_lo < 0) ia_lo = 0;
+  if (ib_lo < 0) ib_lo = 0;
+  if (ia_hi > g.W - 1) ia_hi = g.W - 1;
+  if (ib_hi > g.W - 1) ib_hi = g.W - 1;
+  if (ia_lo > ca) ia_lo = ca;
+  if (ia_hi < ca) ia_hi = ca;
+  if (ib_lo > cb) ib_lo = cb;
+  if (ib_hi < cb) ib_hi = cb;
+  // signed distances (sines of angular distance) to the four sides
+  double alo = g.a0 + ia_lo * g.delta, ahi = g.a0 + (ia_hi + 1) * g.delta;
+  double blo = g.a0 + ib_lo * g.delta, bhi = g.a0 + (ib_hi + 1) * g.delta;
+  double s1 = cos(alo) * u - sin(alo) * n;
+  double s2 = sin(ahi) * n - cos(ahi) * u;
+  double s3 = cos(blo) * v - sin(blo) * n;
+  double s4 = sin(bhi) * n - cos(bhi) * v;
+  double sm = n;
+  sm = s1 < sm ? s1 : sm;
+  sm = s2 < sm ? s2 : sm;
+  sm = s3 < sm ? s3 : sm;
+  sm = s4 < sm ? s4 : sm;
+  double ang = sm <= 0.0 ? 0.0 : asin(sm > 1.0 ? 1.0 : sm) - 1e-12;
+  Window w;
+  w.f = f;
+  w.ia_lo = ia_lo;
+  w.ia_hi = ia_hi;
+  w.ib_lo = ib_lo;
+  w.ib_hi = ib_hi;
+  w.D = ang <= 0.0 ? 0.0 : 2.0 * sin(0.5 * ang);
+  return w;
+}
+
+// ---------------------------------------------- sequential spherical clipper
+// Fallback construction of one cell: Sutherland-Hodgman clipping of a convex
+// spherical polygon by the half-spaces x . (z - p) >= 0, in any order.  The
+// first candidate's hemisphere is the starting polygon (four vertices on its
+// circle); edges longer than 90 degrees get a midpoint on their own circle so
+// that every arc stays below 180 degrees.  Each polygon slot holds a vertex
+// and the generator whose bisector carries the outgoing edge; a vertex is a
+// Voronoi vertex where consecutive edges change generator.  Works for any
+// cell the sphere allows (also cells beyond a hemisphere, small n).
+constexpr int kClipMax = 64;
+struct ClipPoly {
+  double P[2][kClipMax][3];   // vertices
+  double EP[2][kClipMax][3];  // position of the outgoing edge's generator
+  int32_t ec[2][kClipMax];    // id of that generator
+  int32_t K[2];
+  int32_t cur, err, degen, pad;
+  double R;  // bound on |x - z| over the polygon (2 when unknown)
+};
+
+SCVT_HD V3 cp_get(const double (*A)[3], int k) { return V3{A[k][0], A[k][1], A[k][2]}; }
+SCVT_HD void cp_set(double (*A)[3], int k, V3 v) {
+  A[k][0] = v.x;
+  A[k][1] = v.y;
+  A[k][2] = v.z;
+}
+
+SCVT_HD void clip_reset(ClipPoly& C) {
+  C.cur = 0;
+  C.K[0] = C.K[1] = 0;
+  C.err = C.degen = 0;
+  C.R = 2.0;
+}
+
+// bound: max vertex distance if the polygon lies in z's open hemisphere (then
+// the farthest point is a vertex: along an arc inside that hemisphere x.z is
+// concave), else 2
+SCVT_HD void clip_update_R(ClipPoly& C, V3 z) {
+  const int b = C.cur, K = C.K[b];
+  double r2 = 0.0;
+  bool hemi = K > 0;
+  for (int k = 0; k < K; k++) {
+    V3 P = cp_get(C.P[b], k);
+    if (!(dot(P, z) > 0.0)) hemi = false;
+    V3 d = P - z;
+    r2 = fmax(r2, dot(d, d));
+  }
+  C.R = hemi ? sqrt(r2) : 2.0;
+}
+
+SCVT_HD void clip_init(ClipPoly& C, V3 z, int j, V3 pj) {
+  V3 N = normalized(z - pj);
+  V3 ax = fabs(N.x) < 0.6 ? V3{1, 0, 0} : (fabs(N.y) < 0.6 ? V3{0, 1, 0} : V3{0, 0, 1});
+  V3 u1 = normalized(cross(N, ax));
+  V3 u2 = normalized(cross(N, u1));
+  C.cur = 0;
+  C.K[0] = 4;
+  V3 v[4] = {u1, u2, -u1, -u2};
+  for (int k = 0; k < 4; k++) {
+    cp_set(C.P[0], k, v[k]);
+    cp_set(C.EP[0], k, pj);
+    C.ec[0][k] = j;
+  }
+}
+
+SCVT_HD void clip_by(ClipPoly& C, V3 z, int m, V3 pm) {
+  const int b = C.cur, nb = 1 - b, K = C.K[b];
+  for (int k = 0; k < K; k++)
+    if (C.ec[b][k] == m) return;  // already an edge of the polygon
+  const V3 N = z - pm;
+  double s[kClipMax];
+  bool any_out = false;
+  for (int k = 0; k < K; k++) {
+    V3 P = cp_get(C.P[b], k);
+    s[k] = dot(P, N);
+    double err = 8.0 * kU * (fabs(P.x * N.x) + fabs(P.y * N.y) + fabs(P.z * N.z));
+    if (fabs(s[k]) <= err) C.degen = 1;
+    if (s[k] < 0.0) any_out = true;
+  }
+  if (!any_out) return;
+  int c = 0;
+  for (int k = 0; k < K; k++) {
+    if (c > kClipMax - 2) {
+      C.err = 1;
+      break;
+    }
+    int k1 = (k + 1) % K;
+    V3 P = cp_get(C.P[b], k), Q = cp_get(C.P[b], k1);
+    bool inP = s[k] >= 0.0, inQ = s[k1] >= 0.0;
+    if (inP) {
+      cp_set(C.P[nb], c, P);
+      cp_set(C.EP[nb], c, cp_get(C.EP[b], k));
+      C.ec[nb][c++] = C.ec[b][k];
+    }
+    if (inP != inQ) {
+      V3 X = normalized(fabs(s[k1]) * P + fabs(s[k]) * Q);
+      cp_set(C.P[nb], c, X);
+      if (inP) {  // leaving: the new edge runs along m
+        cp_set(C.EP[nb], c, pm);
+        C.ec[nb][c++] = m;
+      } else {    // entering: continue along the old edge
+        cp_set(C.EP[nb], c, cp_get(C.EP[b], k));
+        C.ec[nb][c++] = C.ec[b][k];
+      }
+    }
+  }
+  // midpoints of arcs longer than 90 degrees, rotated along the arc's circle
+  int c2 = 0;
+  for (int k = 0; k < c; k++) {
+    if (c2 > kClipMax - 2) {
+      C.err = 1;
+      break;
+    }
+    V3 P = cp_get(C.P[nb], k), Q = cp_get(C.P[nb], (k + 1) % c);
+    V3 EPk = cp_get(C.EP[nb], k);
+    int e = C.ec[nb][k];
+    cp_set(C.P[b], c2, P);
+    cp_set(C.EP[b], c2, EPk);
+    C.ec[b][c2++] = e;
+    if (dot(P, Q) < 0.0) {
+      V3 Nh = normalized(z - EPk);
+      V3 T = normalized(cross(Nh, P));
+      double th = atan2(dot(Q, T), dot(Q, P));
+      if (th < 0.0) th += 6.283185307179586;
+      V3 Mid = normalized(cos(0.5 * th) * P + sin(0.5 * th) * T);
+      cp_set(C.P[b], c2, Mid);
+      cp_set(C.EP[b], c2, EPk);
+      C.ec[b][c2++] = e;
+    }
+  }
+  C.cur = b;
+  C.K[b] = c2;
+}
+
+// offer generator j at pj (j != own index) to the clipper
+SCVT_HD void clip_offer(ClipPoly& C, V3 z, int j, V3 pj) {
+  if (C.K[C.cur] == 0) {
+    clip_init(C, z, j, pj);
+  } else {
+    clip_by(C, z, j, pj);
+  }
+  clip_update_R(C, z);
+}
+
+// Finish: real vertices in counter-clockwise order, each recomputed as the
+// canonical circumcentre of (own, incoming, outgoing generator) on the side
+// of the clipped vertex; edges k (v_k -> v_k+1 on the bisector with
+// enbr[k]) written sorted by neighbour index.  Returns the edge count (0 and
+// err set when the polygon is not a proper cell); C.R becomes the circumradius.
+template <class Pos>
+SCVT_HD int clip_finish(ClipPoly& C, int self, V3 z, const Pos& pos, int32_t* enbr, double* v0,
+                        double* v1, int vmax) {
+  const int b = C.cur, K = C.K[b], ob = 1 - b;
+  int nreal = 0;
+  for (int k = 0; k < K; k++) {
+    int ein = C.ec[b][(k + K - 1) % K], eout = C.ec[b][k];
+    if (ein == eout) continue;
+    if (nreal >= kClipMax) {
+      C.err = 1;
+      break;
+    }
+    V3 X = cp_get(C.P[b], k);
+    V3 v = circumcentre(self, z, ein, pos(ein), eout, pos(eout));
+    if (dot(v, X) < 0.0) v = -v;
+    cp_set(C.P[ob], nreal, v);
+    C.ec[ob][nreal] = eout;
+    nreal++;
+  }
+  if (nreal < 3 || nreal > vmax) C.err = 1;
+  const int E = C.err ? 0 : nreal;
+  double r2 = 0.0;
+  for (int k = 0; k < E; k++) {
+    int nbk = C.ec[ob][k];
+    V3 p0 = cp_get(C.P[ob], k), p1 = cp_get(C.P[ob], (k + 1) % E);
+    V3 d0 = p0 - z;
+    r2 = fmax(r2, dot(d0, d0));
+    V3 dd = p1 - p0;
+    if (dot(dd, dd) == 0.0) C.degen = 1;
+    int r = k;
+    while (r > 0 && enbr[r - 1] > nbk) {
+      enbr[r] = enbr[r - 1];
+      for (int c = 0; c < 3; c++) {
+        v0[3 * r + c] = v0[3 * (r - 1) + c];
+        v1[3 * r + c] = v1[3 * (r - 1) + c];
+      }
+      r--;
+    }
+    enbr[r] = nbk;
+    v0[3 * r] = p0.x; v0[3 * r + 1] = p0.y; v0[3 * r + 2] = p0.z;
+    v1[3 * r] = p1.x; v1[3 * r + 1] = p1.y; v1[3 * r + 2] = p1.z;
+  }
+  C.R = sqrt(r2);
+  return E;
+}
+
+}  // namespace scvt

@@ -1,0 +1,405 @@
+// Voronoi cell construction + cell quadrature + per-cell epilogue.
+//
+// Certified path (k_cells): one wavefront per generator z, in cube-map order
+// (neighbouring waves share cached grid data), block index remapped so that
+// each XCD's L2 sees a contiguous stretch of the sphere.
+//   A. candidates: every generator within chord radius rc of z, read from a
+//      rectangle of grid cells whose certified radius D >= rc (at most 64);
+//   B. one lane per candidate j computes the edge of the cell on the bisector
+//      of (z, p_j) against all other candidates (edge_on_bisector);
+//   C. certificate: the cell's circumradius R obeys 2R <= rc, so no
+//      generator outside the candidate set can cut the cell (a point p can
+//      only cut if |p - z| < 2R); otherwise the radius grows and A-C repeat;
+//   D. quadrature: fan triangles (z, v_lo, v_hi) over the edges, ordered by
+//      neighbour index, each split into 4^levels geodesic sub-triangles with
+//      the 7-point rule; one (edge, sub-triangle) item per lane;
+//   E. epilogue: m, mu, e -> g, h, Lloyd step (section 3.1).
+// Cells that cannot be certified with 64 candidates, or meet a predicate
+// within its error bound, go to a list for k_fallback: a sequential
+// half-space clipper run by lane 0 (no size limit: any cell the sphere
+// allows), then the same quadrature and epilogue.
+#include "kernels.h"
+
+namespace scvt {
+
+// ------------------------------------------------------------- wave tools
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+__device__ inline int mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline int wave_sum_i(int v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// logical block for a physical one: consecutive physical blocks go to
+// different XCDs (8 of them), so give each XCD a contiguous range
+__device__ inline int64_t xcd_block(int64_t b, int64_t nblocks) {
+  const int64_t X = 8;
+  int64_t per = nblocks / X, rem = nblocks % X;
+  int64_t x = b % X, k = b / X;
+  // XCD x owns per (+1 for the first rem XCDs) consecutive logical blocks
+  int64_t start = x * per + (x < rem ? x : rem);
+  return start + k;
+}
+
+// --------------------------------------------------------------- LDS layout
+struct WaveLds {
+  double px[kMaxCand], py[kMaxCand], pz[kMaxCand];
+  double dx[kMaxCand], dy[kMaxCand], dz[kMaxCand];
+  int32_t idx[kMaxCand];
+  int32_t rowoff[kWinMax + 1];
+  int32_t rowstart[kWinMax];
+  // edges ordered by neighbour index: fan triangle (z, v0, v1)
+  double v0[kMaxCand][3], v1[kMaxCand][3];
+  int32_t enbr[kMaxCand];
+};
+
+// ------------------------------------------------------ quadrature + output
+// Every lane integrates items lane, lane+64, ... of E * 4^levels (edge,
+// leaf) pairs; the wave sum is taken in a fixed butterfly order.
+__device__ Acc5 wave_quadrature(const WaveLds& L, int E, V3 z, const DensityP& rho, int levels) {
+  Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int per = 1 << (2 * levels);
+  const int total = E * per;
+  for (int t = lane_id(); t < total; t += 64) {
+    int e = t >> (2 * levels), s = t & (per - 1);
+    V3 A = z;
+    V3 B = V3{L.v0[e][0], L.v0[e][1], L.v0[e][2]};
+    V3 C = V3{L.v1[e][0], L.v1[e][1], L.v1[e][2]};
+    subtriangle(A, B, C, s, levels);
+    quad_tri(A, B, C, z, rho, acc);
+  }
+  acc.m = wave_sum(acc.m);
+  acc.mx = wave_sum(acc.mx);
+  acc.my = wave_sum(acc.my);
+  acc.mz = wave_sum(acc.mz);
+  acc.e = wave_sum(acc.e);
+  return acc;
+}
+
+__device__ void write_cell(const CellArgs& a, int64_t i, V3 z, const Acc5& acc, double R, int E,
+                           uint8_t flags, const WaveLds& L) {
+  const EvalOut& o = a.out;
+  if (lane_id() == 0) {
+    V3 mu = V3{acc.mx, acc.my, acc.mz};
+    double mz = dot(mu, z);
+    V3 g = 2.0 * mz * z - 2.0 * mu;
+    V3 l = normalized(mu) - z;
+    o.m[i] = acc.m;
+    o.e[i] = acc.e;
+    o.mu[3 * i] = mu.x;
+    o.mu[3 * i + 1] = mu.y;
+    o.mu[3 * i + 2] = mu.z;
+    o.g[3 * i] = g.x;
+    o.g[3 * i + 1] = g.y;
+    o.g[3 * i + 2] = g.z;
+    o.h[i] = 1.0 / (2.0 * mz);
+    o.lloyd[3 * i] = l.x;
+    o.lloyd[3 * i + 1] = l.y;
+    o.lloyd[3 * i + 2] = l.z;
+    o.R[i] = R;
+    o.flags[i] = flags;
+    o.deg[i] = E;
+  }
+  if (a.keep_cells) {
+    int ln = lane_id();
+    if (ln < kVmax) {
+      bool have = ln < E;
+      o.cell_nbr[i * kVmax + ln] = have ? L.enbr[ln] : -1;
+      for (int k = 0; k < 3; k++) {
+        o.cell_verts[(i * kVmax + ln) * 6 + k] = have ? L.v0[ln][k] : 0.0;
+        o.cell_verts[(i * kVmax + ln) * 6 + 3 + k] = have ? L.v1[ln][k] : 0.0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------- certified path
+// Gather every generator p != z with |p - z| < rc from window w into the
+// candidate arrays; returns the count (> kMaxCand means overflow).
+__device__ int gather(const CellArgs& a, WaveLds& L, const Window& w, int64_t i, V3 z, double rc2) {
+  const GridP& g = a.grid.g;
+  const int nrows = w.ib_hi - w.ib_lo + 1;
+  const int ln = lane_id();
+  wave_sync();  // earlier reads of the candidate arrays are done
+  int cnt = 0, st = 0;
+  if (ln < nrows) {
+    int64_t c0 = cell_of(g, w.f, w.ia_lo, w.ib_lo + ln);
+    int64_t c1 = cell_of(g, w.f, w.ia_hi, w.ib_lo + ln) + 1;
+    st = a.grid.start_tot[c0];
+    cnt = a.grid.start_tot[c1] - st;
+  }
+  // inclusive scan of the row counts across lanes
+  int incl = cnt;
+  for (int off = 1; off < 64; off <<= 1) {
+    int v = __shfl_up(incl, off, 64);
+    if (ln >= off) incl += v;
+  }
+  if (ln < nrows) {
+    L.rowoff[ln] = incl - cnt;
+    L.rowstart[ln] = st;
+  }
+  const int T = __shfl(incl, 63, 64);
+  wave_sync();
+  int kept = 0;
+  for (int t0 = 0; t0 < T; t0 += 64) {
+    int t = t0 + ln;
+    bool keep = false;
+    Entry en;
+    V3 d;
+    if (t < T) {
+      int r = 0;
+      while (r + 1 < nrows && L.rowoff[r + 1] <= t) r++;
+      en = a.grid.entries[L.rowstart[r] + (t - L.rowoff[r])];
+      d = V3{en.x - z.x, en.y - z.y, en.z - z.z};
+      keep = en.idx != (int32_t)i && dot(d, d) < rc2;
+      if (en.idx != (int32_t)i && d.x == 0.0 && d.y == 0.0 && d.z == 0.0) {
+        atomicAdd(&a.ctr->pad[0], 1);  // duplicate generator
+        keep = false;
+      }
+    }
+    uint64_t m = __ballot(keep);
+    int slot = kept + mbcnt(m);
+    if (keep && slot < kMaxCand) {
+      L.px[slot] = en.x;
+      L.py[slot] = en.y;
+      L.pz[slot] = en.z;
+      L.dx[slot] = d.x;
+      L.dy[slot] = d.y;
+      L.dz[slot] = d.z;
+      L.idx[slot] = en.idx;
+    }
+    kept += __popcll(m);
+  }
+  wave_sync();
+  return kept;
+}
+
+__global__ __launch_bounds__(256) void k_cells(CellArgs a) {
+  __shared__ WaveLds lds[4];
+  const int ln = lane_id(), wv = threadIdx.x >> 6;
+  WaveLds& L = lds[wv];
+  const int64_t pos = xcd_block(blockIdx.x, gridDim.x) * 4 + wv;
+  if (pos >= a.n) return;
+  const int64_t i = a.grid.order[pos];
+  const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
+  const int f = home_face(z);
+  const CandView S = {L.px, L.py, L.pz, L.dx, L.dy, L.dz};
+
+  double Rg = a.out.R[i];
+  double rt = Rg > 0.0 ? 2.3 * Rg : a.r_default;
+  bool ok = false, degen = false;
+  int E = 0;
+  double R = 0.0;
+  for (int attempt = 0; attempt < 8 && !ok && !degen; attempt++) {
+    Window w = make_window(a.grid.g, z, f, rt, kWinMax);
+    double rc = rt < w.D ? rt : w.D;
+    int ns = gather(a, L, w, i, z, rc * rc);
+    if (ns > kMaxCand) {  // too many: shrink the radius toward ~48 candidates
+      rt = rc * sqrt(48.0 / (double)ns);
+      continue;
+    }
+    EdgeRes er = EdgeRes{kEdgeNone, -1, -1};
+    if (ln < ns) er = edge_on_bisector(ln, ns, z, S);
+    if (__ballot(er.status == kEdgeDegenerate)) {
+      degen = true;
+      break;
+    }
+    if (__ballot(er.status == kEdgeUnbounded) || ns < 3) {
+      if (rc < rt) break;  // the window cannot grow: fallback
+      rt = 1.6 * rc;
+      continue;
+    }
+    const bool has = er.status == kEdgeYes;
+    const uint64_t emask = __ballot(has);
+    E = __popcll(emask);
+    V3 vlo = V3{0, 0, 0}, vhi = V3{0, 0, 0};
+    double r2 = 0.0;
+    if (has) {
+      int ij = L.idx[ln];
+      V3 pj = S.p(ln);
+      vlo = circumcentre((int)i, z, ij, pj, L.idx[er.lo], S.p(er.lo));
+      vhi = circumcentre((int)i, z, ij, pj, L.idx[er.hi], S.p(er.hi));
+      V3 a1 = vlo - z, a2 = vhi - z;
+      r2 = fmax(dot(a1, a1), dot(a2, a2));
+    }
+    r2 = wave_max(r2);
+    R = sqrt(r2);
+    if (4.0 * r2 * (1.0 + 1e-12) <= rc * rc && E >= 3 && E <= kVmax) {
+      ok = true;
+      // rank edges by neighbour index (deterministic summation order)
+      if (has) {
+        int me = L.idx[ln], rank = 0;
+        uint64_t mm = emask;
+        while (mm) {
+          int k = __builtin_ctzll(mm);
+          mm &= mm - 1;
+          rank += L.idx[k] < me ? 1 : 0;
+        }
+        L.v0[rank][0] = vlo.x; L.v0[rank][1] = vlo.y; L.v0[rank][2] = vlo.z;
+        L.v1[rank][0] = vhi.x; L.v1[rank][1] = vhi.y; L.v1[rank][2] = vhi.z;
+        L.enbr[rank] = me;
+      }
+      wave_sync();
+    } else {
+      if (rc < rt && 2.0 * R >= w.D) break;  // window-limited: fallback
+      // R of an incomplete candidate set overestimates the cell: grow by at
+      // most 1.6x per attempt (about 2.5x the candidates)
+      rt = fmin(2.1 * R, 1.6 * rt);
+    }
+  }
+  if (!ok) {
+    if (ln == 0) {
+      int k = atomicAdd(&a.ctr->fb_count, 1);
+      a.fb_list[k] = (int32_t)i;
+      if (degen) atomicAdd(&a.ctr->n_degenerate, 1);
+    }
+    return;
+  }
+  Acc5 acc = wave_quadrature(L, E, z, a.rho, a.levels);
+  write_cell(a, i, z, acc, R, E, 0, L);
+}
+
+// ------------------------------------------------------------ fallback path
+struct FbLds {
+  ClipPoly poly;
+  int32_t brute;
+  WaveLds w;  // edges for the quadrature
+};
+
+__device__ inline V3 genpos(const double* Z, int j) { return V3{Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]}; }
+
+// Whole wave: offer the generators of `count` candidates (given by a
+// callable index -> generator id) to the clipper; lanes prefilter by the
+// polygon bound |p - z| < 2R, lane 0 clips by the survivors in lane order.
+template <class Src>
+__device__ void fb_offer(FbLds& F, const double* Z, V3 z, int64_t self, int64_t count,
+                         const Src& src, int32_t* ctr_dup) {
+  const int ln = lane_id();
+  for (int64_t t0 = 0; t0 < count; t0 += 64) {
+    int64_t t = t0 + ln;
+    int j = -1;
+    bool cand = false;
+    if (t < count) {
+      j = src(t);
+      if (j != (int)self) {
+        V3 d = genpos(Z, j) - z;
+        double R = F.poly.R;
+        cand = dot(d, d) < 4.0 * R * R * (1.0 + 1e-9) + 1e-300;
+        if (d.x == 0.0 && d.y == 0.0 && d.z == 0.0) {
+          atomicAdd(&ctr_dup[0], 1);  // duplicate generator
+          cand = false;
+        }
+      }
+    }
+    uint64_t m = __ballot(cand);
+    while (m) {
+      int k = __builtin_ctzll(m);
+      m &= m - 1;
+      int jk = __shfl(j, k, 64);
+      if (ln == 0) clip_offer(F.poly, z, jk, genpos(Z, jk));
+      wave_sync();
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
+  __shared__ FbLds F;
+  const int ln = lane_id();
+  const int count = a.ctr->fb_count;
+  for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
+    const int64_t i = a.fb_list[w];
+    const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
+    if (ln == 0) {
+      clip_reset(F.poly);
+      F.brute = 0;
+    }
+    wave_sync();
+    bool done = false;
+    const GridP& g = a.grid.g;
+    if (a.n > 256 && g.B > 0) {
+      // nearby first: growing windows of the grid
+      const int f = home_face(z);
+      double rt = a.out.R[i] > 0.0 ? 2.3 * a.out.R[i] : a.r_default;
+      for (int it = 0; it < 6 && !done; it++) {
+        Window win = make_window(g, z, f, rt, kWinMax);
+        const int nrows = win.ib_hi - win.ib_lo + 1;
+        for (int r = 0; r < nrows; r++) {
+          int64_t c0 = cell_of(g, f, win.ia_lo, win.ib_lo + r);
+          int64_t c1 = cell_of(g, f, win.ia_hi, win.ib_lo + r) + 1;
+          const int32_t st = a.grid.start_tot[c0], en = a.grid.start_tot[c1];
+          const Entry* E = a.grid.entries;
+          fb_offer(F, a.Z, z, i, en - st, [&](int64_t t) { return (int)E[st + t].idx; },
+                   &a.ctr->pad[0]);
+        }
+        wave_sync();
+        if (F.poly.K[F.poly.cur] > 0 && 2.0 * F.poly.R * (1.0 + 1e-12) <= win.D) done = true;
+        double grow = 2.0 * F.poly.R * 1.05;
+        if (!done && win.D <= rt * 0.999 && grow > win.D) break;  // window cannot grow
+        rt = fmax(2.0 * rt, grow);
+      }
+    }
+    if (!done) {
+      if (ln == 0) F.brute = 1;
+      wave_sync();
+      fb_offer(F, a.Z, z, i, a.n, [](int64_t t) { return (int)t; }, &a.ctr->pad[0]);
+    }
+    wave_sync();
+    // real vertices (where consecutive edges change circle), canonical
+    // positions, edges sorted by neighbour index
+    if (ln == 0) {
+      int E = clip_finish(F.poly, (int)i, z, [&](int j) { return genpos(a.Z, j); }, F.w.enbr,
+                          &F.w.v0[0][0], &F.w.v1[0][0], kVmax);
+      F.poly.K[0] = E;  // reuse as the edge count
+    }
+    wave_sync();
+    const int E = F.poly.K[0];
+    uint8_t flags = kFlagFallback | (F.poly.degen ? kFlagDegenerate : 0) |
+                    (F.poly.err ? kFlagError : 0) | (F.brute ? kFlagBrute : 0);
+    if (ln == 0) {
+      atomicAdd(&a.ctr->n_fallback, 1);
+      if (F.poly.err) atomicAdd(&a.ctr->n_error, 1);
+      if (F.brute) atomicAdd(&a.ctr->n_brute, 1);
+      if (F.poly.degen) atomicAdd(&a.ctr->n_degenerate, 1);
+    }
+    Acc5 acc = wave_quadrature(F.w, E, z, a.rho, a.levels);
+    write_cell(a, i, z, acc, F.poly.R, E, flags, F.w);
+    wave_sync();
+  }
+}
+
+// small problems: every cell goes through the fallback clipper
+__global__ void k_fb_all(int32_t* fb_list, Counters* ctr, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) fb_list[i] = (int32_t)i;
+  if (i == 0) ctr->fb_count = (int32_t)n;
+}
+
+hipError_t launch_cells_main(const CellArgs& a, hipStream_t s) {
+  int64_t nb = (a.n + 3) / 4;
+  k_cells<<<(unsigned)nb, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s) {
+  if (all) k_fb_all<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a.fb_list, a.ctr, a.n);
+  int64_t fb_blocks = a.n < 8192 ? a.n : 8192;
+  k_fallback<<<(unsigned)fb_blocks, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace scvt

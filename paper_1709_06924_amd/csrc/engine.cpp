@@ -1,0 +1,795 @@
+// Host engine behind the C ABI: device state, the evaluation pipeline and
+// the P-LBFGS state machine (two-loop direction, descent check, Armijo line
+// search with projection, history ring).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/scvt.h"
+#include "kernels.h"
+#include "lbfgs.h"
+
+using namespace scvt;
+
+namespace {
+
+struct EvalSet {
+  double *m = nullptr, *mu = nullptr, *e = nullptr, *g = nullptr, *h = nullptr,
+         *lloyd = nullptr;
+  uint8_t* flags = nullptr;
+  int32_t* deg = nullptr;
+  int32_t* cell_nbr = nullptr;
+  double* cell_verts = nullptr;
+};
+
+struct Timer {
+  double ms = 0.0;
+  int64_t launches = 0;
+};
+
+constexpr int kTimers = 5;
+constexpr int kStateMagic = 0x53435654;  // "SCVT"
+
+}  // namespace
+
+struct scvt_handle {
+  scvt_config cfg;
+  int64_t n = 0;
+  int M = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DensityP rho{};
+  GridBufs grid{};
+  double *Z = nullptr, *Zt = nullptr, *q = nullptr, *R = nullptr;
+  EvalSet cur, trial;
+  double *S = nullptr, *Y = nullptr;  // (M+1) slots of 3n
+  double* dscal = nullptr;            // device scalars
+  double* partials = nullptr;
+  unsigned* tickets = nullptr;
+  int32_t* fb_list = nullptr;
+  Counters* ctr = nullptr;
+  double* pinned = nullptr;  // host-pinned mirror of scalars
+  std::vector<void*> allocs;
+  // ring: slots ordered oldest -> newest
+  std::vector<int> ring;
+  std::vector<int> free_slots;
+  // current state
+  double F = 0, step_inf = 0, gnorm2 = 0, min_mz = 0, alpha = 0;
+  int64_t iter = 0, n_evals = 0, n_fb = 0, n_deg = 0;
+  // evaluation results of the last trial
+  double tF = 0, tstep = 0, tg2 = 0, tmz = 0;
+  int64_t tfb = 0, tdeg = 0;
+  bool timing = false;
+  Timer timers[kTimers];
+  hipEvent_t ev[8] = {};
+  int main_path = 1;
+  double r_default = 0;
+};
+
+namespace {
+
+// device scalar layout (doubles)
+enum : int { kA = 0, kCoef = 64, kR = 128, kGQ = 200, kPush = 201, kEval = 204, kNScal = 256 };
+
+int hip_err(hipError_t e) { return e == hipSuccess ? SCVT_OK : SCVT_E_HIP; }
+#define HIPCK(x)                          \
+  do {                                    \
+    hipError_t _e = (x);                  \
+    if (_e != hipSuccess) return SCVT_E_HIP; \
+  } while (0)
+
+template <class T>
+int dalloc(scvt_handle* h, T** p, size_t count) {
+  void* v = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&v, count * sizeof(T)) != hipSuccess) return SCVT_E_OOM;
+  h->allocs.push_back(v);
+  *p = (T*)v;
+  return SCVT_OK;
+}
+#define ALLOC(p, cnt)                    \
+  do {                                   \
+    int _r = dalloc(h, &(p), (size_t)(cnt)); \
+    if (_r) return _r;                   \
+  } while (0)
+
+int alloc_set(scvt_handle* h, EvalSet& s) {
+  const int64_t n = h->n;
+  ALLOC(s.m, n);
+  ALLOC(s.mu, 3 * n);
+  ALLOC(s.e, n);
+  ALLOC(s.g, 3 * n);
+  ALLOC(s.h, n);
+  ALLOC(s.lloyd, 3 * n);
+  ALLOC(s.flags, n);
+  ALLOC(s.deg, n);
+  if (h->cfg.keep_cells) {
+    ALLOC(s.cell_nbr, n * kVmax);
+    ALLOC(s.cell_verts, n * kVmax * 6);
+  }
+  return SCVT_OK;
+}
+
+GridP make_grid(int64_t n) {
+  GridP g{};
+  int G = (int)llround(sqrt((double)n / 12.0));
+  if (G < 1) G = 1;
+  int B = (int)floor(0.45 * G);
+  if (B > 24) B = 24;
+  g.G = G;
+  g.B = B;
+  g.W = G + 2 * B;
+  g.delta = 1.5707963267948966 / G;
+  g.inv_delta = G / 1.5707963267948966;
+  g.a0 = -0.7853981633974483 - B * g.delta;
+  g.ncells = 6LL * g.W * g.W;
+  return g;
+}
+
+DensityP to_dev(const scvt_density& d) {
+  DensityP r{};
+  r.kind = d.kind;
+  r.geodesic = d.geodesic;
+  r.nbumps = d.nbumps;
+  for (int k = 0; k < 2; k++) {
+    for (int c = 0; c < 3; c++) r.xc[k][c] = d.xc[k][c];
+    r.beta[k] = d.beta[k];
+    r.alpha[k] = d.alpha[k];
+    r.amp[k] = d.amp[k];
+  }
+  r.gamma = d.gamma;
+  r.w_lon = d.w_lon;
+  r.w_lat = d.w_lat;
+  return r;
+}
+
+int validate(const scvt_config* c) {
+  if (!c || c->n < 4 || c->n > (int64_t)1 << 30) return SCVT_E_INVALID;
+  if (c->m_hist < 0 || c->m_hist > 60) return SCVT_E_INVALID;
+  if (c->precision != SCVT_FP64 && c->precision != SCVT_MIXED) return SCVT_E_INVALID;
+  if (c->quad_levels < 0 || c->quad_levels > 3) return SCVT_E_INVALID;
+  if (c->ls_max_evals < 1 || !(c->ls_c1 > 0.0 && c->ls_c1 < 1.0)) return SCVT_E_INVALID;
+  if (!(c->curv_eps >= 0.0)) return SCVT_E_INVALID;
+  const scvt_density& d = c->rho;
+  if (d.kind < 0 || d.kind > 3) return SCVT_E_INVALID;
+  if (d.kind == SCVT_RHO_TANH) {
+    if (d.nbumps < 1 || d.nbumps > 2) return SCVT_E_INVALID;
+    for (int k = 0; k < d.nbumps; k++)
+      if (!(d.alpha[k] > 0.0)) return SCVT_E_INVALID;
+  }
+  if (d.kind == SCVT_RHO_X16 && !(d.alpha[0] > 0.0 && d.w_lon > 0.0 && d.w_lat > 0.0))
+    return SCVT_E_INVALID;
+  if (d.kind != SCVT_RHO_CONST && !(d.gamma > 0.0)) return SCVT_E_INVALID;
+  return SCVT_OK;
+}
+
+CellArgs cell_args(scvt_handle* h, const double* Zsrc, EvalSet& s) {
+  CellArgs a{};
+  a.n = h->n;
+  a.Z = Zsrc;
+  a.grid = h->grid;
+  a.rho = h->rho;
+  a.levels = h->cfg.quad_levels;
+  a.keep_cells = h->cfg.keep_cells;
+  a.mixed = h->cfg.precision == SCVT_MIXED;
+  a.out.m = s.m;
+  a.out.mu = s.mu;
+  a.out.e = s.e;
+  a.out.g = s.g;
+  a.out.h = s.h;
+  a.out.lloyd = s.lloyd;
+  a.out.R = h->R;
+  a.out.flags = s.flags;
+  a.out.deg = s.deg;
+  a.out.cell_nbr = s.cell_nbr;
+  a.out.cell_verts = s.cell_verts;
+  a.fb_list = h->fb_list;
+  a.ctr = h->ctr;
+  a.r_default = h->r_default;
+  return a;
+}
+
+void timer_add(scvt_handle* h, int k, hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+    h->timers[k].ms += ms;
+    h->timers[k].launches += 1;
+  }
+}
+
+// Evaluate at Zsrc into set s: grid, cells, reductions; one host sync.
+int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
+  hipStream_t st = h->stream;
+  const bool tm = h->timing;
+  HIPCK(launch_fill_i32((int32_t*)h->ctr, 0, sizeof(Counters) / 4, st));
+  if (tm) HIPCK(hipEventRecord(h->ev[0], st));
+  HIPCK(launch_grid_build(Zsrc, h->n, h->grid, st));
+  if (tm) HIPCK(hipEventRecord(h->ev[1], st));
+  CellArgs a = cell_args(h, Zsrc, s);
+  if (h->main_path) HIPCK(launch_cells_main(a, st));
+  if (tm) HIPCK(hipEventRecord(h->ev[2], st));
+  HIPCK(launch_cells_fallback(a, h->main_path ? 0 : 1, st));
+  if (tm) HIPCK(hipEventRecord(h->ev[3], st));
+  EvalRedArgs r{};
+  r.n = h->n;
+  r.e = s.e;
+  r.lloyd = s.lloyd;
+  r.g = s.g;
+  r.mu = s.mu;
+  r.Z = Zsrc;
+  r.out = h->dscal + kEval;
+  r.partials = h->partials;
+  r.ticket = h->tickets + 1;
+  HIPCK(launch_eval_reduce(r, st));
+  if (tm) HIPCK(hipEventRecord(h->ev[4], st));
+  HIPCK(hipMemcpyAsync(h->pinned, h->dscal + kEval, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(h->pinned + 8, h->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  if (tm) {
+    if (h->main_path) timer_add(h, 0, h->ev[1], h->ev[2]);
+    timer_add(h, 1, h->ev[2], h->ev[3]);
+    timer_add(h, 2, h->ev[0], h->ev[1]);
+    timer_add(h, 4, h->ev[0], h->ev[4]);
+  }
+  Counters c;
+  memcpy(&c, h->pinned + 8, sizeof(Counters));
+  h->tF = h->pinned[0];
+  h->tstep = h->pinned[1];
+  h->tg2 = h->pinned[2];
+  h->tmz = h->pinned[3];
+  h->tfb = c.n_fallback;
+  h->tdeg = c.n_degenerate;
+  if (c.pad[0] > 0) return SCVT_E_DEGENERATE;
+  if (c.n_error > 0) return SCVT_E_CERT;
+  if (!(h->tF == h->tF) || !(h->tmz > 0.0)) return SCVT_E_NUMERIC;
+  return SCVT_OK;
+}
+
+void swap_sets(scvt_handle* h) {
+  EvalSet t = h->cur;
+  h->cur = h->trial;
+  h->trial = t;
+  double* z = h->Z;
+  h->Z = h->Zt;
+  h->Zt = z;
+}
+
+void adopt_trial_scalars(scvt_handle* h) {
+  h->F = h->tF;
+  h->step_inf = h->tstep;
+  h->gnorm2 = h->tg2;
+  h->min_mz = h->tmz;
+  h->n_fb = h->tfb;
+  h->n_deg = h->tdeg;
+}
+
+// P-LBFGS direction into h->q; g . q into *gq (one host sync)
+int direction(scvt_handle* h, double* gq) {
+  hipStream_t st = h->stream;
+  const int64_t n3 = 3 * h->n;
+  double* D = h->dscal;
+  const int c = (int)h->ring.size();
+  auto S = [&](int j) { return h->S + (size_t)h->ring[j] * n3; };
+  auto Y = [&](int j) { return h->Y + (size_t)h->ring[j] * n3; };
+  auto R = [&](int j) { return D + kR + h->ring[j]; };
+  if (h->timing) HIPCK(hipEventRecord(h->ev[5], st));
+  PassArgs p{};
+  p.n3 = n3;
+  p.q = h->q;
+  p.g = h->cur.g;
+  p.h = h->cur.h;
+  p.partials = h->partials;
+  p.ticket = h->tickets;
+  if (c == 0) {
+    p.init_neg_g = 1;
+    p.scale_h = 1;
+    p.dot_vec = h->cur.g;
+    p.out = D + kGQ;
+    HIPCK(launch_lbfgs_pass(p, st));
+  } else {
+    // backward loop, newest to oldest
+    PassArgs b = p;
+    b.init_neg_g = 1;
+    b.dot_vec = S(c - 1);
+    b.mul = R(c - 1);
+    b.out = D + kA + (c - 1);
+    HIPCK(launch_lbfgs_pass(b, st));
+    for (int j = c - 2; j >= 0; j--) {
+      PassArgs m = p;
+      m.ax_vec = Y(j + 1);
+      m.ax_coef = D + kA + (j + 1);
+      m.ax_sign = -1.0;
+      m.dot_vec = S(j);
+      m.mul = R(j);
+      m.out = D + kA + j;
+      HIPCK(launch_lbfgs_pass(m, st));
+    }
+    // turn-around: finish the backward loop, apply diag(h), first forward dot
+    PassArgs t = p;
+    t.ax_vec = Y(0);
+    t.ax_coef = D + kA;
+    t.ax_sign = -1.0;
+    t.scale_h = 1;
+    t.dot_vec = Y(0);
+    t.mul = R(0);
+    t.sub_from = D + kA;
+    t.out = D + kCoef;
+    HIPCK(launch_lbfgs_pass(t, st));
+    // forward loop, oldest to newest: coef_j = a_j - r_j y_j.q
+    for (int j = 1; j < c; j++) {
+      PassArgs f = p;
+      f.ax_vec = S(j - 1);
+      f.ax_coef = D + kCoef + (j - 1);
+      f.ax_sign = 1.0;
+      f.dot_vec = Y(j);
+      f.mul = R(j);
+      f.sub_from = D + kA + j;
+      f.out = D + kCoef + j;
+      HIPCK(launch_lbfgs_pass(f, st));
+    }
+    PassArgs l = p;
+    l.ax_vec = S(c - 1);
+    l.ax_coef = D + kCoef + (c - 1);
+    l.ax_sign = 1.0;
+    l.dot_vec = h->cur.g;
+    l.out = D + kGQ;
+    HIPCK(launch_lbfgs_pass(l, st));
+  }
+  if (h->timing) HIPCK(hipEventRecord(h->ev[6], st));
+  HIPCK(hipMemcpyAsync(h->pinned + 4, D + kGQ, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  if (h->timing) timer_add(h, 3, h->ev[5], h->ev[6]);
+  *gq = h->pinned[4];
+  return SCVT_OK;
+}
+
+// Armijo backtracking along q from the current point; on success the trial
+// set holds the accepted evaluation.
+int line_search(scvt_handle* h, double gq, bool* accepted, double* alpha_out) {
+  double alpha = 1.0;
+  *accepted = false;
+  for (int k = 0; k < h->cfg.ls_max_evals; k++) {
+    HIPCK(launch_normalize_trial(h->Z, h->q, alpha, h->Zt, h->n, h->stream));
+    int rc = evaluate(h, h->Zt, h->trial);
+    h->n_evals++;
+    if (rc < 0) return rc;
+    if (h->tF <= h->F + h->cfg.ls_c1 * alpha * gq) {
+      *accepted = true;
+      *alpha_out = alpha;
+      return SCVT_OK;
+    }
+    alpha *= 0.5;
+  }
+  return SCVT_OK;
+}
+
+int push_pair(scvt_handle* h) {
+  if (h->M == 0) return SCVT_OK;
+  const int slot = h->free_slots.back();
+  const int64_t n3 = 3 * h->n;
+  PushArgs p{};
+  p.n3 = n3;
+  p.Z = h->Z;
+  p.Zt = h->Zt;
+  p.g = h->cur.g;
+  p.gt = h->trial.g;
+  p.s = h->S + (size_t)slot * n3;
+  p.y = h->Y + (size_t)slot * n3;
+  p.out = h->dscal + kPush;
+  p.r_slot = h->dscal + kR + slot;
+  p.partials = h->partials;
+  p.ticket = h->tickets + 2;
+  HIPCK(launch_push(p, h->stream));
+  HIPCK(hipMemcpyAsync(h->pinned + 5, h->dscal + kPush, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                       h->stream));
+  HIPCK(hipStreamSynchronize(h->stream));
+  double ys = h->pinned[5], yy = h->pinned[6], ss = h->pinned[7];
+  if (ys > h->cfg.curv_eps * sqrt(yy * ss)) {
+    h->free_slots.pop_back();
+    h->ring.push_back(slot);
+    if ((int)h->ring.size() > h->M) {
+      h->free_slots.push_back(h->ring.front());
+      h->ring.erase(h->ring.begin());
+    }
+  }
+  return SCVT_OK;
+}
+
+void clear_history(scvt_handle* h) {
+  for (int s : h->ring) h->free_slots.push_back(s);
+  h->ring.clear();
+}
+
+int do_step(scvt_handle* h) {
+  double gq = 0.0;
+  int rc = direction(h, &gq);
+  if (rc) return rc;
+  if (!(gq < 0.0)) {  // not a descent direction: back to the Lloyd direction
+    clear_history(h);
+    rc = direction(h, &gq);
+    if (rc) return rc;
+  }
+  bool ok = false;
+  double alpha = 0.0;
+  rc = line_search(h, gq, &ok, &alpha);
+  if (rc) return rc;
+  if (!ok && !h->ring.empty()) {
+    clear_history(h);
+    rc = direction(h, &gq);
+    if (rc) return rc;
+    rc = line_search(h, gq, &ok, &alpha);
+    if (rc) return rc;
+  }
+  if (!ok) return SCVT_E_LINESEARCH;
+  rc = push_pair(h);
+  if (rc) return rc;
+  swap_sets(h);
+  adopt_trial_scalars(h);
+  h->alpha = alpha;
+  h->iter++;
+  return SCVT_OK;
+}
+
+void fill_info(scvt_handle* h, scvt_info* info, int status) {
+  if (!info) return;
+  info->iter = h->iter;
+  info->n_evals = h->n_evals;
+  info->F = h->F;
+  info->grad_norm2 = sqrt(h->gnorm2);
+  info->step_inf = h->step_inf;
+  info->alpha = h->alpha;
+  info->n_fallback = h->n_fb;
+  info->n_degenerate = h->n_deg;
+  info->status = status;
+  info->hist_len = (int32_t)h->ring.size();
+}
+
+void destroy(scvt_handle* h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream);
+  for (void* p : h->allocs) hipFree(p);
+  if (h->pinned) hipHostFree(h->pinned);
+  for (auto& e : h->ev)
+    if (e) hipEventDestroy(e);
+  if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int init_device_state(scvt_handle* h) {
+  const int64_t n = h->n;
+  const int M = h->M;
+  h->grid.g = make_grid(n);
+  const int64_t nc = h->grid.g.ncells;
+  ALLOC(h->Z, 3 * n);
+  ALLOC(h->Zt, 3 * n);
+  ALLOC(h->q, 3 * n);
+  ALLOC(h->R, n);
+  int rc = alloc_set(h, h->cur);
+  if (rc) return rc;
+  rc = alloc_set(h, h->trial);
+  if (rc) return rc;
+  if (M > 0) {
+    ALLOC(h->S, (size_t)(M + 1) * 3 * n);
+    ALLOC(h->Y, (size_t)(M + 1) * 3 * n);
+  }
+  ALLOC(h->dscal, kNScal);
+  ALLOC(h->partials, 4 * reduce_grid_max());
+  ALLOC(h->tickets, 8);
+  ALLOC(h->fb_list, n);
+  ALLOC(h->ctr, 1);
+  ALLOC(h->grid.cnt_tot, nc + 1);
+  ALLOC(h->grid.cnt_home, nc + 1);
+  ALLOC(h->grid.start_tot, nc + 1);
+  ALLOC(h->grid.start_home, nc + 1);
+  ALLOC(h->grid.cell3, 3 * n);
+  h->grid.cap_entries = 3 * n;
+  ALLOC(h->grid.entries, 3 * n);
+  ALLOC(h->grid.order, n);
+  ALLOC(h->grid.scan_tmp, 2 * ((nc + 1) / 2048 + 2));
+  ALLOC(h->grid.overflow, 1);
+  if (hipHostMalloc((void**)&h->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return SCVT_E_OOM;
+  for (auto& e : h->ev)
+    if (hipEventCreate(&e) != hipSuccess) return SCVT_E_HIP;
+  hipStream_t st = h->stream;
+  HIPCK(launch_fill_i32(h->grid.cnt_tot, 0, nc + 1, st));
+  HIPCK(launch_fill_i32(h->grid.cnt_home, 0, nc + 1, st));
+  HIPCK(launch_fill_i32(h->grid.overflow, 0, 1, st));
+  HIPCK(launch_fill_i32((int32_t*)h->tickets, 0, 8, st));
+  HIPCK(launch_fill_i32((int32_t*)h->R, 0, 2 * n, st));
+  HIPCK(launch_fill_i32((int32_t*)h->dscal, 0, 2 * kNScal, st));
+  HIPCK(launch_fill_i32((int32_t*)h->q, 0, 6 * n, st));
+  for (int s = M; s >= 0 && M > 0; s--) h->free_slots.push_back(s);
+  h->main_path = n > 256 ? 1 : 0;
+  h->r_default = 2.0 * sqrt(4.0 * 3.141592653589793 / (double)n);
+  return SCVT_OK;
+}
+
+}  // namespace
+
+// =============================================================== C ABI ====
+extern "C" {
+
+int scvt_config_init(scvt_config* c, int64_t n) {
+  if (!c) return SCVT_E_INVALID;
+  memset(c, 0, sizeof(*c));
+  c->n = n;
+  c->m_hist = 7;
+  c->precision = SCVT_FP64;
+  c->rho.kind = SCVT_RHO_CONST;
+  c->rho.nbumps = 0;
+  c->rho.w_lon = 1.0;
+  c->rho.w_lat = 1.0;
+  c->quad_levels = 2;
+  c->ls_max_evals = 10;
+  c->ls_c1 = 1e-4;
+  c->curv_eps = 1e-10;
+  c->keep_cells = 0;
+  c->hip_stream = nullptr;
+  return SCVT_OK;
+}
+
+int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt_handle** out) {
+  if (!out) return SCVT_E_INVALID;
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!z0) return SCVT_E_INVALID;
+  const int64_t n = cfg->n;
+  if (!z0_on_device) {
+    for (int64_t k = 0; k < 3 * n; k++)
+      if (!isfinite(z0[k])) return SCVT_E_INVALID;
+    for (int64_t i = 0; i < n; i++)
+      if (z0[3 * i] == 0.0 && z0[3 * i + 1] == 0.0 && z0[3 * i + 2] == 0.0)
+        return SCVT_E_DEGENERATE;
+  }
+  scvt_handle* h = new (std::nothrow) scvt_handle();
+  if (!h) return SCVT_E_OOM;
+  h->cfg = *cfg;
+  h->n = n;
+  h->M = cfg->m_hist;
+  h->rho = to_dev(cfg->rho);
+  if (cfg->hip_stream) {
+    h->stream = (hipStream_t)cfg->hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete h;
+      return SCVT_E_HIP;
+    }
+    h->own_stream = true;
+  }
+  rc = init_device_state(h);
+  if (!rc) {
+    hipError_t e = hipMemcpyAsync(h->Zt, z0, 3 * n * sizeof(double),
+                                  z0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  h->stream);
+    if (e == hipSuccess) e = launch_normalize_trial(h->Zt, nullptr, 0.0, h->Z, n, h->stream);
+    rc = hip_err(e);
+  }
+  if (!rc) {
+    rc = evaluate(h, h->Z, h->cur);
+    h->n_evals = 1;
+    if (!rc) adopt_trial_scalars(h);
+  }
+  if (rc) {
+    destroy(h);
+    return rc;
+  }
+  *out = h;
+  return SCVT_OK;
+}
+
+int scvt_step(scvt_handle* h, scvt_info* info) {
+  if (!h) return SCVT_E_INVALID;
+  int rc = do_step(h);
+  fill_info(h, info, rc);
+  return rc;
+}
+
+int scvt_solve(scvt_handle* h, int64_t max_iter, double tol, scvt_info* info) {
+  if (!h) return SCVT_E_INVALID;
+  int rc = SCVT_OK;
+  while (!(h->step_inf < tol) && h->iter < max_iter) {
+    rc = do_step(h);
+    if (rc) break;
+  }
+  if (!rc && !(h->step_inf < tol)) rc = SCVT_NOT_CONVERGED;
+  fill_info(h, info, rc);
+  return rc;
+}
+
+int scvt_energy(scvt_handle* h, double* F, double* mass, double* centroid, double* e_cell,
+                int on_dev) {
+  if (!h) return SCVT_E_INVALID;
+  const int64_t n = h->n;
+  const hipMemcpyKind k = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (F) *F = h->F;
+  if (mass) HIPCK(hipMemcpyAsync(mass, h->cur.m, n * sizeof(double), k, h->stream));
+  if (e_cell) HIPCK(hipMemcpyAsync(e_cell, h->cur.e, n * sizeof(double), k, h->stream));
+  if (centroid) {
+    if (on_dev) {
+      HIPCK(launch_centroid(h->cur.mu, h->cur.m, centroid, n, h->stream));
+    } else {
+      HIPCK(launch_centroid(h->cur.mu, h->cur.m, h->q, n, h->stream));
+      HIPCK(hipMemcpyAsync(centroid, h->q, 3 * n * sizeof(double), k, h->stream));
+    }
+  }
+  HIPCK(hipStreamSynchronize(h->stream));
+  return SCVT_OK;
+}
+
+int scvt_get_generators(scvt_handle* h, double* z, int on_dev) {
+  if (!h || !z) return SCVT_E_INVALID;
+  HIPCK(hipMemcpyAsync(z, h->Z, 3 * h->n * sizeof(double),
+                       on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  HIPCK(hipStreamSynchronize(h->stream));
+  return SCVT_OK;
+}
+
+int scvt_get_vectors(scvt_handle* h, int which, double* out, int on_dev) {
+  if (!h || !out) return SCVT_E_INVALID;
+  const int64_t n = h->n;
+  const double* src = nullptr;
+  int64_t cnt = 3 * n;
+  switch (which) {
+    case 0: src = h->cur.g; break;
+    case 1: src = h->cur.h; cnt = n; break;
+    case 2: src = h->cur.lloyd; break;
+    case 3: src = h->cur.mu; break;
+    case 4: src = h->q; break;
+    case 5: src = h->R; cnt = n; break;
+    default: return SCVT_E_INVALID;
+  }
+  HIPCK(hipMemcpyAsync(out, src, cnt * sizeof(double),
+                       on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  HIPCK(hipStreamSynchronize(h->stream));
+  return SCVT_OK;
+}
+
+int scvt_direction(scvt_handle* h, double* out, int on_dev, double* gq) {
+  if (!h) return SCVT_E_INVALID;
+  double v = 0.0;
+  int rc = direction(h, &v);
+  if (rc) return rc;
+  if (gq) *gq = v;
+  if (out) return scvt_get_vectors(h, 4, out, on_dev);
+  return SCVT_OK;
+}
+
+int scvt_get_cells(scvt_handle* h, int32_t max_deg, int32_t* nbr, int32_t* deg, double* verts,
+                   uint8_t* flags) {
+  if (!h || max_deg != kVmax) return SCVT_E_INVALID;
+  const int64_t n = h->n;
+  hipStream_t st = h->stream;
+  if ((nbr || verts) && !h->cfg.keep_cells) return SCVT_E_INVALID;
+  if (nbr)
+    HIPCK(hipMemcpyAsync(nbr, h->cur.cell_nbr, n * kVmax * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  if (verts)
+    HIPCK(hipMemcpyAsync(verts, h->cur.cell_verts, n * kVmax * 6 * sizeof(double),
+                         hipMemcpyDeviceToHost, st));
+  if (deg) HIPCK(hipMemcpyAsync(deg, h->cur.deg, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  if (flags) HIPCK(hipMemcpyAsync(flags, h->cur.flags, n, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  return SCVT_OK;
+}
+
+// state blob: int64 header[8] = {magic, n, M, ring size, iter, n_evals, 0, 0},
+// double alpha, then Z (3n), then per ring entry oldest first: r, s (3n), y (3n)
+int scvt_get_state(scvt_handle* h, void* buf, size_t* bytes) {
+  if (!h || !bytes) return SCVT_E_INVALID;
+  const int64_t n3 = 3 * h->n;
+  const size_t c = h->ring.size();
+  const size_t need = 8 * sizeof(int64_t) + sizeof(double) + n3 * sizeof(double) +
+                      c * (sizeof(double) + 2 * n3 * sizeof(double));
+  if (!buf) {
+    *bytes = need;
+    return SCVT_OK;
+  }
+  if (*bytes < need) return SCVT_E_INVALID;
+  char* p = (char*)buf;
+  int64_t hdr[8] = {kStateMagic, h->n, h->M, (int64_t)c, h->iter, h->n_evals, 0, 0};
+  memcpy(p, hdr, sizeof(hdr));
+  p += sizeof(hdr);
+  memcpy(p, &h->alpha, sizeof(double));
+  p += sizeof(double);
+  hipStream_t st = h->stream;
+  HIPCK(hipMemcpyAsync(p, h->Z, n3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  p += n3 * sizeof(double);
+  std::vector<double> rr(c);
+  for (size_t j = 0; j < c; j++) {
+    int slot = h->ring[j];
+    HIPCK(hipMemcpyAsync(&rr[j], h->dscal + kR + slot, sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  HIPCK(hipStreamSynchronize(st));
+  for (size_t j = 0; j < c; j++) {
+    int slot = h->ring[j];
+    memcpy(p, &rr[j], sizeof(double));
+    p += sizeof(double);
+    HIPCK(hipMemcpy(p, h->S + (size_t)slot * n3, n3 * sizeof(double), hipMemcpyDeviceToHost));
+    p += n3 * sizeof(double);
+    HIPCK(hipMemcpy(p, h->Y + (size_t)slot * n3, n3 * sizeof(double), hipMemcpyDeviceToHost));
+    p += n3 * sizeof(double);
+  }
+  *bytes = need;
+  return SCVT_OK;
+}
+
+int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes) {
+  if (!h || !buf || bytes < 8 * sizeof(int64_t) + sizeof(double)) return SCVT_E_INVALID;
+  const char* p = (const char*)buf;
+  int64_t hdr[8];
+  memcpy(hdr, p, sizeof(hdr));
+  p += sizeof(hdr);
+  const int64_t n3 = 3 * h->n;
+  const int64_t c = hdr[3];
+  if (hdr[0] != kStateMagic || hdr[1] != h->n || hdr[2] != h->M || c < 0 || c > h->M)
+    return SCVT_E_INVALID;
+  const size_t need = 8 * sizeof(int64_t) + sizeof(double) + n3 * sizeof(double) +
+                      c * (sizeof(double) + 2 * n3 * sizeof(double));
+  if (bytes < need) return SCVT_E_INVALID;
+  double alpha;
+  memcpy(&alpha, p, sizeof(double));
+  p += sizeof(double);
+  hipStream_t st = h->stream;
+  HIPCK(hipStreamSynchronize(st));
+  HIPCK(hipMemcpy(h->Z, p, n3 * sizeof(double), hipMemcpyHostToDevice));
+  p += n3 * sizeof(double);
+  clear_history(h);
+  for (int64_t j = 0; j < c; j++) {
+    int slot = h->free_slots.back();
+    h->free_slots.pop_back();
+    double r;
+    memcpy(&r, p, sizeof(double));
+    p += sizeof(double);
+    HIPCK(hipMemcpy(h->dscal + kR + slot, &r, sizeof(double), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(h->S + (size_t)slot * n3, p, n3 * sizeof(double), hipMemcpyHostToDevice));
+    p += n3 * sizeof(double);
+    HIPCK(hipMemcpy(h->Y + (size_t)slot * n3, p, n3 * sizeof(double), hipMemcpyHostToDevice));
+    p += n3 * sizeof(double);
+    h->ring.push_back(slot);
+  }
+  h->iter = hdr[4];
+  h->n_evals = hdr[5];
+  h->alpha = alpha;
+  int rc = evaluate(h, h->Z, h->cur);
+  if (!rc) adopt_trial_scalars(h);
+  return rc;
+}
+
+int scvt_set_timing(scvt_handle* h, int enable) {
+  if (!h) return SCVT_E_INVALID;
+  h->timing = enable != 0;
+  for (auto& t : h->timers) t = Timer{};
+  return SCVT_OK;
+}
+
+int scvt_kernel_time(scvt_handle* h, int kernel, double* total_ms, int64_t* launches) {
+  if (!h || kernel < 0 || kernel >= kTimers) return SCVT_E_INVALID;
+  if (total_ms) *total_ms = h->timers[kernel].ms;
+  if (launches) *launches = h->timers[kernel].launches;
+  return SCVT_OK;
+}
+
+void scvt_destroy(scvt_handle* h) { destroy(h); }
+
+const char* scvt_strerror(int code) {
+  switch (code) {
+    case SCVT_OK: return "ok";
+    case SCVT_NOT_CONVERGED: return "not converged (iteration cap reached)";
+    case SCVT_PENDING: return "pending";
+    case SCVT_E_INVALID: return "invalid argument";
+    case SCVT_E_OOM: return "out of device memory";
+    case SCVT_E_DEGENERATE: return "degenerate generators (duplicate or zero)";
+    case SCVT_E_CERT: return "a Voronoi cell could not be built";
+    case SCVT_E_LINESEARCH: return "line search failed after reset";
+    case SCVT_E_NUMERIC: return "numeric failure (NaN or mu.z <= 0)";
+    case SCVT_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+// Cube-map bucketing of the generators (counting sort by cell).
+//
+// count:   every generator adds itself to its home cell and to the ghost
+//          border of each neighbouring face whose extended grid holds it;
+// scan:    exclusive prefix sums of the counts (three-kernel block scan);
+// scatter: positions are taken by decrementing the counts back to zero, so
+//          the counts are ready for the next evaluation without a memset.
+#include "kernels.h"
+
+namespace scvt {
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; t < count; t += (int64_t)gridDim.x * blockDim.x) p[t] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_fill_i32<<<(unsigned)blocks, 256, 0, s>>>(p, v, count);
+  return hipGetLastError();
+}
+
+// trial point: Zt = normalize(Z + alpha q) (q == nullptr: normalize Z)
+__global__ void k_normalize_trial(const double* __restrict__ Z, const double* __restrict__ q,
+                                  double alpha, double* __restrict__ Zt, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  V3 z = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
+  if (q) z = z + alpha * V3{q[3 * i], q[3 * i + 1], q[3 * i + 2]};
+  V3 w = normalized(z);
+  Zt[3 * i] = w.x;
+  Zt[3 * i + 1] = w.y;
+  Zt[3 * i + 2] = w.z;
+}
+
+hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha, double* Zt,
+                                  int64_t n, hipStream_t s) {
+  k_normalize_trial<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Z, q, alpha, Zt, n);
+  return hipGetLastError();
+}
+
+// the four faces sharing an edge with face f (all but f and its opposite)
+__device__ inline void side_faces(int f, int out[4]) {
+  int k = f >> 1, c = 0;
+  for (int g = 0; g < 6; g++)
+    if ((g >> 1) != k) out[c++] = g;
+}
+
+__global__ void k_grid_count(const double* __restrict__ Z, int64_t n, GridP g,
+                             int32_t* __restrict__ cnt_tot, int32_t* __restrict__ cnt_home,
+                             int32_t* __restrict__ cell3) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  V3 p = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
+  int f = home_face(p);
+  int64_t c = cell_on_face(g, p, f);
+  // a point always lies inside its home face (|a|,|b| <= pi/4); guard the
+  // index anyway against rounding at the face edge
+  if (c < 0) {
+    double nn, u, v;
+    face_local(p, f, nn, u, v);
+    double fa = floor((atan(u / nn) - g.a0) * g.inv_delta);
+    double fb = floor((atan(v / nn) - g.a0) * g.inv_delta);
+    int ia = fa < 0.0 ? 0 : (fa > g.W - 1 ? g.W - 1 : (int)fa);
+    int ib = fb < 0.0 ? 0 : (fb > g.W - 1 ? g.W - 1 : (int)fb);
+    c = cell_of(g, f, ia, ib);
+  }
+  atomicAdd(&cnt_tot[c], 1);
+  atomicAdd(&cnt_home[c], 1);
+  cell3[3 * i] = (int32_t)c;
+  int k = 1;
+  int sf[4];
+  side_faces(f, sf);
+  for (int t = 0; t < 4 && g.B > 0; t++) {
+    int64_t cg = cell_on_face(g, p, sf[t]);
+    if (cg >= 0 && k < 3) {
+      atomicAdd(&cnt_tot[cg], 1);
+      cell3[3 * i + k] = (int32_t)cg;
+      k++;
+    }
+  }
+  for (; k < 3; k++) cell3[3 * i + k] = -1;
+}
+
+// ---- exclusive scan of two int arrays of length m (m+1 outputs) ----
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = 256;
+constexpr int kScanTile = kScanItems * kScanBlock;
+
+__device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
+  // Hillis-Steele in shared memory over 256 threads
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    int add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  total = sh[kScanBlock - 1];
+  int excl = sh[t] - v;
+  __syncthreads();
+  return excl;
+}
+
+// pass 1: per-tile sums of both arrays
+__global__ void k_scan_tiles(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
+                             int64_t m, int32_t* __restrict__ sums) {
+  __shared__ int sh[kScanBlock];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int sa = 0, sb = 0;
+  for (int k = 0; k < kScanItems; k++) {
+    int64_t t = base + k;
+    if (t < m) {
+      sa += a[t];
+      sb += b[t];
+    }
+  }
+  int tot;
+  block_exclusive_scan(sa, sh, tot);
+  if (threadIdx.x == 0) sums[2 * blockIdx.x] = tot;
+  block_exclusive_scan(sb, sh, tot);
+  if (threadIdx.x == 0) sums[2 * blockIdx.x + 1] = tot;
+}
+
+// pass 2: exclusive scan of the tile sums by one block (loops over chunks)
+__global__ void k_scan_sums(int32_t* sums, int64_t ntiles) {
+  __shared__ int sh[kScanBlock];
+  int carry_a = 0, carry_b = 0;
+  for (int64_t c0 = 0; c0 < ntiles; c0 += kScanBlock) {
+    int64_t t = c0 + threadIdx.x;
+    int va = t < ntiles ? sums[2 * t] : 0;
+    int vb = t < ntiles ? sums[2 * t + 1] : 0;
+    int ta, tb;
+    int ea = block_exclusive_scan(va, sh, ta);
+    int eb = block_exclusive_scan(vb, sh, tb);
+    if (t < ntiles) {
+      sums[2 * t] = ea + carry_a;
+      sums[2 * t + 1] = eb + carry_b;
+    }
+    carry_a += ta;
+    carry_b += tb;
+  }
+}
+
+// pass 3: scan inside each tile, add the tile offset; element m gets the total
+__global__ void k_scan_apply(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
+                             int64_t m, const int32_t* __restrict__ sums,
+                             int32_t* __restrict__ oa, int32_t* __restrict__ ob) {
+  __shared__ int sh[kScanBlock];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int va[kScanItems], vb[kScanItems];
+  int sa = 0, sb = 0;
+  for (int k = 0; k < kScanItems; k++) {
+    int64_t t = base + k;
+    va[k] = t < m ? a[t] : 0;
+    vb[k] = t < m ? b[t] : 0;
+    sa += va[k];
+    sb += vb[k];
+  }
+  int tot;
+  int ea = block_exclusive_scan(sa, sh, tot) + sums[2 * blockIdx.x];
+  int eb = block_exclusive_scan(sb, sh, tot) + sums[2 * blockIdx.x + 1];
+  for (int k = 0; k < kScanItems; k++) {
+    int64_t t = base + k;
+    if (t <= m) {
+      oa[t] = ea;
+      ob[t] = eb;
+    }
+    ea += va[k];
+    eb += vb[k];
+  }
+}
+
+__global__ void k_grid_scatter(const double* __restrict__ Z, int64_t n,
+                               const int32_t* __restrict__ cell3,
+                               const int32_t* __restrict__ start_tot,
+                               const int32_t* __restrict__ start_home, int32_t* cnt_tot,
+                               int32_t* cnt_home, Entry* __restrict__ entries, int64_t cap,
+                               int32_t* __restrict__ order, int32_t* overflow) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Entry en;
+  en.x = Z[3 * i];
+  en.y = Z[3 * i + 1];
+  en.z = Z[3 * i + 2];
+  en.idx = (int32_t)i;
+  en.pad = 0;
+  for (int k = 0; k < 3; k++) {
+    int32_t c = cell3[3 * i + k];
+    if (c < 0) continue;
+    int32_t pos = start_tot[c] + atomicSub(&cnt_tot[c], 1) - 1;
+    if (pos < cap) {
+      entries[pos] = en;
+    } else {
+      atomicOr(overflow, 1);
+    }
+    if (k == 0) {
+      int32_t ph = start_home[c] + atomicSub(&cnt_home[c], 1) - 1;
+      order[ph] = (int32_t)i;
+    }
+  }
+}
+
+__global__ void k_centroid(const double* __restrict__ mu, const double* __restrict__ m,
+                           double* __restrict__ out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 3; k++) out[3 * i + k] = mu[3 * i + k] / m[i];
+}
+
+hipError_t launch_centroid(const double* mu, const double* m, double* out, int64_t n,
+                           hipStream_t s) {
+  k_centroid<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(mu, m, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s) {
+  const int64_t m = gb.g.ncells;
+  unsigned nb = (unsigned)((n + 255) / 256);
+  k_grid_count<<<nb, 256, 0, s>>>(Z, n, gb.g, gb.cnt_tot, gb.cnt_home, gb.cell3);
+  int64_t ntiles = (m + 1 + kScanTile - 1) / kScanTile;
+  k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, s>>>(gb.cnt_tot, gb.cnt_home, m, gb.scan_tmp);
+  k_scan_sums<<<1, kScanBlock, 0, s>>>(gb.scan_tmp, ntiles);
+  k_scan_apply<<<(unsigned)ntiles, kScanBlock, 0, s>>>(gb.cnt_tot, gb.cnt_home, m, gb.scan_tmp,
+                                                      gb.start_tot, gb.start_home);
+  k_grid_scatter<<<nb, 256, 0, s>>>(Z, n, gb.cell3, gb.start_tot, gb.start_home, gb.cnt_tot,
+                                    gb.cnt_home, gb.entries, gb.cap_entries, gb.order,
+                                    gb.overflow);
+  return hipGetLastError();
+}
+
+}  // namespace scvt

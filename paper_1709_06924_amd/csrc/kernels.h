@@ -1,0 +1,85 @@
+// Internal declarations shared by the kernel files and the host engine.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cellgeom.h"
+
+namespace scvt {
+
+constexpr int kVmax = 32;          // max Voronoi edges per cell kept in debug output
+constexpr int kMaxCand = 64;       // candidates per wave in the certified path
+constexpr int kWinMax = 63;        // max window side in cells
+constexpr int kFbPolyMax = 64;     // polygon capacity of the fallback clipper
+
+// sorted grid entry: a generator (or a ghost copy of it) in one cell
+struct Entry {
+  double x, y, z;
+  int32_t idx;
+  int32_t pad;
+};
+
+// per-cell status bits
+enum CellFlags : uint8_t {
+  kFlagFallback = 1,    // built by the sequential fallback
+  kFlagDegenerate = 2,  // a predicate was within its error bound
+  kFlagError = 4,       // the fallback could not build the cell
+  kFlagBrute = 8,       // the fallback scanned every generator
+};
+
+struct EvalOut {  // per-generator results of one evaluation
+  double *m, *mu, *e, *g, *h, *lloyd;  // mu, g, lloyd are n x 3
+  double* R;                           // circumradius of the cell (next search radius)
+  uint8_t* flags;
+  int32_t* deg;
+  // optional debug copy of the cells: nbr n x kVmax, verts n x kVmax x 6
+  int32_t* cell_nbr;
+  double* cell_verts;
+};
+
+struct GridBufs {
+  GridP g;
+  int32_t* cnt_tot;    // ncells (+1)
+  int32_t* cnt_home;   // ncells (+1)
+  int32_t* start_tot;  // ncells + 1 (exclusive scan)
+  int32_t* start_home; // ncells + 1
+  int32_t* cell3;      // n x 3 cells of each generator (home, ghosts, -1)
+  Entry* entries;      // capacity cap_entries
+  int32_t* order;      // n: generators sorted by home cell
+  int64_t cap_entries;
+  int32_t* scan_tmp;   // block sums for the scan
+  int32_t* overflow;   // 1 int: set when entries exceed capacity
+};
+
+struct Counters {  // device-side counters of one evaluation
+  int32_t fb_count;
+  int32_t n_fallback, n_degenerate, n_error, n_brute;
+  int32_t pad[3];  // pad[0]: duplicate generators seen
+};
+
+struct CellArgs {
+  int64_t n;
+  const double* Z;  // n x 3 (unit rows)
+  GridBufs grid;
+  DensityP rho;
+  int levels;
+  int keep_cells;
+  int mixed;
+  int pad;
+  EvalOut out;
+  int32_t* fb_list;
+  Counters* ctr;
+  double r_default;  // initial search radius when no previous one is known
+};
+
+// ---- launch wrappers (return hipError_t) ----
+hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha, double* Zt,
+                                  int64_t n, hipStream_t s);
+hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s);
+hipError_t launch_cells_main(const CellArgs& a, hipStream_t s);
+hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s);
+hipError_t launch_centroid(const double* mu, const double* m, double* out, int64_t n,
+                           hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
+
+}  // namespace scvt

@@ -1,0 +1,210 @@
+// LBFGS two-loop recursion with the Lloyd preconditioner, history push and
+// the per-evaluation reductions, as fused streaming passes with grid
+// reductions finished by the last block to arrive (fixed summation order:
+// thread partials over a fixed grid-stride, block tree, then block partials
+// in block order -- the result is the same bits on every run).
+//
+// Two-loop (section 2.2.2, initial inverse Hessian replaced by diag(h),
+// section 3.1) over c stored pairs (oldest j = 0):
+//   q = -g;  for j = c-1..0: a_j = r_j s_j.q ; q -= a_j y_j
+//   q = h (.) q  (h_i on the three coordinates of generator i)
+//   for j = 0..c-1: b = r_j y_j.q ; q += (a_j - b) s_j
+// One pass per loop step: the axpy of step k is fused with the dot product
+// of step k+1, so the 2c+1 passes each stream q once.
+#include "kernels.h"
+#include "lbfgs.h"
+
+namespace scvt {
+
+constexpr int kRedBlock = 256;
+constexpr int kRedGrid = 1024;
+
+__device__ inline double block_sum(double v, double* sh) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+__device__ inline double block_max(double v, double* sh) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+__device__ inline double block_min(double v, double* sh) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmin(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// last-block election: returns true in exactly one block, after every
+// block's partials are visible
+__device__ inline bool last_block(unsigned* ticket) {
+  __shared__ bool is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = atomicAdd(ticket, 1u);
+    is_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last;
+}
+
+// ------------------------------------------------------------- two-loop pass
+__global__ __launch_bounds__(kRedBlock) void k_lbfgs_pass(PassArgs a) {
+  __shared__ double sh[kRedBlock];
+  double part = 0.0;
+  const double axc = a.ax_vec ? a.ax_sign * (*a.ax_coef) : 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n3;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double qk = a.init_neg_g ? -a.g[k] : a.q[k];
+    if (a.ax_vec) qk += axc * a.ax_vec[k];
+    if (a.scale_h) qk *= a.h[k / 3];
+    a.q[k] = qk;
+    part += a.dot_vec[k] * qk;
+  }
+  double bs = block_sum(part, sh);
+  if (threadIdx.x == 0) a.partials[blockIdx.x] = bs;
+  if (last_block(a.ticket)) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) v += a.partials[b];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+      double r = a.mul ? (*a.mul) * v : v;
+      *a.out = a.sub_from ? (*a.sub_from) - r : r;
+      *a.ticket = 0u;
+    }
+  }
+}
+
+// --------------------------------------------------------------- push pass
+// s = Zt - Z, y = gt - g into the ring slot; reduce y.s, y.y, s.s
+__global__ __launch_bounds__(kRedBlock) void k_push(PushArgs a) {
+  __shared__ double sh[kRedBlock];
+  double ys = 0.0, yy = 0.0, ss = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n3;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double s = a.Zt[k] - a.Z[k];
+    double y = a.gt[k] - a.g[k];
+    a.s[k] = s;
+    a.y[k] = y;
+    ys += y * s;
+    yy += y * y;
+    ss += s * s;
+  }
+  double b0 = block_sum(ys, sh), b1 = block_sum(yy, sh), b2 = block_sum(ss, sh);
+  if (threadIdx.x == 0) {
+    a.partials[3 * blockIdx.x] = b0;
+    a.partials[3 * blockIdx.x + 1] = b1;
+    a.partials[3 * blockIdx.x + 2] = b2;
+  }
+  if (last_block(a.ticket)) {
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+      v0 += a.partials[3 * b];
+      v1 += a.partials[3 * b + 1];
+      v2 += a.partials[3 * b + 2];
+    }
+    v0 = block_sum(v0, sh);
+    v1 = block_sum(v1, sh);
+    v2 = block_sum(v2, sh);
+    if (threadIdx.x == 0) {
+      a.out[0] = v0;
+      a.out[1] = v1;
+      a.out[2] = v2;
+      *a.r_slot = 1.0 / v0;
+      *a.ticket = 0u;
+    }
+  }
+}
+
+// ------------------------------------------------------ evaluation reduce
+// F = sum e_i, max |l_ik|, sum |g_i|^2, min mu_i . z_i
+__global__ __launch_bounds__(kRedBlock) void k_eval_reduce(EvalRedArgs a) {
+  __shared__ double sh[kRedBlock];
+  double F = 0.0, lmax = 0.0, gg = 0.0, mzmin = 1e300;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    F += a.e[i];
+    for (int k = 0; k < 3; k++) {
+      lmax = fmax(lmax, fabs(a.lloyd[3 * i + k]));
+      gg += a.g[3 * i + k] * a.g[3 * i + k];
+    }
+    double mz = a.mu[3 * i] * a.Z[3 * i] + a.mu[3 * i + 1] * a.Z[3 * i + 1] +
+                a.mu[3 * i + 2] * a.Z[3 * i + 2];
+    mzmin = fmin(mzmin, mz);
+    if (!(a.e[i] == a.e[i]) || !(mz == mz)) mzmin = -1.0;  // NaN guard
+  }
+  double b0 = block_sum(F, sh), b1 = block_max(lmax, sh), b2 = block_sum(gg, sh),
+         b3 = block_min(mzmin, sh);
+  if (threadIdx.x == 0) {
+    a.partials[4 * blockIdx.x] = b0;
+    a.partials[4 * blockIdx.x + 1] = b1;
+    a.partials[4 * blockIdx.x + 2] = b2;
+    a.partials[4 * blockIdx.x + 3] = b3;
+  }
+  if (last_block(a.ticket)) {
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 1e300;
+    for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+      v0 += a.partials[4 * b];
+      v1 = fmax(v1, a.partials[4 * b + 1]);
+      v2 += a.partials[4 * b + 2];
+      v3 = fmin(v3, a.partials[4 * b + 3]);
+    }
+    v0 = block_sum(v0, sh);
+    v1 = block_max(v1, sh);
+    v2 = block_sum(v2, sh);
+    v3 = block_min(v3, sh);
+    if (threadIdx.x == 0) {
+      a.out[0] = v0;
+      a.out[1] = v1;
+      a.out[2] = v2;
+      a.out[3] = v3;
+      *a.ticket = 0u;
+    }
+  }
+}
+
+static unsigned grid_for(int64_t count) {
+  int64_t b = (count + kRedBlock - 1) / kRedBlock;
+  if (b > kRedGrid) b = kRedGrid;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t launch_lbfgs_pass(const PassArgs& a, hipStream_t s) {
+  k_lbfgs_pass<<<grid_for(a.n3), kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_push(const PushArgs& a, hipStream_t s) {
+  k_push<<<grid_for(a.n3), kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_eval_reduce(const EvalRedArgs& a, hipStream_t s) {
+  k_eval_reduce<<<grid_for(a.n), kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+int reduce_grid_max() { return kRedGrid; }
+
+}  // namespace scvt

@@ -1,0 +1,241 @@
+"""ctypes binding of libscvt.so (include/scvt.h): argument marshalling only.
+
+Every step of the hot path runs in the HIP library; this module converts
+numpy arrays / torch tensors to pointers and status codes to exceptions.  It
+raises ImportError when the library has not been built -- there is no CPU
+fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscvt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libscvt.so is not built; run `python -m paper_1709_06924_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SCVT_OK, SCVT_NOT_CONVERGED, SCVT_PENDING = 0, 1, 2
+FP64, MIXED = 0, 1
+KIND = {"const": 0, "tanh": 1, "x3": 2, "x16": 3}
+KERNEL_CELLS, KERNEL_FALLBACK, KERNEL_GRID, KERNEL_LBFGS, KERNEL_EVAL = 0, 1, 2, 3, 4
+VMAX = 32
+
+
+class Density(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("geodesic", ctypes.c_int32), ("nbumps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("xc", ctypes.c_double * 6),
+                ("beta", ctypes.c_double * 2), ("alpha", ctypes.c_double * 2),
+                ("amp", ctypes.c_double * 2), ("gamma", ctypes.c_double),
+                ("w_lon", ctypes.c_double), ("w_lat", ctypes.c_double)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m_hist", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("rho", Density), ("quad_levels", ctypes.c_int32),
+                ("ls_max_evals", ctypes.c_int32), ("ls_c1", ctypes.c_double),
+                ("curv_eps", ctypes.c_double), ("keep_cells", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int64), ("n_evals", ctypes.c_int64), ("F", ctypes.c_double),
+                ("grad_norm2", ctypes.c_double), ("step_inf", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("n_fallback", ctypes.c_int64),
+                ("n_degenerate", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("hist_len", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+_H = ctypes.c_void_p
+_sig = {
+    "scvt_config_init": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_int64]),
+    "scvt_create": (ctypes.c_int, [ctypes.POINTER(Config), _vp, ctypes.c_int, ctypes.POINTER(_H)]),
+    "scvt_step": (ctypes.c_int, [_H, ctypes.POINTER(Info)]),
+    "scvt_solve": (ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(Info)]),
+    "scvt_energy": (ctypes.c_int, [_H, _dp, _vp, _vp, _vp, ctypes.c_int]),
+    "scvt_get_generators": (ctypes.c_int, [_H, _vp, ctypes.c_int]),
+    "scvt_get_vectors": (ctypes.c_int, [_H, ctypes.c_int, _vp, ctypes.c_int]),
+    "scvt_direction": (ctypes.c_int, [_H, _vp, ctypes.c_int, _dp]),
+    "scvt_get_cells": (ctypes.c_int, [_H, ctypes.c_int32, _vp, _vp, _vp, _vp]),
+    "scvt_get_state": (ctypes.c_int, [_H, _vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "scvt_set_state": (ctypes.c_int, [_H, _vp, ctypes.c_size_t]),
+    "scvt_set_timing": (ctypes.c_int, [_H, ctypes.c_int]),
+    "scvt_kernel_time": (ctypes.c_int, [_H, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int64)]),
+    "scvt_destroy": (None, [_H]),
+    "scvt_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class ScvtError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, _lib.scvt_strerror(code).decode(), code))
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise ScvtError(rc, what)
+    return rc
+
+
+def exported_symbols():
+    return list(_sig)
+
+
+def density_struct(d):
+    s = Density()
+    s.kind = KIND[d["kind"]]
+    s.geodesic = 1 if d.get("geodesic") else 0
+    xcs = d.get("xc", [])
+    s.nbumps = len(xcs)
+    for k, xc in enumerate(xcs[:2]):
+        for j in range(3):
+            s.xc[3 * k + j] = float(xc[j])
+    for name in ("beta", "alpha", "amp"):
+        for k, v in enumerate(d.get(name, [])[:2]):
+            getattr(s, name)[k] = float(v)
+    s.gamma = float(d.get("gamma", 0.0))
+    s.w_lon = float(d.get("w_lon", 1.0))
+    s.w_lat = float(d.get("w_lat", 1.0))
+    return s
+
+
+def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_max_evals=10,
+                ls_c1=1e-4, curv_eps=1e-10, keep_cells=False, stream=None):
+    c = Config()
+    _check(_lib.scvt_config_init(ctypes.byref(c), int(n)), "scvt_config_init")
+    c.m_hist = int(m_hist)
+    c.precision = MIXED if precision in ("mixed", MIXED) else FP64
+    c.rho = density_struct(density or {"kind": "const"})
+    c.quad_levels = int(quad_levels)
+    c.ls_max_evals = int(ls_max_evals)
+    c.ls_c1 = float(ls_c1)
+    c.curv_eps = float(curv_eps)
+    c.keep_cells = 1 if keep_cells else 0
+    c.hip_stream = stream
+    return c
+
+
+def _ptr(x, n_expected=None):
+    """(pointer, on_device) for a numpy array or a torch tensor."""
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"]
+        if n_expected is not None:
+            assert x.size == n_expected
+        return x.ctypes.data_as(ctypes.c_void_p), 0
+    # torch tensor
+    assert x.is_contiguous()
+    if n_expected is not None:
+        assert x.numel() == n_expected
+    return ctypes.c_void_p(x.data_ptr()), 1 if x.is_cuda else 0
+
+
+class Solver:
+    """One SCVT problem resident on the device (scvt_handle)."""
+
+    def __init__(self, z0, density=None, **kw):
+        n = z0.shape[0]
+        self.n = n
+        self.cfg = make_config(n, density, **kw)
+        if isinstance(z0, np.ndarray):
+            z0 = np.ascontiguousarray(z0, dtype=np.float64)
+        p, dev = _ptr(z0, 3 * n)
+        self._z0 = z0
+        h = _H()
+        _check(_lib.scvt_create(ctypes.byref(self.cfg), p, dev, ctypes.byref(h)), "scvt_create")
+        self.h = h
+        self.info = Info()
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.scvt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self):
+        _check(_lib.scvt_step(self.h, ctypes.byref(self.info)), "scvt_step")
+        return self.info.as_dict()
+
+    def solve(self, max_iter, tol):
+        rc = _check(_lib.scvt_solve(self.h, int(max_iter), float(tol), ctypes.byref(self.info)),
+                    "scvt_solve")
+        d = self.info.as_dict()
+        d["converged"] = rc == SCVT_OK
+        return d
+
+    def energy(self):
+        F = ctypes.c_double()
+        m = np.zeros(self.n)
+        c = np.zeros((self.n, 3))
+        e = np.zeros(self.n)
+        _check(_lib.scvt_energy(self.h, ctypes.byref(F), m.ctypes.data_as(ctypes.c_void_p),
+                                c.ctypes.data_as(ctypes.c_void_p),
+                                e.ctypes.data_as(ctypes.c_void_p), 0), "scvt_energy")
+        return F.value, m, c, e
+
+    def generators(self, out=None):
+        if out is None:
+            out = np.zeros((self.n, 3))
+        p, dev = _ptr(out, 3 * self.n)
+        _check(_lib.scvt_get_generators(self.h, p, dev), "scvt_get_generators")
+        return out
+
+    def vector(self, which):
+        names = {"g": 0, "h": 1, "lloyd": 2, "mu": 3, "q": 4, "R": 5}
+        w = names.get(which, which)
+        out = np.zeros(self.n) if w in (1, 5) else np.zeros((self.n, 3))
+        _check(_lib.scvt_get_vectors(self.h, w, out.ctypes.data_as(ctypes.c_void_p), 0),
+               "scvt_get_vectors")
+        return out
+
+    def direction(self):
+        q = np.zeros((self.n, 3))
+        gq = ctypes.c_double()
+        _check(_lib.scvt_direction(self.h, q.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(gq)),
+               "scvt_direction")
+        return q, gq.value
+
+    def cells(self):
+        nbr = np.zeros((self.n, VMAX), np.int32)
+        deg = np.zeros(self.n, np.int32)
+        verts = np.zeros((self.n, VMAX, 6))
+        flags = np.zeros(self.n, np.uint8)
+        _check(_lib.scvt_get_cells(self.h, VMAX, nbr.ctypes.data_as(ctypes.c_void_p),
+                                   deg.ctypes.data_as(ctypes.c_void_p),
+                                   verts.ctypes.data_as(ctypes.c_void_p),
+                                   flags.ctypes.data_as(ctypes.c_void_p)), "scvt_get_cells")
+        return nbr, deg, verts, flags
+
+    def get_state(self):
+        nb = ctypes.c_size_t()
+        _check(_lib.scvt_get_state(self.h, None, ctypes.byref(nb)), "scvt_get_state")
+        buf = ctypes.create_string_buffer(nb.value)
+        _check(_lib.scvt_get_state(self.h, buf, ctypes.byref(nb)), "scvt_get_state")
+        return buf.raw
+
+    def set_state(self, blob):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(_lib.scvt_set_state(self.h, buf, len(blob)), "scvt_set_state")
+
+    def set_timing(self, on=True):
+        _check(_lib.scvt_set_timing(self.h, 1 if on else 0), "scvt_set_timing")
+
+    def kernel_time(self, kernel):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(_lib.scvt_kernel_time(self.h, int(kernel), ctypes.byref(ms), ctypes.byref(cnt)),
+               "scvt_kernel_time")
+        return ms.value, cnt.value

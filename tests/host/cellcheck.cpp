@@ -1,0 +1,202 @@
+// Host build of the HIP path's geometry code (csrc/cellgeom.h) for the CPU
+// tests: runs the per-bisector edge construction the kernels run per lane,
+// the sequential fallback clipper, the window certificate and the cell
+// quadrature on the host, so that their logic is checked against the oracle
+// without a GPU.  Compiled by tests/test_hostcheck.py with hipcc.
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "cellgeom.h"
+
+using namespace scvt;
+
+extern "C" {
+
+// Certified-path construction for every generator with all generators
+// within chord radius rad[i] as candidates (emulates the wave: one loop
+// iteration per lane).  Outputs per cell: status (0 ok certified, 1
+// degenerate, 2 unbounded, 3 not certified, 4 too many candidates), deg,
+// nbr[i*32+k] sorted ascending, verts[(i*32+k)*6 + 0..5] edge endpoints.
+int hc_cells(int64_t n, const double* Z, const double* rad, int32_t* status, int32_t* deg,
+             int32_t* nbr, double* verts, double* Rout) {
+  std::vector<double> px(64), py(64), pz(64), dx(64), dy(64), dz(64);
+  std::vector<int> idx(64);
+  for (int64_t i = 0; i < n; i++) {
+    V3 z = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
+    int ns = 0;
+    bool over = false;
+    for (int64_t j = 0; j < n; j++) {
+      if (j == i) continue;
+      V3 p = V3{Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]};
+      V3 d = p - z;
+      if (dot(d, d) < rad[i] * rad[i]) {
+        if (ns == 64) {
+          over = true;
+          break;
+        }
+        px[ns] = p.x; py[ns] = p.y; pz[ns] = p.z;
+        dx[ns] = d.x; dy[ns] = d.y; dz[ns] = d.z;
+        idx[ns] = (int)j;
+        ns++;
+      }
+    }
+    deg[i] = 0;
+    for (int k = 0; k < 32; k++) nbr[i * 32 + k] = -1;
+    if (over) {
+      status[i] = 4;
+      continue;
+    }
+    CandView S = {px.data(), py.data(), pz.data(), dx.data(), dy.data(), dz.data()};
+    std::vector<EdgeRes> er(ns);
+    int st = 0;
+    for (int l = 0; l < ns; l++) {
+      er[l] = edge_on_bisector(l, ns, z, S);
+      if (er[l].status == kEdgeDegenerate) st = 1;
+      if (er[l].status == kEdgeUnbounded && st == 0) st = 2;
+    }
+    if (ns < 3 && st == 0) st = 2;
+    if (st) {
+      status[i] = st;
+      continue;
+    }
+    double r2 = 0.0;
+    int E = 0;
+    std::vector<int> en;
+    std::vector<V3> a0, a1;
+    for (int l = 0; l < ns; l++) {
+      if (er[l].status != kEdgeYes) continue;
+      V3 vlo = circumcentre((int)i, z, idx[l], S.p(l), idx[er[l].lo], S.p(er[l].lo));
+      V3 vhi = circumcentre((int)i, z, idx[l], S.p(l), idx[er[l].hi], S.p(er[l].hi));
+      V3 q0 = vlo - z, q1 = vhi - z;
+      r2 = fmax(r2, fmax(dot(q0, q0), dot(q1, q1)));
+      en.push_back(idx[l]);
+      a0.push_back(vlo);
+      a1.push_back(vhi);
+      E++;
+    }
+    Rout[i] = sqrt(r2);
+    if (!(4.0 * r2 * (1.0 + 1e-12) <= rad[i] * rad[i]) || E < 3 || E > 32) {
+      status[i] = 3;
+      continue;
+    }
+    status[i] = 0;
+    deg[i] = E;
+    for (int k = 0; k < E; k++) {
+      int rank = 0;
+      for (int t = 0; t < E; t++) rank += en[t] < en[k];
+      nbr[i * 32 + rank] = en[k];
+      double* v = verts + (i * 32 + rank) * 6;
+      v[0] = a0[k].x; v[1] = a0[k].y; v[2] = a0[k].z;
+      v[3] = a1[k].x; v[4] = a1[k].y; v[5] = a1[k].z;
+    }
+  }
+  return 0;
+}
+
+// Fallback clipper for cell i over all generators in index order.
+int hc_clip(int64_t n, const double* Z, int64_t i, int32_t* deg, int32_t* nbr, double* verts,
+            int32_t* flags, double* Rout) {
+  static ClipPoly C;
+  clip_reset(C);
+  V3 z = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
+  for (int64_t j = 0; j < n; j++) {
+    if (j == i) continue;
+    V3 p = V3{Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]};
+    V3 d = p - z;
+    if (dot(d, d) < 4.0 * C.R * C.R * (1.0 + 1e-9) + 1e-300) clip_offer(C, z, (int)j, p);
+  }
+  int32_t en[32];
+  double v0[96], v1[96];
+  auto pos = [&](int j) { return V3{Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]}; };
+  int E = clip_finish(C, (int)i, z, pos, en, v0, v1, 32);
+  *deg = E;
+  *flags = (C.err ? 4 : 0) | (C.degen ? 2 : 0);
+  *Rout = C.R;
+  for (int k = 0; k < 32; k++) nbr[k] = k < E ? en[k] : -1;
+  for (int k = 0; k < E; k++)
+    for (int c = 0; c < 3; c++) {
+      verts[6 * k + c] = v0[3 * k + c];
+      verts[6 * k + 3 + c] = v1[3 * k + c];
+    }
+  return 0;
+}
+
+// Cell integrals from fan edges (z, v0[k], v1[k]), k < E, as the kernels do.
+int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int levels,
+            double* out5) {
+  Acc5 acc = {0, 0, 0, 0, 0};
+  V3 z = V3{z3[0], z3[1], z3[2]};
+  const int per = 1 << (2 * levels);
+  for (int t = 0; t < E * per; t++) {
+    int e = t >> (2 * levels), s = t & (per - 1);
+    V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
+       C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
+    subtriangle(A, B, C, s, levels);
+    quad_tri(A, B, C, z, *D, acc);
+  }
+  out5[0] = acc.m;
+  out5[1] = acc.mx;
+  out5[2] = acc.my;
+  out5[3] = acc.mz;
+  out5[4] = acc.e;
+  return 0;
+}
+
+// Grid helpers: grid parameters for n, the window for (z, rt), the cell of
+// p on face f (-1 outside the face's extended grid).
+int hc_grid(int64_t n, int32_t* GBW, double* dd) {
+  int G = (int)llround(sqrt((double)n / 12.0));
+  if (G < 1) G = 1;
+  int B = (int)floor(0.45 * G);
+  if (B > 24) B = 24;
+  GBW[0] = G;
+  GBW[1] = B;
+  GBW[2] = G + 2 * B;
+  dd[0] = 1.5707963267948966 / G;
+  dd[1] = G / 1.5707963267948966;
+  dd[2] = -0.7853981633974483 - B * dd[0];
+  return 0;
+}
+
+static GridP gp(const int32_t* GBW, const double* dd) {
+  GridP g{};
+  g.G = GBW[0];
+  g.B = GBW[1];
+  g.W = GBW[2];
+  g.delta = dd[0];
+  g.inv_delta = dd[1];
+  g.a0 = dd[2];
+  g.ncells = 6LL * g.W * g.W;
+  return g;
+}
+
+int hc_window(const int32_t* GBW, const double* dd, const double* z3, double rt, int maxw,
+              int32_t* out5, double* D) {
+  GridP g = gp(GBW, dd);
+  V3 z = V3{z3[0], z3[1], z3[2]};
+  int f = home_face(z);
+  Window w = make_window(g, z, f, rt, maxw);
+  out5[0] = w.f;
+  out5[1] = w.ia_lo;
+  out5[2] = w.ia_hi;
+  out5[3] = w.ib_lo;
+  out5[4] = w.ib_hi;
+  *D = w.D;
+  return 0;
+}
+
+int hc_cell_on_face(const int32_t* GBW, const double* dd, int64_t n, const double* P, int f,
+                    int64_t* out) {
+  GridP g = gp(GBW, dd);
+  for (int64_t k = 0; k < n; k++) out[k] = cell_on_face(g, V3{P[3 * k], P[3 * k + 1], P[3 * k + 2]}, f);
+  return 0;
+}
+
+int hc_home_face(int64_t n, const double* P, int32_t* out) {
+  for (int64_t k = 0; k < n; k++) out[k] = home_face(V3{P[3 * k], P[3 * k + 1], P[3 * k + 2]});
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance (FP64 path): 1e-12 relative on m, mu, e, F, g, h, Lloyd step and
+the search direction q; neighbour sets bit-exact away from edges flagged
+near-degenerate by either side.
+"""
+import math
+from collections import defaultdict
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1709_06924_amd.inputs as I
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def scvt():
+    from paper_1709_06924_amd import scvt as mod
+    return mod
+
+
+def oracle_nbr_sets(Z, ev):
+    i, j, fl = oracle.neighbour_sets(Z, ev.cells)
+    nb = defaultdict(set)
+    flagged = set()
+    for a, b, f in zip(i, j, fl):
+        nb[a].add(b)
+        nb[b].add(a)
+        if f:
+            flagged.add((a, b))
+            flagged.add((b, a))
+    return nb, flagged
+
+
+def compare_eval(S, ev, n, check_cells=True):
+    F, m, cen, e = S.energy()
+    mu = S.vector("mu")
+    assert abs(F - ev.F) <= RTOL * ev.F, (F, ev.F)
+    assert np.max(np.abs(m - ev.m) / ev.m) <= RTOL
+    assert np.max(np.abs(e - ev.e) / ev.e) <= RTOL
+    scale = np.linalg.norm(ev.mu, axis=1)
+    assert np.max(np.linalg.norm(mu - ev.mu, axis=1) / scale) <= RTOL
+    assert np.max(np.linalg.norm(cen - ev.centroid, axis=1)) <= 1e-12
+    g = S.vector("g")
+    gs = np.max(np.abs(ev.g))
+    assert np.max(np.abs(g - ev.g)) <= RTOL * max(gs, 1e-300) + 1e-15 * np.max(np.abs(ev.mu))
+    h = S.vector("h")
+    assert np.max(np.abs(h - ev.h) / ev.h) <= RTOL
+    l = S.vector("lloyd")
+    assert np.max(np.abs(l - ev.lloyd)) <= 1e-13
+    if check_cells:
+        nbr, deg, verts, flags = S.cells()
+        nb, flagged = oracle_nbr_sets(ev.Z, ev)
+        for k in range(n):
+            got = set(nbr[k][:deg[k]].tolist())
+            want = nb[k]
+            diff = {x for x in got ^ want if (k, x) not in flagged}
+            if not (flags[k] & 2):
+                assert not diff, (k, got, want)
+
+
+@pytest.mark.parametrize("case", ["c1_const", "tanh_ragged", "x3", "two_centre", "geodesic"])
+def test_evaluation_parity(scvt, case):
+    n, d, seed = {
+        "c1_const": (2562, {"kind": "const"}, 1),
+        "tanh_ragged": (10007, I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8), 2),
+        "x3": (4099, I.density_x3(), 3),
+        "two_centre": (20011, I.density_two_centre(), 5),
+        "geodesic": (3001, I.density_tanh(I.latlon(-20, 40), math.pi / 9, 0.15, 16, True), 6),
+    }[case]
+    print("case", case, n, flush=True)
+    Z = I.uniform_sphere(n, seed)
+    ev = oracle.evaluate(Z, d)
+    S = scvt.Solver(Z, d, keep_cells=True)
+    compare_eval(S, ev, n)
+    S.close()
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 12, 31, 100, 256, 257, 300, 1000])
+def test_small_and_boundary_sizes(scvt, n):
+    print("n", n, flush=True)
+    Z = I.platonic({4: "tetra", 6: "octa", 12: "icosa"}[n]) if n in (4, 6, 12) else I.uniform_sphere(n, n)
+    d = I.density_tanh(I.latlon(10, 10), math.pi / 5, 0.3, 4)
+    ev = oracle.evaluate(Z, d)
+    S = scvt.Solver(Z, d, keep_cells=True)
+    compare_eval(S, ev, n)
+
+
+def test_degenerate_cube(scvt):
+    P = I.platonic("cube")
+    S = scvt.Solver(P, {"kind": "const"}, keep_cells=True)
+    F, m, c, e = S.energy()
+    ev = oracle.evaluate(P, {"kind": "const"})
+    assert abs(F - ev.F) <= 1e-12 * ev.F
+    assert np.max(np.abs(m - ev.m)) <= 1e-12
+    assert np.max(np.abs(S.vector("lloyd"))) < 1e-14
+
+
+def test_duplicate_generators_rejected(scvt):
+    Z = I.uniform_sphere(500, 3)
+    Z[7] = Z[100]
+    with pytest.raises(scvt.ScvtError) as e:
+        scvt.Solver(Z)
+    assert e.value.code == -3
+
+
+def test_direction_parity_with_history(scvt):
+    n = 3000
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    S = scvt.Solver(I.uniform_sphere(n, 7), d, m_hist=5)
+    for _ in range(7):
+        S.step()
+    blob = S.get_state()
+    # unpack the state blob: header, alpha, Z, then (r, s, y) oldest first
+    hdr = np.frombuffer(blob[:64], dtype=np.int64)
+    c = int(hdr[3])
+    arr = np.frombuffer(blob[64:], dtype=np.float64)
+    Z = arr[1:1 + 3 * n].reshape(n, 3)
+    hist = []
+    off = 1 + 3 * n
+    for _ in range(c):
+        r = arr[off]
+        s = arr[off + 1:off + 1 + 3 * n].reshape(n, 3)
+        y = arr[off + 1 + 3 * n:off + 1 + 6 * n].reshape(n, 3)
+        hist.append((s, y, r))
+        off += 1 + 6 * n
+    assert c == 5
+    ev = oracle.evaluate(Z, d)
+    q_ref = oracle.two_loop(ev.g, ev.h, hist)
+    q, gq = S.direction()
+    assert np.linalg.norm(q - q_ref) <= RTOL * np.linalg.norm(q_ref) * 10
+    assert abs(gq - oracle.dot(ev.g, q_ref)) <= 1e-11 * abs(gq)
+    # stored pairs themselves: r = 1/(y.s)
+    for s, y, r in hist:
+        assert abs(r * oracle.dot(y, s) - 1.0) < 1e-13
+
+
+def test_first_step_is_lloyd_and_trajectory(scvt):
+    n = 2562
+    d = {"kind": "const"}
+    Z0 = I.uniform_sphere(n, 1)
+    S = scvt.Solver(Z0, d, m_hist=7)
+    O = oracle.Solver(Z0, d, m_hist=7)
+    dev = []
+    for k in range(10):
+        info = S.step()
+        O.step()
+        Zg = S.generators()
+        dev.append(np.max(np.abs(Zg - O.Z)))
+        assert info["alpha"] == O.last_alpha
+        assert abs(info["F"] - O.cur.F) <= 1e-10 * O.cur.F
+    print("trajectory deviation per iteration", dev)
+    assert dev[0] < 1e-14          # Lloyd step
+    assert max(dev) < 1e-9
+
+
+def test_m0_is_lloyd_iteration(scvt):
+    n = 1500
+    d = I.density_x3()
+    Z0 = I.uniform_sphere(n, 8)
+    S = scvt.Solver(Z0, d, m_hist=0)
+    O = oracle.Solver(Z0, d, m_hist=0)
+    for _ in range(3):
+        S.step()
+        O.step()
+    assert np.max(np.abs(S.generators() - O.Z)) < 1e-13
+
+
+def test_monotone_energy_and_counts(scvt):
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    S = scvt.Solver(I.uniform_sphere(5000, 9), d, m_hist=7)
+    F = [S.energy()[0]]
+    for _ in range(30):
+        info = S.step()
+        F.append(info["F"])
+    assert np.all(np.diff(F) <= 0)
+    assert info["n_evals"] >= info["iter"] + 1
+    assert info["hist_len"] == 7
+
+
+def test_checkpoint_resume_bitwise(scvt):
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    Z0 = I.uniform_sphere(4000, 10)
+    A = scvt.Solver(Z0, d)
+    for _ in range(8):
+        A.step()
+    ZA = A.generators()
+    B = scvt.Solver(Z0, d)
+    for _ in range(4):
+        B.step()
+    blob = B.get_state()
+    C = scvt.Solver(Z0, d)
+    C.set_state(blob)
+    for _ in range(4):
+        C.step()
+    assert np.array_equal(C.generators(), ZA)
+    assert C.energy()[0] == A.energy()[0]
+
+
+def test_run_to_run_bitwise(scvt):
+    d = I.density_two_centre()
+    Z0 = I.uniform_sphere(30000, 11)
+    out = []
+    for _ in range(2):
+        S = scvt.Solver(Z0, d, m_hist=10)
+        for _ in range(3):
+            S.step()
+        out.append((S.generators(), S.energy()[0]))
+        S.close()
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+def test_full_size_sampled(scvt):
+    """n = 1,048,576 with the 16x tanh density, in the configuration the
+    benchmark times: totals against 1-D quadrature, Euler counts, symmetric
+    neighbour relation, and sampled cells against the oracle's
+    neighbourhood-only cells."""
+    from scipy import integrate
+    cfg = I.CONFIGS["C3"]
+    n, d = cfg["n"], cfg["density"]
+    Z = I.uniform_sphere(n, cfg["seed"])
+    S = scvt.Solver(Z, d, m_hist=cfg["m_hist"], keep_cells=True)
+    F, m, cen, e = S.energy()
+    mu = S.vector("mu")
+    nbr, deg, verts, flags = S.cells()
+    assert deg.sum() == 6 * n - 12
+    g, a, b, amp = d["gamma"], d["alpha"][0], d["beta"][0], d["amp"][0]
+    rho = lambda t: g + amp * 0.5 * (math.tanh((b - 2 * math.sin(t / 2)) / a) + 1)
+    M = 2 * math.pi * integrate.quad(lambda t: rho(t) * math.sin(t), 0, math.pi, epsabs=0,
+                                     epsrel=1e-13, limit=400)[0]
+    assert abs(m.sum() - M) / M < 1e-10
+    rng = np.random.default_rng(0)
+    sample = rng.choice(n, 64, replace=False)
+    h = math.sqrt(4 * math.pi / n)
+    for i in sample:
+        for j in nbr[i][:deg[i]]:
+            assert i in nbr[j][:deg[j]]
+        nb, vv, om, omu, oe = oracle.local_cell(Z, i, d, 8 * h)
+        assert set(nb) == set(nbr[i][:deg[i]].tolist())
+        assert abs(m[i] - om) <= RTOL * om
+        assert np.linalg.norm(mu[i] - omu) <= RTOL * np.linalg.norm(omu)
+        assert abs(e[i] - oe) <= RTOL * oe
+    # two steps in the benchmark's configuration stay finite and decrease F
+    info = S.step()
+    info = S.step()
+    assert info["F"] < F

@@ -1,0 +1,174 @@
+"""CPU checks of the HIP path's geometry and quadrature code (host build of
+csrc/cellgeom.h, see tests/host/cellcheck.cpp) against the oracle.
+
+These run the very functions the kernels call per lane, sequentially on the
+host: the per-bisector edge construction with its certificate, the
+sequential fallback clipper, the window certificate of the cube-map grid and
+the fan quadrature.  The GPU parity tests then check the wave-level drivers.
+"""
+import math
+from collections import defaultdict
+
+import numpy as np
+import pytest
+
+import hostcheck as hc
+import oracle
+import paper_1709_06924_amd.inputs as I
+
+
+def oracle_nbrs(Z):
+    C = oracle.cells(Z)
+    i, j, fl = oracle.neighbour_sets(Z, C)
+    nb = defaultdict(set)
+    for a, b in zip(i, j):
+        nb[a].add(b)
+        nb[b].add(a)
+    return C, nb, {(a, b) for a, b, f in zip(i, j, fl) if f}
+
+
+def oracle_cell_edges(C, k):
+    """{neighbour: (v_start, v_end)} of the oracle's cell k."""
+    out = {}
+    verts = C.verts[C.ptr[k]:C.ptr[k + 1]]
+    fac = C.fac[C.ptr[k]:C.ptr[k + 1]]
+    d = len(verts)
+    for t in range(d):
+        f0, f1 = set(C.F[fac[t]]), set(C.F[fac[(t + 1) % d]])
+        common = (f0 & f1) - {k}
+        assert len(common) == 1
+        out[common.pop()] = (verts[t], verts[(t + 1) % d])
+    return out
+
+
+@pytest.mark.parametrize("n,seed", [(500, 1), (3000, 2)])
+def test_certified_cells_match_oracle(n, seed):
+    Z = I.uniform_sphere(n, seed)
+    C, nb, _ = oracle_nbrs(Z)
+    h = math.sqrt(4 * math.pi / n)
+    st, deg, nbr, verts, R = hc.cells(Z, 3.5 * h)
+    ok = np.where(st == 0)[0]
+    assert len(ok) > 0.95 * n
+    for k in ok:
+        got = nbr[k][:deg[k]].tolist()
+        assert set(got) == nb[k]
+        ed = oracle_cell_edges(C, k)
+        for t, j in enumerate(got):
+            v0, v1 = ed[j]
+            assert np.max(np.abs(verts[k, t, :3] - v0)) < 1e-14
+            assert np.max(np.abs(verts[k, t, 3:] - v1)) < 1e-14
+
+
+def test_retry_policy_certifies_nearly_all():
+    """The kernel's retry policy (grow the radius to min(2.1 R, 1.6 r) after
+    an uncertified attempt, 1.6 r after an unbounded one, shrink toward 48
+    candidates on overflow) certifies almost every cell of random input."""
+    n = 3000
+    Z = I.uniform_sphere(n, 2)
+    h = math.sqrt(4 * math.pi / n)
+    rt = np.full(n, 2.0 * h)
+    done = np.zeros(n, bool)
+    for attempt in range(8):
+        st, deg, nbr, verts, R = hc.cells(Z, rt)
+        done |= st == 0
+        rt = np.where(st == 3, np.minimum(2.1 * R, 1.6 * rt), rt)
+        rt = np.where(st == 2, 1.6 * rt, rt)
+        rt = np.where(st == 4, rt * 0.7, rt)
+    assert done.mean() > 0.998
+
+
+def test_certificate_is_sound():
+    """A cell certified with a small candidate set equals the one built from
+    all generators (brute force within radius 2)."""
+    n = 800
+    Z = I.uniform_sphere(n, 9)
+    h = math.sqrt(4 * math.pi / n)
+    st, deg, nbr, verts, R = hc.cells(Z, 2.4 * h)
+    st_all, deg_all, nbr_all, verts_all, _ = hc.cells(Z, np.full(n, 2.0001))
+    for k in np.where(st == 0)[0]:
+        if st_all[k] == 4:  # more than 64 within radius 2: skip
+            continue
+        assert np.array_equal(nbr[k], nbr_all[k])
+        assert np.array_equal(verts[k], verts_all[k])
+
+
+@pytest.mark.parametrize("name", ["tetra", "octa", "icosa", "cube"])
+def test_fallback_clipper_platonic(name):
+    P = I.platonic(name)
+    C, nb, flagged = oracle_nbrs(P)
+    ev = oracle.evaluate(P, {"kind": "const"})
+    for k in range(len(P)):
+        deg, nbr, verts, flags, R = hc.clip(P, k)
+        assert deg >= 3 and not (flags & 4)
+        out = hc.quad(P[k], deg, verts, {"kind": "const"})
+        assert abs(out[0] - ev.m[k]) < 1e-12 * ev.m[k]
+        assert np.max(np.abs(out[1:4] - ev.mu[k])) < 1e-12
+        assert abs(out[4] - ev.e[k]) < 1e-12 * ev.e[k]
+        if name != "cube":
+            assert set(nbr[:deg].tolist()) == nb[k]
+
+
+@pytest.mark.parametrize("n,seed", [(4, 0), (5, 1), (9, 2), (40, 3), (600, 4)])
+def test_fallback_clipper_random(n, seed):
+    Z = I.uniform_sphere(n, seed)
+    C, nb, _ = oracle_nbrs(Z)
+    for k in range(n):
+        deg, nbr, verts, flags, R = hc.clip(Z, k)
+        assert not (flags & 4)
+        assert set(nbr[:deg].tolist()) == nb[k]
+        ed = oracle_cell_edges(C, k)
+        for t, j in enumerate(nbr[:deg]):
+            v0, v1 = ed[j]
+            assert np.max(np.abs(verts[t, :3] - v0)) < 1e-13
+            assert np.max(np.abs(verts[t, 3:] - v1)) < 1e-13
+
+
+@pytest.mark.parametrize("density", ["const", "tanh", "tanh_geo", "x3", "x16", "two"])
+def test_quadrature_matches_oracle(density):
+    d = {"const": {"kind": "const"},
+         "tanh": I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8),
+         "tanh_geo": I.density_tanh(I.latlon(10, 20), math.pi / 9, 0.15, 16, geodesic=True),
+         "x3": I.density_x3(), "x16": I.density_x16(), "two": I.density_two_centre()}[density]
+    n = 1500
+    Z = I.uniform_sphere(n, 5)
+    ev = oracle.evaluate(Z, d)
+    h = math.sqrt(4 * math.pi / n)
+    st, deg, nbr, verts, R = hc.cells(Z, 4.0 * h)
+    worst = [0.0, 0.0, 0.0]
+    for k in np.where(st == 0)[0]:
+        out = hc.quad(Z[k], deg[k], verts[k], d)
+        worst[0] = max(worst[0], abs(out[0] - ev.m[k]) / ev.m[k])
+        worst[1] = max(worst[1], np.linalg.norm(out[1:4] - ev.mu[k]) / np.linalg.norm(ev.mu[k]))
+        worst[2] = max(worst[2], abs(out[4] - ev.e[k]) / ev.e[k])
+    assert max(worst) < 1e-12, worst
+
+
+@pytest.mark.parametrize("n", [300, 2562, 100000])
+def test_window_certificate_covers_ball(n):
+    """Every generator within the window's certified radius D of z is stored
+    in the window's cells on z's home face (home or ghost copy)."""
+    GBW, dd = hc.grid(n)
+    W = GBW[2]
+    X = I.uniform_sphere(20000, 1)
+    Z = I.uniform_sphere(300, 2)
+    h = math.sqrt(4 * math.pi / n)
+    for z in Z:
+        for rt in (2.0 * h, 6.0 * h, 20.0 * h):
+            (f, alo, ahi, blo, bhi), D = hc.window(GBW, dd, z, rt)
+            if D <= 0:
+                continue
+            near = X[np.linalg.norm(X - z, axis=1) < D]
+            c = hc.cell_on_face(GBW, dd, near, f)
+            assert np.all(c >= 0)
+            loc = c - f * W * W
+            ia, ib = loc % W, loc // W
+            assert np.all((ia >= alo) & (ia <= ahi) & (ib >= blo) & (ib <= bhi))
+
+
+def test_home_face_inside_its_grid():
+    GBW, dd = hc.grid(100000)
+    X = I.uniform_sphere(50000, 3)
+    hf = hc.home_face(X)
+    for f in range(6):
+        sel = X[hf == f]
+        assert np.all(hc.cell_on_face(GBW, dd, sel, f) >= 0)

@@ -218,3 +218,19 @@ def test_total_mass_x3():
     g = 3.0 ** -4
     exact = (1 - g) * 4 * math.pi / 5 + 4 * math.pi * g
     assert abs(ev.m.sum() - exact) / exact < 1e-10
+
+
+def test_local_cell_equals_global():
+    """The neighbourhood-only cell (used for sampled checks at full size)
+    equals the global one."""
+    n = 5000
+    Z = I.uniform_sphere(n, 21)
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    ev = oracle.evaluate(Z, d)
+    h = math.sqrt(4 * math.pi / n)
+    for i in range(0, n, 499):
+        nb, verts, m, mu, e = oracle.local_cell(Z, i, d, 6 * h)
+        assert abs(m - ev.m[i]) <= 1e-14 * ev.m[i]
+        assert np.max(np.abs(mu - ev.mu[i])) <= 1e-15
+        assert abs(e - ev.e[i]) <= 1e-14 * ev.e[i]
+        assert len(nb) == ev.cells.deg()[i]
