@@ -175,7 +175,12 @@ static void tri_rule(const oracle_density *D, const double *z, const double *A,
                      const double *B, const double *C, acc5 *acc) {
   double lam[21], w[7];
   oracle_rule7(lam, w);
-  double half_det = 0.5 * det3(A, B, C);
+  /* det(A,B,C) = det(A, B-A, C-A): the same value, computed from the
+   * differences of the nearby vertices so that small sub-triangles do not
+   * lose digits to cancellation */
+  double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+  double v[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+  double half_det = 0.5 * det3(A, u, v);
   for (int q = 0; q < 7; q++) {
     double p[3];
     for (int k = 0; k < 3; k++)
