@@ -30,8 +30,11 @@ SCVT_HD double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 SCVT_HD V3 cross(V3 a, V3 b) {
   return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
+// a / |a| with one rounding per operation (no fused multiply-add): the same
+// bits as ((x*x + y*y) + z*z), sqrt, divide evaluated anywhere else
 SCVT_HD V3 normalized(V3 a) {
-  double r = sqrt(dot(a, a));
+#pragma clang fp contract(off)
+  double r = sqrt(a.x * a.x + a.y * a.y + a.z * a.z);
   return V3{a.x / r, a.y / r, a.z / r};
 }
 
@@ -84,7 +87,11 @@ SCVT_HD Pred det_cached(const CrossCache& k, V3 l) {
 // equidistant from all three, on their side.  Computed from the triple in
 // increasing index order so that every cell that meets at the vertex gets the
 // same bits: normalize((p_b - p_a) x (p_c - p_a)), signed so that v . p_a > 0.
+// Evaluated without fused multiply-adds (one rounding per operation), so the
+// vertex of an ill-conditioned thin triple is the same bits as the plain
+// formula evaluated anywhere else.
 SCVT_HD V3 circumcentre(int ia, V3 pa, int ib, V3 pb, int ic, V3 pc) {
+#pragma clang fp contract(off)
   if (ia > ib) {
     int t = ia; ia = ib; ib = t;
     V3 s = pa; pa = pb; pb = s;
@@ -97,9 +104,21 @@ SCVT_HD V3 circumcentre(int ia, V3 pa, int ib, V3 pb, int ic, V3 pc) {
     int t = ia; ia = ib; ib = t;
     V3 s = pa; pa = pb; pb = s;
   }
-  V3 w = normalized(cross(pb - pa, pc - pa));
-  if (dot(w, pa) < 0.0) w = -w;
-  return w;
+  const double ux = pb.x - pa.x, uy = pb.y - pa.y, uz = pb.z - pa.z;
+  const double vx = pc.x - pa.x, vy = pc.y - pa.y, vz = pc.z - pa.z;
+  double wx = uy * vz - uz * vy;
+  double wy = uz * vx - ux * vz;
+  double wz = ux * vy - uy * vx;
+  const double r = sqrt(wx * wx + wy * wy + wz * wz);
+  wx = wx / r;
+  wy = wy / r;
+  wz = wz / r;
+  if (wx * pa.x + wy * pa.y + wz * pa.z < 0.0) {
+    wx = -wx;
+    wy = -wy;
+    wz = -wz;
+  }
+  return V3{wx, wy, wz};
 }
 
 // ------------------------------------------ edge of the cell on one bisector
@@ -254,7 +273,10 @@ struct Acc5 {
 //   int_sph f dsigma = det(A,B,C)/2 * sum_q w_q f(p_q/|p_q|) / |p_q|^3.
 SCVT_HD void quad_tri(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
   const Rule7 R = rule7();
-  const double hd = 0.5 * dot(A, cross(B, C));
+  // det(A,B,C) = A . ((B-A) x (C-A)): the differences of nearby unit vectors
+  // are exact to a rounding, so small sub-triangles keep full relative
+  // accuracy (the plain triple product cancels ~log10(1/size) digits)
+  const double hd = 0.5 * dot(A, cross(B - A, C - A));
   for (int q = 0; q < 7; q++) {
     V3 p = R.l[q][0] * A + R.l[q][1] * B + R.l[q][2] * C;
     double r2 = dot(p, p);

@@ -25,9 +25,11 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s) 
 // trial point: Zt = normalize(Z + alpha q) (q == nullptr: normalize Z)
 __global__ void k_normalize_trial(const double* __restrict__ Z, const double* __restrict__ q,
                                   double alpha, double* __restrict__ Zt, int64_t n) {
+#pragma clang fp contract(off)
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   V3 z = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
+  // z + alpha q with one rounding per operation, then z / |z|
   if (q) z = z + alpha * V3{q[3 * i], q[3 * i + 1], q[3 * i + 2]};
   V3 w = normalized(z);
   Zt[3 * i] = w.x;
