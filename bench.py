@@ -1,0 +1,176 @@
+"""Benchmark: SCVT P-LBFGS iterations per second at 1,048,576 generators.
+
+Workload (one "step" = one Lloyd-preconditioned LBFGS iteration: two-loop
+direction, Armijo line search with projected trial points, each trial a full
+Voronoi build + cell quadrature + gradient/preconditioner/Lloyd step, and the
+history update): n = 1,048,576 uniform random generators (seed 3), tanh
+density with 16x spacing ratio (x_c at lat 30 lon 90, beta = pi/9,
+alpha = 0.15), M = 10.  Generators start resident in HBM; the timed region is
+K iterations from the seeded start, bracketed by device synchronisation.
+
+Prints one JSON line.  Options: --steps K (default 200, the workload's
+iteration count), --warmup W, --precision fp64|mixed|both, --no-cpu-baseline.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SCVT iterations/sec at 1M generators (FP64 vs mixed); p50/p99 solve latency"
+
+# MI355X published peaks used as roofline denominators
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops_per_point():
+    """FP64 operations of one quadrature point of the tanh density as the
+    formula is written ('Algorithmic work'): multiply, add,
+    divide and square root count 1, fused multiply-add 2; tanh counts as
+    the 20 operations of its exp-based evaluation."""
+    point = 15 + 5 + 1 + 1 + 3 + 2 + 3 + 3 + 5 + 1 + 6 + 2   # position, Jacobian, moments
+    rho = 3 + 5 + 1 + 1 + 1 + 20 + 1 + 2 + 1                  # chord, tanh bump
+    subtri = (2 * 3 * 12 + 22) / 7.0                          # subdivision + Jacobian, per point
+    return point + rho + subtri
+
+
+def cell_flops(mean_degree, levels=2):
+    return mean_degree * (4 ** levels) * 7 * algorithmic_flops_per_point()
+
+
+def run_gpu(args, precision, Z0_dev, cfg, stream):
+    import torch
+
+    from paper_1709_06924_amd import scvt
+    kw = dict(m_hist=cfg["m_hist"], precision=precision, stream=stream)
+    if args.warmup > 0:
+        W = scvt.Solver(Z0_dev, cfg["density"], **kw)
+        for _ in range(args.warmup):
+            W.step()
+        W.close()
+    S = scvt.Solver(Z0_dev, cfg["density"], keep_cells=False, **kw)
+    F0 = S.energy()[0]
+    S.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = S.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = {"elapsed_s": t1 - t0, "info": info, "F0": F0}
+    for name, k in (("cells", scvt.KERNEL_CELLS), ("fallback", scvt.KERNEL_FALLBACK),
+                    ("grid", scvt.KERNEL_GRID), ("lbfgs", scvt.KERNEL_LBFGS),
+                    ("eval", scvt.KERNEL_EVAL)):
+        ms, cnt = S.kernel_time(k)
+        out[name] = {"total_ms": ms, "launches": cnt}
+    deg = None
+    try:
+        S2 = scvt.Solver(S.generators(), cfg["density"], keep_cells=True, m_hist=0,
+                         precision=precision, stream=stream)
+        _, deg, _, _ = S2.cells()
+        out["mean_degree"] = float(deg.mean())
+        S2.close()
+    except Exception:  # pragma: no cover - informational only
+        out["mean_degree"] = 6.0
+    S.close()
+    return out
+
+
+def cpu_baseline(cfg, Z0):
+    import oracle
+    from oracle import _clib
+    S = oracle.Solver(Z0, cfg["density"], m_hist=cfg["m_hist"])  # initial evaluation, untimed
+    t0 = time.perf_counter()
+    S.step()
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "iterations/s", "cores": int(_clib.lib().oracle_num_threads()),
+            "kind": "oracle",
+            "sample": "one FP64 oracle P-LBFGS iteration (Qhull hull, C cell integrals, numpy "
+                      "two-loop) at n=1,048,576 from the seeded start; %d evaluation(s), %.1f s"
+                      % (S.n_evals - 1, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
+              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1709_06924_amd.inputs as I
+    cfg = I.CONFIGS["C3"]
+    n = cfg["n"]
+    Z0 = I.uniform_sphere(n, cfg["seed"])
+    torch.cuda.set_device(0)
+    Z0_dev = torch.from_numpy(Z0).to("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    print("bench: n=%d steps=%d warmup=%d" % (n, args.steps, args.warmup), file=sys.stderr,
+          flush=True)
+
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    runs = {}
+    for p in precisions:
+        runs[p] = run_gpu(args, p, Z0_dev, cfg, stream)
+        r = runs[p]
+        print("bench: %s %.3f it/s (%d evals)" % (p, args.steps / r["elapsed_s"], r["info"]["n_evals"]),
+              file=sys.stderr, flush=True)
+
+    main_p = precisions[0]
+    r = runs[main_p]
+    value = args.steps / r["elapsed_s"]
+    cells = r["cells"]
+    avg_ms = cells["total_ms"] / max(cells["launches"], 1)
+    flops = cell_flops(r["mean_degree"]) * n
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 / value,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_p == "fp64" else "f32-quadrature/f64-geometry",
+        "data": "synthetic",
+        "config": {"workload": "n=1048576 uniform start (seed 3), tanh density 16x "
+                               "(lat 30 lon 90, beta pi/9, alpha 0.15), M=10, %s" % main_p,
+                   "n": n, "m_hist": cfg["m_hist"], "quad": "7-point, 2 levels",
+                   "evals": r["info"]["n_evals"] - 1, "F_start": r["F0"],
+                   "F_end": r["info"]["F"], "step_inf_end": r["info"]["step_inf"]},
+        "kernels_ms_per_eval": {k: r[k]["total_ms"] / max(r[k]["launches"], 1)
+                                for k in ("cells", "fallback", "grid", "eval")},
+        "lbfgs_ms_per_iter": r["lbfgs"]["total_ms"] / max(r["lbfgs"]["launches"], 1),
+        "roofline": {"kernel": "k_cells", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops, "avg_launch_ms": avg_ms,
+                     "mean_degree": r["mean_degree"]},
+    }
+    for p in precisions[1:]:
+        rr = runs[p]
+        line[p] = {"value": args.steps / rr["elapsed_s"], "unit": "iterations/s",
+                   "cells_ms_per_eval": rr["cells"]["total_ms"] / max(rr["cells"]["launches"], 1),
+                   "F_end": rr["info"]["F"]}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, Z0)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
