@@ -63,20 +63,12 @@ def run_gpu(args, precision, Z0_dev, cfg, stream):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     out = {"elapsed_s": t1 - t0, "info": info, "F0": F0}
-    for name, k in (("cells", scvt.KERNEL_CELLS), ("fallback", scvt.KERNEL_FALLBACK),
+    for name, k in (("geom", scvt.KERNEL_CELLS), ("fallback", scvt.KERNEL_FALLBACK),
                     ("grid", scvt.KERNEL_GRID), ("lbfgs", scvt.KERNEL_LBFGS),
-                    ("eval", scvt.KERNEL_EVAL)):
+                    ("eval", scvt.KERNEL_EVAL), ("quad", scvt.KERNEL_QUAD)):
         ms, cnt = S.kernel_time(k)
         out[name] = {"total_ms": ms, "launches": cnt}
-    deg = None
-    try:
-        S2 = scvt.Solver(S.generators(), cfg["density"], keep_cells=True, m_hist=0,
-                         precision=precision, stream=stream)
-        _, deg, _, _ = S2.cells()
-        out["mean_degree"] = float(deg.mean())
-        S2.close()
-    except Exception:  # pragma: no cover - informational only
-        out["mean_degree"] = 6.0
+    out["mean_degree"] = float(S.degrees().mean())
     S.close()
     return out
 
@@ -131,8 +123,8 @@ def main():
     main_p = precisions[0]
     r = runs[main_p]
     value = args.steps / r["elapsed_s"]
-    cells = r["cells"]
-    avg_ms = cells["total_ms"] / max(cells["launches"], 1)
+    quad = r["quad"]
+    avg_ms = quad["total_ms"] / max(quad["launches"], 1)
     flops = cell_flops(r["mean_degree"]) * n
     achieved = flops / (avg_ms * 1e-3) / 1e12
     line = {
@@ -154,9 +146,9 @@ def main():
                    "evals": r["info"]["n_evals"] - 1, "F_start": r["F0"],
                    "F_end": r["info"]["F"], "step_inf_end": r["info"]["step_inf"]},
         "kernels_ms_per_eval": {k: r[k]["total_ms"] / max(r[k]["launches"], 1)
-                                for k in ("cells", "fallback", "grid", "eval")},
+                                for k in ("geom", "fallback", "quad", "grid", "eval")},
         "lbfgs_ms_per_iter": r["lbfgs"]["total_ms"] / max(r["lbfgs"]["launches"], 1),
-        "roofline": {"kernel": "k_cells", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "k_quad", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
                      "flops_per_launch": flops, "avg_launch_ms": avg_ms,
@@ -165,7 +157,7 @@ def main():
     for p in precisions[1:]:
         rr = runs[p]
         line[p] = {"value": args.steps / rr["elapsed_s"], "unit": "iterations/s",
-                   "cells_ms_per_eval": rr["cells"]["total_ms"] / max(rr["cells"]["launches"], 1),
+                   "quad_ms_per_eval": rr["quad"]["total_ms"] / max(rr["quad"]["launches"], 1),
                    "F_end": rr["info"]["F"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, Z0)

@@ -171,9 +171,10 @@ int scvt_get_state(scvt_handle* h, void* buf, size_t* bytes);
 int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes);
 
 /* Kernel timing (HIP events on the handle's stream, enabled by
- * scvt_set_timing): kernel 0 = cell kernel (certified path), 1 = fallback
- * kernel, 2 = grid build, 3 = two-loop passes, 4 = whole evaluation.
- * Returns accumulated milliseconds and launch count since enabling. */
+ * scvt_set_timing): kernel 0 = certified cell geometry kernel, 1 = fallback
+ * clipper, 2 = grid build, 3 = two-loop passes, 4 = whole evaluation,
+ * 5 = cell quadrature kernel.  Returns accumulated milliseconds and launch
+ * count since enabling. */
 int scvt_set_timing(scvt_handle* h, int enable);
 int scvt_kernel_time(scvt_handle* h, int kernel, double* total_ms, int64_t* launches);
 

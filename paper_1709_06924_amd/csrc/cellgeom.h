@@ -206,7 +206,23 @@ struct DensityP {
   double xc[2][3];
   double beta[2], alpha[2], amp[2];
   double gamma, w_lon, w_lat;
+  double k2[2];  // -2 / alpha_k (filled by density_prepare)
 };
+
+SCVT_HD DensityP density_prepare(DensityP d) {
+  for (int k = 0; k < 2; k++) d.k2[k] = d.alpha[k] > 0.0 ? -2.0 / d.alpha[k] : 0.0;
+  return d;
+}
+
+// reciprocal square root: the device's correctly refined rsqrt, 1/sqrt on
+// the host build used by the CPU checks
+SCVT_HD double rsq(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ::rsqrt(x);
+#else
+  return 1.0 / ::sqrt(x);
+#endif
+}
 
 SCVT_HD double chord_to_angle(double ch) {
   double s = 0.5 * ch;
@@ -218,20 +234,30 @@ SCVT_HD double chord_to_angle(double ch) {
 // (the printed prefactor 1/(2(1-gamma)) is read as (1-gamma)/2 so that rho
 // spans [gamma, 1]); X3 = (1-gamma) z^4 + gamma; X16 with the anisotropic
 // distance built from the latitude/longitude-swapped points.
-SCVT_HD double rho_eval(const DensityP& D, V3 y) {
-  if (D.kind == kRhoConst) return 1.0;
-  if (D.kind == kRhoTanh) {
+// (tanh(x) + 1)/2 is evaluated as the equal 1/(1 + exp(-2x)), which does not
+// cancel where tanh is close to -1 (far from a bump, where rho ~ gamma).
+SCVT_HD double bump(double amp, double beta, double k2, double d) {
+  return amp / (1.0 + exp((beta - d) * k2));
+}
+
+// Density specialised on its kind (kRhoTanh + 8: tanh bumps over the
+// geodesic distance), so a kernel instantiated for one kind carries no code
+// (and no registers) for the others.
+template <int KIND>
+SCVT_HD double rho_kind(const DensityP& D, V3 y) {
+  if (KIND == kRhoConst) return 1.0;
+  if (KIND == kRhoTanh || KIND == kRhoTanh + 8) {
     double rho = D.gamma;
     for (int k = 0; k < D.nbumps; k++) {
       V3 c = V3{D.xc[k][0], D.xc[k][1], D.xc[k][2]};
       V3 t = y - c;
       double d = sqrt(dot(t, t));
-      if (D.geodesic) d = chord_to_angle(d);
-      rho += D.amp[k] * 0.5 * (tanh((D.beta[k] - d) / D.alpha[k]) + 1.0);
+      if (KIND == kRhoTanh + 8) d = chord_to_angle(d);
+      rho += bump(D.amp[k], D.beta[k], D.k2[k], d);
     }
     return rho;
   }
-  if (D.kind == kRhoX3) {
+  if (KIND == kRhoX3) {
     double z2 = y.z * y.z;
     return (1.0 - D.gamma) * z2 * z2 + D.gamma;
   }
@@ -246,23 +272,38 @@ SCVT_HD double rho_eval(const DensityP& D, V3 y) {
   double d1 = chord_to_angle(sqrt(dot(t1, t1)));
   double d2 = chord_to_angle(sqrt(dot(t2, t2)));
   double d = sqrt(d1 * d1 / (D.w_lon * D.w_lon) + d2 * d2 / (D.w_lat * D.w_lat));
-  return D.amp[0] * 0.5 * (tanh((D.beta[0] - d) / D.alpha[0]) + 1.0) + D.gamma;
+  return bump(D.amp[0], D.beta[0], D.k2[0], d) + D.gamma;
+}
+
+// instantiation index of a density: kind, or kRhoTanh + 8 for geodesic bumps
+SCVT_HD int rho_variant(const DensityP& D) {
+  return (D.kind == kRhoTanh && D.geodesic) ? kRhoTanh + 8 : D.kind;
+}
+
+SCVT_HD double rho_eval(const DensityP& D, V3 y) {
+  switch (rho_variant(D)) {
+    case kRhoConst: return rho_kind<kRhoConst>(D, y);
+    case kRhoTanh: return rho_kind<kRhoTanh>(D, y);
+    case kRhoTanh + 8: return rho_kind<kRhoTanh + 8>(D, y);
+    case kRhoX3: return rho_kind<kRhoX3>(D, y);
+    default: return rho_kind<kRhoX16>(D, y);
+  }
 }
 
 // ------------------------------------------------------------- quadrature
-// Radon's 7-point degree-5 rule (Stroud T2:5-1), barycentric, weights sum to 1.
-struct Rule7 {
-  double l[7][3], w[7];
-};
-SCVT_HD Rule7 rule7() {
-  const double a1 = 0.10128650732345634, a2 = 0.4701420641051151;
-  const double w1 = 0.12593918054482714, w2 = 0.1323941527885062;
-  const double b1 = 1.0 - 2.0 * a1, b2 = 1.0 - 2.0 * a2, t = 1.0 / 3.0;
-  Rule7 r = {{{t, t, t}, {b1, a1, a1}, {a1, b1, a1}, {a1, a1, b1},
-              {b2, a2, a2}, {a2, b2, a2}, {a2, a2, b2}},
-             {9.0 / 40.0, w1, w1, w1, w2, w2, w2}};
-  return r;
-}
+// Radon's 7-point degree-5 rule (Stroud T2:5-1): barycentric coordinates and
+// weight per row, weights summing to 1.
+#define SCVT_A1 0.10128650732345634
+#define SCVT_A2 0.4701420641051151
+#define SCVT_W1 0.12593918054482714
+#define SCVT_W2 0.1323941527885062
+#define SCVT_B1 (1.0 - 2.0 * SCVT_A1)
+#define SCVT_B2 (1.0 - 2.0 * SCVT_A2)
+__host__ __device__ constexpr double kRule7[7][4] = {
+    {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0, 9.0 / 40.0}, {SCVT_B1, SCVT_A1, SCVT_A1, SCVT_W1},
+    {SCVT_A1, SCVT_B1, SCVT_A1, SCVT_W1},          {SCVT_A1, SCVT_A1, SCVT_B1, SCVT_W1},
+    {SCVT_B2, SCVT_A2, SCVT_A2, SCVT_W2},          {SCVT_A2, SCVT_B2, SCVT_A2, SCVT_W2},
+    {SCVT_A2, SCVT_A2, SCVT_B2, SCVT_W2}};
 
 struct Acc5 {
   double m, mx, my, mz, e;
@@ -271,20 +312,20 @@ struct Acc5 {
 // Radial projection of the flat triangle (A,B,C) onto the sphere has Jacobian
 // (n.p)/|p|^3 with n.p constant = det(A,B,C)/(2 area), so
 //   int_sph f dsigma = det(A,B,C)/2 * sum_q w_q f(p_q/|p_q|) / |p_q|^3.
-SCVT_HD void quad_tri(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
-  const Rule7 R = rule7();
+template <int KIND>
+SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
   // det(A,B,C) = A . ((B-A) x (C-A)): the differences of nearby unit vectors
   // are exact to a rounding, so small sub-triangles keep full relative
   // accuracy (the plain triple product cancels ~log10(1/size) digits)
   const double hd = 0.5 * dot(A, cross(B - A, C - A));
+#pragma unroll 1
   for (int q = 0; q < 7; q++) {
-    V3 p = R.l[q][0] * A + R.l[q][1] * B + R.l[q][2] * C;
-    double r2 = dot(p, p);
-    double r = sqrt(r2);
-    double ri = 1.0 / r;
+    const double l0 = kRule7[q][0], l1 = kRule7[q][1], l2 = kRule7[q][2];
+    V3 p = l0 * A + l1 * B + l2 * C;
+    double ri = rsq(dot(p, p));
     V3 y = ri * p;
     double jac = ri * ri * ri;
-    double wt = hd * R.w[q] * jac * rho_eval(D, y);
+    double wt = hd * kRule7[q][3] * jac * rho_kind<KIND>(D, y);
     V3 dy = y - z;
     acc.m += wt;
     acc.mx += wt * y.x;
@@ -294,13 +335,27 @@ SCVT_HD void quad_tri(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
   }
 }
 
+SCVT_HD void quad_tri(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
+  switch (rho_variant(D)) {
+    case kRhoConst: quad_tri_k<kRhoConst>(A, B, C, z, D, acc); break;
+    case kRhoTanh: quad_tri_k<kRhoTanh>(A, B, C, z, D, acc); break;
+    case kRhoTanh + 8: quad_tri_k<kRhoTanh + 8>(A, B, C, z, D, acc); break;
+    case kRhoX3: quad_tri_k<kRhoX3>(A, B, C, z, D, acc); break;
+    default: quad_tri_k<kRhoX16>(A, B, C, z, D, acc); break;
+  }
+}
+
+// a / |a| through the reciprocal square root (quadrature only; the shared
+// vertices use the correctly rounded `normalized`)
+SCVT_HD V3 normalized_fast(V3 a) { return rsq(dot(a, a)) * a; }
+
 // Leaf `s` (base-4 digits, most significant first) of `levels` geodesic
 // midpoint subdivisions of (A,B,C): children (A,ab,ca), (ab,B,bc), (ca,bc,C),
 // (ab,bc,ca), midpoints normalize(a+b).
 SCVT_HD void subtriangle(V3& A, V3& B, V3& C, int s, int levels) {
   for (int lv = levels - 1; lv >= 0; lv--) {
     int k = (s >> (2 * lv)) & 3;
-    V3 ab = normalized(A + B), bc = normalized(B + C), ca = normalized(C + A);
+    V3 ab = normalized_fast(A + B), bc = normalized_fast(B + C), ca = normalized_fast(C + A);
     if (k == 0) {
       B = ab; C = ca;
     } else if (k == 1) {

@@ -1,6 +1,6 @@
-// Voronoi cell construction + cell quadrature + per-cell epilogue.
+// Voronoi cell construction, cell quadrature and per-cell epilogue.
 //
-// Certified path (k_cells): one wavefront per generator z, in cube-map order
+// k_cells_geom: one wavefront per generator z, in cube-map order
 // (neighbouring waves share cached grid data), block index remapped so that
 // each XCD's L2 sees a contiguous stretch of the sphere.
 //   A. candidates: every generator within chord radius rc of z, read from a
@@ -9,15 +9,16 @@
 //      of (z, p_j) against all other candidates (edge_on_bisector);
 //   C. certificate: the cell's circumradius R obeys 2R <= rc, so no
 //      generator outside the candidate set can cut the cell (a point p can
-//      only cut if |p - z| < 2R); otherwise the radius grows and A-C repeat;
-//   D. quadrature: fan triangles (z, v_lo, v_hi) over the edges, ordered by
-//      neighbour index, each split into 4^levels geodesic sub-triangles with
-//      the 7-point rule; one (edge, sub-triangle) item per lane;
-//   E. epilogue: m, mu, e -> g, h, Lloyd step (section 3.1).
-// Cells that cannot be certified with 64 candidates, or meet a predicate
-// within its error bound, go to a list for k_fallback: a sequential
-// half-space clipper run by lane 0 (no size limit: any cell the sphere
-// allows), then the same quadrature and epilogue.
+//      only cut if |p - z| < 2R); otherwise the radius grows and A-C repeat.
+//   The edges (vertex pairs, ordered by neighbour index) go to the cell's
+//   slot in HBM.  Cells that cannot be certified with 64 candidates, or meet
+//   a predicate within its error bound, go to a list for
+// k_fallback: a sequential half-space clipper run by lane 0 (no size limit:
+//   any cell the sphere allows), writing the same slot.
+// k_quad: one wavefront per cell: fan triangles (z, v_lo, v_hi), each split
+//   into 4^levels geodesic sub-triangles with the 7-point rule, one (edge,
+//   sub-triangle) item per lane; then m, mu, e -> g, h, Lloyd step
+//   (section 3.1).
 #include "kernels.h"
 
 namespace scvt {
@@ -63,69 +64,21 @@ struct WaveLds {
   int32_t idx[kMaxCand];
   int32_t rowoff[kWinMax + 1];
   int32_t rowstart[kWinMax];
-  // edges ordered by neighbour index: fan triangle (z, v0, v1)
-  double v0[kMaxCand][3], v1[kMaxCand][3];
-  int32_t enbr[kMaxCand];
 };
 
-// ------------------------------------------------------ quadrature + output
-// Every lane integrates items lane, lane+64, ... of E * 4^levels (edge,
-// leaf) pairs; the wave sum is taken in a fixed butterfly order.
-__device__ Acc5 wave_quadrature(const WaveLds& L, int E, V3 z, const DensityP& rho, int levels) {
-  Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int per = 1 << (2 * levels);
-  const int total = E * per;
-  for (int t = lane_id(); t < total; t += 64) {
-    int e = t >> (2 * levels), s = t & (per - 1);
-    V3 A = z;
-    V3 B = V3{L.v0[e][0], L.v0[e][1], L.v0[e][2]};
-    V3 C = V3{L.v1[e][0], L.v1[e][1], L.v1[e][2]};
-    subtriangle(A, B, C, s, levels);
-    quad_tri(A, B, C, z, rho, acc);
-  }
-  acc.m = wave_sum(acc.m);
-  acc.mx = wave_sum(acc.mx);
-  acc.my = wave_sum(acc.my);
-  acc.mz = wave_sum(acc.mz);
-  acc.e = wave_sum(acc.e);
-  return acc;
-}
-
-__device__ void write_cell(const CellArgs& a, int64_t i, V3 z, const Acc5& acc, double R, int E,
-                           uint8_t flags, const WaveLds& L) {
-  const EvalOut& o = a.out;
-  if (lane_id() == 0) {
-    V3 mu = V3{acc.mx, acc.my, acc.mz};
-    double mz = dot(mu, z);
-    V3 g = 2.0 * mz * z - 2.0 * mu;
-    V3 l = normalized(mu) - z;
-    o.m[i] = acc.m;
-    o.e[i] = acc.e;
-    o.mu[3 * i] = mu.x;
-    o.mu[3 * i + 1] = mu.y;
-    o.mu[3 * i + 2] = mu.z;
-    o.g[3 * i] = g.x;
-    o.g[3 * i + 1] = g.y;
-    o.g[3 * i + 2] = g.z;
-    o.h[i] = 1.0 / (2.0 * mz);
-    o.lloyd[3 * i] = l.x;
-    o.lloyd[3 * i + 1] = l.y;
-    o.lloyd[3 * i + 2] = l.z;
-    o.R[i] = R;
-    o.flags[i] = flags;
-    o.deg[i] = E;
-  }
-  if (a.keep_cells) {
-    int ln = lane_id();
-    if (ln < kVmax) {
-      bool have = ln < E;
-      o.cell_nbr[i * kVmax + ln] = have ? L.enbr[ln] : -1;
-      for (int k = 0; k < 3; k++) {
-        o.cell_verts[(i * kVmax + ln) * 6 + k] = have ? L.v0[ln][k] : 0.0;
-        o.cell_verts[(i * kVmax + ln) * 6 + 3 + k] = have ? L.v1[ln][k] : 0.0;
-      }
-    }
-  }
+// ------------------------------------------------------------- edge slots
+// Edge k of cell i (ordered by neighbour index): vertices v0 -> v1,
+// counter-clockwise seen from outside, at edges[(i * kVmax + k) * 6 ...].
+__device__ inline void store_edge(const EvalOut& o, int64_t i, int k, V3 v0, V3 v1, int nbr,
+                                  int keep) {
+  double* e = o.edges + (i * kVmax + k) * 6;
+  e[0] = v0.x;
+  e[1] = v0.y;
+  e[2] = v0.z;
+  e[3] = v1.x;
+  e[4] = v1.y;
+  e[5] = v1.z;
+  if (keep) o.cell_nbr[i * kVmax + k] = nbr;
 }
 
 // ---------------------------------------------------------- certified path
@@ -189,7 +142,7 @@ __device__ int gather(const CellArgs& a, WaveLds& L, const Window& w, int64_t i,
   return kept;
 }
 
-__global__ __launch_bounds__(256) void k_cells(CellArgs a) {
+__global__ __launch_bounds__(256) void k_cells_geom(CellArgs a) {
   __shared__ WaveLds lds[4];
   const int ln = lane_id(), wv = threadIdx.x >> 6;
   WaveLds& L = lds[wv];
@@ -250,11 +203,8 @@ __global__ __launch_bounds__(256) void k_cells(CellArgs a) {
           mm &= mm - 1;
           rank += L.idx[k] < me ? 1 : 0;
         }
-        L.v0[rank][0] = vlo.x; L.v0[rank][1] = vlo.y; L.v0[rank][2] = vlo.z;
-        L.v1[rank][0] = vhi.x; L.v1[rank][1] = vhi.y; L.v1[rank][2] = vhi.z;
-        L.enbr[rank] = me;
+        store_edge(a.out, i, rank, vlo, vhi, me, a.keep_cells);
       }
-      wave_sync();
     } else {
       if (rc < rt && 2.0 * R >= w.D) break;  // window-limited: fallback
       // R of an incomplete candidate set overestimates the cell: grow by at
@@ -262,23 +212,27 @@ __global__ __launch_bounds__(256) void k_cells(CellArgs a) {
       rt = fmin(2.1 * R, 1.6 * rt);
     }
   }
-  if (!ok) {
-    if (ln == 0) {
+  if (ln == 0) {
+    if (!ok) {
       int k = atomicAdd(&a.ctr->fb_count, 1);
       a.fb_list[k] = (int32_t)i;
       if (degen) atomicAdd(&a.ctr->n_degenerate, 1);
+      a.out.deg[i] = 0;
+    } else {
+      a.out.deg[i] = E;
+      a.out.R[i] = R;
+      a.out.flags[i] = 0;
     }
-    return;
   }
-  Acc5 acc = wave_quadrature(L, E, z, a.rho, a.levels);
-  write_cell(a, i, z, acc, R, E, 0, L);
+  if (ok && a.keep_cells && ln >= E && ln < kVmax) a.out.cell_nbr[i * kVmax + ln] = -1;
 }
 
 // ------------------------------------------------------------ fallback path
 struct FbLds {
   ClipPoly poly;
   int32_t brute;
-  WaveLds w;  // edges for the quadrature
+  int32_t enbr[kVmax];
+  double v0[kVmax][3], v1[kVmax][3];
 };
 
 __device__ inline V3 genpos(const double* Z, int j) { return V3{Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]}; }
@@ -362,23 +316,79 @@ __global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
     // real vertices (where consecutive edges change circle), canonical
     // positions, edges sorted by neighbour index
     if (ln == 0) {
-      int E = clip_finish(F.poly, (int)i, z, [&](int j) { return genpos(a.Z, j); }, F.w.enbr,
-                          &F.w.v0[0][0], &F.w.v1[0][0], kVmax);
+      int E = clip_finish(F.poly, (int)i, z, [&](int j) { return genpos(a.Z, j); }, F.enbr,
+                          &F.v0[0][0], &F.v1[0][0], kVmax);
       F.poly.K[0] = E;  // reuse as the edge count
     }
     wave_sync();
     const int E = F.poly.K[0];
-    uint8_t flags = kFlagFallback | (F.poly.degen ? kFlagDegenerate : 0) |
-                    (F.poly.err ? kFlagError : 0) | (F.brute ? kFlagBrute : 0);
+    if (ln < E)
+      store_edge(a.out, i, ln, V3{F.v0[ln][0], F.v0[ln][1], F.v0[ln][2]},
+                 V3{F.v1[ln][0], F.v1[ln][1], F.v1[ln][2]}, F.enbr[ln], a.keep_cells);
+    else if (a.keep_cells && ln < kVmax)
+      a.out.cell_nbr[i * kVmax + ln] = -1;
     if (ln == 0) {
+      a.out.deg[i] = E;
+      a.out.R[i] = F.poly.R;
+      a.out.flags[i] = kFlagFallback | (F.poly.degen ? kFlagDegenerate : 0) |
+                       (F.poly.err ? kFlagError : 0) | (F.brute ? kFlagBrute : 0);
       atomicAdd(&a.ctr->n_fallback, 1);
       if (F.poly.err) atomicAdd(&a.ctr->n_error, 1);
       if (F.brute) atomicAdd(&a.ctr->n_brute, 1);
       if (F.poly.degen) atomicAdd(&a.ctr->n_degenerate, 1);
     }
-    Acc5 acc = wave_quadrature(F.w, E, z, a.rho, a.levels);
-    write_cell(a, i, z, acc, F.poly.R, E, flags, F.w);
     wave_sync();
+  }
+}
+
+// -------------------------------------------------------------- quadrature
+// One wave per cell (index order).  Every lane integrates items lane,
+// lane+64, ... of the E * 4^levels (edge, leaf) pairs; the five sums are
+// reduced across the wave in a fixed butterfly order, so the result does not
+// depend on scheduling.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_quad(CellArgs a) {
+  const int ln = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= a.n) return;
+  const EvalOut& o = a.out;
+  const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
+  const int E = o.deg[i];
+  const int lv = a.levels;
+  const int per = 1 << (2 * lv);
+  const int total = E * per;
+  Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = ln; t < total; t += 64) {
+    const int e = t >> (2 * lv), s = t & (per - 1);
+    const double* ed = o.edges + (i * kVmax + e) * 6;
+    V3 A = z;
+    V3 B = V3{ed[0], ed[1], ed[2]};
+    V3 C = V3{ed[3], ed[4], ed[5]};
+    subtriangle(A, B, C, s, lv);
+    quad_tri_k<KIND>(A, B, C, z, a.rho, acc);
+  }
+  acc.m = wave_sum(acc.m);
+  acc.mx = wave_sum(acc.mx);
+  acc.my = wave_sum(acc.my);
+  acc.mz = wave_sum(acc.mz);
+  acc.e = wave_sum(acc.e);
+  if (ln == 0) {
+    V3 mu = V3{acc.mx, acc.my, acc.mz};
+    double mz = dot(mu, z);
+    V3 g = 2.0 * mz * z - 2.0 * mu;
+    V3 l = normalized(mu) - z;
+    o.m[i] = acc.m;
+    o.e[i] = acc.e;
+    o.mu[3 * i] = mu.x;
+    o.mu[3 * i + 1] = mu.y;
+    o.mu[3 * i + 2] = mu.z;
+    o.g[3 * i] = g.x;
+    o.g[3 * i + 1] = g.y;
+    o.g[3 * i + 2] = g.z;
+    o.h[i] = 1.0 / (2.0 * mz);
+    o.lloyd[3 * i] = l.x;
+    o.lloyd[3 * i + 1] = l.y;
+    o.lloyd[3 * i + 2] = l.z;
   }
 }
 
@@ -391,7 +401,7 @@ __global__ void k_fb_all(int32_t* fb_list, Counters* ctr, int64_t n) {
 
 hipError_t launch_cells_main(const CellArgs& a, hipStream_t s) {
   int64_t nb = (a.n + 3) / 4;
-  k_cells<<<(unsigned)nb, 256, 0, s>>>(a);
+  k_cells_geom<<<(unsigned)nb, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -399,6 +409,18 @@ hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s) {
   if (all) k_fb_all<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a.fb_list, a.ctr, a.n);
   int64_t fb_blocks = a.n < 8192 ? a.n : 8192;
   k_fallback<<<(unsigned)fb_blocks, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad(const CellArgs& a, hipStream_t s) {
+  const unsigned nb = (unsigned)((a.n + 3) / 4);
+  switch (rho_variant(a.rho)) {
+    case kRhoConst: k_quad<kRhoConst><<<nb, 256, 0, s>>>(a); break;
+    case kRhoTanh: k_quad<kRhoTanh><<<nb, 256, 0, s>>>(a); break;
+    case kRhoTanh + 8: k_quad<kRhoTanh + 8><<<nb, 256, 0, s>>>(a); break;
+    case kRhoX3: k_quad<kRhoX3><<<nb, 256, 0, s>>>(a); break;
+    default: k_quad<kRhoX16><<<nb, 256, 0, s>>>(a); break;
+  }
   return hipGetLastError();
 }
 

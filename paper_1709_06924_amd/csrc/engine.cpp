@@ -23,7 +23,7 @@ struct EvalSet {
   uint8_t* flags = nullptr;
   int32_t* deg = nullptr;
   int32_t* cell_nbr = nullptr;
-  double* cell_verts = nullptr;
+  double* edges = nullptr;
 };
 
 struct Timer {
@@ -31,7 +31,7 @@ struct Timer {
   int64_t launches = 0;
 };
 
-constexpr int kTimers = 5;
+constexpr int kTimers = 6;
 constexpr int kStateMagic = 0x53435654;  // "SCVT"
 
 }  // namespace
@@ -68,6 +68,7 @@ struct scvt_handle {
   hipEvent_t ev[8] = {};
   int main_path = 1;
   double r_default = 0;
+  double* shared_edges = nullptr;
 };
 
 namespace {
@@ -107,9 +108,14 @@ int alloc_set(scvt_handle* h, EvalSet& s) {
   ALLOC(s.lloyd, 3 * n);
   ALLOC(s.flags, n);
   ALLOC(s.deg, n);
+  // edge slots: per set when the cells are kept for scvt_get_cells, else one
+  // buffer shared by both sets (it only lives through one evaluation)
   if (h->cfg.keep_cells) {
     ALLOC(s.cell_nbr, n * kVmax);
-    ALLOC(s.cell_verts, n * kVmax * 6);
+    ALLOC(s.edges, n * kVmax * 6);
+  } else {
+    if (!h->shared_edges) ALLOC(h->shared_edges, n * kVmax * 6);
+    s.edges = h->shared_edges;
   }
   return SCVT_OK;
 }
@@ -144,7 +150,7 @@ DensityP to_dev(const scvt_density& d) {
   r.gamma = d.gamma;
   r.w_lon = d.w_lon;
   r.w_lat = d.w_lat;
-  return r;
+  return density_prepare(r);
 }
 
 int validate(const scvt_config* c) {
@@ -186,7 +192,7 @@ CellArgs cell_args(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   a.out.flags = s.flags;
   a.out.deg = s.deg;
   a.out.cell_nbr = s.cell_nbr;
-  a.out.cell_verts = s.cell_verts;
+  a.out.edges = s.edges;
   a.fb_list = h->fb_list;
   a.ctr = h->ctr;
   a.r_default = h->r_default;
@@ -214,6 +220,8 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   if (tm) HIPCK(hipEventRecord(h->ev[2], st));
   HIPCK(launch_cells_fallback(a, h->main_path ? 0 : 1, st));
   if (tm) HIPCK(hipEventRecord(h->ev[3], st));
+  HIPCK(launch_quad(a, st));
+  if (tm) HIPCK(hipEventRecord(h->ev[7], st));
   EvalRedArgs r{};
   r.n = h->n;
   r.e = s.e;
@@ -234,6 +242,7 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
     timer_add(h, 1, h->ev[2], h->ev[3]);
     timer_add(h, 2, h->ev[0], h->ev[1]);
     timer_add(h, 4, h->ev[0], h->ev[4]);
+    timer_add(h, 5, h->ev[3], h->ev[7]);
   }
   Counters c;
   memcpy(&c, h->pinned + 8, sizeof(Counters));
@@ -669,7 +678,7 @@ int scvt_get_cells(scvt_handle* h, int32_t max_deg, int32_t* nbr, int32_t* deg, 
   if (nbr)
     HIPCK(hipMemcpyAsync(nbr, h->cur.cell_nbr, n * kVmax * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   if (verts)
-    HIPCK(hipMemcpyAsync(verts, h->cur.cell_verts, n * kVmax * 6 * sizeof(double),
+    HIPCK(hipMemcpyAsync(verts, h->cur.edges, n * kVmax * 6 * sizeof(double),
                          hipMemcpyDeviceToHost, st));
   if (deg) HIPCK(hipMemcpyAsync(deg, h->cur.deg, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   if (flags) HIPCK(hipMemcpyAsync(flags, h->cur.flags, n, hipMemcpyDeviceToHost, st));

@@ -32,9 +32,8 @@ struct EvalOut {  // per-generator results of one evaluation
   double* R;                           // circumradius of the cell (next search radius)
   uint8_t* flags;
   int32_t* deg;
-  // optional debug copy of the cells: nbr n x kVmax, verts n x kVmax x 6
-  int32_t* cell_nbr;
-  double* cell_verts;
+  double* edges;      // n x kVmax x 6: edge k of cell i, v0 -> v1
+  int32_t* cell_nbr;  // n x kVmax neighbour ids (only with keep_cells)
 };
 
 struct GridBufs {
@@ -78,6 +77,7 @@ hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha
 hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s);
 hipError_t launch_cells_main(const CellArgs& a, hipStream_t s);
 hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s);
+hipError_t launch_quad(const CellArgs& a, hipStream_t s);
 hipError_t launch_centroid(const double* mu, const double* m, double* out, int64_t n,
                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);

@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 SCVT_OK, SCVT_NOT_CONVERGED, SCVT_PENDING = 0, 1, 2
 FP64, MIXED = 0, 1
 KIND = {"const": 0, "tanh": 1, "x3": 2, "x16": 3}
-KERNEL_CELLS, KERNEL_FALLBACK, KERNEL_GRID, KERNEL_LBFGS, KERNEL_EVAL = 0, 1, 2, 3, 4
+KERNEL_CELLS, KERNEL_FALLBACK, KERNEL_GRID, KERNEL_LBFGS, KERNEL_EVAL, KERNEL_QUAD = 0, 1, 2, 3, 4, 5
 VMAX = 32
 
 
@@ -218,6 +218,13 @@ class Solver:
                                    verts.ctypes.data_as(ctypes.c_void_p),
                                    flags.ctypes.data_as(ctypes.c_void_p)), "scvt_get_cells")
         return nbr, deg, verts, flags
+
+    def degrees(self):
+        """Voronoi degree of every cell at the current generators."""
+        deg = np.zeros(self.n, np.int32)
+        _check(_lib.scvt_get_cells(self.h, VMAX, None, deg.ctypes.data_as(ctypes.c_void_p), None,
+                                   None), "scvt_get_cells")
+        return deg
 
     def get_state(self):
         nb = ctypes.c_size_t()

@@ -127,6 +127,7 @@ int hc_clip(int64_t n, const double* Z, int64_t i, int32_t* deg, int32_t* nbr, d
 int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int levels,
             double* out5) {
   Acc5 acc = {0, 0, 0, 0, 0};
+  DensityP Dp = density_prepare(*D);
   V3 z = V3{z3[0], z3[1], z3[2]};
   const int per = 1 << (2 * levels);
   for (int t = 0; t < E * per; t++) {
@@ -134,7 +135,7 @@ int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int
     V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
        C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
     subtriangle(A, B, C, s, levels);
-    quad_tri(A, B, C, z, *D, acc);
+    quad_tri(A, B, C, z, Dp, acc);
   }
   out5[0] = acc.m;
   out5[1] = acc.mx;
