@@ -369,15 +369,18 @@ SCVT_HD void subtriangle(V3& A, V3& B, V3& C, int s, int levels) {
 }
 
 // ------------------------------------------------------------ cube-map grid
-// Each face f = 2k + (sign<0) of the cube [-1,1]^3 carries an equiangular
-// W x W grid, W = G + 2B: G cells span the face proper, B extra cells on each
-// side hold copies ("ghosts") of generators of the neighbouring faces, so
-// that a search window around any generator stays on its own face.
+// Each face f = 2k + (sign<0) of the cube [-1,1]^3 carries a gnomonic grid:
+// a point p with depth n = +-p_k > 0 has face coordinates u = p_k+1 / n,
+// v = p_k+2 / n, and cells of side du in (u, v).  G cells span the face
+// proper ([-1,1]), B more on each side hold copies ("ghosts") of generators
+// of the neighbouring faces (|u|,|v| up to U = 1 + B du), so that a search
+// window around any generator stays on its own face.  Lines u = const are
+// great circles through the face's v axis, so every bound below is algebraic.
 struct GridP {
   int G, B, W;
   int pad;
-  double delta, inv_delta, a0;  // cell angle, its inverse, angle of column 0
-  int64_t ncells;               // 6 W^2
+  double du, inv_du, U;  // cell side, its inverse, extent of the extended grid
+  int64_t ncells;        // 6 W^2
 };
 
 SCVT_HD int home_face(V3 p) {
@@ -406,8 +409,7 @@ SCVT_HD int64_t cell_on_face(const GridP& g, V3 p, int f) {
   double n, u, v;
   face_local(p, f, n, u, v);
   if (!(n > 0.0)) return -1;
-  double a = atan(u / n), b = atan(v / n);
-  double fa = floor((a - g.a0) * g.inv_delta), fb = floor((b - g.a0) * g.inv_delta);
+  double fa = floor((u / n + g.U) * g.inv_du), fb = floor((v / n + g.U) * g.inv_du);
   if (fa < 0.0 || fb < 0.0 || fa >= (double)g.W || fb >= (double)g.W) return -1;
   return cell_of(g, f, (int)fa, (int)fb);
 }
@@ -419,33 +421,57 @@ struct Window {
   double D;
 };
 
+// Bounds c_lo <= c_z <= c_hi on one face coordinate (c = w/n) such that the
+// planes c = c_lo, c = c_hi are at angular distance >= theta from z, where
+// sin(theta) = st: z sits at angle phi_z = atan(c_z) about the other face
+// axis, at radius rho = sqrt(n^2 + w^2) from it, so the planes must be at
+// phi_z -+ delta with sin(delta) = st / rho; tan(phi_z -+ delta) in closed form.
+SCVT_HD void coord_bounds(double cz, double rho, double st, double& lo, double& hi) {
+  double s = st / rho;
+  if (s >= 1.0) {
+    lo = -1e300;
+    hi = 1e300;
+    return;
+  }
+  double t = s / sqrt(1.0 - s * s);  // tan(delta)
+  double dl = 1.0 + cz * t, dh = 1.0 - cz * t;
+  lo = dl > 0.0 ? (cz - t) / dl : -1e300;
+  hi = dh > 0.0 ? (cz + t) / dh : 1e300;
+}
+
+// sine of the angular distance from z (depth n, coordinate w) to the plane
+// c = cc through the face's other axis, signed positive on z's side (sgn)
+SCVT_HD double plane_sine(double n, double w, double cc, double sgn) {
+  return sgn * (w - cc * n) / sqrt(1.0 + cc * cc);
+}
+
 // Smallest window around z (face f = home face) that covers the chord
 // radius rt (clamped to the grid and to at most maxw cells a side), and the
-// certified radius D of the window actually chosen.  The window's sides are
-// great circles (planes through the origin containing a face axis), so the
-// angular distance from z to a side is asin of z's signed distance to that
-// plane; points outside the face's extended grid lie beyond its outer sides
-// or behind the face (distance asin(depth)).
+// certified radius D of the window actually chosen: the distance from z to
+// the nearest window side, or to the face's horizon (points behind the face
+// are not in its grid).
 SCVT_HD Window make_window(const GridP& g, V3 z, int f, double rt, int maxw) {
   double n, u, v;
   face_local(z, f, n, u, v);
-  double az = atan(u / n), bz = atan(v / n);
-  double half = 0.5 * rt;
-  double th = 2.0 * asin(half > 1.0 ? 1.0 : half);
-  double sth = th >= 1.5707963267948966 ? 1.0 : sin(th);
-  double ru = sqrt(n * n + u * u), rv = sqrt(n * n + v * v);
-  double da = sth >= ru ? 1.5707963267948966 : asin(sth / ru);
-  double db = sth >= rv ? 1.5707963267948966 : asin(sth / rv);
-  int ca = (int)floor((az - g.a0) * g.inv_delta), cb = (int)floor((bz - g.a0) * g.inv_delta);
+  const double uz = u / n, vz = v / n;
+  double r = rt > 2.0 ? 2.0 : rt;
+  double st = r * sqrt(fmax(0.0, 1.0 - 0.25 * r * r));  // sin of the angular radius
+  if (rt >= 1.4142135623730951) st = 1.0;              // beyond 90 degrees: everything
+  double ulo, uhi, vlo, vhi;
+  coord_bounds(uz, sqrt(n * n + u * u), st, ulo, uhi);
+  coord_bounds(vz, sqrt(n * n + v * v), st, vlo, vhi);
+  int ca = (int)floor((uz + g.U) * g.inv_du), cb = (int)floor((vz + g.U) * g.inv_du);
   ca = ca < 0 ? 0 : (ca >= g.W ? g.W - 1 : ca);
   cb = cb < 0 ? 0 : (cb >= g.W ? g.W - 1 : cb);
-  double fl = floor((az - da - g.a0) * g.inv_delta), fh = floor((az + da - g.a0) * g.inv_delta);
-  double gl = floor((bz - db - g.a0) * g.inv_delta), gh = floor((bz + db - g.a0) * g.inv_delta);
   const int half_max = (maxw - 1) / 2;
-  int ia_lo = fl < (double)(ca - half_max) ? ca - half_max : (int)fl;
-  int ia_hi = fh > (double)(ca + half_max) ? ca + half_max : (int)fh;
-  int ib_lo = gl < (double)(cb - half_max) ? cb - half_max : (int)gl;
-  int ib_hi = gh > (double)(cb + half_max) ? cb + half_max : (int)gh;
+  auto col = [&](double c, int centre, int dir) {
+    double x = floor((c + g.U) * g.inv_du);
+    double lim = (double)(centre + dir * half_max);
+    if (dir < 0) return x < lim ? (int)lim : (int)x;
+    return x > lim ? (int)lim : (int)x;
+  };
+  int ia_lo = col(ulo, ca, -1), ia_hi = col(uhi, ca, 1);
+  int ib_lo = col(vlo, cb, -1), ib_hi = col(vhi, cb, 1);
   if (ia_lo < 0) ia_lo = 0;
   if (ib_lo < 0) ib_lo = 0;
   if (ia_hi > g.W - 1) ia_hi = g.W - 1;
@@ -454,26 +480,29 @@ SCVT_HD Window make_window(const GridP& g, V3 z, int f, double rt, int maxw) {
   if (ia_hi < ca) ia_hi = ca;
   if (ib_lo > cb) ib_lo = cb;
   if (ib_hi < cb) ib_hi = cb;
-  // signed distances (sines of angular distance) to the four sides
-  double alo = g.a0 + ia_lo * g.delta, ahi = g.a0 + (ia_hi + 1) * g.delta;
-  double blo = g.a0 + ib_lo * g.delta, bhi = g.a0 + (ib_hi + 1) * g.delta;
-  double s1 = cos(alo) * u - sin(alo) * n;
-  double s2 = sin(ahi) * n - cos(ahi) * u;
-  double s3 = cos(blo) * v - sin(blo) * n;
-  double s4 = sin(bhi) * n - cos(bhi) * v;
+  const double a0 = -g.U + ia_lo * g.du, a1 = -g.U + (ia_hi + 1) * g.du;
+  const double b0 = -g.U + ib_lo * g.du, b1 = -g.U + (ib_hi + 1) * g.du;
   double sm = n;
-  sm = s1 < sm ? s1 : sm;
-  sm = s2 < sm ? s2 : sm;
-  sm = s3 < sm ? s3 : sm;
-  sm = s4 < sm ? s4 : sm;
-  double ang = sm <= 0.0 ? 0.0 : asin(sm > 1.0 ? 1.0 : sm) - 1e-12;
+  sm = fmin(sm, plane_sine(n, u, a0, 1.0));
+  sm = fmin(sm, plane_sine(n, u, a1, -1.0));
+  sm = fmin(sm, plane_sine(n, v, b0, 1.0));
+  sm = fmin(sm, plane_sine(n, v, b1, -1.0));
   Window w;
   w.f = f;
   w.ia_lo = ia_lo;
   w.ia_hi = ia_hi;
   w.ib_lo = ib_lo;
   w.ib_hi = ib_hi;
-  w.D = ang <= 0.0 ? 0.0 : 2.0 * sin(0.5 * ang);
+  if (sm <= 0.0) {
+    w.D = 0.0;
+  } else {
+    sm = fmin(sm, 1.0);
+    // chord of the angle asin(sm): 2 sin(asin(sm)/2), cancellation-free;
+    // shrunk to cover points binned across a side by rounding
+    double D = sm * sqrt(2.0 / (1.0 + sqrt(1.0 - sm * sm)));
+    w.D = D * (1.0 - 1e-10) - 1e-14;
+    if (w.D < 0.0) w.D = 0.0;
+  }
   return w;
 }
 

@@ -124,14 +124,14 @@ GridP make_grid(int64_t n) {
   GridP g{};
   int G = (int)llround(sqrt((double)n / 12.0));
   if (G < 1) G = 1;
-  int B = (int)floor(0.45 * G);
+  int B = G / 2;  // ghost border up to U = 2 (about 63 degrees off the face axis)
   if (B > 24) B = 24;
   g.G = G;
   g.B = B;
   g.W = G + 2 * B;
-  g.delta = 1.5707963267948966 / G;
-  g.inv_delta = G / 1.5707963267948966;
-  g.a0 = -0.7853981633974483 - B * g.delta;
+  g.du = 2.0 / G;
+  g.inv_du = G / 2.0;
+  g.U = 1.0 + B * g.du;
   g.ncells = 6LL * g.W * g.W;
   return g;
 }

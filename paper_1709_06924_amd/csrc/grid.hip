@@ -58,13 +58,13 @@ __global__ void k_grid_count(const double* __restrict__ Z, int64_t n, GridP g,
   V3 p = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
   int f = home_face(p);
   int64_t c = cell_on_face(g, p, f);
-  // a point always lies inside its home face (|a|,|b| <= pi/4); guard the
+  // a point always lies inside its home face (|u|,|v| <= 1); guard the
   // index anyway against rounding at the face edge
   if (c < 0) {
     double nn, u, v;
     face_local(p, f, nn, u, v);
-    double fa = floor((atan(u / nn) - g.a0) * g.inv_delta);
-    double fb = floor((atan(v / nn) - g.a0) * g.inv_delta);
+    double fa = floor((u / nn + g.U) * g.inv_du);
+    double fb = floor((v / nn + g.U) * g.inv_du);
     int ia = fa < 0.0 ? 0 : (fa > g.W - 1 ? g.W - 1 : (int)fa);
     int ib = fb < 0.0 ? 0 : (fb > g.W - 1 ? g.W - 1 : (int)fb);
     c = cell_of(g, f, ia, ib);

@@ -150,14 +150,14 @@ int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int
 int hc_grid(int64_t n, int32_t* GBW, double* dd) {
   int G = (int)llround(sqrt((double)n / 12.0));
   if (G < 1) G = 1;
-  int B = (int)floor(0.45 * G);
+  int B = G / 2;
   if (B > 24) B = 24;
   GBW[0] = G;
   GBW[1] = B;
   GBW[2] = G + 2 * B;
-  dd[0] = 1.5707963267948966 / G;
-  dd[1] = G / 1.5707963267948966;
-  dd[2] = -0.7853981633974483 - B * dd[0];
+  dd[0] = 2.0 / G;
+  dd[1] = G / 2.0;
+  dd[2] = 1.0 + B * dd[0];
   return 0;
 }
 
@@ -166,9 +166,9 @@ static GridP gp(const int32_t* GBW, const double* dd) {
   g.G = GBW[0];
   g.B = GBW[1];
   g.W = GBW[2];
-  g.delta = dd[0];
-  g.inv_delta = dd[1];
-  g.a0 = dd[2];
+  g.du = dd[0];
+  g.inv_du = dd[1];
+  g.U = dd[2];
   g.ncells = 6LL * g.W * g.W;
   return g;
 }
