@@ -229,6 +229,21 @@ SCVT_HD double chord_to_angle(double ch) {
   return 2.0 * asin(s > 1.0 ? 1.0 : s);
 }
 
+// Newton-refined reciprocal for x >= 1 (two steps from the hardware
+// estimate: a few ulp, no division sequence); the host build divides
+SCVT_HD double rcp_refined(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (!(x < 1e300)) return 0.0;
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
 // Densities of section 4: constant; tanh bumps
 //   rho = gamma + sum_k amp_k (tanh((beta_k - d_k)/alpha_k) + 1)/2
 // (the printed prefactor 1/(2(1-gamma)) is read as (1-gamma)/2 so that rho
@@ -237,27 +252,33 @@ SCVT_HD double chord_to_angle(double ch) {
 // (tanh(x) + 1)/2 is evaluated as the equal 1/(1 + exp(-2x)), which does not
 // cancel where tanh is close to -1 (far from a bump, where rho ~ gamma).
 SCVT_HD double bump(double amp, double beta, double k2, double d) {
-  return amp / (1.0 + exp((beta - d) * k2));
+  return amp * rcp_refined(1.0 + exp((beta - d) * k2));
 }
 
-// Density specialised on its kind (kRhoTanh + 8: tanh bumps over the
-// geodesic distance), so a kernel instantiated for one kind carries no code
-// (and no registers) for the others.
+// Density variants, each compiled separately so that a kernel carries only
+// its own code and registers: kind, and for tanh bumps +8 geodesic distance,
+// +16 two bumps.
+constexpr int kVarGeo = 8, kVarTwo = 16;
+
 template <int KIND>
 SCVT_HD double rho_kind(const DensityP& D, V3 y) {
-  if (KIND == kRhoConst) return 1.0;
-  if (KIND == kRhoTanh || KIND == kRhoTanh + 8) {
+  constexpr int base = KIND & 7;
+  if (base == kRhoConst) return 1.0;
+  if (base == kRhoTanh) {
+    constexpr int NB = (KIND & kVarTwo) ? 2 : 1;
     double rho = D.gamma;
-    for (int k = 0; k < D.nbumps; k++) {
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
       V3 c = V3{D.xc[k][0], D.xc[k][1], D.xc[k][2]};
       V3 t = y - c;
-      double d = sqrt(dot(t, t));
-      if (KIND == kRhoTanh + 8) d = chord_to_angle(d);
+      double t2 = dot(t, t);
+      double d = t2 > 0.0 ? t2 * rsq(t2) : 0.0;
+      if (KIND & kVarGeo) d = chord_to_angle(d);
       rho += bump(D.amp[k], D.beta[k], D.k2[k], d);
     }
     return rho;
   }
-  if (KIND == kRhoX3) {
+  if (base == kRhoX3) {
     double z2 = y.z * y.z;
     return (1.0 - D.gamma) * z2 * z2 + D.gamma;
   }
@@ -275,19 +296,30 @@ SCVT_HD double rho_kind(const DensityP& D, V3 y) {
   return bump(D.amp[0], D.beta[0], D.k2[0], d) + D.gamma;
 }
 
-// instantiation index of a density: kind, or kRhoTanh + 8 for geodesic bumps
+// variant index of a density
 SCVT_HD int rho_variant(const DensityP& D) {
-  return (D.kind == kRhoTanh && D.geodesic) ? kRhoTanh + 8 : D.kind;
+  if (D.kind != kRhoTanh) return D.kind;
+  return kRhoTanh + (D.geodesic ? kVarGeo : 0) + (D.nbumps == 2 ? kVarTwo : 0);
 }
 
-SCVT_HD double rho_eval(const DensityP& D, V3 y) {
-  switch (rho_variant(D)) {
-    case kRhoConst: return rho_kind<kRhoConst>(D, y);
-    case kRhoTanh: return rho_kind<kRhoTanh>(D, y);
-    case kRhoTanh + 8: return rho_kind<kRhoTanh + 8>(D, y);
-    case kRhoX3: return rho_kind<kRhoX3>(D, y);
-    default: return rho_kind<kRhoX16>(D, y);
+// call f.template operator()<V>() with the density's variant as a constant
+#define SCVT_RHO_DISPATCH(var, CALL)                      \
+  switch (var) {                                           \
+    case kRhoConst: CALL(kRhoConst); break;                \
+    case kRhoTanh: CALL(kRhoTanh); break;                  \
+    case kRhoTanh + kVarGeo: CALL(kRhoTanh + kVarGeo); break; \
+    case kRhoTanh + kVarTwo: CALL(kRhoTanh + kVarTwo); break; \
+    case kRhoTanh + kVarGeo + kVarTwo: CALL(kRhoTanh + kVarGeo + kVarTwo); break; \
+    case kRhoX3: CALL(kRhoX3); break;                      \
+    default: CALL(kRhoX16); break;                         \
   }
+
+SCVT_HD double rho_eval(const DensityP& D, V3 y) {
+  double r = 0.0;
+#define SCVT_RHO_CALL(V) r = rho_kind<V>(D, y)
+  SCVT_RHO_DISPATCH(rho_variant(D), SCVT_RHO_CALL)
+#undef SCVT_RHO_CALL
+  return r;
 }
 
 // ------------------------------------------------------------- quadrature
@@ -336,13 +368,143 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
 }
 
 SCVT_HD void quad_tri(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
-  switch (rho_variant(D)) {
-    case kRhoConst: quad_tri_k<kRhoConst>(A, B, C, z, D, acc); break;
-    case kRhoTanh: quad_tri_k<kRhoTanh>(A, B, C, z, D, acc); break;
-    case kRhoTanh + 8: quad_tri_k<kRhoTanh + 8>(A, B, C, z, D, acc); break;
-    case kRhoX3: quad_tri_k<kRhoX3>(A, B, C, z, D, acc); break;
-    default: quad_tri_k<kRhoX16>(A, B, C, z, D, acc); break;
+#define SCVT_QUAD_CALL(V) quad_tri_k<V>(A, B, C, z, D, acc)
+  SCVT_RHO_DISPATCH(rho_variant(D), SCVT_QUAD_CALL)
+#undef SCVT_QUAD_CALL
+}
+
+// ------------------------------------------------ mixed-precision quadrature
+// The same rule with the point arithmetic in FP32, in a frame local to the
+// generator z: every quantity is a small offset from z, so FP32 keeps its
+// relative precision on the cell scale h instead of on the unit sphere.
+//   d  = p - z = sum_q lambda_q (X_q - z)      (vertex offsets formed in FP64)
+//   s  = |p|^2 - 1 = 2 z.d + |d|^2,  r = (1 + s)^(-1/2),  Jacobian r^3
+//   y - z = r d + (r - 1) z,  r - 1 = -s r^2 / (1 + r)   (no cancellation)
+//   rho at y from (z - x_c) + (y - z), with (z - x_c) formed in FP64.
+// Each sub-triangle's 7-point sums are added to FP64 accumulators (the
+// compensation for the FP32 point values); the first moment is accumulated
+// as int rho (y - z) and mu = m z + int rho (y - z) is formed in FP64.
+struct F3 {
+  float x, y, z;
+};
+SCVT_HD F3 operator+(F3 a, F3 b) { return F3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+SCVT_HD F3 operator-(F3 a, F3 b) { return F3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+SCVT_HD F3 operator*(float s, F3 a) { return F3{s * a.x, s * a.y, s * a.z}; }
+SCVT_HD float dotf(F3 a, F3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+SCVT_HD F3 crossf(F3 a, F3 b) {
+  return F3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+SCVT_HD F3 to_f3(V3 v) { return F3{(float)v.x, (float)v.y, (float)v.z}; }
+
+SCVT_HD float rsqf(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ::rsqrtf(x);
+#else
+  return 1.0f / ::sqrtf(x);
+#endif
+}
+SCVT_HD float rcpf(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
+struct DensityF {  // FP32 density parameters
+  float gamma, w_lon2i, w_lat2i, pad;
+  float amp[2], beta[2], k2l[2];  // k2l = -2 log2(e) / alpha
+};
+
+SCVT_HD DensityF density_f32(const DensityP& D) {
+  DensityF f{};
+  f.gamma = (float)D.gamma;
+  f.w_lon2i = (float)(1.0 / (D.w_lon * D.w_lon));
+  f.w_lat2i = (float)(1.0 / (D.w_lat * D.w_lat));
+  for (int k = 0; k < 2; k++) {
+    f.amp[k] = (float)D.amp[k];
+    f.beta[k] = (float)D.beta[k];
+    f.k2l[k] = (float)(D.k2[k] * 1.4426950408889634);
   }
+  return f;
+}
+
+SCVT_HD float bumpf(float amp, float beta, float k2l, float d) {
+  return amp * rcpf(1.0f + exp2f((beta - d) * k2l));
+}
+
+SCVT_HD float chord_to_anglef(float ch) {
+  float s = 0.5f * ch;
+  return 2.0f * asinf(s > 1.0f ? 1.0f : s);
+}
+
+// zc[k] = z - x_c_k (FP64 difference, rounded); zf = z rounded
+template <int KIND>
+SCVT_HD float rho_kind_f(const DensityF& D, const F3* zc, F3 zf, F3 dyz, const DensityP& Dd) {
+  constexpr int base = KIND & 7;
+  if (base == kRhoConst) return 1.0f;
+  if (base == kRhoTanh) {
+    constexpr int NB = (KIND & kVarTwo) ? 2 : 1;
+    float rho = D.gamma;
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+      F3 t = zc[k] + dyz;
+      float t2 = dotf(t, t);
+      float d = t2 > 0.0f ? t2 * rsqf(t2) : 0.0f;
+      if (KIND & kVarGeo) d = chord_to_anglef(d);
+      rho += bumpf(D.amp[k], D.beta[k], D.k2l[k], d);
+    }
+    return rho;
+  }
+  F3 y = zf + dyz;
+  if (base == kRhoX3) {
+    float z2 = y.z * y.z;
+    return (1.0f - D.gamma) * z2 * z2 + D.gamma;
+  }
+  // X16
+  float sz = y.z > 1.0f ? 1.0f : (y.z < -1.0f ? -1.0f : y.z);
+  float la = asinf(sz), lo = atan2f(y.y, y.x);
+  float czc = (float)Dd.xc[0][2];
+  czc = czc > 1.0f ? 1.0f : (czc < -1.0f ? -1.0f : czc);
+  float lac = asinf(czc), loc = atan2f((float)Dd.xc[0][1], (float)Dd.xc[0][0]);
+  F3 zic = F3{cosf(la) * cosf(loc), cosf(la) * sinf(loc), sinf(la)};
+  F3 zci = F3{cosf(lac) * cosf(lo), cosf(lac) * sinf(lo), sinf(lac)};
+  F3 t1 = y - zic, t2 = y - zci;
+  float d1 = chord_to_anglef(sqrtf(dotf(t1, t1)));
+  float d2 = chord_to_anglef(sqrtf(dotf(t2, t2)));
+  float d = sqrtf(d1 * d1 * D.w_lon2i + d2 * d2 * D.w_lat2i);
+  return bumpf(D.amp[0], D.beta[0], D.k2l[0], d) + D.gamma;
+}
+
+// sub-triangle with vertex offsets dA, dB, dC from z; accumulates m,
+// int rho (y - z) (in mx, my, mz) and e into the FP64 accumulator
+template <int KIND>
+SCVT_HD void quad_tri_mixed(F3 dA, F3 dB, F3 dC, F3 zf, const F3* zc, const DensityF& D,
+                            const DensityP& Dd, Acc5& acc) {
+  const F3 A = zf + dA;
+  const float hd = 0.5f * dotf(A, crossf(dB - dA, dC - dA));
+  float sm = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, se = 0.f;
+#pragma unroll 1
+  for (int q = 0; q < 7; q++) {
+    const float l0 = (float)kRule7[q][0], l1 = (float)kRule7[q][1], l2 = (float)kRule7[q][2];
+    F3 d = l0 * dA + l1 * dB + l2 * dC;
+    float s = 2.0f * dotf(zf, d) + dotf(d, d);
+    float r = rsqf(1.0f + s);
+    float rm1 = -s * r * r * rcpf(1.0f + r);
+    F3 dyz = r * d + rm1 * zf;
+    float jac = r * r * r;
+    float wt = hd * (float)kRule7[q][3] * jac * rho_kind_f<KIND>(D, zc, zf, dyz, Dd);
+    sm += wt;
+    sx += wt * dyz.x;
+    sy += wt * dyz.y;
+    sz += wt * dyz.z;
+    se += wt * dotf(dyz, dyz);
+  }
+  acc.m += (double)sm;
+  acc.mx += (double)sx;
+  acc.my += (double)sy;
+  acc.mz += (double)sz;
+  acc.e += (double)se;
 }
 
 // a / |a| through the reciprocal square root (quadrature only; the shared

@@ -345,8 +345,9 @@ __global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
 // One wave per cell (index order).  Every lane integrates items lane,
 // lane+64, ... of the E * 4^levels (edge, leaf) pairs; the five sums are
 // reduced across the wave in a fixed butterfly order, so the result does not
-// depend on scheduling.
-template <int KIND>
+// depend on scheduling.  MIXED: FP32 points in the generator's local frame
+// (quad_tri_mixed), FP64 sub-triangle vertices, accumulation and epilogue.
+template <int KIND, bool MIXED>
 __global__ __launch_bounds__(256) void k_quad(CellArgs a) {
   const int ln = lane_id();
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -358,6 +359,14 @@ __global__ __launch_bounds__(256) void k_quad(CellArgs a) {
   const int per = 1 << (2 * lv);
   const int total = E * per;
   Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
+  F3 zf{}, zc[2]{};
+  DensityF Df{};
+  if (MIXED) {
+    zf = to_f3(z);
+    Df = density_f32(a.rho);
+    for (int k = 0; k < 2; k++)
+      zc[k] = to_f3(z - V3{a.rho.xc[k][0], a.rho.xc[k][1], a.rho.xc[k][2]});
+  }
   for (int t = ln; t < total; t += 64) {
     const int e = t >> (2 * lv), s = t & (per - 1);
     const double* ed = o.edges + (i * kVmax + e) * 6;
@@ -365,7 +374,10 @@ __global__ __launch_bounds__(256) void k_quad(CellArgs a) {
     V3 B = V3{ed[0], ed[1], ed[2]};
     V3 C = V3{ed[3], ed[4], ed[5]};
     subtriangle(A, B, C, s, lv);
-    quad_tri_k<KIND>(A, B, C, z, a.rho, acc);
+    if (MIXED)
+      quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), zf, zc, Df, a.rho, acc);
+    else
+      quad_tri_k<KIND>(A, B, C, z, a.rho, acc);
   }
   acc.m = wave_sum(acc.m);
   acc.mx = wave_sum(acc.mx);
@@ -374,6 +386,7 @@ __global__ __launch_bounds__(256) void k_quad(CellArgs a) {
   acc.e = wave_sum(acc.e);
   if (ln == 0) {
     V3 mu = V3{acc.mx, acc.my, acc.mz};
+    if (MIXED) mu = acc.m * z + mu;  // first moment from int rho (y - z)
     double mz = dot(mu, z);
     V3 g = 2.0 * mz * z - 2.0 * mu;
     V3 l = normalized(mu) - z;
@@ -414,13 +427,15 @@ hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s) {
 
 hipError_t launch_quad(const CellArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)((a.n + 3) / 4);
-  switch (rho_variant(a.rho)) {
-    case kRhoConst: k_quad<kRhoConst><<<nb, 256, 0, s>>>(a); break;
-    case kRhoTanh: k_quad<kRhoTanh><<<nb, 256, 0, s>>>(a); break;
-    case kRhoTanh + 8: k_quad<kRhoTanh + 8><<<nb, 256, 0, s>>>(a); break;
-    case kRhoX3: k_quad<kRhoX3><<<nb, 256, 0, s>>>(a); break;
-    default: k_quad<kRhoX16><<<nb, 256, 0, s>>>(a); break;
-  }
+#define SCVT_LAUNCH_QUAD(V)                                  \
+  do {                                                       \
+    if (a.mixed)                                             \
+      k_quad<V, true><<<nb, 256, 0, s>>>(a);                 \
+    else                                                     \
+      k_quad<V, false><<<nb, 256, 0, s>>>(a);                \
+  } while (0)
+  SCVT_RHO_DISPATCH(rho_variant(a.rho), SCVT_LAUNCH_QUAD)
+#undef SCVT_LAUNCH_QUAD
   return hipGetLastError();
 }
 

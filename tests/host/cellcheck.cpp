@@ -145,6 +145,36 @@ int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int
   return 0;
 }
 
+// Mixed-precision cell integrals as the kernel computes them (FP64
+// sub-triangles, FP32 local-frame points, FP64 accumulation, mu = m z + ...)
+int hc_quad_mixed(const double* z3, int E, const double* verts, const DensityP* D, int levels,
+                  double* out5) {
+  Acc5 acc = {0, 0, 0, 0, 0};
+  DensityP Dp = density_prepare(*D);
+  V3 z = V3{z3[0], z3[1], z3[2]};
+  F3 zf = to_f3(z);
+  DensityF Df = density_f32(Dp);
+  F3 zc[2];
+  for (int k = 0; k < 2; k++) zc[k] = to_f3(z - V3{Dp.xc[k][0], Dp.xc[k][1], Dp.xc[k][2]});
+  const int per = 1 << (2 * levels);
+  const int var = rho_variant(Dp);
+  for (int t = 0; t < E * per; t++) {
+    int e = t >> (2 * levels), s = t & (per - 1);
+    V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
+       C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
+    subtriangle(A, B, C, s, levels);
+#define HC_MIXED(V) quad_tri_mixed<V>(to_f3(A - z), to_f3(B - z), to_f3(C - z), zf, zc, Df, Dp, acc)
+    SCVT_RHO_DISPATCH(var, HC_MIXED)
+#undef HC_MIXED
+  }
+  out5[0] = acc.m;
+  out5[1] = acc.m * z.x + acc.mx;
+  out5[2] = acc.m * z.y + acc.my;
+  out5[3] = acc.m * z.z + acc.mz;
+  out5[4] = acc.e;
+  return 0;
+}
+
 // Grid helpers: grid parameters for n, the window for (z, rt), the cell of
 // p on face f (-1 outside the face's extended grid).
 int hc_grid(int64_t n, int32_t* GBW, double* dd) {

@@ -67,7 +67,8 @@ class CDensity(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("geodesic", ctypes.c_int32), ("nbumps", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("xc", ctypes.c_double * 6), ("beta", ctypes.c_double * 2),
                 ("alpha", ctypes.c_double * 2), ("amp", ctypes.c_double * 2),
-                ("gamma", ctypes.c_double), ("w_lon", ctypes.c_double), ("w_lat", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("w_lon", ctypes.c_double), ("w_lat", ctypes.c_double),
+                ("k2", ctypes.c_double * 2)]
 
 
 KIND = {"const": 0, "tanh": 1, "x3": 2, "x16": 3}
@@ -97,6 +98,16 @@ def quad(z, E, verts, density, levels=2):
     out = np.zeros(5)
     D = cdensity(density)
     lib().hc_quad(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D), ctypes.c_int(levels), P(out))
+    return out
+
+
+def quad_mixed(z, E, verts, density, levels=2):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    out = np.zeros(5)
+    D = cdensity(density)
+    lib().hc_quad_mixed(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D), ctypes.c_int(levels),
+                        P(out))
     return out
 
 

@@ -254,3 +254,41 @@ def test_full_size_sampled(scvt):
     info = S.step()
     info = S.step()
     assert info["F"] < F
+
+
+@pytest.mark.parametrize("case", ["tanh16", "two_centre", "const"])
+def test_mixed_precision_error(scvt, case):
+    """Mixed path (FP32 local-frame quadrature, FP64 geometry and
+    reductions) against the FP64 oracle at the same generators: per cell
+    |dm|/m <= 1e-5, |de|/e <= 1e-5, centroid error <= 1e-6 R_i; F to 1e-6.
+    The measured errors are printed."""
+    n, d = {"tanh16": (30011, I.CONFIGS["C3"]["density"]),
+            "two_centre": (20011, I.density_two_centre()),
+            "const": (2562, {"kind": "const"})}[case]
+    Z = I.uniform_sphere(n, 12)
+    S = scvt.Solver(Z, d, precision="mixed", keep_cells=True)
+    Zg = S.generators()
+    ev = oracle.evaluate(Zg, d)
+    F, m, cen, e = S.energy()
+    R = S.vector("R")
+    dm = np.abs(m - ev.m) / ev.m
+    de = np.abs(e - ev.e) / ev.e
+    dc = np.linalg.norm(cen - ev.centroid, axis=1) / R
+    print("mixed %s: max dm/m %.2e  de/e %.2e  dc/R %.2e  dF/F %.2e" %
+          (case, dm.max(), de.max(), dc.max(), abs(F - ev.F) / ev.F))
+    assert dm.max() <= 1e-5 and de.max() <= 1e-5 and dc.max() <= 1e-6
+    assert abs(F - ev.F) <= 1e-6 * ev.F
+    # the geometry is the FP64 path's: same neighbour sets
+    nbr, deg, verts, flags = S.cells()
+    nb, flagged = oracle_nbr_sets(Zg, ev)
+    for k in range(0, n, 7):
+        assert set(nbr[k][:deg[k]].tolist()) == nb[k]
+
+
+def test_mixed_solver_decreases_energy(scvt):
+    d = I.CONFIGS["C3"]["density"]
+    S = scvt.Solver(I.uniform_sphere(20000, 13), d, precision="mixed", m_hist=10)
+    F = [S.energy()[0]]
+    for _ in range(10):
+        F.append(S.step()["F"])
+    assert np.all(np.diff(F) <= 0)

@@ -172,3 +172,23 @@ def test_home_face_inside_its_grid():
     for f in range(6):
         sel = X[hf == f]
         assert np.all(hc.cell_on_face(GBW, dd, sel, f) >= 0)
+
+
+@pytest.mark.parametrize("density", ["const", "tanh16", "two", "x3", "geo", "x16"])
+def test_mixed_quadrature_error(density):
+    """FP32 local-frame quadrature (the mixed path) against the FP64 oracle:
+    per cell |dm|/m <= 1e-5, |de|/e <= 1e-5, |dc| <= 1e-6 R (R the cell's
+    circumradius)."""
+    d = {"const": {"kind": "const"}, "tanh16": I.CONFIGS["C3"]["density"],
+         "two": I.density_two_centre(), "x3": I.density_x3(), "geo": I.density_x64(),
+         "x16": I.density_x16()}[density]
+    n = 4000
+    Z = I.uniform_sphere(n, 5)
+    ev = oracle.evaluate(Z, d)
+    h = math.sqrt(4 * math.pi / n)
+    st, deg, nbr, verts, R = hc.cells(Z, 4 * h)
+    for k in np.where(st == 0)[0][::3]:
+        out = hc.quad_mixed(Z[k], deg[k], verts[k], d)
+        assert abs(out[0] - ev.m[k]) <= 1e-5 * ev.m[k]
+        assert abs(out[4] - ev.e[k]) <= 1e-5 * ev.e[k]
+        assert np.linalg.norm(out[1:4] / out[0] - ev.centroid[k]) <= 1e-6 * R[k]
