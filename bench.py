@@ -9,7 +9,10 @@ alpha = 0.15), M = 10.  Generators start resident in HBM; the timed region is
 K iterations from the seeded start, bracketed by device synchronisation.
 
 Prints one JSON line.  Options: --steps K (default 200, the workload's
-iteration count), --warmup W, --precision fp64|mixed|both, --no-cpu-baseline.
+iteration count), --warmup W, --precision fp64|mixed|both (default both:
+`value` is the FP64 path, the "mixed" object the mixed-precision path),
+--no-cpu-baseline, --copy-calibration (only run a plain 256 MiB device copy,
+used to scale the profiler's FETCH_SIZE / WRITE_SIZE counters).
 """
 import argparse
 import json
@@ -25,6 +28,7 @@ METRIC = "SCVT iterations/sec at 1M generators (FP64 vs mixed); p50/p99 solve la
 
 # MI355X published peaks used as roofline denominators
 PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # published, with packed FP32 (not generated here)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -92,9 +96,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
               "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -156,10 +170,22 @@ def main():
     }
     for p in precisions[1:]:
         rr = runs[p]
+        qms = rr["quad"]["total_ms"] / max(rr["quad"]["launches"], 1)
+        qfl = cell_flops(rr["mean_degree"]) * n
         line[p] = {"value": args.steps / rr["elapsed_s"], "unit": "iterations/s",
-                   "quad_ms_per_eval": rr["quad"]["total_ms"] / max(rr["quad"]["launches"], 1),
-                   "F_end": rr["info"]["F"]}
+                   "ms_per_step": 1000.0 * rr["elapsed_s"] / args.steps,
+                   "dtype": "f32 quadrature points, f64 geometry/accumulation/LBFGS",
+                   "kernels_ms_per_eval": {k: rr[k]["total_ms"] / max(rr[k]["launches"], 1)
+                                           for k in ("geom", "fallback", "quad", "grid", "eval")},
+                   "F_end": rr["info"]["F"],
+                   "roofline": {"kernel": "k_quad (mixed)", "bound": "alu",
+                                "achieved": qfl / (qms * 1e-3) / 1e12,
+                                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                "frac": qfl / (qms * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+                                "avg_launch_ms": qms}}
     if not args.no_cpu_baseline:
+        print("bench: timing the oracle on the host (one iteration at n=%d)" % n,
+              file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cfg, Z0)
     print(json.dumps(line), flush=True)
 
