@@ -181,6 +181,39 @@ int scvt_kernel_time(scvt_handle* h, int kernel, double* total_ms, int64_t* laun
 void scvt_destroy(scvt_handle* h);
 const char* scvt_strerror(int code);
 
+/* Device memory a handle with this configuration allocates (bytes). */
+int scvt_footprint(const scvt_config* cfg, size_t* bytes);
+
+/* ------------------------------------------------------------- serving --
+ * A persistent request loop (north of the per-iteration path): requests of
+ * any size and density are submitted while others run.  A request is
+ * admitted when one of max_slots slots is free and its footprint
+ * (scvt_footprint) fits in what hbm_budget has left, first come first
+ * served; it then runs on its own HIP stream with its generators, cells and
+ * LBFGS history resident in HBM, concurrently with the other admitted
+ * requests, until step_inf < tol or max_iter iterations.  Results do not
+ * depend on the other requests (all kernels are deterministic).
+ * The server uses the device current at creation.  Submit copies z0 (host,
+ * n x 3); cfg->hip_stream is ignored.  Errors: SCVT_E_INVALID,
+ * SCVT_E_OOM (footprint above the whole budget). */
+typedef struct scvt_server scvt_server;
+int scvt_server_create(size_t hbm_budget, int max_slots, scvt_server** out);
+int scvt_server_submit(scvt_server* s, const scvt_config* cfg, const double* z0, double tol,
+                       int64_t max_iter, int64_t* req_id);
+/* SCVT_PENDING while waiting or running; otherwise the request's final
+ * status (SCVT_OK, SCVT_NOT_CONVERGED or an error), with the final
+ * generators in z_out (n x 3 host, may be NULL), its record in info and
+ * times[0..2] = submission, admission and completion (seconds, steady
+ * clock), each output optional. */
+int scvt_server_poll(scvt_server* s, int64_t req_id, double* z_out, scvt_info* info,
+                     double* times);
+/* Forget a finished request (frees its host copy of the result). */
+int scvt_server_release(scvt_server* s, int64_t req_id);
+/* Queue depth, running requests and device bytes held by them. */
+int scvt_server_stats(scvt_server* s, int64_t* waiting, int64_t* running, size_t* bytes_used);
+/* Drops waiting requests, waits for running ones, frees everything. */
+void scvt_server_destroy(scvt_server* s);
+
 #ifdef __cplusplus
 }
 #endif

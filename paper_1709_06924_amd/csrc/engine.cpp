@@ -69,6 +69,8 @@ struct scvt_handle {
   int main_path = 1;
   double r_default = 0;
   double* shared_edges = nullptr;
+  bool dry_run = false;
+  size_t dry_bytes = 0;
 };
 
 namespace {
@@ -87,6 +89,11 @@ template <class T>
 int dalloc(scvt_handle* h, T** p, size_t count) {
   void* v = nullptr;
   if (count == 0) count = 1;
+  if (h->dry_run) {  // footprint only: count the bytes, allocate nothing
+    h->dry_bytes += (count * sizeof(T) + 255) / 256 * 256;
+    *p = (T*)(uintptr_t)256;
+    return SCVT_OK;
+  }
   if (hipMalloc(&v, count * sizeof(T)) != hipSuccess) return SCVT_E_OOM;
   h->allocs.push_back(v);
   *p = (T*)v;
@@ -468,7 +475,7 @@ void destroy(scvt_handle* h) {
   delete h;
 }
 
-int init_device_state(scvt_handle* h) {
+int alloc_device_state(scvt_handle* h) {
   const int64_t n = h->n;
   const int M = h->M;
   h->grid.g = make_grid(n);
@@ -500,6 +507,15 @@ int init_device_state(scvt_handle* h) {
   ALLOC(h->grid.order, n);
   ALLOC(h->grid.scan_tmp, 2 * ((nc + 1) / 2048 + 2));
   ALLOC(h->grid.overflow, 1);
+  return SCVT_OK;
+}
+
+int init_device_state(scvt_handle* h) {
+  int rc = alloc_device_state(h);
+  if (rc) return rc;
+  const int64_t n = h->n;
+  const int M = h->M;
+  const int64_t nc = h->grid.g.ncells;
   if (hipHostMalloc((void**)&h->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return SCVT_E_OOM;
   for (auto& e : h->ev)
@@ -522,6 +538,22 @@ int init_device_state(scvt_handle* h) {
 
 // =============================================================== C ABI ====
 extern "C" {
+
+int scvt_footprint(const scvt_config* cfg, size_t* bytes) {
+  if (!bytes) return SCVT_E_INVALID;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  scvt_handle* h = new (std::nothrow) scvt_handle();
+  if (!h) return SCVT_E_OOM;
+  h->cfg = *cfg;
+  h->n = cfg->n;
+  h->M = cfg->m_hist;
+  h->dry_run = true;
+  rc = alloc_device_state(h);
+  *bytes = h->dry_bytes;
+  delete h;
+  return rc;
+}
 
 int scvt_config_init(scvt_config* c, int64_t n) {
   if (!c) return SCVT_E_INVALID;

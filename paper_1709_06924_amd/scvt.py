@@ -70,6 +70,16 @@ _sig = {
     "scvt_kernel_time": (ctypes.c_int, [_H, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int64)]),
     "scvt_destroy": (None, [_H]),
     "scvt_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "scvt_footprint": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]),
+    "scvt_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_H)]),
+    "scvt_server_submit": (ctypes.c_int, [_H, ctypes.POINTER(Config), _vp, ctypes.c_double,
+                                          ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "scvt_server_poll": (ctypes.c_int, [_H, ctypes.c_int64, _vp, ctypes.POINTER(Info), _dp]),
+    "scvt_server_release": (ctypes.c_int, [_H, ctypes.c_int64]),
+    "scvt_server_stats": (ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "scvt_server_destroy": (None, [_H]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -246,3 +256,65 @@ class Solver:
         _check(_lib.scvt_kernel_time(self.h, int(kernel), ctypes.byref(ms), ctypes.byref(cnt)),
                "scvt_kernel_time")
         return ms.value, cnt.value
+
+
+def footprint(n, density=None, **kw):
+    """Device bytes a solver with this configuration allocates."""
+    c = make_config(n, density, **kw)
+    b = ctypes.c_size_t()
+    _check(_lib.scvt_footprint(ctypes.byref(c), ctypes.byref(b)), "scvt_footprint")
+    return b.value
+
+
+class Server:
+    """Persistent request loop (scvt_server): submit requests at any time,
+    poll for results.  Admission by slots and HBM footprint."""
+
+    def __init__(self, hbm_budget, max_slots=8):
+        h = _H()
+        _check(_lib.scvt_server_create(int(hbm_budget), int(max_slots), ctypes.byref(h)),
+               "scvt_server_create")
+        self.h = h
+        self.n_of = {}
+
+    def submit(self, z0, density, tol, max_iter, **kw):
+        z0 = np.ascontiguousarray(z0, dtype=np.float64)
+        c = make_config(len(z0), density, **kw)
+        rid = ctypes.c_int64()
+        _check(_lib.scvt_server_submit(self.h, ctypes.byref(c), z0.ctypes.data_as(ctypes.c_void_p),
+                                       float(tol), int(max_iter), ctypes.byref(rid)),
+               "scvt_server_submit")
+        self.n_of[rid.value] = len(z0)
+        return rid.value
+
+    def poll(self, rid, want_z=True):
+        """None while pending, else a dict with status, info, times, z."""
+        n = self.n_of[rid]
+        z = np.zeros((n, 3)) if want_z else None
+        info = Info()
+        times = np.zeros(3)
+        rc = _lib.scvt_server_poll(self.h, int(rid),
+                                   z.ctypes.data_as(ctypes.c_void_p) if want_z else None,
+                                   ctypes.byref(info), times.ctypes.data_as(_dp))
+        if rc == SCVT_PENDING:
+            return None
+        return {"status": rc, "info": info.as_dict(), "t_submit": times[0], "t_start": times[1],
+                "t_done": times[2], "z": z}
+
+    def release(self, rid):
+        _check(_lib.scvt_server_release(self.h, int(rid)), "scvt_server_release")
+        self.n_of.pop(rid, None)
+
+    def stats(self):
+        w, r, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(_lib.scvt_server_stats(self.h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(b)),
+               "scvt_server_stats")
+        return {"waiting": w.value, "running": r.value, "bytes_used": b.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.scvt_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
