@@ -99,6 +99,10 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=24)
+    ap.add_argument("--serving-rate", type=float, default=20.0)
+    ap.add_argument("--serving-max-iter", type=int, default=200)
+    ap.add_argument("--serving-slots", type=int, default=8)
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -183,6 +187,21 @@ def main():
                                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                                 "frac": qfl / (qms * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
                                 "avg_launch_ms": qms}}
+    if args.serving_requests > 0:
+        from paper_1709_06924_amd import serving
+        stream = I.serving_stream(seed=4, rate=args.serving_rate, count=args.serving_requests)
+        print("bench: serving %d requests at %.0f req/s" % (len(stream), args.serving_rate),
+              file=sys.stderr, flush=True)
+        records, summ = serving.run_stream(
+            stream, tol=1e-8, max_iter=args.serving_max_iter, max_slots=args.serving_slots,
+            hbm_budget=64 << 30, precision="mixed", m_hist=10,
+            log=lambda m: print(m, file=sys.stderr, flush=True))
+        summ.update({"workload": "Poisson %.0f req/s (seed 4), first %d requests, n log-uniform "
+                                 "in [10242, 655362], per-request tanh density, mixed precision, "
+                                 "M=10, tol 1e-8 with an iteration cap of %d"
+                                 % (args.serving_rate, len(stream), args.serving_max_iter),
+                     "max_slots": args.serving_slots, "hbm_budget_bytes": 64 << 30})
+        line["serving"] = summ
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host (one iteration at n=%d)" % n,
               file=sys.stderr, flush=True)

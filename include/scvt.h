@@ -54,7 +54,7 @@ extern "C" {
 #define SCVT_E_OOM -2          /* device allocation failed or over budget */
 #define SCVT_E_DEGENERATE -3   /* duplicate or zero generators */
 #define SCVT_E_CERT -4         /* a Voronoi cell could not be built */
-#define SCVT_E_LINESEARCH -5   /* no sufficient decrease, also after reset */
+#define SCVT_E_LINESEARCH -5   /* reserved (the Lloyd step is taken instead) */
 #define SCVT_E_NUMERIC -6      /* NaN, or mu_i . z_i <= 0 (h undefined) */
 #define SCVT_E_HIP -7          /* a HIP runtime call failed */
 
@@ -113,6 +113,8 @@ typedef struct {
   int64_t n_degenerate; /* cells with a predicate inside its error bound */
   int32_t status;       /* last return code */
   int32_t hist_len;     /* stored pairs */
+  int64_t n_lloyd_fallback; /* iterations that took the Lloyd step after the
+                               line search found no sufficient decrease */
 } scvt_info;
 
 /* Fill *cfg with defaults for n generators: M = 7, FP64, rho = 1,
@@ -129,7 +131,10 @@ int scvt_config_init(scvt_config* cfg, int64_t n);
 int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt_handle** out);
 
 /* One P-LBFGS iteration (two-loop direction, descent check with reset to the
- * Lloyd direction, Armijo line search, history update).  info may be NULL. */
+ * Lloyd direction, Armijo line search, history update).  If the line search
+ * finds no sufficient decrease in ls_max_evals evaluations, the history is
+ * cleared and the Lloyd step (alpha = 1) is taken, which decreases F in
+ * exact arithmetic (section 2.2.1).  info may be NULL. */
 int scvt_step(scvt_handle* h, scvt_info* info);
 
 /* Iterate until step_inf < tol_step_inf or max_iter iterations in total.

@@ -18,6 +18,8 @@ of eq. loyInit).  The line search is the documented reading: Armijo
 backtracking from alpha = 1 (the Lloyd step length, section 3.1), factor 1/2,
 c1 = 1e-4, at most ten evaluations (section 4: ten evaluations, M = 7 by
 default); every trial point is projected back to the sphere (section 3.1).
+When no trial passes, the history is cleared and the Lloyd step itself is
+taken (it decreases F without a line search, section 2.2.1).
 """
 import numpy as np
 
@@ -105,6 +107,7 @@ class Solver:
         self.iter = 0
         self.n_evals = 1
         self.last_alpha = 0.0
+        self.n_lloyd_fallback = 0
         self.history_F = [self.cur.F]
 
     @property
@@ -134,13 +137,16 @@ class Solver:
             q = -cur.h[:, None] * cur.g
             gq = dot(cur.g, q)
         alpha, ev = self._line_search(q, gq)
-        if ev is None and self.hist:                   # reset to the Lloyd step
+        if ev is None:
+            # no sufficient decrease within the evaluation budget: take the
+            # Lloyd step (alpha = 1 along -h g), which decreases F without a
+            # line search (section 2.2.1), and restart the history
             self.hist = []
             q = -cur.h[:, None] * cur.g
-            gq = dot(cur.g, q)
-            alpha, ev = self._line_search(q, gq)
-        if ev is None:
-            raise RuntimeError("line search failed")
+            ev = evaluate(normalize_rows(cur.Z + q), self.density, self.levels)
+            self.n_evals += 1
+            alpha = 1.0
+            self.n_lloyd_fallback += 1
         s = ev.Z - cur.Z
         y = ev.g - cur.g
         ys = dot(y, s)

@@ -59,7 +59,7 @@ struct scvt_handle {
   std::vector<int> free_slots;
   // current state
   double F = 0, step_inf = 0, gnorm2 = 0, min_mz = 0, alpha = 0;
-  int64_t iter = 0, n_evals = 0, n_fb = 0, n_deg = 0;
+  int64_t iter = 0, n_evals = 0, n_fb = 0, n_deg = 0, n_lloyd_fallback = 0;
   // evaluation results of the last trial
   double tF = 0, tstep = 0, tg2 = 0, tmz = 0;
   int64_t tfb = 0, tdeg = 0;
@@ -433,14 +433,23 @@ int do_step(scvt_handle* h) {
   double alpha = 0.0;
   rc = line_search(h, gq, &ok, &alpha);
   if (rc) return rc;
-  if (!ok && !h->ring.empty()) {
+  if (!ok) {
+    // No sufficient decrease along the direction within ls_max_evals
+    // evaluations -- near convergence the energy differences fall below the
+    // evaluation's rounding (the mixed path's FP32 quadrature above all).
+    // Take the Lloyd step (alpha = 1 along -h g, i.e. z <- mu/|mu|), which
+    // decreases F without a line search (section 2.2.1), and restart the
+    // history from there.
     clear_history(h);
     rc = direction(h, &gq);
     if (rc) return rc;
-    rc = line_search(h, gq, &ok, &alpha);
-    if (rc) return rc;
+    HIPCK(launch_normalize_trial(h->Z, h->q, 1.0, h->Zt, h->n, h->stream));
+    rc = evaluate(h, h->Zt, h->trial);
+    h->n_evals++;
+    if (rc < 0) return rc;
+    alpha = 1.0;
+    h->n_lloyd_fallback++;
   }
-  if (!ok) return SCVT_E_LINESEARCH;
   rc = push_pair(h);
   if (rc) return rc;
   swap_sets(h);
@@ -462,6 +471,7 @@ void fill_info(scvt_handle* h, scvt_info* info, int status) {
   info->n_degenerate = h->n_deg;
   info->status = status;
   info->hist_len = (int32_t)h->ring.size();
+  info->n_lloyd_fallback = h->n_lloyd_fallback;
 }
 
 void destroy(scvt_handle* h) {

@@ -46,7 +46,7 @@ class Info(ctypes.Structure):
                 ("grad_norm2", ctypes.c_double), ("step_inf", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("n_fallback", ctypes.c_int64),
                 ("n_degenerate", ctypes.c_int64), ("status", ctypes.c_int32),
-                ("hist_len", ctypes.c_int32)]
+                ("hist_len", ctypes.c_int32), ("n_lloyd_fallback", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

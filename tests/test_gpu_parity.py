@@ -292,3 +292,19 @@ def test_mixed_solver_decreases_energy(scvt):
     for _ in range(10):
         F.append(S.step()["F"])
     assert np.all(np.diff(F) <= 0)
+
+
+def test_lloyd_fallback_matches_oracle(scvt):
+    """Failure handling forced from the host: one evaluation per line search
+    and c1 = 0.9999 make the Armijo test fail, so iterations take the Lloyd
+    step; the trajectory matches the oracle's."""
+    n = 2000
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    Z0 = I.uniform_sphere(n, 15)
+    S = scvt.Solver(Z0, d, m_hist=7, ls_max_evals=1, ls_c1=0.9999)
+    O = oracle.Solver(Z0, d, m_hist=7, ls_max_evals=1, c1=0.9999)
+    for _ in range(6):
+        info = S.step()
+        O.step()
+    assert info["n_lloyd_fallback"] == O.n_lloyd_fallback >= 1
+    assert np.max(np.abs(S.generators() - O.Z)) < 1e-10

@@ -140,3 +140,21 @@ def test_x3_energy_near_paper_table():
         for z, w in zip(*np.polynomial.legendre.leggauss(200)))
     bound = 5 / (18 * math.sqrt(3)) * sqrt_mass ** 2 / n
     assert 1.0 <= ev.F / bound < 1.015
+
+
+def test_line_search_failure_takes_lloyd_step():
+    """With one evaluation per line search and c1 close to 1 the Armijo test
+    fails; the iteration then takes the Lloyd step mu/|mu| (section 2.2.1)
+    and clears the history."""
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    S = oracle.Solver(I.uniform_sphere(300, 14), d, m_hist=7, ls_max_evals=1, c1=0.9999)
+    for _ in range(6):
+        ev0 = S.cur
+        n0 = S.n_lloyd_fallback
+        S.step()
+        if S.n_lloyd_fallback > n0:
+            target = ev0.mu / np.linalg.norm(ev0.mu, axis=1)[:, None]
+            assert np.max(np.abs(S.Z - target)) < 1e-14
+            assert len(S.hist) <= 1
+    assert S.n_lloyd_fallback >= 1
+    assert S.history_F[-1] < S.history_F[0]
