@@ -96,6 +96,9 @@ typedef struct {
   int32_t ls_max_evals; /* energy evaluations per line search (default 10) */
   double ls_c1;         /* Armijo constant (default 1e-4) */
   double curv_eps;      /* store (s,y) only if y.s > curv_eps |y||s| (default 1e-10) */
+  double ls_noise;      /* Armijo allowance: accept F' <= F + c1 alpha g.q + ls_noise |F|;
+                           < 0 = automatic: 0 for FP64, 1e-8 for the mixed path, whose FP32
+                           quadrature leaves ~1e-9 relative noise in energy differences */
   int32_t keep_cells;   /* 1: keep a copy of every cell for scvt_get_cells */
   int32_t reserved;
   void* hip_stream;     /* hipStream_t to order work on, or NULL */
@@ -119,7 +122,7 @@ typedef struct {
 
 /* Fill *cfg with defaults for n generators: M = 7, FP64, rho = 1,
  * 2 subdivision levels, 10 evaluations per line search, c1 = 1e-4,
- * curv_eps = 1e-10, no cell copy, NULL stream. */
+ * curv_eps = 1e-10, automatic ls_noise, no cell copy, NULL stream. */
 int scvt_config_init(scvt_config* cfg, int64_t n);
 
 /* Create a solver.  z0: n x 3 (host, or device if z0_on_device); rows are

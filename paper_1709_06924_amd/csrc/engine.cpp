@@ -71,6 +71,7 @@ struct scvt_handle {
   double* shared_edges = nullptr;
   bool dry_run = false;
   size_t dry_bytes = 0;
+  double ls_noise = 0.0;
 };
 
 namespace {
@@ -373,7 +374,7 @@ int line_search(scvt_handle* h, double gq, bool* accepted, double* alpha_out) {
     int rc = evaluate(h, h->Zt, h->trial);
     h->n_evals++;
     if (rc < 0) return rc;
-    if (h->tF <= h->F + h->cfg.ls_c1 * alpha * gq) {
+    if (h->tF <= h->F + h->cfg.ls_c1 * alpha * gq + h->ls_noise * fabs(h->F)) {
       *accepted = true;
       *alpha_out = alpha;
       return SCVT_OK;
@@ -579,6 +580,7 @@ int scvt_config_init(scvt_config* c, int64_t n) {
   c->ls_max_evals = 10;
   c->ls_c1 = 1e-4;
   c->curv_eps = 1e-10;
+  c->ls_noise = -1.0;
   c->keep_cells = 0;
   c->hip_stream = nullptr;
   return SCVT_OK;
@@ -604,6 +606,7 @@ int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt
   h->n = n;
   h->M = cfg->m_hist;
   h->rho = to_dev(cfg->rho);
+  h->ls_noise = cfg->ls_noise >= 0.0 ? cfg->ls_noise : (cfg->precision == SCVT_MIXED ? 1e-8 : 0.0);
   if (cfg->hip_stream) {
     h->stream = (hipStream_t)cfg->hip_stream;
   } else {

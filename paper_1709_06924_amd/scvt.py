@@ -37,7 +37,8 @@ class Config(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m_hist", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rho", Density), ("quad_levels", ctypes.c_int32),
                 ("ls_max_evals", ctypes.c_int32), ("ls_c1", ctypes.c_double),
-                ("curv_eps", ctypes.c_double), ("keep_cells", ctypes.c_int32),
+                ("curv_eps", ctypes.c_double), ("ls_noise", ctypes.c_double),
+                ("keep_cells", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
 
 
@@ -122,7 +123,7 @@ def density_struct(d):
 
 
 def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_max_evals=10,
-                ls_c1=1e-4, curv_eps=1e-10, keep_cells=False, stream=None):
+                ls_c1=1e-4, curv_eps=1e-10, keep_cells=False, stream=None, ls_noise=-1.0):
     c = Config()
     _check(_lib.scvt_config_init(ctypes.byref(c), int(n)), "scvt_config_init")
     c.m_hist = int(m_hist)
@@ -132,6 +133,7 @@ def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_m
     c.ls_max_evals = int(ls_max_evals)
     c.ls_c1 = float(ls_c1)
     c.curv_eps = float(curv_eps)
+    c.ls_noise = float(ls_noise)
     c.keep_cells = 1 if keep_cells else 0
     c.hip_stream = stream
     return c
