@@ -138,21 +138,32 @@ struct EdgeRes {
 };
 
 struct CandView {  // structure-of-arrays view (LDS on the device)
-  const double *px, *py, *pz, *dx, *dy, *dz;
+  const double *px, *py, *pz, *dx, *dy, *dz, *nrm;  // nrm[l] = |d_l|
   SCVT_HD V3 p(int l) const { return V3{px[l], py[l], pz[l]}; }
   SCVT_HD V3 d(int l) const { return V3{dx[l], dy[l], dz[l]}; }
 };
 
+// Error bound for det(a, b, c) of rounded difference vectors: 16u times the
+// permanent (see det_pred), and the permanent's six terms are each at most
+// |a||b||c|, so 96u |a||b||c| bounds the error from the norms alone.
+constexpr double kDetBound = 96.0 * kU;
+
 SCVT_HD EdgeRes edge_on_bisector(int j, int ns, V3 z, const CandView& S) {
   const V3 dj = S.d(j), pj = S.p(j);
+  const double nj = S.nrm[j];
+  // sigma_jl = det(z, d_j, d_l) = d_l . (z x d_j), |z| = 1
+  const V3 wj = cross(z, dj);
+  const double ebj = kDetBound * nj;
   int lo = -1, hi = -1;
-  CrossCache clo{}, chi{};
+  V3 clo = V3{0, 0, 0}, chi = V3{0, 0, 0};  // d_j x d_lo, d_j x d_hi
+  double elo = 0.0, ehi = 0.0;              // kDetBound |d_j| |d_lo| (|d_hi|)
   bool degenerate = false;
   for (int l = 0; l < ns; l++) {
     if (l == j) continue;
     const V3 dl = S.d(l);
-    Pred sg = det_pred(z, dj, dl);
-    if (fabs(sg.v) <= sg.err) {
+    const double nl = S.nrm[l];
+    const double sg = dot(dl, wj);
+    if (fabs(sg) <= ebj * nl) {
       // lines (nearly) parallel in the chart: line l either leaves all of
       // line j feasible or none of it; decided at the foot of line j by the
       // sign of d_l . (p_l - p_j)
@@ -164,39 +175,43 @@ SCVT_HD EdgeRes edge_on_bisector(int j, int ns, V3 z, const CandView& S) {
       degenerate = true;
       continue;
     }
-    if (sg.v > 0.0) {
+    if (sg > 0.0) {
       if (hi < 0) {
         hi = l;
-        chi = make_cross(dj, dl);
+        chi = cross(dj, dl);
+        ehi = ebj * nl;
       } else {
-        Pred o = det_cached(chi, dl);  // det(d_j, d_hi, d_l)
-        if (fabs(o.v) <= o.err) {
+        const double o = dot(dl, chi);  // det(d_j, d_hi, d_l)
+        if (fabs(o) <= ehi * nl) {
           degenerate = true;
-        } else if (o.v > 0.0) {  // vertex (j,hi) violates l: l is tighter
+        } else if (o > 0.0) {  // vertex (j,hi) violates l: l is tighter
           hi = l;
-          chi = make_cross(dj, dl);
+          chi = cross(dj, dl);
+          ehi = ebj * nl;
         }
       }
     } else {
       if (lo < 0) {
         lo = l;
-        clo = make_cross(dj, dl);
+        clo = cross(dj, dl);
+        elo = ebj * nl;
       } else {
-        Pred o = det_cached(clo, dl);  // det(d_j, d_lo, d_l)
-        if (fabs(o.v) <= o.err) {
+        const double o = dot(dl, clo);  // det(d_j, d_lo, d_l)
+        if (fabs(o) <= elo * nl) {
           degenerate = true;
-        } else if (o.v < 0.0) {
+        } else if (o < 0.0) {
           lo = l;
-          clo = make_cross(dj, dl);
+          clo = cross(dj, dl);
+          elo = ebj * nl;
         }
       }
     }
   }
   if (degenerate) return EdgeRes{kEdgeDegenerate, lo, hi};
   if (lo < 0 || hi < 0) return EdgeRes{kEdgeUnbounded, lo, hi};
-  Pred o = det_cached(clo, S.d(hi));  // det(d_j, d_lo, d_hi) > 0  <=>  lo < hi
-  if (fabs(o.v) <= o.err) return EdgeRes{kEdgeDegenerate, lo, hi};
-  return EdgeRes{o.v > 0.0 ? kEdgeYes : kEdgeNone, lo, hi};
+  const double o = dot(S.d(hi), clo);  // det(d_j, d_lo, d_hi) > 0  <=>  lo < hi
+  if (fabs(o) <= elo * S.nrm[hi]) return EdgeRes{kEdgeDegenerate, lo, hi};
+  return EdgeRes{o > 0.0 ? kEdgeYes : kEdgeNone, lo, hi};
 }
 
 // ------------------------------------------------------------- densities

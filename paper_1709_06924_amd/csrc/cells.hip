@@ -60,7 +60,7 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nblocks) {
 // --------------------------------------------------------------- LDS layout
 struct WaveLds {
   double px[kMaxCand], py[kMaxCand], pz[kMaxCand];
-  double dx[kMaxCand], dy[kMaxCand], dz[kMaxCand];
+  double dx[kMaxCand], dy[kMaxCand], dz[kMaxCand], nrm[kMaxCand];
   int32_t idx[kMaxCand];
   int32_t rowoff[kWinMax + 1];
   int32_t rowstart[kWinMax];
@@ -134,6 +134,7 @@ __device__ int gather(const CellArgs& a, WaveLds& L, const Window& w, int64_t i,
       L.dx[slot] = d.x;
       L.dy[slot] = d.y;
       L.dz[slot] = d.z;
+      L.nrm[slot] = sqrt(dot(d, d));
       L.idx[slot] = en.idx;
     }
     kept += __popcll(m);
@@ -142,7 +143,7 @@ __device__ int gather(const CellArgs& a, WaveLds& L, const Window& w, int64_t i,
   return kept;
 }
 
-__global__ __launch_bounds__(256) void k_cells_geom(CellArgs a) {
+__global__ __launch_bounds__(256, 4) void k_cells_geom(CellArgs a) {
   __shared__ WaveLds lds[4];
   const int ln = lane_id(), wv = threadIdx.x >> 6;
   WaveLds& L = lds[wv];
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(256) void k_cells_geom(CellArgs a) {
   const int64_t i = a.grid.order[pos];
   const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
   const int f = home_face(z);
-  const CandView S = {L.px, L.py, L.pz, L.dx, L.dy, L.dz};
+  const CandView S = {L.px, L.py, L.pz, L.dx, L.dy, L.dz, L.nrm};
 
   double Rg = a.out.R[i];
   double rt = Rg > 0.0 ? 2.3 * Rg : a.r_default;
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
 // depend on scheduling.  MIXED: FP32 points in the generator's local frame
 // (quad_tri_mixed), FP64 sub-triangle vertices, accumulation and epilogue.
 template <int KIND, bool MIXED>
-__global__ __launch_bounds__(256) void k_quad(CellArgs a) {
+__global__ __launch_bounds__(256, 5) void k_quad(CellArgs a) {
   const int ln = lane_id();
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= a.n) return;

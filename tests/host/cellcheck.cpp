@@ -21,7 +21,7 @@ extern "C" {
 // nbr[i*32+k] sorted ascending, verts[(i*32+k)*6 + 0..5] edge endpoints.
 int hc_cells(int64_t n, const double* Z, const double* rad, int32_t* status, int32_t* deg,
              int32_t* nbr, double* verts, double* Rout) {
-  std::vector<double> px(64), py(64), pz(64), dx(64), dy(64), dz(64);
+  std::vector<double> px(64), py(64), pz(64), dx(64), dy(64), dz(64), nr(64);
   std::vector<int> idx(64);
   for (int64_t i = 0; i < n; i++) {
     V3 z = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
@@ -38,6 +38,7 @@ int hc_cells(int64_t n, const double* Z, const double* rad, int32_t* status, int
         }
         px[ns] = p.x; py[ns] = p.y; pz[ns] = p.z;
         dx[ns] = d.x; dy[ns] = d.y; dz[ns] = d.z;
+        nr[ns] = sqrt(dot(d, d));
         idx[ns] = (int)j;
         ns++;
       }
@@ -48,7 +49,7 @@ int hc_cells(int64_t n, const double* Z, const double* rad, int32_t* status, int
       status[i] = 4;
       continue;
     }
-    CandView S = {px.data(), py.data(), pz.data(), dx.data(), dy.data(), dz.data()};
+    CandView S = {px.data(), py.data(), pz.data(), dx.data(), dy.data(), dz.data(), nr.data()};
     std::vector<EdgeRes> er(ns);
     int st = 0;
     for (int l = 0; l < ns; l++) {
