@@ -88,7 +88,7 @@ typedef struct {
 } scvt_density;
 
 typedef struct {
-  int64_t n;            /* number of generators (>= 4) */
+  int64_t n;            /* number of generators (4 .. 2^28) */
   int32_t m_hist;       /* M, stored LBFGS pairs (0 = Lloyd iteration) */
   int32_t precision;    /* scvt_precision */
   scvt_density rho;

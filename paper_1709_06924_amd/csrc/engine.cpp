@@ -162,7 +162,7 @@ DensityP to_dev(const scvt_density& d) {
 }
 
 int validate(const scvt_config* c) {
-  if (!c || c->n < 4 || c->n > (int64_t)1 << 30) return SCVT_E_INVALID;
+  if (!c || c->n < 4 || c->n > (int64_t)1 << 28) return SCVT_E_INVALID;  // 3n < 2^31
   if (c->m_hist < 0 || c->m_hist > 60) return SCVT_E_INVALID;
   if (c->precision != SCVT_FP64 && c->precision != SCVT_MIXED) return SCVT_E_INVALID;
   if (c->quad_levels < 0 || c->quad_levels > 3) return SCVT_E_INVALID;

@@ -72,40 +72,19 @@ __device__ inline bool last_block(unsigned* ticket) {
 }
 
 // ------------------------------------------------------------- two-loop pass
-// One thread per generator (its three coordinates and its h), 32-bit
-// indices; each thread walks generators with a grid stride.
+// Flat, contiguous elements with 32-bit indices (3n < 2^31): element k
+// belongs to generator k/3, a multiply-high with a 32-bit divisor.
 __global__ __launch_bounds__(kRedBlock) void k_lbfgs_pass(PassArgs a) {
   __shared__ double sh[kRedBlock];
   double part = 0.0;
   const double axc = a.ax_vec ? a.ax_sign * (*a.ax_coef) : 0.0;
-  const int n = (int)(a.n3 / 3);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int b = 3 * i;
-    double q0, q1, q2;
-    if (a.init_neg_g) {
-      q0 = -a.g[b];
-      q1 = -a.g[b + 1];
-      q2 = -a.g[b + 2];
-    } else {
-      q0 = a.q[b];
-      q1 = a.q[b + 1];
-      q2 = a.q[b + 2];
-    }
-    if (a.ax_vec) {
-      q0 += axc * a.ax_vec[b];
-      q1 += axc * a.ax_vec[b + 1];
-      q2 += axc * a.ax_vec[b + 2];
-    }
-    if (a.scale_h) {
-      const double hi = a.h[i];
-      q0 *= hi;
-      q1 *= hi;
-      q2 *= hi;
-    }
-    a.q[b] = q0;
-    a.q[b + 1] = q1;
-    a.q[b + 2] = q2;
-    part += a.dot_vec[b] * q0 + a.dot_vec[b + 1] * q1 + a.dot_vec[b + 2] * q2;
+  const int n3 = (int)a.n3;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
+    double qk = a.init_neg_g ? -a.g[k] : a.q[k];
+    if (a.ax_vec) qk += axc * a.ax_vec[k];
+    if (a.scale_h) qk *= a.h[(unsigned)k / 3u];
+    a.q[k] = qk;
+    part += a.dot_vec[k] * qk;
   }
   double bs = block_sum(part, sh);
   if (threadIdx.x == 0) a.partials[blockIdx.x] = bs;
@@ -217,7 +196,7 @@ static unsigned grid_for(int64_t count) {
 }
 
 hipError_t launch_lbfgs_pass(const PassArgs& a, hipStream_t s) {
-  k_lbfgs_pass<<<grid_for(a.n3 / 3), kRedBlock, 0, s>>>(a);
+  k_lbfgs_pass<<<grid_for(a.n3), kRedBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_push(const PushArgs& a, hipStream_t s) {
