@@ -49,7 +49,6 @@ struct scvt_handle {
   double *S = nullptr, *Y = nullptr;  // (M+1) slots of 3n
   double* dscal = nullptr;            // device scalars
   double* partials = nullptr;
-  unsigned* tickets = nullptr;
   int32_t* fb_list = nullptr;
   Counters* ctr = nullptr;
   double* pinned = nullptr;  // host-pinned mirror of scalars
@@ -78,6 +77,8 @@ namespace {
 
 // device scalar layout (doubles)
 enum : int { kA = 0, kCoef = 64, kR = 128, kGQ = 200, kPush = 201, kEval = 204, kNScal = 256 };
+// partial-sum buffers, in units of reduce_grid_max() doubles
+enum : int { kPartPass = 0, kPartPush = 2, kPartEval = 5, kPartTotal = 9 };
 
 int hip_err(hipError_t e) { return e == hipSuccess ? SCVT_OK : SCVT_E_HIP; }
 #define HIPCK(x)                          \
@@ -237,10 +238,18 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   r.g = s.g;
   r.mu = s.mu;
   r.Z = Zsrc;
-  r.out = h->dscal + kEval;
-  r.partials = h->partials;
-  r.ticket = h->tickets + 1;
+  r.partials = h->partials + kPartEval * reduce_grid_max();
   HIPCK(launch_eval_reduce(r, st));
+  FinalizeArgs fa{};
+  fa.partials = r.partials;
+  fa.nblocks = reduce_grid(h->n);
+  fa.nvals = 4;
+  fa.op[0] = 0;
+  fa.op[1] = 1;
+  fa.op[2] = 0;
+  fa.op[3] = 2;
+  fa.out = h->dscal + kEval;
+  HIPCK(launch_finalize(fa, st));
   if (tm) HIPCK(hipEventRecord(h->ev[4], st));
   HIPCK(hipMemcpyAsync(h->pinned, h->dscal + kEval, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCK(hipMemcpyAsync(h->pinned + 8, h->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -284,7 +293,9 @@ void adopt_trial_scalars(scvt_handle* h) {
   h->n_deg = h->tdeg;
 }
 
-// P-LBFGS direction into h->q; g . q into *gq (one host sync)
+// P-LBFGS direction into h->q; g . q into *gq (one host sync).  Each pass
+// finishes the previous pass's dot product from its block partials (no
+// separate reduction launch), see lbfgs.hip.
 int direction(scvt_handle* h, double* gq) {
   hipStream_t st = h->stream;
   const int64_t n3 = 3 * h->n;
@@ -293,69 +304,71 @@ int direction(scvt_handle* h, double* gq) {
   auto S = [&](int j) { return h->S + (size_t)h->ring[j] * n3; };
   auto Y = [&](int j) { return h->Y + (size_t)h->ring[j] * n3; };
   auto R = [&](int j) { return D + kR + h->ring[j]; };
+  double* pb[2] = {h->partials, h->partials + reduce_grid_max()};
+  int cur = 0;
   if (h->timing) HIPCK(hipEventRecord(h->ev[5], st));
-  PassArgs p{};
-  p.n3 = n3;
-  p.q = h->q;
-  p.g = h->cur.g;
-  p.h = h->cur.h;
-  p.partials = h->partials;
-  p.ticket = h->tickets;
+  PassArgs base{};
+  base.n3 = n3;
+  base.q = h->q;
+  base.g = h->cur.g;
+  base.h = h->cur.h;
+  auto run = [&](PassArgs p) -> hipError_t {
+    p.partials = pb[1 - cur];
+    hipError_t e = launch_lbfgs_pass(p, st);
+    cur = 1 - cur;
+    return e;
+  };
   if (c == 0) {
+    PassArgs p = base;
     p.init_neg_g = 1;
     p.scale_h = 1;
     p.dot_vec = h->cur.g;
-    p.out = D + kGQ;
-    HIPCK(launch_lbfgs_pass(p, st));
+    HIPCK(run(p));
   } else {
-    // backward loop, newest to oldest
-    PassArgs b = p;
+    // backward loop, newest to oldest: a_j = r_j s_j.q ; q -= a_j y_j
+    PassArgs b = base;
     b.init_neg_g = 1;
     b.dot_vec = S(c - 1);
-    b.mul = R(c - 1);
-    b.out = D + kA + (c - 1);
-    HIPCK(launch_lbfgs_pass(b, st));
+    HIPCK(run(b));
     for (int j = c - 2; j >= 0; j--) {
-      PassArgs m = p;
+      PassArgs m = base;
+      m.prev_partials = pb[cur];
+      m.prev_mul = R(j + 1);
+      m.prev_store = D + kA + (j + 1);
       m.ax_vec = Y(j + 1);
-      m.ax_coef = D + kA + (j + 1);
       m.ax_sign = -1.0;
       m.dot_vec = S(j);
-      m.mul = R(j);
-      m.out = D + kA + j;
-      HIPCK(launch_lbfgs_pass(m, st));
+      HIPCK(run(m));
     }
-    // turn-around: finish the backward loop, apply diag(h), first forward dot
-    PassArgs t = p;
+    // turn-around: finish a_0, q -= a_0 y_0, apply diag(h), dot y_0.q
+    PassArgs t = base;
+    t.prev_partials = pb[cur];
+    t.prev_mul = R(0);
+    t.prev_store = D + kA;
     t.ax_vec = Y(0);
-    t.ax_coef = D + kA;
     t.ax_sign = -1.0;
     t.scale_h = 1;
     t.dot_vec = Y(0);
-    t.mul = R(0);
-    t.sub_from = D + kA;
-    t.out = D + kCoef;
-    HIPCK(launch_lbfgs_pass(t, st));
-    // forward loop, oldest to newest: coef_j = a_j - r_j y_j.q
-    for (int j = 1; j < c; j++) {
-      PassArgs f = p;
+    HIPCK(run(t));
+    // forward loop, oldest to newest: coef_j = a_j - r_j y_j.q ; q += coef_j s_j
+    for (int j = 1; j <= c; j++) {
+      PassArgs f = base;
+      f.prev_partials = pb[cur];
+      f.prev_mul = R(j - 1);
+      f.prev_sub = D + kA + (j - 1);
+      f.prev_store = D + kCoef + (j - 1);
       f.ax_vec = S(j - 1);
-      f.ax_coef = D + kCoef + (j - 1);
       f.ax_sign = 1.0;
-      f.dot_vec = Y(j);
-      f.mul = R(j);
-      f.sub_from = D + kA + j;
-      f.out = D + kCoef + j;
-      HIPCK(launch_lbfgs_pass(f, st));
+      f.dot_vec = j < c ? Y(j) : h->cur.g;
+      HIPCK(run(f));
     }
-    PassArgs l = p;
-    l.ax_vec = S(c - 1);
-    l.ax_coef = D + kCoef + (c - 1);
-    l.ax_sign = 1.0;
-    l.dot_vec = h->cur.g;
-    l.out = D + kGQ;
-    HIPCK(launch_lbfgs_pass(l, st));
   }
+  FinalizeArgs fa{};
+  fa.partials = pb[cur];
+  fa.nblocks = reduce_grid(n3);
+  fa.nvals = 1;
+  fa.out = D + kGQ;
+  HIPCK(launch_finalize(fa, st));
   if (h->timing) HIPCK(hipEventRecord(h->ev[6], st));
   HIPCK(hipMemcpyAsync(h->pinned + 4, D + kGQ, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
@@ -396,11 +409,15 @@ int push_pair(scvt_handle* h) {
   p.gt = h->trial.g;
   p.s = h->S + (size_t)slot * n3;
   p.y = h->Y + (size_t)slot * n3;
-  p.out = h->dscal + kPush;
-  p.r_slot = h->dscal + kR + slot;
-  p.partials = h->partials;
-  p.ticket = h->tickets + 2;
+  p.partials = h->partials + kPartPush * reduce_grid_max();
   HIPCK(launch_push(p, h->stream));
+  FinalizeArgs fa{};
+  fa.partials = p.partials;
+  fa.nblocks = reduce_grid(n3);
+  fa.nvals = 3;
+  fa.out = h->dscal + kPush;
+  fa.r_slot = h->dscal + kR + slot;
+  HIPCK(launch_finalize(fa, h->stream));
   HIPCK(hipMemcpyAsync(h->pinned + 5, h->dscal + kPush, 3 * sizeof(double), hipMemcpyDeviceToHost,
                        h->stream));
   HIPCK(hipStreamSynchronize(h->stream));
@@ -504,8 +521,7 @@ int alloc_device_state(scvt_handle* h) {
     ALLOC(h->Y, (size_t)(M + 1) * 3 * n);
   }
   ALLOC(h->dscal, kNScal);
-  ALLOC(h->partials, 4 * reduce_grid_max());
-  ALLOC(h->tickets, 8);
+  ALLOC(h->partials, kPartTotal * reduce_grid_max());
   ALLOC(h->fb_list, n);
   ALLOC(h->ctr, 1);
   ALLOC(h->grid.cnt_tot, nc + 1);
@@ -535,7 +551,6 @@ int init_device_state(scvt_handle* h) {
   HIPCK(launch_fill_i32(h->grid.cnt_tot, 0, nc + 1, st));
   HIPCK(launch_fill_i32(h->grid.cnt_home, 0, nc + 1, st));
   HIPCK(launch_fill_i32(h->grid.overflow, 0, 1, st));
-  HIPCK(launch_fill_i32((int32_t*)h->tickets, 0, 8, st));
   HIPCK(launch_fill_i32((int32_t*)h->R, 0, 2 * n, st));
   HIPCK(launch_fill_i32((int32_t*)h->dscal, 0, 2 * kNScal, st));
   HIPCK(launch_fill_i32((int32_t*)h->q, 0, 6 * n, st));

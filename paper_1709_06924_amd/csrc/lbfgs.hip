@@ -1,8 +1,9 @@
 // LBFGS two-loop recursion with the Lloyd preconditioner, history push and
-// the per-evaluation reductions, as fused streaming passes with grid
-// reductions finished by the last block to arrive (fixed summation order:
-// thread partials over a fixed grid-stride, block tree, then block partials
-// in block order -- the result is the same bits on every run).
+// the per-evaluation reductions, as fused streaming passes.  Every grid
+// reduction is taken in a fixed order: thread partials over a fixed
+// grid-stride, a block tree, then the block partials in block order, summed
+// by whoever needs the value (the next pass, or a one-block finalize
+// kernel) -- no atomics, the same bits on every run.
 //
 // Two-loop (section 2.2.2, initial inverse Hessian replaced by diag(h),
 // section 3.1) over c stored pairs (oldest j = 0):
@@ -17,7 +18,7 @@
 namespace scvt {
 
 constexpr int kRedBlock = 256;
-constexpr int kRedGrid = 2048;
+constexpr int kRedGrid = 512;
 
 __device__ inline double block_sum(double v, double* sh) {
   int t = threadIdx.x;
@@ -56,19 +57,11 @@ __device__ inline double block_min(double v, double* sh) {
   return r;
 }
 
-// last-block election: returns true in exactly one block, after every
-// block's partials are visible
-__device__ inline bool last_block(unsigned* ticket) {
-  __shared__ bool is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(ticket, 1u);
-    is_last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last;
+// fixed-order sum of nb partials (stride `stride`, offset `off`)
+__device__ inline double sum_partials(const double* p, int nb, int stride, int off, double* sh) {
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) v += p[b * stride + off];
+  return block_sum(v, sh);
 }
 
 // ------------------------------------------------------------- two-loop pass
@@ -76,8 +69,15 @@ __device__ inline bool last_block(unsigned* ticket) {
 // belongs to generator k/3, a multiply-high with a 32-bit divisor.
 __global__ __launch_bounds__(kRedBlock) void k_lbfgs_pass(PassArgs a) {
   __shared__ double sh[kRedBlock];
+  double coef = 0.0;
+  if (a.prev_partials) {
+    double sum = sum_partials(a.prev_partials, gridDim.x, 1, 0, sh);
+    double v = a.prev_sub ? (*a.prev_sub) - (*a.prev_mul) * sum : (*a.prev_mul) * sum;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.prev_store = v;
+    coef = v;
+  }
+  const double axc = a.ax_sign * coef;
   double part = 0.0;
-  const double axc = a.ax_vec ? a.ax_sign * (*a.ax_coef) : 0.0;
   const int n3 = (int)a.n3;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
     double qk = a.init_neg_g ? -a.g[k] : a.q[k];
@@ -88,20 +88,10 @@ __global__ __launch_bounds__(kRedBlock) void k_lbfgs_pass(PassArgs a) {
   }
   double bs = block_sum(part, sh);
   if (threadIdx.x == 0) a.partials[blockIdx.x] = bs;
-  if (last_block(a.ticket)) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) v += a.partials[b];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) {
-      double r = a.mul ? (*a.mul) * v : v;
-      *a.out = a.sub_from ? (*a.sub_from) - r : r;
-      *a.ticket = 0u;
-    }
-  }
 }
 
 // --------------------------------------------------------------- push pass
-// s = Zt - Z, y = gt - g into the ring slot; reduce y.s, y.y, s.s
+// s = Zt - Z, y = gt - g into the ring slot; partials of y.s, y.y, s.s
 __global__ __launch_bounds__(kRedBlock) void k_push(PushArgs a) {
   __shared__ double sh[kRedBlock];
   double ys = 0.0, yy = 0.0, ss = 0.0;
@@ -121,33 +111,15 @@ __global__ __launch_bounds__(kRedBlock) void k_push(PushArgs a) {
     a.partials[3 * blockIdx.x + 1] = b1;
     a.partials[3 * blockIdx.x + 2] = b2;
   }
-  if (last_block(a.ticket)) {
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-    for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
-      v0 += a.partials[3 * b];
-      v1 += a.partials[3 * b + 1];
-      v2 += a.partials[3 * b + 2];
-    }
-    v0 = block_sum(v0, sh);
-    v1 = block_sum(v1, sh);
-    v2 = block_sum(v2, sh);
-    if (threadIdx.x == 0) {
-      a.out[0] = v0;
-      a.out[1] = v1;
-      a.out[2] = v2;
-      *a.r_slot = 1.0 / v0;
-      *a.ticket = 0u;
-    }
-  }
 }
 
 // ------------------------------------------------------ evaluation reduce
-// F = sum e_i, max |l_ik|, sum |g_i|^2, min mu_i . z_i
+// partials of F = sum e_i, max |l_ik|, sum |g_i|^2, min mu_i . z_i
 __global__ __launch_bounds__(kRedBlock) void k_eval_reduce(EvalRedArgs a) {
   __shared__ double sh[kRedBlock];
   double F = 0.0, lmax = 0.0, gg = 0.0, mzmin = 1e300;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  const int n = (int)a.n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     F += a.e[i];
     for (int k = 0; k < 3; k++) {
       lmax = fmax(lmax, fabs(a.lloyd[3 * i + k]));
@@ -166,45 +138,44 @@ __global__ __launch_bounds__(kRedBlock) void k_eval_reduce(EvalRedArgs a) {
     a.partials[4 * blockIdx.x + 2] = b2;
     a.partials[4 * blockIdx.x + 3] = b3;
   }
-  if (last_block(a.ticket)) {
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 1e300;
-    for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
-      v0 += a.partials[4 * b];
-      v1 = fmax(v1, a.partials[4 * b + 1]);
-      v2 += a.partials[4 * b + 2];
-      v3 = fmin(v3, a.partials[4 * b + 3]);
-    }
-    v0 = block_sum(v0, sh);
-    v1 = block_max(v1, sh);
-    v2 = block_sum(v2, sh);
-    v3 = block_min(v3, sh);
-    if (threadIdx.x == 0) {
-      a.out[0] = v0;
-      a.out[1] = v1;
-      a.out[2] = v2;
-      a.out[3] = v3;
-      *a.ticket = 0u;
-    }
-  }
 }
 
-static unsigned grid_for(int64_t count) {
+__global__ __launch_bounds__(kRedBlock) void k_finalize(FinalizeArgs a) {
+  __shared__ double sh[kRedBlock];
+  for (int v = 0; v < a.nvals; v++) {
+    const int op = a.op[v];
+    double acc = op == 0 ? 0.0 : (op == 1 ? -1e300 : 1e300);
+    for (int b = threadIdx.x; b < a.nblocks; b += blockDim.x) {
+      double x = a.partials[b * a.nvals + v];
+      acc = op == 0 ? acc + x : (op == 1 ? fmax(acc, x) : fmin(acc, x));
+    }
+    acc = op == 0 ? block_sum(acc, sh) : (op == 1 ? block_max(acc, sh) : block_min(acc, sh));
+    if (threadIdx.x == 0) a.out[v] = acc;
+  }
+  if (threadIdx.x == 0 && a.r_slot) *a.r_slot = 1.0 / a.out[0];
+}
+
+int reduce_grid(int64_t count) {
   int64_t b = (count + kRedBlock - 1) / kRedBlock;
   if (b > kRedGrid) b = kRedGrid;
   if (b < 1) b = 1;
-  return (unsigned)b;
+  return (int)b;
 }
 
 hipError_t launch_lbfgs_pass(const PassArgs& a, hipStream_t s) {
-  k_lbfgs_pass<<<grid_for(a.n3), kRedBlock, 0, s>>>(a);
+  k_lbfgs_pass<<<reduce_grid(a.n3), kRedBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_push(const PushArgs& a, hipStream_t s) {
-  k_push<<<grid_for(a.n3), kRedBlock, 0, s>>>(a);
+  k_push<<<reduce_grid(a.n3), kRedBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_eval_reduce(const EvalRedArgs& a, hipStream_t s) {
-  k_eval_reduce<<<grid_for(a.n), kRedBlock, 0, s>>>(a);
+  k_eval_reduce<<<reduce_grid(a.n), kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
+  k_finalize<<<1, kRedBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 int reduce_grid_max() { return kRedGrid; }
