@@ -343,67 +343,92 @@ __global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
 }
 
 // -------------------------------------------------------------- quadrature
-// One wave per cell (index order).  Every lane integrates items lane,
-// lane+64, ... of the E * 4^levels (edge, leaf) pairs; the five sums are
-// reduced across the wave in a fixed butterfly order, so the result does not
+// One wave per pair of cells (index order): the (edge, leaf) items of both
+// cells form one list -- about 3 full rounds of 64 lanes for two hexagons
+// instead of 2 rounds at 75% for one -- and every lane adds each item into
+// the accumulator of the cell it belongs to.  The five sums of each cell are
+// reduced across the wave in a fixed butterfly order, so results do not
 // depend on scheduling.  MIXED: FP32 points in the generator's local frame
 // (quad_tri_mixed), FP64 sub-triangle vertices, accumulation and epilogue.
+template <bool MIXED>
+__device__ inline void cell_epilogue(const EvalOut& o, int64_t i, V3 z, Acc5 acc) {
+  V3 mu = V3{acc.mx, acc.my, acc.mz};
+  if (MIXED) mu = acc.m * z + mu;  // first moment from int rho (y - z)
+  double mz = dot(mu, z);
+  V3 g = 2.0 * mz * z - 2.0 * mu;
+  V3 l = normalized(mu) - z;
+  o.m[i] = acc.m;
+  o.e[i] = acc.e;
+  o.mu[3 * i] = mu.x;
+  o.mu[3 * i + 1] = mu.y;
+  o.mu[3 * i + 2] = mu.z;
+  o.g[3 * i] = g.x;
+  o.g[3 * i + 1] = g.y;
+  o.g[3 * i + 2] = g.z;
+  o.h[i] = 1.0 / (2.0 * mz);
+  o.lloyd[3 * i] = l.x;
+  o.lloyd[3 * i + 1] = l.y;
+  o.lloyd[3 * i + 2] = l.z;
+}
+
+__device__ inline Acc5 wave_sum5(Acc5 a) {
+  a.m = wave_sum(a.m);
+  a.mx = wave_sum(a.mx);
+  a.my = wave_sum(a.my);
+  a.mz = wave_sum(a.mz);
+  a.e = wave_sum(a.e);
+  return a;
+}
+
 template <int KIND, bool MIXED>
-__global__ __launch_bounds__(256, 5) void k_quad(CellArgs a) {
+__global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
   const int ln = lane_id();
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= a.n) return;
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;
+  if (i0 >= a.n) return;
+  const int64_t i1 = i0 + 1;
+  const bool has1 = i1 < a.n;
   const EvalOut& o = a.out;
-  const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
-  const int E = o.deg[i];
+  const V3 z0 = V3{a.Z[3 * i0], a.Z[3 * i0 + 1], a.Z[3 * i0 + 2]};
+  const V3 z1 = has1 ? V3{a.Z[3 * i1], a.Z[3 * i1 + 1], a.Z[3 * i1 + 2]} : z0;
   const int lv = a.levels;
   const int per = 1 << (2 * lv);
-  const int total = E * per;
-  Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
-  F3 zf{}, zc[2]{};
+  const int tot0 = o.deg[i0] * per;
+  const int total = tot0 + (has1 ? o.deg[i1] * per : 0);
+  Acc5 acc0 = {0.0, 0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
   DensityF Df{};
-  if (MIXED) {
-    zf = to_f3(z);
-    Df = density_f32(a.rho);
-    for (int k = 0; k < 2; k++)
-      zc[k] = to_f3(z - V3{a.rho.xc[k][0], a.rho.xc[k][1], a.rho.xc[k][2]});
-  }
+  if (MIXED) Df = density_f32(a.rho);
   for (int t = ln; t < total; t += 64) {
-    const int e = t >> (2 * lv), s = t & (per - 1);
+    const bool second = t >= tot0;
+    const int local = second ? t - tot0 : t;
+    const int64_t i = second ? i1 : i0;
+    const V3 z = second ? z1 : z0;
+    const int e = local >> (2 * lv), s = local & (per - 1);
     const double* ed = o.edges + (i * kVmax + e) * 6;
     V3 A = z;
     V3 B = V3{ed[0], ed[1], ed[2]};
     V3 C = V3{ed[3], ed[4], ed[5]};
     subtriangle(A, B, C, s, lv);
-    if (MIXED)
-      quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), zf, zc, Df, a.rho, acc);
-    else
-      quad_tri_k<KIND>(A, B, C, z, a.rho, acc);
+    Acc5 part = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (MIXED) {
+      F3 zc[2];
+      for (int k = 0; k < 2; k++)
+        zc[k] = to_f3(z - V3{a.rho.xc[k][0], a.rho.xc[k][1], a.rho.xc[k][2]});
+      quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), to_f3(z), zc, Df, a.rho,
+                           part);
+    } else {
+      quad_tri_k<KIND>(A, B, C, z, a.rho, part);
+    }
+    Acc5& acc = second ? acc1 : acc0;
+    acc.m += part.m;
+    acc.mx += part.mx;
+    acc.my += part.my;
+    acc.mz += part.mz;
+    acc.e += part.e;
   }
-  acc.m = wave_sum(acc.m);
-  acc.mx = wave_sum(acc.mx);
-  acc.my = wave_sum(acc.my);
-  acc.mz = wave_sum(acc.mz);
-  acc.e = wave_sum(acc.e);
-  if (ln == 0) {
-    V3 mu = V3{acc.mx, acc.my, acc.mz};
-    if (MIXED) mu = acc.m * z + mu;  // first moment from int rho (y - z)
-    double mz = dot(mu, z);
-    V3 g = 2.0 * mz * z - 2.0 * mu;
-    V3 l = normalized(mu) - z;
-    o.m[i] = acc.m;
-    o.e[i] = acc.e;
-    o.mu[3 * i] = mu.x;
-    o.mu[3 * i + 1] = mu.y;
-    o.mu[3 * i + 2] = mu.z;
-    o.g[3 * i] = g.x;
-    o.g[3 * i + 1] = g.y;
-    o.g[3 * i + 2] = g.z;
-    o.h[i] = 1.0 / (2.0 * mz);
-    o.lloyd[3 * i] = l.x;
-    o.lloyd[3 * i + 1] = l.y;
-    o.lloyd[3 * i + 2] = l.z;
-  }
+  acc0 = wave_sum5(acc0);
+  acc1 = wave_sum5(acc1);
+  if (ln == 0) cell_epilogue<MIXED>(o, i0, z0, acc0);
+  if (ln == 1 && has1) cell_epilogue<MIXED>(o, i1, z1, acc1);
 }
 
 // small problems: every cell goes through the fallback clipper
@@ -427,7 +452,7 @@ hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s) {
 }
 
 hipError_t launch_quad(const CellArgs& a, hipStream_t s) {
-  const unsigned nb = (unsigned)((a.n + 3) / 4);
+  const unsigned nb = (unsigned)((a.n + 7) / 8);  // two cells per wave, four waves per block
 #define SCVT_LAUNCH_QUAD(V)                                  \
   do {                                                       \
     if (a.mixed)                                             \
