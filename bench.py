@@ -69,7 +69,8 @@ def run_gpu(args, precision, Z0_dev, cfg, stream):
     out = {"elapsed_s": t1 - t0, "info": info, "F0": F0}
     for name, k in (("geom", scvt.KERNEL_CELLS), ("fallback", scvt.KERNEL_FALLBACK),
                     ("grid", scvt.KERNEL_GRID), ("lbfgs", scvt.KERNEL_LBFGS),
-                    ("eval", scvt.KERNEL_EVAL), ("quad", scvt.KERNEL_QUAD)):
+                    ("eval", scvt.KERNEL_EVAL), ("quad", scvt.KERNEL_QUAD),
+                    ("wide", scvt.KERNEL_CELLS_WIDE)):
         ms, cnt = S.kernel_time(k)
         out[name] = {"total_ms": ms, "launches": cnt}
     out["mean_degree"] = float(S.degrees().mean())
@@ -164,7 +165,7 @@ def main():
                    "evals": r["info"]["n_evals"] - 1, "F_start": r["F0"],
                    "F_end": r["info"]["F"], "step_inf_end": r["info"]["step_inf"]},
         "kernels_ms_per_eval": {k: r[k]["total_ms"] / max(r[k]["launches"], 1)
-                                for k in ("geom", "fallback", "quad", "grid", "eval")},
+                                for k in ("geom", "wide", "fallback", "quad", "grid", "eval")},
         "lbfgs_ms_per_iter": r["lbfgs"]["total_ms"] / max(r["lbfgs"]["launches"], 1),
         "roofline": {"kernel": "k_quad", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -180,7 +181,7 @@ def main():
                    "ms_per_step": 1000.0 * rr["elapsed_s"] / args.steps,
                    "dtype": "f32 quadrature points, f64 geometry/accumulation/LBFGS",
                    "kernels_ms_per_eval": {k: rr[k]["total_ms"] / max(rr[k]["launches"], 1)
-                                           for k in ("geom", "fallback", "quad", "grid", "eval")},
+                                           for k in ("geom", "wide", "fallback", "quad", "grid", "eval")},
                    "F_end": rr["info"]["F"],
                    "roofline": {"kernel": "k_quad (mixed)", "bound": "alu",
                                 "achieved": qfl / (qms * 1e-3) / 1e12,

@@ -1,17 +1,19 @@
 // Voronoi cell construction, cell quadrature and per-cell epilogue.
 //
-// k_cells_geom: one wavefront per generator z, in cube-map order
-// (neighbouring waves share cached grid data), block index remapped so that
-// each XCD's L2 sees a contiguous stretch of the sphere.
+// k_cells_geom: a group of 16 lanes per generator z (four per wavefront),
+// in cube-map order (neighbouring groups share cached grid data), block
+// index remapped so that each XCD's L2 sees a contiguous stretch of the
+// sphere.
 //   A. candidates: every generator within chord radius rc of z, read from a
-//      rectangle of grid cells whose certified radius D >= rc (at most 64);
-//   B. one lane per candidate j computes the edge of the cell on the bisector
-//      of (z, p_j) against all other candidates (edge_on_bisector);
+//      rectangle of grid cells whose certified radius D >= rc (at most 32);
+//   B. each lane takes two candidates j and computes the edge of the cell on
+//      the bisector of (z, p_j) against all other candidates
+//      (edge_on_bisector);
 //   C. certificate: the cell's circumradius R obeys 2R <= rc, so no
 //      generator outside the candidate set can cut the cell (a point p can
 //      only cut if |p - z| < 2R); otherwise the radius grows and A-C repeat.
 //   The edges (vertex pairs, ordered by neighbour index) go to the cell's
-//   slot in HBM.  Cells that cannot be certified with 64 candidates, or meet
+//   slot in HBM.  Cells that cannot be certified with 32 candidates, or meet
 //   a predicate within its error bound, go to a list for
 // k_fallback: a sequential half-space clipper run by lane 0 (no size limit:
 //   any cell the sphere allows), writing the same slot.
@@ -57,15 +59,6 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nblocks) {
   return start + k;
 }
 
-// --------------------------------------------------------------- LDS layout
-struct WaveLds {
-  double px[kMaxCand], py[kMaxCand], pz[kMaxCand];
-  double dx[kMaxCand], dy[kMaxCand], dz[kMaxCand], nrm[kMaxCand];
-  int32_t idx[kMaxCand];
-  int32_t rowoff[kWinMax + 1];
-  int32_t rowstart[kWinMax];
-};
-
 // ------------------------------------------------------------- edge slots
 // Edge k of cell i (ordered by neighbour index): vertices v0 -> v1,
 // counter-clockwise seen from outside, at edges[(i * kVmax + k) * 6 ...].
@@ -82,52 +75,104 @@ __device__ inline void store_edge(const EvalOut& o, int64_t i, int k, V3 v0, V3 
 }
 
 // ---------------------------------------------------------- certified path
-// Gather every generator p != z with |p - z| < rc from window w into the
-// candidate arrays; returns the count (> kMaxCand means overflow).
-__device__ int gather(const CellArgs& a, WaveLds& L, const Window& w, int64_t i, V3 z, double rc2) {
-  const GridP& g = a.grid.g;
-  const int nrows = w.ib_hi - w.ib_lo + 1;
+// A cell is built by a group of GS lanes holding at most CAP candidates
+// (CAP / GS per lane).  Most cells have 10-20 candidates, so the main kernel
+// uses groups of 16 lanes (four cells per wave, 32 candidates); the few
+// cells that need more go to a second kernel with one whole wave and 64
+// candidates per cell, and only what that cannot certify to the fallback.
+template <int GS, int CAP>
+struct CandLds {
+  double px[CAP], py[CAP], pz[CAP], dx[CAP], dy[CAP], dz[CAP], nrm[CAP];
+  int32_t idx[CAP];
+  int32_t rowoff[kWinMax + 1];
+  int32_t rowstart[kWinMax];
+};
+
+template <int GS>
+__device__ inline double group_max(double v) {
+  for (int off = GS / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+template <int GS>
+__device__ inline int group_scan_incl(int v, int gl) {
+  for (int off = 1; off < GS; off <<= 1) {
+    int t = __shfl_up(v, off, GS);
+    if (gl >= off) v += t;
+  }
+  return v;
+}
+
+// Lanes of one group: gl = lane within the group, gid = group within the
+// wave, gm = the group's lanes as a wave mask.
+struct GroupPos {
+  int gl, gid;
+  uint64_t gm;
+};
+template <int GS>
+__device__ inline GroupPos group_pos() {
   const int ln = lane_id();
+  GroupPos g;
+  g.gl = ln & (GS - 1);
+  g.gid = ln / GS;
+  g.gm = GS == 64 ? ~0ull : (((1ull << GS) - 1) << (GS * g.gid));
+  return g;
+}
+
+// Gather every generator p != z with |p - z| < rc from window w into the
+// group's candidate arrays; returns the count (> CAP means overflow).  All
+// lanes of the wave take part; groups with active == false gather nothing.
+template <int GS, int CAP>
+__device__ int gather(const CellArgs& a, CandLds<GS, CAP>& L, const Window& w, int64_t i, V3 z,
+                      double rc2, bool active, const GroupPos& G) {
+  const GridP& g = a.grid.g;
+  const int nrows = active ? w.ib_hi - w.ib_lo + 1 : 0;
   wave_sync();  // earlier reads of the candidate arrays are done
-  int cnt = 0, st = 0;
-  if (ln < nrows) {
-    int64_t c0 = cell_of(g, w.f, w.ia_lo, w.ib_lo + ln);
-    int64_t c1 = cell_of(g, w.f, w.ia_hi, w.ib_lo + ln) + 1;
-    st = a.grid.start_tot[c0];
-    cnt = a.grid.start_tot[c1] - st;
+  int base = 0;
+  for (int r0 = 0;; r0 += GS) {
+    if (!__ballot(r0 < nrows)) break;
+    const int r = r0 + G.gl;
+    const bool in = r < nrows;
+    int cnt = 0, st = 0;
+    if (in) {
+      int64_t c0 = cell_of(g, w.f, w.ia_lo, w.ib_lo + r);
+      int64_t c1 = cell_of(g, w.f, w.ia_hi, w.ib_lo + r) + 1;
+      st = a.grid.start_tot[c0];
+      cnt = a.grid.start_tot[c1] - st;
+    }
+    const int incl = group_scan_incl<GS>(cnt, G.gl);
+    if (in) {
+      L.rowoff[r] = base + incl - cnt;
+      L.rowstart[r] = st;
+    }
+    base += __shfl(incl, G.gid * GS + GS - 1, 64);
   }
-  // inclusive scan of the row counts across lanes
-  int incl = cnt;
-  for (int off = 1; off < 64; off <<= 1) {
-    int v = __shfl_up(incl, off, 64);
-    if (ln >= off) incl += v;
-  }
-  if (ln < nrows) {
-    L.rowoff[ln] = incl - cnt;
-    L.rowstart[ln] = st;
-  }
-  const int T = __shfl(incl, 63, 64);
+  const int T = base;
   wave_sync();
   int kept = 0;
-  for (int t0 = 0; t0 < T; t0 += 64) {
-    int t = t0 + ln;
+  for (int t0 = 0;; t0 += GS) {
+    if (!__ballot(t0 < T)) break;
+    const int t = t0 + G.gl;
     bool keep = false;
     Entry en;
     V3 d;
     if (t < T) {
-      int r = 0;
-      while (r + 1 < nrows && L.rowoff[r + 1] <= t) r++;
-      en = a.grid.entries[L.rowstart[r] + (t - L.rowoff[r])];
+      int lo = 0, hi = nrows - 1;  // the last row whose offset is <= t
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.rowoff[mid] <= t) lo = mid;
+        else hi = mid - 1;
+      }
+      en = a.grid.entries[L.rowstart[lo] + (t - L.rowoff[lo])];
       d = V3{en.x - z.x, en.y - z.y, en.z - z.z};
       keep = en.idx != (int32_t)i && dot(d, d) < rc2;
       if (en.idx != (int32_t)i && d.x == 0.0 && d.y == 0.0 && d.z == 0.0) {
-        atomicAdd(&a.ctr->pad[0], 1);  // duplicate generator
+        atomicAdd(&a.ctr->n_duplicate, 1);
         keep = false;
       }
     }
-    uint64_t m = __ballot(keep);
-    int slot = kept + mbcnt(m);
-    if (keep && slot < kMaxCand) {
+    const uint64_t m = __ballot(keep) & G.gm;
+    const int slot = kept + mbcnt(m);
+    if (keep && slot < CAP) {
       L.px[slot] = en.x;
       L.py[slot] = en.y;
       L.pz[slot] = en.z;
@@ -143,89 +188,172 @@ __device__ int gather(const CellArgs& a, WaveLds& L, const Window& w, int64_t i,
   return kept;
 }
 
-__global__ __launch_bounds__(256, 4) void k_cells_geom(CellArgs a) {
-  __shared__ WaveLds lds[4];
-  const int ln = lane_id(), wv = threadIdx.x >> 6;
-  WaveLds& L = lds[wv];
-  const int64_t pos = xcd_block(blockIdx.x, gridDim.x) * 4 + wv;
-  if (pos >= a.n) return;
-  const int64_t i = a.grid.order[pos];
-  const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
+enum CellOutcome { kCellOk = 0, kCellDegenerate = 1, kCellOpen = 2 };
+
+// Build and certify cell i (all lanes of the wave call this together; a
+// group with valid == false only keeps step).  Search radius: grow to
+// min(2.1 R, 1.6 r) after an uncertified attempt and to 1.6 r after an
+// unbounded one; on overflow shrink toward 3/4 CAP candidates, unless that
+// is no larger than a radius already found too small (the cell needs more
+// than CAP candidates).  Writes the edges, deg, R and flags of a certified
+// cell and returns the outcome.
+template <int GS, int CAP>
+__device__ int build_cell(const CellArgs& a, CandLds<GS, CAP>& L, bool valid, int64_t i,
+                          const GroupPos& G) {
+  constexpr int PER = CAP / GS;
+  static_assert(PER * GS == CAP && PER >= 1 && PER <= 2, "one or two candidates per lane");
+  const V3 z = valid ? V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]} : V3{0.0, 0.0, 1.0};
   const int f = home_face(z);
   const CandView S = {L.px, L.py, L.pz, L.dx, L.dy, L.dz, L.nrm};
-
-  double Rg = a.out.R[i];
+  const double Rg = valid ? a.out.R[i] : 0.0;
   double rt = Rg > 0.0 ? 2.3 * Rg : a.r_default;
-  bool ok = false, degen = false;
-  int E = 0;
+  double r_small = 0.0;  // largest radius found too small
+  bool active = valid;
+  int outcome = kCellOpen, E = 0;
   double R = 0.0;
-  for (int attempt = 0; attempt < 8 && !ok && !degen; attempt++) {
-    Window w = make_window(a.grid.g, z, f, rt, kWinMax);
-    double rc = rt < w.D ? rt : w.D;
-    int ns = gather(a, L, w, i, z, rc * rc);
-    if (ns > kMaxCand) {  // too many: shrink the radius toward ~48 candidates
-      rt = rc * sqrt(48.0 / (double)ns);
-      continue;
+  for (int attempt = 0; attempt < 8; attempt++) {
+    if (!__ballot(active)) break;
+    const Window w = make_window(a.grid.g, z, f, rt, kWinMax);
+    const double rc = rt < w.D ? rt : w.D;
+    const int ns = gather<GS, CAP>(a, L, w, i, z, rc * rc, active, G);
+    bool go = active;
+    if (go && ns > CAP) {
+      rt = rc * sqrt(0.75 * CAP / (double)ns);
+      if (rt <= r_small) active = false;
+      go = false;
     }
-    EdgeRes er = EdgeRes{kEdgeNone, -1, -1};
-    if (ln < ns) er = edge_on_bisector(ln, ns, z, S);
-    if (__ballot(er.status == kEdgeDegenerate)) {
-      degen = true;
-      break;
+    EdgeRes er[PER];
+    bool anydeg = false, anyunb = false;
+    for (int k = 0; k < PER; k++) {
+      const int j = G.gl + k * GS;
+      er[k] = EdgeRes{kEdgeNone, -1, -1};
+      if (go && j < ns) er[k] = edge_on_bisector(j, ns, z, S);
+      anydeg |= er[k].status == kEdgeDegenerate;
+      anyunb |= er[k].status == kEdgeUnbounded;
     }
-    if (__ballot(er.status == kEdgeUnbounded) || ns < 3) {
-      if (rc < rt) break;  // the window cannot grow: fallback
+    if (go && (__ballot(anydeg) & G.gm)) {
+      outcome = kCellDegenerate;
+      active = false;
+      go = false;
+    }
+    if (go && ((__ballot(anyunb) & G.gm) || ns < 3)) {
+      if (rc < rt) active = false;  // the window cannot grow
+      r_small = fmax(r_small, rc);
       rt = 1.6 * rc;
-      continue;
+      go = false;
     }
-    const bool has = er.status == kEdgeYes;
-    const uint64_t emask = __ballot(has);
-    E = __popcll(emask);
-    V3 vlo = V3{0, 0, 0}, vhi = V3{0, 0, 0};
+    uint64_t em[PER];
+    V3 vlo[PER], vhi[PER];
     double r2 = 0.0;
-    if (has) {
-      int ij = L.idx[ln];
-      V3 pj = S.p(ln);
-      vlo = circumcentre((int)i, z, ij, pj, L.idx[er.lo], S.p(er.lo));
-      vhi = circumcentre((int)i, z, ij, pj, L.idx[er.hi], S.p(er.hi));
-      V3 a1 = vlo - z, a2 = vhi - z;
-      r2 = fmax(dot(a1, a1), dot(a2, a2));
-    }
-    r2 = wave_max(r2);
-    R = sqrt(r2);
-    if (4.0 * r2 * (1.0 + 1e-12) <= rc * rc && E >= 3 && E <= kVmax) {
-      ok = true;
-      // rank edges by neighbour index (deterministic summation order)
+    int En = 0;
+    for (int k = 0; k < PER; k++) {
+      const int j = G.gl + k * GS;
+      const bool has = go && er[k].status == kEdgeYes;
+      em[k] = __ballot(has) & G.gm;
+      En += __popcll(em[k]);
+      vlo[k] = vhi[k] = V3{0.0, 0.0, 0.0};
       if (has) {
-        int me = L.idx[ln], rank = 0;
-        uint64_t mm = emask;
-        while (mm) {
-          int k = __builtin_ctzll(mm);
-          mm &= mm - 1;
-          rank += L.idx[k] < me ? 1 : 0;
-        }
-        store_edge(a.out, i, rank, vlo, vhi, me, a.keep_cells);
+        vlo[k] = circumcentre((int)i, z, L.idx[j], S.p(j), L.idx[er[k].lo], S.p(er[k].lo));
+        vhi[k] = circumcentre((int)i, z, L.idx[j], S.p(j), L.idx[er[k].hi], S.p(er[k].hi));
+        const V3 q0 = vlo[k] - z, q1 = vhi[k] - z;
+        r2 = fmax(r2, fmax(dot(q0, q0), dot(q1, q1)));
       }
-    } else {
-      if (rc < rt && 2.0 * R >= w.D) break;  // window-limited: fallback
-      // R of an incomplete candidate set overestimates the cell: grow by at
-      // most 1.6x per attempt (about 2.5x the candidates)
-      rt = fmin(2.1 * R, 1.6 * rt);
+    }
+    r2 = group_max<GS>(r2);
+    bool store = false;
+    if (go) {
+      R = sqrt(r2);
+      if (4.0 * r2 * (1.0 + 1e-12) <= rc * rc && En >= 3 && En <= kVmax) {
+        outcome = kCellOk;
+        active = false;
+        E = En;
+        store = true;
+      } else if (rc < rt && 2.0 * R >= w.D) {
+        active = false;  // window-limited
+      } else {
+        // R of an incomplete candidate set overestimates the cell: grow by
+        // at most 1.6x per attempt (about 2.5x the candidates)
+        r_small = fmax(r_small, rc);
+        rt = fmin(2.1 * R, 1.6 * rt);
+      }
+    }
+    if (store) {
+      // rank edges by neighbour index (deterministic summation order)
+      for (int k = 0; k < PER; k++) {
+        const int j = G.gl + k * GS;
+        if (!(er[k].status == kEdgeYes)) continue;
+        const int me = L.idx[j];
+        int rank = 0;
+        for (int kk = 0; kk < PER; kk++) {
+          uint64_t mm = em[kk] >> (GS == 64 ? 0 : GS * G.gid);
+          while (mm) {
+            const int t = __builtin_ctzll(mm);
+            mm &= mm - 1;
+            rank += L.idx[t + kk * GS] < me ? 1 : 0;
+          }
+        }
+        store_edge(a.out, i, rank, vlo[k], vhi[k], me, a.keep_cells);
+      }
     }
   }
-  if (ln == 0) {
-    if (!ok) {
-      int k = atomicAdd(&a.ctr->fb_count, 1);
-      a.fb_list[k] = (int32_t)i;
-      if (degen) atomicAdd(&a.ctr->n_degenerate, 1);
-      a.out.deg[i] = 0;
-    } else {
+  if (valid && outcome == kCellOk) {
+    if (G.gl == 0) {
       a.out.deg[i] = E;
       a.out.R[i] = R;
       a.out.flags[i] = 0;
     }
+    if (a.keep_cells)
+      for (int k = G.gl; k < kVmax; k += GS)
+        if (k >= E) a.out.cell_nbr[i * kVmax + k] = -1;
   }
-  if (ok && a.keep_cells && ln >= E && ln < kVmax) a.out.cell_nbr[i * kVmax + ln] = -1;
+  return outcome;
+}
+
+__device__ inline void to_list(int32_t* list, int32_t* count, int64_t i) {
+  const int k = atomicAdd(count, 1);
+  list[k] = (int32_t)i;
+}
+
+// Main certified pass: four cells per wave in cube-map order.  Cells that
+// need more than 32 candidates go to the wide list, degenerate ones to the
+// fallback list.
+__global__ __launch_bounds__(256, 4) void k_cells_geom(CellArgs a) {
+  constexpr int GS = 16;
+  __shared__ CandLds<GS, 32> lds[16];
+  const GroupPos G = group_pos<GS>();
+  const int wv = threadIdx.x >> 6;
+  const int64_t pos = (xcd_block(blockIdx.x, gridDim.x) * 4 + wv) * 4 + G.gid;
+  const bool valid = pos < a.n;
+  if (!__ballot(valid)) return;
+  const int64_t i = valid ? a.grid.order[pos] : 0;
+  const int oc = build_cell<GS, 32>(a, lds[wv * 4 + G.gid], valid, i, G);
+  if (valid && G.gl == 0 && oc != kCellOk) {
+    a.out.deg[i] = 0;
+    if (oc == kCellDegenerate) {
+      atomicAdd(&a.ctr->n_degenerate, 1);
+      to_list(a.fb_list, &a.ctr->fb_count, i);
+    } else {
+      to_list(a.wide_list, &a.ctr->wide_count, i);
+    }
+  }
+}
+
+// Second certified pass over the wide list: one wave and up to 64
+// candidates per cell; what stays open goes to the fallback list.
+__global__ __launch_bounds__(256, 2) void k_cells_wide(CellArgs a) {
+  __shared__ CandLds<64, 64> lds[4];
+  const GroupPos G = group_pos<64>();
+  const int wv = threadIdx.x >> 6;
+  const int count = a.ctr->wide_count;
+  for (int w = blockIdx.x * 4 + wv; w < count; w += gridDim.x * 4) {
+    const int64_t i = a.wide_list[w];
+    const int oc = build_cell<64, 64>(a, lds[wv], true, i, G);
+    if (G.gl == 0 && oc != kCellOk) {
+      a.out.deg[i] = 0;
+      if (oc == kCellDegenerate) atomicAdd(&a.ctr->n_degenerate, 1);
+      to_list(a.fb_list, &a.ctr->fb_count, i);
+    }
+  }
 }
 
 // ------------------------------------------------------------ fallback path
@@ -299,7 +427,7 @@ __global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
           const int32_t st = a.grid.start_tot[c0], en = a.grid.start_tot[c1];
           const Entry* E = a.grid.entries;
           fb_offer(F, a.Z, z, i, en - st, [&](int64_t t) { return (int)E[st + t].idx; },
-                   &a.ctr->pad[0]);
+                   &a.ctr->n_duplicate);
         }
         wave_sync();
         if (F.poly.K[F.poly.cur] > 0 && 2.0 * F.poly.R * (1.0 + 1e-12) <= win.D) done = true;
@@ -311,7 +439,7 @@ __global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
     if (!done) {
       if (ln == 0) F.brute = 1;
       wave_sync();
-      fb_offer(F, a.Z, z, i, a.n, [](int64_t t) { return (int)t; }, &a.ctr->pad[0]);
+      fb_offer(F, a.Z, z, i, a.n, [](int64_t t) { return (int)t; }, &a.ctr->n_duplicate);
     }
     wave_sync();
     // real vertices (where consecutive edges change circle), canonical
@@ -439,8 +567,15 @@ __global__ void k_fb_all(int32_t* fb_list, Counters* ctr, int64_t n) {
 }
 
 hipError_t launch_cells_main(const CellArgs& a, hipStream_t s) {
-  int64_t nb = (a.n + 3) / 4;
+  const int64_t nb = (a.n + 15) / 16;  // four cells per wave, four waves per block
   k_cells_geom<<<(unsigned)nb, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cells_wide(const CellArgs& a, hipStream_t s) {
+  // the list length is only known on the device: a fixed grid
+  const int64_t nw = (a.n + 63) / 64 < 512 ? (a.n + 63) / 64 : 512;
+  k_cells_wide<<<(unsigned)nw, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ struct Timer {
   int64_t launches = 0;
 };
 
-constexpr int kTimers = 6;
+constexpr int kTimers = 7;
 constexpr int kStateMagic = 0x53435654;  // "SCVT"
 
 }  // namespace
@@ -50,6 +50,7 @@ struct scvt_handle {
   double* dscal = nullptr;            // device scalars
   double* partials = nullptr;
   int32_t* fb_list = nullptr;
+  int32_t* wide_list = nullptr;
   Counters* ctr = nullptr;
   double* pinned = nullptr;  // host-pinned mirror of scalars
   std::vector<void*> allocs;
@@ -64,7 +65,7 @@ struct scvt_handle {
   int64_t tfb = 0, tdeg = 0;
   bool timing = false;
   Timer timers[kTimers];
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[9] = {};
   int main_path = 1;
   double r_default = 0;
   double* shared_edges = nullptr;
@@ -203,6 +204,7 @@ CellArgs cell_args(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   a.out.cell_nbr = s.cell_nbr;
   a.out.edges = s.edges;
   a.fb_list = h->fb_list;
+  a.wide_list = h->wide_list;
   a.ctr = h->ctr;
   a.r_default = h->r_default;
   return a;
@@ -226,6 +228,8 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   if (tm) HIPCK(hipEventRecord(h->ev[1], st));
   CellArgs a = cell_args(h, Zsrc, s);
   if (h->main_path) HIPCK(launch_cells_main(a, st));
+  if (tm) HIPCK(hipEventRecord(h->ev[8], st));
+  if (h->main_path) HIPCK(launch_cells_wide(a, st));
   if (tm) HIPCK(hipEventRecord(h->ev[2], st));
   HIPCK(launch_cells_fallback(a, h->main_path ? 0 : 1, st));
   if (tm) HIPCK(hipEventRecord(h->ev[3], st));
@@ -255,7 +259,8 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   HIPCK(hipMemcpyAsync(h->pinned + 8, h->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   if (tm) {
-    if (h->main_path) timer_add(h, 0, h->ev[1], h->ev[2]);
+    if (h->main_path) timer_add(h, 0, h->ev[1], h->ev[8]);
+    if (h->main_path) timer_add(h, 6, h->ev[8], h->ev[2]);
     timer_add(h, 1, h->ev[2], h->ev[3]);
     timer_add(h, 2, h->ev[0], h->ev[1]);
     timer_add(h, 4, h->ev[0], h->ev[4]);
@@ -269,7 +274,7 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   h->tmz = h->pinned[3];
   h->tfb = c.n_fallback;
   h->tdeg = c.n_degenerate;
-  if (c.pad[0] > 0) return SCVT_E_DEGENERATE;
+  if (c.n_duplicate > 0) return SCVT_E_DEGENERATE;
   if (c.n_error > 0) return SCVT_E_CERT;
   if (!(h->tF == h->tF) || !(h->tmz > 0.0)) return SCVT_E_NUMERIC;
   return SCVT_OK;
@@ -523,6 +528,7 @@ int alloc_device_state(scvt_handle* h) {
   ALLOC(h->dscal, kNScal);
   ALLOC(h->partials, kPartTotal * reduce_grid_max());
   ALLOC(h->fb_list, n);
+  ALLOC(h->wide_list, n);
   ALLOC(h->ctr, 1);
   ALLOC(h->grid.cnt_tot, nc + 1);
   ALLOC(h->grid.cnt_home, nc + 1);

@@ -8,7 +8,6 @@
 namespace scvt {
 
 constexpr int kVmax = 32;          // max Voronoi edges per cell kept in debug output
-constexpr int kMaxCand = 64;       // candidates per wave in the certified path
 constexpr int kWinMax = 63;        // max window side in cells
 constexpr int kFbPolyMax = 64;     // polygon capacity of the fallback clipper
 
@@ -53,7 +52,9 @@ struct GridBufs {
 struct Counters {  // device-side counters of one evaluation
   int32_t fb_count;
   int32_t n_fallback, n_degenerate, n_error, n_brute;
-  int32_t pad[3];  // pad[0]: duplicate generators seen
+  int32_t n_duplicate;  // duplicate generators seen
+  int32_t wide_count;   // cells handed to the wide certified pass
+  int32_t pad;
 };
 
 struct CellArgs {
@@ -66,7 +67,8 @@ struct CellArgs {
   int mixed;
   int pad;
   EvalOut out;
-  int32_t* fb_list;
+  int32_t* fb_list;    // n: cells for the fallback clipper
+  int32_t* wide_list;  // n: cells for the wide certified pass
   Counters* ctr;
   double r_default;  // initial search radius when no previous one is known
 };
@@ -76,6 +78,7 @@ hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha
                                   int64_t n, hipStream_t s);
 hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s);
 hipError_t launch_cells_main(const CellArgs& a, hipStream_t s);
+hipError_t launch_cells_wide(const CellArgs& a, hipStream_t s);
 hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s);
 hipError_t launch_quad(const CellArgs& a, hipStream_t s);
 hipError_t launch_centroid(const double* mu, const double* m, double* out, int64_t n,

@@ -22,6 +22,7 @@ SCVT_OK, SCVT_NOT_CONVERGED, SCVT_PENDING = 0, 1, 2
 FP64, MIXED = 0, 1
 KIND = {"const": 0, "tanh": 1, "x3": 2, "x16": 3}
 KERNEL_CELLS, KERNEL_FALLBACK, KERNEL_GRID, KERNEL_LBFGS, KERNEL_EVAL, KERNEL_QUAD = 0, 1, 2, 3, 4, 5
+KERNEL_CELLS_WIDE = 6
 VMAX = 32
 
 

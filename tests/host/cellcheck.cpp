@@ -19,23 +19,22 @@ extern "C" {
 // iteration per lane).  Outputs per cell: status (0 ok certified, 1
 // degenerate, 2 unbounded, 3 not certified, 4 too many candidates), deg,
 // nbr[i*32+k] sorted ascending, verts[(i*32+k)*6 + 0..5] edge endpoints.
+// At most `cap` candidates (<= 64) are kept; on overflow Rout[i] holds the
+// number of generators inside the radius.
 int hc_cells(int64_t n, const double* Z, const double* rad, int32_t* status, int32_t* deg,
-             int32_t* nbr, double* verts, double* Rout) {
+             int32_t* nbr, double* verts, double* Rout, int cap) {
+  if (cap < 1 || cap > 64) return -1;
   std::vector<double> px(64), py(64), pz(64), dx(64), dy(64), dz(64), nr(64);
   std::vector<int> idx(64);
   for (int64_t i = 0; i < n; i++) {
     V3 z = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
-    int ns = 0;
-    bool over = false;
+    int ns = 0, total = 0;
     for (int64_t j = 0; j < n; j++) {
       if (j == i) continue;
       V3 p = V3{Z[3 * j], Z[3 * j + 1], Z[3 * j + 2]};
       V3 d = p - z;
       if (dot(d, d) < rad[i] * rad[i]) {
-        if (ns == 64) {
-          over = true;
-          break;
-        }
+        if (total++ >= cap) continue;
         px[ns] = p.x; py[ns] = p.y; pz[ns] = p.z;
         dx[ns] = d.x; dy[ns] = d.y; dz[ns] = d.z;
         nr[ns] = sqrt(dot(d, d));
@@ -45,8 +44,9 @@ int hc_cells(int64_t n, const double* Z, const double* rad, int32_t* status, int
     }
     deg[i] = 0;
     for (int k = 0; k < 32; k++) nbr[i * 32 + k] = -1;
-    if (over) {
+    if (total > cap) {
       status[i] = 4;
+      Rout[i] = (double)total;
       continue;
     }
     CandView S = {px.data(), py.data(), pz.data(), dx.data(), dy.data(), dz.data(), nr.data()};

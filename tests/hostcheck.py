@@ -38,7 +38,7 @@ def P(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def cells(Z, rad):
+def cells(Z, rad, cap=64):
     Z = np.ascontiguousarray(Z, dtype=np.float64)
     n = len(Z)
     rad = np.ascontiguousarray(np.broadcast_to(rad, (n,)), dtype=np.float64)
@@ -47,7 +47,8 @@ def cells(Z, rad):
     nbr = np.zeros((n, 32), np.int32)
     verts = np.zeros((n, 32, 6))
     R = np.zeros(n)
-    lib().hc_cells(ctypes.c_int64(n), P(Z), P(rad), P(st), P(deg), P(nbr), P(verts), P(R))
+    lib().hc_cells(ctypes.c_int64(n), P(Z), P(rad), P(st), P(deg), P(nbr), P(verts), P(R),
+                   ctypes.c_int(cap))
     return st, deg, nbr, verts, R
 
 

@@ -59,22 +59,47 @@ def test_certified_cells_match_oracle(n, seed):
             assert np.max(np.abs(verts[k, t, 3:] - v1)) < 1e-14
 
 
+def _certify(Z, rt, cap, attempts=8):
+    """The kernels' radius policy for a group holding `cap` candidates: grow
+    to min(2.1 R, 1.6 r) after an uncertified attempt and to 1.6 r after an
+    unbounded one; on overflow shrink toward 3/4 cap candidates, giving up
+    when that is no larger than a radius already found too small."""
+    n = len(Z)
+    rt = np.array(rt, dtype=float)
+    r_small = np.zeros(n)
+    done = np.zeros(n, bool)
+    open_ = np.ones(n, bool)
+    for attempt in range(attempts):
+        st, deg, nbr, verts, R = hc.cells(Z, rt, cap=cap)
+        st = np.where(open_, st, -1)
+        done |= st == 0
+        open_ &= st != 0
+        grow_u = st == 3
+        grow_b = st == 2
+        r_small = np.where(grow_u | grow_b, np.maximum(r_small, rt), r_small)
+        shrink = rt * np.sqrt(0.75 * cap / np.maximum(R, 1.0))
+        give_up = (st == 4) & (shrink <= r_small)
+        open_ &= ~give_up
+        rt = np.where(grow_u, np.minimum(2.1 * R, 1.6 * rt), rt)
+        rt = np.where(grow_b, 1.6 * rt, rt)
+        rt = np.where(st == 4, shrink, rt)
+    return done
+
+
 def test_retry_policy_certifies_nearly_all():
-    """The kernel's retry policy (grow the radius to min(2.1 R, 1.6 r) after
-    an uncertified attempt, 1.6 r after an unbounded one, shrink toward 48
-    candidates on overflow) certifies almost every cell of random input."""
+    """The main pass (32 candidates per cell) certifies most cells of random
+    input, from a too small and from a too large first radius, and the wide
+    pass (64 candidates) nearly all of the rest."""
     n = 3000
     Z = I.uniform_sphere(n, 2)
     h = math.sqrt(4 * math.pi / n)
-    rt = np.full(n, 2.0 * h)
-    done = np.zeros(n, bool)
-    for attempt in range(8):
-        st, deg, nbr, verts, R = hc.cells(Z, rt)
-        done |= st == 0
-        rt = np.where(st == 3, np.minimum(2.1 * R, 1.6 * rt), rt)
-        rt = np.where(st == 2, 1.6 * rt, rt)
-        rt = np.where(st == 4, rt * 0.7, rt)
-    assert done.mean() > 0.998
+    for r0 in (2.0 * h, 6.0 * h):
+        done = _certify(Z, np.full(n, r0), cap=32)
+        assert done.mean() > 0.98
+        rest = np.where(~done)[0]
+        done_w = _certify(Z, np.full(n, 2.0 * h), cap=64)
+        assert done_w[rest].mean() > 0.8
+        assert (done | done_w).mean() > 0.998
 
 
 def test_certificate_is_sound():
