@@ -13,6 +13,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "exp_table.h"
+
 #define SCVT_HD __host__ __device__ inline
 
 namespace scvt {
@@ -239,16 +241,50 @@ SCVT_HD double rsq(double x) {
 #endif
 }
 
+// 1/sqrt(x) for positive, finite, normal x: the hardware estimate r and one
+// second-order correction, r (1 + e/2 + 3e^2/8) with e = 1 - x r^2 (the
+// Taylor series of (1 - e)^(-1/2)); no special-value handling.  The host
+// build divides.
+SCVT_HD double rsq_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * r, r, 1.0);
+  return fma(r * e, fma(e, 0.375, 0.5), r);
+#else
+  return 1.0 / ::sqrt(x);
+#endif
+}
+
+// exp(t) for t in [-708, 700] (callers clamp), table-driven (Tang's
+// method): t = (64 m + j) ln2/64 + r with |r| <= ln2/128, so
+// exp(t) = 2^m 2^(j/64) exp(r), and exp(r) - 1 is the degree-5 Taylor
+// polynomial (truncation error below 4e-17).  Within about one ulp.
+SCVT_HD double exp_tab(double t) {
+  const double k = rint(t * kExpInvLn);
+  double r = fma(-k, kExpLnHi, t);
+  r = fma(-k, kExpLnLo, r);
+  const int ki = (int)k;
+  const int j = ki & 63;
+  const int m = ki >> 6;  // floor(ki / 64): arithmetic shift
+  double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p *= r;  // exp(r) - 1
+  const double T = kExp2Tab[j];
+  return ldexp(fma(T, p, T), m);
+}
+
 SCVT_HD double chord_to_angle(double ch) {
   double s = 0.5 * ch;
   return 2.0 * asin(s > 1.0 ? 1.0 : s);
 }
 
-// Newton-refined reciprocal for x >= 1 (two steps from the hardware
-// estimate: a few ulp, no division sequence); the host build divides
+// Newton-refined reciprocal for 1 <= x < 2^1012 (two steps from the
+// hardware estimate: a few ulp, no division sequence); the host build
+// divides
 SCVT_HD double rcp_refined(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  if (!(x < 1e300)) return 0.0;
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
   r = fma(r, e, r);
@@ -266,8 +302,11 @@ SCVT_HD double rcp_refined(double x) {
 // distance built from the latitude/longitude-swapped points.
 // (tanh(x) + 1)/2 is evaluated as the equal 1/(1 + exp(-2x)), which does not
 // cancel where tanh is close to -1 (far from a bump, where rho ~ gamma).
+// The exponent is clamped to [-708, 700]: below, exp(t) is under 1e-307 and
+// the bump equals amp; above, the bump is below 1e-304 amp.
 SCVT_HD double bump(double amp, double beta, double k2, double d) {
-  return amp * rcp_refined(1.0 + exp((beta - d) * k2));
+  const double t = fmin(fmax((beta - d) * k2, -708.0), 700.0);
+  return amp * rcp_refined(1.0 + exp_tab(t));
 }
 
 // Density variants, each compiled separately so that a kernel carries only
@@ -287,7 +326,7 @@ SCVT_HD double rho_kind(const DensityP& D, V3 y) {
       V3 c = V3{D.xc[k][0], D.xc[k][1], D.xc[k][2]};
       V3 t = y - c;
       double t2 = dot(t, t);
-      double d = t2 > 0.0 ? t2 * rsq(t2) : 0.0;
+      double d = t2 * rsq_pos(fmax(t2, 1e-300));  // 0 at t2 = 0
       if (KIND & kVarGeo) d = chord_to_angle(d);
       rho += bump(D.amp[k], D.beta[k], D.k2[k], d);
     }
@@ -369,7 +408,7 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
   for (int q = 0; q < 7; q++) {
     const double l0 = kRule7[q][0], l1 = kRule7[q][1], l2 = kRule7[q][2];
     V3 p = l0 * A + l1 * B + l2 * C;
-    double ri = rsq(dot(p, p));
+    double ri = rsq_pos(dot(p, p));
     V3 y = ri * p;
     double jac = ri * ri * ri;
     double wt = hd * kRule7[q][3] * jac * rho_kind<KIND>(D, y);
@@ -524,7 +563,7 @@ SCVT_HD void quad_tri_mixed(F3 dA, F3 dB, F3 dC, F3 zf, const F3* zc, const Dens
 
 // a / |a| through the reciprocal square root (quadrature only; the shared
 // vertices use the correctly rounded `normalized`)
-SCVT_HD V3 normalized_fast(V3 a) { return rsq(dot(a, a)) * a; }
+SCVT_HD V3 normalized_fast(V3 a) { return rsq_pos(dot(a, a)) * a; }
 
 // Leaf `s` (base-4 digits, most significant first) of `levels` geodesic
 // midpoint subdivisions of (A,B,C): children (A,ab,ca), (ab,B,bc), (ca,bc,C),

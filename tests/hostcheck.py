@@ -139,3 +139,10 @@ def home_face(Pts):
     out = np.zeros(len(Pts), np.int32)
     lib().hc_home_face(ctypes.c_int64(len(Pts)), P(Pts), P(out))
     return out
+
+
+def exp_tab(t):
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    out = np.zeros_like(t)
+    lib().hc_exp(ctypes.c_int64(len(t)), P(t), P(out))
+    return out

@@ -217,3 +217,18 @@ def test_mixed_quadrature_error(density):
         assert abs(out[0] - ev.m[k]) <= 1e-5 * ev.m[k]
         assert abs(out[4] - ev.e[k]) <= 1e-5 * ev.e[k]
         assert np.linalg.norm(out[1:4] / out[0] - ev.centroid[k]) <= 1e-6 * R[k]
+
+
+def test_exp_table_accuracy():
+    """The table-driven exponential of the FP64 density agrees with the C
+    library's exp within two ulp over the whole clamped range."""
+    rng = np.random.default_rng(5)
+    t = np.concatenate([rng.uniform(-708.0, 700.0, 100000), rng.uniform(-1.0, 1.0, 100000),
+                        rng.uniform(-30.0, 30.0, 100000),
+                        [0.0, -708.0, 700.0, 1e-300, -1e-300, math.log(2) / 128,
+                         -math.log(2) / 128, math.log(2) / 64, 0.5 * math.log(2)]])
+    got = hc.exp_tab(t)
+    ref = np.array([math.exp(x) for x in t])
+    rel = np.abs(got - ref) / ref
+    assert rel.max() < 5e-16, rel.max()
+    assert got[-9] == 1.0 and got[-6] == 1.0  # t = 0 and t = 1e-300
