@@ -391,6 +391,13 @@ __host__ __device__ constexpr double kRule7[7][4] = {
     {SCVT_B2, SCVT_A2, SCVT_A2, SCVT_W2},          {SCVT_A2, SCVT_B2, SCVT_A2, SCVT_W2},
     {SCVT_A2, SCVT_A2, SCVT_B2, SCVT_W2}};
 
+// the rule rounded to FP32 for the mixed-precision points
+__host__ __device__ constexpr float kRule7f[7][4] = {
+#define SCVT_F(r) {(float)kRule7[r][0], (float)kRule7[r][1], (float)kRule7[r][2], (float)kRule7[r][3]}
+    SCVT_F(0), SCVT_F(1), SCVT_F(2), SCVT_F(3), SCVT_F(4), SCVT_F(5), SCVT_F(6)
+#undef SCVT_F
+};
+
 struct Acc5 {
   double m, mx, my, mz, e;
 };
@@ -450,11 +457,21 @@ SCVT_HD F3 crossf(F3 a, F3 b) {
 }
 SCVT_HD F3 to_f3(V3 v) { return F3{(float)v.x, (float)v.y, (float)v.z}; }
 
+// hardware reciprocal square root and 2^x (about 1 ulp; no special-value or
+// denormal handling: arguments are positive and normal, resp. any finite
+// value with overflow to inf and underflow to 0 both harmless below)
 SCVT_HD float rsqf(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  return ::rsqrtf(x);
+  return __builtin_amdgcn_rsqf(x);
 #else
   return 1.0f / ::sqrtf(x);
+#endif
+}
+SCVT_HD float exp2_hw(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_exp2f(x);
+#else
+  return ::exp2f(x);
 #endif
 }
 SCVT_HD float rcpf(float x) {
@@ -484,7 +501,7 @@ SCVT_HD DensityF density_f32(const DensityP& D) {
 }
 
 SCVT_HD float bumpf(float amp, float beta, float k2l, float d) {
-  return amp * rcpf(1.0f + exp2f((beta - d) * k2l));
+  return amp * rcpf(1.0f + exp2_hw((beta - d) * k2l));
 }
 
 SCVT_HD float chord_to_anglef(float ch) {
@@ -504,7 +521,7 @@ SCVT_HD float rho_kind_f(const DensityF& D, const F3* zc, F3 zf, F3 dyz, const D
     for (int k = 0; k < NB; k++) {
       F3 t = zc[k] + dyz;
       float t2 = dotf(t, t);
-      float d = t2 > 0.0f ? t2 * rsqf(t2) : 0.0f;
+      float d = t2 * rsqf(fmaxf(t2, 1e-30f));  // 0 at t2 = 0
       if (KIND & kVarGeo) d = chord_to_anglef(d);
       rho += bumpf(D.amp[k], D.beta[k], D.k2l[k], d);
     }
@@ -540,14 +557,14 @@ SCVT_HD void quad_tri_mixed(F3 dA, F3 dB, F3 dC, F3 zf, const F3* zc, const Dens
   float sm = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, se = 0.f;
 #pragma unroll 1
   for (int q = 0; q < 7; q++) {
-    const float l0 = (float)kRule7[q][0], l1 = (float)kRule7[q][1], l2 = (float)kRule7[q][2];
+    const float l0 = kRule7f[q][0], l1 = kRule7f[q][1], l2 = kRule7f[q][2];
     F3 d = l0 * dA + l1 * dB + l2 * dC;
     float s = 2.0f * dotf(zf, d) + dotf(d, d);
     float r = rsqf(1.0f + s);
     float rm1 = -s * r * r * rcpf(1.0f + r);
     F3 dyz = r * d + rm1 * zf;
     float jac = r * r * r;
-    float wt = hd * (float)kRule7[q][3] * jac * rho_kind_f<KIND>(D, zc, zf, dyz, Dd);
+    float wt = hd * kRule7f[q][3] * jac * rho_kind_f<KIND>(D, zc, zf, dyz, Dd);
     sm += wt;
     sx += wt * dyz.x;
     sy += wt * dyz.y;

@@ -499,13 +499,18 @@ __device__ inline void cell_epilogue(const EvalOut& o, int64_t i, V3 z, Acc5 acc
   o.lloyd[3 * i + 2] = l.z;
 }
 
-__device__ inline Acc5 wave_sum5(Acc5 a) {
-  a.m = wave_sum(a.m);
-  a.mx = wave_sum(a.mx);
-  a.my = wave_sum(a.my);
-  a.mz = wave_sum(a.mz);
-  a.e = wave_sum(a.e);
-  return a;
+// Sums over the wave of a (on lanes 0-31) and b (on lanes 32-63): the
+// first butterfly step swaps halves so that each half then reduces one of
+// the two; the additions are those of two full butterflies (same bits).
+__device__ inline double pair_sum(double a, double b) {
+  const bool hi = lane_id() >= 32;
+  double v = (hi ? b : a) + __shfl_xor(hi ? a : b, 32, 64);
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline Acc5 pair_sum5(const Acc5& a, const Acc5& b) {
+  return Acc5{pair_sum(a.m, b.m), pair_sum(a.mx, b.mx), pair_sum(a.my, b.my),
+              pair_sum(a.mz, b.mz), pair_sum(a.e, b.e)};
 }
 
 template <int KIND, bool MIXED>
@@ -546,17 +551,23 @@ __global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
     } else {
       quad_tri_k<KIND>(A, B, C, z, a.rho, part);
     }
-    Acc5& acc = second ? acc1 : acc0;
-    acc.m += part.m;
-    acc.mx += part.mx;
-    acc.my += part.my;
-    acc.mz += part.mz;
-    acc.e += part.e;
+    // add into the item's cell: f * part with f in {0, 1} adds exactly
+    // part or exactly zero, without selecting between accumulators
+    const double f0 = second ? 0.0 : 1.0, f1 = 1.0 - f0;
+    acc0.m = fma(f0, part.m, acc0.m);
+    acc0.mx = fma(f0, part.mx, acc0.mx);
+    acc0.my = fma(f0, part.my, acc0.my);
+    acc0.mz = fma(f0, part.mz, acc0.mz);
+    acc0.e = fma(f0, part.e, acc0.e);
+    acc1.m = fma(f1, part.m, acc1.m);
+    acc1.mx = fma(f1, part.mx, acc1.mx);
+    acc1.my = fma(f1, part.my, acc1.my);
+    acc1.mz = fma(f1, part.mz, acc1.mz);
+    acc1.e = fma(f1, part.e, acc1.e);
   }
-  acc0 = wave_sum5(acc0);
-  acc1 = wave_sum5(acc1);
-  if (ln == 0) cell_epilogue<MIXED>(o, i0, z0, acc0);
-  if (ln == 1 && has1) cell_epilogue<MIXED>(o, i1, z1, acc1);
+  const Acc5 tot = pair_sum5(acc0, acc1);
+  if (ln == 0 || (ln == 32 && has1))  // one code path for both cells
+    cell_epilogue<MIXED>(o, ln == 0 ? i0 : i1, ln == 0 ? z0 : z1, tot);
 }
 
 // small problems: every cell goes through the fallback clipper
