@@ -181,9 +181,9 @@ int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes);
 /* Kernel timing (HIP events on the handle's stream, enabled by
  * scvt_set_timing): kernel 0 = certified cell geometry kernel, 1 = fallback
  * clipper, 2 = grid build, 3 = two-loop passes, 4 = whole evaluation,
- * 5 = cell quadrature kernel, 6 = wide certified pass (cells needing more
- * candidates than the main geometry kernel holds).  Returns accumulated
- * milliseconds and launch count since enabling. */
+ * 5 = cell quadrature kernel, 6 = list passes of the certified geometry
+ * (cells needing more candidates than the main geometry kernel holds).
+ * Returns accumulated milliseconds and launch count since enabling. */
 int scvt_set_timing(scvt_handle* h, int enable);
 int scvt_kernel_time(scvt_handle* h, int kernel, double* total_ms, int64_t* launches);
 

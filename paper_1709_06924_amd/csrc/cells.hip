@@ -76,16 +76,18 @@ __device__ inline void store_edge(const EvalOut& o, int64_t i, int k, V3 v0, V3 
 
 // ---------------------------------------------------------- certified path
 // A cell is built by a group of GS lanes holding at most CAP candidates
-// (CAP / GS per lane).  Most cells have 10-20 candidates, so the main kernel
-// uses groups of 16 lanes (four cells per wave, 32 candidates); the few
-// cells that need more go to a second kernel with one whole wave and 64
-// candidates per cell, and only what that cannot certify to the fallback.
-template <int GS, int CAP>
+// (CAP / GS per lane) from a window of at most ROWS x ROWS grid cells.
+// Once the generators are spread evenly a cell has 6-8 candidates, so the
+// main kernel uses groups of 8 lanes (eight cells per wave, 16 candidates);
+// cells that need more go through two list passes, 16 lanes / 32
+// candidates, then a whole wave / 64 candidates, and only what those cannot
+// certify to the fallback clipper.
+template <int GS, int CAP, int ROWS>
 struct CandLds {
   double px[CAP], py[CAP], pz[CAP], dx[CAP], dy[CAP], dz[CAP], nrm[CAP];
   int32_t idx[CAP];
-  int32_t rowoff[kWinMax + 1];
-  int32_t rowstart[kWinMax];
+  int32_t rowoff[ROWS + 1];
+  int32_t rowstart[ROWS];
 };
 
 template <int GS>
@@ -121,8 +123,8 @@ __device__ inline GroupPos group_pos() {
 // Gather every generator p != z with |p - z| < rc from window w into the
 // group's candidate arrays; returns the count (> CAP means overflow).  All
 // lanes of the wave take part; groups with active == false gather nothing.
-template <int GS, int CAP>
-__device__ int gather(const CellArgs& a, CandLds<GS, CAP>& L, const Window& w, int64_t i, V3 z,
+template <int GS, int CAP, int ROWS>
+__device__ int gather(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, const Window& w, int64_t i, V3 z,
                       double rc2, bool active, const GroupPos& G) {
   const GridP& g = a.grid.g;
   const int nrows = active ? w.ib_hi - w.ib_lo + 1 : 0;
@@ -197,8 +199,8 @@ enum CellOutcome { kCellOk = 0, kCellDegenerate = 1, kCellOpen = 2 };
 // is no larger than a radius already found too small (the cell needs more
 // than CAP candidates).  Writes the edges, deg, R and flags of a certified
 // cell and returns the outcome.
-template <int GS, int CAP>
-__device__ int build_cell(const CellArgs& a, CandLds<GS, CAP>& L, bool valid, int64_t i,
+template <int GS, int CAP, int ROWS>
+__device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool valid, int64_t i,
                           const GroupPos& G) {
   constexpr int PER = CAP / GS;
   static_assert(PER * GS == CAP && PER >= 1 && PER <= 2, "one or two candidates per lane");
@@ -213,9 +215,9 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP>& L, bool valid, in
   double R = 0.0;
   for (int attempt = 0; attempt < 8; attempt++) {
     if (!__ballot(active)) break;
-    const Window w = make_window(a.grid.g, z, f, rt, kWinMax);
+    const Window w = make_window(a.grid.g, z, f, rt, ROWS);
     const double rc = rt < w.D ? rt : w.D;
-    const int ns = gather<GS, CAP>(a, L, w, i, z, rc * rc, active, G);
+    const int ns = gather<GS, CAP, ROWS>(a, L, w, i, z, rc * rc, active, G);
     bool go = active;
     if (go && ns > CAP) {
       rt = rc * sqrt(0.75 * CAP / (double)ns);
@@ -314,45 +316,47 @@ __device__ inline void to_list(int32_t* list, int32_t* count, int64_t i) {
   list[k] = (int32_t)i;
 }
 
-// Main certified pass: four cells per wave in cube-map order.  Cells that
-// need more than 32 candidates go to the wide list, degenerate ones to the
-// fallback list.
+// where a cell goes when a pass could not certify it: degenerate ones to
+// the fallback clipper, the others to the next pass (or the fallback)
+__device__ inline void hand_on(const CellArgs& a, int64_t i, int oc, int next_tier) {
+  a.out.deg[i] = 0;
+  if (oc == kCellDegenerate) atomicAdd(&a.ctr->n_degenerate, 1);
+  if (oc == kCellDegenerate || next_tier < 0)
+    to_list(a.fb_list, &a.ctr->fb_count, i);
+  else
+    to_list(a.tier_list[next_tier], &a.ctr->tier_count[next_tier], i);
+}
+
+// Main certified pass: eight cells per wave in cube-map order.
 __global__ __launch_bounds__(256, 4) void k_cells_geom(CellArgs a) {
-  constexpr int GS = 16;
-  __shared__ CandLds<GS, 32> lds[16];
+  constexpr int GS = 8, GPW = 64 / GS;
+  __shared__ CandLds<GS, 16, 15> lds[4 * GPW];
   const GroupPos G = group_pos<GS>();
   const int wv = threadIdx.x >> 6;
-  const int64_t pos = (xcd_block(blockIdx.x, gridDim.x) * 4 + wv) * 4 + G.gid;
+  const int64_t pos = (xcd_block(blockIdx.x, gridDim.x) * 4 + wv) * GPW + G.gid;
   const bool valid = pos < a.n;
   if (!__ballot(valid)) return;
   const int64_t i = valid ? a.grid.order[pos] : 0;
-  const int oc = build_cell<GS, 32>(a, lds[wv * 4 + G.gid], valid, i, G);
-  if (valid && G.gl == 0 && oc != kCellOk) {
-    a.out.deg[i] = 0;
-    if (oc == kCellDegenerate) {
-      atomicAdd(&a.ctr->n_degenerate, 1);
-      to_list(a.fb_list, &a.ctr->fb_count, i);
-    } else {
-      to_list(a.wide_list, &a.ctr->wide_count, i);
-    }
-  }
+  const int oc = build_cell(a, lds[wv * GPW + G.gid], valid, i, G);
+  if (valid && G.gl == 0 && oc != kCellOk) hand_on(a, i, oc, 0);
 }
 
-// Second certified pass over the wide list: one wave and up to 64
-// candidates per cell; what stays open goes to the fallback list.
-__global__ __launch_bounds__(256, 2) void k_cells_wide(CellArgs a) {
-  __shared__ CandLds<64, 64> lds[4];
-  const GroupPos G = group_pos<64>();
+// List passes: the cells of tier list T, GS lanes each; what stays open
+// goes to list T + 1 (or, after the last pass, to the fallback).
+template <int T, int GS, int CAP, int ROWS>
+__global__ __launch_bounds__(256, 2) void k_cells_tier(CellArgs a) {
+  constexpr int GPW = 64 / GS;
+  __shared__ CandLds<GS, CAP, ROWS> lds[4 * GPW];
+  const GroupPos G = group_pos<GS>();
   const int wv = threadIdx.x >> 6;
-  const int count = a.ctr->wide_count;
-  for (int w = blockIdx.x * 4 + wv; w < count; w += gridDim.x * 4) {
-    const int64_t i = a.wide_list[w];
-    const int oc = build_cell<64, 64>(a, lds[wv], true, i, G);
-    if (G.gl == 0 && oc != kCellOk) {
-      a.out.deg[i] = 0;
-      if (oc == kCellDegenerate) atomicAdd(&a.ctr->n_degenerate, 1);
-      to_list(a.fb_list, &a.ctr->fb_count, i);
-    }
+  const int count = a.ctr->tier_count[T];
+  const int stride = gridDim.x * 4 * GPW;
+  for (int base = (blockIdx.x * 4 + wv) * GPW; base < count; base += stride) {
+    const int w = base + G.gid;
+    const bool valid = w < count;
+    const int64_t i = valid ? a.tier_list[T][w] : 0;
+    const int oc = build_cell(a, lds[wv * GPW + G.gid], valid, i, G);
+    if (valid && G.gl == 0 && oc != kCellOk) hand_on(a, i, oc, T + 1 < kTiers ? T + 1 : -1);
   }
 }
 
@@ -578,15 +582,16 @@ __global__ void k_fb_all(int32_t* fb_list, Counters* ctr, int64_t n) {
 }
 
 hipError_t launch_cells_main(const CellArgs& a, hipStream_t s) {
-  const int64_t nb = (a.n + 15) / 16;  // four cells per wave, four waves per block
+  const int64_t nb = (a.n + 31) / 32;  // eight cells per wave, four waves per block
   k_cells_geom<<<(unsigned)nb, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_cells_wide(const CellArgs& a, hipStream_t s) {
-  // the list length is only known on the device: a fixed grid
-  const int64_t nw = (a.n + 63) / 64 < 512 ? (a.n + 63) / 64 : 512;
-  k_cells_wide<<<(unsigned)nw, 256, 0, s>>>(a);
+hipError_t launch_cells_tiers(const CellArgs& a, hipStream_t s) {
+  // list lengths are only known on the device: fixed grids
+  const int64_t nb = (a.n + 255) / 256 < 256 ? (a.n + 255) / 256 : 256;
+  k_cells_tier<0, 16, 32, 31><<<(unsigned)nb, 256, 0, s>>>(a);
+  k_cells_tier<1, 64, 64, kWinMax><<<(unsigned)nb, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

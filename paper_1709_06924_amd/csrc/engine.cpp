@@ -50,7 +50,7 @@ struct scvt_handle {
   double* dscal = nullptr;            // device scalars
   double* partials = nullptr;
   int32_t* fb_list = nullptr;
-  int32_t* wide_list = nullptr;
+  int32_t* tier_list[2] = {nullptr, nullptr};
   Counters* ctr = nullptr;
   double* pinned = nullptr;  // host-pinned mirror of scalars
   std::vector<void*> allocs;
@@ -204,7 +204,8 @@ CellArgs cell_args(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   a.out.cell_nbr = s.cell_nbr;
   a.out.edges = s.edges;
   a.fb_list = h->fb_list;
-  a.wide_list = h->wide_list;
+  a.tier_list[0] = h->tier_list[0];
+  a.tier_list[1] = h->tier_list[1];
   a.ctr = h->ctr;
   a.r_default = h->r_default;
   return a;
@@ -229,7 +230,7 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   CellArgs a = cell_args(h, Zsrc, s);
   if (h->main_path) HIPCK(launch_cells_main(a, st));
   if (tm) HIPCK(hipEventRecord(h->ev[8], st));
-  if (h->main_path) HIPCK(launch_cells_wide(a, st));
+  if (h->main_path) HIPCK(launch_cells_tiers(a, st));
   if (tm) HIPCK(hipEventRecord(h->ev[2], st));
   HIPCK(launch_cells_fallback(a, h->main_path ? 0 : 1, st));
   if (tm) HIPCK(hipEventRecord(h->ev[3], st));
@@ -528,7 +529,8 @@ int alloc_device_state(scvt_handle* h) {
   ALLOC(h->dscal, kNScal);
   ALLOC(h->partials, kPartTotal * reduce_grid_max());
   ALLOC(h->fb_list, n);
-  ALLOC(h->wide_list, n);
+  ALLOC(h->tier_list[0], n);
+  ALLOC(h->tier_list[1], n);
   ALLOC(h->ctr, 1);
   ALLOC(h->grid.cnt_tot, nc + 1);
   ALLOC(h->grid.cnt_home, nc + 1);

@@ -52,10 +52,10 @@ struct GridBufs {
 struct Counters {  // device-side counters of one evaluation
   int32_t fb_count;
   int32_t n_fallback, n_degenerate, n_error, n_brute;
-  int32_t n_duplicate;  // duplicate generators seen
-  int32_t wide_count;   // cells handed to the wide certified pass
-  int32_t pad;
+  int32_t n_duplicate;    // duplicate generators seen
+  int32_t tier_count[2];  // cells handed to the list passes of the certified path
 };
+constexpr int kTiers = 2;
 
 struct CellArgs {
   int64_t n;
@@ -68,7 +68,7 @@ struct CellArgs {
   int pad;
   EvalOut out;
   int32_t* fb_list;    // n: cells for the fallback clipper
-  int32_t* wide_list;  // n: cells for the wide certified pass
+  int32_t* tier_list[2];  // n each: cells for the list passes of the certified path
   Counters* ctr;
   double r_default;  // initial search radius when no previous one is known
 };
@@ -78,7 +78,7 @@ hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha
                                   int64_t n, hipStream_t s);
 hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s);
 hipError_t launch_cells_main(const CellArgs& a, hipStream_t s);
-hipError_t launch_cells_wide(const CellArgs& a, hipStream_t s);
+hipError_t launch_cells_tiers(const CellArgs& a, hipStream_t s);
 hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s);
 hipError_t launch_quad(const CellArgs& a, hipStream_t s);
 hipError_t launch_centroid(const double* mu, const double* m, double* out, int64_t n,

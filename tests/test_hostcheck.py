@@ -87,19 +87,29 @@ def _certify(Z, rt, cap, attempts=8):
 
 
 def test_retry_policy_certifies_nearly_all():
-    """The main pass (32 candidates per cell) certifies most cells of random
-    input, from a too small and from a too large first radius, and the wide
-    pass (64 candidates) nearly all of the rest."""
+    """On random input the main pass (16 candidates per cell) certifies most
+    cells from a too small and from a too large first radius, the list
+    passes (32, then 64 candidates) nearly all of the rest."""
     n = 3000
     Z = I.uniform_sphere(n, 2)
     h = math.sqrt(4 * math.pi / n)
     for r0 in (2.0 * h, 6.0 * h):
-        done = _certify(Z, np.full(n, r0), cap=32)
-        assert done.mean() > 0.98
-        rest = np.where(~done)[0]
-        done_w = _certify(Z, np.full(n, 2.0 * h), cap=64)
-        assert done_w[rest].mean() > 0.8
-        assert (done | done_w).mean() > 0.998
+        done = _certify(Z, np.full(n, r0), cap=16)
+        assert done.mean() > 0.6
+        done |= _certify(Z, np.full(n, 2.0 * h), cap=32)
+        assert done.mean() > 0.99
+        done |= _certify(Z, np.full(n, 2.0 * h), cap=64)
+        assert done.mean() > 0.998
+    # from the previous evaluation's circumradius (2.3 R) as well; on random
+    # input (irregular cells) about 30% need more than 16 candidates
+    st, deg, nbr, verts, R = hc.cells(Z, 3.5 * h)
+    R = np.where(st == 0, R, h)
+    done = _certify(Z, 2.3 * R, cap=16)
+    assert done.mean() > 0.6
+    done |= _certify(Z, 2.3 * R, cap=32)
+    assert done.mean() > 0.98
+    done |= _certify(Z, 2.3 * R, cap=64)
+    assert done.mean() > 0.998
 
 
 def test_certificate_is_sound():
