@@ -49,6 +49,8 @@ struct scvt_handle {
   double *S = nullptr, *Y = nullptr;  // (M+1) slots of 3n
   double* dscal = nullptr;            // device scalars
   double* partials = nullptr;
+  double* gram = nullptr;   // s_j . y_k (j older than k) by slot, (M+1)^2
+  double* hpart = nullptr;  // block partials of the history passes
   int32_t* fb_list = nullptr;
   int32_t* tier_list[2] = {nullptr, nullptr};
   Counters* ctr = nullptr;
@@ -76,8 +78,6 @@ struct scvt_handle {
 
 namespace {
 
-// device scalar layout (doubles)
-enum : int { kA = 0, kCoef = 64, kR = 128, kGQ = 200, kPush = 201, kEval = 204, kNScal = 256 };
 // partial-sum buffers, in units of reduce_grid_max() doubles
 enum : int { kPartPass = 0, kPartPush = 2, kPartEval = 5, kPartTotal = 9 };
 
@@ -299,10 +299,102 @@ void adopt_trial_scalars(scvt_handle* h) {
   h->n_deg = h->tdeg;
 }
 
-// P-LBFGS direction into h->q; g . q into *gq (one host sync).  Each pass
+// P-LBFGS direction into h->q; g . q into *gq (one host sync).
+//
+// Up to kHmax pairs: the two recursions run on the history's inner products
+// (s_j.g from the last push, s_j.y_k kept as pairs arrive), so the vectors
+// are streamed twice (q0 pass, direction pass), see lbfgs.h.
+int direction_fused(scvt_handle* h, double* gq) {
+  hipStream_t st = h->stream;
+  const int64_t n3 = 3 * h->n;
+  double* D = h->dscal;
+  const int c = (int)h->ring.size();
+  if (h->timing) HIPCK(hipEventRecord(h->ev[5], st));
+  HistFinArgs f{};
+  f.partials = h->hpart;
+  f.nblocks = hist_grid(n3);
+  f.c = c;
+  f.stride = h->M + 1;
+  f.dscal = D;
+  f.gram = h->gram;
+  HistPassArgs p{};
+  p.n3 = n3;
+  p.c = c;
+  p.g = h->cur.g;
+  p.h = h->cur.h;
+  p.partials = h->hpart;
+  for (int j = 0; j < c; j++) {
+    f.slot[j] = h->ring[j];
+    p.S[j] = h->S + (size_t)h->ring[j] * n3;
+    p.Y[j] = h->Y + (size_t)h->ring[j] * n3;
+  }
+  if (c > 0) {
+    f.mode = kFinBackward;
+    f.nvals = 0;
+    HIPCK(launch_hist_fin(f, st));
+  }
+  p.coef = D + kA;
+  p.q = h->q;
+  HIPCK(launch_hist_q0(p, st));
+  if (c > 0) {
+    f.mode = kFinForward;
+    f.nvals = c;
+    HIPCK(launch_hist_fin(f, st));
+  }
+  p.coef = D + kCoef;
+  p.qin = h->q;
+  p.q = h->q;
+  HIPCK(launch_hist_dir(p, st));
+  f.mode = kFinGQ;
+  f.nvals = 1;
+  HIPCK(launch_hist_fin(f, st));
+  if (h->timing) HIPCK(hipEventRecord(h->ev[6], st));
+  HIPCK(hipMemcpyAsync(h->pinned + 4, D + kGQ, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  if (h->timing) timer_add(h, 3, h->ev[5], h->ev[6]);
+  *gq = h->pinned[4];
+  return SCVT_OK;
+}
+
+// s_j . g for the stored pairs and s_j . y_k (j older than k), recomputed
+// from the vectors (after a restored state); the same kernels' sums as the
+// pushes that produced them, so the values are the same bits.
+int hist_rebuild(scvt_handle* h) {
+  const int c = (int)h->ring.size();
+  if (h->M > kHmax || c == 0) return SCVT_OK;
+  hipStream_t st = h->stream;
+  const int64_t n3 = 3 * h->n;
+  const int stride = h->M + 1;
+  auto S = [&](int j) { return h->S + (size_t)h->ring[j] * n3; };
+  for (int k = 0; k <= c; k++) {  // k = c: against g; else against y_k
+    const int cnt = k == c ? c : k;
+    if (cnt == 0) continue;
+    MultiDotArgs m{};
+    m.n3 = n3;
+    m.c = cnt;
+    m.v = k == c ? h->cur.g : h->Y + (size_t)h->ring[k] * n3;
+    m.partials = h->hpart;
+    HistFinArgs f{};
+    f.mode = kFinDots;
+    f.partials = h->hpart;
+    f.nblocks = hist_grid(n3);
+    f.nvals = cnt;
+    f.c = cnt;
+    for (int j = 0; j < cnt; j++) {
+      m.A[j] = S(j);
+      f.dst[j] = k == c ? h->dscal + kSG + h->ring[j] : h->gram + h->ring[j] * stride + h->ring[k];
+    }
+    HIPCK(launch_multi_dot(m, st));
+    HIPCK(launch_hist_fin(f, st));
+  }
+  HIPCK(hipStreamSynchronize(st));
+  return SCVT_OK;
+}
+
+// More than kHmax pairs: the two-loop as 2c+1 streaming passes; each pass
 // finishes the previous pass's dot product from its block partials (no
 // separate reduction launch), see lbfgs.hip.
-int direction(scvt_handle* h, double* gq) {
+int direction_passes(scvt_handle* h, double* gq) {
   hipStream_t st = h->stream;
   const int64_t n3 = 3 * h->n;
   double* D = h->dscal;
@@ -383,6 +475,10 @@ int direction(scvt_handle* h, double* gq) {
   return SCVT_OK;
 }
 
+int direction(scvt_handle* h, double* gq) {
+  return h->M <= kHmax ? direction_fused(h, gq) : direction_passes(h, gq);
+}
+
 // Armijo backtracking along q from the current point; on success the trial
 // set holds the accepted evaluation.
 int line_search(scvt_handle* h, double gq, bool* accepted, double* alpha_out) {
@@ -407,23 +503,54 @@ int push_pair(scvt_handle* h) {
   if (h->M == 0) return SCVT_OK;
   const int slot = h->free_slots.back();
   const int64_t n3 = 3 * h->n;
-  PushArgs p{};
-  p.n3 = n3;
-  p.Z = h->Z;
-  p.Zt = h->Zt;
-  p.g = h->cur.g;
-  p.gt = h->trial.g;
-  p.s = h->S + (size_t)slot * n3;
-  p.y = h->Y + (size_t)slot * n3;
-  p.partials = h->partials + kPartPush * reduce_grid_max();
-  HIPCK(launch_push(p, h->stream));
-  FinalizeArgs fa{};
-  fa.partials = p.partials;
-  fa.nblocks = reduce_grid(n3);
-  fa.nvals = 3;
-  fa.out = h->dscal + kPush;
-  fa.r_slot = h->dscal + kR + slot;
-  HIPCK(launch_finalize(fa, h->stream));
+  if (h->M <= kHmax) {
+    // also s_j . g_new and s_j . y_new for the stored pairs (next direction)
+    const int c = (int)h->ring.size();
+    PushExtArgs p{};
+    p.n3 = n3;
+    p.Z = h->Z;
+    p.Zt = h->Zt;
+    p.g = h->cur.g;
+    p.gt = h->trial.g;
+    p.s = h->S + (size_t)slot * n3;
+    p.y = h->Y + (size_t)slot * n3;
+    p.c = c;
+    p.partials = h->hpart;
+    HistFinArgs f{};
+    f.mode = kFinPush;
+    f.partials = h->hpart;
+    f.nblocks = hist_grid(n3);
+    f.nvals = 4 + 2 * c;
+    f.c = c;
+    f.p = slot;
+    f.stride = h->M + 1;
+    f.dscal = h->dscal;
+    f.gram = h->gram;
+    for (int j = 0; j < c; j++) {
+      p.S[j] = h->S + (size_t)h->ring[j] * n3;
+      f.slot[j] = h->ring[j];
+    }
+    HIPCK(launch_push_ext(p, h->stream));
+    HIPCK(launch_hist_fin(f, h->stream));
+  } else {
+    PushArgs p{};
+    p.n3 = n3;
+    p.Z = h->Z;
+    p.Zt = h->Zt;
+    p.g = h->cur.g;
+    p.gt = h->trial.g;
+    p.s = h->S + (size_t)slot * n3;
+    p.y = h->Y + (size_t)slot * n3;
+    p.partials = h->partials + kPartPush * reduce_grid_max();
+    HIPCK(launch_push(p, h->stream));
+    FinalizeArgs fa{};
+    fa.partials = p.partials;
+    fa.nblocks = reduce_grid(n3);
+    fa.nvals = 3;
+    fa.out = h->dscal + kPush;
+    fa.r_slot = h->dscal + kR + slot;
+    HIPCK(launch_finalize(fa, h->stream));
+  }
   HIPCK(hipMemcpyAsync(h->pinned + 5, h->dscal + kPush, 3 * sizeof(double), hipMemcpyDeviceToHost,
                        h->stream));
   HIPCK(hipStreamSynchronize(h->stream));
@@ -528,6 +655,8 @@ int alloc_device_state(scvt_handle* h) {
   }
   ALLOC(h->dscal, kNScal);
   ALLOC(h->partials, kPartTotal * reduce_grid_max());
+  ALLOC(h->gram, (size_t)(M + 1) * (M + 1));
+  ALLOC(h->hpart, hist_grid_max());
   ALLOC(h->fb_list, n);
   ALLOC(h->tier_list[0], n);
   ALLOC(h->tier_list[1], n);
@@ -834,6 +963,7 @@ int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes) {
   h->alpha = alpha;
   int rc = evaluate(h, h->Z, h->cur);
   if (!rc) adopt_trial_scalars(h);
+  if (!rc) rc = hist_rebuild(h);
   return rc;
 }
 

@@ -52,6 +52,84 @@ struct EvalRedArgs {
   double* partials;  // F, max|l|, sum|g|^2, min mu.z per block
 };
 
+// ---- two-loop through the history's inner products (up to kHmax pairs) ----
+// The backward loop's a_j = r_j s_j.q_{j+1} with q_{j+1} = -g - sum_{k>j} a_k y_k
+// equals r_j (-s_j.g - sum_{k>j} a_k s_j.y_k), and the forward loop's
+// b_j = r_j y_j.(r + sum_{k<j} c_k s_k) equals r_j (y_j.r + sum_{k<j} c_k s_k.y_j)
+// with r = h (.) q_0.  With s_j.g (from the push of the previous iteration) and
+// the products s_j.y_k, j older than k (kept as pairs arrive), the two
+// recursions are scalar work; the vectors are streamed twice:
+//   q0 pass:  r = h (.) (-g - sum_k a_k y_k), partials of y_j.r
+//   dir pass: q = r + sum_k c_k s_k, partials of g.q
+constexpr int kHmax = 16;
+
+// device scalar layout (doubles, in the handle's scalar buffer)
+enum : int {
+  kA = 0,       // a_j by ring position
+  kCoef = 64,   // c_j = a_j - b_j by ring position
+  kR = 128,     // r = 1 / y.s by slot
+  kGQ = 200,    // g . q
+  kPush = 201,  // y.s, y.y, s.s of the last push
+  kEval = 204,  // F, max |l|, sum |g|^2, min mu.z
+  kSG = 256,    // s.g by slot (g at the current point)
+  kNScal = 384
+};
+
+struct HistPassArgs {
+  int64_t n3;
+  int c;  // stored pairs, ring order (oldest first)
+  const double* S[kHmax];
+  const double* Y[kHmax];
+  const double* g;
+  const double* h;     // per generator
+  const double* qin;   // dir pass: r
+  double* q;           // output
+  const double* coef;  // a_j (q0 pass) or c_j (dir pass), ring order
+  double* partials;
+};
+
+// s = Zt - Z, y = gt - g into the new slot; per block: y.s, y.y, s.s,
+// s.gt, then s_j.gt and s_j.y for the c stored pairs.
+struct PushExtArgs {
+  int64_t n3;
+  const double *Z, *Zt, *g, *gt;
+  double *s, *y;
+  int c;
+  const double* S[kHmax];
+  double* partials;
+};
+
+// per block: A_j . v for j < c
+struct MultiDotArgs {
+  int64_t n3;
+  int c;
+  const double* A[kHmax];
+  const double* v;
+  double* partials;
+};
+
+enum : int { kFinPush = 0, kFinDots = 1, kFinBackward = 2, kFinForward = 3, kFinGQ = 4 };
+struct HistFinArgs {
+  int mode;
+  const double* partials;
+  int nblocks, nvals;
+  int c;
+  int slot[kHmax];  // ring slots, oldest first
+  int p;            // push: slot of the new pair
+  int stride;       // row stride of the s.y table (M + 1)
+  double* dscal;
+  double* gram;     // s_j.y_k at [slot_j * stride + slot_k]
+  double* dst[kHmax];
+};
+
+hipError_t launch_push_ext(const PushExtArgs& a, hipStream_t s);
+hipError_t launch_multi_dot(const MultiDotArgs& a, hipStream_t s);
+hipError_t launch_hist_q0(const HistPassArgs& a, hipStream_t s);
+hipError_t launch_hist_dir(const HistPassArgs& a, hipStream_t s);
+hipError_t launch_hist_fin(const HistFinArgs& a, hipStream_t s);
+int hist_grid(int64_t n3);  // blocks of the history passes
+int hist_grid_max();
+
 hipError_t launch_lbfgs_pass(const PassArgs& a, hipStream_t s);
 hipError_t launch_push(const PushArgs& a, hipStream_t s);
 hipError_t launch_eval_reduce(const EvalRedArgs& a, hipStream_t s);

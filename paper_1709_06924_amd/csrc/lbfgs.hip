@@ -155,6 +155,204 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize(FinalizeArgs a) {
   if (threadIdx.x == 0 && a.r_slot) *a.r_slot = 1.0 / a.out[0];
 }
 
+// ------------------------------------------- history passes (kHmax pairs)
+constexpr int kHGrid = 1024;
+constexpr int kHVals = 4 + 2 * kHmax;  // most values one block reduces
+
+__device__ inline double wave_sum64(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block partials of K (<= KMAX) per-thread values: a butterfly within each
+// wave, then the four waves in order; written to out[0..K).
+template <int KMAX>
+__device__ inline void block_partials(const double* acc, int K, double* out) {
+  __shared__ double sh[4][KMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < KMAX; v++) {
+    if (v < K) {
+      const double x = wave_sum64(acc[v]);
+      if (lane == 0) sh[wave][v] = x;
+    }
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < K; v += blockDim.x)
+    out[v] = ((sh[0][v] + sh[1][v]) + sh[2][v]) + sh[3][v];
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_push_ext(PushExtArgs a) {
+  double acc[kHVals];
+#pragma unroll
+  for (int v = 0; v < kHVals; v++) acc[v] = 0.0;
+  const int c = a.c;
+  const int n3 = (int)a.n3;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
+    const double gt = a.gt[k];
+    const double s = a.Zt[k] - a.Z[k];
+    const double y = gt - a.g[k];
+    a.s[k] = s;
+    a.y[k] = y;
+    acc[0] = fma(y, s, acc[0]);
+    acc[1] = fma(y, y, acc[1]);
+    acc[2] = fma(s, s, acc[2]);
+    acc[3] = fma(s, gt, acc[3]);
+#pragma unroll
+    for (int j = 0; j < kHmax; j++) {
+      if (j < c) {
+        const double sj = a.S[j][k];
+        acc[4 + 2 * j] = fma(sj, gt, acc[4 + 2 * j]);
+        acc[5 + 2 * j] = fma(sj, y, acc[5 + 2 * j]);
+      }
+    }
+  }
+  block_partials<kHVals>(acc, 4 + 2 * c, a.partials + (size_t)blockIdx.x * (4 + 2 * c));
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_multi_dot(MultiDotArgs a) {
+  double acc[kHmax];
+#pragma unroll
+  for (int v = 0; v < kHmax; v++) acc[v] = 0.0;
+  const int c = a.c;
+  const int n3 = (int)a.n3;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
+    const double v = a.v[k];
+#pragma unroll
+    for (int j = 0; j < kHmax; j++)
+      if (j < c) acc[j] = fma(a.A[j][k], v, acc[j]);
+  }
+  block_partials<kHmax>(acc, c, a.partials + (size_t)blockIdx.x * c);
+}
+
+// r = h (.) (-g - sum_k a_k y_k), newest pair first as in the backward loop;
+// partials of y_j . r
+__global__ __launch_bounds__(kRedBlock) void k_hist_q0(HistPassArgs a) {
+  const int c = a.c;
+  double coef[kHmax], acc[kHmax];
+#pragma unroll
+  for (int j = 0; j < kHmax; j++) {
+    coef[j] = j < c ? a.coef[j] : 0.0;
+    acc[j] = 0.0;
+  }
+  const int n3 = (int)a.n3;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
+    double yv[kHmax];
+    double q = -a.g[k];
+#pragma unroll
+    for (int j = kHmax - 1; j >= 0; j--) {
+      if (j < c) {
+        yv[j] = a.Y[j][k];
+        q = fma(-coef[j], yv[j], q);
+      }
+    }
+    const double r = a.h[(unsigned)k / 3u] * q;
+    a.q[k] = r;
+#pragma unroll
+    for (int j = 0; j < kHmax; j++)
+      if (j < c) acc[j] = fma(yv[j], r, acc[j]);
+  }
+  if (c > 0) block_partials<kHmax>(acc, c, a.partials + (size_t)blockIdx.x * c);
+}
+
+// q = r + sum_k c_k s_k, oldest pair first as in the forward loop; partials
+// of g . q
+__global__ __launch_bounds__(kRedBlock) void k_hist_dir(HistPassArgs a) {
+  const int c = a.c;
+  double coef[kHmax];
+#pragma unroll
+  for (int j = 0; j < kHmax; j++) coef[j] = j < c ? a.coef[j] : 0.0;
+  double acc[1] = {0.0};
+  const int n3 = (int)a.n3;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
+    double q = a.qin[k];
+#pragma unroll
+    for (int j = 0; j < kHmax; j++)
+      if (j < c) q = fma(coef[j], a.S[j][k], q);
+    a.q[k] = q;
+    acc[0] = fma(a.g[k], q, acc[0]);
+  }
+  block_partials<1>(acc, 1, a.partials + blockIdx.x);
+}
+
+// One block: sums the block partials of each value in block order (wave w
+// takes values w, w+4, ...; lane l blocks l, l+64, ...), then the scalar
+// step of the mode.
+__global__ __launch_bounds__(kRedBlock) void k_hist_fin(HistFinArgs a) {
+  __shared__ double red[kHVals];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int v = wave; v < a.nvals; v += 4) {
+    double x = 0.0;
+    for (int b = lane; b < a.nblocks; b += 64) x += a.partials[(size_t)b * a.nvals + v];
+    x = wave_sum64(x);
+    if (lane == 0) red[v] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double* D = a.dscal;
+  const int c = a.c;
+  if (a.mode == kFinPush) {
+    D[kPush] = red[0];
+    D[kPush + 1] = red[1];
+    D[kPush + 2] = red[2];
+    D[kR + a.p] = 1.0 / red[0];
+    D[kSG + a.p] = red[3];
+    for (int j = 0; j < c; j++) {
+      D[kSG + a.slot[j]] = red[4 + 2 * j];
+      a.gram[a.slot[j] * a.stride + a.p] = red[5 + 2 * j];
+    }
+  } else if (a.mode == kFinDots) {
+    for (int j = 0; j < c; j++) *a.dst[j] = red[j];
+  } else if (a.mode == kFinBackward) {
+    // a_j = r_j (-s_j.g - sum_{k>j} a_k s_j.y_k), newest first
+    for (int j = c - 1; j >= 0; j--) {
+      const int sj = a.slot[j];
+      double t = -D[kSG + sj];
+      for (int k = c - 1; k > j; k--) t = fma(-D[kA + k], a.gram[sj * a.stride + a.slot[k]], t);
+      D[kA + j] = D[kR + sj] * t;
+    }
+  } else if (a.mode == kFinForward) {
+    // c_j = a_j - r_j (y_j.r + sum_{k<j} c_k s_k.y_j), oldest first
+    for (int j = 0; j < c; j++) {
+      const int sj = a.slot[j];
+      double t = red[j];
+      for (int k = 0; k < j; k++) t = fma(D[kCoef + k], a.gram[a.slot[k] * a.stride + sj], t);
+      D[kCoef + j] = D[kA + j] - D[kR + sj] * t;
+    }
+  } else {
+    D[kGQ] = red[0];
+  }
+}
+
+int hist_grid(int64_t n3) {
+  int64_t b = (n3 + kRedBlock - 1) / kRedBlock;
+  if (b > kHGrid) b = kHGrid;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+int hist_grid_max() { return kHGrid * kHVals; }
+
+hipError_t launch_push_ext(const PushExtArgs& a, hipStream_t s) {
+  k_push_ext<<<hist_grid(a.n3), kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_multi_dot(const MultiDotArgs& a, hipStream_t s) {
+  k_multi_dot<<<hist_grid(a.n3), kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_hist_q0(const HistPassArgs& a, hipStream_t s) {
+  k_hist_q0<<<hist_grid(a.n3), kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_hist_dir(const HistPassArgs& a, hipStream_t s) {
+  k_hist_dir<<<hist_grid(a.n3), kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_hist_fin(const HistFinArgs& a, hipStream_t s) {
+  k_hist_fin<<<1, kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 int reduce_grid(int64_t count) {
   int64_t b = (count + kRedBlock - 1) / kRedBlock;
   if (b > kRedGrid) b = kRedGrid;

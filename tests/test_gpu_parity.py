@@ -113,11 +113,14 @@ def test_duplicate_generators_rejected(scvt):
     assert e.value.code == -3
 
 
-def test_direction_parity_with_history(scvt):
+@pytest.mark.parametrize("m_hist,steps", [(5, 7), (16, 20), (20, 24)])
+def test_direction_parity_with_history(scvt, m_hist, steps):
+    """Up to 16 pairs the two-loop runs on the history's inner products,
+    beyond on 2c+1 streaming passes: both against the oracle's two-loop."""
     n = 3000
     d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
-    S = scvt.Solver(I.uniform_sphere(n, 7), d, m_hist=5)
-    for _ in range(7):
+    S = scvt.Solver(I.uniform_sphere(n, 7), d, m_hist=m_hist)
+    for _ in range(steps):
         S.step()
     blob = S.get_state()
     # unpack the state blob: header, alpha, Z, then (r, s, y) oldest first
@@ -133,7 +136,7 @@ def test_direction_parity_with_history(scvt):
         y = arr[off + 1 + 3 * n:off + 1 + 6 * n].reshape(n, 3)
         hist.append((s, y, r))
         off += 1 + 6 * n
-    assert c == 5
+    assert c == m_hist
     ev = oracle.evaluate(Z, d)
     q_ref = oracle.two_loop(ev.g, ev.h, hist)
     q, gq = S.direction()
@@ -187,18 +190,19 @@ def test_monotone_energy_and_counts(scvt):
     assert info["hist_len"] == 7
 
 
-def test_checkpoint_resume_bitwise(scvt):
+@pytest.mark.parametrize("m_hist", [7, 20])
+def test_checkpoint_resume_bitwise(scvt, m_hist):
     d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
     Z0 = I.uniform_sphere(4000, 10)
-    A = scvt.Solver(Z0, d)
+    A = scvt.Solver(Z0, d, m_hist=m_hist)
     for _ in range(8):
         A.step()
     ZA = A.generators()
-    B = scvt.Solver(Z0, d)
+    B = scvt.Solver(Z0, d, m_hist=m_hist)
     for _ in range(4):
         B.step()
     blob = B.get_state()
-    C = scvt.Solver(Z0, d)
+    C = scvt.Solver(Z0, d, m_hist=m_hist)
     C.set_state(blob)
     for _ in range(4):
         C.step()
