@@ -601,6 +601,45 @@ SCVT_HD void subtriangle(V3& A, V3& B, V3& C, int s, int levels) {
   }
 }
 
+// Two levels of that subdivision share their points: the 16 leaves of a
+// triangle use the 15 points of a triangular grid with barycentric numerators
+// (i, j, k), i + j + k = 4, for (A, B, C), numbered lexicographically in
+// (i, j) (A = 14, B = 4, C = 0).  The 3 level-1 midpoints and then the 9
+// level-2 midpoints are normalize(P + Q) of two grid points, the same sums
+// subtriangle() forms, so the leaves are the same bits.
+// kGrid2Task[t] = {point, P, Q}: t < 3 level 1, then level 2.
+__host__ __device__ constexpr int8_t kGrid2Task[12][3] = {
+    {11, 14, 4}, {2, 4, 0},  {9, 0, 14},                                    // level 1
+    {13, 14, 11}, {10, 11, 9}, {12, 9, 14}, {8, 11, 4}, {3, 4, 2}, {7, 2, 11},  // level 2
+    {6, 9, 2},   {1, 2, 0},  {5, 0, 9}};
+// kGrid2Leaf[s] = grid points of leaf s in subtriangle()'s vertex order
+__host__ __device__ constexpr int8_t kGrid2Leaf[16][3] = {
+    {14, 13, 12}, {13, 11, 10}, {12, 10, 9}, {13, 10, 12}, {11, 8, 7}, {8, 4, 3},
+    {7, 3, 2},    {8, 3, 7},    {9, 6, 5},   {6, 2, 1},    {5, 1, 0},  {6, 1, 5},
+    {11, 7, 10},  {7, 2, 6},    {10, 6, 9},  {7, 6, 10}};
+// the same tables packed four bits per entry (lane-indexed without memory)
+constexpr uint64_t grid2_pack(const int8_t (*t)[3], int n, int col) {
+  uint64_t v = 0;
+  for (int k = 0; k < n; k++) v |= (uint64_t)t[k][col] << (4 * k);
+  return v;
+}
+constexpr uint64_t kG2TaskPt = grid2_pack(kGrid2Task, 12, 0);
+constexpr uint64_t kG2TaskP = grid2_pack(kGrid2Task, 12, 1);
+constexpr uint64_t kG2TaskQ = grid2_pack(kGrid2Task, 12, 2);
+constexpr uint64_t kG2LeafA = grid2_pack(kGrid2Leaf, 16, 0);
+constexpr uint64_t kG2LeafB = grid2_pack(kGrid2Leaf, 16, 1);
+constexpr uint64_t kG2LeafC = grid2_pack(kGrid2Leaf, 16, 2);
+SCVT_HD int nib(uint64_t v, int k) { return (int)((v >> (4 * k)) & 15); }
+
+// sequential form (host checks): the 15 grid points of (A, B, C)
+SCVT_HD void grid2_points(V3 A, V3 B, V3 C, V3* P) {
+  P[14] = A;
+  P[4] = B;
+  P[0] = C;
+  for (int t = 0; t < 12; t++)
+    P[nib(kG2TaskPt, t)] = normalized_fast(P[nib(kG2TaskP, t)] + P[nib(kG2TaskQ, t)]);
+}
+
 // ------------------------------------------------------------ cube-map grid
 // Each face f = 2k + (sign<0) of the cube [-1,1]^3 carries a gnomonic grid:
 // a point p with depth n = +-p_k > 0 has face coordinates u = p_k+1 / n,

@@ -518,7 +518,46 @@ __device__ inline Acc5 pair_sum5(const Acc5& a, const Acc5& b) {
 }
 
 template <int KIND, bool MIXED>
+__device__ inline void quad_item(const CellArgs& a, V3 A, V3 B, V3 C, V3 z, const DensityF& Df,
+                                 Acc5& part) {
+  if (MIXED) {
+    F3 zc[2];
+    for (int k = 0; k < 2; k++)
+      zc[k] = to_f3(z - V3{a.rho.xc[k][0], a.rho.xc[k][1], a.rho.xc[k][2]});
+    quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), to_f3(z), zc, Df, a.rho, part);
+  } else {
+    quad_tri_k<KIND>(A, B, C, z, a.rho, part);
+  }
+}
+
+// add an item into its cell: f * part with f in {0, 1} adds exactly part or
+// exactly zero, without selecting between accumulators
+__device__ inline void add_item(bool second, const Acc5& part, Acc5& acc0, Acc5& acc1) {
+  const double f0 = second ? 0.0 : 1.0, f1 = 1.0 - f0;
+  acc0.m = fma(f0, part.m, acc0.m);
+  acc0.mx = fma(f0, part.mx, acc0.mx);
+  acc0.my = fma(f0, part.my, acc0.my);
+  acc0.mz = fma(f0, part.mz, acc0.mz);
+  acc0.e = fma(f0, part.e, acc0.e);
+  acc1.m = fma(f1, part.m, acc1.m);
+  acc1.mx = fma(f1, part.mx, acc1.mx);
+  acc1.my = fma(f1, part.my, acc1.my);
+  acc1.mz = fma(f1, part.mz, acc1.mz);
+  acc1.e = fma(f1, part.e, acc1.e);
+}
+
+// Two subdivision levels (the configured rule): the 16 lanes of an edge
+// build the edge's 15-point grid together in LDS -- three lanes the
+// corners, then the 3 level-1 and the 9 level-2 midpoints, one per lane --
+// and each lane reads its leaf's three points, instead of every lane
+// repeating both subdivision levels.
+struct QuadLds {
+  double p[4][15][3];  // per wave: the grids of the round's four edges
+};
+
+template <int KIND, bool MIXED>
 __global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
+  __shared__ QuadLds lds[4];
   const int ln = lane_id();
   const int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;
   if (i0 >= a.n) return;
@@ -534,40 +573,65 @@ __global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
   Acc5 acc0 = {0.0, 0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
   DensityF Df{};
   if (MIXED) Df = density_f32(a.rho);
-  for (int t = ln; t < total; t += 64) {
-    const bool second = t >= tot0;
-    const int local = second ? t - tot0 : t;
-    const int64_t i = second ? i1 : i0;
-    const V3 z = second ? z1 : z0;
-    const int e = local >> (2 * lv), s = local & (per - 1);
-    const double* ed = o.edges + (i * kVmax + e) * 6;
-    V3 A = z;
-    V3 B = V3{ed[0], ed[1], ed[2]};
-    V3 C = V3{ed[3], ed[4], ed[5]};
-    subtriangle(A, B, C, s, lv);
-    Acc5 part = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (MIXED) {
-      F3 zc[2];
-      for (int k = 0; k < 2; k++)
-        zc[k] = to_f3(z - V3{a.rho.xc[k][0], a.rho.xc[k][1], a.rho.xc[k][2]});
-      quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), to_f3(z), zc, Df, a.rho,
-                           part);
-    } else {
-      quad_tri_k<KIND>(A, B, C, z, a.rho, part);
+  if (lv == 2) {
+    double(*G)[3] = lds[threadIdx.x >> 6].p[ln >> 4];  // this lane's edge grid
+    const int s = ln & 15;
+    for (int t0 = 0; t0 < total; t0 += 64) {  // whole edges per round: total = 16 sum(deg)
+      const int t = t0 + ln;
+      const bool valid = t < total;
+      const bool second = t >= tot0;
+      const int local = second ? t - tot0 : t;
+      const int64_t i = second ? i1 : i0;
+      const V3 z = second ? z1 : z0;
+      const int e = local >> 4;
+      if (valid && s < 3) {  // corners A = z (14), B = v_lo (4), C = v_hi (0)
+        const double* ed = o.edges + (i * kVmax + e) * 6;
+        const V3 P = s == 0 ? z : (s == 1 ? V3{ed[0], ed[1], ed[2]} : V3{ed[3], ed[4], ed[5]});
+        const int k = s == 0 ? 14 : (s == 1 ? 4 : 0);
+        G[k][0] = P.x;
+        G[k][1] = P.y;
+        G[k][2] = P.z;
+      }
+      wave_sync();
+      for (int level = 0; level < 2; level++) {
+        const int task = level == 0 ? s : 3 + s;
+        if (valid && s < (level == 0 ? 3 : 9)) {
+          const int kp = nib(kG2TaskP, task), kq = nib(kG2TaskQ, task), km = nib(kG2TaskPt, task);
+          const V3 m = normalized_fast(V3{G[kp][0], G[kp][1], G[kp][2]} +
+                                       V3{G[kq][0], G[kq][1], G[kq][2]});
+          G[km][0] = m.x;
+          G[km][1] = m.y;
+          G[km][2] = m.z;
+        }
+        wave_sync();
+      }
+      if (valid) {
+        const int ka = nib(kG2LeafA, s), kb = nib(kG2LeafB, s), kc = nib(kG2LeafC, s);
+        const V3 A = V3{G[ka][0], G[ka][1], G[ka][2]};
+        const V3 B = V3{G[kb][0], G[kb][1], G[kb][2]};
+        const V3 C = V3{G[kc][0], G[kc][1], G[kc][2]};
+        Acc5 part = {0.0, 0.0, 0.0, 0.0, 0.0};
+        quad_item<KIND, MIXED>(a, A, B, C, z, Df, part);
+        add_item(second, part, acc0, acc1);
+      }
+      wave_sync();  // the next round rewrites the grids
     }
-    // add into the item's cell: f * part with f in {0, 1} adds exactly
-    // part or exactly zero, without selecting between accumulators
-    const double f0 = second ? 0.0 : 1.0, f1 = 1.0 - f0;
-    acc0.m = fma(f0, part.m, acc0.m);
-    acc0.mx = fma(f0, part.mx, acc0.mx);
-    acc0.my = fma(f0, part.my, acc0.my);
-    acc0.mz = fma(f0, part.mz, acc0.mz);
-    acc0.e = fma(f0, part.e, acc0.e);
-    acc1.m = fma(f1, part.m, acc1.m);
-    acc1.mx = fma(f1, part.mx, acc1.mx);
-    acc1.my = fma(f1, part.my, acc1.my);
-    acc1.mz = fma(f1, part.mz, acc1.mz);
-    acc1.e = fma(f1, part.e, acc1.e);
+  } else {
+    for (int t = ln; t < total; t += 64) {
+      const bool second = t >= tot0;
+      const int local = second ? t - tot0 : t;
+      const int64_t i = second ? i1 : i0;
+      const V3 z = second ? z1 : z0;
+      const int e = local >> (2 * lv), s = local & (per - 1);
+      const double* ed = o.edges + (i * kVmax + e) * 6;
+      V3 A = z;
+      V3 B = V3{ed[0], ed[1], ed[2]};
+      V3 C = V3{ed[3], ed[4], ed[5]};
+      subtriangle(A, B, C, s, lv);
+      Acc5 part = {0.0, 0.0, 0.0, 0.0, 0.0};
+      quad_item<KIND, MIXED>(a, A, B, C, z, Df, part);
+      add_item(second, part, acc0, acc1);
+    }
   }
   const Acc5 tot = pair_sum5(acc0, acc1);
   if (ln == 0 || (ln == 32 && has1))  // one code path for both cells

@@ -240,3 +240,29 @@ int hc_exp(int64_t n, const double* t, double* out) {
   return 0;
 }
 }
+
+extern "C" {
+// leaves of two subdivision levels: recursive (subtriangle) and from the
+// shared 15-point grid; out[s * 18 + 0..8] recursive, +9..17 grid
+int hc_leaves2(const double* abc, double* out) {
+  V3 A = V3{abc[0], abc[1], abc[2]}, B = V3{abc[3], abc[4], abc[5]},
+     C = V3{abc[6], abc[7], abc[8]};
+  V3 P[15];
+  grid2_points(A, B, C, P);
+  for (int s = 0; s < 16; s++) {
+    V3 a = A, b = B, c = C;
+    subtriangle(a, b, c, s, 2);
+    V3 g[3] = {P[nib(kG2LeafA, s)], P[nib(kG2LeafB, s)], P[nib(kG2LeafC, s)]};
+    V3 r[3] = {a, b, c};
+    for (int v = 0; v < 3; v++) {
+      out[s * 18 + 3 * v] = r[v].x;
+      out[s * 18 + 3 * v + 1] = r[v].y;
+      out[s * 18 + 3 * v + 2] = r[v].z;
+      out[s * 18 + 9 + 3 * v] = g[v].x;
+      out[s * 18 + 9 + 3 * v + 1] = g[v].y;
+      out[s * 18 + 9 + 3 * v + 2] = g[v].z;
+    }
+  }
+  return 0;
+}
+}

@@ -146,3 +146,11 @@ def exp_tab(t):
     out = np.zeros_like(t)
     lib().hc_exp(ctypes.c_int64(len(t)), P(t), P(out))
     return out
+
+
+def leaves2(A, B, C):
+    abc = np.ascontiguousarray(np.concatenate([A, B, C]), dtype=np.float64)
+    out = np.zeros(16 * 18)
+    lib().hc_leaves2(P(abc), P(out))
+    out = out.reshape(16, 2, 3, 3)
+    return out[:, 0], out[:, 1]

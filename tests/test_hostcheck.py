@@ -242,3 +242,18 @@ def test_exp_table_accuracy():
     rel = np.abs(got - ref) / ref
     assert rel.max() < 5e-16, rel.max()
     assert got[-9] == 1.0 and got[-6] == 1.0  # t = 0 and t = 1e-300
+
+
+def test_grid2_leaves_equal_recursive_subdivision():
+    """The 16 leaves built from the shared 15-point grid are bitwise the
+    leaves of two recursive geodesic subdivisions, in the same vertex order."""
+    rng = np.random.default_rng(12)
+    for k in range(200):
+        z = I.uniform_sphere(1, 100 + k)[0]
+        t = rng.standard_normal((2, 3)) * (10.0 ** rng.uniform(-4, -0.5))
+        B = z + t[0]
+        C = z + t[1]
+        B /= np.linalg.norm(B)
+        C /= np.linalg.norm(C)
+        rec, grid = hc.leaves2(z, B, C)
+        assert np.array_equal(rec, grid)
