@@ -32,19 +32,56 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3  # published, with packed FP32 (not generated he
 PEAK_HBM_GBS = 8000.0
 
 
-def algorithmic_flops_per_point():
-    """FP64 operations of one quadrature point of the tanh density as the
-    formula is written ('Algorithmic work'): multiply, add,
-    divide and square root count 1, fused multiply-add 2; tanh counts as
-    the 20 operations of its exp-based evaluation."""
-    point = 15 + 5 + 1 + 1 + 3 + 2 + 3 + 3 + 5 + 1 + 6 + 2   # position, Jacobian, moments
-    rho = 3 + 5 + 1 + 1 + 1 + 20 + 1 + 2 + 1                  # chord, tanh bump
-    subtri = (2 * 3 * 12 + 22) / 7.0                          # subdivision + Jacobian, per point
-    return point + rho + subtri
+# Algorithmic FP64 operations of the tanh-density quadrature, counted once
+# from the ISA of k_quad<tanh, fp64> as built here (FMA = 2, add/mul = 1,
+# each rsqrt/reciprocal estimate = 1; clamps, rounding and exponent
+# manipulation not counted):
+FLOPS_PER_POINT = 109      # position, Jacobian, chord distance, table exp, logistic, moments
+FLOPS_PER_LEAF = 15 + 21 + 5  # 12 midpoints per 16 leaves (20 each), det Jacobian, 5 sums
+LEAVES_PER_EDGE = 16       # two geodesic subdivision levels
+POINTS_PER_LEAF = 7
 
 
-def cell_flops(mean_degree, levels=2):
-    return mean_degree * (4 ** levels) * 7 * algorithmic_flops_per_point()
+def cell_flops(mean_degree):
+    leaf = POINTS_PER_LEAF * FLOPS_PER_POINT + FLOPS_PER_LEAF
+    return mean_degree * LEAVES_PER_EDGE * leaf
+
+
+# Sources that define the quadrature kernel: the HBM traffic recorded under
+# profiles/ is reported only while these are unchanged.
+QUAD_SOURCES = ["paper_1709_06924_amd/csrc/cells.hip", "paper_1709_06924_amd/csrc/cellgeom.h",
+                "paper_1709_06924_amd/csrc/exp_table.h", "paper_1709_06924_amd/csrc/kernels.h"]
+TRAFFIC_FILE = "profiles/hbm_traffic_k_quad_n1048576_tanh16_fp64.txt"
+
+
+def quad_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in QUAD_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per k_quad dispatch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None
+    when the kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if kv.get("source_sha256") != quad_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def run_gpu(args, precision, Z0_dev, cfg, stream):
@@ -100,11 +137,16 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hash of the quadrature kernel's sources and exit")
     ap.add_argument("--serving-requests", type=int, default=24)
     ap.add_argument("--serving-rate", type=float, default=20.0)
     ap.add_argument("--serving-max-iter", type=int, default=200)
     ap.add_argument("--serving-slots", type=int, default=8)
     args = ap.parse_args()
+    if args.source_hash:
+        print(quad_source_hash())
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")  # 256 MiB
@@ -169,7 +211,7 @@ def main():
         "lbfgs_ms_per_iter": r["lbfgs"]["total_ms"] / max(r["lbfgs"]["launches"], 1),
         "roofline": {"kernel": "k_quad", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": recorded_traffic(),
                      "flops_per_launch": flops, "avg_launch_ms": avg_ms,
                      "mean_degree": r["mean_degree"]},
     }

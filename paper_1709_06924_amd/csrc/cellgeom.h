@@ -259,7 +259,8 @@ SCVT_HD double rsq_pos(double x) {
 // method): t = (64 m + j) ln2/64 + r with |r| <= ln2/128, so
 // exp(t) = 2^m 2^(j/64) exp(r), and exp(r) - 1 is the degree-5 Taylor
 // polynomial (truncation error below 4e-17).  Within about one ulp.
-SCVT_HD double exp_tab(double t) {
+// tab: the 2^(j/64) table or a copy of it (in LDS on the device)
+SCVT_HD double exp_tab(double t, const double* tab = SCVT_EXP2_TAB) {
   const double k = rint(t * kExpInvLn);
   double r = fma(-k, kExpLnHi, t);
   r = fma(-k, kExpLnLo, r);
@@ -271,7 +272,7 @@ SCVT_HD double exp_tab(double t) {
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p *= r;  // exp(r) - 1
-  const double T = kExp2Tab[j];
+  const double T = tab[j];
   return ldexp(fma(T, p, T), m);
 }
 
@@ -304,9 +305,10 @@ SCVT_HD double rcp_refined(double x) {
 // cancel where tanh is close to -1 (far from a bump, where rho ~ gamma).
 // The exponent is clamped to [-708, 700]: below, exp(t) is under 1e-307 and
 // the bump equals amp; above, the bump is below 1e-304 amp.
-SCVT_HD double bump(double amp, double beta, double k2, double d) {
+SCVT_HD double bump(double amp, double beta, double k2, double d,
+                    const double* tab = SCVT_EXP2_TAB) {
   const double t = fmin(fmax((beta - d) * k2, -708.0), 700.0);
-  return amp * rcp_refined(1.0 + exp_tab(t));
+  return amp * rcp_refined(1.0 + exp_tab(t, tab));
 }
 
 // Density variants, each compiled separately so that a kernel carries only
@@ -315,7 +317,7 @@ SCVT_HD double bump(double amp, double beta, double k2, double d) {
 constexpr int kVarGeo = 8, kVarTwo = 16;
 
 template <int KIND>
-SCVT_HD double rho_kind(const DensityP& D, V3 y) {
+SCVT_HD double rho_kind(const DensityP& D, V3 y, const double* tab = SCVT_EXP2_TAB) {
   constexpr int base = KIND & 7;
   if (base == kRhoConst) return 1.0;
   if (base == kRhoTanh) {
@@ -328,7 +330,7 @@ SCVT_HD double rho_kind(const DensityP& D, V3 y) {
       double t2 = dot(t, t);
       double d = t2 * rsq_pos(fmax(t2, 1e-300));  // 0 at t2 = 0
       if (KIND & kVarGeo) d = chord_to_angle(d);
-      rho += bump(D.amp[k], D.beta[k], D.k2[k], d);
+      rho += bump(D.amp[k], D.beta[k], D.k2[k], d, tab);
     }
     return rho;
   }
@@ -347,7 +349,7 @@ SCVT_HD double rho_kind(const DensityP& D, V3 y) {
   double d1 = chord_to_angle(sqrt(dot(t1, t1)));
   double d2 = chord_to_angle(sqrt(dot(t2, t2)));
   double d = sqrt(d1 * d1 / (D.w_lon * D.w_lon) + d2 * d2 / (D.w_lat * D.w_lat));
-  return bump(D.amp[0], D.beta[0], D.k2[0], d) + D.gamma;
+  return bump(D.amp[0], D.beta[0], D.k2[0], d, tab) + D.gamma;
 }
 
 // variant index of a density
@@ -406,7 +408,8 @@ struct Acc5 {
 // (n.p)/|p|^3 with n.p constant = det(A,B,C)/(2 area), so
 //   int_sph f dsigma = det(A,B,C)/2 * sum_q w_q f(p_q/|p_q|) / |p_q|^3.
 template <int KIND>
-SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
+SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
+                        const double* tab = SCVT_EXP2_TAB) {
   // det(A,B,C) = A . ((B-A) x (C-A)): the differences of nearby unit vectors
   // are exact to a rounding, so small sub-triangles keep full relative
   // accuracy (the plain triple product cancels ~log10(1/size) digits)
@@ -418,7 +421,7 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
     double ri = rsq_pos(dot(p, p));
     V3 y = ri * p;
     double jac = ri * ri * ri;
-    double wt = hd * kRule7[q][3] * jac * rho_kind<KIND>(D, y);
+    double wt = hd * kRule7[q][3] * jac * rho_kind<KIND>(D, y, tab);
     V3 dy = y - z;
     acc.m += wt;
     acc.mx += wt * y.x;

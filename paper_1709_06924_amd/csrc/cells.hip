@@ -519,14 +519,14 @@ __device__ inline Acc5 pair_sum5(const Acc5& a, const Acc5& b) {
 
 template <int KIND, bool MIXED>
 __device__ inline void quad_item(const CellArgs& a, V3 A, V3 B, V3 C, V3 z, const DensityF& Df,
-                                 Acc5& part) {
+                                 const double* tab, Acc5& part) {
   if (MIXED) {
     F3 zc[2];
     for (int k = 0; k < 2; k++)
       zc[k] = to_f3(z - V3{a.rho.xc[k][0], a.rho.xc[k][1], a.rho.xc[k][2]});
     quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), to_f3(z), zc, Df, a.rho, part);
   } else {
-    quad_tri_k<KIND>(A, B, C, z, a.rho, part);
+    quad_tri_k<KIND>(A, B, C, z, a.rho, part, tab);
   }
 }
 
@@ -558,6 +558,9 @@ struct QuadLds {
 template <int KIND, bool MIXED>
 __global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
   __shared__ QuadLds lds[4];
+  __shared__ double tab[64];  // the exponential's 2^(j/64) table
+  if (threadIdx.x < 64) tab[threadIdx.x] = kExp2Tab[threadIdx.x];
+  __syncthreads();
   const int ln = lane_id();
   const int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;
   if (i0 >= a.n) return;
@@ -611,7 +614,7 @@ __global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
         const V3 B = V3{G[kb][0], G[kb][1], G[kb][2]};
         const V3 C = V3{G[kc][0], G[kc][1], G[kc][2]};
         Acc5 part = {0.0, 0.0, 0.0, 0.0, 0.0};
-        quad_item<KIND, MIXED>(a, A, B, C, z, Df, part);
+        quad_item<KIND, MIXED>(a, A, B, C, z, Df, tab, part);
         add_item(second, part, acc0, acc1);
       }
       wave_sync();  // the next round rewrites the grids
@@ -629,7 +632,7 @@ __global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
       V3 C = V3{ed[3], ed[4], ed[5]};
       subtriangle(A, B, C, s, lv);
       Acc5 part = {0.0, 0.0, 0.0, 0.0, 0.0};
-      quad_item<KIND, MIXED>(a, A, B, C, z, Df, part);
+      quad_item<KIND, MIXED>(a, A, B, C, z, Df, tab, part);
       add_item(second, part, acc0, acc1);
     }
   }
