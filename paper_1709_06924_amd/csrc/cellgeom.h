@@ -267,11 +267,10 @@ SCVT_HD double exp_tab(double t, const double* tab = SCVT_EXP2_TAB) {
   const int ki = (int)k;
   const int j = ki & 63;
   const int m = ki >> 6;  // floor(ki / 64): arithmetic shift
-  double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
-  p *= r;  // exp(r) - 1
+  // exp(r) - 1 = r + r^2 (1/2 + r/6) + r^4 (1/24 + r/120)
+  const double r2 = r * r;
+  const double lo = fma(r, 1.0 / 6.0, 0.5), hi = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  const double p = fma(r2, fma(r2, hi, lo), r);
   const double T = tab[j];
   return ldexp(fma(T, p, T), m);
 }
@@ -413,11 +412,14 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
   // det(A,B,C) = A . ((B-A) x (C-A)): the differences of nearby unit vectors
   // are exact to a rounding, so small sub-triangles keep full relative
   // accuracy (the plain triple product cancels ~log10(1/size) digits)
-  const double hd = 0.5 * dot(A, cross(B - A, C - A));
+  const V3 BA = B - A, CA = C - A;
+  const double hd = 0.5 * dot(A, cross(BA, CA));
 #pragma unroll 1
   for (int q = 0; q < 7; q++) {
-    const double l0 = kRule7[q][0], l1 = kRule7[q][1], l2 = kRule7[q][2];
-    V3 p = l0 * A + l1 * B + l2 * C;
+    // p = l0 A + l1 B + l2 C with l0 = 1 - l1 - l2
+    const double l1 = kRule7[q][1], l2 = kRule7[q][2];
+    const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
+                    fma(l2, CA.z, fma(l1, BA.z, A.z))};
     double ri = rsq_pos(dot(p, p));
     V3 y = ri * p;
     double jac = ri * ri * ri;
@@ -556,12 +558,15 @@ template <int KIND>
 SCVT_HD void quad_tri_mixed(F3 dA, F3 dB, F3 dC, F3 zf, const F3* zc, const DensityF& D,
                             const DensityP& Dd, Acc5& acc) {
   const F3 A = zf + dA;
-  const float hd = 0.5f * dotf(A, crossf(dB - dA, dC - dA));
+  const F3 dBA = dB - dA, dCA = dC - dA;
+  const float hd = 0.5f * dotf(A, crossf(dBA, dCA));
   float sm = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, se = 0.f;
 #pragma unroll 1
   for (int q = 0; q < 7; q++) {
-    const float l0 = kRule7f[q][0], l1 = kRule7f[q][1], l2 = kRule7f[q][2];
-    F3 d = l0 * dA + l1 * dB + l2 * dC;
+    // d = l0 dA + l1 dB + l2 dC with l0 = 1 - l1 - l2
+    const float l1 = kRule7f[q][1], l2 = kRule7f[q][2];
+    const F3 d = F3{fmaf(l2, dCA.x, fmaf(l1, dBA.x, dA.x)), fmaf(l2, dCA.y, fmaf(l1, dBA.y, dA.y)),
+                    fmaf(l2, dCA.z, fmaf(l1, dBA.z, dA.z))};
     float s = 2.0f * dotf(zf, d) + dotf(d, d);
     float r = rsqf(1.0f + s);
     float rm1 = -s * r * r * rcpf(1.0f + r);

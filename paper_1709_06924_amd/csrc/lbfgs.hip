@@ -277,9 +277,11 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_dir(HistPassArgs a) {
 
 // One block: sums the block partials of each value in block order (wave w
 // takes values w, w+4, ...; lane l blocks l, l+64, ...), then the scalar
-// step of the mode.
+// step of the mode.  The recursions read their operands from LDS (staged by
+// all threads), so the one thread that runs them waits on no global loads.
 __global__ __launch_bounds__(kRedBlock) void k_hist_fin(HistFinArgs a) {
   __shared__ double red[kHVals];
+  __shared__ double sg[kHmax], rr[kHmax], co[kHmax], gm[kHmax][kHmax];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int v = wave; v < a.nvals; v += 4) {
     double x = 0.0;
@@ -287,40 +289,57 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_fin(HistFinArgs a) {
     x = wave_sum64(x);
     if (lane == 0) red[v] = x;
   }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
   double* D = a.dscal;
   const int c = a.c;
-  if (a.mode == kFinPush) {
-    D[kPush] = red[0];
-    D[kPush + 1] = red[1];
-    D[kPush + 2] = red[2];
-    D[kR + a.p] = 1.0 / red[0];
-    D[kSG + a.p] = red[3];
-    for (int j = 0; j < c; j++) {
-      D[kSG + a.slot[j]] = red[4 + 2 * j];
-      a.gram[a.slot[j] * a.stride + a.p] = red[5 + 2 * j];
+  if (a.mode == kFinBackward || a.mode == kFinForward) {
+    for (int t = threadIdx.x; t < c * c; t += blockDim.x) {
+      const int j = t / c, k = t - j * c;
+      gm[j][k] = j < k ? a.gram[a.slot[j] * a.stride + a.slot[k]] : 0.0;  // s_j . y_k, j older
     }
-  } else if (a.mode == kFinDots) {
-    for (int j = 0; j < c; j++) *a.dst[j] = red[j];
-  } else if (a.mode == kFinBackward) {
-    // a_j = r_j (-s_j.g - sum_{k>j} a_k s_j.y_k), newest first
-    for (int j = c - 1; j >= 0; j--) {
-      const int sj = a.slot[j];
-      double t = -D[kSG + sj];
-      for (int k = c - 1; k > j; k--) t = fma(-D[kA + k], a.gram[sj * a.stride + a.slot[k]], t);
-      D[kA + j] = D[kR + sj] * t;
+    if (threadIdx.x < c) {
+      const int sj = a.slot[threadIdx.x];
+      sg[threadIdx.x] = D[kSG + sj];
+      rr[threadIdx.x] = D[kR + sj];
+      co[threadIdx.x] = D[kA + threadIdx.x];
     }
-  } else if (a.mode == kFinForward) {
-    // c_j = a_j - r_j (y_j.r + sum_{k<j} c_k s_k.y_j), oldest first
-    for (int j = 0; j < c; j++) {
-      const int sj = a.slot[j];
-      double t = red[j];
-      for (int k = 0; k < j; k++) t = fma(D[kCoef + k], a.gram[a.slot[k] * a.stride + sj], t);
-      D[kCoef + j] = D[kA + j] - D[kR + sj] * t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (a.mode == kFinPush) {
+      D[kPush] = red[0];
+      D[kPush + 1] = red[1];
+      D[kPush + 2] = red[2];
+      D[kR + a.p] = 1.0 / red[0];
+      D[kSG + a.p] = red[3];
+      for (int j = 0; j < c; j++) {
+        D[kSG + a.slot[j]] = red[4 + 2 * j];
+        a.gram[a.slot[j] * a.stride + a.p] = red[5 + 2 * j];
+      }
+    } else if (a.mode == kFinDots) {
+      for (int j = 0; j < c; j++) *a.dst[j] = red[j];
+    } else if (a.mode == kFinBackward) {
+      // a_j = r_j (-s_j.g - sum_{k>j} a_k s_j.y_k), newest first
+      for (int j = c - 1; j >= 0; j--) {
+        double t = -sg[j];
+        for (int k = c - 1; k > j; k--) t = fma(-co[k], gm[j][k], t);
+        co[j] = rr[j] * t;
+      }
+    } else if (a.mode == kFinForward) {
+      // c_j = a_j - r_j (y_j.r + sum_{k<j} c_k s_k.y_j), oldest first; co
+      // holds a_j and receives c_j
+      for (int j = 0; j < c; j++) {
+        double t = red[j];
+        for (int k = 0; k < j; k++) t = fma(co[k], gm[k][j], t);
+        co[j] = co[j] - rr[j] * t;
+      }
+    } else {
+      D[kGQ] = red[0];
     }
-  } else {
-    D[kGQ] = red[0];
+  }
+  __syncthreads();
+  if (threadIdx.x < c) {
+    if (a.mode == kFinBackward) D[kA + threadIdx.x] = co[threadIdx.x];
+    if (a.mode == kFinForward) D[kCoef + threadIdx.x] = co[threadIdx.x];
   }
 }
 
