@@ -62,6 +62,16 @@ typedef struct scvt_handle scvt_handle;
 
 typedef enum { SCVT_FP64 = 0, SCVT_MIXED = 1 } scvt_precision;
 
+/* Optimiser (section 2.2):
+ *   SCVT_METHOD_PLBFGS -- LBFGS with the Lloyd preconditioner diag(h) as the
+ *                         initial inverse Hessian (section 3.1), the default;
+ *   SCVT_METHOD_LLOYD  -- Lloyd's iteration (section 2.2.1): z <- mu/|mu| for
+ *                         every generator, no line search, no history;
+ *   SCVT_METHOD_LBFGS  -- plain LBFGS with gamma_n I, gamma_n = y.s / y.y of the
+ *                         newest stored pair (section 2.2.2; the identity while
+ *                         no pair is stored), same line search and history. */
+typedef enum { SCVT_METHOD_PLBFGS = 0, SCVT_METHOD_LLOYD = 1, SCVT_METHOD_LBFGS = 2 } scvt_method;
+
 typedef enum {
   SCVT_RHO_CONST = 0, /* rho = 1 */
   SCVT_RHO_TANH = 1,  /* rho = gamma + sum_k amp_k (tanh((beta_k - d_k)/alpha_k) + 1)/2 */
@@ -100,7 +110,7 @@ typedef struct {
                            < 0 = automatic: 0 for FP64, 1e-8 for the mixed path, whose FP32
                            quadrature leaves ~1e-9 relative noise in energy differences */
   int32_t keep_cells;   /* 1: keep a copy of every cell for scvt_get_cells */
-  int32_t reserved;
+  int32_t method;       /* scvt_method (default SCVT_METHOD_PLBFGS) */
   void* hip_stream;     /* hipStream_t to order work on, or NULL */
 } scvt_config;
 
@@ -133,16 +143,25 @@ int scvt_config_init(scvt_config* cfg, int64_t n);
  * *out is NULL on error. */
 int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt_handle** out);
 
-/* One P-LBFGS iteration (two-loop direction, descent check with reset to the
- * Lloyd direction, Armijo line search, history update).  If the line search
- * finds no sufficient decrease in ls_max_evals evaluations, the history is
- * cleared and the Lloyd step (alpha = 1) is taken, which decreases F in
- * exact arithmetic (section 2.2.1).  info may be NULL. */
+/* One iteration of the configured method.  P-LBFGS and LBFGS: two-loop
+ * direction, descent check with reset to the history-free direction, Armijo
+ * line search, history update; if the line search finds no sufficient
+ * decrease in ls_max_evals evaluations, the history is cleared and the Lloyd
+ * step (alpha = 1) is taken, which decreases F in exact arithmetic (section
+ * 2.2.1).  Lloyd: the Lloyd step, one evaluation.  info may be NULL. */
 int scvt_step(scvt_handle* h, scvt_info* info);
 
 /* Iterate until step_inf < tol_step_inf or max_iter iterations in total.
  * Returns SCVT_OK when converged, SCVT_NOT_CONVERGED at the cap, or an error. */
 int scvt_solve(scvt_handle* h, int64_t max_iter, double tol_step_inf, scvt_info* info);
+
+/* scvt_solve with the stopping tests of the paper's method comparison
+ * (section 4.1): stop when max |l_ik| < step_tol, or (quasi-Newton methods
+ * only) |g|_2 / F <= grad_rel_tol, or |F_prev - F| / F_prev < f_rel_tol, or
+ * after max_iter iterations (SCVT_NOT_CONVERGED).  A tolerance <= 0 disables
+ * its test. */
+int scvt_solve_rel(scvt_handle* h, int64_t max_iter, double step_tol, double grad_rel_tol,
+                   double f_rel_tol, scvt_info* info);
 
 /* Cached results at the current generators (no recomputation): F, and
  * optionally per cell mass (n), centroid mu_i/m_i (n x 3) and energy e_i (n).

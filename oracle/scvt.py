@@ -96,10 +96,18 @@ def two_loop(g, h, hist):
 
 
 class Solver:
-    """Lloyd-preconditioned LBFGS (state machine written out plainly)."""
+    """Lloyd-preconditioned LBFGS (state machine written out plainly).
+
+    method: "plbfgs" (section 3.1, initial inverse Hessian diag(h)),
+    "lloyd" (section 2.2.1: every generator moves to its constrained mass
+    centroid mu/|mu|), "lbfgs" (section 2.2.2: initial inverse Hessian
+    gamma_n I with gamma_n = y.s / y.y of the newest stored pair, the
+    identity while none is stored)."""
 
     def __init__(self, Z0, density, m_hist=7, levels=2, ls_max_evals=10, c1=1e-4,
-                 curv_eps=1e-10):
+                 curv_eps=1e-10, method="plbfgs"):
+        assert method in ("plbfgs", "lloyd", "lbfgs")
+        self.method = method
         self.density, self.M, self.levels = density, int(m_hist), levels
         self.ls_max_evals, self.c1, self.curv_eps = ls_max_evals, c1, curv_eps
         self.cur = evaluate(normalize_rows(np.asarray(Z0, dtype=np.float64)), density, levels)
@@ -114,8 +122,16 @@ class Solver:
     def Z(self):
         return self.cur.Z
 
+    def initial_diag(self):
+        if self.method != "lbfgs":
+            return self.cur.h
+        if not self.hist:
+            return np.ones(len(self.cur.h))
+        s, y, r = self.hist[-1]
+        return np.full(len(self.cur.h), dot(y, s) / dot(y, y))
+
     def direction(self):
-        return two_loop(self.cur.g, self.cur.h, self.hist)
+        return two_loop(self.cur.g, self.initial_diag(), self.hist)
 
     def _line_search(self, q, gq):
         alpha = 1.0
@@ -130,11 +146,19 @@ class Solver:
 
     def step(self):
         cur = self.cur
+        if self.method == "lloyd":
+            ev = evaluate(normalize_rows(cur.mu), self.density, self.levels)
+            self.n_evals += 1
+            self.cur = ev
+            self.iter += 1
+            self.last_alpha = 1.0
+            self.history_F.append(ev.F)
+            return ev
         q = self.direction()
         gq = dot(cur.g, q)
         if gq >= 0.0:                                  # not a descent direction
             self.hist = []
-            q = -cur.h[:, None] * cur.g
+            q = -self.initial_diag()[:, None] * cur.g
             gq = dot(cur.g, q)
         alpha, ev = self._line_search(q, gq)
         if ev is None:
@@ -164,6 +188,26 @@ class Solver:
         while self.cur.step_inf >= tol and self.iter < max_iter:
             self.step()
         return self.cur
+
+    def solve_rel(self, max_iter, step_tol=0.0, grad_rel_tol=0.0, f_rel_tol=0.0):
+        """Stopping tests of the method comparison (section 4.1): point
+        movement (the Lloyd step) below step_tol; for the quasi-Newton
+        methods also |g|/F <= grad_rel_tol or |dF|/F < f_rel_tol.  Returns
+        True when a test (not the iteration cap) stopped it."""
+        qn = self.method != "lloyd"
+        F_prev = None
+        while True:
+            c = self.cur
+            if step_tol > 0 and c.step_inf < step_tol:
+                return True
+            if qn and grad_rel_tol > 0 and np.sqrt(dot(c.g, c.g)) / c.F <= grad_rel_tol:
+                return True
+            if qn and f_rel_tol > 0 and F_prev is not None and abs(F_prev - c.F) / F_prev < f_rel_tol:
+                return True
+            if self.iter >= max_iter:
+                return False
+            F_prev = c.F
+            self.step()
 
 
 def local_cell(Z, i, density, radius, levels=2):

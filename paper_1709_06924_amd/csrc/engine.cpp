@@ -50,6 +50,7 @@ struct scvt_handle {
   double* dscal = nullptr;            // device scalars
   double* partials = nullptr;
   double* gram = nullptr;   // s_j . y_k (j older than k) by slot, (M+1)^2
+  double* hgam = nullptr;   // plain LBFGS: gamma_n on every generator
   double* hpart = nullptr;  // block partials of the history passes
   int32_t* fb_list = nullptr;
   int32_t* tier_list[2] = {nullptr, nullptr};
@@ -166,6 +167,7 @@ DensityP to_dev(const scvt_density& d) {
 int validate(const scvt_config* c) {
   if (!c || c->n < 4 || c->n > (int64_t)1 << 28) return SCVT_E_INVALID;  // 3n < 2^31
   if (c->m_hist < 0 || c->m_hist > 60) return SCVT_E_INVALID;
+  if (c->method < SCVT_METHOD_PLBFGS || c->method > SCVT_METHOD_LBFGS) return SCVT_E_INVALID;
   if (c->precision != SCVT_FP64 && c->precision != SCVT_MIXED) return SCVT_E_INVALID;
   if (c->quad_levels < 0 || c->quad_levels > 3) return SCVT_E_INVALID;
   if (c->ls_max_evals < 1 || !(c->ls_c1 > 0.0 && c->ls_c1 < 1.0)) return SCVT_E_INVALID;
@@ -304,7 +306,7 @@ void adopt_trial_scalars(scvt_handle* h) {
 // Up to kHmax pairs: the two recursions run on the history's inner products
 // (s_j.g from the last push, s_j.y_k kept as pairs arrive), so the vectors
 // are streamed twice (q0 pass, direction pass), see lbfgs.h.
-int direction_fused(scvt_handle* h, double* gq) {
+int direction_fused(scvt_handle* h, const double* hv, double* gq) {
   hipStream_t st = h->stream;
   const int64_t n3 = 3 * h->n;
   double* D = h->dscal;
@@ -321,7 +323,7 @@ int direction_fused(scvt_handle* h, double* gq) {
   p.n3 = n3;
   p.c = c;
   p.g = h->cur.g;
-  p.h = h->cur.h;
+  p.h = hv;
   p.partials = h->hpart;
   for (int j = 0; j < c; j++) {
     f.slot[j] = h->ring[j];
@@ -391,10 +393,34 @@ int hist_rebuild(scvt_handle* h) {
   return SCVT_OK;
 }
 
+// y.y of every stored pair (plain LBFGS scaling) after a restored state
+int yy_rebuild(scvt_handle* h) {
+  const int64_t n3 = 3 * h->n;
+  for (int slot : h->ring) {
+    MultiDotArgs m{};
+    m.n3 = n3;
+    m.c = 1;
+    m.A[0] = h->Y + (size_t)slot * n3;
+    m.v = m.A[0];
+    m.partials = h->hpart;
+    HistFinArgs f{};
+    f.mode = kFinDots;
+    f.partials = h->hpart;
+    f.nblocks = hist_grid(n3);
+    f.nvals = 1;
+    f.c = 1;
+    f.dst[0] = h->dscal + kYY + slot;
+    HIPCK(launch_multi_dot(m, h->stream));
+    HIPCK(launch_hist_fin(f, h->stream));
+  }
+  HIPCK(hipStreamSynchronize(h->stream));
+  return SCVT_OK;
+}
+
 // More than kHmax pairs: the two-loop as 2c+1 streaming passes; each pass
 // finishes the previous pass's dot product from its block partials (no
 // separate reduction launch), see lbfgs.hip.
-int direction_passes(scvt_handle* h, double* gq) {
+int direction_passes(scvt_handle* h, const double* hv, double* gq) {
   hipStream_t st = h->stream;
   const int64_t n3 = 3 * h->n;
   double* D = h->dscal;
@@ -409,7 +435,7 @@ int direction_passes(scvt_handle* h, double* gq) {
   base.n3 = n3;
   base.q = h->q;
   base.g = h->cur.g;
-  base.h = h->cur.h;
+  base.h = hv;
   auto run = [&](PassArgs p) -> hipError_t {
     p.partials = pb[1 - cur];
     hipError_t e = launch_lbfgs_pass(p, st);
@@ -475,8 +501,27 @@ int direction_passes(scvt_handle* h, double* gq) {
   return SCVT_OK;
 }
 
+// The initial inverse Hessian's diagonal: the Lloyd preconditioner h, or for
+// plain LBFGS gamma_n = y.s / y.y of the newest stored pair (1 without one).
+const double* initial_diag(scvt_handle* h) {
+  if (h->cfg.method != SCVT_METHOD_LBFGS) return h->cur.h;
+  const int newest = h->ring.empty() ? -1 : h->ring.back();
+  if (launch_fill_gamma(h->hgam, h->n, h->dscal, newest < 0 ? -1 : kR + newest,
+                        newest < 0 ? -1 : kYY + newest, h->stream) != hipSuccess)
+    return nullptr;
+  return h->hgam;
+}
+
 int direction(scvt_handle* h, double* gq) {
-  return h->M <= kHmax ? direction_fused(h, gq) : direction_passes(h, gq);
+  const double* hv = initial_diag(h);
+  if (!hv) return SCVT_E_HIP;
+  return h->M <= kHmax ? direction_fused(h, hv, gq) : direction_passes(h, hv, gq);
+}
+
+// direction with no history and the Lloyd preconditioner: q = -h (.) g, the
+// Lloyd step (z - h g = mu / (mu . z))
+int lloyd_direction(scvt_handle* h, double* gq) {
+  return h->M <= kHmax ? direction_fused(h, h->cur.h, gq) : direction_passes(h, h->cur.h, gq);
 }
 
 // Armijo backtracking along q from the current point; on success the trial
@@ -551,6 +596,8 @@ int push_pair(scvt_handle* h) {
     fa.r_slot = h->dscal + kR + slot;
     HIPCK(launch_finalize(fa, h->stream));
   }
+  HIPCK(hipMemcpyAsync(h->dscal + kYY + slot, h->dscal + kPush + 1, sizeof(double),
+                       hipMemcpyDeviceToDevice, h->stream));
   HIPCK(hipMemcpyAsync(h->pinned + 5, h->dscal + kPush, 3 * sizeof(double), hipMemcpyDeviceToHost,
                        h->stream));
   HIPCK(hipStreamSynchronize(h->stream));
@@ -571,7 +618,23 @@ void clear_history(scvt_handle* h) {
   h->ring.clear();
 }
 
+int lloyd_step(scvt_handle* h) {
+  double gq = 0.0;
+  int rc = lloyd_direction(h, &gq);
+  if (rc) return rc;
+  HIPCK(launch_normalize_trial(h->Z, h->q, 1.0, h->Zt, h->n, h->stream));
+  rc = evaluate(h, h->Zt, h->trial);
+  h->n_evals++;
+  if (rc < 0) return rc;
+  swap_sets(h);
+  adopt_trial_scalars(h);
+  h->alpha = 1.0;
+  h->iter++;
+  return SCVT_OK;
+}
+
 int do_step(scvt_handle* h) {
+  if (h->cfg.method == SCVT_METHOD_LLOYD) return lloyd_step(h);
   double gq = 0.0;
   int rc = direction(h, &gq);
   if (rc) return rc;
@@ -592,7 +655,7 @@ int do_step(scvt_handle* h) {
     // decreases F without a line search (section 2.2.1), and restart the
     // history from there.
     clear_history(h);
-    rc = direction(h, &gq);
+    rc = lloyd_direction(h, &gq);
     if (rc) return rc;
     HIPCK(launch_normalize_trial(h->Z, h->q, 1.0, h->Zt, h->n, h->stream));
     rc = evaluate(h, h->Zt, h->trial);
@@ -656,6 +719,7 @@ int alloc_device_state(scvt_handle* h) {
   ALLOC(h->dscal, kNScal);
   ALLOC(h->partials, kPartTotal * reduce_grid_max());
   ALLOC(h->gram, (size_t)(M + 1) * (M + 1));
+  if (h->cfg.method == SCVT_METHOD_LBFGS) ALLOC(h->hgam, n);
   ALLOC(h->hpart, hist_grid_max());
   ALLOC(h->fb_list, n);
   ALLOC(h->tier_list[0], n);
@@ -804,6 +868,30 @@ int scvt_solve(scvt_handle* h, int64_t max_iter, double tol, scvt_info* info) {
     if (rc) break;
   }
   if (!rc && !(h->step_inf < tol)) rc = SCVT_NOT_CONVERGED;
+  fill_info(h, info, rc);
+  return rc;
+}
+
+int scvt_solve_rel(scvt_handle* h, int64_t max_iter, double step_tol, double grad_rel_tol,
+                   double f_rel_tol, scvt_info* info) {
+  if (!h) return SCVT_E_INVALID;
+  const bool qn = h->cfg.method != SCVT_METHOD_LLOYD;
+  int rc = SCVT_OK;
+  bool done = false;
+  double F_prev = h->F;
+  bool have_prev = false;
+  for (;;) {
+    if (step_tol > 0.0 && h->step_inf < step_tol) done = true;
+    if (qn && grad_rel_tol > 0.0 && sqrt(h->gnorm2) / h->F <= grad_rel_tol) done = true;
+    if (qn && f_rel_tol > 0.0 && have_prev && fabs(F_prev - h->F) / F_prev < f_rel_tol)
+      done = true;
+    if (done || h->iter >= max_iter) break;
+    F_prev = h->F;
+    have_prev = true;
+    rc = do_step(h);
+    if (rc) break;
+  }
+  if (!rc && !done) rc = SCVT_NOT_CONVERGED;
   fill_info(h, info, rc);
   return rc;
 }
@@ -964,6 +1052,7 @@ int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes) {
   int rc = evaluate(h, h->Z, h->cur);
   if (!rc) adopt_trial_scalars(h);
   if (!rc) rc = hist_rebuild(h);
+  if (!rc && h->cfg.method == SCVT_METHOD_LBFGS) rc = yy_rebuild(h);
   return rc;
 }
 

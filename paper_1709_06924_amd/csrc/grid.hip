@@ -22,6 +22,21 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s) 
   return hipGetLastError();
 }
 
+__global__ void k_fill_gamma(double* p, int64_t count, const double* dscal, int r_at, int yy_at) {
+  const double g = r_at < 0 ? 1.0 : 1.0 / (dscal[r_at] * dscal[yy_at]);
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; t < count; t += (int64_t)gridDim.x * blockDim.x) p[t] = g;
+}
+
+hipError_t launch_fill_gamma(double* p, int64_t count, const double* dscal, int r_at, int yy_at,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_fill_gamma<<<(unsigned)blocks, 256, 0, s>>>(p, count, dscal, r_at, yy_at);
+  return hipGetLastError();
+}
+
 // trial point: Zt = normalize(Z + alpha q) (q == nullptr: normalize Z)
 __global__ void k_normalize_trial(const double* __restrict__ Z, const double* __restrict__ q,
                                   double alpha, double* __restrict__ Zt, int64_t n) {

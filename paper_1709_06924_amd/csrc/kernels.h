@@ -84,5 +84,9 @@ hipError_t launch_quad(const CellArgs& a, hipStream_t s);
 hipError_t launch_centroid(const double* mu, const double* m, double* out, int64_t n,
                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
+// p[0..count) = gamma = 1 / (dscal[r_at] * dscal[yy_at]) (y.s / y.y of a stored
+// pair), or 1 when r_at < 0
+hipError_t launch_fill_gamma(double* p, int64_t count, const double* dscal, int r_at, int yy_at,
+                             hipStream_t s);
 
 }  // namespace scvt

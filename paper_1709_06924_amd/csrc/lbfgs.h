@@ -72,6 +72,7 @@ enum : int {
   kPush = 201,  // y.s, y.y, s.s of the last push
   kEval = 204,  // F, max |l|, sum |g|^2, min mu.z
   kSG = 256,    // s.g by slot (g at the current point)
+  kYY = 320,    // y.y by slot (plain LBFGS scaling)
   kNScal = 384
 };
 

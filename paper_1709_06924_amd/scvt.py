@@ -40,7 +40,7 @@ class Config(ctypes.Structure):
                 ("ls_max_evals", ctypes.c_int32), ("ls_c1", ctypes.c_double),
                 ("curv_eps", ctypes.c_double), ("ls_noise", ctypes.c_double),
                 ("keep_cells", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+                ("method", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -61,6 +61,8 @@ _sig = {
     "scvt_create": (ctypes.c_int, [ctypes.POINTER(Config), _vp, ctypes.c_int, ctypes.POINTER(_H)]),
     "scvt_step": (ctypes.c_int, [_H, ctypes.POINTER(Info)]),
     "scvt_solve": (ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(Info)]),
+    "scvt_solve_rel": (ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.POINTER(Info)]),
     "scvt_energy": (ctypes.c_int, [_H, _dp, _vp, _vp, _vp, ctypes.c_int]),
     "scvt_get_generators": (ctypes.c_int, [_H, _vp, ctypes.c_int]),
     "scvt_get_vectors": (ctypes.c_int, [_H, ctypes.c_int, _vp, ctypes.c_int]),
@@ -123,8 +125,12 @@ def density_struct(d):
     return s
 
 
+METHODS = {"plbfgs": 0, "lloyd": 1, "lbfgs": 2}
+
+
 def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_max_evals=10,
-                ls_c1=1e-4, curv_eps=1e-10, keep_cells=False, stream=None, ls_noise=-1.0):
+                ls_c1=1e-4, curv_eps=1e-10, keep_cells=False, stream=None, ls_noise=-1.0,
+                method="plbfgs"):
     c = Config()
     _check(_lib.scvt_config_init(ctypes.byref(c), int(n)), "scvt_config_init")
     c.m_hist = int(m_hist)
@@ -136,6 +142,7 @@ def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_m
     c.curv_eps = float(curv_eps)
     c.ls_noise = float(ls_noise)
     c.keep_cells = 1 if keep_cells else 0
+    c.method = METHODS[method] if isinstance(method, str) else int(method)
     c.hip_stream = stream
     return c
 
@@ -171,7 +178,7 @@ class Solver:
         self.info = Info()
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:  # _lib is None at interpreter exit
             _lib.scvt_destroy(self.h)
             self.h = None
 
@@ -185,6 +192,15 @@ class Solver:
     def solve(self, max_iter, tol):
         rc = _check(_lib.scvt_solve(self.h, int(max_iter), float(tol), ctypes.byref(self.info)),
                     "scvt_solve")
+        d = self.info.as_dict()
+        d["converged"] = rc == SCVT_OK
+        return d
+
+    def solve_rel(self, max_iter, step_tol=0.0, grad_rel_tol=0.0, f_rel_tol=0.0):
+        """Stopping tests of the paper's method comparison (scvt_solve_rel)."""
+        rc = _check(_lib.scvt_solve_rel(self.h, int(max_iter), float(step_tol),
+                                        float(grad_rel_tol), float(f_rel_tol),
+                                        ctypes.byref(self.info)), "scvt_solve_rel")
         d = self.info.as_dict()
         d["converged"] = rc == SCVT_OK
         return d
@@ -315,7 +331,7 @@ class Server:
         return {"waiting": w.value, "running": r.value, "bytes_used": b.value}
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.scvt_server_destroy(self.h)
             self.h = None
 

@@ -1,0 +1,89 @@
+"""Lloyd's method and plain LBFGS on the device against the oracle, and the
+qualitative method comparison of section 4.1."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1709_06924_amd.inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def scvt():
+    from paper_1709_06924_amd import scvt as s
+    return s
+
+
+def test_lloyd_trajectory_matches_oracle(scvt):
+    d = I.density_x3()
+    Z0 = I.uniform_sphere(2562, 24)
+    S = scvt.Solver(Z0, d, method="lloyd")
+    O = oracle.Solver(Z0, d, method="lloyd")
+    for k in range(5):
+        info = S.step()
+        O.step()
+        assert info["alpha"] == 1.0 and info["n_evals"] == k + 2 and info["hist_len"] == 0
+        assert np.max(np.abs(S.generators() - O.Z)) < 1e-13
+        assert abs(info["F"] - O.cur.F) <= 1e-11 * O.cur.F
+
+
+def test_plain_lbfgs_trajectory_matches_oracle(scvt):
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    Z0 = I.uniform_sphere(2562, 25)
+    S = scvt.Solver(Z0, d, method="lbfgs", m_hist=7)
+    O = oracle.Solver(Z0, d, method="lbfgs", m_hist=7)
+    dev = []
+    for _ in range(8):
+        info = S.step()
+        O.step()
+        assert info["alpha"] == O.last_alpha
+        dev.append(np.max(np.abs(S.generators() - O.Z)))
+        assert abs(info["F"] - O.cur.F) <= 1e-10 * O.cur.F
+    print("plain LBFGS trajectory deviation", dev)
+    assert max(dev) < 1e-9
+
+
+def test_plain_lbfgs_resume_bitwise(scvt):
+    d = I.density_x3()
+    Z0 = I.uniform_sphere(3000, 26)
+    A = scvt.Solver(Z0, d, method="lbfgs", m_hist=5)
+    for _ in range(8):
+        A.step()
+    B = scvt.Solver(Z0, d, method="lbfgs", m_hist=5)
+    for _ in range(4):
+        B.step()
+    C = scvt.Solver(Z0, d, method="lbfgs", m_hist=5)
+    C.set_state(B.get_state())
+    for _ in range(4):
+        C.step()
+    assert np.array_equal(C.generators(), A.generators())
+
+
+def test_solve_rel_matches_oracle_stopping(scvt):
+    d = I.density_x3()
+    Z0 = I.uniform_sphere(2562, 27)
+    for method, kw in (("lloyd", dict(step_tol=2e-3)), ("plbfgs", dict(f_rel_tol=1e-3))):
+        S = scvt.Solver(Z0, d, method=method)
+        O = oracle.Solver(Z0, d, method=method)
+        info = S.solve_rel(60, **kw)
+        conv = O.solve_rel(60, **kw)
+        assert info["converged"] == conv and info["iter"] == O.iter
+
+
+def test_method_comparison_x16_x64():
+    """Section 4.1, qualitatively: on a common start, with the paper's
+    stopping tests, Lloyd P-LBFGS needs far fewer iterations than Lloyd's
+    method on the strongly variable densities, and ends at a lower or equal
+    energy than plain LBFGS."""
+    from paper_1709_06924_amd import compare
+    rows = compare.compare(n=2562, seed=31, densities=("x16", "x64"))
+    by = {(r["density"], r["method"]): r for r in rows}
+    for r in rows:
+        print(r)
+    for dn in ("x16", "x64"):
+        lloyd, plain, pl = by[(dn, "lloyd")], by[(dn, "lbfgs")], by[(dn, "plbfgs")]
+        assert pl["iterations"] * 2 < lloyd["iterations"]
+        assert pl["F"] <= plain["F"] * (1 + 1e-3)

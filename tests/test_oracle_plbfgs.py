@@ -158,3 +158,69 @@ def test_line_search_failure_takes_lloyd_step():
             assert len(S.hist) <= 1
     assert S.n_lloyd_fallback >= 1
     assert S.history_F[-1] < S.history_F[0]
+
+
+# ---- the compared methods of section 4.1: Lloyd and plain LBFGS ----
+
+@pytest.mark.parametrize("density", [I.density_x3(),
+                                     I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)])
+def test_lloyd_method_is_the_centroid_map_and_descends(density):
+    """Lloyd's method (section 2.2.1): each iteration moves every generator to
+    its constrained mass centroid mu/|mu| = z + l, and F never increases."""
+    Z = I.uniform_sphere(600, 21)
+    S = oracle.Solver(Z, density, method="lloyd")
+    F = [S.cur.F]
+    for _ in range(5):
+        ev0 = S.cur
+        S.step()
+        target = ev0.mu / np.linalg.norm(ev0.mu, axis=1)[:, None]
+        assert np.array_equal(S.Z, target)
+        assert np.max(np.abs(S.Z - (ev0.Z + ev0.lloyd))) < 1e-15
+        F.append(S.cur.F)
+    assert np.all(np.diff(F) <= 0.0)
+    assert S.n_evals == 6 and S.hist == []
+
+
+@pytest.mark.parametrize("name", ["tetra", "octa", "icosa"])
+def test_platonic_sets_are_lloyd_fixed_points(name):
+    P = I.platonic(name)
+    S = oracle.Solver(P, {"kind": "const"}, method="lloyd")
+    S.step()
+    assert np.max(np.abs(S.Z - P)) < 1e-15
+
+
+def test_plain_lbfgs_scaling_and_first_direction():
+    """Plain LBFGS (section 2.2.2): with no stored pair the direction is -g;
+    afterwards the initial inverse Hessian is gamma_n I with gamma_n =
+    y.s / y.y of the newest pair, and the direction is the dense BFGS
+    product with that H0."""
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    S = oracle.Solver(I.uniform_sphere(400, 22), d, method="lbfgs", m_hist=5)
+    q0 = S.direction()
+    assert np.array_equal(q0, -S.cur.g)
+    for _ in range(4):
+        S.step()
+    assert len(S.hist) >= 1
+    s, y, r = S.hist[-1]
+    gam = np.sum(y * s) / np.sum(y * y)
+    H = dense_bfgs(np.full(3 * len(S.Z), gam), [(a.ravel(), b.ravel(), c) for a, b, c in S.hist])
+    ref = -(H @ S.cur.g.ravel())
+    q = S.direction()
+    assert np.linalg.norm(q.ravel() - ref) <= 1e-11 * np.linalg.norm(ref)
+    # the Lloyd-preconditioned direction differs (diag(h) is not a multiple of I)
+    P = oracle.two_loop(S.cur.g, S.cur.h, S.hist)
+    assert np.linalg.norm(P - q) > 1e-3 * np.linalg.norm(q)
+
+
+def test_solve_rel_stopping_tests():
+    d = I.density_x3()
+    Z = I.uniform_sphere(300, 23)
+    S = oracle.Solver(Z, d, method="plbfgs")
+    assert S.solve_rel(10, grad_rel_tol=1e30) and S.iter == 0        # gradient test first
+    S = oracle.Solver(Z, d, method="plbfgs")
+    assert S.solve_rel(10, f_rel_tol=1.0) and S.iter == 1            # |dF|/F < 1 after one step
+    S = oracle.Solver(Z, d, method="lloyd")
+    assert not S.solve_rel(3, grad_rel_tol=1e30, f_rel_tol=1.0)      # Lloyd: movement test only
+    assert S.iter == 3
+    S = oracle.Solver(Z, d, method="lloyd")
+    assert S.solve_rel(50, step_tol=1.0) and S.iter == 0
