@@ -191,6 +191,40 @@ int scvt_direction(scvt_handle* h, double* out, int on_device, double* gq);
 int scvt_get_cells(scvt_handle* h, int32_t max_deg, int32_t* nbr, int32_t* deg, double* verts,
                    uint8_t* flags);
 
+/* Number of generators of a handle. */
+int scvt_num_generators(scvt_handle* h, int64_t* n);
+
+/* Bisection step of the optimisation-bisection initialisation (section 3.3;
+ * section 4.3 refines a converged 2,562-generator SCVT up to 655,362): the
+ * current generators followed by the normalised midpoint of every Delaunay
+ * edge (i, j) -- generators whose cells share a Voronoi edge -- ordered by i,
+ * then j (i < j).  A spherical triangulation has 3n - 6 edges, so n becomes
+ * 4n - 6.  *n_out receives the new count; z_out (n_out x 3, host, or device
+ * when on_device) may be NULL to query it.  Uses temporary device memory;
+ * the handle's state is unchanged. */
+int scvt_refine(scvt_handle* h, double* z_out, int on_device, int64_t* n_out);
+
+/* The optimisation-bisection driver: create a handle from z0 (cfg0->n
+ * generators), solve it (scvt_solve with max_iter and tol), then `levels`
+ * times refine it (scvt_refine) into a new handle with the same settings
+ * and solve again.  infos (levels + 1 entries, may be NULL) receives each
+ * level's final record; *out the last level's handle (caller destroys).
+ * Returns SCVT_OK, SCVT_NOT_CONVERGED if the last level stopped at max_iter,
+ * or an error (then *out is NULL). */
+int scvt_multilevel(const scvt_config* cfg0, const double* z0, int z0_on_device, int levels,
+                    int64_t max_iter, double tol, scvt_info* infos, scvt_handle** out);
+
+/* Mesh export and quality (sections 3.3 and 4) at the current generators:
+ * the Delaunay triangles, each once as (i, j, k) with i its smallest index,
+ * counter-clockwise seen from outside, ordered by i then j (2n - 4 of them
+ * for points in general position); cellQ = min / max edge of every Voronoi
+ * cell; triQ = (a+b-c)(b+c-a)(c+a-b)/(abc) of every triangle, in the order of
+ * the list.  Lengths are chords.  *ntri receives the triangle count; tri
+ * (ntri x 3), cell_q (n) and tri_q (ntri) are host buffers and may be NULL
+ * (call once with all NULL to size tri and tri_q).  Uses temporary device
+ * memory; the handle's state is unchanged. */
+int scvt_mesh(scvt_handle* h, int32_t* tri, int64_t* ntri, double* cell_q, double* tri_q);
+
 /* Checkpoint: serialise (Z, history ring, counters) into buf.  With buf ==
  * NULL, *bytes receives the size needed.  scvt_set_state restores a state
  * produced by a handle with the same n and M and re-evaluates at Z. */

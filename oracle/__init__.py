@@ -8,6 +8,8 @@ imports the product package.
     voronoi  -- Delaunay triangulation as the convex hull, Voronoi cells
     scvt     -- cell integrals (C, scvt_oracle.c), energy, gradient, Lloyd
                 preconditioner and step, two-loop recursion, P-LBFGS loop
+                (and the compared methods: Lloyd, plain LBFGS)
+    mesh     -- bisection, Delaunay triangle list, cellQ and triQ
 
 Parity notes: every function here is pinned by the `-m "not gpu"` tests
 (closed forms, brute force, invariants); see tests/test_oracle_*.py.
@@ -21,3 +23,4 @@ from ._clib import build  # noqa: F401
 from .scvt import (Evaluation, Solver, cell_integrals, dot, evaluate, local_cell,  # noqa: F401
                    normalize_rows, two_loop)
 from .voronoi import cells, circumcentres, delaunay, neighbour_sets  # noqa: F401
+from . import mesh  # noqa: F401

@@ -283,6 +283,45 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   return SCVT_OK;
 }
 
+// Cells of Zsrc with their neighbour lists written to nbr (n x kVmax, the
+// neighbours of a cell in increasing index order); uses the trial set's
+// buffers, so the current evaluation is left as it is.
+int geometry_with_neighbours(scvt_handle* h, const double* Zsrc, int32_t* nbr) {
+  hipStream_t st = h->stream;
+  HIPCK(launch_fill_i32((int32_t*)h->ctr, 0, sizeof(Counters) / 4, st));
+  HIPCK(launch_grid_build(Zsrc, h->n, h->grid, st));
+  CellArgs a = cell_args(h, Zsrc, h->trial);
+  a.keep_cells = 1;
+  a.out.cell_nbr = nbr;
+  if (h->main_path) {
+    HIPCK(launch_cells_main(a, st));
+    HIPCK(launch_cells_tiers(a, st));
+  }
+  HIPCK(launch_cells_fallback(a, h->main_path ? 0 : 1, st));
+  HIPCK(hipMemcpyAsync(h->pinned + 8, h->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  Counters c;
+  memcpy(&c, h->pinned + 8, sizeof(Counters));
+  if (c.n_duplicate > 0) return SCVT_E_DEGENERATE;
+  if (c.n_error > 0) return SCVT_E_CERT;
+  return SCVT_OK;
+}
+
+// device buffers of one call, freed on every return path
+struct TempBufs {
+  std::vector<void*> p;
+  template <class T>
+  T* get(size_t count) {
+    void* v = nullptr;
+    if (hipMalloc(&v, (count ? count : 1) * sizeof(T)) != hipSuccess) return nullptr;
+    p.push_back(v);
+    return (T*)v;
+  }
+  ~TempBufs() {
+    for (void* v : p) hipFree(v);
+  }
+};
+
 void swap_sets(scvt_handle* h) {
   EvalSet t = h->cur;
   h->cur = h->trial;
@@ -952,6 +991,130 @@ int scvt_direction(scvt_handle* h, double* out, int on_dev, double* gq) {
   if (gq) *gq = v;
   if (out) return scvt_get_vectors(h, 4, out, on_dev);
   return SCVT_OK;
+}
+
+int scvt_num_generators(scvt_handle* h, int64_t* n) {
+  if (!h || !n) return SCVT_E_INVALID;
+  *n = h->n;
+  return SCVT_OK;
+}
+
+int scvt_refine(scvt_handle* h, double* z_out, int on_device, int64_t* n_out) {
+  if (!h || !n_out) return SCVT_E_INVALID;
+  const int64_t n = h->n;
+  hipStream_t st = h->stream;
+  TempBufs t;
+  int32_t* nbr = t.get<int32_t>((size_t)n * kVmax);
+  int32_t* cnt = t.get<int32_t>(n);
+  int32_t* off = t.get<int32_t>(n + 1);
+  int32_t* junk = t.get<int32_t>(n + 1);
+  int32_t* tmp = t.get<int32_t>(scan_tmp_ints(n));
+  if (!nbr || !cnt || !off || !junk || !tmp) return SCVT_E_OOM;
+  int rc = geometry_with_neighbours(h, h->Z, nbr);
+  if (rc) return rc;
+  HIPCK(launch_refine_count(h->trial.deg, nbr, n, cnt, st));
+  HIPCK(launch_scan_pair(cnt, cnt, n, tmp, off, junk, st));
+  int32_t edges = 0;
+  HIPCK(hipMemcpyAsync(&edges, off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  const int64_t m = n + edges;
+  *n_out = m;
+  if (!z_out) return SCVT_OK;
+  double* dst = z_out;
+  if (!on_device) {
+    dst = t.get<double>((size_t)3 * m);
+    if (!dst) return SCVT_E_OOM;
+  }
+  HIPCK(launch_refine_emit(h->Z, h->trial.deg, nbr, off, n, dst, st));
+  if (!on_device)
+    HIPCK(hipMemcpyAsync(z_out, dst, 3 * m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  return SCVT_OK;
+}
+
+int scvt_mesh(scvt_handle* h, int32_t* tri, int64_t* ntri, double* cell_q, double* tri_q) {
+  if (!h || !ntri) return SCVT_E_INVALID;
+  const int64_t n = h->n;
+  hipStream_t st = h->stream;
+  TempBufs t;
+  int32_t* nbr = t.get<int32_t>((size_t)n * kVmax);
+  int32_t* cnt = t.get<int32_t>(n);
+  int32_t* off = t.get<int32_t>(n + 1);
+  int32_t* junk = t.get<int32_t>(n + 1);
+  int32_t* tmp = t.get<int32_t>(scan_tmp_ints(n));
+  if (!nbr || !cnt || !off || !junk || !tmp) return SCVT_E_OOM;
+  int rc = geometry_with_neighbours(h, h->Z, nbr);
+  if (rc) return rc;
+  const double* edges = h->trial.edges;
+  HIPCK(launch_tri_list(h->trial.deg, nbr, edges, n, nullptr, cnt, nullptr, st));
+  HIPCK(launch_scan_pair(cnt, cnt, n, tmp, off, junk, st));
+  int32_t total = 0;
+  HIPCK(hipMemcpyAsync(&total, off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  *ntri = total;
+  if (cell_q) {
+    double* cq = t.get<double>(n);
+    if (!cq) return SCVT_E_OOM;
+    HIPCK(launch_cell_quality(h->trial.deg, edges, n, cq, st));
+    HIPCK(hipMemcpyAsync(cell_q, cq, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  if (tri || tri_q) {
+    int32_t* td = t.get<int32_t>((size_t)3 * total);
+    if (!td) return SCVT_E_OOM;
+    HIPCK(launch_tri_list(h->trial.deg, nbr, edges, n, off, nullptr, td, st));
+    if (tri) HIPCK(hipMemcpyAsync(tri, td, 3 * total * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (tri_q) {
+      double* tq = t.get<double>(total);
+      if (!tq) return SCVT_E_OOM;
+      HIPCK(launch_tri_quality(h->Z, td, total, tq, st));
+      HIPCK(hipMemcpyAsync(tri_q, tq, total * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+  }
+  HIPCK(hipStreamSynchronize(st));
+  return SCVT_OK;
+}
+
+int scvt_multilevel(const scvt_config* cfg0, const double* z0, int z0_on_device, int levels,
+                    int64_t max_iter, double tol, scvt_info* infos, scvt_handle** out) {
+  if (!cfg0 || !z0 || !out || levels < 0 || max_iter < 0) return SCVT_E_INVALID;
+  *out = nullptr;
+  scvt_handle* h = nullptr;
+  int rc = scvt_create(cfg0, z0, z0_on_device, &h);
+  if (rc) return rc;
+  rc = scvt_solve(h, max_iter, tol, infos ? &infos[0] : nullptr);
+  for (int l = 1; l <= levels && rc >= 0; l++) {
+    int64_t m = 0;
+    rc = scvt_refine(h, nullptr, 1, &m);
+    if (rc) break;
+    if (m > ((int64_t)1 << 28)) {
+      rc = SCVT_E_INVALID;
+      break;
+    }
+    double* z = nullptr;
+    if (hipMalloc(&z, 3 * m * sizeof(double)) != hipSuccess) {
+      rc = SCVT_E_OOM;
+      break;
+    }
+    rc = scvt_refine(h, z, 1, &m);
+    scvt_handle* h2 = nullptr;
+    if (!rc) {
+      scvt_config cfg = h->cfg;
+      cfg.n = m;
+      cfg.hip_stream = h->own_stream ? nullptr : h->stream;
+      rc = scvt_create(&cfg, z, 1, &h2);  // synchronises before it returns
+    }
+    hipFree(z);
+    if (rc) break;
+    destroy(h);
+    h = h2;
+    rc = scvt_solve(h, max_iter, tol, infos ? &infos[l] : nullptr);
+  }
+  if (rc < 0) {
+    destroy(h);
+    return rc;
+  }
+  *out = h;
+  return rc;
 }
 
 int scvt_get_cells(scvt_handle* h, int32_t max_deg, int32_t* nbr, int32_t* deg, double* verts,

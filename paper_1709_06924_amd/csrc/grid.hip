@@ -235,6 +235,17 @@ hipError_t launch_centroid(const double* mu, const double* m, double* out, int64
   return hipGetLastError();
 }
 
+hipError_t launch_scan_pair(const int32_t* a, const int32_t* b, int64_t m, int32_t* tmp,
+                            int32_t* oa, int32_t* ob, hipStream_t s) {
+  int64_t ntiles = (m + 1 + kScanTile - 1) / kScanTile;
+  k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, s>>>(a, b, m, tmp);
+  k_scan_sums<<<1, kScanBlock, 0, s>>>(tmp, ntiles);
+  k_scan_apply<<<(unsigned)ntiles, kScanBlock, 0, s>>>(a, b, m, tmp, oa, ob);
+  return hipGetLastError();
+}
+
+int64_t scan_tmp_ints(int64_t m) { return 2 * ((m + 1 + kScanTile - 1) / kScanTile + 1); }
+
 hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s) {
   const int64_t m = gb.g.ncells;
   unsigned nb = (unsigned)((n + 255) / 256);

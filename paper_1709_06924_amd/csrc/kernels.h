@@ -77,6 +77,26 @@ struct CellArgs {
 hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha, double* Zt,
                                   int64_t n, hipStream_t s);
 hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s);
+// exclusive scans of a[0..m) and b[0..m) into oa, ob (m+1 entries each; the
+// last holds the total); tmp holds scan_tmp_ints(m) ints
+hipError_t launch_scan_pair(const int32_t* a, const int32_t* b, int64_t m, int32_t* tmp,
+                            int32_t* oa, int32_t* ob, hipStream_t s);
+int64_t scan_tmp_ints(int64_t m);
+// bisection (n -> n + #edges): cnt[i] = neighbours of i with a larger index
+hipError_t launch_refine_count(const int32_t* deg, const int32_t* nbr, int64_t n, int32_t* cnt,
+                               hipStream_t s);
+// out[0..n) = Z, then normalize(z_i + z_j) for every edge i < j, by i then j,
+// at n + off[i] + t
+// triangle list: cnt[i] (if cnt) = triangles listed by cell i; with tri,
+// they are written at off[i] (3 ints each)
+hipError_t launch_tri_list(const int32_t* deg, const int32_t* nbr, const double* edges, int64_t n,
+                           const int32_t* off, int32_t* cnt, int32_t* tri, hipStream_t s);
+hipError_t launch_cell_quality(const int32_t* deg, const double* edges, int64_t n, double* q,
+                               hipStream_t s);
+hipError_t launch_tri_quality(const double* Z, const int32_t* tri, int64_t ntri, double* q,
+                              hipStream_t s);
+hipError_t launch_refine_emit(const double* Z, const int32_t* deg, const int32_t* nbr,
+                              const int32_t* off, int64_t n, double* out, hipStream_t s);
 hipError_t launch_cells_main(const CellArgs& a, hipStream_t s);
 hipError_t launch_cells_tiers(const CellArgs& a, hipStream_t s);
 hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s);

@@ -73,6 +73,12 @@ _sig = {
     "scvt_set_timing": (ctypes.c_int, [_H, ctypes.c_int]),
     "scvt_kernel_time": (ctypes.c_int, [_H, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int64)]),
     "scvt_destroy": (None, [_H]),
+    "scvt_num_generators": (ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_int64)]),
+    "scvt_refine": (ctypes.c_int, [_H, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
+    "scvt_mesh": (ctypes.c_int, [_H, _vp, ctypes.POINTER(ctypes.c_int64), _vp, _vp]),
+    "scvt_multilevel": (ctypes.c_int, [ctypes.POINTER(Config), _vp, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int64, ctypes.c_double, ctypes.POINTER(Info),
+                                       ctypes.POINTER(_H)]),
     "scvt_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "scvt_footprint": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]),
     "scvt_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_H)]),
@@ -147,6 +153,20 @@ def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_m
     return c
 
 
+def multilevel(z0, density=None, levels=1, max_iter=100, tol=1e-8, **kw):
+    """Optimisation-bisection (scvt_multilevel): solve at z0, then `levels`
+    times refine and solve again.  Returns (Solver of the last level, list
+    of per-level info dicts)."""
+    z0 = np.ascontiguousarray(z0, dtype=np.float64)
+    cfg = make_config(z0.shape[0], density, **kw)
+    infos = (Info * (levels + 1))()
+    h = _H()
+    rc = _lib.scvt_multilevel(ctypes.byref(cfg), z0.ctypes.data_as(ctypes.c_void_p), 0, int(levels),
+                              int(max_iter), float(tol), infos, ctypes.byref(h))
+    _check(rc, "scvt_multilevel")
+    return Solver._adopt(h, cfg), [infos[k].as_dict() for k in range(levels + 1)]
+
+
 def _ptr(x, n_expected=None):
     """(pointer, on_device) for a numpy array or a torch tensor."""
     if isinstance(x, np.ndarray):
@@ -176,6 +196,43 @@ class Solver:
         _check(_lib.scvt_create(ctypes.byref(self.cfg), p, dev, ctypes.byref(h)), "scvt_create")
         self.h = h
         self.info = Info()
+
+    @classmethod
+    def _adopt(cls, h, cfg):
+        """Wrap a handle the library created (scvt_multilevel)."""
+        self = cls.__new__(cls)
+        n = ctypes.c_int64()
+        _check(_lib.scvt_num_generators(h, ctypes.byref(n)), "scvt_num_generators")
+        self.n = n.value
+        self.cfg = cfg
+        self.cfg.n = n.value
+        self._z0 = None
+        self.h = h
+        self.info = Info()
+        return self
+
+    def refine(self):
+        """Bisection: the generators followed by the normalised midpoints of
+        all Delaunay edges (scvt_refine), as an (m, 3) array."""
+        m = ctypes.c_int64()
+        _check(_lib.scvt_refine(self.h, None, 0, ctypes.byref(m)), "scvt_refine")
+        out = np.zeros((m.value, 3))
+        _check(_lib.scvt_refine(self.h, out.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(m)),
+               "scvt_refine")
+        return out
+
+    def mesh(self):
+        """(triangles (ntri, 3) int32, cellQ (n,), triQ (ntri,)) at the
+        current generators (scvt_mesh)."""
+        nt = ctypes.c_int64()
+        _check(_lib.scvt_mesh(self.h, None, ctypes.byref(nt), None, None), "scvt_mesh")
+        tri = np.zeros((nt.value, 3), np.int32)
+        cq = np.zeros(self.n)
+        tq = np.zeros(nt.value)
+        _check(_lib.scvt_mesh(self.h, tri.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nt),
+                              cq.ctypes.data_as(ctypes.c_void_p), tq.ctypes.data_as(ctypes.c_void_p)),
+               "scvt_mesh")
+        return tri, cq, tq
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:  # _lib is None at interpreter exit
