@@ -24,7 +24,10 @@
  *     the sphere by radial projection, whose exact Jacobian gives
  *       int_sph f dsigma = 1/2 det(A,B,C) * sum_q w_q f(p_q/|p_q|) / |p_q|^3,
  *     p_q = sum of barycentric weights times (A,B,C);
- *   - the planar rule is Radon's 7-point degree-5 rule (Stroud T2:5-1).
+ *   - the planar rule is Radon's 7-point degree-5 rule (Stroud T2:5-1) by
+ *     default, or a rule passed in (oracle_rule: barycentric points and
+ *     weights summing to one), e.g. the conical product rules of 4 and 9
+ *     points built by oracle/rules.py.
  *
  * Densities (section 4): constant; the tanh bump family with the prefactor
  * read as (1-gamma)/2 (the printed 1/(2(1-gamma)) cannot give a density whose
@@ -77,6 +80,15 @@ void oracle_rule7(double lam[21], double w[7]) {
   }
 }
 
+/* A triangle rule: nq points (barycentric lam[3q..3q+2]) and weights w[q]
+ * summing to one.  NULL means Radon's rule. */
+typedef struct {
+  int32_t nq;
+  int32_t pad;
+  double lam[3 * 16];
+  double w[16];
+} oracle_rule;
+
 /* ------------------------------------------------------------- density --- */
 
 static double dot3(const double *a, const double *b) {
@@ -110,6 +122,12 @@ static void from_latlon(double lat, double lon, double *out) {
   out[2] = sin(lat);
 }
 
+/* (tanh(x) + 1) / 2 of the section-4 bump, in the equal form 1/(1 + e^{-2x}):
+ * tanh(x) + 1 cancels to a few digits where the bump is far below 1, and the
+ * density's floor gamma can be as small as 64^-4 (X64), so the tanh form
+ * would carry errors of ~1e-9 relative into rho there. */
+static double half_tanh_plus_one(double x) { return 1.0 / (1.0 + exp(-2.0 * x)); }
+
 double oracle_rho(const oracle_density *D, const double *y) {
   switch (D->kind) {
     case ORACLE_RHO_CONST:
@@ -119,7 +137,7 @@ double oracle_rho(const oracle_density *D, const double *y) {
       for (int k = 0; k < D->nbumps; k++) {
         double d = chord(y, D->xc[k]);
         if (D->geodesic) d = chord_to_angle(d);
-        rho += D->amp[k] * 0.5 * (tanh((D->beta[0 + k] - d) / D->alpha[k]) + 1.0);
+        rho += D->amp[k] * half_tanh_plus_one((D->beta[k] - d) / D->alpha[k]);
       }
       return rho;
     }
@@ -138,7 +156,7 @@ double oracle_rho(const oracle_density *D, const double *y) {
       double d1 = chord_to_angle(chord(y, zic));
       double d2 = chord_to_angle(chord(y, zci));
       double d = sqrt(d1 * d1 / (D->w_lon * D->w_lon) + d2 * d2 / (D->w_lat * D->w_lat));
-      return D->amp[0] * 0.5 * (tanh((D->beta[0] - d) / D->alpha[0]) + 1.0) + D->gamma;
+      return D->amp[0] * half_tanh_plus_one((D->beta[0] - d) / D->alpha[0]) + D->gamma;
     }
   }
   return NAN;
@@ -171,17 +189,20 @@ static double det3(const double *a, const double *b, const double *c) {
 
 /* Integrate rho, y rho and |y - z|^2 rho over the spherical triangle (A,B,C)
  * with the radial-projection rule (no subdivision). */
-static void tri_rule(const oracle_density *D, const double *z, const double *A,
-                     const double *B, const double *C, acc5 *acc) {
-  double lam[21], w[7];
-  oracle_rule7(lam, w);
+static void tri_rule(const oracle_density *D, const oracle_rule *R, const double *z,
+                     const double *A, const double *B, const double *C, acc5 *acc) {
+  double lam7[21], w7[7];
+  oracle_rule7(lam7, w7);
+  const int nq = R ? R->nq : 7;
+  const double *lam = R ? R->lam : lam7;
+  const double *w = R ? R->w : w7;
   /* det(A,B,C) = det(A, B-A, C-A): the same value, computed from the
    * differences of the nearby vertices so that small sub-triangles do not
    * lose digits to cancellation */
   double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
   double v[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
   double half_det = 0.5 * det3(A, u, v);
-  for (int q = 0; q < 7; q++) {
+  for (int q = 0; q < nq; q++) {
     double p[3];
     for (int k = 0; k < 3; k++)
       p[k] = lam[3 * q + 0] * A[k] + lam[3 * q + 1] * B[k] + lam[3 * q + 2] * C[k];
@@ -201,28 +222,30 @@ static void tri_rule(const oracle_density *D, const double *z, const double *A,
 
 /* Split (A,B,C) into four by geodesic midpoints `levels` times, then apply
  * the rule on every leaf. */
-static void tri_subdivide(const oracle_density *D, const double *z, const double *A,
-                          const double *B, const double *C, int levels, acc5 *acc) {
+static void tri_subdivide(const oracle_density *D, const oracle_rule *R, const double *z,
+                          const double *A, const double *B, const double *C, int levels,
+                          acc5 *acc) {
   if (levels == 0) {
-    tri_rule(D, z, A, B, C, acc);
+    tri_rule(D, R, z, A, B, C, acc);
     return;
   }
   double ab[3], bc[3], ca[3];
   midpoint(A, B, ab);
   midpoint(B, C, bc);
   midpoint(C, A, ca);
-  tri_subdivide(D, z, A, ab, ca, levels - 1, acc);
-  tri_subdivide(D, z, ab, B, bc, levels - 1, acc);
-  tri_subdivide(D, z, ca, bc, C, levels - 1, acc);
-  tri_subdivide(D, z, ab, bc, ca, levels - 1, acc);
+  tri_subdivide(D, R, z, A, ab, ca, levels - 1, acc);
+  tri_subdivide(D, R, z, ab, B, bc, levels - 1, acc);
+  tri_subdivide(D, R, z, ca, bc, C, levels - 1, acc);
+  tri_subdivide(D, R, z, ab, bc, ca, levels - 1, acc);
 }
 
 /* One spherical triangle, exposed for the closed-form tests.
  * out[0]=mass, out[1..3]=moment, out[4]=energy about z. */
 void oracle_triangle_integrals(const oracle_density *D, const double *z, const double *A,
-                               const double *B, const double *C, int levels, double *out) {
+                               const double *B, const double *C, int levels,
+                               const oracle_rule *R, double *out) {
   acc5 acc = {0.0, {0.0, 0.0, 0.0}, 0.0};
-  tri_subdivide(D, z, A, B, C, levels, &acc);
+  tri_subdivide(D, R, z, A, B, C, levels, &acc);
   out[0] = acc.m;
   out[1] = acc.mu[0];
   out[2] = acc.mu[1];
@@ -237,8 +260,8 @@ void oracle_triangle_integrals(const oracle_density *D, const double *z, const d
  * outside the sphere.  Output per cell: mass m[i], moment mu[3i..3i+2],
  * energy e[i].  Returns 0. */
 int oracle_cell_integrals(int64_t n, const double *Z, const int64_t *ptr, const double *V,
-                          const oracle_density *D, int levels, double *m, double *mu,
-                          double *e) {
+                          const oracle_density *D, int levels, const oracle_rule *R, double *m,
+                          double *mu, double *e) {
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < n; i++) {
     const double *z = Z + 3 * i;
@@ -247,7 +270,7 @@ int oracle_cell_integrals(int64_t n, const double *Z, const int64_t *ptr, const 
     for (int64_t k = 0; k < deg; k++) {
       const double *v0 = V + 3 * (b + k);
       const double *v1 = V + 3 * (b + (k + 1) % deg);
-      tri_subdivide(D, z, z, v0, v1, levels, &acc);
+      tri_subdivide(D, R, z, z, v0, v1, levels, &acc);
     }
     m[i] = acc.m;
     mu[3 * i + 0] = acc.mu[0];
