@@ -14,7 +14,8 @@
  *      security-radius certificate, sequential fallback);
  *   2. per cell: m_i = int rho, mu_i = int y rho (the paper's c_i),
  *      e_i = int |y - z_i|^2 rho  (fan triangles, geodesic subdivision,
- *      7-point rule through the radial-projection Jacobian);
+ *      a triangle rule (7 points by default) through the radial-projection
+ *      Jacobian);
  *   3. g_i = 2 (mu_i . z_i) z_i - 2 mu_i   (tangential gradient),
  *      h_i = 1 / (2 mu_i . z_i)            (spherical Lloyd preconditioner),
  *      l_i = mu_i/|mu_i| - z_i             (Lloyd step);
@@ -111,6 +112,10 @@ typedef struct {
                            quadrature leaves ~1e-9 relative noise in energy differences */
   int32_t keep_cells;   /* 1: keep a copy of every cell for scvt_get_cells */
   int32_t method;       /* scvt_method (default SCVT_METHOD_PLBFGS) */
+  int32_t quad_rule;    /* points of the triangle rule: 7 (Radon, degree 5; default), or the
+                           conical product rules of the sizes section 4.1 uses: 4 (degree 3),
+                           9 (degree 5) */
+  int32_t reserved;
   void* hip_stream;     /* hipStream_t to order work on, or NULL */
 } scvt_config;
 

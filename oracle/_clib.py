@@ -45,6 +45,22 @@ def build(force=False):
     return _LIB
 
 
+class CRule(ctypes.Structure):
+    _fields_ = [("nq", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("lam", ctypes.c_double * 48), ("w", ctypes.c_double * 16)]
+
+
+def crule(lam, w):
+    """A rule as the C struct: lam (nq, 3) barycentric points, w (nq,)."""
+    r = CRule()
+    r.nq = len(w)
+    for q in range(len(w)):
+        for k in range(3):
+            r.lam[3 * q + k] = float(lam[q][k])
+        r.w[q] = float(w[q])
+    return r
+
+
 _lib = None
 
 
@@ -59,9 +75,10 @@ def lib():
         L.oracle_rho.restype = ctypes.c_double
         L.oracle_rho_many.argtypes = [ctypes.POINTER(CDensity), ctypes.c_int64, dp, dp]
         L.oracle_triangle_integrals.argtypes = [ctypes.POINTER(CDensity), dp, dp, dp, dp,
-                                                ctypes.c_int, dp]
+                                                ctypes.c_int, ctypes.POINTER(CRule), dp]
         L.oracle_cell_integrals.argtypes = [ctypes.c_int64, dp, ctypes.POINTER(ctypes.c_int64), dp,
-                                            ctypes.POINTER(CDensity), ctypes.c_int, dp, dp, dp]
+                                            ctypes.POINTER(CDensity), ctypes.c_int,
+                                            ctypes.POINTER(CRule), dp, dp, dp]
         L.oracle_cell_integrals.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L

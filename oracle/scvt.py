@@ -36,8 +36,10 @@ def normalize_rows(X):
     return X / np.linalg.norm(X, axis=1)[:, None]
 
 
-def cell_integrals(C, density, levels=2):
-    """m (n,), mu (n,3), e (n,) for the cells C (oracle.voronoi.Cells)."""
+def cell_integrals(C, density, levels=2, rule=7):
+    """m (n,), mu (n,3), e (n,) for the cells C (oracle.voronoi.Cells), with
+    the triangle rule of `rule` points (oracle.rules)."""
+    from .rules import crule
     L = _clib.lib()
     n = len(C.ptr) - 1
     Z = np.ascontiguousarray(C.Z, dtype=np.float64)
@@ -49,7 +51,8 @@ def cell_integrals(C, density, levels=2):
     D = _clib.cdensity(density)
     import ctypes
     rc = L.oracle_cell_integrals(n, _clib.ptr(Z), ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                 _clib.ptr(V), ctypes.byref(D), int(levels), _clib.ptr(m),
+                                 _clib.ptr(V), ctypes.byref(D), int(levels),
+                                 ctypes.byref(crule(rule)), _clib.ptr(m),
                                  _clib.ptr(mu), _clib.ptr(e))
     assert rc == 0
     return m, mu, e
@@ -69,10 +72,10 @@ class Evaluation:
         self.centroid = mu / m[:, None]
 
 
-def evaluate(Z, density, levels=2):
+def evaluate(Z, density, levels=2, rule=7):
     Z = np.ascontiguousarray(Z, dtype=np.float64)
     C = _cells(Z)
-    m, mu, e = cell_integrals(C, density, levels)
+    m, mu, e = cell_integrals(C, density, levels, rule)
     return Evaluation(Z, C, m, mu, e)
 
 
@@ -105,12 +108,13 @@ class Solver:
     identity while none is stored)."""
 
     def __init__(self, Z0, density, m_hist=7, levels=2, ls_max_evals=10, c1=1e-4,
-                 curv_eps=1e-10, method="plbfgs"):
+                 curv_eps=1e-10, method="plbfgs", rule=7):
         assert method in ("plbfgs", "lloyd", "lbfgs")
         self.method = method
+        self.rule = rule
         self.density, self.M, self.levels = density, int(m_hist), levels
         self.ls_max_evals, self.c1, self.curv_eps = ls_max_evals, c1, curv_eps
-        self.cur = evaluate(normalize_rows(np.asarray(Z0, dtype=np.float64)), density, levels)
+        self.cur = evaluate(normalize_rows(np.asarray(Z0, dtype=np.float64)), density, levels, rule)
         self.hist = []
         self.iter = 0
         self.n_evals = 1
@@ -137,7 +141,7 @@ class Solver:
         alpha = 1.0
         for _ in range(self.ls_max_evals):
             Zt = normalize_rows(self.cur.Z + alpha * q)
-            ev = evaluate(Zt, self.density, self.levels)
+            ev = evaluate(Zt, self.density, self.levels, self.rule)
             self.n_evals += 1
             if ev.F <= self.cur.F + self.c1 * alpha * gq:
                 return alpha, ev
@@ -147,7 +151,7 @@ class Solver:
     def step(self):
         cur = self.cur
         if self.method == "lloyd":
-            ev = evaluate(normalize_rows(cur.mu), self.density, self.levels)
+            ev = evaluate(normalize_rows(cur.mu), self.density, self.levels, self.rule)
             self.n_evals += 1
             self.cur = ev
             self.iter += 1
@@ -167,7 +171,7 @@ class Solver:
             # line search (section 2.2.1), and restart the history
             self.hist = []
             q = -cur.h[:, None] * cur.g
-            ev = evaluate(normalize_rows(cur.Z + q), self.density, self.levels)
+            ev = evaluate(normalize_rows(cur.Z + q), self.density, self.levels, self.rule)
             self.n_evals += 1
             alpha = 1.0
             self.n_lloyd_fallback += 1

@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include "exp_table.h"
+#include "rules.h"
 
 #define SCVT_HD __host__ __device__ inline
 
@@ -378,26 +379,38 @@ SCVT_HD double rho_eval(const DensityP& D, V3 y) {
 }
 
 // ------------------------------------------------------------- quadrature
-// Radon's 7-point degree-5 rule (Stroud T2:5-1): barycentric coordinates and
-// weight per row, weights summing to 1.
-#define SCVT_A1 0.10128650732345634
-#define SCVT_A2 0.4701420641051151
-#define SCVT_W1 0.12593918054482714
-#define SCVT_W2 0.1323941527885062
-#define SCVT_B1 (1.0 - 2.0 * SCVT_A1)
-#define SCVT_B2 (1.0 - 2.0 * SCVT_A2)
-__host__ __device__ constexpr double kRule7[7][4] = {
-    {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0, 9.0 / 40.0}, {SCVT_B1, SCVT_A1, SCVT_A1, SCVT_W1},
-    {SCVT_A1, SCVT_B1, SCVT_A1, SCVT_W1},          {SCVT_A1, SCVT_A1, SCVT_B1, SCVT_W1},
-    {SCVT_B2, SCVT_A2, SCVT_A2, SCVT_W2},          {SCVT_A2, SCVT_B2, SCVT_A2, SCVT_W2},
-    {SCVT_A2, SCVT_A2, SCVT_B2, SCVT_W2}};
-
-// the rule rounded to FP32 for the mixed-precision points
-__host__ __device__ constexpr float kRule7f[7][4] = {
-#define SCVT_F(r) {(float)kRule7[r][0], (float)kRule7[r][1], (float)kRule7[r][2], (float)kRule7[r][3]}
-    SCVT_F(0), SCVT_F(1), SCVT_F(2), SCVT_F(3), SCVT_F(4), SCVT_F(5), SCVT_F(6)
-#undef SCVT_F
-};
+// Triangle rules (rules.h, weights summing to 1): Radon's 7-point degree-5
+// rule (the configured one) and the 4- and 9-point conical product rules of
+// degrees 3 and 5 (the sizes the paper uses, section 4.1).  The FP32 copies
+// serve the mixed-precision points.
+#define SCVT_RULE_F(T, r) {(float)T[r][0], (float)T[r][1], (float)T[r][2], (float)T[r][3]}
+__device__ constexpr float kRule7f[7][4] = {
+    SCVT_RULE_F(kRule7, 0), SCVT_RULE_F(kRule7, 1), SCVT_RULE_F(kRule7, 2),
+    SCVT_RULE_F(kRule7, 3), SCVT_RULE_F(kRule7, 4), SCVT_RULE_F(kRule7, 5),
+    SCVT_RULE_F(kRule7, 6)};
+__device__ constexpr float kRule4f[4][4] = {SCVT_RULE_F(kRule4, 0), SCVT_RULE_F(kRule4, 1),
+                                            SCVT_RULE_F(kRule4, 2), SCVT_RULE_F(kRule4, 3)};
+__device__ constexpr float kRule9f[9][4] = {
+    SCVT_RULE_F(kRule9, 0), SCVT_RULE_F(kRule9, 1), SCVT_RULE_F(kRule9, 2),
+    SCVT_RULE_F(kRule9, 3), SCVT_RULE_F(kRule9, 4), SCVT_RULE_F(kRule9, 5),
+    SCVT_RULE_F(kRule9, 6), SCVT_RULE_F(kRule9, 7), SCVT_RULE_F(kRule9, 8)};
+constexpr float kRule7fHost[7][4] = {
+    SCVT_RULE_F(kRule7Host, 0), SCVT_RULE_F(kRule7Host, 1), SCVT_RULE_F(kRule7Host, 2),
+    SCVT_RULE_F(kRule7Host, 3), SCVT_RULE_F(kRule7Host, 4), SCVT_RULE_F(kRule7Host, 5),
+    SCVT_RULE_F(kRule7Host, 6)};
+constexpr float kRule4fHost[4][4] = {SCVT_RULE_F(kRule4Host, 0), SCVT_RULE_F(kRule4Host, 1),
+                                     SCVT_RULE_F(kRule4Host, 2), SCVT_RULE_F(kRule4Host, 3)};
+constexpr float kRule9fHost[9][4] = {
+    SCVT_RULE_F(kRule9Host, 0), SCVT_RULE_F(kRule9Host, 1), SCVT_RULE_F(kRule9Host, 2),
+    SCVT_RULE_F(kRule9Host, 3), SCVT_RULE_F(kRule9Host, 4), SCVT_RULE_F(kRule9Host, 5),
+    SCVT_RULE_F(kRule9Host, 6), SCVT_RULE_F(kRule9Host, 7), SCVT_RULE_F(kRule9Host, 8)};
+#undef SCVT_RULE_F
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SCVT_RULE_TABLE_F(nq) ((nq) == 4 ? kRule4f : ((nq) == 9 ? kRule9f : kRule7f))
+#else
+#define SCVT_RULE_TABLE_F(nq) ((nq) == 4 ? kRule4fHost : ((nq) == 9 ? kRule9fHost : kRule7fHost))
+#endif
+SCVT_HD bool valid_rule(int nq) { return nq == 4 || nq == 7 || nq == 9; }
 
 struct Acc5 {
   double m, mx, my, mz, e;
@@ -408,22 +421,23 @@ struct Acc5 {
 //   int_sph f dsigma = det(A,B,C)/2 * sum_q w_q f(p_q/|p_q|) / |p_q|^3.
 template <int KIND>
 SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
-                        const double* tab = SCVT_EXP2_TAB) {
+                        const double* tab = SCVT_EXP2_TAB, int nq = 7) {
+  const double(*R)[4] = SCVT_RULE_TABLE(nq);
   // det(A,B,C) = A . ((B-A) x (C-A)): the differences of nearby unit vectors
   // are exact to a rounding, so small sub-triangles keep full relative
   // accuracy (the plain triple product cancels ~log10(1/size) digits)
   const V3 BA = B - A, CA = C - A;
   const double hd = 0.5 * dot(A, cross(BA, CA));
 #pragma unroll 1
-  for (int q = 0; q < 7; q++) {
+  for (int q = 0; q < nq; q++) {
     // p = l0 A + l1 B + l2 C with l0 = 1 - l1 - l2
-    const double l1 = kRule7[q][1], l2 = kRule7[q][2];
+    const double l1 = R[q][1], l2 = R[q][2];
     const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
                     fma(l2, CA.z, fma(l1, BA.z, A.z))};
     double ri = rsq_pos(dot(p, p));
     V3 y = ri * p;
     double jac = ri * ri * ri;
-    double wt = hd * kRule7[q][3] * jac * rho_kind<KIND>(D, y, tab);
+    double wt = hd * R[q][3] * jac * rho_kind<KIND>(D, y, tab);
     V3 dy = y - z;
     acc.m += wt;
     acc.mx += wt * y.x;
@@ -433,8 +447,8 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
   }
 }
 
-SCVT_HD void quad_tri(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc) {
-#define SCVT_QUAD_CALL(V) quad_tri_k<V>(A, B, C, z, D, acc)
+SCVT_HD void quad_tri(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc, int nq = 7) {
+#define SCVT_QUAD_CALL(V) quad_tri_k<V>(A, B, C, z, D, acc, SCVT_EXP2_TAB, nq)
   SCVT_RHO_DISPATCH(rho_variant(D), SCVT_QUAD_CALL)
 #undef SCVT_QUAD_CALL
 }
@@ -556,15 +570,16 @@ SCVT_HD float rho_kind_f(const DensityF& D, const F3* zc, F3 zf, F3 dyz, const D
 // int rho (y - z) (in mx, my, mz) and e into the FP64 accumulator
 template <int KIND>
 SCVT_HD void quad_tri_mixed(F3 dA, F3 dB, F3 dC, F3 zf, const F3* zc, const DensityF& D,
-                            const DensityP& Dd, Acc5& acc) {
+                            const DensityP& Dd, Acc5& acc, int nq = 7) {
+  const float(*R)[4] = SCVT_RULE_TABLE_F(nq);
   const F3 A = zf + dA;
   const F3 dBA = dB - dA, dCA = dC - dA;
   const float hd = 0.5f * dotf(A, crossf(dBA, dCA));
   float sm = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, se = 0.f;
 #pragma unroll 1
-  for (int q = 0; q < 7; q++) {
+  for (int q = 0; q < nq; q++) {
     // d = l0 dA + l1 dB + l2 dC with l0 = 1 - l1 - l2
-    const float l1 = kRule7f[q][1], l2 = kRule7f[q][2];
+    const float l1 = R[q][1], l2 = R[q][2];
     const F3 d = F3{fmaf(l2, dCA.x, fmaf(l1, dBA.x, dA.x)), fmaf(l2, dCA.y, fmaf(l1, dBA.y, dA.y)),
                     fmaf(l2, dCA.z, fmaf(l1, dBA.z, dA.z))};
     float s = 2.0f * dotf(zf, d) + dotf(d, d);
@@ -572,7 +587,7 @@ SCVT_HD void quad_tri_mixed(F3 dA, F3 dB, F3 dC, F3 zf, const F3* zc, const Dens
     float rm1 = -s * r * r * rcpf(1.0f + r);
     F3 dyz = r * d + rm1 * zf;
     float jac = r * r * r;
-    float wt = hd * kRule7f[q][3] * jac * rho_kind_f<KIND>(D, zc, zf, dyz, Dd);
+    float wt = hd * R[q][3] * jac * rho_kind_f<KIND>(D, zc, zf, dyz, Dd);
     sm += wt;
     sx += wt * dyz.x;
     sy += wt * dyz.y;

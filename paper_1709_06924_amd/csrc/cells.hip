@@ -524,9 +524,10 @@ __device__ inline void quad_item(const CellArgs& a, V3 A, V3 B, V3 C, V3 z, cons
     F3 zc[2];
     for (int k = 0; k < 2; k++)
       zc[k] = to_f3(z - V3{a.rho.xc[k][0], a.rho.xc[k][1], a.rho.xc[k][2]});
-    quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), to_f3(z), zc, Df, a.rho, part);
+    quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), to_f3(z), zc, Df, a.rho, part,
+                         a.quad_rule);
   } else {
-    quad_tri_k<KIND>(A, B, C, z, a.rho, part, tab);
+    quad_tri_k<KIND>(A, B, C, z, a.rho, part, tab, a.quad_rule);
   }
 }
 

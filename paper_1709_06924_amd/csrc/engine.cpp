@@ -170,6 +170,7 @@ int validate(const scvt_config* c) {
   if (c->method < SCVT_METHOD_PLBFGS || c->method > SCVT_METHOD_LBFGS) return SCVT_E_INVALID;
   if (c->precision != SCVT_FP64 && c->precision != SCVT_MIXED) return SCVT_E_INVALID;
   if (c->quad_levels < 0 || c->quad_levels > 3) return SCVT_E_INVALID;
+  if (c->quad_rule != 4 && c->quad_rule != 7 && c->quad_rule != 9) return SCVT_E_INVALID;
   if (c->ls_max_evals < 1 || !(c->ls_c1 > 0.0 && c->ls_c1 < 1.0)) return SCVT_E_INVALID;
   if (!(c->curv_eps >= 0.0)) return SCVT_E_INVALID;
   const scvt_density& d = c->rho;
@@ -194,6 +195,7 @@ CellArgs cell_args(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   a.levels = h->cfg.quad_levels;
   a.keep_cells = h->cfg.keep_cells;
   a.mixed = h->cfg.precision == SCVT_MIXED;
+  a.quad_rule = h->cfg.quad_rule;
   a.out.m = s.m;
   a.out.mu = s.mu;
   a.out.e = s.e;
@@ -832,6 +834,7 @@ int scvt_config_init(scvt_config* c, int64_t n) {
   c->rho.w_lon = 1.0;
   c->rho.w_lat = 1.0;
   c->quad_levels = 2;
+  c->quad_rule = 7;
   c->ls_max_evals = 10;
   c->ls_c1 = 1e-4;
   c->curv_eps = 1e-10;

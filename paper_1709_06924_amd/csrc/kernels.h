@@ -65,7 +65,7 @@ struct CellArgs {
   int levels;
   int keep_cells;
   int mixed;
-  int pad;
+  int quad_rule;  // points of the triangle rule: 7 (default), 4 or 9
   EvalOut out;
   int32_t* fb_list;    // n: cells for the fallback clipper
   int32_t* tier_list[2];  // n each: cells for the list passes of the certified path

@@ -40,7 +40,8 @@ class Config(ctypes.Structure):
                 ("ls_max_evals", ctypes.c_int32), ("ls_c1", ctypes.c_double),
                 ("curv_eps", ctypes.c_double), ("ls_noise", ctypes.c_double),
                 ("keep_cells", ctypes.c_int32),
-                ("method", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+                ("method", ctypes.c_int32), ("quad_rule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -136,7 +137,7 @@ METHODS = {"plbfgs": 0, "lloyd": 1, "lbfgs": 2}
 
 def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_max_evals=10,
                 ls_c1=1e-4, curv_eps=1e-10, keep_cells=False, stream=None, ls_noise=-1.0,
-                method="plbfgs"):
+                method="plbfgs", quad_rule=7):
     c = Config()
     _check(_lib.scvt_config_init(ctypes.byref(c), int(n)), "scvt_config_init")
     c.m_hist = int(m_hist)
@@ -149,6 +150,7 @@ def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_m
     c.ls_noise = float(ls_noise)
     c.keep_cells = 1 if keep_cells else 0
     c.method = METHODS[method] if isinstance(method, str) else int(method)
+    c.quad_rule = int(quad_rule)
     c.hip_stream = stream
     return c
 

@@ -126,7 +126,7 @@ int hc_clip(int64_t n, const double* Z, int64_t i, int32_t* deg, int32_t* nbr, d
 
 // Cell integrals from fan edges (z, v0[k], v1[k]), k < E, as the kernels do.
 int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int levels,
-            double* out5) {
+            int nq, double* out5) {
   Acc5 acc = {0, 0, 0, 0, 0};
   DensityP Dp = density_prepare(*D);
   V3 z = V3{z3[0], z3[1], z3[2]};
@@ -136,7 +136,7 @@ int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int
     V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
        C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
     subtriangle(A, B, C, s, levels);
-    quad_tri(A, B, C, z, Dp, acc);
+    quad_tri(A, B, C, z, Dp, acc, nq);
   }
   out5[0] = acc.m;
   out5[1] = acc.mx;
@@ -149,7 +149,7 @@ int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int
 // Mixed-precision cell integrals as the kernel computes them (FP64
 // sub-triangles, FP32 local-frame points, FP64 accumulation, mu = m z + ...)
 int hc_quad_mixed(const double* z3, int E, const double* verts, const DensityP* D, int levels,
-                  double* out5) {
+                  int nq, double* out5) {
   Acc5 acc = {0, 0, 0, 0, 0};
   DensityP Dp = density_prepare(*D);
   V3 z = V3{z3[0], z3[1], z3[2]};
@@ -164,7 +164,8 @@ int hc_quad_mixed(const double* z3, int E, const double* verts, const DensityP* 
     V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
        C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
     subtriangle(A, B, C, s, levels);
-#define HC_MIXED(V) quad_tri_mixed<V>(to_f3(A - z), to_f3(B - z), to_f3(C - z), zf, zc, Df, Dp, acc)
+#define HC_MIXED(V) \
+  quad_tri_mixed<V>(to_f3(A - z), to_f3(B - z), to_f3(C - z), zf, zc, Df, Dp, acc, nq)
     SCVT_RHO_DISPATCH(var, HC_MIXED)
 #undef HC_MIXED
   }

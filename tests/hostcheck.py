@@ -93,22 +93,23 @@ def cdensity(d):
     return c
 
 
-def quad(z, E, verts, density, levels=2):
+def quad(z, E, verts, density, levels=2, rule=7):
     z = np.ascontiguousarray(z, dtype=np.float64)
     verts = np.ascontiguousarray(verts, dtype=np.float64)
     out = np.zeros(5)
     D = cdensity(density)
-    lib().hc_quad(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D), ctypes.c_int(levels), P(out))
+    lib().hc_quad(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D), ctypes.c_int(levels),
+                  ctypes.c_int(rule), P(out))
     return out
 
 
-def quad_mixed(z, E, verts, density, levels=2):
+def quad_mixed(z, E, verts, density, levels=2, rule=7):
     z = np.ascontiguousarray(z, dtype=np.float64)
     verts = np.ascontiguousarray(verts, dtype=np.float64)
     out = np.zeros(5)
     D = cdensity(density)
     lib().hc_quad_mixed(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D), ctypes.c_int(levels),
-                        P(out))
+                        ctypes.c_int(rule), P(out))
     return out
 
 

@@ -158,20 +158,23 @@ def test_fallback_clipper_random(n, seed):
             assert np.max(np.abs(verts[t, 3:] - v1)) < 1e-13
 
 
-@pytest.mark.parametrize("density", ["const", "tanh", "tanh_geo", "x3", "x16", "two"])
-def test_quadrature_matches_oracle(density):
+@pytest.mark.parametrize("density,rule", [("const", 7), ("tanh", 7), ("tanh_geo", 7), ("x3", 7),
+                                          ("x16", 7), ("two", 7), ("x3", 4), ("x16", 4),
+                                          ("x64", 9), ("tanh", 9)])
+def test_quadrature_matches_oracle(density, rule):
     d = {"const": {"kind": "const"},
          "tanh": I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8),
          "tanh_geo": I.density_tanh(I.latlon(10, 20), math.pi / 9, 0.15, 16, geodesic=True),
-         "x3": I.density_x3(), "x16": I.density_x16(), "two": I.density_two_centre()}[density]
+         "x3": I.density_x3(), "x16": I.density_x16(), "x64": I.density_x64(),
+         "two": I.density_two_centre()}[density]
     n = 1500
     Z = I.uniform_sphere(n, 5)
-    ev = oracle.evaluate(Z, d)
+    ev = oracle.evaluate(Z, d, rule=rule)
     h = math.sqrt(4 * math.pi / n)
     st, deg, nbr, verts, R = hc.cells(Z, 4.0 * h)
     worst = [0.0, 0.0, 0.0]
     for k in np.where(st == 0)[0]:
-        out = hc.quad(Z[k], deg[k], verts[k], d)
+        out = hc.quad(Z[k], deg[k], verts[k], d, rule=rule)
         worst[0] = max(worst[0], abs(out[0] - ev.m[k]) / ev.m[k])
         worst[1] = max(worst[1], np.linalg.norm(out[1:4] - ev.mu[k]) / np.linalg.norm(ev.mu[k]))
         worst[2] = max(worst[2], abs(out[4] - ev.e[k]) / ev.e[k])

@@ -70,12 +70,13 @@ def stokes_moment(verts):
     return mu
 
 
-def tri_integrals(z, A, B, C, levels, density=None):
+def tri_integrals(z, A, B, C, levels, density=None, rule=7):
+    from oracle.rules import crule
     D = _clib.cdensity(density or {"kind": "const"})
     out = np.zeros(5)
     arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (z, A, B, C)]
     _clib.lib().oracle_triangle_integrals(ctypes.byref(D), *[_clib.ptr(v) for v in arrs],
-                                          int(levels), _clib.ptr(out))
+                                          int(levels), ctypes.byref(crule(rule)), _clib.ptr(out))
     return out
 
 
@@ -126,3 +127,47 @@ def test_density_values():
     x3 = _clib.cdensity(I.density_x3())
     p = np.array([0.0, 0.6, 0.8])
     assert abs(L.oracle_rho(ctypes.byref(x3), _clib.ptr(p)) - ((1 - 3.0 ** -4) * 0.8 ** 4 + 3.0 ** -4)) < 1e-15
+
+
+# ---- the conical product rules of 4 and 9 points (the sizes of section 4.1)
+
+@pytest.mark.parametrize("nq,degree", [(4, 3), (9, 5)])
+def test_conical_rules_exactness(nq, degree):
+    """Exact on every planar monomial up to the rule's degree, not beyond;
+    positive weights summing to one, points inside the triangle."""
+    from oracle.rules import rule
+    lam, w = rule(nq)
+    assert len(w) == nq and abs(w.sum() - 1.0) < 1e-15 and np.all(w > 0)
+    assert np.all(lam > 0) and np.allclose(lam.sum(axis=1), 1.0, atol=1e-15)
+    x, y = lam[:, 1], lam[:, 2]
+    for deg in range(degree + 2):
+        worst = 0.0
+        for a in range(deg + 1):
+            b = deg - a
+            exact = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+            worst = max(worst, abs(0.5 * np.sum(w * x ** a * y ** b) - exact) / exact)
+        if deg <= degree:
+            assert worst < 5e-15, (deg, worst)
+        else:
+            assert worst > 1e-6
+
+
+@pytest.mark.parametrize("nq,ratio", [(4, 12.0), (9, 30.0)])
+def test_conical_rules_converge_on_spherical_triangles(nq, ratio):
+    """Through the radial projection the 4-point (degree 3) rule's error
+    falls by about 2^4 per subdivision level, the 9-point (degree 5) rule's
+    by about 2^6, toward the closed-form area and first moment."""
+    rng = np.random.default_rng(8)
+    z = unit(rng.standard_normal(3))
+    A, B, C = [unit(z + 0.3 * unit(rng.standard_normal(3))) for _ in range(3)]
+    if np.dot(A, np.cross(B, C)) < 0:
+        B, C = C, B
+    area = vos_area(A, B, C)
+    mu = stokes_moment([A, B, C])
+    errs = []
+    for L in range(0, 5):
+        r = tri_integrals(z, A, B, C, L, rule=nq)
+        errs.append(max(abs(r[0] - area) / area, np.linalg.norm(r[1:4] - mu) / np.linalg.norm(mu)))
+    for L in range(1, 5):
+        if errs[L] > 1e-13:
+            assert errs[L - 1] / errs[L] > ratio, errs
