@@ -5,9 +5,11 @@ and for the quasi-Newton methods |grad F| / F <= 5e-4 or |dF| / F < 1e-7.
 
     python -m paper_1709_06924_amd.compare [--n 2562] [--seed 31] [--densities x3,x16,x64]
 
-Starts are seeded uniform points (the paper samples its densities by Monte
-Carlo), so absolute iteration counts differ from the paper's; the
-comparison is between the methods on a common start.
+Each density is integrated with the rule size the paper uses for it
+(4 points for X3 and X16, 9 for X64).  Starts are seeded uniform points
+(the paper samples its densities by Monte Carlo), so absolute iteration
+counts differ from the paper's; the comparison is between the methods on a
+common start.
 """
 import argparse
 import json
@@ -18,10 +20,12 @@ from . import scvt
 
 PAPER_TESTS = dict(max_iter=2000, step_tol=5e-4, grad_rel_tol=5e-4, f_rel_tol=1e-7)
 DENSITIES = {"x3": I.density_x3, "x16": I.density_x16, "x64": I.density_x64}
+PAPER_RULE = {"x3": 4, "x16": 4, "x64": 9}
 
 
-def run_method(Z0, density, method, m_hist=7, precision="fp64", tests=PAPER_TESTS):
-    S = scvt.Solver(Z0, density, method=method, m_hist=m_hist, precision=precision)
+def run_method(Z0, density, method, m_hist=7, precision="fp64", tests=PAPER_TESTS, quad_rule=7):
+    S = scvt.Solver(Z0, density, method=method, m_hist=m_hist, precision=precision,
+                    quad_rule=quad_rule)
     t0 = time.perf_counter()
     info = S.solve_rel(**tests)
     dt = time.perf_counter() - t0
@@ -36,7 +40,7 @@ def compare(n=2562, seed=31, densities=("x3", "x16", "x64"), methods=("lloyd", "
     rows = []
     for dn in densities:
         for m in methods:
-            r = run_method(Z0, DENSITIES[dn](), m)
+            r = run_method(Z0, DENSITIES[dn](), m, quad_rule=PAPER_RULE[dn])
             r["density"] = dn
             r["n"] = n
             rows.append(r)

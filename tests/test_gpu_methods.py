@@ -87,3 +87,30 @@ def test_method_comparison_x16_x64():
         lloyd, plain, pl = by[(dn, "lloyd")], by[(dn, "lbfgs")], by[(dn, "plbfgs")]
         assert pl["iterations"] * 2 < lloyd["iterations"]
         assert pl["F"] <= plain["F"] * (1 + 1e-3)
+
+
+@pytest.mark.parametrize("dname,rule", [("x3", 4), ("x16", 4), ("x64", 9), ("x64", 7)])
+def test_rule_evaluation_parity(scvt, dname, rule):
+    """Each triangle rule (section 4.1 pairs 4 points with X3 and X16, 9
+    with X64) against the oracle's rule at the same generators: F to 1e-12,
+    every cell's m, mu, e to 1e-12."""
+    d = {"x3": I.density_x3(), "x16": I.density_x16(), "x64": I.density_x64()}[dname]
+    S = scvt.Solver(I.uniform_sphere(3000, 28), d, quad_rule=rule)
+    Zg = S.generators()
+    ev = oracle.evaluate(Zg, d, rule=rule)
+    F, m, c, e = S.energy()
+    assert abs(F - ev.F) <= 1e-12 * ev.F
+    assert np.max(np.abs(m - ev.m) / ev.m) <= 1e-12
+    assert np.max(np.abs(e - ev.e) / ev.e) <= 1e-12
+    assert np.max(np.linalg.norm(S.vector("mu") - ev.mu, axis=1) /
+                  np.linalg.norm(ev.mu, axis=1)) <= 1e-12
+
+
+def test_rule_mixed_precision_error(scvt):
+    d = I.density_x64()
+    S = scvt.Solver(I.uniform_sphere(3000, 29), d, quad_rule=9, precision="mixed")
+    ev = oracle.evaluate(S.generators(), d, rule=9)
+    F, m, c, e = S.energy()
+    dm = np.max(np.abs(m - ev.m) / ev.m)
+    print("mixed x64 rule 9: dm/m %.2e dF/F %.2e" % (dm, abs(F - ev.F) / ev.F))
+    assert dm <= 1e-5 and abs(F - ev.F) <= 1e-6 * ev.F
