@@ -50,7 +50,8 @@ def cell_flops(mean_degree):
 # Sources that define the quadrature kernel: the HBM traffic recorded under
 # profiles/ is reported only while these are unchanged.
 QUAD_SOURCES = ["paper_1709_06924_amd/csrc/cells.hip", "paper_1709_06924_amd/csrc/cellgeom.h",
-                "paper_1709_06924_amd/csrc/exp_table.h", "paper_1709_06924_amd/csrc/kernels.h"]
+                "paper_1709_06924_amd/csrc/exp_table.h", "paper_1709_06924_amd/csrc/rules.h",
+                "paper_1709_06924_amd/csrc/kernels.h"]
 TRAFFIC_FILE = "profiles/hbm_traffic_k_quad_n1048576_tanh16_fp64.txt"
 
 

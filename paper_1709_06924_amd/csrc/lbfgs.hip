@@ -182,51 +182,98 @@ __device__ inline void block_partials(const double* acc, int K, double* out) {
     out[v] = ((sh[0][v] + sh[1][v]) + sh[2][v]) + sh[3][v];
 }
 
+// The streaming passes read VW consecutive elements per thread and step (16-
+// byte loads when 3n is even, so that every vector is 16-byte aligned).
+template <int VW>
+__device__ inline void ld(const double* __restrict__ p, int u, double (&o)[VW]) {
+  if constexpr (VW == 2) {
+    const double2 t = reinterpret_cast<const double2*>(p)[u];
+    o[0] = t.x;
+    o[1] = t.y;
+  } else {
+    o[0] = p[u];
+  }
+}
+template <int VW>
+__device__ inline void st(double* __restrict__ p, int u, const double (&o)[VW]) {
+  if constexpr (VW == 2) {
+    reinterpret_cast<double2*>(p)[u] = make_double2(o[0], o[1]);
+  } else {
+    p[u] = o[0];
+  }
+}
+
+template <int VW>
 __global__ __launch_bounds__(kRedBlock) void k_push_ext(PushExtArgs a) {
   double acc[kHVals];
 #pragma unroll
   for (int v = 0; v < kHVals; v++) acc[v] = 0.0;
   const int c = a.c;
-  const int n3 = (int)a.n3;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
-    const double gt = a.gt[k];
-    const double s = a.Zt[k] - a.Z[k];
-    const double y = gt - a.g[k];
-    a.s[k] = s;
-    a.y[k] = y;
-    acc[0] = fma(y, s, acc[0]);
-    acc[1] = fma(y, y, acc[1]);
-    acc[2] = fma(s, s, acc[2]);
-    acc[3] = fma(s, gt, acc[3]);
+  const int nu = (int)(a.n3 / VW);
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+    double gt[VW], zt[VW], z[VW], g[VW], s[VW], y[VW];
+    ld<VW>(a.gt, u, gt);
+    ld<VW>(a.Zt, u, zt);
+    ld<VW>(a.Z, u, z);
+    ld<VW>(a.g, u, g);
+#pragma unroll
+    for (int e = 0; e < VW; e++) {
+      s[e] = zt[e] - z[e];
+      y[e] = gt[e] - g[e];
+    }
+    st<VW>(a.s, u, s);
+    st<VW>(a.y, u, y);
+#pragma unroll
+    for (int e = 0; e < VW; e++) {
+      acc[0] = fma(y[e], s[e], acc[0]);
+      acc[1] = fma(y[e], y[e], acc[1]);
+      acc[2] = fma(s[e], s[e], acc[2]);
+      acc[3] = fma(s[e], gt[e], acc[3]);
+    }
 #pragma unroll
     for (int j = 0; j < kHmax; j++) {
       if (j < c) {
-        const double sj = a.S[j][k];
-        acc[4 + 2 * j] = fma(sj, gt, acc[4 + 2 * j]);
-        acc[5 + 2 * j] = fma(sj, y, acc[5 + 2 * j]);
+        double sj[VW];
+        ld<VW>(a.S[j], u, sj);
+#pragma unroll
+        for (int e = 0; e < VW; e++) {
+          acc[4 + 2 * j] = fma(sj[e], gt[e], acc[4 + 2 * j]);
+          acc[5 + 2 * j] = fma(sj[e], y[e], acc[5 + 2 * j]);
+        }
       }
     }
   }
   block_partials<kHVals>(acc, 4 + 2 * c, a.partials + (size_t)blockIdx.x * (4 + 2 * c));
 }
 
+// the same sums as k_push_ext forms for s_j . g and s_j . y (same element
+// order per thread), so a restored state recomputes them bit for bit
+template <int VW>
 __global__ __launch_bounds__(kRedBlock) void k_multi_dot(MultiDotArgs a) {
   double acc[kHmax];
 #pragma unroll
   for (int v = 0; v < kHmax; v++) acc[v] = 0.0;
   const int c = a.c;
-  const int n3 = (int)a.n3;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
-    const double v = a.v[k];
+  const int nu = (int)(a.n3 / VW);
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+    double v[VW];
+    ld<VW>(a.v, u, v);
 #pragma unroll
-    for (int j = 0; j < kHmax; j++)
-      if (j < c) acc[j] = fma(a.A[j][k], v, acc[j]);
+    for (int j = 0; j < kHmax; j++) {
+      if (j < c) {
+        double aj[VW];
+        ld<VW>(a.A[j], u, aj);
+#pragma unroll
+        for (int e = 0; e < VW; e++) acc[j] = fma(aj[e], v[e], acc[j]);
+      }
+    }
   }
   block_partials<kHmax>(acc, c, a.partials + (size_t)blockIdx.x * c);
 }
 
 // r = h (.) (-g - sum_k a_k y_k), newest pair first as in the backward loop;
 // partials of y_j . r
+template <int VW>
 __global__ __launch_bounds__(kRedBlock) void k_hist_q0(HistPassArgs a) {
   const int c = a.c;
   double coef[kHmax], acc[kHmax];
@@ -235,42 +282,60 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_q0(HistPassArgs a) {
     coef[j] = j < c ? a.coef[j] : 0.0;
     acc[j] = 0.0;
   }
-  const int n3 = (int)a.n3;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
-    double yv[kHmax];
-    double q = -a.g[k];
+  const int nu = (int)(a.n3 / VW);
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+    double yv[kHmax][VW];
+    double q[VW];
+    ld<VW>(a.g, u, q);
+#pragma unroll
+    for (int e = 0; e < VW; e++) q[e] = -q[e];
 #pragma unroll
     for (int j = kHmax - 1; j >= 0; j--) {
       if (j < c) {
-        yv[j] = a.Y[j][k];
-        q = fma(-coef[j], yv[j], q);
+        ld<VW>(a.Y[j], u, yv[j]);
+#pragma unroll
+        for (int e = 0; e < VW; e++) q[e] = fma(-coef[j], yv[j][e], q[e]);
       }
     }
-    const double r = a.h[(unsigned)k / 3u] * q;
-    a.q[k] = r;
+    double r[VW];
+#pragma unroll
+    for (int e = 0; e < VW; e++) r[e] = a.h[(unsigned)(u * VW + e) / 3u] * q[e];
+    st<VW>(a.q, u, r);
 #pragma unroll
     for (int j = 0; j < kHmax; j++)
-      if (j < c) acc[j] = fma(yv[j], r, acc[j]);
+      if (j < c) {
+#pragma unroll
+        for (int e = 0; e < VW; e++) acc[j] = fma(yv[j][e], r[e], acc[j]);
+      }
   }
   if (c > 0) block_partials<kHmax>(acc, c, a.partials + (size_t)blockIdx.x * c);
 }
 
 // q = r + sum_k c_k s_k, oldest pair first as in the forward loop; partials
 // of g . q
+template <int VW>
 __global__ __launch_bounds__(kRedBlock) void k_hist_dir(HistPassArgs a) {
   const int c = a.c;
   double coef[kHmax];
 #pragma unroll
   for (int j = 0; j < kHmax; j++) coef[j] = j < c ? a.coef[j] : 0.0;
   double acc[1] = {0.0};
-  const int n3 = (int)a.n3;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n3; k += gridDim.x * blockDim.x) {
-    double q = a.qin[k];
+  const int nu = (int)(a.n3 / VW);
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+    double q[VW], g[VW];
+    ld<VW>(a.qin, u, q);
+    ld<VW>(a.g, u, g);
 #pragma unroll
     for (int j = 0; j < kHmax; j++)
-      if (j < c) q = fma(coef[j], a.S[j][k], q);
-    a.q[k] = q;
-    acc[0] = fma(a.g[k], q, acc[0]);
+      if (j < c) {
+        double sj[VW];
+        ld<VW>(a.S[j], u, sj);
+#pragma unroll
+        for (int e = 0; e < VW; e++) q[e] = fma(coef[j], sj[e], q[e]);
+      }
+    st<VW>(a.q, u, q);
+#pragma unroll
+    for (int e = 0; e < VW; e++) acc[0] = fma(g[e], q[e], acc[0]);
   }
   block_partials<1>(acc, 1, a.partials + blockIdx.x);
 }
@@ -352,19 +417,35 @@ int hist_grid(int64_t n3) {
 int hist_grid_max() { return kHGrid * kHVals; }
 
 hipError_t launch_push_ext(const PushExtArgs& a, hipStream_t s) {
-  k_push_ext<<<hist_grid(a.n3), kRedBlock, 0, s>>>(a);
+  const int nb = hist_grid(a.n3);
+  if (a.n3 % 2 == 0)
+    k_push_ext<2><<<nb, kRedBlock, 0, s>>>(a);
+  else
+    k_push_ext<1><<<nb, kRedBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_multi_dot(const MultiDotArgs& a, hipStream_t s) {
-  k_multi_dot<<<hist_grid(a.n3), kRedBlock, 0, s>>>(a);
+  const int nb = hist_grid(a.n3);
+  if (a.n3 % 2 == 0)
+    k_multi_dot<2><<<nb, kRedBlock, 0, s>>>(a);
+  else
+    k_multi_dot<1><<<nb, kRedBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_hist_q0(const HistPassArgs& a, hipStream_t s) {
-  k_hist_q0<<<hist_grid(a.n3), kRedBlock, 0, s>>>(a);
+  const int nb = hist_grid(a.n3);
+  if (a.n3 % 2 == 0)
+    k_hist_q0<2><<<nb, kRedBlock, 0, s>>>(a);
+  else
+    k_hist_q0<1><<<nb, kRedBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_hist_dir(const HistPassArgs& a, hipStream_t s) {
-  k_hist_dir<<<hist_grid(a.n3), kRedBlock, 0, s>>>(a);
+  const int nb = hist_grid(a.n3);
+  if (a.n3 % 2 == 0)
+    k_hist_dir<2><<<nb, kRedBlock, 0, s>>>(a);
+  else
+    k_hist_dir<1><<<nb, kRedBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_hist_fin(const HistFinArgs& a, hipStream_t s) {
