@@ -116,6 +116,36 @@ def run_gpu(args, precision, Z0_dev, cfg, stream):
     return out
 
 
+def mixed_errors(cfg, Z0_dev, stream, checkpoints=(0, 50, 100, 200)):
+    """The mixed path's evaluation against the FP64 one at the FP64 iterates
+    Z_0, Z_50, Z_100, Z_200 of the workload (both on the device): |dF|/F,
+    max |dm|/m and max |d centroid| / R_i (R_i the cell's circumradius)."""
+    import numpy as np
+    import torch
+
+    from paper_1709_06924_amd import scvt
+    kw = dict(m_hist=cfg["m_hist"], stream=stream)
+    S = scvt.Solver(Z0_dev, cfg["density"], precision="fp64", **kw)
+    out = []
+    it = 0
+    for k in checkpoints:
+        while it < k:
+            S.step()
+            it += 1
+        Z = torch.empty((S.n, 3), dtype=torch.float64, device="cuda:0")
+        S.generators(Z)
+        F64, m64, c64, _ = S.energy()
+        R = S.vector("R")
+        M = scvt.Solver(Z, cfg["density"], precision="mixed", **kw)
+        Fmx, mmx, cmx, _ = M.energy()
+        M.close()
+        out.append({"iteration": k, "dF_over_F": abs(Fmx - F64) / F64,
+                    "max_dm_over_m": float(np.max(np.abs(mmx - m64) / m64)),
+                    "max_dcentroid_over_R": float(np.max(np.linalg.norm(cmx - c64, axis=1) / R))})
+    S.close()
+    return out
+
+
 def cpu_baseline(cfg, Z0):
     import oracle
     from oracle import _clib
@@ -138,6 +168,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-mixed-errors", action="store_true",
+                    help="skip the mixed-vs-FP64 evaluation errors at iterations 0/50/100/200")
     ap.add_argument("--source-hash", action="store_true",
                     help="print the hash of the quadrature kernel's sources and exit")
     ap.add_argument("--serving-requests", type=int, default=24)
@@ -231,6 +263,10 @@ def main():
                                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                                 "frac": qfl / (qms * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
                                 "avg_launch_ms": qms}}
+    if "mixed" in line and not args.no_mixed_errors:
+        print("bench: mixed-vs-FP64 evaluation errors at the FP64 iterates", file=sys.stderr,
+              flush=True)
+        line["mixed"]["errors_vs_fp64"] = mixed_errors(cfg, Z0_dev, stream)
     if args.serving_requests > 0:
         from paper_1709_06924_amd import serving
         stream = I.serving_stream(seed=4, rate=args.serving_rate, count=args.serving_requests)
