@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/scvt.h"
@@ -229,6 +230,7 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   const bool tm = h->timing;
   HIPCK(launch_fill_i32((int32_t*)h->ctr, 0, sizeof(Counters) / 4, st));
   if (tm) HIPCK(hipEventRecord(h->ev[0], st));
+  std::swap(h->grid.order, h->grid.order_prev);  // last build's order drives this one
   HIPCK(launch_grid_build(Zsrc, h->n, h->grid, st));
   if (tm) HIPCK(hipEventRecord(h->ev[1], st));
   CellArgs a = cell_args(h, Zsrc, s);
@@ -291,6 +293,7 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
 int geometry_with_neighbours(scvt_handle* h, const double* Zsrc, int32_t* nbr) {
   hipStream_t st = h->stream;
   HIPCK(launch_fill_i32((int32_t*)h->ctr, 0, sizeof(Counters) / 4, st));
+  std::swap(h->grid.order, h->grid.order_prev);  // last build's order drives this one
   HIPCK(launch_grid_build(Zsrc, h->n, h->grid, st));
   CellArgs a = cell_args(h, Zsrc, h->trial);
   a.keep_cells = 1;
@@ -774,6 +777,7 @@ int alloc_device_state(scvt_handle* h) {
   h->grid.cap_entries = 3 * n;
   ALLOC(h->grid.entries, 3 * n);
   ALLOC(h->grid.order, n);
+  ALLOC(h->grid.order_prev, n);
   ALLOC(h->grid.scan_tmp, 2 * ((nc + 1) / 2048 + 2));
   ALLOC(h->grid.overflow, 1);
   return SCVT_OK;
@@ -793,6 +797,7 @@ int init_device_state(scvt_handle* h) {
   HIPCK(launch_fill_i32(h->grid.cnt_tot, 0, nc + 1, st));
   HIPCK(launch_fill_i32(h->grid.cnt_home, 0, nc + 1, st));
   HIPCK(launch_fill_i32(h->grid.overflow, 0, 1, st));
+  HIPCK(launch_iota(h->grid.order, n, st));  // first build: generator order
   HIPCK(launch_fill_i32((int32_t*)h->R, 0, 2 * n, st));
   HIPCK(launch_fill_i32((int32_t*)h->dscal, 0, 2 * kNScal, st));
   HIPCK(launch_fill_i32((int32_t*)h->q, 0, 6 * n, st));

@@ -5,6 +5,8 @@
 // scan:    exclusive prefix sums of the counts (three-kernel block scan);
 // scatter: positions are taken by decrementing the counts back to zero, so
 //          the counts are ready for the next evaluation without a memset.
+// Both passes take the generators in the previous build's order (by home
+// cell) and aggregate per block (see k_grid_count).
 #include "kernels.h"
 
 namespace scvt {
@@ -65,11 +67,42 @@ __device__ inline void side_faces(int f, int out[4]) {
     if ((g >> 1) != k) out[c++] = g;
 }
 
-__global__ void k_grid_count(const double* __restrict__ Z, int64_t n, GridP g,
-                             int32_t* __restrict__ cnt_tot, int32_t* __restrict__ cnt_home,
-                             int32_t* __restrict__ cell3) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Generators are taken in the previous build's cell order, so a block's
+// 256 generators fall into few grid cells (dense regions hold tens of
+// generators per cell).  Each block counts its cells in a small LDS hash
+// table and adds one device-scope atomic per distinct cell instead of one
+// per generator; the scatter reserves one contiguous range per (block, cell)
+// the same way and places its entries by LDS ranks.
+constexpr int kBucketBlock = 256;
+constexpr int kHashSize = 1024;  // > 3 cells x 256 generators: probing ends
+
+struct BucketLds {
+  int32_t key[kHashSize];
+  int32_t ntot[kHashSize], nhome[kHashSize];
+  int32_t btot[kHashSize], bhome[kHashSize];  // reserved range starts (scatter)
+};
+
+__device__ inline int hash_slot(BucketLds& L, int32_t c) {
+  uint32_t h = ((uint32_t)c * 2654435761u) >> 22;  // 10 bits
+  for (;;) {
+    const int32_t k = atomicCAS(&L.key[h], -1, c);
+    if (k == -1 || k == c) return (int)h;
+    h = (h + 1) & (kHashSize - 1);
+  }
+}
+
+__device__ inline void bucket_init(BucketLds& L) {
+  for (int s = threadIdx.x; s < kHashSize; s += blockDim.x) {
+    L.key[s] = -1;
+    L.ntot[s] = 0;
+    L.nhome[s] = 0;
+  }
+  __syncthreads();
+}
+
+// home cell and up to two ghost cells of generator i (cell3 row)
+__device__ inline void generator_cells(const double* __restrict__ Z, int64_t i, const GridP& g,
+                                       int32_t out[3]) {
   V3 p = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
   int f = home_face(p);
   int64_t c = cell_on_face(g, p, f);
@@ -84,21 +117,42 @@ __global__ void k_grid_count(const double* __restrict__ Z, int64_t n, GridP g,
     int ib = fb < 0.0 ? 0 : (fb > g.W - 1 ? g.W - 1 : (int)fb);
     c = cell_of(g, f, ia, ib);
   }
-  atomicAdd(&cnt_tot[c], 1);
-  atomicAdd(&cnt_home[c], 1);
-  cell3[3 * i] = (int32_t)c;
+  out[0] = (int32_t)c;
   int k = 1;
   int sf[4];
   side_faces(f, sf);
   for (int t = 0; t < 4 && g.B > 0; t++) {
     int64_t cg = cell_on_face(g, p, sf[t]);
-    if (cg >= 0 && k < 3) {
-      atomicAdd(&cnt_tot[cg], 1);
-      cell3[3 * i + k] = (int32_t)cg;
-      k++;
+    if (cg >= 0 && k < 3) out[k++] = (int32_t)cg;
+  }
+  for (; k < 3; k++) out[k] = -1;
+}
+
+__global__ __launch_bounds__(kBucketBlock) void k_grid_count(
+    const double* __restrict__ Z, int64_t n, GridP g, const int32_t* __restrict__ order_prev,
+    int32_t* __restrict__ cnt_tot, int32_t* __restrict__ cnt_home, int32_t* __restrict__ cell3) {
+  __shared__ BucketLds L;
+  bucket_init(L);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    const int64_t i = order_prev[t];
+    int32_t c[3];
+    generator_cells(Z, i, g, c);
+    for (int k = 0; k < 3; k++) {
+      cell3[3 * i + k] = c[k];
+      if (c[k] < 0) continue;
+      const int s = hash_slot(L, c[k]);
+      atomicAdd(&L.ntot[s], 1);
+      if (k == 0) atomicAdd(&L.nhome[s], 1);
     }
   }
-  for (; k < 3; k++) cell3[3 * i + k] = -1;
+  __syncthreads();
+  for (int s = threadIdx.x; s < kHashSize; s += blockDim.x) {
+    const int32_t c = L.key[s];
+    if (c < 0) continue;
+    atomicAdd(&cnt_tot[c], L.ntot[s]);
+    if (L.nhome[s]) atomicAdd(&cnt_home[c], L.nhome[s]);
+  }
 }
 
 // ---- exclusive scan of two int arrays of length m (m+1 outputs) ----
@@ -192,14 +246,43 @@ __global__ void k_scan_apply(const int32_t* __restrict__ a, const int32_t* __res
   }
 }
 
-__global__ void k_grid_scatter(const double* __restrict__ Z, int64_t n,
-                               const int32_t* __restrict__ cell3,
-                               const int32_t* __restrict__ start_tot,
-                               const int32_t* __restrict__ start_home, int32_t* cnt_tot,
-                               int32_t* cnt_home, Entry* __restrict__ entries, int64_t cap,
-                               int32_t* __restrict__ order, int32_t* overflow) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__global__ __launch_bounds__(kBucketBlock) void k_grid_scatter(
+    const double* __restrict__ Z, int64_t n, const int32_t* __restrict__ order_prev,
+    const int32_t* __restrict__ cell3, const int32_t* __restrict__ start_tot,
+    const int32_t* __restrict__ start_home, int32_t* cnt_tot, int32_t* cnt_home,
+    Entry* __restrict__ entries, int64_t cap, int32_t* __restrict__ order,
+    int32_t* overflow) {
+  __shared__ BucketLds L;
+  bucket_init(L);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < n;
+  const int64_t i = valid ? order_prev[t] : 0;
+  int32_t c[3] = {-1, -1, -1};
+  int slot[3] = {0, 0, 0};
+  if (valid) {
+    for (int k = 0; k < 3; k++) {
+      c[k] = cell3[3 * i + k];
+      if (c[k] >= 0) slot[k] = hash_slot(L, c[k]);
+    }
+    for (int k = 0; k < 3; k++) {
+      if (c[k] < 0) continue;
+      atomicAdd(&L.ntot[slot[k]], 1);
+      if (k == 0) atomicAdd(&L.nhome[slot[k]], 1);
+    }
+  }
+  __syncthreads();
+  // reserve this block's range in every cell: the counts run down to zero
+  // over all blocks (ready for the next build)
+  for (int s = threadIdx.x; s < kHashSize; s += blockDim.x) {
+    const int32_t cs = L.key[s];
+    if (cs < 0) continue;
+    L.btot[s] = atomicSub(&cnt_tot[cs], L.ntot[s]) - L.ntot[s];
+    if (L.nhome[s]) L.bhome[s] = atomicSub(&cnt_home[cs], L.nhome[s]) - L.nhome[s];
+    L.ntot[s] = 0;  // reused as the in-block rank counters
+    L.nhome[s] = 0;
+  }
+  __syncthreads();
+  if (!valid) return;
   Entry en;
   en.x = Z[3 * i];
   en.y = Z[3 * i + 1];
@@ -207,19 +290,26 @@ __global__ void k_grid_scatter(const double* __restrict__ Z, int64_t n,
   en.idx = (int32_t)i;
   en.pad = 0;
   for (int k = 0; k < 3; k++) {
-    int32_t c = cell3[3 * i + k];
-    if (c < 0) continue;
-    int32_t pos = start_tot[c] + atomicSub(&cnt_tot[c], 1) - 1;
+    if (c[k] < 0) continue;
+    const int s = slot[k];
+    const int32_t pos = start_tot[c[k]] + L.btot[s] + atomicAdd(&L.ntot[s], 1);
     if (pos < cap) {
       entries[pos] = en;
     } else {
       atomicOr(overflow, 1);
     }
-    if (k == 0) {
-      int32_t ph = start_home[c] + atomicSub(&cnt_home[c], 1) - 1;
-      order[ph] = (int32_t)i;
-    }
+    if (k == 0) order[start_home[c[k]] + L.bhome[s] + atomicAdd(&L.nhome[s], 1)] = (int32_t)i;
   }
+}
+
+__global__ void k_iota(int32_t* p, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = (int32_t)t;
+}
+
+hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s) {
+  k_iota<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+  return hipGetLastError();
 }
 
 __global__ void k_centroid(const double* __restrict__ mu, const double* __restrict__ m,
@@ -248,16 +338,17 @@ int64_t scan_tmp_ints(int64_t m) { return 2 * ((m + 1 + kScanTile - 1) / kScanTi
 
 hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s) {
   const int64_t m = gb.g.ncells;
-  unsigned nb = (unsigned)((n + 255) / 256);
-  k_grid_count<<<nb, 256, 0, s>>>(Z, n, gb.g, gb.cnt_tot, gb.cnt_home, gb.cell3);
+  unsigned nb = (unsigned)((n + kBucketBlock - 1) / kBucketBlock);
+  k_grid_count<<<nb, kBucketBlock, 0, s>>>(Z, n, gb.g, gb.order_prev, gb.cnt_tot, gb.cnt_home,
+                                           gb.cell3);
   int64_t ntiles = (m + 1 + kScanTile - 1) / kScanTile;
   k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, s>>>(gb.cnt_tot, gb.cnt_home, m, gb.scan_tmp);
   k_scan_sums<<<1, kScanBlock, 0, s>>>(gb.scan_tmp, ntiles);
   k_scan_apply<<<(unsigned)ntiles, kScanBlock, 0, s>>>(gb.cnt_tot, gb.cnt_home, m, gb.scan_tmp,
                                                       gb.start_tot, gb.start_home);
-  k_grid_scatter<<<nb, 256, 0, s>>>(Z, n, gb.cell3, gb.start_tot, gb.start_home, gb.cnt_tot,
-                                    gb.cnt_home, gb.entries, gb.cap_entries, gb.order,
-                                    gb.overflow);
+  k_grid_scatter<<<nb, kBucketBlock, 0, s>>>(Z, n, gb.order_prev, gb.cell3, gb.start_tot,
+                                             gb.start_home, gb.cnt_tot, gb.cnt_home, gb.entries,
+                                             gb.cap_entries, gb.order, gb.overflow);
   return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ struct GridBufs {
   int32_t* cell3;      // n x 3 cells of each generator (home, ghosts, -1)
   Entry* entries;      // capacity cap_entries
   int32_t* order;      // n: generators sorted by home cell
+  int32_t* order_prev; // n: the previous build's order (input of the next build)
   int64_t cap_entries;
   int32_t* scan_tmp;   // block sums for the scan
   int32_t* overflow;   // 1 int: set when entries exceed capacity
@@ -76,7 +77,10 @@ struct CellArgs {
 // ---- launch wrappers (return hipError_t) ----
 hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha, double* Zt,
                                   int64_t n, hipStream_t s);
+// builds the buckets of Z; then gb.order holds the new order (the caller
+// swaps order and order_prev before the next build)
 hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s);
+hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
 // exclusive scans of a[0..m) and b[0..m) into oa, ob (m+1 entries each; the
 // last holds the total); tmp holds scan_tmp_ints(m) ints
 hipError_t launch_scan_pair(const int32_t* a, const int32_t* b, int64_t m, int32_t* tmp,
