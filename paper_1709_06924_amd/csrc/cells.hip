@@ -17,10 +17,10 @@
 //   a predicate within its error bound, go to a list for
 // k_fallback: a sequential half-space clipper run by lane 0 (no size limit:
 //   any cell the sphere allows), writing the same slot.
-// k_quad: one wavefront per cell: fan triangles (z, v_lo, v_hi), each split
-//   into 4^levels geodesic sub-triangles with the 7-point rule, one (edge,
-//   sub-triangle) item per lane; then m, mu, e -> g, h, Lloyd step
-//   (section 3.1).
+// k_quad: two cells per wavefront: fan triangles (z, v_lo, v_hi), each split
+//   into 4^levels geodesic sub-triangles with the triangle rule, one (edge,
+//   sub-triangle) item per lane; m, mu, e per cell (g, h and the Lloyd step
+//   of section 3.1 follow in the evaluation's reduction pass).
 #include "kernels.h"
 
 namespace scvt {
@@ -482,25 +482,16 @@ __global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
 // reduced across the wave in a fixed butterfly order, so results do not
 // depend on scheduling.  MIXED: FP32 points in the generator's local frame
 // (quad_tri_mixed), FP64 sub-triangle vertices, accumulation and epilogue.
+// m, mu, e of the cell (g, h and the Lloyd step follow in k_eval_reduce)
 template <bool MIXED>
 __device__ inline void cell_epilogue(const EvalOut& o, int64_t i, V3 z, Acc5 acc) {
   V3 mu = V3{acc.mx, acc.my, acc.mz};
   if (MIXED) mu = acc.m * z + mu;  // first moment from int rho (y - z)
-  double mz = dot(mu, z);
-  V3 g = 2.0 * mz * z - 2.0 * mu;
-  V3 l = normalized(mu) - z;
   o.m[i] = acc.m;
   o.e[i] = acc.e;
   o.mu[3 * i] = mu.x;
   o.mu[3 * i + 1] = mu.y;
   o.mu[3 * i + 2] = mu.z;
-  o.g[3 * i] = g.x;
-  o.g[3 * i + 1] = g.y;
-  o.g[3 * i + 2] = g.z;
-  o.h[i] = 1.0 / (2.0 * mz);
-  o.lloyd[3 * i] = l.x;
-  o.lloyd[3 * i + 1] = l.y;
-  o.lloyd[3 * i + 2] = l.z;
 }
 
 // Sums over the wave of a (on lanes 0-31) and b (on lanes 32-63): the

@@ -245,10 +245,11 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   EvalRedArgs r{};
   r.n = h->n;
   r.e = s.e;
-  r.lloyd = s.lloyd;
-  r.g = s.g;
   r.mu = s.mu;
   r.Z = Zsrc;
+  r.g = s.g;
+  r.h = s.h;
+  r.lloyd = s.lloyd;
   r.partials = h->partials + kPartEval * reduce_grid_max();
   HIPCK(launch_eval_reduce(r, st));
   FinalizeArgs fa{};

@@ -46,9 +46,12 @@ struct PushArgs {
   double* partials;  // ys, yy, ss per block
 };
 
+// per generator: g = 2 (mu.z) z - 2 mu, h = 1 / (2 mu.z), l = mu/|mu| - z
+// (section 3.1), written; partials of F, max |l|, sum |g|^2, min mu.z
 struct EvalRedArgs {
   int64_t n;
-  const double *e, *lloyd, *g, *mu, *Z;
+  const double *e, *mu, *Z;
+  double *g, *h, *lloyd;
   double* partials;  // F, max|l|, sum|g|^2, min mu.z per block
 };
 

@@ -114,21 +114,31 @@ __global__ __launch_bounds__(kRedBlock) void k_push(PushArgs a) {
 }
 
 // ------------------------------------------------------ evaluation reduce
-// partials of F = sum e_i, max |l_ik|, sum |g_i|^2, min mu_i . z_i
+// Per generator the gradient, preconditioner and Lloyd step from mu (section
+// 3.1), then partials of F = sum e_i, max |l_ik|, sum |g_i|^2, min mu_i . z_i
 __global__ __launch_bounds__(kRedBlock) void k_eval_reduce(EvalRedArgs a) {
   __shared__ double sh[kRedBlock];
   double F = 0.0, lmax = 0.0, gg = 0.0, mzmin = 1e300;
   const int n = (int)a.n;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    F += a.e[i];
-    for (int k = 0; k < 3; k++) {
-      lmax = fmax(lmax, fabs(a.lloyd[3 * i + k]));
-      gg += a.g[3 * i + k] * a.g[3 * i + k];
-    }
-    double mz = a.mu[3 * i] * a.Z[3 * i] + a.mu[3 * i + 1] * a.Z[3 * i + 1] +
-                a.mu[3 * i + 2] * a.Z[3 * i + 2];
+    const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
+    const V3 mu = V3{a.mu[3 * i], a.mu[3 * i + 1], a.mu[3 * i + 2]};
+    const double e = a.e[i];
+    const double mz = dot(mu, z);
+    const V3 g = 2.0 * mz * z - 2.0 * mu;
+    const V3 l = normalized(mu) - z;
+    a.g[3 * i] = g.x;
+    a.g[3 * i + 1] = g.y;
+    a.g[3 * i + 2] = g.z;
+    a.h[i] = 1.0 / (2.0 * mz);
+    a.lloyd[3 * i] = l.x;
+    a.lloyd[3 * i + 1] = l.y;
+    a.lloyd[3 * i + 2] = l.z;
+    F += e;
+    lmax = fmax(lmax, fmax(fabs(l.x), fmax(fabs(l.y), fabs(l.z))));
+    gg += dot(g, g);
     mzmin = fmin(mzmin, mz);
-    if (!(a.e[i] == a.e[i]) || !(mz == mz)) mzmin = -1.0;  // NaN guard
+    if (!(e == e) || !(mz == mz)) mzmin = -1.0;  // NaN guard
   }
   double b0 = block_sum(F, sh), b1 = block_max(lmax, sh), b2 = block_sum(gg, sh),
          b3 = block_min(mzmin, sh);
