@@ -224,11 +224,17 @@ struct DensityP {
   double xc[2][3];
   double beta[2], alpha[2], amp[2];
   double gamma, w_lon, w_lat;
-  double k2[2];  // -2 / alpha_k (filled by density_prepare)
+  // filled by density_prepare: k2 = -2 / alpha_k, and the base-2 exponent's
+  // K = 128/(alpha_k ln2) and bK = -beta_k K
+  double k2[2], K[2], bK[2];
 };
 
 SCVT_HD DensityP density_prepare(DensityP d) {
-  for (int k = 0; k < 2; k++) d.k2[k] = d.alpha[k] > 0.0 ? -2.0 / d.alpha[k] : 0.0;
+  for (int k = 0; k < 2; k++) {
+    d.k2[k] = d.alpha[k] > 0.0 ? -2.0 / d.alpha[k] : 0.0;
+    d.K[k] = -d.k2[k] * kExpInvLn;
+    d.bK[k] = -d.beta[k] * d.K[k];
+  }
   return d;
 }
 
@@ -256,43 +262,75 @@ SCVT_HD double rsq_pos(double x) {
 #endif
 }
 
-// exp(t) for t in [-708, 700] (callers clamp), table-driven (Tang's
-// method): t = (64 m + j) ln2/64 + r with |r| <= ln2/128, so
-// exp(t) = 2^m 2^(j/64) exp(r), and exp(r) - 1 is the degree-5 Taylor
-// polynomial (truncation error below 4e-17).  Within about one ulp.
+// a b + c as one three-address FMA (on the device, v_fma_f64 with all
+// operands in vector registers: the compiler otherwise ties the addend to
+// the result and copies loop-invariant addends on every use)
+SCVT_HD double fma3(double a, double b, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double d;
+  __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+#else
+  return fma(a, b, c);
+#endif
+}
+
+// keeps x in a vector register from here on: a loop that uses a kernel
+// argument as an FMA addend otherwise copies it from its scalar register at
+// every iteration
+SCVT_HD void pin_v(double& x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __asm__ volatile("" : "+v"(x));
+#endif
+}
+
+// 2^(u/64) for u in [-64 * 1021, 64 * 1009] (callers clamp), table-driven
+// (Tang's method in base 2): u = 64 m + j + f with k = rint(u), j = k mod 64,
+// m = floor(k / 64) and f = u - k exact, |f| <= 1/2, so
+// 2^(u/64) = 2^m 2^(j/64) exp(x) with x = f ln2/64, |x| <= ln2/128, and
+// exp(x) - 1 is the degree-5 Taylor polynomial written in f (truncation
+// error below 4e-17).  Within about one ulp of 2^(u/64) for the double u.
 // tab: the 2^(j/64) table or a copy of it (in LDS on the device)
-SCVT_HD double exp_tab(double t, const double* tab = SCVT_EXP2_TAB) {
-  const double k = rint(t * kExpInvLn);
-  double r = fma(-k, kExpLnHi, t);
-  r = fma(-k, kExpLnLo, r);
+SCVT_HD double exp2_64(double u, const double* tab = SCVT_EXP2_TAB) {
+  const double k = rint(u);
+  const double f = u - k;
   const int ki = (int)k;
   const int j = ki & 63;
   const int m = ki >> 6;  // floor(ki / 64): arithmetic shift
-  // exp(r) - 1 = r + r^2 (1/2 + r/6) + r^4 (1/24 + r/120)
-  const double r2 = r * r;
-  const double lo = fma(r, 1.0 / 6.0, 0.5), hi = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-  const double p = fma(r2, fma(r2, hi, lo), r);
+  const double p = f * fma3(f, fma3(f, fma3(f, fma3(f, kExpC5, kExpC4), kExpC3), kExpC2), kExpC1);
   const double T = tab[j];
   return ldexp(fma(T, p, T), m);
 }
+constexpr double kU64Min = -64.0 * 1021, kU64Max = 64.0 * 1009;
 
 SCVT_HD double chord_to_angle(double ch) {
   double s = 0.5 * ch;
   return 2.0 * asin(s > 1.0 ? 1.0 : s);
 }
 
-// Newton-refined reciprocal for 1 <= x < 2^1012 (two steps from the
-// hardware estimate: a few ulp, no division sequence); the host build
-// divides
-SCVT_HD double rcp_refined(double x) {
+// Reciprocal for 1 <= x < 2^1010: one Newton step from the hardware
+// estimate (relative error at most 2^-23), so within 2^-46 = 1.4e-14; the
+// host build divides
+SCVT_HD double rcp_nr(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 #else
   return 1.0 / x;
+#endif
+}
+
+// sqrt(x) for x >= 0 (x = 0 gives 0): x r (1 + e/2) with r the hardware
+// estimate of 1/sqrt(max(x, 1e-300)) (relative error at most 2^-23) and
+// e = 1 - x r^2; the dropped term 3e^2/8 bounds the error by 2.2e-14.  The
+// host build calls sqrt.
+SCVT_HD double sqrt_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rsq(fmax(x, 1e-300));
+  const double xr = x * r;
+  return fma(xr * fma(-xr, r, 1.0), 0.5, xr);
+#else
+  return ::sqrt(x);
 #endif
 }
 
@@ -303,12 +341,13 @@ SCVT_HD double rcp_refined(double x) {
 // distance built from the latitude/longitude-swapped points.
 // (tanh(x) + 1)/2 is evaluated as the equal 1/(1 + exp(-2x)), which does not
 // cancel where tanh is close to -1 (far from a bump, where rho ~ gamma).
-// The exponent is clamped to [-708, 700]: below, exp(t) is under 1e-307 and
-// the bump equals amp; above, the bump is below 1e-304 amp.
-SCVT_HD double bump(double amp, double beta, double k2, double d,
-                    const double* tab = SCVT_EXP2_TAB) {
-  const double t = fmin(fmax((beta - d) * k2, -708.0), 700.0);
-  return amp * rcp_refined(1.0 + exp_tab(t, tab));
+// The bump's logistic 1/(1 + exp(t)), t = 2 (d - beta)/alpha, is evaluated
+// in base 2 from u = t 64/ln2 = K (d - beta) with K = 128/(alpha ln2), one
+// fused product with bK = -beta K, clamped to [-64 1021, 64 1009]: below,
+// exp(t) is under 5e-308 and the logistic is 1; above, it is below 2e-304.
+SCVT_HD double logistic(double bK, double K, double d, const double* tab = SCVT_EXP2_TAB) {
+  const double u = fmin(fmax(fma3(d, K, bK), kU64Min), kU64Max);
+  return rcp_nr(1.0 + exp2_64(u, tab));
 }
 
 // Density variants, each compiled separately so that a kernel carries only
@@ -327,10 +366,9 @@ SCVT_HD double rho_kind(const DensityP& D, V3 y, const double* tab = SCVT_EXP2_T
     for (int k = 0; k < NB; k++) {
       V3 c = V3{D.xc[k][0], D.xc[k][1], D.xc[k][2]};
       V3 t = y - c;
-      double t2 = dot(t, t);
-      double d = t2 * rsq_pos(fmax(t2, 1e-300));  // 0 at t2 = 0
+      double d = sqrt_nr(dot(t, t));
       if (KIND & kVarGeo) d = chord_to_angle(d);
-      rho += bump(D.amp[k], D.beta[k], D.k2[k], d, tab);
+      rho = fma3(logistic(D.bK[k], D.K[k], d, tab), D.amp[k], rho);
     }
     return rho;
   }
@@ -349,7 +387,7 @@ SCVT_HD double rho_kind(const DensityP& D, V3 y, const double* tab = SCVT_EXP2_T
   double d1 = chord_to_angle(sqrt(dot(t1, t1)));
   double d2 = chord_to_angle(sqrt(dot(t2, t2)));
   double d = sqrt(d1 * d1 / (D.w_lon * D.w_lon) + d2 * d2 / (D.w_lat * D.w_lat));
-  return bump(D.amp[0], D.beta[0], D.k2[0], d, tab) + D.gamma;
+  return fma3(logistic(D.bK[0], D.K[0], d, tab), D.amp[0], D.gamma);
 }
 
 // variant index of a density
@@ -440,9 +478,10 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
     double wt = hd * R[q][3] * jac * rho_kind<KIND>(D, y, tab);
     V3 dy = y - z;
     acc.m += wt;
-    acc.mx += wt * y.x;
-    acc.my += wt * y.y;
-    acc.mz += wt * y.z;
+    const double wr = wt * ri;  // first moment: wt y = (wt ri) p
+    acc.mx += wr * p.x;
+    acc.my += wr * p.y;
+    acc.mz += wr * p.z;
     acc.e += wt * dot(dy, dy);
   }
 }

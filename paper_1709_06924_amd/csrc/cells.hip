@@ -17,10 +17,11 @@
 //   a predicate within its error bound, go to a list for
 // k_fallback: a sequential half-space clipper run by lane 0 (no size limit:
 //   any cell the sphere allows), writing the same slot.
-// k_quad: two cells per wavefront: fan triangles (z, v_lo, v_hi), each split
-//   into 4^levels geodesic sub-triangles with the triangle rule, one (edge,
-//   sub-triangle) item per lane; m, mu, e per cell (g, h and the Lloyd step
-//   of section 3.1 follow in the evaluation's reduction pass).
+// k_quad: one cell per half-wave, cells sorted by degree within a block:
+//   fan triangles (z, v_lo, v_hi), each split into 4^levels geodesic
+//   sub-triangles with the triangle rule, one (edge, sub-triangle) item per
+//   lane; m, mu, e per cell (g, h and the Lloyd step of section 3.1 follow
+//   in the evaluation's reduction pass).
 #include "kernels.h"
 
 namespace scvt {
@@ -475,14 +476,17 @@ __global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
 }
 
 // -------------------------------------------------------------- quadrature
-// One wave per pair of cells (index order): the (edge, leaf) items of both
-// cells form one list -- about 3 full rounds of 64 lanes for two hexagons
-// instead of 2 rounds at 75% for one -- and every lane adds each item into
-// the accumulator of the cell it belongs to.  The five sums of each cell are
-// reduced across the wave in a fixed butterfly order, so results do not
-// depend on scheduling.  MIXED: FP32 points in the generator's local frame
-// (quad_tri_mixed), FP64 sub-triangle vertices, accumulation and epilogue.
-// m, mu, e of the cell (g, h and the Lloyd step follow in k_eval_reduce)
+// 64 cells per block of four waves.  The block first sorts its cells by
+// degree (counting sort in LDS); each wave then takes eight pairs of
+// neighbours in that order, one cell per half-wave, so that the two cells of
+// a pair mostly have the same degree and finish in the same round.  A
+// half-wave covers its cell's (edge, sub-triangle) items 32 at a time, adds
+// each into one accumulator per lane, and sums its 32 lanes in a fixed
+// butterfly order: a cell's result depends neither on its partner nor on
+// the sort nor on the schedule.  MIXED: FP32 points in the generator's local
+// frame (quad_tri_mixed), FP64 sub-triangle vertices, accumulation and
+// epilogue.  Writes m, mu, e of the cell (g, h and the Lloyd step follow in
+// k_eval_reduce).
 template <bool MIXED>
 __device__ inline void cell_epilogue(const EvalOut& o, int64_t i, V3 z, Acc5 acc) {
   V3 mu = V3{acc.mx, acc.my, acc.mz};
@@ -494,48 +498,24 @@ __device__ inline void cell_epilogue(const EvalOut& o, int64_t i, V3 z, Acc5 acc
   o.mu[3 * i + 2] = mu.z;
 }
 
-// Sums over the wave of a (on lanes 0-31) and b (on lanes 32-63): the
-// first butterfly step swaps halves so that each half then reduces one of
-// the two; the additions are those of two full butterflies (same bits).
-__device__ inline double pair_sum(double a, double b) {
-  const bool hi = lane_id() >= 32;
-  double v = (hi ? b : a) + __shfl_xor(hi ? a : b, 32, 64);
+// sum over each half-wave (lanes 0-31 and 32-63 separately)
+__device__ inline double half_sum(double v) {
   for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
-}
-__device__ inline Acc5 pair_sum5(const Acc5& a, const Acc5& b) {
-  return Acc5{pair_sum(a.m, b.m), pair_sum(a.mx, b.mx), pair_sum(a.my, b.my),
-              pair_sum(a.mz, b.mz), pair_sum(a.e, b.e)};
 }
 
 template <int KIND, bool MIXED>
 __device__ inline void quad_item(const CellArgs& a, V3 A, V3 B, V3 C, V3 z, const DensityF& Df,
-                                 const double* tab, Acc5& part) {
+                                 const double* tab, Acc5& acc) {
   if (MIXED) {
     F3 zc[2];
     for (int k = 0; k < 2; k++)
       zc[k] = to_f3(z - V3{a.rho.xc[k][0], a.rho.xc[k][1], a.rho.xc[k][2]});
-    quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), to_f3(z), zc, Df, a.rho, part,
+    quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), to_f3(z), zc, Df, a.rho, acc,
                          a.quad_rule);
   } else {
-    quad_tri_k<KIND>(A, B, C, z, a.rho, part, tab, a.quad_rule);
+    quad_tri_k<KIND>(A, B, C, z, a.rho, acc, tab, a.quad_rule);
   }
-}
-
-// add an item into its cell: f * part with f in {0, 1} adds exactly part or
-// exactly zero, without selecting between accumulators
-__device__ inline void add_item(bool second, const Acc5& part, Acc5& acc0, Acc5& acc1) {
-  const double f0 = second ? 0.0 : 1.0, f1 = 1.0 - f0;
-  acc0.m = fma(f0, part.m, acc0.m);
-  acc0.mx = fma(f0, part.mx, acc0.mx);
-  acc0.my = fma(f0, part.my, acc0.my);
-  acc0.mz = fma(f0, part.mz, acc0.mz);
-  acc0.e = fma(f0, part.e, acc0.e);
-  acc1.m = fma(f1, part.m, acc1.m);
-  acc1.mx = fma(f1, part.mx, acc1.mx);
-  acc1.my = fma(f1, part.my, acc1.my);
-  acc1.mz = fma(f1, part.mz, acc1.mz);
-  acc1.e = fma(f1, part.e, acc1.e);
 }
 
 // Two subdivision levels (the configured rule): the 16 lanes of an edge
@@ -546,91 +526,109 @@ __device__ inline void add_item(bool second, const Acc5& part, Acc5& acc0, Acc5&
 struct QuadLds {
   double p[4][15][3];  // per wave: the grids of the round's four edges
 };
+constexpr int kQuadCells = 64;  // cells per block: eight pairs per wave
 
 template <int KIND, bool MIXED>
 __global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
   __shared__ QuadLds lds[4];
   __shared__ double tab[64];  // the exponential's 2^(j/64) table
-  if (threadIdx.x < 64) tab[threadIdx.x] = kExp2Tab[threadIdx.x];
-  __syncthreads();
-  const int ln = lane_id();
-  const int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;
-  if (i0 >= a.n) return;
-  const int64_t i1 = i0 + 1;
-  const bool has1 = i1 < a.n;
+  __shared__ int bin[kVmax + 1];
+  __shared__ int list[kQuadCells];
+  const int tid = threadIdx.x;
   const EvalOut& o = a.out;
-  const V3 z0 = V3{a.Z[3 * i0], a.Z[3 * i0 + 1], a.Z[3 * i0 + 2]};
-  const V3 z1 = has1 ? V3{a.Z[3 * i1], a.Z[3 * i1 + 1], a.Z[3 * i1 + 2]} : z0;
-  const int lv = a.levels;
-  const int per = 1 << (2 * lv);
-  const int tot0 = o.deg[i0] * per;
-  const int total = tot0 + (has1 ? o.deg[i1] * per : 0);
-  Acc5 acc0 = {0.0, 0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-  DensityF Df{};
-  if (MIXED) Df = density_f32(a.rho);
-  if (lv == 2) {
-    double(*G)[3] = lds[threadIdx.x >> 6].p[ln >> 4];  // this lane's edge grid
-    const int s = ln & 15;
-    for (int t0 = 0; t0 < total; t0 += 64) {  // whole edges per round: total = 16 sum(deg)
-      const int t = t0 + ln;
-      const bool valid = t < total;
-      const bool second = t >= tot0;
-      const int local = second ? t - tot0 : t;
-      const int64_t i = second ? i1 : i0;
-      const V3 z = second ? z1 : z0;
-      const int e = local >> 4;
-      if (valid && s < 3) {  // corners A = z (14), B = v_lo (4), C = v_hi (0)
-        const double* ed = o.edges + (i * kVmax + e) * 6;
-        const V3 P = s == 0 ? z : (s == 1 ? V3{ed[0], ed[1], ed[2]} : V3{ed[3], ed[4], ed[5]});
-        const int k = s == 0 ? 14 : (s == 1 ? 4 : 0);
-        G[k][0] = P.x;
-        G[k][1] = P.y;
-        G[k][2] = P.z;
-      }
-      wave_sync();
-      for (int level = 0; level < 2; level++) {
-        const int task = level == 0 ? s : 3 + s;
-        if (valid && s < (level == 0 ? 3 : 9)) {
-          const int kp = nib(kG2TaskP, task), kq = nib(kG2TaskQ, task), km = nib(kG2TaskPt, task);
-          const V3 m = normalized_fast(V3{G[kp][0], G[kp][1], G[kp][2]} +
-                                       V3{G[kq][0], G[kq][1], G[kq][2]});
-          G[km][0] = m.x;
-          G[km][1] = m.y;
-          G[km][2] = m.z;
-        }
-        wave_sync();
-      }
-      if (valid) {
-        const int ka = nib(kG2LeafA, s), kb = nib(kG2LeafB, s), kc = nib(kG2LeafC, s);
-        const V3 A = V3{G[ka][0], G[ka][1], G[ka][2]};
-        const V3 B = V3{G[kb][0], G[kb][1], G[kb][2]};
-        const V3 C = V3{G[kc][0], G[kc][1], G[kc][2]};
-        Acc5 part = {0.0, 0.0, 0.0, 0.0, 0.0};
-        quad_item<KIND, MIXED>(a, A, B, C, z, Df, tab, part);
-        add_item(second, part, acc0, acc1);
-      }
-      wave_sync();  // the next round rewrites the grids
-    }
-  } else {
-    for (int t = ln; t < total; t += 64) {
-      const bool second = t >= tot0;
-      const int local = second ? t - tot0 : t;
-      const int64_t i = second ? i1 : i0;
-      const V3 z = second ? z1 : z0;
-      const int e = local >> (2 * lv), s = local & (per - 1);
-      const double* ed = o.edges + (i * kVmax + e) * 6;
-      V3 A = z;
-      V3 B = V3{ed[0], ed[1], ed[2]};
-      V3 C = V3{ed[3], ed[4], ed[5]};
-      subtriangle(A, B, C, s, lv);
-      Acc5 part = {0.0, 0.0, 0.0, 0.0, 0.0};
-      quad_item<KIND, MIXED>(a, A, B, C, z, Df, tab, part);
-      add_item(second, part, acc0, acc1);
+  const int64_t base = (int64_t)blockIdx.x * kQuadCells;
+  const int ncell = a.n - base < kQuadCells ? (int)(a.n - base) : kQuadCells;
+  if (tid < 64) tab[tid] = kExp2Tab[tid];
+  if (tid <= kVmax) bin[tid] = 0;
+  __syncthreads();
+  const int dme = tid < ncell ? min(max(o.deg[base + tid], 0), kVmax) : 0;
+  if (tid < ncell) atomicAdd(&bin[dme], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int b = 0; b <= kVmax; b++) {
+      const int c = bin[b];
+      bin[b] = run;
+      run += c;
     }
   }
-  const Acc5 tot = pair_sum5(acc0, acc1);
-  if (ln == 0 || (ln == 32 && has1))  // one code path for both cells
-    cell_epilogue<MIXED>(o, ln == 0 ? i0 : i1, ln == 0 ? z0 : z1, tot);
+  __syncthreads();
+  if (tid < ncell) list[atomicAdd(&bin[dme], 1)] = tid;
+  __syncthreads();
+
+  const int ln = lane_id(), w = tid >> 6, hl = ln & 31;
+  const int lv = a.levels, per = 1 << (2 * lv);
+  CellArgs ar = a;  // density constants held in vector registers
+  pin_v(ar.rho.gamma);
+  for (int k = 0; k < 2; k++) {
+    pin_v(ar.rho.K[k]);
+    pin_v(ar.rho.bK[k]);
+    pin_v(ar.rho.amp[k]);
+  }
+  DensityF Df{};
+  if (MIXED) Df = density_f32(a.rho);
+  double(*G)[3] = lds[w].p[ln >> 4];  // this lane's edge grid
+  const int s = ln & 15;
+  for (int pr = 0; pr < kQuadCells / 8; pr++) {
+    const int slot = (pr * 4 + w) * 2 + (ln >> 5);
+    const bool has = slot < ncell;
+    const int64_t i = base + (has ? list[slot] : 0);
+    const int d = has ? min(max(o.deg[i], 0), kVmax) : 0;
+    const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
+    const int items = d * per;  // this half's (edge, sub-triangle) items
+    const int both = max(items, __shfl_xor(items, 32, 64));
+    if (both == 0) continue;  // wave-uniform
+    Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (lv == 2) {
+      for (int t0 = 0; t0 < both; t0 += 32) {  // two whole edges per half and round
+        const int t = t0 + hl;
+        const bool valid = t < items;
+        const int e = t >> 4;
+        if (valid && s < 3) {  // corners A = z (14), B = v_lo (4), C = v_hi (0)
+          const double* ed = o.edges + (i * kVmax + e) * 6;
+          const V3 P = s == 0 ? z : (s == 1 ? V3{ed[0], ed[1], ed[2]} : V3{ed[3], ed[4], ed[5]});
+          const int k = s == 0 ? 14 : (s == 1 ? 4 : 0);
+          G[k][0] = P.x;
+          G[k][1] = P.y;
+          G[k][2] = P.z;
+        }
+        wave_sync();
+        for (int level = 0; level < 2; level++) {
+          const int task = level == 0 ? s : 3 + s;
+          if (valid && s < (level == 0 ? 3 : 9)) {
+            const int kp = nib(kG2TaskP, task), kq = nib(kG2TaskQ, task), km = nib(kG2TaskPt, task);
+            const V3 m = normalized_fast(V3{G[kp][0], G[kp][1], G[kp][2]} +
+                                         V3{G[kq][0], G[kq][1], G[kq][2]});
+            G[km][0] = m.x;
+            G[km][1] = m.y;
+            G[km][2] = m.z;
+          }
+          wave_sync();
+        }
+        if (valid) {
+          const int ka = nib(kG2LeafA, s), kb = nib(kG2LeafB, s), kc = nib(kG2LeafC, s);
+          const V3 A = V3{G[ka][0], G[ka][1], G[ka][2]};
+          const V3 B = V3{G[kb][0], G[kb][1], G[kb][2]};
+          const V3 C = V3{G[kc][0], G[kc][1], G[kc][2]};
+          quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
+        }
+        wave_sync();  // the next round rewrites the grids
+      }
+    } else {
+      for (int t = hl; t < items; t += 32) {
+        const int e = t >> (2 * lv), sub = t & (per - 1);
+        const double* ed = o.edges + (i * kVmax + e) * 6;
+        V3 A = z;
+        V3 B = V3{ed[0], ed[1], ed[2]};
+        V3 C = V3{ed[3], ed[4], ed[5]};
+        subtriangle(A, B, C, sub, lv);
+        quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
+      }
+    }
+    const Acc5 tot = {half_sum(acc.m), half_sum(acc.mx), half_sum(acc.my), half_sum(acc.mz),
+                      half_sum(acc.e)};
+    if (hl == 0 && has) cell_epilogue<MIXED>(o, i, z, tot);
+  }
 }
 
 // small problems: every cell goes through the fallback clipper
@@ -662,7 +660,7 @@ hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s) {
 }
 
 hipError_t launch_quad(const CellArgs& a, hipStream_t s) {
-  const unsigned nb = (unsigned)((a.n + 7) / 8);  // two cells per wave, four waves per block
+  const unsigned nb = (unsigned)((a.n + kQuadCells - 1) / kQuadCells);
 #define SCVT_LAUNCH_QUAD(V)                                  \
   do {                                                       \
     if (a.mixed)                                             \

@@ -142,10 +142,10 @@ def home_face(Pts):
     return out
 
 
-def exp_tab(t):
-    t = np.ascontiguousarray(t, dtype=np.float64)
-    out = np.zeros_like(t)
-    lib().hc_exp(ctypes.c_int64(len(t)), P(t), P(out))
+def exp2_64(u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros_like(u)
+    lib().hc_exp(ctypes.c_int64(len(u)), P(u), P(out))
     return out
 
 

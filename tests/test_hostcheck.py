@@ -233,18 +233,22 @@ def test_mixed_quadrature_error(density):
 
 
 def test_exp_table_accuracy():
-    """The table-driven exponential of the FP64 density agrees with the C
-    library's exp within two ulp over the whole clamped range."""
+    """The table-driven exponential 2^(u/64) of the FP64 density agrees with
+    an extended-precision evaluation within two ulp over the whole clamped
+    range [-64 1021, 64 1009], and is exact at the table's own points."""
     rng = np.random.default_rng(5)
-    t = np.concatenate([rng.uniform(-708.0, 700.0, 100000), rng.uniform(-1.0, 1.0, 100000),
-                        rng.uniform(-30.0, 30.0, 100000),
-                        [0.0, -708.0, 700.0, 1e-300, -1e-300, math.log(2) / 128,
-                         -math.log(2) / 128, math.log(2) / 64, 0.5 * math.log(2)]])
-    got = hc.exp_tab(t)
-    ref = np.array([math.exp(x) for x in t])
-    rel = np.abs(got - ref) / ref
-    assert rel.max() < 5e-16, rel.max()
-    assert got[-9] == 1.0 and got[-6] == 1.0  # t = 0 and t = 1e-300
+    lo, hi = -64.0 * 1021, 64.0 * 1009
+    u = np.concatenate([rng.uniform(lo, hi, 100000), rng.uniform(-100.0, 100.0, 100000),
+                        rng.uniform(-3000.0, 3000.0, 100000),
+                        [0.0, lo, hi, 1e-300, -1e-300, 0.5, -0.5, 64.0, -64.0, 32.0, 0.4999999]])
+    got = hc.exp2_64(u)
+    ln2_64 = np.log(np.longdouble(2)) / 64
+    ref = np.exp(u.astype(np.longdouble) * ln2_64)
+    rel = np.abs((got.astype(np.longdouble) - ref) / ref).astype(np.float64)
+    assert rel.max() < 4.5e-16, rel.max()
+    assert got[-11] == 1.0 and got[-8] == 1.0                 # u = 0 and u = 1e-300
+    assert got[-4] == 2.0 and got[-3] == 0.5                  # u = +-64: exact powers of two
+    assert got[-10] == 2.0 ** -1021 and got[-9] == 2.0 ** 1009
 
 
 def test_grid2_leaves_equal_recursive_subdivision():
