@@ -225,7 +225,7 @@ struct DensityP {
   double beta[2], alpha[2], amp[2];
   double gamma, w_lon, w_lat;
   // filled by density_prepare: k2 = -2 / alpha_k, and the base-2 exponent's
-  // K = 128/(alpha_k ln2) and bK = -beta_k K
+  // K = 2N/(alpha_k ln2) and bK = -beta_k K (N = kExpN)
   double k2[2], K[2], bK[2];
 };
 
@@ -284,24 +284,30 @@ SCVT_HD void pin_v(double& x) {
 #endif
 }
 
-// 2^(u/64) for u in [-64 * 1021, 64 * 1009] (callers clamp), table-driven
-// (Tang's method in base 2): u = 64 m + j + f with k = rint(u), j = k mod 64,
-// m = floor(k / 64) and f = u - k exact, |f| <= 1/2, so
-// 2^(u/64) = 2^m 2^(j/64) exp(x) with x = f ln2/64, |x| <= ln2/128, and
-// exp(x) - 1 is the degree-5 Taylor polynomial written in f (truncation
-// error below 4e-17).  Within about one ulp of 2^(u/64) for the double u.
-// tab: the 2^(j/64) table or a copy of it (in LDS on the device)
-SCVT_HD double exp2_64(double u, const double* tab = SCVT_EXP2_TAB) {
+// 2^(u/N), N = kExpN = 128, for u <= N * 1009 (callers cap), table-driven
+// (Tang's method in base 2): u = N m + j + f with k = rint(u), j = k mod N,
+// m = floor(k / N) and f = u - k exact, |f| <= 1/2, so
+// 2^(u/N) = 2^m 2^(j/N) exp(x) with x = f ln2/N, |x| <= ln2/256, and
+// exp(x) - 1 is the degree-4 Taylor polynomial written in f (truncation
+// error below 1.3e-15).  Below u = -1074 N the result underflows to 0 (the
+// integer k saturates beyond 2^31, where f = 0 and 2^m is still 0).
+// tab: the 2^(j/N) table or a copy of it (in LDS on the device)
+SCVT_HD double exp2_n(double u, const double* tab = SCVT_EXP2_TAB) {
   const double k = rint(u);
   const double f = u - k;
-  const int ki = (int)k;
-  const int j = ki & 63;
-  const int m = ki >> 6;  // floor(ki / 64): arithmetic shift
-  const double p = f * fma3(f, fma3(f, fma3(f, fma3(f, kExpC5, kExpC4), kExpC3), kExpC2), kExpC1);
+#if defined(__HIP_DEVICE_COMPILE__)
+  const int ki = (int)k;  // the conversion saturates
+#else
+  const int ki = (int)fmax(k, -2147483648.0);  // the same, without undefined behaviour
+#endif
+  const int j = ki & (kExpN - 1);
+  const int m = ki >> 7;  // floor(ki / N): arithmetic shift
+  static_assert(kExpN == 128, "table size");
+  const double p = f * fma3(f, fma3(f, fma3(f, kExpC4, kExpC3), kExpC2), kExpC1);
   const double T = tab[j];
   return ldexp(fma(T, p, T), m);
 }
-constexpr double kU64Min = -64.0 * 1021, kU64Max = 64.0 * 1009;
+constexpr double kUMax = 128.0 * 1009;
 
 SCVT_HD double chord_to_angle(double ch) {
   double s = 0.5 * ch;
@@ -342,12 +348,13 @@ SCVT_HD double sqrt_nr(double x) {
 // (tanh(x) + 1)/2 is evaluated as the equal 1/(1 + exp(-2x)), which does not
 // cancel where tanh is close to -1 (far from a bump, where rho ~ gamma).
 // The bump's logistic 1/(1 + exp(t)), t = 2 (d - beta)/alpha, is evaluated
-// in base 2 from u = t 64/ln2 = K (d - beta) with K = 128/(alpha ln2), one
-// fused product with bK = -beta K, clamped to [-64 1021, 64 1009]: below,
-// exp(t) is under 5e-308 and the logistic is 1; above, it is below 2e-304.
+// in base 2 from u = t N/ln2 = K (d - beta) with K = 2N/(alpha ln2), one
+// fused product with bK = -beta K, capped at N 1009 (where the logistic is
+// below 2e-304; there is no lower cap: exp(t) underflows to 0 and the
+// logistic is 1).
 SCVT_HD double logistic(double bK, double K, double d, const double* tab = SCVT_EXP2_TAB) {
-  const double u = fmin(fmax(fma3(d, K, bK), kU64Min), kU64Max);
-  return rcp_nr(1.0 + exp2_64(u, tab));
+  const double u = fmin(fma3(d, K, bK), kUMax);
+  return rcp_nr(1.0 + exp2_n(u, tab));
 }
 
 // Density variants, each compiled separately so that a kernel carries only
@@ -540,6 +547,15 @@ SCVT_HD float rcpf(float x) {
 #endif
 }
 
+// (1 + s)^(-1/2) - 1 for |s| <= 2^-5 by its binomial series to degree 6:
+// the first dropped term is below 0.21 |s|^7, i.e. 0.42 |s|^6 <= 4e-10 of
+// the result
+SCVT_HD float rm1_series(float s) {
+  constexpr float c1 = -0.5f, c2 = 0.375f, c3 = -0.3125f, c4 = 0.2734375f, c5 = -0.24609375f,
+                  c6 = 0.2255859375f;
+  return s * fmaf(s, fmaf(s, fmaf(s, fmaf(s, fmaf(s, c6, c5), c4), c3), c2), c1);
+}
+
 struct DensityF {  // FP32 density parameters
   float gamma, w_lon2i, w_lat2i, pad;
   float amp[2], beta[2], k2l[2];  // k2l = -2 log2(e) / alpha
@@ -622,8 +638,14 @@ SCVT_HD void quad_tri_mixed(F3 dA, F3 dB, F3 dC, F3 zf, const F3* zc, const Dens
     const F3 d = F3{fmaf(l2, dCA.x, fmaf(l1, dBA.x, dA.x)), fmaf(l2, dCA.y, fmaf(l1, dBA.y, dA.y)),
                     fmaf(l2, dCA.z, fmaf(l1, dBA.z, dA.z))};
     float s = 2.0f * dotf(zf, d) + dotf(d, d);
-    float r = rsqf(1.0f + s);
-    float rm1 = -s * r * r * rcpf(1.0f + r);
+    float r, rm1;
+    if (fabsf(s) <= 0x1p-5f) {  // all but very large cells: no special functions
+      rm1 = rm1_series(s);
+      r = 1.0f + rm1;
+    } else {
+      r = rsqf(1.0f + s);
+      rm1 = -s * r * r * rcpf(1.0f + r);
+    }
     F3 dyz = r * d + rm1 * zf;
     float jac = r * r * r;
     float wt = hd * R[q][3] * jac * rho_kind_f<KIND>(D, zc, zf, dyz, Dd);

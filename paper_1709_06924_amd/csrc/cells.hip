@@ -531,14 +531,14 @@ constexpr int kQuadCells = 64;  // cells per block: eight pairs per wave
 template <int KIND, bool MIXED>
 __global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
   __shared__ QuadLds lds[4];
-  __shared__ double tab[64];  // the exponential's 2^(j/64) table
+  __shared__ double tab[kExpN];  // the exponential's 2^(j/N) table
   __shared__ int bin[kVmax + 1];
   __shared__ int list[kQuadCells];
   const int tid = threadIdx.x;
   const EvalOut& o = a.out;
   const int64_t base = (int64_t)blockIdx.x * kQuadCells;
   const int ncell = a.n - base < kQuadCells ? (int)(a.n - base) : kQuadCells;
-  if (tid < 64) tab[tid] = kExp2Tab[tid];
+  if (tid < kExpN) tab[tid] = kExp2Tab[tid];
   if (tid <= kVmax) bin[tid] = 0;
   __syncthreads();
   const int dme = tid < ncell ? min(max(o.deg[base + tid], 0), kVmax) : 0;

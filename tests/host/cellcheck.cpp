@@ -235,9 +235,9 @@ int hc_home_face(int64_t n, const double* P, int32_t* out) {
 }  // extern "C"
 
 extern "C" {
-// the table-driven exponential of the FP64 density path, 2^(u/64)
+// the table-driven exponential of the FP64 density path, 2^(u/128)
 int hc_exp(int64_t n, const double* u, double* out) {
-  for (int64_t k = 0; k < n; k++) out[k] = exp2_64(u[k]);
+  for (int64_t k = 0; k < n; k++) out[k] = exp2_n(u[k]);
   return 0;
 }
 }

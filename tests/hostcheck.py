@@ -142,7 +142,7 @@ def home_face(Pts):
     return out
 
 
-def exp2_64(u):
+def exp2_n(u):
     u = np.ascontiguousarray(u, dtype=np.float64)
     out = np.zeros_like(u)
     lib().hc_exp(ctypes.c_int64(len(u)), P(u), P(out))

@@ -233,22 +233,26 @@ def test_mixed_quadrature_error(density):
 
 
 def test_exp_table_accuracy():
-    """The table-driven exponential 2^(u/64) of the FP64 density agrees with
-    an extended-precision evaluation within two ulp over the whole clamped
-    range [-64 1021, 64 1009], and is exact at the table's own points."""
+    """The table-driven exponential 2^(u/128) of the FP64 density agrees with
+    an extended-precision evaluation within its bound (1.3e-15 truncation
+    plus rounding) from the largest argument down into the denormal range,
+    is exact at the table's own points, and underflows to 0 below."""
     rng = np.random.default_rng(5)
-    lo, hi = -64.0 * 1021, 64.0 * 1009
+    lo, hi = -128.0 * 1021, 128.0 * 1009
     u = np.concatenate([rng.uniform(lo, hi, 100000), rng.uniform(-100.0, 100.0, 100000),
                         rng.uniform(-3000.0, 3000.0, 100000),
-                        [0.0, lo, hi, 1e-300, -1e-300, 0.5, -0.5, 64.0, -64.0, 32.0, 0.4999999]])
-    got = hc.exp2_64(u)
-    ln2_64 = np.log(np.longdouble(2)) / 64
-    ref = np.exp(u.astype(np.longdouble) * ln2_64)
+                        [0.0, lo, hi, 1e-300, -1e-300, 0.5, -0.5, 128.0, -128.0, 64.0, 0.4999999]])
+    got = hc.exp2_n(u)
+    ln2_n = np.log(np.longdouble(2)) / 128
+    ref = np.exp(u.astype(np.longdouble) * ln2_n)
     rel = np.abs((got.astype(np.longdouble) - ref) / ref).astype(np.float64)
-    assert rel.max() < 4.5e-16, rel.max()
+    assert rel.max() < 1.6e-15, rel.max()
     assert got[-11] == 1.0 and got[-8] == 1.0                 # u = 0 and u = 1e-300
-    assert got[-4] == 2.0 and got[-3] == 0.5                  # u = +-64: exact powers of two
+    assert got[-4] == 2.0 and got[-3] == 0.5                  # u = +-128: exact powers of two
     assert got[-10] == 2.0 ** -1021 and got[-9] == 2.0 ** 1009
+    # denormal results and underflow, also where the integer part saturates
+    tiny = hc.exp2_n(np.array([-128.0 * 1030, -128.0 * 1080, -1e7, -3e9, -1e300]))
+    assert tiny[0] == 2.0 ** -1030 and np.all(tiny[1:] == 0.0)
 
 
 def test_grid2_leaves_equal_recursive_subdivision():
