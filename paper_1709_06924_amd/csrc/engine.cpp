@@ -76,9 +76,20 @@ struct scvt_handle {
   bool dry_run = false;
   size_t dry_bytes = 0;
   double ls_noise = 0.0;
+  // the last pushed pair joined the history on the assumption that it
+  // passes the curvature test; decided at the next host sync (resolve_push)
+  bool push_pending = false;
+  std::vector<int> ring_prev, free_prev;
+  bool dir_timer_pending = false;  // direction timer events awaiting a sync
 };
 
 namespace {
+
+// host-pinned scalar mirror: [0] g.q, [1..3] y.s, y.y, s.s of the last push,
+// [4..7] F, max |l|, sum |g|^2, min mu.z of the last evaluation (one copy of
+// the adjacent device scalars), [8..] the counters
+constexpr int kPinGQ = 0, kPinPush = 1, kPinEval = 4, kPinCtr = 8;
+static_assert(kPush == kGQ + 1 && kEval == kPush + 3, "adjacent device scalars");
 
 // partial-sum buffers, in units of reduce_grid_max() doubles
 enum : int { kPartPass = 0, kPartPush = 2, kPartEval = 5, kPartTotal = 9 };
@@ -263,9 +274,16 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   fa.out = h->dscal + kEval;
   HIPCK(launch_finalize(fa, st));
   if (tm) HIPCK(hipEventRecord(h->ev[4], st));
-  HIPCK(hipMemcpyAsync(h->pinned, h->dscal + kEval, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCK(hipMemcpyAsync(h->pinned + 8, h->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  // one copy brings g.q, the last push's curvature scalars and this
+  // evaluation's scalars (adjacent device scalars)
+  HIPCK(hipMemcpyAsync(h->pinned + kPinGQ, h->dscal + kGQ, 8 * sizeof(double),
+                       hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(h->pinned + kPinCtr, h->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
+  if (h->dir_timer_pending) {
+    timer_add(h, 3, h->ev[5], h->ev[6]);
+    h->dir_timer_pending = false;
+  }
   if (tm) {
     if (h->main_path) timer_add(h, 0, h->ev[1], h->ev[8]);
     if (h->main_path) timer_add(h, 6, h->ev[8], h->ev[2]);
@@ -275,11 +293,11 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
     timer_add(h, 5, h->ev[3], h->ev[7]);
   }
   Counters c;
-  memcpy(&c, h->pinned + 8, sizeof(Counters));
-  h->tF = h->pinned[0];
-  h->tstep = h->pinned[1];
-  h->tg2 = h->pinned[2];
-  h->tmz = h->pinned[3];
+  memcpy(&c, h->pinned + kPinCtr, sizeof(Counters));
+  h->tF = h->pinned[kPinEval];
+  h->tstep = h->pinned[kPinEval + 1];
+  h->tg2 = h->pinned[kPinEval + 2];
+  h->tmz = h->pinned[kPinEval + 3];
   h->tfb = c.n_fallback;
   h->tdeg = c.n_degenerate;
   if (c.n_duplicate > 0) return SCVT_E_DEGENERATE;
@@ -304,10 +322,10 @@ int geometry_with_neighbours(scvt_handle* h, const double* Zsrc, int32_t* nbr) {
     HIPCK(launch_cells_tiers(a, st));
   }
   HIPCK(launch_cells_fallback(a, h->main_path ? 0 : 1, st));
-  HIPCK(hipMemcpyAsync(h->pinned + 8, h->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(h->pinned + kPinCtr, h->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   Counters c;
-  memcpy(&c, h->pinned + 8, sizeof(Counters));
+  memcpy(&c, h->pinned + kPinCtr, sizeof(Counters));
   if (c.n_duplicate > 0) return SCVT_E_DEGENERATE;
   if (c.n_error > 0) return SCVT_E_CERT;
   return SCVT_OK;
@@ -346,7 +364,24 @@ void adopt_trial_scalars(scvt_handle* h) {
   h->n_deg = h->tdeg;
 }
 
-// P-LBFGS direction into h->q; g . q into *gq (one host sync).
+// g . q of the direction just launched: into *gq after a host sync, or, with
+// gq == nullptr, left on the device for the next evaluation's sync to bring
+// (the direction timer is taken then too)
+int finish_direction(scvt_handle* h, double* gq) {
+  if (!gq) {
+    h->dir_timer_pending = h->timing;
+    return SCVT_OK;
+  }
+  HIPCK(hipMemcpyAsync(h->pinned + kPinGQ, h->dscal + kGQ, sizeof(double), hipMemcpyDeviceToHost,
+                       h->stream));
+  HIPCK(hipStreamSynchronize(h->stream));
+  if (h->timing) timer_add(h, 3, h->ev[5], h->ev[6]);
+  h->dir_timer_pending = false;
+  *gq = h->pinned[kPinGQ];
+  return SCVT_OK;
+}
+
+// P-LBFGS direction into h->q; g . q as finish_direction.
 //
 // Up to kHmax pairs: the two recursions run on the history's inner products
 // (s_j.g from the last push, s_j.y_k kept as pairs arrive), so the vectors
@@ -396,11 +431,7 @@ int direction_fused(scvt_handle* h, const double* hv, double* gq) {
   f.nvals = 1;
   HIPCK(launch_hist_fin(f, st));
   if (h->timing) HIPCK(hipEventRecord(h->ev[6], st));
-  HIPCK(hipMemcpyAsync(h->pinned + 4, D + kGQ, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
-  if (h->timing) timer_add(h, 3, h->ev[5], h->ev[6]);
-  *gq = h->pinned[4];
-  return SCVT_OK;
+  return finish_direction(h, gq);
 }
 
 // s_j . g for the stored pairs and s_j . y_k (j older than k), recomputed
@@ -539,11 +570,7 @@ int direction_passes(scvt_handle* h, const double* hv, double* gq) {
   fa.out = D + kGQ;
   HIPCK(launch_finalize(fa, st));
   if (h->timing) HIPCK(hipEventRecord(h->ev[6], st));
-  HIPCK(hipMemcpyAsync(h->pinned + 4, D + kGQ, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
-  if (h->timing) timer_add(h, 3, h->ev[5], h->ev[6]);
-  *gq = h->pinned[4];
-  return SCVT_OK;
+  return finish_direction(h, gq);
 }
 
 // The initial inverse Hessian's diagonal: the Lloyd preconditioner h, or for
@@ -569,17 +596,23 @@ int lloyd_direction(scvt_handle* h, double* gq) {
   return h->M <= kHmax ? direction_fused(h, h->cur.h, gq) : direction_passes(h, h->cur.h, gq);
 }
 
-// Armijo backtracking along q from the current point; on success the trial
-// set holds the accepted evaluation.
-int line_search(scvt_handle* h, double gq, bool* accepted, double* alpha_out) {
-  double alpha = 1.0;
+// Armijo's sufficient decrease for the trial just evaluated at step alpha
+bool armijo(const scvt_handle* h, double alpha, double gq) {
+  return h->tF <= h->F + h->cfg.ls_c1 * alpha * gq + h->ls_noise * fabs(h->F);
+}
+
+// Armijo backtracking along q from the current point, from the k0-th
+// evaluation on (alpha = 2^-k0); on success the trial set holds the
+// accepted evaluation.
+int line_search(scvt_handle* h, double gq, int k0, bool* accepted, double* alpha_out) {
+  double alpha = ldexp(1.0, -k0);
   *accepted = false;
-  for (int k = 0; k < h->cfg.ls_max_evals; k++) {
+  for (int k = k0; k < h->cfg.ls_max_evals; k++) {
     HIPCK(launch_normalize_trial(h->Z, h->q, alpha, h->Zt, h->n, h->stream));
     int rc = evaluate(h, h->Zt, h->trial);
     h->n_evals++;
     if (rc < 0) return rc;
-    if (h->tF <= h->F + h->cfg.ls_c1 * alpha * gq + h->ls_noise * fabs(h->F)) {
+    if (armijo(h, alpha, gq)) {
       *accepted = true;
       *alpha_out = alpha;
       return SCVT_OK;
@@ -621,7 +654,7 @@ int push_pair(scvt_handle* h) {
       f.slot[j] = h->ring[j];
     }
     HIPCK(launch_push_ext(p, h->stream));
-    HIPCK(launch_hist_fin(f, h->stream));
+    HIPCK(launch_hist_fin(f, h->stream));  // also y.y into the slot's kYY entry
   } else {
     PushArgs p{};
     p.n3 = n3;
@@ -640,23 +673,48 @@ int push_pair(scvt_handle* h) {
     fa.out = h->dscal + kPush;
     fa.r_slot = h->dscal + kR + slot;
     HIPCK(launch_finalize(fa, h->stream));
+    HIPCK(hipMemcpyAsync(h->dscal + kYY + slot, h->dscal + kPush + 1, sizeof(double),
+                         hipMemcpyDeviceToDevice, h->stream));
   }
-  HIPCK(hipMemcpyAsync(h->dscal + kYY + slot, h->dscal + kPush + 1, sizeof(double),
-                       hipMemcpyDeviceToDevice, h->stream));
-  HIPCK(hipMemcpyAsync(h->pinned + 5, h->dscal + kPush, 3 * sizeof(double), hipMemcpyDeviceToHost,
-                       h->stream));
-  HIPCK(hipStreamSynchronize(h->stream));
-  double ys = h->pinned[5], yy = h->pinned[6], ss = h->pinned[7];
-  if (ys > h->cfg.curv_eps * sqrt(yy * ss)) {
-    h->free_slots.pop_back();
-    h->ring.push_back(slot);
-    if ((int)h->ring.size() > h->M) {
-      h->free_slots.push_back(h->ring.front());
-      h->ring.erase(h->ring.begin());
-    }
+  // The pair joins the history now; the curvature test (section 2.2.2: a
+  // pair enters only with y.s > 0) is taken at the next host sync, and
+  // resolve_push restores the history if it fails.
+  h->ring_prev = h->ring;
+  h->free_prev = h->free_slots;
+  h->free_slots.pop_back();
+  h->ring.push_back(slot);
+  if ((int)h->ring.size() > h->M) {
+    h->free_slots.push_back(h->ring.front());
+    h->ring.erase(h->ring.begin());
+  }
+  h->push_pending = true;
+  return SCVT_OK;
+}
+
+// Decides the pending push: y.s > curv_eps |y| |s| keeps the pair, anything
+// else restores the history as it was before the push (*undone).  synced:
+// the caller's last host sync already brought the scalars.
+int resolve_push(scvt_handle* h, bool synced, bool* undone) {
+  if (undone) *undone = false;
+  if (!h->push_pending) return SCVT_OK;
+  if (!synced) {
+    HIPCK(hipMemcpyAsync(h->pinned + kPinPush, h->dscal + kPush, 3 * sizeof(double),
+                         hipMemcpyDeviceToHost, h->stream));
+    HIPCK(hipStreamSynchronize(h->stream));
+  }
+  h->push_pending = false;
+  const double ys = h->pinned[kPinPush], yy = h->pinned[kPinPush + 1], ss = h->pinned[kPinPush + 2];
+  if (!(ys > h->cfg.curv_eps * sqrt(yy * ss))) {
+    h->ring = h->ring_prev;
+    h->free_slots = h->free_prev;
+    if (undone) *undone = true;
   }
   return SCVT_OK;
 }
+
+// every entry point other than the iteration loops starts from a decided
+// history
+int settle(scvt_handle* h) { return resolve_push(h, false, nullptr); }
 
 void clear_history(scvt_handle* h) {
   for (int s : h->ring) h->free_slots.push_back(s);
@@ -664,8 +722,7 @@ void clear_history(scvt_handle* h) {
 }
 
 int lloyd_step(scvt_handle* h) {
-  double gq = 0.0;
-  int rc = lloyd_direction(h, &gq);
+  int rc = lloyd_direction(h, nullptr);
   if (rc) return rc;
   HIPCK(launch_normalize_trial(h->Z, h->q, 1.0, h->Zt, h->n, h->stream));
   rc = evaluate(h, h->Zt, h->trial);
@@ -678,19 +735,40 @@ int lloyd_step(scvt_handle* h) {
   return SCVT_OK;
 }
 
-int do_step(scvt_handle* h) {
-  if (h->cfg.method == SCVT_METHOD_LLOYD) return lloyd_step(h);
-  double gq = 0.0;
-  int rc = direction(h, &gq);
-  if (rc) return rc;
-  if (!(gq < 0.0)) {  // not a descent direction: back to the Lloyd direction
+// One P-LBFGS (or plain LBFGS) iteration.  The first trial (alpha = 1) is
+// launched right behind the direction, so that one host sync -- the
+// evaluation's -- brings g.q, the trial's energy and the curvature scalars
+// of the previous push; the speculative parts (the previous pair's place in
+// the history, a direction that turns out not to descend) are redone in the
+// rare case they were wrong, and not counted as evaluations.
+int quasi_newton_step(scvt_handle* h) {
+  int rc;
+  for (;;) {
+    rc = direction(h, nullptr);
+    if (rc) return rc;
+    HIPCK(launch_normalize_trial(h->Z, h->q, 1.0, h->Zt, h->n, h->stream));
+    rc = evaluate(h, h->Zt, h->trial);
+    if (rc == SCVT_E_HIP) return rc;  // no scalars arrived
+    bool undone = false;
+    const int rc2 = resolve_push(h, true, &undone);
+    if (rc2) return rc2;
+    if (!undone) break;  // else: the direction used a pair the history does not hold
+  }
+  if (rc < 0) return rc;
+  double gq = h->pinned[kPinGQ];
+  bool ok = false;
+  double alpha = 1.0;
+  if (!(gq < 0.0)) {
+    // not a descent direction: back to the Lloyd direction (no history)
     clear_history(h);
     rc = direction(h, &gq);
     if (rc) return rc;
+    rc = line_search(h, gq, 0, &ok, &alpha);
+  } else {
+    h->n_evals++;
+    ok = armijo(h, 1.0, gq);
+    if (!ok) rc = line_search(h, gq, 1, &ok, &alpha);
   }
-  bool ok = false;
-  double alpha = 0.0;
-  rc = line_search(h, gq, &ok, &alpha);
   if (rc) return rc;
   if (!ok) {
     // No sufficient decrease along the direction within ls_max_evals
@@ -700,7 +778,7 @@ int do_step(scvt_handle* h) {
     // decreases F without a line search (section 2.2.1), and restart the
     // history from there.
     clear_history(h);
-    rc = lloyd_direction(h, &gq);
+    rc = lloyd_direction(h, nullptr);
     if (rc) return rc;
     HIPCK(launch_normalize_trial(h->Z, h->q, 1.0, h->Zt, h->n, h->stream));
     rc = evaluate(h, h->Zt, h->trial);
@@ -716,6 +794,14 @@ int do_step(scvt_handle* h) {
   h->alpha = alpha;
   h->iter++;
   return SCVT_OK;
+}
+
+// lazy: leave the last push's curvature test to the next iteration's sync
+// (the solve loops); otherwise decide it before returning
+int do_step(scvt_handle* h, bool lazy) {
+  int rc = h->cfg.method == SCVT_METHOD_LLOYD ? lloyd_step(h) : quasi_newton_step(h);
+  if (!rc && !lazy) rc = settle(h);
+  return rc;
 }
 
 void fill_info(scvt_handle* h, scvt_info* info, int status) {
@@ -903,7 +989,8 @@ int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt
 
 int scvt_step(scvt_handle* h, scvt_info* info) {
   if (!h) return SCVT_E_INVALID;
-  int rc = do_step(h);
+  int rc = settle(h);
+  if (!rc) rc = do_step(h, false);
   fill_info(h, info, rc);
   return rc;
 }
@@ -912,9 +999,11 @@ int scvt_solve(scvt_handle* h, int64_t max_iter, double tol, scvt_info* info) {
   if (!h) return SCVT_E_INVALID;
   int rc = SCVT_OK;
   while (!(h->step_inf < tol) && h->iter < max_iter) {
-    rc = do_step(h);
+    rc = do_step(h, true);
     if (rc) break;
   }
+  const int rs = settle(h);
+  if (!rc) rc = rs;
   if (!rc && !(h->step_inf < tol)) rc = SCVT_NOT_CONVERGED;
   fill_info(h, info, rc);
   return rc;
@@ -936,9 +1025,11 @@ int scvt_solve_rel(scvt_handle* h, int64_t max_iter, double step_tol, double gra
     if (done || h->iter >= max_iter) break;
     F_prev = h->F;
     have_prev = true;
-    rc = do_step(h);
+    rc = do_step(h, true);
     if (rc) break;
   }
+  const int rs = settle(h);
+  if (!rc) rc = rs;
   if (!rc && !done) rc = SCVT_NOT_CONVERGED;
   fill_info(h, info, rc);
   return rc;
@@ -995,7 +1086,8 @@ int scvt_get_vectors(scvt_handle* h, int which, double* out, int on_dev) {
 int scvt_direction(scvt_handle* h, double* out, int on_dev, double* gq) {
   if (!h) return SCVT_E_INVALID;
   double v = 0.0;
-  int rc = direction(h, &v);
+  int rc = settle(h);
+  if (!rc) rc = direction(h, &v);
   if (rc) return rc;
   if (gq) *gq = v;
   if (out) return scvt_get_vectors(h, 4, out, on_dev);
@@ -1147,6 +1239,8 @@ int scvt_get_cells(scvt_handle* h, int32_t max_deg, int32_t* nbr, int32_t* deg, 
 // double alpha, then Z (3n), then per ring entry oldest first: r, s (3n), y (3n)
 int scvt_get_state(scvt_handle* h, void* buf, size_t* bytes) {
   if (!h || !bytes) return SCVT_E_INVALID;
+  const int rs = settle(h);
+  if (rs) return rs;
   const int64_t n3 = 3 * h->n;
   const size_t c = h->ring.size();
   const size_t need = 8 * sizeof(int64_t) + sizeof(double) + n3 * sizeof(double) +
@@ -1202,6 +1296,7 @@ int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes) {
   p += sizeof(double);
   hipStream_t st = h->stream;
   HIPCK(hipStreamSynchronize(st));
+  h->push_pending = false;  // the restored history replaces it
   HIPCK(hipMemcpy(h->Z, p, n3 * sizeof(double), hipMemcpyHostToDevice));
   p += n3 * sizeof(double);
   clear_history(h);

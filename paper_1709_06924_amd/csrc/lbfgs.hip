@@ -385,6 +385,7 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_fin(HistFinArgs a) {
       D[kPush + 1] = red[1];
       D[kPush + 2] = red[2];
       D[kR + a.p] = 1.0 / red[0];
+      D[kYY + a.p] = red[1];
       D[kSG + a.p] = red[3];
       for (int j = 0; j < c; j++) {
         D[kSG + a.slot[j]] = red[4 + 2 * j];
