@@ -85,6 +85,33 @@ def recorded_traffic():
         return None
 
 
+VALU_KINDS = ["f64 fma", "f64 mul", "f64 rsq", "f64 rcp", "f64 ldexp", "f64 rndne", "f64 max",
+              "f32 fma", "f32 rsq", "f32 rcp", "f32 exp", "u32 add", "f64 rsq + 3 f64 fma",
+              "f32 rsq + 3 f64 fma"]
+
+
+def valu_rates():
+    """ns per wave-instruction per SIMD of each instruction kind, and the
+    FMA rates they imply (TFLOP/s over all SIMDs)."""
+    import ctypes
+
+    import torch
+
+    from paper_1709_06924_amd import build
+    torch.cuda.init()
+    lib = ctypes.CDLL(build.CALIB_LIB)
+    k = lib.scvt_calib_count()
+    ns = (ctypes.c_double * k)()
+    if lib.scvt_calib_valu(ns, 3) != 0:
+        raise RuntimeError("scvt_calib_valu failed")
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"ns_per_wave_instr_per_simd": {VALU_KINDS[i]: round(ns[i], 4) for i in range(k)},
+           "simds": simds}
+    for name, idx in (("f64_fma_tflops", 0), ("f32_fma_tflops", 7)):
+        out[name] = round(simds * 64 * 2 / (ns[idx] * 1e-9) / 1e12, 2)
+    return out
+
+
 def run_gpu(args, precision, Z0_dev, cfg, stream):
     import torch
 
@@ -167,6 +194,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--valu-rates", action="store_true",
+                    help="only measure vector-ALU instruction rates (libscvt_calib.so)")
     ap.add_argument("--no-mixed-errors", action="store_true",
                     help="skip the mixed-vs-FP64 evaluation errors at iterations 0/50/100/200")
     ap.add_argument("--source-hash", action="store_true",
@@ -187,6 +216,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
+        return
+    if args.valu_rates:
+        print(json.dumps(valu_rates()))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libscvt.so")
+CALIB_LIB = os.path.join(HERE, "libscvt_calib.so")  # measurement only (bench.py --valu-rates)
 SOURCES = ["grid.hip", "cells.hip", "lbfgs.hip", "mesh.hip", "engine.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
@@ -49,6 +50,13 @@ def build(verbose=False, jobs=4):
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    tmp = CALIB_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + COMMON + ["-x", "hip", "-shared", os.path.join(CSRC, "calib.hip"), "-o", tmp]
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if p.returncode != 0:
+        print(p.stdout.decode(errors="replace"), file=sys.stderr)
+        raise RuntimeError("hipcc failed (calib.hip)")
+    os.replace(tmp, CALIB_LIB)
     return LIB
 
 

@@ -36,6 +36,18 @@ def test_library_exports_every_declared_symbol():
     assert set(scvt.exported_symbols()) <= exported
 
 
+def test_calibration_library_exports_its_header():
+    from paper_1709_06924_amd import build
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "scvt_calib.h")).read(),
+                  flags=re.S)
+    names = sorted(set(re.findall(r"\b(scvt_[a-z_]+)\s*\(", text)))
+    assert names == ["scvt_calib_count", "scvt_calib_valu"]
+    lib = ctypes.CDLL(build.CALIB_LIB)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.scvt_calib_count() == 14  # no device work
+
+
 def test_config_defaults_and_validation_on_host():
     from paper_1709_06924_amd import scvt
     c = scvt.make_config(10)
