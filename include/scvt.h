@@ -133,6 +133,8 @@ typedef struct {
   int32_t hist_len;     /* stored pairs */
   int64_t n_lloyd_fallback; /* iterations that took the Lloyd step after the
                                line search found no sufficient decrease */
+  int64_t n_wide[2];    /* cells the 8-lane pass handed to the 16-lane pass,
+                           and that pass to the 64-lane one, last evaluation */
 } scvt_info;
 
 /* Fill *cfg with defaults for n generators: M = 7, FP64, rho = 1,

@@ -63,10 +63,10 @@ struct scvt_handle {
   std::vector<int> free_slots;
   // current state
   double F = 0, step_inf = 0, gnorm2 = 0, min_mz = 0, alpha = 0;
-  int64_t iter = 0, n_evals = 0, n_fb = 0, n_deg = 0, n_lloyd_fallback = 0;
+  int64_t iter = 0, n_evals = 0, n_fb = 0, n_deg = 0, n_lloyd_fallback = 0, n_wide[2] = {0, 0};
   // evaluation results of the last trial
   double tF = 0, tstep = 0, tg2 = 0, tmz = 0;
-  int64_t tfb = 0, tdeg = 0;
+  int64_t tfb = 0, tdeg = 0, twide[2] = {0, 0};
   bool timing = false;
   Timer timers[kTimers];
   hipEvent_t ev[9] = {};
@@ -300,6 +300,8 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   h->tmz = h->pinned[kPinEval + 3];
   h->tfb = c.n_fallback;
   h->tdeg = c.n_degenerate;
+  h->twide[0] = c.tier_count[0];
+  h->twide[1] = c.tier_count[1];
   if (c.n_duplicate > 0) return SCVT_E_DEGENERATE;
   if (c.n_error > 0) return SCVT_E_CERT;
   if (!(h->tF == h->tF) || !(h->tmz > 0.0)) return SCVT_E_NUMERIC;
@@ -362,6 +364,8 @@ void adopt_trial_scalars(scvt_handle* h) {
   h->min_mz = h->tmz;
   h->n_fb = h->tfb;
   h->n_deg = h->tdeg;
+  h->n_wide[0] = h->twide[0];
+  h->n_wide[1] = h->twide[1];
 }
 
 // g . q of the direction just launched: into *gq after a host sync, or, with
@@ -817,6 +821,8 @@ void fill_info(scvt_handle* h, scvt_info* info, int status) {
   info->status = status;
   info->hist_len = (int32_t)h->ring.size();
   info->n_lloyd_fallback = h->n_lloyd_fallback;
+  info->n_wide[0] = h->n_wide[0];
+  info->n_wide[1] = h->n_wide[1];
 }
 
 void destroy(scvt_handle* h) {
@@ -878,8 +884,10 @@ int init_device_state(scvt_handle* h) {
   const int64_t nc = h->grid.g.ncells;
   if (hipHostMalloc((void**)&h->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return SCVT_E_OOM;
+  // timing only, read after a stream synchronisation: no system-scope fence
+  // (which writes back and invalidates caches at every record)
   for (auto& e : h->ev)
-    if (hipEventCreate(&e) != hipSuccess) return SCVT_E_HIP;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return SCVT_E_HIP;
   hipStream_t st = h->stream;
   HIPCK(launch_fill_i32(h->grid.cnt_tot, 0, nc + 1, st));
   HIPCK(launch_fill_i32(h->grid.cnt_home, 0, nc + 1, st));

@@ -49,10 +49,13 @@ class Info(ctypes.Structure):
                 ("grad_norm2", ctypes.c_double), ("step_inf", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("n_fallback", ctypes.c_int64),
                 ("n_degenerate", ctypes.c_int64), ("status", ctypes.c_int32),
-                ("hist_len", ctypes.c_int32), ("n_lloyd_fallback", ctypes.c_int64)]
+                ("hist_len", ctypes.c_int32), ("n_lloyd_fallback", ctypes.c_int64),
+                ("n_wide", ctypes.c_int64 * 2)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["n_wide"] = list(d["n_wide"])
+        return d
 
 
 _vp, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
