@@ -33,6 +33,62 @@ SCVT_HD double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 SCVT_HD V3 cross(V3 a, V3 b) {
   return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
+// reciprocal square root: the device's correctly refined rsqrt, 1/sqrt on
+// the host build used by the CPU checks
+SCVT_HD double rsq(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ::rsqrt(x);
+#else
+  return 1.0 / ::sqrt(x);
+#endif
+}
+
+// 1/sqrt(x) for positive, finite, normal x: the hardware estimate r and one
+// second-order correction, r (1 + e/2 + 3e^2/8) with e = 1 - x r^2 (the
+// Taylor series of (1 - e)^(-1/2)); no special-value handling.  The host
+// build divides.
+SCVT_HD double rsq_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * r, r, 1.0);
+  return fma(r * e, fma(e, 0.375, 0.5), r);
+#else
+  return 1.0 / ::sqrt(x);
+#endif
+}
+
+// a / b and sqrt(x) where the geometry needs neither IEEE rounding nor
+// special values: the window and grid arithmetic (whose certified radius is
+// shrunk by far more than these errors), the Voronoi vertices (every cell
+// computes a shared vertex with the same formula, hence the same bits) and
+// norms inside error bounds.  The hardware estimates refined to about one
+// ulp: the reciprocal by two Newton steps (b normal, nonzero), the square
+// root as x rsq_pos(x) (x >= 0; 0 gives 0).  The host build divides and
+// calls sqrt.
+SCVT_HD double rcp_fast(double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return fma(r, fma(-b, r, 1.0), r);
+#else
+  return 1.0 / b;
+#endif
+}
+SCVT_HD double div_fast(double a, double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return a * rcp_fast(b);
+#else
+  return a / b;
+#endif
+}
+SCVT_HD double sqrt_fast(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return x * rsq_pos(fmax(x, 1e-300));
+#else
+  return ::sqrt(x);
+#endif
+}
+
 // a / |a| with one rounding per operation (no fused multiply-add): the same
 // bits as ((x*x + y*y) + z*z), sqrt, divide evaluated anywhere else
 SCVT_HD V3 normalized(V3 a) {
@@ -90,9 +146,9 @@ SCVT_HD Pred det_cached(const CrossCache& k, V3 l) {
 // equidistant from all three, on their side.  Computed from the triple in
 // increasing index order so that every cell that meets at the vertex gets the
 // same bits: normalize((p_b - p_a) x (p_c - p_a)), signed so that v . p_a > 0.
-// Evaluated without fused multiply-adds (one rounding per operation), so the
-// vertex of an ill-conditioned thin triple is the same bits as the plain
-// formula evaluated anywhere else.
+// The cross product is evaluated without fused multiply-adds (one rounding
+// per operation, as the plain formula); the normalisation multiplies by the
+// refined reciprocal square root (within about one ulp of the division).
 SCVT_HD V3 circumcentre(int ia, V3 pa, int ib, V3 pb, int ic, V3 pc) {
 #pragma clang fp contract(off)
   if (ia > ib) {
@@ -112,10 +168,10 @@ SCVT_HD V3 circumcentre(int ia, V3 pa, int ib, V3 pb, int ic, V3 pc) {
   double wx = uy * vz - uz * vy;
   double wy = uz * vx - ux * vz;
   double wz = ux * vy - uy * vx;
-  const double r = sqrt(wx * wx + wy * wy + wz * wz);
-  wx = wx / r;
-  wy = wy / r;
-  wz = wz / r;
+  const double ri = rsq_pos(wx * wx + wy * wy + wz * wz);
+  wx = wx * ri;
+  wy = wy * ri;
+  wz = wz * ri;
   if (wx * pa.x + wy * pa.y + wz * pa.z < 0.0) {
     wx = -wx;
     wy = -wy;
@@ -238,29 +294,6 @@ SCVT_HD DensityP density_prepare(DensityP d) {
   return d;
 }
 
-// reciprocal square root: the device's correctly refined rsqrt, 1/sqrt on
-// the host build used by the CPU checks
-SCVT_HD double rsq(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return ::rsqrt(x);
-#else
-  return 1.0 / ::sqrt(x);
-#endif
-}
-
-// 1/sqrt(x) for positive, finite, normal x: the hardware estimate r and one
-// second-order correction, r (1 + e/2 + 3e^2/8) with e = 1 - x r^2 (the
-// Taylor series of (1 - e)^(-1/2)); no special-value handling.  The host
-// build divides.
-SCVT_HD double rsq_pos(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  const double r = __builtin_amdgcn_rsq(x);
-  const double e = fma(-x * r, r, 1.0);
-  return fma(r * e, fma(e, 0.375, 0.5), r);
-#else
-  return 1.0 / ::sqrt(x);
-#endif
-}
 
 // a b + c as one three-address FMA (on the device, v_fma_f64 with all
 // operands in vector registers: the compiler otherwise ties the addend to
@@ -765,7 +798,8 @@ SCVT_HD int64_t cell_on_face(const GridP& g, V3 p, int f) {
   double n, u, v;
   face_local(p, f, n, u, v);
   if (!(n > 0.0)) return -1;
-  double fa = floor((u / n + g.U) * g.inv_du), fb = floor((v / n + g.U) * g.inv_du);
+  const double ni = rcp_fast(n);
+  double fa = floor((u * ni + g.U) * g.inv_du), fb = floor((v * ni + g.U) * g.inv_du);
   if (fa < 0.0 || fb < 0.0 || fa >= (double)g.W || fb >= (double)g.W) return -1;
   return cell_of(g, f, (int)fa, (int)fb);
 }
@@ -783,22 +817,22 @@ struct Window {
 // axis, at radius rho = sqrt(n^2 + w^2) from it, so the planes must be at
 // phi_z -+ delta with sin(delta) = st / rho; tan(phi_z -+ delta) in closed form.
 SCVT_HD void coord_bounds(double cz, double rho, double st, double& lo, double& hi) {
-  double s = st / rho;
+  double s = div_fast(st, rho);
   if (s >= 1.0) {
     lo = -1e300;
     hi = 1e300;
     return;
   }
-  double t = s / sqrt(1.0 - s * s);  // tan(delta)
+  double t = div_fast(s, sqrt_fast(1.0 - s * s));  // tan(delta)
   double dl = 1.0 + cz * t, dh = 1.0 - cz * t;
-  lo = dl > 0.0 ? (cz - t) / dl : -1e300;
-  hi = dh > 0.0 ? (cz + t) / dh : 1e300;
+  lo = dl > 0.0 ? div_fast(cz - t, dl) : -1e300;
+  hi = dh > 0.0 ? div_fast(cz + t, dh) : 1e300;
 }
 
 // sine of the angular distance from z (depth n, coordinate w) to the plane
 // c = cc through the face's other axis, signed positive on z's side (sgn)
 SCVT_HD double plane_sine(double n, double w, double cc, double sgn) {
-  return sgn * (w - cc * n) / sqrt(1.0 + cc * cc);
+  return sgn * (w - cc * n) * rsq_pos(1.0 + cc * cc);
 }
 
 // Smallest window around z (face f = home face) that covers the chord
@@ -809,13 +843,14 @@ SCVT_HD double plane_sine(double n, double w, double cc, double sgn) {
 SCVT_HD Window make_window(const GridP& g, V3 z, int f, double rt, int maxw) {
   double n, u, v;
   face_local(z, f, n, u, v);
-  const double uz = u / n, vz = v / n;
+  const double ni = rcp_fast(n);
+  const double uz = u * ni, vz = v * ni;
   double r = rt > 2.0 ? 2.0 : rt;
-  double st = r * sqrt(fmax(0.0, 1.0 - 0.25 * r * r));  // sin of the angular radius
-  if (rt >= 1.4142135623730951) st = 1.0;              // beyond 90 degrees: everything
+  double st = r * sqrt_fast(fmax(0.0, 1.0 - 0.25 * r * r));  // sin of the angular radius
+  if (rt >= 1.4142135623730951) st = 1.0;                   // beyond 90 degrees: everything
   double ulo, uhi, vlo, vhi;
-  coord_bounds(uz, sqrt(n * n + u * u), st, ulo, uhi);
-  coord_bounds(vz, sqrt(n * n + v * v), st, vlo, vhi);
+  coord_bounds(uz, sqrt_fast(n * n + u * u), st, ulo, uhi);
+  coord_bounds(vz, sqrt_fast(n * n + v * v), st, vlo, vhi);
   int ca = (int)floor((uz + g.U) * g.inv_du), cb = (int)floor((vz + g.U) * g.inv_du);
   ca = ca < 0 ? 0 : (ca >= g.W ? g.W - 1 : ca);
   cb = cb < 0 ? 0 : (cb >= g.W ? g.W - 1 : cb);
@@ -855,7 +890,7 @@ SCVT_HD Window make_window(const GridP& g, V3 z, int f, double rt, int maxw) {
     sm = fmin(sm, 1.0);
     // chord of the angle asin(sm): 2 sin(asin(sm)/2), cancellation-free;
     // shrunk to cover points binned across a side by rounding
-    double D = sm * sqrt(2.0 / (1.0 + sqrt(1.0 - sm * sm)));
+    double D = sm * sqrt_fast(div_fast(2.0, 1.0 + sqrt_fast(1.0 - sm * sm)));
     w.D = D * (1.0 - 1e-10) - 1e-14;
     if (w.D < 0.0) w.D = 0.0;
   }

@@ -182,7 +182,7 @@ __device__ int gather(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, const Window
       L.dx[slot] = d.x;
       L.dy[slot] = d.y;
       L.dz[slot] = d.z;
-      L.nrm[slot] = sqrt(dot(d, d));
+      L.nrm[slot] = sqrt_fast(dot(d, d));
       L.idx[slot] = en.idx;
     }
     kept += __popcll(m);
@@ -221,7 +221,7 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
     const int ns = gather<GS, CAP, ROWS>(a, L, w, i, z, rc * rc, active, G);
     bool go = active;
     if (go && ns > CAP) {
-      rt = rc * sqrt(0.75 * CAP / (double)ns);
+      rt = rc * sqrt_fast(0.75 * CAP / (double)ns);
       if (rt <= r_small) active = false;
       go = false;
     }
@@ -265,7 +265,7 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
     r2 = group_max<GS>(r2);
     bool store = false;
     if (go) {
-      R = sqrt(r2);
+      R = sqrt_fast(r2);
       if (4.0 * r2 * (1.0 + 1e-12) <= rc * rc && En >= 3 && En <= kVmax) {
         outcome = kCellOk;
         active = false;

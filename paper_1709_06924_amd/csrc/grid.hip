@@ -111,8 +111,9 @@ __device__ inline void generator_cells(const double* __restrict__ Z, int64_t i, 
   if (c < 0) {
     double nn, u, v;
     face_local(p, f, nn, u, v);
-    double fa = floor((u / nn + g.U) * g.inv_du);
-    double fb = floor((v / nn + g.U) * g.inv_du);
+    const double ni = rcp_fast(nn);
+    double fa = floor((u * ni + g.U) * g.inv_du);
+    double fb = floor((v * ni + g.U) * g.inv_du);
     int ia = fa < 0.0 ? 0 : (fa > g.W - 1 ? g.W - 1 : (int)fa);
     int ib = fb < 0.0 ? 0 : (fb > g.W - 1 ? g.W - 1 : (int)fb);
     c = cell_of(g, f, ia, ib);
