@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # from the ISA of k_quad<tanh, fp64> as built here (FMA = 2, add/mul = 1,
 # each rsqrt/reciprocal estimate = 1; clamps, rounding and exponent
 # manipulation not counted):
-FLOPS_PER_POINT = 93       # position, Jacobian, chord distance, table exp, logistic, moments
+FLOPS_PER_POINT = 89       # position, 1/|p| by its series, chord distance, table exp, logistic, moments
 FLOPS_PER_LEAF = 15 + 21   # 12 midpoints per 16 leaves (20 each), det Jacobian
 LEAVES_PER_EDGE = 16       # two geodesic subdivision levels
 POINTS_PER_LEAF = 7

@@ -33,6 +33,28 @@ SCVT_HD double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 SCVT_HD V3 cross(V3 a, V3 b) {
   return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
+// a b + c as one three-address FMA (on the device, v_fma_f64 with all
+// operands in vector registers: the compiler otherwise ties the addend to
+// the result and copies loop-invariant addends on every use)
+SCVT_HD double fma3(double a, double b, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double d;
+  __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+#else
+  return fma(a, b, c);
+#endif
+}
+
+// keeps x in a vector register from here on: a loop that uses a kernel
+// argument as an FMA addend otherwise copies it from its scalar register at
+// every iteration
+SCVT_HD void pin_v(double& x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __asm__ volatile("" : "+v"(x));
+#endif
+}
+
 // reciprocal square root: the device's correctly refined rsqrt, 1/sqrt on
 // the host build used by the CPU checks
 SCVT_HD double rsq(double x) {
@@ -55,6 +77,16 @@ SCVT_HD double rsq_pos(double x) {
 #else
   return 1.0 / ::sqrt(x);
 #endif
+}
+
+// 1/sqrt(x) for x = |p|^2 of a point p of a flat sub-triangle with vertices
+// on the sphere (x <= 1): when e = 1 - x (exact) is at most 1e-4 -- leaves
+// below ~0.03 rad across, all but very coarse meshes -- the binomial series
+// 1 + e/2 + 3e^2/8 + 5e^3/16 (next term below 3e-17), otherwise rsq_pos.
+SCVT_HD double rsq_near1(double x) {
+  const double e = 1.0 - x;
+  if (fabs(e) <= 1e-4) return fma(e, fma(e, fma3(e, 0.3125, 0.375), 0.5), 1.0);
+  return rsq_pos(x);
 }
 
 // a / b and sqrt(x) where the geometry needs neither IEEE rounding nor
@@ -295,28 +327,6 @@ SCVT_HD DensityP density_prepare(DensityP d) {
 }
 
 
-// a b + c as one three-address FMA (on the device, v_fma_f64 with all
-// operands in vector registers: the compiler otherwise ties the addend to
-// the result and copies loop-invariant addends on every use)
-SCVT_HD double fma3(double a, double b, double c) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  double d;
-  __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-  return d;
-#else
-  return fma(a, b, c);
-#endif
-}
-
-// keeps x in a vector register from here on: a loop that uses a kernel
-// argument as an FMA addend otherwise copies it from its scalar register at
-// every iteration
-SCVT_HD void pin_v(double& x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  __asm__ volatile("" : "+v"(x));
-#endif
-}
-
 // 2^(u/N), N = kExpN = 128, for u <= N * 1009 (callers cap), table-driven
 // (Tang's method in base 2): u = N m + j + f with k = rint(u), j = k mod N,
 // m = floor(k / N) and f = u - k exact, |f| <= 1/2, so
@@ -386,7 +396,7 @@ SCVT_HD double sqrt_nr(double x) {
 // below 2e-304; there is no lower cap: exp(t) underflows to 0 and the
 // logistic is 1).
 SCVT_HD double logistic(double bK, double K, double d, const double* tab = SCVT_EXP2_TAB) {
-  const double u = fmin(fma3(d, K, bK), kUMax);
+  const double u = fmin(fma(d, K, bK), kUMax);
   return rcp_nr(1.0 + exp2_n(u, tab));
 }
 
@@ -512,7 +522,7 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
     const double l1 = R[q][1], l2 = R[q][2];
     const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
                     fma(l2, CA.z, fma(l1, BA.z, A.z))};
-    double ri = rsq_pos(dot(p, p));
+    double ri = rsq_near1(dot(p, p));
     V3 y = ri * p;
     double jac = ri * ri * ri;
     double wt = hd * R[q][3] * jac * rho_kind<KIND>(D, y, tab);
