@@ -529,7 +529,7 @@ struct QuadLds {
 constexpr int kQuadCells = 64;  // cells per block: eight pairs per wave
 
 template <int KIND, bool MIXED>
-__global__ __launch_bounds__(256, 4) void k_quad(CellArgs a) {
+__global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   __shared__ QuadLds lds[4];
   __shared__ double tab[kExpN];  // the exponential's 2^(j/N) table
   __shared__ int bin[kVmax + 1];
