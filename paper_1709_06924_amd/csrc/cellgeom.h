@@ -599,6 +599,24 @@ SCVT_HD float rm1_series(float s) {
   return s * fmaf(s, fmaf(s, fmaf(s, fmaf(s, fmaf(s, c6, c5), c4), c3), c2), c1);
 }
 
+// Midpoint of the arc between the unit vectors z + dP and z + dQ, as an
+// offset from z in FP32: with D = dP + dQ, |P + Q|^2 = 4 - |dP - dQ|^2 =
+// 4 (1 + s), and the midpoint is z + D/2 + r1 (z + D/2), r1 = (1 + s)^(-1/2)
+// - 1 (series for small s, else the hardware rsqrt with the cancellation-
+// free form -s r^2 / (1 + r)).
+SCVT_HD F3 arc_midpoint_local(F3 dP, F3 dQ, F3 zf) {
+  const F3 h = 0.5f * (dP + dQ), dd = dP - dQ;
+  const float s = -0.25f * dotf(dd, dd);
+  float r1;
+  if (s >= -0x1p-5f) {
+    r1 = rm1_series(s);
+  } else {
+    const float r = rsqf(1.0f + s);
+    r1 = -s * r * r * rcpf(1.0f + r);
+  }
+  return F3{fmaf(r1, zf.x + h.x, h.x), fmaf(r1, zf.y + h.y, h.y), fmaf(r1, zf.z + h.z, h.z)};
+}
+
 struct DensityF {  // FP32 density parameters
   float gamma, w_lon2i, w_lat2i, pad;
   float amp[2], beta[2], k2l[2];  // k2l = -2 log2(e) / alpha

@@ -579,7 +579,49 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
     const int both = max(items, __shfl_xor(items, 32, 64));
     if (both == 0) continue;  // wave-uniform
     Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (lv == 2) {
+    if (lv == 2 && MIXED) {
+      // the same grid in FP32 offsets from z (the mixed path's local frame)
+      float(*Gf)[3] = reinterpret_cast<float(*)[3]>(&G[0][0]);
+      F3 zc[2];
+      for (int k = 0; k < 2; k++)
+        zc[k] = to_f3(z - V3{ar.rho.xc[k][0], ar.rho.xc[k][1], ar.rho.xc[k][2]});
+      const F3 zf = to_f3(z);
+      for (int t0 = 0; t0 < both; t0 += 32) {
+        const int t = t0 + hl;
+        const bool valid = t < items;
+        const int e = t >> 4;
+        if (valid && s < 3) {  // corners: z itself (offset 0), v_lo, v_hi
+          const double* ed = o.edges + (i * kVmax + e) * 6;
+          const F3 d = s == 0 ? F3{0.0f, 0.0f, 0.0f}
+                              : to_f3((s == 1 ? V3{ed[0], ed[1], ed[2]} : V3{ed[3], ed[4], ed[5]}) - z);
+          const int k = s == 0 ? 14 : (s == 1 ? 4 : 0);
+          Gf[k][0] = d.x;
+          Gf[k][1] = d.y;
+          Gf[k][2] = d.z;
+        }
+        wave_sync();
+        for (int level = 0; level < 2; level++) {
+          const int task = level == 0 ? s : 3 + s;
+          if (valid && s < (level == 0 ? 3 : 9)) {
+            const int kp = nib(kG2TaskP, task), kq = nib(kG2TaskQ, task), km = nib(kG2TaskPt, task);
+            const F3 m = arc_midpoint_local(F3{Gf[kp][0], Gf[kp][1], Gf[kp][2]},
+                                            F3{Gf[kq][0], Gf[kq][1], Gf[kq][2]}, zf);
+            Gf[km][0] = m.x;
+            Gf[km][1] = m.y;
+            Gf[km][2] = m.z;
+          }
+          wave_sync();
+        }
+        if (valid) {
+          const int ka = nib(kG2LeafA, s), kb = nib(kG2LeafB, s), kc = nib(kG2LeafC, s);
+          quad_tri_mixed<KIND>(F3{Gf[ka][0], Gf[ka][1], Gf[ka][2]},
+                               F3{Gf[kb][0], Gf[kb][1], Gf[kb][2]},
+                               F3{Gf[kc][0], Gf[kc][1], Gf[kc][2]}, zf, zc, Df, ar.rho, acc,
+                               ar.quad_rule);
+        }
+        wave_sync();  // the next round rewrites the grids
+      }
+    } else if (lv == 2) {
       for (int t0 = 0; t0 < both; t0 += 32) {  // two whole edges per half and round
         const int t = t0 + hl;
         const bool valid = t < items;
