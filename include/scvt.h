@@ -239,7 +239,9 @@ int scvt_get_state(scvt_handle* h, void* buf, size_t* bytes);
 int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes);
 
 /* Kernel timing (HIP events on the handle's stream, enabled by
- * scvt_set_timing): kernel 0 = certified cell geometry kernel, 1 = fallback
+ * scvt_set_timing: 0 off, 1 every timer below, 2 only the quadrature
+ * kernel's, two events per evaluation): kernel 0 = certified cell geometry
+ * kernel, 1 = fallback
  * clipper, 2 = grid build, 3 = two-loop passes, 4 = whole evaluation,
  * 5 = cell quadrature kernel, 6 = list passes of the certified geometry
  * (cells needing more candidates than the main geometry kernel holds).

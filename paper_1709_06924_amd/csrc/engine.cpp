@@ -67,7 +67,8 @@ struct scvt_handle {
   // evaluation results of the last trial
   double tF = 0, tstep = 0, tg2 = 0, tmz = 0;
   int64_t tfb = 0, tdeg = 0, twide[2] = {0, 0};
-  bool timing = false;
+  bool timing = false;      // all kernel timers
+  bool timing_quad = false;  // the quadrature kernel's timer (also set by timing)
   Timer timers[kTimers];
   hipEvent_t ev[9] = {};
   int main_path = 1;
@@ -238,7 +239,7 @@ void timer_add(scvt_handle* h, int k, hipEvent_t a, hipEvent_t b) {
 // Evaluate at Zsrc into set s: grid, cells, reductions; one host sync.
 int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   hipStream_t st = h->stream;
-  const bool tm = h->timing;
+  const bool tm = h->timing, tq = h->timing_quad;
   HIPCK(launch_fill_i32((int32_t*)h->ctr, 0, sizeof(Counters) / 4, st));
   if (tm) HIPCK(hipEventRecord(h->ev[0], st));
   std::swap(h->grid.order, h->grid.order_prev);  // last build's order drives this one
@@ -250,9 +251,9 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   if (h->main_path) HIPCK(launch_cells_tiers(a, st));
   if (tm) HIPCK(hipEventRecord(h->ev[2], st));
   HIPCK(launch_cells_fallback(a, h->main_path ? 0 : 1, st));
-  if (tm) HIPCK(hipEventRecord(h->ev[3], st));
+  if (tq) HIPCK(hipEventRecord(h->ev[3], st));
   HIPCK(launch_quad(a, st));
-  if (tm) HIPCK(hipEventRecord(h->ev[7], st));
+  if (tq) HIPCK(hipEventRecord(h->ev[7], st));
   EvalRedArgs r{};
   r.n = h->n;
   r.e = s.e;
@@ -290,8 +291,8 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
     timer_add(h, 1, h->ev[2], h->ev[3]);
     timer_add(h, 2, h->ev[0], h->ev[1]);
     timer_add(h, 4, h->ev[0], h->ev[4]);
-    timer_add(h, 5, h->ev[3], h->ev[7]);
   }
+  if (tq) timer_add(h, 5, h->ev[3], h->ev[7]);
   Counters c;
   memcpy(&c, h->pinned + kPinCtr, sizeof(Counters));
   h->tF = h->pinned[kPinEval];
@@ -1333,7 +1334,8 @@ int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes) {
 
 int scvt_set_timing(scvt_handle* h, int enable) {
   if (!h) return SCVT_E_INVALID;
-  h->timing = enable != 0;
+  h->timing = enable == 1;
+  h->timing_quad = enable == 1 || enable == 2;
   for (auto& t : h->timers) t = Timer{};
   return SCVT_OK;
 }

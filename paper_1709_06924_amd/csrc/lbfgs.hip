@@ -358,10 +358,22 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_fin(HistFinArgs a) {
   __shared__ double red[kHVals];
   __shared__ double sg[kHmax], rr[kHmax], co[kHmax], gm[kHmax][kHmax];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // block partials of each value: lane l takes blocks l, l + 64, ... (at
+  // most kHGrid / 64 of them, loaded together), then a butterfly
+  static_assert(kHGrid % 64 == 0, "partials per lane");
+  constexpr int kPer = kHGrid / 64;
   for (int v = wave; v < a.nvals; v += 4) {
-    double x = 0.0;
-    for (int b = lane; b < a.nblocks; b += 64) x += a.partials[(size_t)b * a.nvals + v];
-    x = wave_sum64(x);
+    double xs[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+      const int b = lane + 64 * k;
+      xs[k] = b < a.nblocks ? a.partials[(size_t)b * a.nvals + v] : 0.0;
+    }
+#pragma unroll
+    for (int w = kPer / 2; w > 0; w >>= 1)
+#pragma unroll
+      for (int k = 0; k < w; k++) xs[k] += xs[k + w];
+    const double x = wave_sum64(xs[0]);
     if (lane == 0) red[v] = x;
   }
   double* D = a.dscal;

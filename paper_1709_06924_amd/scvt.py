@@ -328,8 +328,11 @@ class Solver:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(_lib.scvt_set_state(self.h, buf, len(blob)), "scvt_set_state")
 
-    def set_timing(self, on=True):
-        _check(_lib.scvt_set_timing(self.h, 1 if on else 0), "scvt_set_timing")
+    def set_timing(self, on=True, quad_only=False):
+        """Kernel timers: all of them, or (quad_only) only the quadrature
+        kernel's (two events per evaluation); on=False turns them off."""
+        level = 0 if not on else (2 if quad_only else 1)
+        _check(_lib.scvt_set_timing(self.h, level), "scvt_set_timing")
 
     def kernel_time(self, kernel):
         ms = ctypes.c_double()
