@@ -687,8 +687,10 @@ hipError_t launch_cells_main(const CellArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_cells_tiers(const CellArgs& a, hipStream_t s) {
-  // list lengths are only known on the device: fixed grids
-  const int64_t nb = (a.n + 255) / 256 < 256 ? (a.n + 255) / 256 : 256;
+  // list lengths are only known on the device: fixed grids, large enough
+  // for a long list (a random start hands on a few percent of the cells)
+  // to run at several waves per SIMD; idle blocks exit at once
+  const int64_t nb = (a.n + 255) / 256 < 2048 ? (a.n + 255) / 256 : 2048;
   k_cells_tier<0, 16, 32, 31><<<(unsigned)nb, 256, 0, s>>>(a);
   k_cells_tier<1, 64, 64, kWinMax><<<(unsigned)nb, 256, 0, s>>>(a);
   return hipGetLastError();
