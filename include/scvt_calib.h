@@ -18,8 +18,8 @@ int scvt_calib_count(void);
 
 /* ns: host array of scvt_calib_count() doubles, owned by the caller; on
  * return ns[k] is the time per wave-instruction per SIMD in nanoseconds
- * (best of `reps` launches; SIMDs counted as 4 per compute unit of the
- * current device).  Kinds in order: f64 fma, f64 mul, f64 rsq, f64 rcp,
+ * (best of `reps` launches after 40 untimed ones that bring the clocks up;
+ * SIMDs counted as 4 per compute unit of the current device).  Kinds in order: f64 fma, f64 mul, f64 rsq, f64 rcp,
  * f64 ldexp, f64 rndne, f64 max, f32 fma, f32 rsq, f32 rcp, f32 exp,
  * u32 add, f64 rsq + 3 f64 fma, f32 rsq + 3 f64 fma (the last two: mean per
  * instruction of the mix).  Runs on the current device's default stream and

@@ -82,7 +82,7 @@ int scvt_calib_count() { return kOps; }
 
 // ns[k] = nanoseconds per wave-instruction per SIMD for kind k (k < count),
 // counting the device's SIMDs as 4 per compute unit; best of `reps` timed
-// launches after one untimed one.  Kinds: 0 f64 fma, 1 f64 mul, 2 f64 rsq,
+// launches after one untimed one (and 40 untimed FMA launches first).  Kinds: 0 f64 fma, 1 f64 mul, 2 f64 rsq,
 // 3 f64 rcp, 4 f64 ldexp, 5 f64 rndne, 6 f64 max, 7 f32 fma, 8 f32 rsq,
 // 9 f32 rcp, 10 f32 exp, 11 u32 add, 12 f64 rsq + 3 f64 fma (mean),
 // 13 f32 rsq + 3 f64 fma (mean).  Returns 0, or -1 on a HIP error.  The
@@ -97,6 +97,9 @@ int scvt_calib_valu(double* ns, int reps) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = 0;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = -1;
+  // clocks up before the first timed kind: about 50 ms of FMAs
+  for (int r = 0; r < 40 && !rc; r++)
+    if (launch_rate(0, out, nullptr) != hipSuccess) rc = -1;
   const double simds = 4.0 * cus;
   const double winst = (double)kBlocks * kThreads / 64 * kIters * kUnroll * 4 / simds;
   for (int k = 0; k < kOps && !rc; k++) {
