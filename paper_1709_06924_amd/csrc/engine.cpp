@@ -82,6 +82,9 @@ struct scvt_handle {
   bool push_pending = false;
   std::vector<int> ring_prev, free_prev;
   bool dir_timer_pending = false;  // direction timer events awaiting a sync
+  // a_j of the backward recursion for the current history already computed
+  // (by the last push's chained fin steps)
+  bool backward_ready = false;
 };
 
 namespace {
@@ -415,11 +418,12 @@ int direction_fused(scvt_handle* h, const double* hv, double* gq) {
     p.S[j] = h->S + (size_t)h->ring[j] * n3;
     p.Y[j] = h->Y + (size_t)h->ring[j] * n3;
   }
-  if (c > 0) {
+  if (c > 0 && !h->backward_ready) {
     f.mode = kFinBackward;
     f.nvals = 0;
     HIPCK(launch_hist_fin(f, st));
   }
+  h->backward_ready = false;
   p.coef = D + kA;
   p.q = h->q;
   HIPCK(launch_hist_q0(p, st));
@@ -631,6 +635,10 @@ int push_pair(scvt_handle* h) {
   if (h->M == 0) return SCVT_OK;
   const int slot = h->free_slots.back();
   const int64_t n3 = 3 * h->n;
+  // the history the pair joins (decided at the next host sync, resolve_push)
+  std::vector<int> ring_next = h->ring;
+  ring_next.push_back(slot);
+  if ((int)ring_next.size() > h->M) ring_next.erase(ring_next.begin());
   if (h->M <= kHmax) {
     // also s_j . g_new and s_j . y_new for the stored pairs (next direction)
     const int c = (int)h->ring.size();
@@ -658,8 +666,20 @@ int push_pair(scvt_handle* h) {
       p.S[j] = h->S + (size_t)h->ring[j] * n3;
       f.slot[j] = h->ring[j];
     }
+    // one launch: the push's scalars (also y.y into the slot's kYY entry),
+    // then the next direction's backward recursion over the history with
+    // the pair
+    FinChain fc{};
+    fc.n = 2;
+    fc.step[0] = f;
+    fc.step[1] = f;
+    fc.step[1].mode = kFinBackward;
+    fc.step[1].nvals = 0;
+    fc.step[1].c = (int)ring_next.size();
+    for (int j = 0; j < fc.step[1].c; j++) fc.step[1].slot[j] = ring_next[j];
     HIPCK(launch_push_ext(p, h->stream));
-    HIPCK(launch_hist_fin(f, h->stream));  // also y.y into the slot's kYY entry
+    HIPCK(launch_fin_chain(fc, h->stream));
+    h->backward_ready = true;
   } else {
     PushArgs p{};
     p.n3 = n3;
@@ -712,6 +732,7 @@ int resolve_push(scvt_handle* h, bool synced, bool* undone) {
   if (!(ys > h->cfg.curv_eps * sqrt(yy * ss))) {
     h->ring = h->ring_prev;
     h->free_slots = h->free_prev;
+    h->backward_ready = false;
     if (undone) *undone = true;
   }
   return SCVT_OK;
@@ -722,6 +743,7 @@ int resolve_push(scvt_handle* h, bool synced, bool* undone) {
 int settle(scvt_handle* h) { return resolve_push(h, false, nullptr); }
 
 void clear_history(scvt_handle* h) {
+  h->backward_ready = false;
   for (int s : h->ring) h->free_slots.push_back(s);
   h->ring.clear();
 }

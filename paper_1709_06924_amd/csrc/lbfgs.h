@@ -79,6 +79,26 @@ enum : int {
   kNScal = 384
 };
 
+enum : int { kFinPush = 0, kFinDots = 1, kFinBackward = 2, kFinForward = 3, kFinGQ = 4 };
+struct HistFinArgs {
+  int mode;
+  const double* partials;
+  int nblocks, nvals;
+  int c;
+  int slot[kHmax];  // ring slots, oldest first
+  int p;            // push: slot of the new pair
+  int stride;       // row stride of the s.y table (M + 1)
+  double* dscal;
+  double* gram;     // s_j.y_k at [slot_j * stride + slot_k]
+  double* dst[kHmax];
+};
+
+// Up to two fin steps run in order by one launch.
+struct FinChain {
+  int n;
+  HistFinArgs step[2];
+};
+
 struct HistPassArgs {
   int64_t n3;
   int c;  // stored pairs, ring order (oldest first)
@@ -112,23 +132,12 @@ struct MultiDotArgs {
   double* partials;
 };
 
-enum : int { kFinPush = 0, kFinDots = 1, kFinBackward = 2, kFinForward = 3, kFinGQ = 4 };
-struct HistFinArgs {
-  int mode;
-  const double* partials;
-  int nblocks, nvals;
-  int c;
-  int slot[kHmax];  // ring slots, oldest first
-  int p;            // push: slot of the new pair
-  int stride;       // row stride of the s.y table (M + 1)
-  double* dscal;
-  double* gram;     // s_j.y_k at [slot_j * stride + slot_k]
-  double* dst[kHmax];
-};
+
 
 hipError_t launch_push_ext(const PushExtArgs& a, hipStream_t s);
 hipError_t launch_multi_dot(const MultiDotArgs& a, hipStream_t s);
 hipError_t launch_hist_q0(const HistPassArgs& a, hipStream_t s);
+hipError_t launch_fin_chain(const FinChain& f, hipStream_t s);
 hipError_t launch_hist_dir(const HistPassArgs& a, hipStream_t s);
 hipError_t launch_hist_fin(const HistFinArgs& a, hipStream_t s);
 int hist_grid(int64_t n3);  // blocks of the history passes

@@ -174,6 +174,8 @@ __device__ inline double wave_sum64(double v) {
   return v;
 }
 
+__device__ void hist_fin(const HistFinArgs& a);
+
 // Block partials of K (<= KMAX) per-thread values: a butterfly within each
 // wave, then the four waves in order; written to out[0..K).
 template <int KMAX>
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_dir(HistPassArgs a) {
 // takes values w, w+4, ...; lane l blocks l, l+64, ...), then the scalar
 // step of the mode.  The recursions read their operands from LDS (staged by
 // all threads), so the one thread that runs them waits on no global loads.
-__global__ __launch_bounds__(kRedBlock) void k_hist_fin(HistFinArgs a) {
+__device__ void hist_fin(const HistFinArgs& a) {
   __shared__ double red[kHVals];
   __shared__ double sg[kHmax], rr[kHmax], co[kHmax], gm[kHmax][kHmax];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -431,6 +433,17 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_fin(HistFinArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kRedBlock) void k_hist_fin(HistFinArgs a) { hist_fin(a); }
+
+// several fin steps in one launch, in order (e.g. a push's scalars, then the
+// next direction's backward recursion, which reads them)
+__global__ __launch_bounds__(kRedBlock) void k_fin_chain(FinChain f) {
+  for (int k = 0; k < f.n; k++) {
+    hist_fin(f.step[k]);
+    __syncthreads();
+  }
+}
+
 int hist_grid(int64_t n3) {
   int64_t b = (n3 + kRedBlock - 1) / kRedBlock;
   if (b > kHGrid) b = kHGrid;
@@ -473,6 +486,10 @@ hipError_t launch_hist_dir(const HistPassArgs& a, hipStream_t s) {
 }
 hipError_t launch_hist_fin(const HistFinArgs& a, hipStream_t s) {
   k_hist_fin<<<1, kRedBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_fin_chain(const FinChain& f, hipStream_t s) {
+  k_fin_chain<<<1, kRedBlock, 0, s>>>(f);
   return hipGetLastError();
 }
 
