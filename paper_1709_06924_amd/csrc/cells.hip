@@ -518,13 +518,16 @@ __device__ inline void quad_item(const CellArgs& a, V3 A, V3 B, V3 C, V3 z, cons
   }
 }
 
-// Two subdivision levels (the configured rule): the 16 lanes of an edge
-// build the edge's 15-point grid together in LDS -- three lanes the
-// corners, then the 3 level-1 and the 9 level-2 midpoints, one per lane --
-// and each lane reads its leaf's three points, instead of every lane
-// repeating both subdivision levels.
+// Two subdivision levels (the configured rule): the 32 lanes of a half-wave
+// build the 15-point grids of all the cell's edges (up to kGridEdges at a
+// time) together in LDS -- the corners, then the 3 level-1 midpoints of
+// every edge, then its 9 level-2 ones, one point per lane and pass -- and
+// each leaf's lane reads its three points, instead of every lane repeating
+// both subdivision levels.  Whole-cell passes keep the lanes busy: a
+// degree-6 cell takes four short passes, not three per pair of edges.
+constexpr int kGridEdges = 7;  // edges whose grids a half-wave holds at once
 struct QuadLds {
-  double p[4][15][3];  // per wave: the grids of the round's four edges
+  double p[2][kGridEdges][15][3];  // per wave: the two cells' edge grids
 };
 constexpr int kQuadCells = 64;  // cells per block: eight pairs per wave
 
@@ -567,7 +570,7 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   }
   DensityF Df{};
   if (MIXED) Df = density_f32(a.rho);
-  double(*G)[3] = lds[w].p[ln >> 4];  // this lane's edge grid
+  double(*G)[15][3] = lds[w].p[ln >> 5];  // this half's cell grids
   const int s = ln & 15;
   for (int pr = 0; pr < kQuadCells / 8; pr++) {
     const int slot = (pr * 4 + w) * 2 + (ln >> 5);
@@ -575,91 +578,92 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
     const int64_t i = base + (has ? list[slot] : 0);
     const int d = has ? min(max(o.deg[i], 0), kVmax) : 0;
     const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
+    const double* eb = o.edges + i * (kVmax * 6);  // the cell's edge slots
     const int items = d * per;  // this half's (edge, sub-triangle) items
     const int both = max(items, __shfl_xor(items, 32, 64));
     if (both == 0) continue;  // wave-uniform
     Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (lv == 2 && MIXED) {
-      // the same grid in FP32 offsets from z (the mixed path's local frame)
-      float(*Gf)[3] = reinterpret_cast<float(*)[3]>(&G[0][0]);
-      F3 zc[2];
-      for (int k = 0; k < 2; k++)
-        zc[k] = to_f3(z - V3{ar.rho.xc[k][0], ar.rho.xc[k][1], ar.rho.xc[k][2]});
-      const F3 zf = to_f3(z);
-      for (int t0 = 0; t0 < both; t0 += 32) {
-        const int t = t0 + hl;
-        const bool valid = t < items;
-        const int e = t >> 4;
-        if (valid && s < 3) {  // corners: z itself (offset 0), v_lo, v_hi
-          const double* ed = o.edges + (i * kVmax + e) * 6;
-          const F3 d = s == 0 ? F3{0.0f, 0.0f, 0.0f}
-                              : to_f3((s == 1 ? V3{ed[0], ed[1], ed[2]} : V3{ed[3], ed[4], ed[5]}) - z);
-          const int k = s == 0 ? 14 : (s == 1 ? 4 : 0);
-          Gf[k][0] = d.x;
-          Gf[k][1] = d.y;
-          Gf[k][2] = d.z;
-        }
-        wave_sync();
-        for (int level = 0; level < 2; level++) {
-          const int task = level == 0 ? s : 3 + s;
-          if (valid && s < (level == 0 ? 3 : 9)) {
-            const int kp = nib(kG2TaskP, task), kq = nib(kG2TaskQ, task), km = nib(kG2TaskPt, task);
-            const F3 m = arc_midpoint_local(F3{Gf[kp][0], Gf[kp][1], Gf[kp][2]},
-                                            F3{Gf[kq][0], Gf[kq][1], Gf[kq][2]}, zf);
-            Gf[km][0] = m.x;
-            Gf[km][1] = m.y;
-            Gf[km][2] = m.z;
-          }
-          wave_sync();
-        }
-        if (valid) {
-          const int ka = nib(kG2LeafA, s), kb = nib(kG2LeafB, s), kc = nib(kG2LeafC, s);
-          quad_tri_mixed<KIND>(F3{Gf[ka][0], Gf[ka][1], Gf[ka][2]},
-                               F3{Gf[kb][0], Gf[kb][1], Gf[kb][2]},
-                               F3{Gf[kc][0], Gf[kc][1], Gf[kc][2]}, zf, zc, Df, ar.rho, acc,
-                               ar.quad_rule);
-        }
-        wave_sync();  // the next round rewrites the grids
+    if (lv == 2) {
+      // the whole cell's grids (up to kGridEdges edges at a time), then its
+      // leaves; the mixed path keeps FP32 offsets from z (its local frame)
+      float(*Gf)[15][3] = reinterpret_cast<float(*)[15][3]>(&G[0][0][0]);
+      F3 zc[2] = {}, zf = {};
+      if (MIXED) {
+        for (int k = 0; k < 2; k++)
+          zc[k] = to_f3(z - V3{ar.rho.xc[k][0], ar.rho.xc[k][1], ar.rho.xc[k][2]});
+        zf = to_f3(z);
       }
-    } else if (lv == 2) {
-      for (int t0 = 0; t0 < both; t0 += 32) {  // two whole edges per half and round
-        const int t = t0 + hl;
-        const bool valid = t < items;
-        const int e = t >> 4;
-        if (valid && s < 3) {  // corners A = z (14), B = v_lo (4), C = v_hi (0)
-          const double* ed = o.edges + (i * kVmax + e) * 6;
-          const V3 P = s == 0 ? z : (s == 1 ? V3{ed[0], ed[1], ed[2]} : V3{ed[3], ed[4], ed[5]});
-          const int k = s == 0 ? 14 : (s == 1 ? 4 : 0);
-          G[k][0] = P.x;
-          G[k][1] = P.y;
-          G[k][2] = P.z;
+      const int dboth = max(d, __shfl_xor(d, 32, 64));
+      for (int e0 = 0; e0 < dboth; e0 += kGridEdges) {
+        const int ne = min(max(d - e0, 0), kGridEdges);
+        const int neb = max(ne, __shfl_xor(ne, 32, 64));
+        if (hl < 3 * ne) {  // corners: v_lo (4) and v_hi (0) of each edge, then z (14)
+          const bool vert = hl < 2 * ne;
+          const int e = vert ? hl >> 1 : hl - 2 * ne, k = vert ? ((hl & 1) ? 0 : 4) : 14;
+          const double* ed = eb + (e0 + e) * 6 + ((hl & 1) ? 3 : 0);
+          const V3 P = vert ? V3{ed[0], ed[1], ed[2]} : z;
+          if (MIXED) {
+            const F3 q = vert ? to_f3(P - z) : F3{0.0f, 0.0f, 0.0f};
+            Gf[e][k][0] = q.x;
+            Gf[e][k][1] = q.y;
+            Gf[e][k][2] = q.z;
+          } else {
+            G[e][k][0] = P.x;
+            G[e][k][1] = P.y;
+            G[e][k][2] = P.z;
+          }
         }
         wave_sync();
+        // level-1 midpoints (3 per edge), then level-2 (9 per edge)
         for (int level = 0; level < 2; level++) {
-          const int task = level == 0 ? s : 3 + s;
-          if (valid && s < (level == 0 ? 3 : 9)) {
-            const int kp = nib(kG2TaskP, task), kq = nib(kG2TaskQ, task), km = nib(kG2TaskPt, task);
-            const V3 m = normalized_fast(V3{G[kp][0], G[kp][1], G[kp][2]} +
-                                         V3{G[kq][0], G[kq][1], G[kq][2]});
-            G[km][0] = m.x;
-            G[km][1] = m.y;
-            G[km][2] = m.z;
+          const int per_e = level == 0 ? 3 : 9;
+          for (int q0 = 0; q0 < per_e * neb; q0 += 32) {
+            const unsigned q = (unsigned)(q0 + hl);
+            if ((int)q < per_e * ne) {
+              const int e = (int)(q / (unsigned)per_e);
+              const int task = (int)q - per_e * e + (level == 0 ? 0 : 3);
+              const int kp = nib(kG2TaskP, task), kq = nib(kG2TaskQ, task), km = nib(kG2TaskPt, task);
+              if (MIXED) {
+                const F3 m = arc_midpoint_local(F3{Gf[e][kp][0], Gf[e][kp][1], Gf[e][kp][2]},
+                                                F3{Gf[e][kq][0], Gf[e][kq][1], Gf[e][kq][2]}, zf);
+                Gf[e][km][0] = m.x;
+                Gf[e][km][1] = m.y;
+                Gf[e][km][2] = m.z;
+              } else {
+                const V3 m = normalized_fast(V3{G[e][kp][0], G[e][kp][1], G[e][kp][2]} +
+                                             V3{G[e][kq][0], G[e][kq][1], G[e][kq][2]});
+                G[e][km][0] = m.x;
+                G[e][km][1] = m.y;
+                G[e][km][2] = m.z;
+              }
+            }
           }
           wave_sync();
         }
-        if (valid) {
-          const int ka = nib(kG2LeafA, s), kb = nib(kG2LeafB, s), kc = nib(kG2LeafC, s);
-          const V3 A = V3{G[ka][0], G[ka][1], G[ka][2]};
-          const V3 B = V3{G[kb][0], G[kb][1], G[kb][2]};
-          const V3 C = V3{G[kc][0], G[kc][1], G[kc][2]};
-          quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
+        for (int t0 = 0; t0 < 16 * neb; t0 += 32) {  // two edges' leaves per half and round
+          const int t = t0 + hl;
+          if (t < 16 * ne) {
+            const int e = t >> 4;
+            const int ka = nib(kG2LeafA, s), kb = nib(kG2LeafB, s), kc = nib(kG2LeafC, s);
+            if (MIXED) {
+              quad_tri_mixed<KIND>(F3{Gf[e][ka][0], Gf[e][ka][1], Gf[e][ka][2]},
+                                   F3{Gf[e][kb][0], Gf[e][kb][1], Gf[e][kb][2]},
+                                   F3{Gf[e][kc][0], Gf[e][kc][1], Gf[e][kc][2]}, zf, zc, Df,
+                                   ar.rho, acc, ar.quad_rule);
+            } else {
+              const V3 A = V3{G[e][ka][0], G[e][ka][1], G[e][ka][2]};
+              const V3 B = V3{G[e][kb][0], G[e][kb][1], G[e][kb][2]};
+              const V3 C = V3{G[e][kc][0], G[e][kc][1], G[e][kc][2]};
+              quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
+            }
+          }
         }
-        wave_sync();  // the next round rewrites the grids
+        wave_sync();  // the next chunk or cell rewrites the grids
       }
     } else {
       for (int t = hl; t < items; t += 32) {
         const int e = t >> (2 * lv), sub = t & (per - 1);
-        const double* ed = o.edges + (i * kVmax + e) * 6;
+        const double* ed = eb + e * 6;
         V3 A = z;
         V3 B = V3{ed[0], ed[1], ed[2]};
         V3 C = V3{ed[3], ed[4], ed[5]};
