@@ -565,6 +565,7 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   pin_v(ar.rho.gamma);
   for (int k = 0; k < 2; k++) {
     pin_v(ar.rho.K[k]);
+    pin_v(ar.rho.Ks[k]);
     pin_v(ar.rho.bK[k]);
     pin_v(ar.rho.amp[k]);
   }

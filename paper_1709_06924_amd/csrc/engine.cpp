@@ -93,7 +93,10 @@ namespace {
 // [4..7] F, max |l|, sum |g|^2, min mu.z of the last evaluation (one copy of
 // the adjacent device scalars), [8..] the counters
 constexpr int kPinGQ = 0, kPinPush = 1, kPinEval = 4, kPinCtr = 8;
-static_assert(kPush == kGQ + 1 && kEval == kPush + 3, "adjacent device scalars");
+static_assert(kPush == kGQ + 1 && kEval == kPush + 3 && kCtr == kGQ + kPinCtr,
+              "adjacent device scalars");
+static_assert(sizeof(Counters) <= 4 * sizeof(double) && kCtr + 4 <= kSG, "counters' slot");
+constexpr int kPinWords = kPinCtr + 4;  // doubles of one evaluation's copy
 
 // partial-sum buffers, in units of reduce_grid_max() doubles
 enum : int { kPartPass = 0, kPartPush = 2, kPartEval = 5, kPartTotal = 9 };
@@ -243,10 +246,9 @@ void timer_add(scvt_handle* h, int k, hipEvent_t a, hipEvent_t b) {
 int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   hipStream_t st = h->stream;
   const bool tm = h->timing, tq = h->timing_quad;
-  HIPCK(launch_fill_i32((int32_t*)h->ctr, 0, sizeof(Counters) / 4, st));
   if (tm) HIPCK(hipEventRecord(h->ev[0], st));
   std::swap(h->grid.order, h->grid.order_prev);  // last build's order drives this one
-  HIPCK(launch_grid_build(Zsrc, h->n, h->grid, st));
+  HIPCK(launch_grid_build(Zsrc, h->n, h->grid, (int32_t*)h->ctr, st));  // also clears ctr
   if (tm) HIPCK(hipEventRecord(h->ev[1], st));
   CellArgs a = cell_args(h, Zsrc, s);
   if (h->main_path) HIPCK(launch_cells_main(a, st));
@@ -278,11 +280,10 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   fa.out = h->dscal + kEval;
   HIPCK(launch_finalize(fa, st));
   if (tm) HIPCK(hipEventRecord(h->ev[4], st));
-  // one copy brings g.q, the last push's curvature scalars and this
-  // evaluation's scalars (adjacent device scalars)
-  HIPCK(hipMemcpyAsync(h->pinned + kPinGQ, h->dscal + kGQ, 8 * sizeof(double),
+  // one copy brings g.q, the last push's curvature scalars, this
+  // evaluation's scalars and its counters (adjacent device scalars)
+  HIPCK(hipMemcpyAsync(h->pinned + kPinGQ, h->dscal + kGQ, kPinWords * sizeof(double),
                        hipMemcpyDeviceToHost, st));
-  HIPCK(hipMemcpyAsync(h->pinned + kPinCtr, h->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   if (h->dir_timer_pending) {
     timer_add(h, 3, h->ev[5], h->ev[6]);
@@ -317,9 +318,8 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
 // buffers, so the current evaluation is left as it is.
 int geometry_with_neighbours(scvt_handle* h, const double* Zsrc, int32_t* nbr) {
   hipStream_t st = h->stream;
-  HIPCK(launch_fill_i32((int32_t*)h->ctr, 0, sizeof(Counters) / 4, st));
   std::swap(h->grid.order, h->grid.order_prev);  // last build's order drives this one
-  HIPCK(launch_grid_build(Zsrc, h->n, h->grid, st));
+  HIPCK(launch_grid_build(Zsrc, h->n, h->grid, (int32_t*)h->ctr, st));  // also clears ctr
   CellArgs a = cell_args(h, Zsrc, h->trial);
   a.keep_cells = 1;
   a.out.cell_nbr = nbr;
@@ -877,6 +877,7 @@ int alloc_device_state(scvt_handle* h) {
     ALLOC(h->Y, (size_t)(M + 1) * 3 * n);
   }
   ALLOC(h->dscal, kNScal);
+  h->ctr = reinterpret_cast<Counters*>(h->dscal + kCtr);
   ALLOC(h->partials, kPartTotal * reduce_grid_max());
   ALLOC(h->gram, (size_t)(M + 1) * (M + 1));
   if (h->cfg.method == SCVT_METHOD_LBFGS) ALLOC(h->hgam, n);
@@ -884,7 +885,6 @@ int alloc_device_state(scvt_handle* h) {
   ALLOC(h->fb_list, n);
   ALLOC(h->tier_list[0], n);
   ALLOC(h->tier_list[1], n);
-  ALLOC(h->ctr, 1);
   ALLOC(h->grid.cnt_tot, nc + 1);
   ALLOC(h->grid.cnt_home, nc + 1);
   ALLOC(h->grid.start_tot, nc + 1);

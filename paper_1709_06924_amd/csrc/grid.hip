@@ -131,8 +131,10 @@ __device__ inline void generator_cells(const double* __restrict__ Z, int64_t i, 
 
 __global__ __launch_bounds__(kBucketBlock) void k_grid_count(
     const double* __restrict__ Z, int64_t n, GridP g, const int32_t* __restrict__ order_prev,
-    int32_t* __restrict__ cnt_tot, int32_t* __restrict__ cnt_home, int32_t* __restrict__ cell3) {
+    int32_t* __restrict__ cnt_tot, int32_t* __restrict__ cnt_home, int32_t* __restrict__ cell3,
+    int32_t* __restrict__ clear) {
   __shared__ BucketLds L;
+  if (clear && blockIdx.x == 0 && threadIdx.x < 8) clear[threadIdx.x] = 0;
   bucket_init(L);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) {
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_grid_count(
     int32_t c[3];
     generator_cells(Z, i, g, c);
     for (int k = 0; k < 3; k++) {
-      cell3[3 * i + k] = c[k];
+      cell3[3 * t + k] = c[k];  // by position: the scatter reads it back coalesced
       if (c[k] < 0) continue;
       const int s = hash_slot(L, c[k]);
       atomicAdd(&L.ntot[s], 1);
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_grid_scatter(
   int slot[3] = {0, 0, 0};
   if (valid) {
     for (int k = 0; k < 3; k++) {
-      c[k] = cell3[3 * i + k];
+      c[k] = cell3[3 * t + k];
       if (c[k] >= 0) slot[k] = hash_slot(L, c[k]);
     }
     for (int k = 0; k < 3; k++) {
@@ -337,11 +339,12 @@ hipError_t launch_scan_pair(const int32_t* a, const int32_t* b, int64_t m, int32
 
 int64_t scan_tmp_ints(int64_t m) { return 2 * ((m + 1 + kScanTile - 1) / kScanTile + 1); }
 
-hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s) {
+hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, int32_t* clear,
+                             hipStream_t s) {
   const int64_t m = gb.g.ncells;
   unsigned nb = (unsigned)((n + kBucketBlock - 1) / kBucketBlock);
   k_grid_count<<<nb, kBucketBlock, 0, s>>>(Z, n, gb.g, gb.order_prev, gb.cnt_tot, gb.cnt_home,
-                                           gb.cell3);
+                                           gb.cell3, clear);
   int64_t ntiles = (m + 1 + kScanTile - 1) / kScanTile;
   k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, s>>>(gb.cnt_tot, gb.cnt_home, m, gb.scan_tmp);
   k_scan_sums<<<1, kScanBlock, 0, s>>>(gb.scan_tmp, ntiles);

@@ -41,7 +41,7 @@ struct GridBufs {
   int32_t* cnt_home;   // ncells (+1)
   int32_t* start_tot;  // ncells + 1 (exclusive scan)
   int32_t* start_home; // ncells + 1
-  int32_t* cell3;      // n x 3 cells of each generator (home, ghosts, -1)
+  int32_t* cell3;      // n x 3 cells (home, ghosts, -1) of the generator at each position of order_prev
   Entry* entries;      // capacity cap_entries
   int32_t* order;      // n: generators sorted by home cell
   int32_t* order_prev; // n: the previous build's order (input of the next build)
@@ -79,7 +79,9 @@ hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha
                                   int64_t n, hipStream_t s);
 // builds the buckets of Z; then gb.order holds the new order (the caller
 // swaps order and order_prev before the next build)
-hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, hipStream_t s);
+// (clear: 8 ints zeroed by the first kernel, e.g. the evaluation's counters)
+hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, int32_t* clear,
+                             hipStream_t s);
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
 // exclusive scans of a[0..m) and b[0..m) into oa, ob (m+1 entries each; the
 // last holds the total); tmp holds scan_tmp_ints(m) ints

@@ -74,6 +74,7 @@ enum : int {
   kGQ = 200,    // g . q
   kPush = 201,  // y.s, y.y, s.s of the last push
   kEval = 204,  // F, max |l|, sum |g|^2, min mu.z
+  kCtr = 208,   // the evaluation's Counters (32 bytes)
   kSG = 256,    // s.g by slot (g at the current point)
   kYY = 320,    // y.y by slot (plain LBFGS scaling)
   kNScal = 384
