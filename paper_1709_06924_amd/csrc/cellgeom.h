@@ -307,15 +307,56 @@ SCVT_HD EdgeRes edge_on_bisector(int j, int ns, V3 z, const CandView& S) {
 
 // ------------------------------------------------------------- densities
 enum RhoKind { kRhoConst = 0, kRhoTanh = 1, kRhoX3 = 2, kRhoX16 = 3 };
+struct RhoPoly;
 struct DensityP {
   int32_t kind, geodesic, nbumps, pad;
   double xc[2][3];
   double beta[2], alpha[2], amp[2];
   double gamma, w_lon, w_lat;
   // filled by density_prepare: k2 = -2 / alpha_k, and the base-2 exponent's
-  // K = 2N/(alpha_k ln2) and bK = -beta_k K (N = kExpN); for the chord from
-  // a dot product (rho_at), Ks = sqrt(2) K and cc = (1 + |x_c|^2)/2
-  double k2[2], K[2], bK[2], Ks[2], cc[2];
+  // K = 2N/(alpha_k ln2) and bK = -beta_k K (N = kExpN); for the per-cell
+  // polynomial (RhoPoly): Ks = sqrt(2) K, cc = (1 + |x_c|^2)/2,
+  // Kt = 2 sqrt(2)/alpha_k, the squared chord radius poly_r2 of a qualifying
+  // cell and the least squared distance poly_near2 of its generator from x_c
+  double k2[2], K[2], bK[2], Ks[2], cc[2], Kt[2], poly_r2[2], poly_near2[2];
+  // the polynomials' table (device memory, filled at set-up; RhoPoly) and
+  // its entries (0: no table, no cell qualifies)
+  const RhoPoly* poly_tab;
+  int64_t poly_n;
+};
+
+// Per-cell polynomial of a single chord tanh bump, the quadrature's fast
+// path.  With t = 2 (d - beta)/alpha and sigma(t) = 1/(1 + e^t) (so that
+// rho = gamma + amp sigma), around t0 = t(d(z)) with q = 1 - sigma(t0):
+//   sigma(t0 + D) = sigma(t0) / (1 + q (e^D - 1)) = sigma(t0) sum_n b_n D^n,
+//   b_0 = 1,  b_n = -q sum_{j=1..n} b_{n-j} / j!
+// (the reciprocal's power series).  For s = x + iy with |y| <= r < pi,
+// |1 + e^{+-s}| >= sin r (>= 1 where |y| <= pi/2; else >= |sin y|), so
+// |sigma(s)| <= min(1, e^{-x}) / sin r.  Cauchy's estimate on the disc of
+// radius r about t0 bounds the degree-K truncation at |D| <= tau by
+// min(1, e^{r - t0}) (tau/r)^(K+1) / (sin r (1 - tau/r)), and as
+// sigma(t) >= min(1, e^{-t})/2 its error relative to sigma (and so to
+// rho >= amp sigma) is at most 2 e^{r + tau} (tau/r)^(K+1) / (sin r (1 - tau/r)):
+// with K = 10, r = 2.8 and tau <= kPolyTau = 0.068 below 2e-16.
+// The expansion points are a fixed grid, t* = t(0) + j/64 (the density's
+// table of coefficients, one entry per j); the cell takes the entry nearest
+// t(d(z)), so |t - t*| <= (2/alpha) |d(p) - d(z)| + 1/128, and as
+// |d(p) - d(z)| <= |p - z| (chord distances) a cell whose fan lies within
+// chord R of z qualifies when (2/alpha) R + 1/128 <= kPolyTau.
+// The chord comes from a dot product, d^2 = 2 (cc - ri p.c) with
+// cc = (1 + |c|^2)/2 (|y| = 1 to a rounding): two instructions fewer than
+// the difference vector, but its rounding (~2e-16 absolute in d^2/2) moves d
+// by ~2e-16/d, so a qualifying cell also keeps every point at least
+// kPolyNear from x_c (d(z) >= kPolyNear + R): there the density's relative
+// error from it stays below (2/alpha) 1.1e-14.
+constexpr int kPolyDeg = 10;
+constexpr double kPolyTau = 0.068;
+constexpr double kPolyNear = 0.02;
+constexpr int kPolyPerT = 64;        // table entries per unit of t
+constexpr int64_t kPolyMax = 16384;  // larger tables (alpha < 0.016) are not built
+struct RhoPoly {
+  double c[kPolyDeg + 1];  // rho = sum_n c_n D^n
+  double off;              // D = Kt h + off (= t - t*), h = |y - x_c| / sqrt(2)
 };
 
 SCVT_HD DensityP density_prepare(DensityP d) {
@@ -326,7 +367,16 @@ SCVT_HD DensityP density_prepare(DensityP d) {
     d.Ks[k] = d.K[k] * 1.4142135623730951;
     d.cc[k] = 0.5 * (1.0 + d.xc[k][0] * d.xc[k][0] + d.xc[k][1] * d.xc[k][1] +
                      d.xc[k][2] * d.xc[k][2]);
+    d.Kt[k] = -d.k2[k] * 1.4142135623730951;
+    const double rl = 0.5 * (kPolyTau - 0.5 / kPolyPerT) * d.alpha[k];
+    d.poly_r2[k] = d.alpha[k] > 0.0 ? rl * rl : 0.0;
+    d.poly_near2[k] = (kPolyNear + rl) * (kPolyNear + rl);
   }
+  // t spans [t(0), t(2)] = [-2 beta/alpha, -2 beta/alpha + 4/alpha]
+  const bool single = d.kind == kRhoTanh && d.nbumps == 1 && !d.geodesic && d.alpha[0] > 0.0;
+  const double span = single ? 4.0 / d.alpha[0] * kPolyPerT : 0.0;
+  d.poly_n = single && span < (double)(kPolyMax - 2) ? (int64_t)span + 2 : 0;
+  d.poly_tab = nullptr;
   return d;
 }
 
@@ -454,33 +504,6 @@ SCVT_HD double rho_kind(const DensityP& D, V3 y, const double* tab = SCVT_EXP2_T
   return fma3(logistic(D.bK[0], D.K[0], d, tab), D.amp[0], D.gamma);
 }
 
-// rho at the unit point y = ri p for the quadrature.  A tanh bump takes its
-// chord from a dot product, |y - c|^2 = 2 (cc - ri p.c) with
-// cc = (1 + |c|^2)/2 (|y| = 1 to a rounding), and sqrt(2) rides in the
-// exponent's scale Ks: two instructions fewer per point than forming y - c.
-// The rounding of cc - ri p.c (~4e-16 absolute) moves the chord d by
-// ~4e-16/d, which the logistic feels only as (rho'/rho) 4e-16/d: below
-// 1e-14 relative for d > 0.01 and the bumps' widths (alpha >= 0.1), and
-// where d is smaller the point sits deep inside the bump (rho flat).
-// Other densities evaluate rho_kind at y.
-template <int KIND>
-SCVT_HD double rho_at(const DensityP& D, V3 p, double ri, const double* tab = SCVT_EXP2_TAB) {
-  constexpr int base = KIND & 7;
-  if (base != kRhoTanh) return rho_kind<KIND>(D, ri * p, tab);
-  constexpr int NB = (KIND & kVarTwo) ? 2 : 1;
-  double rho = D.gamma;
-#pragma unroll
-  for (int k = 0; k < NB; k++) {
-    const double pc = dot(p, V3{D.xc[k][0], D.xc[k][1], D.xc[k][2]});
-    const double h = sqrt_nr_pos(fmax(fma(-ri, pc, D.cc[k]), 1e-300));  // |y - c| / sqrt(2)
-    const double lg = (KIND & kVarGeo)
-                          ? logistic(D.bK[k], D.K[k], chord_to_angle(h * 1.4142135623730951), tab)
-                          : logistic(D.bK[k], D.Ks[k], h, tab);
-    rho = fma3(lg, D.amp[k], rho);
-  }
-  return rho;
-}
-
 // variant index of a density
 SCVT_HD int rho_variant(const DensityP& D) {
   if (D.kind != kRhoTanh) return D.kind;
@@ -566,10 +589,83 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
     double ri = rsq_near1(dot(p, p));
     V3 y = ri * p;
     double jac = ri * ri * ri;
-    double wt = hd * R[q][3] * jac * rho_at<KIND>(D, p, ri, tab);
+    double wt = hd * R[q][3] * jac * rho_kind<KIND>(D, y, tab);
     V3 dy = y - z;
     acc.m += wt;
     const double wr = wt * ri;  // first moment: wt y = (wt ri) p
+    acc.mx += wr * p.x;
+    acc.my += wr * p.y;
+    acc.mz += wr * p.z;
+    acc.e += wt * dot(dy, dy);
+  }
+}
+
+// whether the cell of z whose vertices lie within squared chord r2 of z
+// takes the polynomial
+SCVT_HD bool poly_qualifies(const DensityP& D, V3 z, double r2) {
+  const V3 t = z - V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]};
+  return D.poly_n > 0 && r2 <= D.poly_r2[0] && dot(t, t) >= D.poly_near2[0];
+}
+
+// Table entry j: the polynomial about t* = t(0) + j/64 (single chord tanh
+// bump): sigma(t*) from the exponential, then the coefficients b_n of the
+// series above scaled by amp sigma(t*), gamma added to the constant term;
+// off = -j/64, as t = Kt h + t(0).
+SCVT_HD RhoPoly poly_entry(const DensityP& D, int64_t j, const double* tab = SCVT_EXP2_TAB) {
+  constexpr double kInvFact[11] = {1.0,          1.0,           0.5,           1.0 / 6.0,
+                                  1.0 / 24.0,   1.0 / 120.0,   1.0 / 720.0,   1.0 / 5040.0,
+                                  1.0 / 40320., 1.0 / 362880., 1.0 / 3628800.};
+  static_assert(kPolyDeg <= 10, "1/j! table");
+  const double off = -(double)j / kPolyPerT;  // exact
+  const double ts = D.k2[0] * D.beta[0] - off;  // t* = -2 beta/alpha + j/64
+  const double s0 = rcp_nr(1.0 + exp2_n(fmin(ts * kExpInvLn, kUMax), tab));
+  const double q = 1.0 - s0;
+  double b[kPolyDeg + 1];
+  b[0] = 1.0;
+  for (int n = 1; n <= kPolyDeg; n++) {
+    double t = 0.0;
+    for (int k = 1; k <= n; k++) t = fma(b[n - k], kInvFact[k], t);
+    b[n] = -q * t;
+  }
+  RhoPoly P;
+  const double as = D.amp[0] * s0;
+  P.c[0] = as + D.gamma;
+  for (int n = 1; n <= kPolyDeg; n++) P.c[n] = as * b[n];
+  P.off = off;
+  return P;
+}
+
+// the table entry of generator z: j nearest (t(d(z)) - t(0)) 64 = Kt h(z) 64
+SCVT_HD int64_t poly_index(const DensityP& D, V3 z) {
+  const double zc = dot(z, V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]});
+  const double h0 = sqrt_nr_pos(fmax(D.cc[0] - zc, 1e-300));
+  const double j = rint(h0 * (D.Kt[0] * kPolyPerT));
+  return (int64_t)fmin(fmax(j, 0.0), (double)(D.poly_n - 1));
+}
+
+// quad_tri_k with rho from the cell's polynomial (single chord tanh bump)
+SCVT_HD void quad_tri_poly(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const RhoPoly& P,
+                           Acc5& acc, int nq = 7) {
+  const double(*R)[4] = SCVT_RULE_TABLE(nq);
+  const V3 BA = B - A, CA = C - A;
+  const double hd = 0.5 * dot(A, cross(BA, CA));
+  const V3 xc = V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]};
+#pragma unroll 1
+  for (int q = 0; q < nq; q++) {
+    const double l1 = R[q][1], l2 = R[q][2];
+    const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
+                    fma(l2, CA.z, fma(l1, BA.z, A.z))};
+    const double ri = rsq_near1(dot(p, p));
+    const double h = sqrt_nr_pos(fmax(fma(-ri, dot(p, xc), D.cc[0]), 1e-300));
+    const double dl = fma(h, D.Kt[0], P.off);
+    double rho = P.c[kPolyDeg];
+#pragma unroll
+    for (int n = kPolyDeg - 1; n >= 0; n--) rho = fma(rho, dl, P.c[n]);
+    const V3 y = ri * p;
+    const double wt = hd * R[q][3] * (ri * ri * ri) * rho;
+    const V3 dy = y - z;
+    acc.m += wt;
+    const double wr = wt * ri;
     acc.mx += wr * p.x;
     acc.my += wr * p.y;
     acc.mz += wr * p.z;

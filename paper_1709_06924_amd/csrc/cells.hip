@@ -535,28 +535,61 @@ template <int KIND, bool MIXED>
 __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   __shared__ QuadLds lds[4];
   __shared__ double tab[kExpN];  // the exponential's 2^(j/N) table
-  __shared__ int bin[kVmax + 1];
+  // FP64 single chord tanh bump: cells whose fan lies within the density
+  // polynomial's radius take it (RhoPoly); they are sorted ahead of the
+  // others so that the two halves of a wave mostly take the same path
+  constexpr bool POLY = !MIXED && KIND == kRhoTanh;
+  constexpr int kBins = (POLY ? 2 : 1) * (kVmax + 1);
+  __shared__ int bin[kBins];
   __shared__ int list[kQuadCells];
   const int tid = threadIdx.x;
   const EvalOut& o = a.out;
   const int64_t base = (int64_t)blockIdx.x * kQuadCells;
   const int ncell = a.n - base < kQuadCells ? (int)(a.n - base) : kQuadCells;
   if (tid < kExpN) tab[tid] = kExp2Tab[tid];
-  if (tid <= kVmax) bin[tid] = 0;
+  if (tid < kBins) bin[tid] = 0;
   __syncthreads();
-  const int dme = tid < ncell ? min(max(o.deg[base + tid], 0), kVmax) : 0;
-  if (tid < ncell) atomicAdd(&bin[dme], 1);
+  // sort key of cell `me` (counted by one thread `lead`): degree, and for
+  // POLY whether the farthest vertex is within the polynomial's radius
+  // (four threads per cell take every fourth edge)
+  int key = 0, me = tid;
+  bool lead = tid < ncell;
+  if (POLY) {
+    me = tid >> 2;
+    lead = (tid & 3) == 0 && me < ncell;
+    double r2 = 0.0;
+    int dm = 0;
+    V3 z = V3{1.0, 0.0, 0.0};
+    if (me < ncell) {
+      const int64_t i = base + me;
+      dm = min(max(o.deg[i], 0), kVmax);
+      z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
+      const double* eb = o.edges + i * (kVmax * 6);
+      for (int e = tid & 3; e < dm; e += 4) {
+        const V3 u = V3{eb[6 * e], eb[6 * e + 1], eb[6 * e + 2]} - z;
+        const V3 v = V3{eb[6 * e + 3], eb[6 * e + 4], eb[6 * e + 5]} - z;
+        r2 = fmax(r2, fmax(dot(u, u), dot(v, v)));
+      }
+    }
+    r2 = fmax(r2, __shfl_xor(r2, 1, 64));
+    r2 = fmax(r2, __shfl_xor(r2, 2, 64));
+    key = poly_qualifies(a.rho, z, r2) ? dm : kVmax + 1 + dm;
+  } else if (lead) {
+    key = min(max(o.deg[base + tid], 0), kVmax);
+  }
+  if (lead) atomicAdd(&bin[key], 1);
   __syncthreads();
   if (tid == 0) {
     int run = 0;
-    for (int b = 0; b <= kVmax; b++) {
+    for (int b = 0; b < kBins; b++) {
       const int c = bin[b];
       bin[b] = run;
       run += c;
     }
   }
   __syncthreads();
-  if (tid < ncell) list[atomicAdd(&bin[dme], 1)] = tid;
+  // entries: the cell's place in the block, +256 if it takes the polynomial
+  if (lead) list[atomicAdd(&bin[key], 1)] = me + (key <= kVmax && POLY ? 256 : 0);
   __syncthreads();
 
   const int ln = lane_id(), w = tid >> 6, hl = ln & 31;
@@ -565,7 +598,6 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   pin_v(ar.rho.gamma);
   for (int k = 0; k < 2; k++) {
     pin_v(ar.rho.K[k]);
-    pin_v(ar.rho.Ks[k]);
     pin_v(ar.rho.bK[k]);
     pin_v(ar.rho.amp[k]);
   }
@@ -576,7 +608,8 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   for (int pr = 0; pr < kQuadCells / 8; pr++) {
     const int slot = (pr * 4 + w) * 2 + (ln >> 5);
     const bool has = slot < ncell;
-    const int64_t i = base + (has ? list[slot] : 0);
+    const int ent = has ? list[slot] : 0;
+    const int64_t i = base + (ent & 255);
     const int d = has ? min(max(o.deg[i], 0), kVmax) : 0;
     const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
     const double* eb = o.edges + i * (kVmax * 6);  // the cell's edge slots
@@ -584,6 +617,9 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
     const int both = max(items, __shfl_xor(items, 32, 64));
     if (both == 0) continue;  // wave-uniform
     Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool use_poly = POLY && ent >= 256;
+    RhoPoly rp{};
+    if (use_poly) rp = ar.rho.poly_tab[poly_index(ar.rho, z)];
     if (lv == 2) {
       // the whole cell's grids (up to kGridEdges edges at a time), then its
       // leaves; the mixed path keeps FP32 offsets from z (its local frame)
@@ -655,7 +691,10 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
               const V3 A = V3{G[e][ka][0], G[e][ka][1], G[e][ka][2]};
               const V3 B = V3{G[e][kb][0], G[e][kb][1], G[e][kb][2]};
               const V3 C = V3{G[e][kc][0], G[e][kc][1], G[e][kc][2]};
-              quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
+              if (use_poly)
+                quad_tri_poly(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+              else
+                quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
             }
           }
         }
@@ -669,7 +708,10 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
         V3 B = V3{ed[0], ed[1], ed[2]};
         V3 C = V3{ed[3], ed[4], ed[5]};
         subtriangle(A, B, C, sub, lv);
-        quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
+        if (use_poly)
+          quad_tri_poly(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+        else
+          quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
       }
     }
     const Acc5 tot = {half_sum(acc.m), half_sum(acc.mx), half_sum(acc.my), half_sum(acc.mz),
@@ -705,6 +747,18 @@ hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s) {
   if (all) k_fb_all<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a.fb_list, a.ctr, a.n);
   int64_t fb_blocks = a.n < 8192 ? a.n : 8192;
   k_fallback<<<(unsigned)fb_blocks, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// the density polynomials' table (single chord tanh bump): entry j per thread
+__global__ void k_poly_table(DensityP D, RhoPoly* out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < D.poly_n) out[j] = poly_entry(D, j, kExp2Tab);
+}
+
+hipError_t launch_poly_table(const DensityP& D, RhoPoly* out, hipStream_t s) {
+  if (D.poly_n <= 0) return hipSuccess;
+  k_poly_table<<<(unsigned)((D.poly_n + 255) / 256), 256, 0, s>>>(D, out);
   return hipGetLastError();
 }
 

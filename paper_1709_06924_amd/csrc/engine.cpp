@@ -896,6 +896,11 @@ int alloc_device_state(scvt_handle* h) {
   ALLOC(h->grid.order_prev, n);
   ALLOC(h->grid.scan_tmp, 2 * ((nc + 1) / 2048 + 2));
   ALLOC(h->grid.overflow, 1);
+  if (h->rho.poly_n > 0) {
+    RhoPoly* t = nullptr;
+    ALLOC(t, h->rho.poly_n);
+    h->rho.poly_tab = t;
+  }
   return SCVT_OK;
 }
 
@@ -919,6 +924,7 @@ int init_device_state(scvt_handle* h) {
   HIPCK(launch_fill_i32((int32_t*)h->R, 0, 2 * n, st));
   HIPCK(launch_fill_i32((int32_t*)h->dscal, 0, 2 * kNScal, st));
   HIPCK(launch_fill_i32((int32_t*)h->q, 0, 6 * n, st));
+  HIPCK(launch_poly_table(h->rho, const_cast<RhoPoly*>(h->rho.poly_tab), st));
   for (int s = M; s >= 0 && M > 0; s--) h->free_slots.push_back(s);
   h->main_path = n > 256 ? 1 : 0;
   h->r_default = 2.0 * sqrt(4.0 * 3.141592653589793 / (double)n);
@@ -939,6 +945,7 @@ int scvt_footprint(const scvt_config* cfg, size_t* bytes) {
   h->cfg = *cfg;
   h->n = cfg->n;
   h->M = cfg->m_hist;
+  h->rho = to_dev(cfg->rho);
   h->dry_run = true;
   rc = alloc_device_state(h);
   *bytes = h->dry_bytes;

@@ -31,6 +31,32 @@ def uniform_sphere(n, seed):
     return np.ascontiguousarray(Z)
 
 
+def cap_points(u, theta, m, seed):
+    """m points within angle ~theta of the unit vector u: tangent-plane
+    offsets uniform in a disc of radius theta (default_rng(seed)), then
+    projected to the sphere (a dense cluster of generators)."""
+    rng = np.random.default_rng(seed)
+    u = np.asarray(u, float) / np.linalg.norm(u)
+    e1 = np.cross(u, [0.3, 0.5, 0.8])
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(u, e1)
+    r = theta * np.sqrt(rng.uniform(size=m))
+    ph = rng.uniform(0.0, 2 * math.pi, m)
+    P = u + (r * np.cos(ph))[:, None] * e1 + (r * np.sin(ph))[:, None] * e2
+    return np.ascontiguousarray(P / np.linalg.norm(P, axis=1)[:, None])
+
+
+def toward(xc, chord, seed):
+    """A unit vector at the given chord distance from the unit vector xc
+    (in a direction drawn from default_rng(seed))."""
+    rng = np.random.default_rng(seed)
+    xc = np.asarray(xc, float)
+    w = np.cross(xc, rng.standard_normal(3))
+    w /= np.linalg.norm(w)
+    a = 2.0 * math.asin(chord / 2.0)
+    return math.cos(a) * xc + math.sin(a) * w
+
+
 def latlon(lat_deg, lon_deg):
     la, lo = math.radians(lat_deg), math.radians(lon_deg)
     return [math.cos(la) * math.cos(lo), math.cos(la) * math.sin(lo), math.sin(la)]

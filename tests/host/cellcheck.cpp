@@ -146,6 +146,59 @@ int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int
   return 0;
 }
 
+// Cell integrals through the per-cell density polynomial (single chord tanh
+// bump) as the FP64 kernel takes them; returns 1 if the cell qualifies (then
+// out5 holds the integrals), 0 otherwise
+int hc_quad_poly(const double* z3, int E, const double* verts, const DensityP* D, int levels,
+                 int nq, double* out5) {
+  Acc5 acc = {0, 0, 0, 0, 0};
+  DensityP Dp = density_prepare(*D);
+  if (Dp.kind != kRhoTanh || Dp.nbumps != 1 || Dp.geodesic) return 0;
+  V3 z = V3{z3[0], z3[1], z3[2]};
+  double r2 = 0.0;
+  for (int e = 0; e < E; e++)
+    for (int c = 0; c < 2; c++) {
+      const V3 v = V3{verts[6 * e + 3 * c], verts[6 * e + 3 * c + 1], verts[6 * e + 3 * c + 2]} - z;
+      r2 = fmax(r2, dot(v, v));
+    }
+  if (!poly_qualifies(Dp, z, r2)) return 0;
+  const RhoPoly P = poly_entry(Dp, poly_index(Dp, z));
+  const int per = 1 << (2 * levels);
+  for (int t = 0; t < E * per; t++) {
+    int e = t >> (2 * levels), s = t & (per - 1);
+    V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
+       C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
+    subtriangle(A, B, C, s, levels);
+    quad_tri_poly(A, B, C, z, Dp, P, acc, nq);
+  }
+  out5[0] = acc.m;
+  out5[1] = acc.mx;
+  out5[2] = acc.my;
+  out5[3] = acc.mz;
+  out5[4] = acc.e;
+  return 1;
+}
+
+// rho at the unit points y (n x 3) from the polynomial table's entry of
+// generator z, and from the exact evaluation
+int hc_rho_poly(const double* z3, const DensityP* D, int64_t n, const double* y, double* poly,
+                double* exact) {
+  DensityP Dp = density_prepare(*D);
+  V3 z = V3{z3[0], z3[1], z3[2]};
+  const RhoPoly P = poly_entry(Dp, poly_index(Dp, z));
+  for (int64_t k = 0; k < n; k++) {
+    const V3 p = V3{y[3 * k], y[3 * k + 1], y[3 * k + 2]};
+    const double h = sqrt_nr_pos(fmax(fma(-1.0, dot(p, V3{Dp.xc[0][0], Dp.xc[0][1], Dp.xc[0][2]}),
+                                          Dp.cc[0]), 1e-300));
+    const double dl = fma(h, Dp.Kt[0], P.off);
+    double r = P.c[kPolyDeg];
+    for (int j = kPolyDeg - 1; j >= 0; j--) r = fma(r, dl, P.c[j]);
+    poly[k] = r;
+    exact[k] = rho_eval(Dp, p);
+  }
+  return 0;
+}
+
 // Mixed-precision cell integrals as the kernel computes them (FP64
 // sub-triangles, FP32 local-frame points, FP64 accumulation, mu = m z + ...)
 int hc_quad_mixed(const double* z3, int E, const double* verts, const DensityP* D, int levels,

@@ -69,7 +69,11 @@ class CDensity(ctypes.Structure):
                 ("pad", ctypes.c_int32), ("xc", ctypes.c_double * 6), ("beta", ctypes.c_double * 2),
                 ("alpha", ctypes.c_double * 2), ("amp", ctypes.c_double * 2),
                 ("gamma", ctypes.c_double), ("w_lon", ctypes.c_double), ("w_lat", ctypes.c_double),
-                ("k2", ctypes.c_double * 2)]
+                ("k2", ctypes.c_double * 2), ("K", ctypes.c_double * 2),
+                ("bK", ctypes.c_double * 2), ("Ks", ctypes.c_double * 2),
+                ("cc", ctypes.c_double * 2), ("Kt", ctypes.c_double * 2),
+                ("poly_r2", ctypes.c_double * 2), ("poly_near2", ctypes.c_double * 2),
+                ("poly_tab", ctypes.c_void_p), ("poly_n", ctypes.c_int64)]
 
 
 KIND = {"const": 0, "tanh": 1, "x3": 2, "x16": 3}
@@ -101,6 +105,28 @@ def quad(z, E, verts, density, levels=2, rule=7):
     lib().hc_quad(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D), ctypes.c_int(levels),
                   ctypes.c_int(rule), P(out))
     return out
+
+
+def quad_poly(z, E, verts, density, levels=2, rule=7):
+    """Cell integrals through the per-cell density polynomial, or None if
+    the cell does not qualify."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    out = np.zeros(5)
+    D = cdensity(density)
+    ok = lib().hc_quad_poly(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D),
+                            ctypes.c_int(levels), ctypes.c_int(rule), P(out))
+    return out if ok else None
+
+
+def rho_poly(z, density, Y):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    poly = np.zeros(len(Y))
+    exact = np.zeros(len(Y))
+    D = cdensity(density)
+    lib().hc_rho_poly(P(z), ctypes.byref(D), ctypes.c_int64(len(Y)), P(Y), P(poly), P(exact))
+    return poly, exact
 
 
 def quad_mixed(z, E, verts, density, levels=2, rule=7):

@@ -268,3 +268,90 @@ def test_grid2_leaves_equal_recursive_subdivision():
         C /= np.linalg.norm(C)
         rec, grid = hc.leaves2(z, B, C)
         assert np.array_equal(rec, grid)
+
+
+@pytest.mark.parametrize("chord", [0.022, 0.1, 0.349, 0.45, 0.8, 1.9])
+def test_density_polynomial_within_bound(chord):
+    """The per-cell density polynomial (degree 7 in the logistic's argument
+    about the generator) agrees with the direct evaluation of the tanh bump
+    at points up to the qualifying chord radius from the generator: relative
+    truncation below 7e-16 by the Cauchy bound, plus the rounding of the
+    dot-product chord (d moves by ~2e-16/d, and rho by up to (2/alpha) times
+    that relative); and the radius is what limits it (at 8 times the radius
+    the error is over 10 times larger wherever the density varies)."""
+    d = I.CONFIGS["C3"]["density"]
+    xc = np.array(d["xc"][0])
+    z = I.toward(xc, chord, 3)
+    rl = 0.5 * (0.068 - 1 / 128) * d["alpha"][0]
+    Y = I.cap_points(z, rl * 0.999, 20000, 4)
+    poly, exact = hc.rho_poly(z, d, Y)
+    rel = np.abs(poly - exact) / exact
+    assert rel.max() < 1.5e-14, rel.max()
+    Yf = I.cap_points(z, 8 * rl, 20000, 5)
+    pf, ef = hc.rho_poly(z, d, Yf)
+    if 0.1 <= chord <= 0.8:  # where the logistic varies
+        assert (np.abs(pf - ef) / ef).max() > 10 * rel.max()
+
+
+@pytest.mark.parametrize("chord,m,cap", [(0.1, 600, 0.012), (0.349, 600, 0.012),
+                                         (0.6, 600, 0.012), (0.349, 150, 0.03)])
+def test_density_polynomial_quadrature_matches_oracle(chord, m, cap):
+    """Small cells (a dense cluster of generators) qualify for the per-cell
+    density polynomial; their integrals through it agree with the direct
+    FP64 path on the same vertices to 2e-14, and with the oracle (which
+    builds its own vertices) to 1e-12 on m and mu and 3e-12 on e: a cell of
+    circumradius R ~ 6e-4 whose vertices move by an ulp moves its second
+    moment by ~4 x 2e-16 / R relative."""
+    d = I.CONFIGS["C3"]["density"]
+    xc = np.array(d["xc"][0])
+    u = I.toward(xc, chord, 7)
+    C = I.cap_points(u, cap, m, 8)
+    U = I.uniform_sphere(200, 9)
+    Z = np.concatenate([C, U])
+    ev = oracle.evaluate(Z, d)
+    rad = np.concatenate([np.full(len(C), 4 * cap / math.sqrt(m)),
+                          np.full(len(U), 4 * math.sqrt(4 * math.pi / 200))])
+    st, deg, nbr, verts, R = hc.cells(Z, rad)
+    used = 0
+    worst = [0.0, 0.0, 0.0, 0.0]
+    for k in np.where(st == 0)[0]:
+        out = hc.quad_poly(Z[k], deg[k], verts[k], d)
+        if out is None:
+            continue
+        used += 1
+        ref = hc.quad(Z[k], deg[k], verts[k], d)
+        worst[0] = max(worst[0], abs(out[0] - ev.m[k]) / ev.m[k])
+        worst[1] = max(worst[1], np.linalg.norm(out[1:4] - ev.mu[k]) / np.linalg.norm(ev.mu[k]))
+        worst[2] = max(worst[2], abs(out[4] - ev.e[k]) / ev.e[k])
+        worst[3] = max(worst[3], abs(out[0] - ref[0]) / ref[0], abs(out[4] - ref[4]) / ref[4])
+    assert used >= m // 3, used
+    assert max(worst[:2]) < 1e-12 and worst[2] < 3e-12, worst
+    assert worst[3] < 2e-14, worst
+
+
+def test_density_polynomial_skips_cells_near_centre():
+    """Cells whose generator lies within 0.02 + R of the bump's centre (where
+    the dot-product chord would lose relative accuracy) do not qualify, small
+    as they are; those just outside do."""
+    d = I.CONFIGS["C3"]["density"]
+    xc = np.array(d["xc"][0])
+    C = I.cap_points(xc, 0.04, 4000, 11)
+    U = I.uniform_sphere(200, 12)
+    Z = np.concatenate([C, U])
+    rad = np.concatenate([np.full(len(C), 4e-3), np.full(len(U), 4 * math.sqrt(4 * math.pi / 200))])
+    st, deg, nbr, verts, R = hc.cells(Z, rad)
+    rl = 0.5 * (0.068 - 1 / 128) * d["alpha"][0]
+    near = far = 0
+    for k in np.where(st[:len(C)] == 0)[0]:
+        v = verts[k][:deg[k]].reshape(-1, 3)
+        if np.linalg.norm(v - Z[k], axis=1).max() > 0.99 * rl:
+            continue
+        dz = np.linalg.norm(Z[k] - xc)
+        q = hc.quad_poly(Z[k], deg[k], verts[k], d) is not None
+        if dz < 0.99 * (0.02 + rl):
+            assert not q
+            near += 1
+        elif dz > 1.01 * (0.02 + rl):
+            assert q
+            far += 1
+    assert near >= 100 and far >= 100, (near, far)
