@@ -549,33 +549,20 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   if (tid < kExpN) tab[tid] = kExp2Tab[tid];
   if (tid < kBins) bin[tid] = 0;
   __syncthreads();
-  // sort key of cell `me` (counted by one thread `lead`): degree, and for
-  // POLY whether the farthest vertex is within the polynomial's radius
-  // (four threads per cell take every fourth edge)
-  int key = 0, me = tid;
-  bool lead = tid < ncell;
-  if (POLY) {
-    me = tid >> 2;
-    lead = (tid & 3) == 0 && me < ncell;
-    double r2 = 0.0;
-    int dm = 0;
-    V3 z = V3{1.0, 0.0, 0.0};
-    if (me < ncell) {
-      const int64_t i = base + me;
-      dm = min(max(o.deg[i], 0), kVmax);
-      z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
-      const double* eb = o.edges + i * (kVmax * 6);
-      for (int e = tid & 3; e < dm; e += 4) {
-        const V3 u = V3{eb[6 * e], eb[6 * e + 1], eb[6 * e + 2]} - z;
-        const V3 v = V3{eb[6 * e + 3], eb[6 * e + 4], eb[6 * e + 5]} - z;
-        r2 = fmax(r2, fmax(dot(u, u), dot(v, v)));
-      }
+  // sort key of each cell: degree, and for POLY whether its farthest vertex
+  // lies within the polynomial's radius (the geometry passes leave the
+  // distance, or a bound on it, in R; a relative 1e-9 covers its rounding)
+  int key = 0;
+  const bool lead = tid < ncell;
+  if (lead) {
+    const int64_t i = base + tid;
+    const int dm = min(max(o.deg[i], 0), kVmax);
+    key = dm;
+    if (POLY) {
+      const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
+      const double r = o.R[i] * (1.0 + 1e-9);
+      key = poly_qualifies(a.rho, z, r * r) ? dm : kVmax + 1 + dm;
     }
-    r2 = fmax(r2, __shfl_xor(r2, 1, 64));
-    r2 = fmax(r2, __shfl_xor(r2, 2, 64));
-    key = poly_qualifies(a.rho, z, r2) ? dm : kVmax + 1 + dm;
-  } else if (lead) {
-    key = min(max(o.deg[base + tid], 0), kVmax);
   }
   if (lead) atomicAdd(&bin[key], 1);
   __syncthreads();
@@ -589,7 +576,7 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   }
   __syncthreads();
   // entries: the cell's place in the block, +256 if it takes the polynomial
-  if (lead) list[atomicAdd(&bin[key], 1)] = me + (key <= kVmax && POLY ? 256 : 0);
+  if (lead) list[atomicAdd(&bin[key], 1)] = tid + (key <= kVmax && POLY ? 256 : 0);
   __syncthreads();
 
   const int ln = lane_id(), w = tid >> 6, hl = ln & 31;
