@@ -49,15 +49,18 @@ __device__ inline int wave_sum_i(int v) {
   return v;
 }
 
-// logical block for a physical one: consecutive physical blocks go to
-// different XCDs (8 of them), so give each XCD a contiguous range
-__device__ inline int64_t xcd_block(int64_t b, int64_t nblocks) {
-  const int64_t X = 8;
-  int64_t per = nblocks / X, rem = nblocks % X;
-  int64_t x = b % X, k = b / X;
-  // XCD x owns per (+1 for the first rem XCDs) consecutive logical blocks
-  int64_t start = x * per + (x < rem ? x : rem);
-  return start + k;
+// Logical block for a physical one: consecutive physical blocks go to
+// different XCDs (8 of them, round robin), so give each XCD whole chunks of
+// kXcdChunk consecutive logical blocks (neighbouring cells share their
+// windows' grid data in its L2), dealt out in turn: chunk c to XCD c mod 8.
+// Contiguous eighths would leave the XCD holding a dense region (whose
+// windows hold more generators) the last to finish.  The grid is padded to
+// a multiple of 8 kXcdChunk blocks, so the map is a bijection; logical
+// blocks past the end have no work.
+constexpr int64_t kXcdChunk = 16;
+__device__ inline int64_t xcd_block(int64_t b) {
+  const int64_t x = b % 8, k = b / 8;
+  return ((k / kXcdChunk) * 8 + x) * kXcdChunk + k % kXcdChunk;
 }
 
 // ------------------------------------------------------------- edge slots
@@ -334,7 +337,7 @@ __global__ __launch_bounds__(256, 4) void k_cells_geom(CellArgs a) {
   __shared__ CandLds<GS, 16, 15> lds[4 * GPW];
   const GroupPos G = group_pos<GS>();
   const int wv = threadIdx.x >> 6;
-  const int64_t pos = (xcd_block(blockIdx.x, gridDim.x) * 4 + wv) * GPW + G.gid;
+  const int64_t pos = (xcd_block(blockIdx.x) * 4 + wv) * GPW + G.gid;
   const bool valid = pos < a.n;
   if (!__ballot(valid)) return;
   const int64_t i = valid ? a.grid.order[pos] : 0;
@@ -716,7 +719,8 @@ __global__ void k_fb_all(int32_t* fb_list, Counters* ctr, int64_t n) {
 
 hipError_t launch_cells_main(const CellArgs& a, hipStream_t s) {
   const int64_t nb = (a.n + 31) / 32;  // eight cells per wave, four waves per block
-  k_cells_geom<<<(unsigned)nb, 256, 0, s>>>(a);
+  const int64_t pad = 8 * kXcdChunk;
+  k_cells_geom<<<(unsigned)((nb + pad - 1) / pad * pad), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
