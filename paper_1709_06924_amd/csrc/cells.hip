@@ -729,7 +729,7 @@ hipError_t launch_cells_tiers(const CellArgs& a, hipStream_t s) {
   // for a long list (a random start hands on a few percent of the cells)
   // to run at several waves per SIMD; idle blocks exit at once
   const int64_t nb = (a.n + 255) / 256 < 2048 ? (a.n + 255) / 256 : 2048;
-  k_cells_tier<0, 16, 32, 31><<<(unsigned)nb, 256, 0, s>>>(a);
+  k_cells_tier<0, 32, 32, 31><<<(unsigned)nb, 256, 0, s>>>(a);
   k_cells_tier<1, 64, 64, kWinMax><<<(unsigned)nb, 256, 0, s>>>(a);
   return hipGetLastError();
 }
