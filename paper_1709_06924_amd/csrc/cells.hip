@@ -1,11 +1,10 @@
 // Voronoi cell construction, cell quadrature and per-cell epilogue.
 //
-// k_cells_geom: a group of 16 lanes per generator z (four per wavefront),
-// in cube-map order (neighbouring groups share cached grid data), block
-// index remapped so that each XCD's L2 sees a contiguous stretch of the
-// sphere.
+// k_cells_geom: a group of 8 lanes per generator z (eight per wavefront),
+// in cube-map order (neighbouring groups share cached grid data), blocks
+// dealt to the XCDs in chunks of neighbouring cells.
 //   A. candidates: every generator within chord radius rc of z, read from a
-//      rectangle of grid cells whose certified radius D >= rc (at most 32);
+//      rectangle of grid cells whose certified radius D >= rc (at most 16);
 //   B. each lane takes two candidates j and computes the edge of the cell on
 //      the bisector of (z, p_j) against all other candidates
 //      (edge_on_bisector);
@@ -13,8 +12,10 @@
 //      generator outside the candidate set can cut the cell (a point p can
 //      only cut if |p - z| < 2R); otherwise the radius grows and A-C repeat.
 //   The edges (vertex pairs, ordered by neighbour index) go to the cell's
-//   slot in HBM.  Cells that cannot be certified with 32 candidates, or meet
-//   a predicate within its error bound, go to a list for
+//   slot in HBM.  Cells that cannot be certified with 16 candidates go to
+//   the list passes k_cells_tier (32, then 64 candidates, one per lane);
+//   what those cannot certify, or meets a predicate within its error bound,
+//   goes to a list for
 // k_fallback: a sequential half-space clipper run by lane 0 (no size limit:
 //   any cell the sphere allows), writing the same slot.
 // k_quad: one cell per half-wave, cells sorted by degree within a block:
