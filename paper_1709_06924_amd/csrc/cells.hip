@@ -731,13 +731,16 @@ hipError_t launch_cells_tiers(const CellArgs& a, hipStream_t s) {
   // to run at several waves per SIMD; idle blocks exit at once
   const int64_t nb = (a.n + 255) / 256 < 2048 ? (a.n + 255) / 256 : 2048;
   k_cells_tier<0, 32, 32, 31><<<(unsigned)nb, 256, 0, s>>>(a);
-  k_cells_tier<1, 64, 64, kWinMax><<<(unsigned)nb, 256, 0, s>>>(a);
+  // the second list holds what the first could not certify: far shorter
+  k_cells_tier<1, 64, 64, kWinMax><<<(unsigned)(nb < 512 ? nb : 512), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s) {
   if (all) k_fb_all<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a.fb_list, a.ctr, a.n);
-  int64_t fb_blocks = a.n < 8192 ? a.n : 8192;
+  // one cell per block; after the certified passes the list is short
+  const int64_t cap = all ? 8192 : 1024;
+  const int64_t fb_blocks = a.n < cap ? a.n : cap;
   k_fallback<<<(unsigned)fb_blocks, 64, 0, s>>>(a);
   return hipGetLastError();
 }
