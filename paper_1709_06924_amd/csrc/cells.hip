@@ -215,6 +215,7 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
   const double Rg = valid ? a.out.R[i] : 0.0;
   double rt = Rg > 0.0 ? 2.3 * Rg : a.r_default;
   double r_small = 0.0;  // largest radius found too small
+  double rc_over = 0.0;  // last radius that held more than CAP candidates
   bool active = valid;
   int outcome = kCellOpen, E = 0;
   double R = 0.0;
@@ -225,6 +226,7 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
     const int ns = gather<GS, CAP, ROWS>(a, L, w, i, z, rc * rc, active, G);
     bool go = active;
     if (go && ns > CAP) {
+      rc_over = rc;
       rt = rc * sqrt_fast(0.75 * CAP / (double)ns);
       if (rt <= r_small) active = false;
       go = false;
@@ -303,6 +305,10 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
       }
     }
   }
+  // a cell handed on starts the next pass where this one stopped: at the
+  // radius that held too many candidates, else at the next one to try
+  if (valid && outcome == kCellOpen && G.gl == 0)
+    a.out.R[i] = (rc_over > r_small ? rc_over : rt) * (1.0 / 2.3);
   if (valid && outcome == kCellOk) {
     if (G.gl == 0) {
       a.out.deg[i] = E;
