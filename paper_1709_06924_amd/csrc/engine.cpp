@@ -57,6 +57,13 @@ struct scvt_handle {
   int32_t* tier_list[2] = {nullptr, nullptr};
   Counters* ctr = nullptr;
   double* pinned = nullptr;  // host-pinned mirror of scalars
+  // the trial's push (s, y and their products) launched behind its
+  // evaluation, ahead of the host's acceptance test (push_pair reuses it
+  // when the history it was launched for is still the history)
+  bool pre_valid = false;
+  int pre_slot = -1;
+  std::vector<int> pre_ring;
+  hipEvent_t ev_copy = nullptr;
   std::vector<void*> allocs;
   // ring: slots ordered oldest -> newest
   std::vector<int> ring;
@@ -242,8 +249,13 @@ void timer_add(scvt_handle* h, int k, hipEvent_t a, hipEvent_t b) {
   }
 }
 
+int launch_push_pre(scvt_handle* h);
+
 // Evaluate at Zsrc into set s: grid, cells, reductions; one host sync.
-int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
+// prepush (a trial of the P-LBFGS loop): the push of the trial as the next
+// pair is launched behind the evaluation, and the host waits for the
+// scalars' copy only, so the push runs while the host decides.
+int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s, bool prepush = false) {
   hipStream_t st = h->stream;
   const bool tm = h->timing, tq = h->timing_quad;
   if (tm) HIPCK(hipEventRecord(h->ev[0], st));
@@ -284,7 +296,15 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   // evaluation's scalars and its counters (adjacent device scalars)
   HIPCK(hipMemcpyAsync(h->pinned + kPinGQ, h->dscal + kGQ, kPinWords * sizeof(double),
                        hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
+  h->pre_valid = false;
+  if (prepush && h->M > 0 && h->M <= kHmax) {
+    HIPCK(hipEventRecord(h->ev_copy, st));
+    const int rp = launch_push_pre(h);
+    if (rp) return rp;
+    HIPCK(hipEventSynchronize(h->ev_copy));
+  } else {
+    HIPCK(hipStreamSynchronize(st));
+  }
   if (h->dir_timer_pending) {
     timer_add(h, 3, h->ev[5], h->ev[6]);
     h->dir_timer_pending = false;
@@ -618,7 +638,7 @@ int line_search(scvt_handle* h, double gq, int k0, bool* accepted, double* alpha
   *accepted = false;
   for (int k = k0; k < h->cfg.ls_max_evals; k++) {
     HIPCK(launch_normalize_trial(h->Z, h->q, alpha, h->Zt, h->n, h->stream));
-    int rc = evaluate(h, h->Zt, h->trial);
+    int rc = evaluate(h, h->Zt, h->trial, true);
     h->n_evals++;
     if (rc < 0) return rc;
     if (armijo(h, alpha, gq)) {
@@ -628,6 +648,36 @@ int line_search(scvt_handle* h, double gq, int k0, bool* accepted, double* alpha
     }
     alpha *= 0.5;
   }
+  return SCVT_OK;
+}
+
+// s = Zt - Z and y = g_t - g of the trial into the history's next free
+// slot, with y.s, |y|^2, |s|^2 and s_j . g_t, s_j . y for the stored pairs
+// (block partials; fused history path)
+hipError_t launch_push_ext_now(scvt_handle* h, int slot) {
+  const int64_t n3 = 3 * h->n;
+  PushExtArgs p{};
+  p.n3 = n3;
+  p.Z = h->Z;
+  p.Zt = h->Zt;
+  p.g = h->cur.g;
+  p.gt = h->trial.g;
+  p.s = h->S + (size_t)slot * n3;
+  p.y = h->Y + (size_t)slot * n3;
+  p.c = (int)h->ring.size();
+  p.partials = h->hpart;
+  for (int j = 0; j < p.c; j++) p.S[j] = h->S + (size_t)h->ring[j] * n3;
+  return launch_push_ext(p, h->stream);
+}
+
+// the trial's push, ahead of its acceptance (a rejected trial's slot stays
+// free and its partials are overwritten)
+int launch_push_pre(scvt_handle* h) {
+  const int slot = h->free_slots.back();
+  HIPCK(launch_push_ext_now(h, slot));
+  h->pre_valid = true;
+  h->pre_slot = slot;
+  h->pre_ring = h->ring;
   return SCVT_OK;
 }
 
@@ -642,16 +692,6 @@ int push_pair(scvt_handle* h) {
   if (h->M <= kHmax) {
     // also s_j . g_new and s_j . y_new for the stored pairs (next direction)
     const int c = (int)h->ring.size();
-    PushExtArgs p{};
-    p.n3 = n3;
-    p.Z = h->Z;
-    p.Zt = h->Zt;
-    p.g = h->cur.g;
-    p.gt = h->trial.g;
-    p.s = h->S + (size_t)slot * n3;
-    p.y = h->Y + (size_t)slot * n3;
-    p.c = c;
-    p.partials = h->hpart;
     HistFinArgs f{};
     f.mode = kFinPush;
     f.partials = h->hpart;
@@ -662,10 +702,7 @@ int push_pair(scvt_handle* h) {
     f.stride = h->M + 1;
     f.dscal = h->dscal;
     f.gram = h->gram;
-    for (int j = 0; j < c; j++) {
-      p.S[j] = h->S + (size_t)h->ring[j] * n3;
-      f.slot[j] = h->ring[j];
-    }
+    for (int j = 0; j < c; j++) f.slot[j] = h->ring[j];
     // one launch: the push's scalars (also y.y into the slot's kYY entry),
     // then the next direction's backward recursion over the history with
     // the pair
@@ -677,7 +714,11 @@ int push_pair(scvt_handle* h) {
     fc.step[1].nvals = 0;
     fc.step[1].c = (int)ring_next.size();
     for (int j = 0; j < fc.step[1].c; j++) fc.step[1].slot[j] = ring_next[j];
-    HIPCK(launch_push_ext(p, h->stream));
+    // the push launched behind the trial's evaluation serves if the history
+    // is still the one it was launched for
+    if (!(h->pre_valid && h->pre_slot == slot && h->pre_ring == h->ring))
+      HIPCK(launch_push_ext_now(h, slot));
+    h->pre_valid = false;
     HIPCK(launch_fin_chain(fc, h->stream));
     h->backward_ready = true;
   } else {
@@ -774,7 +815,7 @@ int quasi_newton_step(scvt_handle* h) {
     rc = direction(h, nullptr);
     if (rc) return rc;
     HIPCK(launch_normalize_trial(h->Z, h->q, 1.0, h->Zt, h->n, h->stream));
-    rc = evaluate(h, h->Zt, h->trial);
+    rc = evaluate(h, h->Zt, h->trial, true);
     if (rc == SCVT_E_HIP) return rc;  // no scalars arrived
     bool undone = false;
     const int rc2 = resolve_push(h, true, &undone);
@@ -808,7 +849,7 @@ int quasi_newton_step(scvt_handle* h) {
     rc = lloyd_direction(h, nullptr);
     if (rc) return rc;
     HIPCK(launch_normalize_trial(h->Z, h->q, 1.0, h->Zt, h->n, h->stream));
-    rc = evaluate(h, h->Zt, h->trial);
+    rc = evaluate(h, h->Zt, h->trial, true);
     h->n_evals++;
     if (rc < 0) return rc;
     alpha = 1.0;
@@ -855,6 +896,7 @@ void destroy(scvt_handle* h) {
   if (h->pinned) hipHostFree(h->pinned);
   for (auto& e : h->ev)
     if (e) hipEventDestroy(e);
+  if (h->ev_copy) hipEventDestroy(h->ev_copy);
   if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
   delete h;
 }
@@ -912,6 +954,7 @@ int init_device_state(scvt_handle* h) {
   const int64_t nc = h->grid.g.ncells;
   if (hipHostMalloc((void**)&h->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return SCVT_E_OOM;
+  if (hipEventCreateWithFlags(&h->ev_copy, hipEventDisableTiming) != hipSuccess) return SCVT_E_HIP;
   // timing only, read after a stream synchronisation: no system-scope fence
   // (which writes back and invalidates caches at every record)
   for (auto& e : h->ev)
