@@ -337,23 +337,23 @@ struct DensityP {
 // min(1, e^{r - t0}) (tau/r)^(K+1) / (sin r (1 - tau/r)), and as
 // sigma(t) >= min(1, e^{-t})/2 its error relative to sigma (and so to
 // rho >= amp sigma) is at most 2 e^{r + tau} (tau/r)^(K+1) / (sin r (1 - tau/r)):
-// with K = 10, r = 2.8 and tau <= kPolyTau = 0.068 below 2e-16.
-// The expansion points are a fixed grid, t* = t(0) + j/64 (the density's
+// with K = 9, r = 2.78 and tau <= kPolyTau = 0.05 below 3.5e-16.
+// The expansion points are a fixed grid, t* = t(0) + j/256 (the density's
 // table of coefficients, one entry per j); the cell takes the entry nearest
-// t(d(z)), so |t - t*| <= (2/alpha) |d(p) - d(z)| + 1/128, and as
+// t(d(z)), so |t - t*| <= (2/alpha) |d(p) - d(z)| + 1/512, and as
 // |d(p) - d(z)| <= |p - z| (chord distances) a cell whose fan lies within
-// chord R of z qualifies when (2/alpha) R + 1/128 <= kPolyTau.
+// chord R of z qualifies when (2/alpha) R + 1/512 <= kPolyTau.
 // The chord comes from a dot product, d^2 = 2 (cc - ri p.c) with
 // cc = (1 + |c|^2)/2 (|y| = 1 to a rounding): two instructions fewer than
 // the difference vector, but its rounding (~2e-16 absolute in d^2/2) moves d
 // by ~2e-16/d, so a qualifying cell also keeps every point at least
 // kPolyNear from x_c (d(z) >= kPolyNear + R): there the density's relative
 // error from it stays below (2/alpha) 1.1e-14.
-constexpr int kPolyDeg = 10;
-constexpr double kPolyTau = 0.068;
+constexpr int kPolyDeg = 9;
+constexpr double kPolyTau = 0.05;
 constexpr double kPolyNear = 0.02;
-constexpr int kPolyPerT = 64;        // table entries per unit of t
-constexpr int64_t kPolyMax = 16384;  // larger tables (alpha < 0.016) are not built
+constexpr int kPolyPerT = 256;       // table entries per unit of t
+constexpr int64_t kPolyMax = 65536;  // larger tables (alpha < 0.016) are not built
 struct RhoPoly {
   double c[kPolyDeg + 1];  // rho = sum_n c_n D^n
   double off;              // D = Kt h + off (= t - t*), h = |y - x_c| / sqrt(2)
@@ -607,7 +607,7 @@ SCVT_HD bool poly_qualifies(const DensityP& D, V3 z, double r2) {
   return D.poly_n > 0 && r2 <= D.poly_r2[0] && dot(t, t) >= D.poly_near2[0];
 }
 
-// Table entry j: the polynomial about t* = t(0) + j/64 (single chord tanh
+// Table entry j: the polynomial about t* = t(0) + j/256 (single chord tanh
 // bump): sigma(t*) from the exponential, then the coefficients b_n of the
 // series above scaled by amp sigma(t*), gamma added to the constant term;
 // off = -j/64, as t = Kt h + t(0).
@@ -617,7 +617,7 @@ SCVT_HD RhoPoly poly_entry(const DensityP& D, int64_t j, const double* tab = SCV
                                   1.0 / 40320., 1.0 / 362880., 1.0 / 3628800.};
   static_assert(kPolyDeg <= 10, "1/j! table");
   const double off = -(double)j / kPolyPerT;  // exact
-  const double ts = D.k2[0] * D.beta[0] - off;  // t* = -2 beta/alpha + j/64
+  const double ts = D.k2[0] * D.beta[0] - off;  // t* = -2 beta/alpha + j/256
   const double s0 = rcp_nr(1.0 + exp2_n(fmin(ts * kExpInvLn, kUMax), tab));
   const double q = 1.0 - s0;
   double b[kPolyDeg + 1];
@@ -635,7 +635,7 @@ SCVT_HD RhoPoly poly_entry(const DensityP& D, int64_t j, const double* tab = SCV
   return P;
 }
 
-// the table entry of generator z: j nearest (t(d(z)) - t(0)) 64 = Kt h(z) 64
+// the table entry of generator z: j nearest (t(d(z)) - t(0)) 256 = Kt h(z) 256
 SCVT_HD int64_t poly_index(const DensityP& D, V3 z) {
   const double zc = dot(z, V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]});
   const double h0 = sqrt_nr_pos(fmax(D.cc[0] - zc, 1e-300));

@@ -282,7 +282,7 @@ def test_density_polynomial_within_bound(chord):
     d = I.CONFIGS["C3"]["density"]
     xc = np.array(d["xc"][0])
     z = I.toward(xc, chord, 3)
-    rl = 0.5 * (0.068 - 1 / 128) * d["alpha"][0]
+    rl = 0.5 * (0.05 - 1 / 512) * d["alpha"][0]
     Y = I.cap_points(z, rl * 0.999, 20000, 4)
     poly, exact = hc.rho_poly(z, d, Y)
     rel = np.abs(poly - exact) / exact
@@ -294,7 +294,7 @@ def test_density_polynomial_within_bound(chord):
 
 
 @pytest.mark.parametrize("chord,m,cap", [(0.1, 600, 0.012), (0.349, 600, 0.012),
-                                         (0.6, 600, 0.012), (0.349, 150, 0.03)])
+                                         (0.6, 600, 0.012), (0.349, 250, 0.03)])
 def test_density_polynomial_quadrature_matches_oracle(chord, m, cap):
     """Small cells (a dense cluster of generators) qualify for the per-cell
     density polynomial; their integrals through it agree with the direct
@@ -340,7 +340,7 @@ def test_density_polynomial_skips_cells_near_centre():
     Z = np.concatenate([C, U])
     rad = np.concatenate([np.full(len(C), 4e-3), np.full(len(U), 4 * math.sqrt(4 * math.pi / 200))])
     st, deg, nbr, verts, R = hc.cells(Z, rad)
-    rl = 0.5 * (0.068 - 1 / 128) * d["alpha"][0]
+    rl = 0.5 * (0.05 - 1 / 512) * d["alpha"][0]
     near = far = 0
     for k in np.where(st[:len(C)] == 0)[0]:
         v = verts[k][:deg[k]].reshape(-1, 3)
