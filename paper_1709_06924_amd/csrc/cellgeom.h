@@ -319,10 +319,13 @@ struct DensityP {
   // Kt = 2 sqrt(2)/alpha_k, the squared chord radius poly_r2 of a qualifying
   // cell and the least squared distance poly_near2 of its generator from x_c
   double k2[2], K[2], bK[2], Ks[2], cc[2], Kt[2], poly_r2[2], poly_near2[2];
-  // the polynomials' table (device memory, filled at set-up; RhoPoly) and
-  // its entries (0: no table, no cell qualifies)
+  // the polynomials' tables (device memory, filled at set-up; RhoPoly) and
+  // their entries (0: no table, no cell qualifies): in t (poly_*) and in
+  // x = d^2/2 (polyx_*)
   const RhoPoly* poly_tab;
   int64_t poly_n;
+  const RhoPoly* polyx_tab;
+  int64_t polyx_n;
 };
 
 // Per-cell polynomial of a single chord tanh bump, the quadrature's fast
@@ -356,8 +359,26 @@ constexpr int kPolyPerT = 256;       // table entries per unit of t
 constexpr int64_t kPolyMax = 65536;  // larger tables (alpha < 0.016) are not built
 struct RhoPoly {
   double c[kPolyDeg + 1];  // rho = sum_n c_n D^n
-  double off;              // D = Kt h + off (= t - t*), h = |y - x_c| / sqrt(2)
+  double off;  // in t: D = Kt h + off (= t - t*), h = |y - x_c| / sqrt(2);
+               // in x: D = off - r p.x_c (= x - x*, x = |y - x_c|^2 / 2)
+  double lim;  // in x: the largest |x - x*| the entry's bound covers
 };
+// The expansion in x (RhoPolyX): rho(x) = gamma + amp sigma(Kt sqrt(x) + t0)
+// with x = d^2/2 is analytic in the disc |x - x*| <= r_x for r_x < x* (the
+// square root's branch point at 0); there
+// |sqrt(x) - sqrt(x*)| <= sqrt(x*) w / (1 + sqrt(1 - w)), w = r_x / x*, so
+// t stays in the strip |Im t| <= r_t = Kt sqrt(x*) w / (1 + sqrt(1 - w)),
+// where |sigma| <= min(1, e^{-Re t}) / sin r_t.  As for t, the degree-9
+// truncation at |x - x*| <= delta errs relative to rho by at most
+//   2 e^{r_t + dt} (delta/r_x)^10 / (sin r_t (1 - delta/r_x)),
+// dt = Kt (sqrt(x*) - sqrt(x* - delta)) the largest move of t.  Each table
+// entry stores the largest delta with this below 1e-15 (w chosen so that
+// r_t <= 2.5, w <= 0.8).  A cell qualifies when
+// |x(z) - x*| + R (d(z) + R/2) <= that delta (|x(p) - x(z)| =
+// |d(p) - d(z)| (d(p) + d(z))/2 <= R (d(z) + R/2)).  Its points then need
+// neither the square root nor the scaling of the t path.
+constexpr double kPolyDx = 1e-4;     // the x grid: x* = j kPolyDx, x in [0, 2]
+constexpr double kPolyBound = 1e-15;
 
 SCVT_HD DensityP density_prepare(DensityP d) {
   for (int k = 0; k < 2; k++) {
@@ -377,6 +398,8 @@ SCVT_HD DensityP density_prepare(DensityP d) {
   const double span = single ? 4.0 / d.alpha[0] * kPolyPerT : 0.0;
   d.poly_n = single && span < (double)(kPolyMax - 2) ? (int64_t)span + 2 : 0;
   d.poly_tab = nullptr;
+  d.polyx_n = d.poly_n > 0 ? (int64_t)(2.0 / kPolyDx) + 2 : 0;
+  d.polyx_tab = nullptr;
   return d;
 }
 
@@ -643,7 +666,84 @@ SCVT_HD int64_t poly_index(const DensityP& D, V3 z) {
   return (int64_t)fmin(fmax(j, 0.0), (double)(D.poly_n - 1));
 }
 
+// Table entry j of the expansion in x about x* = j kPolyDx: the t-series
+// (poly_entry's b_n about t* = t(x*)) composed with the binomial series of
+// t(x* + D) - t* = Kt sqrt(x*) sum_{k>=1} binom(1/2, k) (D/x*)^k, both
+// truncated at degree 9; lim from the bound above (bisection).
+SCVT_HD RhoPoly polyx_entry(const DensityP& D, int64_t j, const double* tab = SCVT_EXP2_TAB) {
+  constexpr int K = kPolyDeg;
+  RhoPoly P{};
+  const double xs = (double)j * kPolyDx;
+  P.off = D.cc[0] - xs;
+  P.lim = 0.0;
+  if (j < 1) return P;
+  const double ss = sqrt(xs), ks = D.Kt[0] * ss;
+  const double ts = D.k2[0] * D.beta[0] + ks;  // t(x*) = Kt sqrt(x*) - 2 beta/alpha
+  const double s0 = rcp_nr(1.0 + exp2_n(fmin(ts * kExpInvLn, kUMax), tab));
+  const double q = 1.0 - s0;
+  double b[K + 1], a[K + 1], pw[K + 1], nw[K + 1], r[K + 1];
+  b[0] = 1.0;
+  for (int n = 1; n <= K; n++) {
+    double t = 0.0, f = 1.0;  // f = 1/k!
+    for (int k = 1; k <= n; k++) {
+      f /= (double)k;
+      t = fma(b[n - k], f, t);
+    }
+    b[n] = -q * t;
+  }
+  a[0] = 0.0;
+  double bin = 1.0, inv = 1.0;
+  for (int k = 1; k <= K; k++) {
+    bin *= (0.5 - (double)(k - 1)) / (double)k;
+    inv /= xs;
+    a[k] = ks * bin * inv;
+  }
+  for (int m = 0; m <= K; m++) {
+    pw[m] = m == 0 ? 1.0 : 0.0;
+    r[m] = m == 0 ? b[0] : 0.0;
+  }
+  for (int n = 1; n <= K; n++) {
+    for (int m = 0; m <= K; m++) {
+      double t = 0.0;
+      for (int i = 1; i <= m; i++) t = fma(a[i], pw[m - i], t);
+      nw[m] = t;
+    }
+    for (int m = 0; m <= K; m++) {
+      pw[m] = nw[m];
+      r[m] = fma(b[n], pw[m], r[m]);
+    }
+  }
+  const double as = D.amp[0] * s0;
+  for (int m = 0; m <= K; m++) P.c[m] = as * r[m];
+  P.c[0] += D.gamma;
+  // the bound: w for |Im t| <= 2.5 (at most 0.8), then the largest delta
+  const double y = 2.5 / ks;
+  const double w = y >= 0.5528 ? 0.8 : 2.0 * y - y * y;
+  const double rx = w * xs, rt = ks * w / (1.0 + sqrt(1.0 - w));
+  double lo = 0.0, hi = 0.5 * rx;
+  for (int it = 0; it < 60; it++) {
+    const double dl = 0.5 * (lo + hi), u = dl / rx;
+    const double dt = ks * (1.0 - sqrt(1.0 - dl / xs));
+    double pu = 1.0;
+    for (int k = 0; k <= K; k++) pu *= u;
+    const double bound = 2.0 * exp(rt + dt) * pu / (sin(rt) * (1.0 - u));
+    if (bound <= kPolyBound) lo = dl; else hi = dl;
+  }
+  P.lim = 0.98 * lo;
+  return P;
+}
+
+// the x table's entry of generator z, and x(z) = d(z)^2 / 2
+SCVT_HD int64_t polyx_index(const DensityP& D, V3 z, double* xz) {
+  const double x = fmax(D.cc[0] - dot(z, V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]}), 0.0);
+  *xz = x;
+  const double j = rint(x * (1.0 / kPolyDx));
+  return (int64_t)fmin(fmax(j, 1.0), (double)(D.polyx_n - 1));
+}
+
 // quad_tri_k with rho from the cell's polynomial (single chord tanh bump)
+// (X: the expansion in x, else in t)
+template <bool X>
 SCVT_HD void quad_tri_poly(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const RhoPoly& P,
                            Acc5& acc, int nq = 7) {
   const double(*R)[4] = SCVT_RULE_TABLE(nq);
@@ -656,8 +756,13 @@ SCVT_HD void quad_tri_poly(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const RhoP
     const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
                     fma(l2, CA.z, fma(l1, BA.z, A.z))};
     const double ri = rsq_near1(dot(p, p));
-    const double h = sqrt_nr_pos(fmax(fma(-ri, dot(p, xc), D.cc[0]), 1e-300));
-    const double dl = fma(h, D.Kt[0], P.off);
+    double dl;
+    if constexpr (X) {
+      dl = fma(-ri, dot(p, xc), P.off);
+    } else {
+      const double h = sqrt_nr_pos(fmax(fma(-ri, dot(p, xc), D.cc[0]), 1e-300));
+      dl = fma(h, D.Kt[0], P.off);
+    }
     double rho = P.c[kPolyDeg];
 #pragma unroll
     for (int n = kPolyDeg - 1; n >= 0; n--) rho = fma(rho, dl, P.c[n]);

@@ -549,7 +549,7 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   // polynomial's radius take it (RhoPoly); they are sorted ahead of the
   // others so that the two halves of a wave mostly take the same path
   constexpr bool POLY = !MIXED && KIND == kRhoTanh;
-  constexpr int kBins = (POLY ? 2 : 1) * (kVmax + 1);
+  constexpr int kBins = (POLY ? 3 : 1) * (kVmax + 1);
   __shared__ int bin[kBins];
   __shared__ int list[kQuadCells];
   const int tid = threadIdx.x;
@@ -559,19 +559,28 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
   if (tid < kExpN) tab[tid] = kExp2Tab[tid];
   if (tid < kBins) bin[tid] = 0;
   __syncthreads();
-  // sort key of each cell: degree, and for POLY whether its farthest vertex
-  // lies within the polynomial's radius (the geometry passes leave the
-  // distance, or a bound on it, in R; a relative 1e-9 covers its rounding)
-  int key = 0;
+  // sort key of each cell: degree, and for POLY which density path it takes
+  // -- the polynomial in x, else the one in t, else the direct evaluation --
+  // from the farthest vertex's distance (the geometry passes leave it, or a
+  // bound on it, in R; a relative 1e-9 covers its rounding)
+  int key = 0, dm = 0;
   const bool lead = tid < ncell;
   if (lead) {
     const int64_t i = base + tid;
-    const int dm = min(max(o.deg[i], 0), kVmax);
+    dm = min(max(o.deg[i], 0), kVmax);
     key = dm;
     if (POLY) {
       const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
       const double r = o.R[i] * (1.0 + 1e-9);
-      key = poly_qualifies(a.rho, z, r * r) ? dm : kVmax + 1 + dm;
+      double xz = 0.0;
+      bool xmode = false;
+      if (a.rho.polyx_n > 0) {
+        const int64_t j = polyx_index(a.rho, z, &xz);
+        const double dz = sqrt_nr_pos(fmax(2.0 * xz, 1e-300));
+        const double delta = fabs(xz - (double)j * kPolyDx) + r * (dz + 0.5 * r);
+        xmode = delta <= a.rho.polyx_tab[j].lim;
+      }
+      key = xmode ? dm : (poly_qualifies(a.rho, z, r * r) ? kVmax + 1 + dm : 2 * (kVmax + 1) + dm);
     }
   }
   if (lead) atomicAdd(&bin[key], 1);
@@ -585,8 +594,12 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
     }
   }
   __syncthreads();
-  // entries: the cell's place in the block, +256 if it takes the polynomial
-  if (lead) list[atomicAdd(&bin[key], 1)] = tid + (key <= kVmax && POLY ? 256 : 0);
+  // entries: the cell's place in the block, +256 if it takes a polynomial,
+  // +512 if that is the one in x, its degree from bit 10 on
+  if (lead) {
+    const int cls = POLY ? key / (kVmax + 1) : 2;
+    list[atomicAdd(&bin[key], 1)] = tid + (cls < 2 ? 256 : 0) + (cls == 0 ? 512 : 0) + (dm << 10);
+  }
   __syncthreads();
 
   const int ln = lane_id(), w = tid >> 6, hl = ln & 31;
@@ -607,16 +620,20 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
     const bool has = slot < ncell;
     const int ent = has ? list[slot] : 0;
     const int64_t i = base + (ent & 255);
-    const int d = has ? min(max(o.deg[i], 0), kVmax) : 0;
+    const int d = ent >> 10;
     const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
     const double* eb = o.edges + i * (kVmax * 6);  // the cell's edge slots
     const int items = d * per;  // this half's (edge, sub-triangle) items
     const int both = max(items, __shfl_xor(items, 32, 64));
     if (both == 0) continue;  // wave-uniform
     Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const bool use_poly = POLY && ent >= 256;
+    const bool use_poly = POLY && (ent & 256), xmode = POLY && (ent & 512);
     RhoPoly rp{};
-    if (use_poly) rp = ar.rho.poly_tab[poly_index(ar.rho, z)];
+    if (use_poly) {
+      double xz;
+      rp = xmode ? ar.rho.polyx_tab[polyx_index(ar.rho, z, &xz)]
+                 : ar.rho.poly_tab[poly_index(ar.rho, z)];
+    }
     if (lv == 2) {
       // the whole cell's grids (up to kGridEdges edges at a time), then its
       // leaves; the mixed path keeps FP32 offsets from z (its local frame)
@@ -688,8 +705,10 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
               const V3 A = V3{G[e][ka][0], G[e][ka][1], G[e][ka][2]};
               const V3 B = V3{G[e][kb][0], G[e][kb][1], G[e][kb][2]};
               const V3 C = V3{G[e][kc][0], G[e][kc][1], G[e][kc][2]};
-              if (use_poly)
-                quad_tri_poly(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+              if (xmode)
+                quad_tri_poly<true>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+              else if (use_poly)
+                quad_tri_poly<false>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
               else
                 quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
             }
@@ -705,8 +724,10 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
         V3 B = V3{ed[0], ed[1], ed[2]};
         V3 C = V3{ed[3], ed[4], ed[5]};
         subtriangle(A, B, C, sub, lv);
-        if (use_poly)
-          quad_tri_poly(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+        if (xmode)
+          quad_tri_poly<true>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+        else if (use_poly)
+          quad_tri_poly<false>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
         else
           quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
       }
@@ -751,15 +772,18 @@ hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s) {
   return hipGetLastError();
 }
 
-// the density polynomials' table (single chord tanh bump): entry j per thread
+// the density polynomials' tables (single chord tanh bump): entry j per
+// thread, of the expansion in t (X = false) or in x
+template <bool X>
 __global__ void k_poly_table(DensityP D, RhoPoly* out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < D.poly_n) out[j] = poly_entry(D, j, kExp2Tab);
+  if (j < (X ? D.polyx_n : D.poly_n)) out[j] = X ? polyx_entry(D, j, kExp2Tab) : poly_entry(D, j, kExp2Tab);
 }
 
-hipError_t launch_poly_table(const DensityP& D, RhoPoly* out, hipStream_t s) {
-  if (D.poly_n <= 0) return hipSuccess;
-  k_poly_table<<<(unsigned)((D.poly_n + 255) / 256), 256, 0, s>>>(D, out);
+hipError_t launch_poly_table(const DensityP& D, RhoPoly* out, RhoPoly* outx, hipStream_t s) {
+  if (D.poly_n > 0) k_poly_table<false><<<(unsigned)((D.poly_n + 255) / 256), 256, 0, s>>>(D, out);
+  if (D.polyx_n > 0)
+    k_poly_table<true><<<(unsigned)((D.polyx_n + 255) / 256), 256, 0, s>>>(D, outx);
   return hipGetLastError();
 }
 

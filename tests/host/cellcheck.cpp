@@ -147,10 +147,12 @@ int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int
 }
 
 // Cell integrals through the per-cell density polynomial (single chord tanh
-// bump) as the FP64 kernel takes them; returns 1 if the cell qualifies (then
-// out5 holds the integrals), 0 otherwise
+// bump) as the FP64 kernel takes them: the expansion in x if the cell
+// qualifies for it (returns 2), else the one in t if it qualifies for that
+// (returns 1); returns 0 (nothing computed) otherwise.  force: 1 only t, 2
+// only x (0: the kernel's choice).
 int hc_quad_poly(const double* z3, int E, const double* verts, const DensityP* D, int levels,
-                 int nq, double* out5) {
+                 int nq, double* out5, int force) {
   Acc5 acc = {0, 0, 0, 0, 0};
   DensityP Dp = density_prepare(*D);
   if (Dp.kind != kRhoTanh || Dp.nbumps != 1 || Dp.geodesic) return 0;
@@ -161,36 +163,53 @@ int hc_quad_poly(const double* z3, int E, const double* verts, const DensityP* D
       const V3 v = V3{verts[6 * e + 3 * c], verts[6 * e + 3 * c + 1], verts[6 * e + 3 * c + 2]} - z;
       r2 = fmax(r2, dot(v, v));
     }
-  if (!poly_qualifies(Dp, z, r2)) return 0;
-  const RhoPoly P = poly_entry(Dp, poly_index(Dp, z));
+  const double r = sqrt(r2);
+  double xz = 0.0;
+  const int64_t jx = polyx_index(Dp, z, &xz);
+  const RhoPoly PX = polyx_entry(Dp, jx);
+  const double delta = fabs(xz - (double)jx * kPolyDx) + r * (sqrt(2.0 * xz) + 0.5 * r);
+  const bool xq = delta <= PX.lim, tq = poly_qualifies(Dp, z, r2);
+  int mode = 0;
+  if (force == 2) mode = xq ? 2 : 0;
+  else if (force == 1) mode = tq ? 1 : 0;
+  else mode = xq ? 2 : (tq ? 1 : 0);
+  if (mode == 0) return 0;
+  const RhoPoly P = mode == 2 ? PX : poly_entry(Dp, poly_index(Dp, z));
   const int per = 1 << (2 * levels);
   for (int t = 0; t < E * per; t++) {
     int e = t >> (2 * levels), s = t & (per - 1);
     V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
        C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
     subtriangle(A, B, C, s, levels);
-    quad_tri_poly(A, B, C, z, Dp, P, acc, nq);
+    if (mode == 2)
+      quad_tri_poly<true>(A, B, C, z, Dp, P, acc, nq);
+    else
+      quad_tri_poly<false>(A, B, C, z, Dp, P, acc, nq);
   }
   out5[0] = acc.m;
   out5[1] = acc.mx;
   out5[2] = acc.my;
   out5[3] = acc.mz;
   out5[4] = acc.e;
-  return 1;
+  return mode;
 }
 
 // rho at the unit points y (n x 3) from the polynomial table's entry of
-// generator z, and from the exact evaluation
+// generator z (mode 0: in t, 1: in x), and from the exact evaluation; lim
+// receives the x entry's radius
 int hc_rho_poly(const double* z3, const DensityP* D, int64_t n, const double* y, double* poly,
-                double* exact) {
+                double* exact, int mode, double* lim) {
   DensityP Dp = density_prepare(*D);
   V3 z = V3{z3[0], z3[1], z3[2]};
-  const RhoPoly P = poly_entry(Dp, poly_index(Dp, z));
+  double xz = 0.0;
+  const RhoPoly P = mode == 1 ? polyx_entry(Dp, polyx_index(Dp, z, &xz))
+                              : poly_entry(Dp, poly_index(Dp, z));
+  *lim = P.lim;
   for (int64_t k = 0; k < n; k++) {
     const V3 p = V3{y[3 * k], y[3 * k + 1], y[3 * k + 2]};
-    const double h = sqrt_nr_pos(fmax(fma(-1.0, dot(p, V3{Dp.xc[0][0], Dp.xc[0][1], Dp.xc[0][2]}),
-                                          Dp.cc[0]), 1e-300));
-    const double dl = fma(h, Dp.Kt[0], P.off);
+    const double u = fma(-1.0, dot(p, V3{Dp.xc[0][0], Dp.xc[0][1], Dp.xc[0][2]}),
+                         mode == 1 ? P.off : Dp.cc[0]);
+    const double dl = mode == 1 ? u : fma(sqrt_nr_pos(fmax(u, 1e-300)), Dp.Kt[0], P.off);
     double r = P.c[kPolyDeg];
     for (int j = kPolyDeg - 1; j >= 0; j--) r = fma(r, dl, P.c[j]);
     poly[k] = r;

@@ -73,7 +73,8 @@ class CDensity(ctypes.Structure):
                 ("bK", ctypes.c_double * 2), ("Ks", ctypes.c_double * 2),
                 ("cc", ctypes.c_double * 2), ("Kt", ctypes.c_double * 2),
                 ("poly_r2", ctypes.c_double * 2), ("poly_near2", ctypes.c_double * 2),
-                ("poly_tab", ctypes.c_void_p), ("poly_n", ctypes.c_int64)]
+                ("poly_tab", ctypes.c_void_p), ("poly_n", ctypes.c_int64),
+                ("polyx_tab", ctypes.c_void_p), ("polyx_n", ctypes.c_int64)]
 
 
 KIND = {"const": 0, "tanh": 1, "x3": 2, "x16": 3}
@@ -107,26 +108,32 @@ def quad(z, E, verts, density, levels=2, rule=7):
     return out
 
 
-def quad_poly(z, E, verts, density, levels=2, rule=7):
-    """Cell integrals through the per-cell density polynomial, or None if
-    the cell does not qualify."""
+def quad_poly(z, E, verts, density, levels=2, rule=7, force=0):
+    """Cell integrals through the per-cell density polynomial as the kernel
+    chooses it (force 1: only the expansion in t, 2: only in x); returns
+    (integrals, mode) with mode 2 for x, 1 for t, or None if the cell does
+    not qualify."""
     z = np.ascontiguousarray(z, dtype=np.float64)
     verts = np.ascontiguousarray(verts, dtype=np.float64)
     out = np.zeros(5)
     D = cdensity(density)
-    ok = lib().hc_quad_poly(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D),
-                            ctypes.c_int(levels), ctypes.c_int(rule), P(out))
-    return out if ok else None
+    mode = lib().hc_quad_poly(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D),
+                              ctypes.c_int(levels), ctypes.c_int(rule), P(out), ctypes.c_int(force))
+    return (out, mode) if mode else None
 
 
-def rho_poly(z, density, Y):
+def rho_poly(z, density, Y, mode=0):
+    """rho at unit points Y from generator z's table entry (mode 0: the
+    expansion in t, 1: in x) and directly; also the x entry's radius."""
     z = np.ascontiguousarray(z, dtype=np.float64)
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     poly = np.zeros(len(Y))
     exact = np.zeros(len(Y))
+    lim = np.zeros(1)
     D = cdensity(density)
-    lib().hc_rho_poly(P(z), ctypes.byref(D), ctypes.c_int64(len(Y)), P(Y), P(poly), P(exact))
-    return poly, exact
+    lib().hc_rho_poly(P(z), ctypes.byref(D), ctypes.c_int64(len(Y)), P(Y), P(poly), P(exact),
+                      ctypes.c_int(mode), P(lim))
+    return poly, exact, float(lim[0])
 
 
 def quad_mixed(z, E, verts, density, levels=2, rule=7):

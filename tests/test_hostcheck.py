@@ -284,11 +284,11 @@ def test_density_polynomial_within_bound(chord):
     z = I.toward(xc, chord, 3)
     rl = 0.5 * (0.05 - 1 / 512) * d["alpha"][0]
     Y = I.cap_points(z, rl * 0.999, 20000, 4)
-    poly, exact = hc.rho_poly(z, d, Y)
+    poly, exact, _ = hc.rho_poly(z, d, Y)
     rel = np.abs(poly - exact) / exact
     assert rel.max() < 1.5e-14, rel.max()
     Yf = I.cap_points(z, 8 * rl, 20000, 5)
-    pf, ef = hc.rho_poly(z, d, Yf)
+    pf, ef, _ = hc.rho_poly(z, d, Yf)
     if 0.1 <= chord <= 0.8:  # where the logistic varies
         assert (np.abs(pf - ef) / ef).max() > 10 * rel.max()
 
@@ -297,8 +297,9 @@ def test_density_polynomial_within_bound(chord):
                                          (0.6, 600, 0.012), (0.349, 250, 0.03)])
 def test_density_polynomial_quadrature_matches_oracle(chord, m, cap):
     """Small cells (a dense cluster of generators) qualify for the per-cell
-    density polynomial; their integrals through it agree with the direct
-    FP64 path on the same vertices to 2e-14, and with the oracle (which
+    density polynomials (in t and, away from the centre, in x); their
+    integrals through either agree with the direct FP64 path on the same
+    vertices to 2e-14, and with the oracle (which
     builds its own vertices) to 1e-12 on m and mu and 3e-12 on e: a cell of
     circumradius R ~ 6e-4 whose vertices move by an ulp moves its second
     moment by ~4 x 2e-16 / R relative."""
@@ -314,10 +315,11 @@ def test_density_polynomial_quadrature_matches_oracle(chord, m, cap):
     st, deg, nbr, verts, R = hc.cells(Z, rad)
     used = 0
     worst = [0.0, 0.0, 0.0, 0.0]
-    for k in np.where(st == 0)[0]:
-        out = hc.quad_poly(Z[k], deg[k], verts[k], d)
-        if out is None:
+    for k, force in [(k, f) for k in np.where(st == 0)[0] for f in (1, 2)]:
+        res = hc.quad_poly(Z[k], deg[k], verts[k], d, force=force)
+        if res is None:
             continue
+        out = res[0]
         used += 1
         ref = hc.quad(Z[k], deg[k], verts[k], d)
         worst[0] = max(worst[0], abs(out[0] - ev.m[k]) / ev.m[k])
@@ -355,3 +357,30 @@ def test_density_polynomial_skips_cells_near_centre():
             assert q
             far += 1
     assert near >= 100 and far >= 100, (near, far)
+
+
+@pytest.mark.parametrize("chord", [0.45, 0.8, 1.3, 1.95])
+def test_density_polynomial_in_x_within_bound(chord):
+    """The expansion in x = d^2/2 (no square root per point) agrees with the
+    direct evaluation wherever its table entry's radius covers |x - x*|
+    (truncation below 1e-15 by its Cauchy bound, plus the dot product's
+    rounding), the radius covers the benchmark's cells (R ~ 3e-3) at these
+    distances, and beyond 4 times the radius the error is far larger."""
+    d = I.CONFIGS["C3"]["density"]
+    xc = np.array(d["xc"][0])
+    z = I.toward(xc, chord, 3)
+    _, _, lim = hc.rho_poly(z, d, z[None, :], mode=1)
+    xz = 0.5 * float(np.sum((z - xc) ** 2))
+    jx = round(xz / 1e-4)
+    slack = lim - abs(xz - jx * 1e-4)
+    dz = math.sqrt(2 * xz)
+    rcap = slack / (dz + slack)  # R (d + R/2) <= slack
+    assert rcap >= 3.3e-3 or chord < 0.5, rcap
+    Y = I.cap_points(z, 0.999 * rcap, 20000, 4)
+    poly, exact, _ = hc.rho_poly(z, d, Y, mode=1)
+    rel = np.abs(poly - exact) / exact
+    assert rel.max() < 1.5e-14, rel.max()
+    if chord <= 0.8:  # where the logistic varies
+        Yf = I.cap_points(z, 4 * rcap, 20000, 5)
+        pf, ef, _ = hc.rho_poly(z, d, Yf, mode=1)
+        assert (np.abs(pf - ef) / ef).max() > 10 * rel.max()
