@@ -662,8 +662,10 @@ SCVT_HD RhoPoly poly_entry(const DensityP& D, int64_t j, const double* tab = SCV
 SCVT_HD int64_t poly_index(const DensityP& D, V3 z) {
   const double zc = dot(z, V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]});
   const double h0 = sqrt_nr_pos(fmax(D.cc[0] - zc, 1e-300));
-  const double j = rint(h0 * (D.Kt[0] * kPolyPerT));
-  return (int64_t)fmin(fmax(j, 0.0), (double)(D.poly_n - 1));
+  // clamped in 32-bit integers (both tables hold fewer than 2^31 entries):
+  // the bounds stay scalar operands
+  const int j = (int)fmin(rint(h0 * (D.Kt[0] * kPolyPerT)), 2e9);
+  return min(max(j, 0), (int)D.poly_n - 1);
 }
 
 // Table entry j of the expansion in x about x* = j kPolyDx: the t-series
@@ -737,8 +739,8 @@ SCVT_HD RhoPoly polyx_entry(const DensityP& D, int64_t j, const double* tab = SC
 SCVT_HD int64_t polyx_index(const DensityP& D, V3 z, double* xz) {
   const double x = fmax(D.cc[0] - dot(z, V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]}), 0.0);
   *xz = x;
-  const double j = rint(x * (1.0 / kPolyDx));
-  return (int64_t)fmin(fmax(j, 1.0), (double)(D.polyx_n - 1));
+  const int j = (int)fmin(rint(x * (1.0 / kPolyDx)), 2e9);
+  return min(max(j, 1), (int)D.polyx_n - 1);
 }
 
 // quad_tri_k with rho from the cell's polynomial (single chord tanh bump)
