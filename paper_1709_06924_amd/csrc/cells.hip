@@ -648,11 +648,15 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
       for (int e0 = 0; e0 < dboth; e0 += kGridEdges) {
         const int ne = min(max(d - e0, 0), kGridEdges);
         const int neb = max(ne, __shfl_xor(ne, 32, 64));
-        if (hl < 3 * ne) {  // corners: v_lo (4) and v_hi (0) of each edge, then z (14)
+        // corners: v_lo (4) and v_hi (0) of each edge, then z (14); the edge
+        // slots are read once, so their loads are marked streaming and do
+        // not push the density tables out of the L2
+        if (hl < 3 * ne) {
           const bool vert = hl < 2 * ne;
           const int e = vert ? hl >> 1 : hl - 2 * ne, k = vert ? ((hl & 1) ? 0 : 4) : 14;
           const double* ed = eb + (e0 + e) * 6 + ((hl & 1) ? 3 : 0);
-          const V3 P = vert ? V3{ed[0], ed[1], ed[2]} : z;
+          const V3 P = vert ? V3{__builtin_nontemporal_load(ed), __builtin_nontemporal_load(ed + 1),
+                                    __builtin_nontemporal_load(ed + 2)} : z;
           if (MIXED) {
             const F3 q = vert ? to_f3(P - z) : F3{0.0f, 0.0f, 0.0f};
             Gf[e][k][0] = q.x;
