@@ -315,8 +315,11 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
       a.out.R[i] = R;
       a.out.flags[i] = 0;
     }
+    // the lane recounted from the exec mask's bits below it: reading
+    // threadIdx.x again here would keep it live through the whole build
     if (a.keep_cells)
-      for (int k = G.gl; k < kVmax; k += GS)
+      for (int k = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)) & (GS - 1);
+           k < kVmax; k += GS)
         if (k >= E) a.out.cell_nbr[i * kVmax + k] = -1;
   }
   return outcome;
