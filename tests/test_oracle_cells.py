@@ -188,18 +188,28 @@ def test_total_area_and_moment_rho1():
 
 
 def tanh_totals(d):
-    xc = np.array(d["xc"][0])
-    g, a, b, amp = d["gamma"], d["alpha"][0], d["beta"][0], d["amp"][0]
+    """Total mass and first moment of the tanh family by linearity: the floor
+    gamma contributes 4 pi gamma and no moment; bump k is axially symmetric
+    about its own centre x_c,k, so with theta the angle from x_c,k its mass
+    is 2 pi amp_k int sigma_k(theta) sin(theta) and its moment is x_c,k times
+    2 pi amp_k int sigma_k(theta) cos(theta) sin(theta)  (1-D scipy quad)."""
+    g = d["gamma"]
+    M = 4 * math.pi * g
+    MU = np.zeros(3)
+    for k in range(len(d["xc"])):
+        xc = np.array(d["xc"][k])
+        a, b, amp = d["alpha"][k], d["beta"][k], d["amp"][k]
 
-    def rho(theta):
-        dist = theta if d.get("geodesic") else 2 * math.sin(theta / 2)
-        return g + amp * 0.5 * (math.tanh((b - dist) / a) + 1)
+        def bump(theta):
+            dist = theta if d.get("geodesic") else 2 * math.sin(theta / 2)
+            return amp * 0.5 * (math.tanh((b - dist) / a) + 1)
 
-    M = 2 * math.pi * integrate.quad(lambda t: rho(t) * math.sin(t), 0, math.pi, epsabs=0,
-                                     epsrel=1e-13, limit=400)[0]
-    m1 = 2 * math.pi * integrate.quad(lambda t: rho(t) * math.cos(t) * math.sin(t), 0, math.pi,
-                                      epsabs=0, epsrel=1e-13, limit=400)[0]
-    return M, m1 * xc
+        M += 2 * math.pi * integrate.quad(lambda t: bump(t) * math.sin(t), 0, math.pi, epsabs=0,
+                                          epsrel=1e-13, limit=400)[0]
+        m1 = 2 * math.pi * integrate.quad(lambda t: bump(t) * math.cos(t) * math.sin(t), 0,
+                                          math.pi, epsabs=0, epsrel=1e-13, limit=400)[0]
+        MU += m1 * xc
+    return M, MU
 
 
 @pytest.mark.parametrize("geodesic", [False, True])
@@ -209,6 +219,63 @@ def test_total_mass_tanh(geodesic):
     ev = oracle.evaluate(Z, d)
     M, MU = tanh_totals(d)
     assert abs(ev.m.sum() - M) / M < 1e-9
+    assert np.linalg.norm(ev.mu.sum(0) - MU) / np.linalg.norm(MU) < 1e-8
+
+
+def test_total_mass_two_centre():
+    """The two-bump density (sum over bumps with their own heights) against
+    the per-bump 1-D integrals; dropping the second bump moves the mass by
+    ~5% and the moment's direction by tens of degrees."""
+    d = I.density_two_centre()
+    Z = I.uniform_sphere(10242, 5)
+    ev = oracle.evaluate(Z, d)
+    M, MU = tanh_totals(d)
+    assert abs(ev.m.sum() - M) / M < 1e-9
+    assert np.linalg.norm(ev.mu.sum(0) - MU) / np.linalg.norm(MU) < 1e-8
+    M1, _ = tanh_totals(dict(d, xc=d["xc"][:1], beta=d["beta"][:1], alpha=d["alpha"][:1],
+                             amp=d["amp"][:1]))
+    assert (M - M1) / M > 0.01
+
+
+def x16_totals(d):
+    """Mass and first moment of the X16 density by 2-D scipy quadrature over
+    latitude and longitude (area element cos(lat)), the distance in spherical
+    trigonometry (see test_oracle_rule._x16_closed_form), the ranges split
+    at the centre's parallel and meridian where the distance has kinks."""
+    xc = np.array(d["xc"][0])
+    lat_c, lon_c = math.asin(xc[2]), math.atan2(xc[1], xc[0])
+
+    def rho(la, lo):
+        d_lon = 2.0 * math.asin(math.cos(la) * abs(math.sin((lo - lon_c) / 2.0)))
+        dist = math.hypot(d_lon / d["w_lon"], (la - lat_c) / d["w_lat"])
+        return d["gamma"] + d["amp"][0] * 0.5 * (math.tanh((d["beta"][0] - dist) / d["alpha"][0]) + 1)
+
+    def integral(f):
+        tot = 0.0
+        for lo0, lo1 in ((lon_c - math.pi, lon_c), (lon_c, lon_c + math.pi)):
+            for la0, la1 in ((-math.pi / 2, lat_c), (lat_c, math.pi / 2)):
+                tot += integrate.dblquad(lambda la, lo: f(la, lo) * math.cos(la), lo0, lo1,
+                                         la0, la1, epsabs=1e-13, epsrel=1e-12)[0]
+        return tot
+
+    M = integral(rho)
+    MU = np.array([integral(lambda la, lo: rho(la, lo) * math.cos(la) * math.cos(lo)),
+                   integral(lambda la, lo: rho(la, lo) * math.cos(la) * math.sin(lo)),
+                   integral(lambda la, lo: rho(la, lo) * math.sin(la))])
+    return M, MU
+
+
+def test_total_mass_x16():
+    """X16 totals against 2-D quadrature of its closed form.  The density has
+    kinks along the centre's parallel and meridian (|lat - lat_c| and the arc
+    of the parallel), which the cells' degree-5 rule resolves only to about
+    1.3e-9 relative at n = 10,242 (measured), so the tolerance is 1e-8; a
+    swap of the two widths moves the mass by 1.5e-3."""
+    d = I.density_x16()
+    Z = I.uniform_sphere(10242, 6)
+    ev = oracle.evaluate(Z, d)
+    M, MU = x16_totals(d)
+    assert abs(ev.m.sum() - M) / M < 1e-8, (ev.m.sum(), M)
     assert np.linalg.norm(ev.mu.sum(0) - MU) / np.linalg.norm(MU) < 1e-8
 
 
@@ -234,3 +301,25 @@ def test_local_cell_equals_global():
         assert np.max(np.abs(mu - ev.mu[i])) <= 1e-15
         assert abs(e - ev.e[i]) <= 1e-14 * ev.e[i]
         assert len(nb) == ev.cells.deg()[i]
+
+
+def test_one_ulp_generator_change_conditioning():
+    """The limit of per-cell parity: renormalising the rows once more (a
+    change of at most an ulp or two in ~a third of the generators) moves the
+    masses of a few ill-conditioned cells (near-cocircular generators, whose
+    Voronoi vertices move by ~ulp / angle) by a few 1e-12 relative, while the
+    median cell moves by ~1e-13.  So the GPU and the oracle must evaluate the
+    very same generators (the library's renormalised rows) before their
+    cells are compared at 1e-12."""
+    n = 2562
+    Z0 = I.uniform_sphere(n, 1)
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    Z1 = oracle.normalize_rows(Z0)
+    changed = np.any(Z1 != Z0, axis=1)
+    assert 0.1 * n < changed.sum() < 0.6 * n
+    assert np.max(np.abs(Z1 - Z0)) <= 2 * np.finfo(float).eps
+    a, b = oracle.evaluate(Z0, d), oracle.evaluate(Z1, d)
+    rel = np.abs(a.m - b.m) / a.m
+    assert 1e-12 < rel.max() < 2e-11, rel.max()
+    assert np.median(rel) < 2e-13
+    assert abs(a.F - b.F) < 1e-14 * a.F

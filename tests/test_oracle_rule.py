@@ -171,3 +171,69 @@ def test_conical_rules_converge_on_spherical_triangles(nq, ratio):
     for L in range(1, 5):
         if errs[L] > 1e-13:
             assert errs[L - 1] / errs[L] > ratio, errs
+
+
+# ---- the anisotropic X16 density of section 4 --------------------------------
+
+def _x16_closed_form(d, lat, lon):
+    """rho at (lat, lon) from the section-4 definition written with spherical
+    trigonometry instead of points: z_ic shares the point's latitude and the
+    centre's longitude, so |z - z_ic| is the arc between two points of one
+    parallel, 2 asin(cos(lat) |sin(dlon/2)|); z_ci shares the centre's
+    latitude and the point's longitude, so |z - z_ci| = |lat - lat_c| along
+    one meridian.  (tanh(x) + 1)/2 in its tanh form."""
+    xc = np.array(d["xc"][0])
+    lat_c = math.asin(xc[2])
+    lon_c = math.atan2(xc[1], xc[0])
+    dlon = lon - lon_c
+    d_lon = 2.0 * math.asin(math.cos(lat) * abs(math.sin(dlon / 2.0)))
+    d_lat = abs(lat - lat_c)
+    dist = math.sqrt((d_lon / d["w_lon"]) ** 2 + (d_lat / d["w_lat"]) ** 2)
+    t = (d["beta"][0] - dist) / d["alpha"][0]
+    return d["gamma"] + d["amp"][0] * 0.5 * (math.tanh(t) + 1.0), dist
+
+
+def _x16_at(d, lat, lon):
+    L = _clib.lib()
+    D = _clib.cdensity(d)
+    p = np.array([math.cos(lat) * math.cos(lon), math.cos(lat) * math.sin(lon), math.sin(lat)])
+    return L.oracle_rho(ctypes.byref(D), _clib.ptr(p))
+
+
+@pytest.mark.parametrize("centre", [(0.0, 0.0), (20.0, 40.0), (-35.0, -120.0)])
+def test_x16_density_closed_forms(centre):
+    """X16 (section 4) at points on the centre's parallel (distance = the
+    parallel's arc over w_lon), on its meridian (distance = latitude offset
+    over w_lat) and anywhere (both terms), against the closed form; a swap of
+    the widths or of the two auxiliary points fails the first two families."""
+    import paper_1709_06924_amd.inputs as I
+    d = I.density_x16()
+    lat_c, lon_c = map(math.radians, centre)
+    d["xc"] = [I.latlon(*centre)]
+    worst = 0.0
+    # on the centre's parallel: only the longitude term
+    for dl in np.linspace(-3.0, 3.0, 25):
+        rho, dist = _x16_closed_form(d, lat_c, lon_c + dl)
+        assert abs(dist - 2 * math.asin(math.cos(lat_c) * abs(math.sin(dl / 2))) / d["w_lon"]) < 1e-15
+        worst = max(worst, abs(_x16_at(d, lat_c, lon_c + dl) - rho))
+    # on the centre's meridian: only the latitude term
+    for la in np.linspace(-1.5, 1.5, 25):
+        rho, dist = _x16_closed_form(d, la, lon_c)
+        assert abs(dist - abs(la - lat_c) / d["w_lat"]) < 1e-15
+        worst = max(worst, abs(_x16_at(d, la, lon_c) - rho))
+    # general points
+    rng = np.random.default_rng(16)
+    for _ in range(200):
+        la, lo = rng.uniform(-1.5, 1.5), rng.uniform(-math.pi, math.pi)
+        rho, _ = _x16_closed_form(d, la, lo)
+        worst = max(worst, abs(_x16_at(d, la, lo) - rho))
+    assert worst < 2e-15, worst
+    # the anisotropy: the same angular offset costs w_lat/w_lon = 4 times more
+    # distance along the parallel than along the meridian
+    if centre == (0.0, 0.0):
+        r_lon = _x16_at(d, 0.0, 0.3)
+        r_lat = _x16_at(d, 1.2, 0.0)
+        exact = d["gamma"] + d["amp"][0] * 0.5 * (math.tanh((d["beta"][0] - 1.0) / d["alpha"][0]) + 1)
+        assert abs(r_lon - exact) < 1e-15 and abs(r_lat - exact) < 1e-15
+        assert abs(_x16_at(d, 0.0, 0.0) - (d["gamma"] + d["amp"][0] * 0.5 * (
+            math.tanh(d["beta"][0] / d["alpha"][0]) + 1))) < 1e-15
