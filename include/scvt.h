@@ -55,7 +55,12 @@ extern "C" {
 #define SCVT_E_OOM -2          /* device allocation failed or over budget */
 #define SCVT_E_DEGENERATE -3   /* duplicate or zero generators */
 #define SCVT_E_CERT -4         /* a Voronoi cell could not be built */
-#define SCVT_E_LINESEARCH -5   /* reserved (the Lloyd step is taken instead) */
+#define SCVT_E_LINESEARCH -5   /* no sufficient decrease along the direction, and the
+                                  Lloyd step taken instead raised F beyond the
+                                  evaluation's rounding, max(ls_noise, 1e-13) |F|
+                                  (section 2.2.1: it lowers the exact energy); the
+                                  generators stay at the last iterate, the LBFGS
+                                  history is cleared */
 #define SCVT_E_NUMERIC -6      /* NaN, or mu_i . z_i <= 0 (h undefined) */
 #define SCVT_E_HIP -7          /* a HIP runtime call failed */
 
@@ -155,7 +160,8 @@ int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt
  * line search, history update; if the line search finds no sufficient
  * decrease in ls_max_evals evaluations, the history is cleared and the Lloyd
  * step (alpha = 1) is taken, which decreases F in exact arithmetic (section
- * 2.2.1).  Lloyd: the Lloyd step, one evaluation.  info may be NULL. */
+ * 2.2.1); SCVT_E_LINESEARCH if it does not.  Lloyd: the Lloyd step, one
+ * evaluation.  info may be NULL. */
 int scvt_step(scvt_handle* h, scvt_info* info);
 
 /* Iterate until step_inf < tol_step_inf or max_iter iterations in total.

@@ -20,7 +20,7 @@ fixes; both sides implement the same ones.  Converged meshes beyond the
 energy statistics are unpinned too (the energy has many local minima).
 """
 from ._clib import build  # noqa: F401
-from .scvt import (Evaluation, Solver, cell_integrals, dot, evaluate, local_cell,  # noqa: F401
+from .scvt import (Evaluation, LineSearchError, Solver, cell_integrals, dot, evaluate, local_cell,  # noqa: F401
                    normalize_rows, two_loop)
 from .voronoi import cells, circumcentres, delaunay, neighbour_sets  # noqa: F401
 from . import mesh  # noqa: F401

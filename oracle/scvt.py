@@ -19,7 +19,9 @@ backtracking from alpha = 1 (the Lloyd step length, section 3.1), factor 1/2,
 c1 = 1e-4, at most ten evaluations (section 4: ten evaluations, M = 7 by
 default); every trial point is projected back to the sphere (section 3.1).
 When no trial passes, the history is cleared and the Lloyd step itself is
-taken (it decreases F without a line search, section 2.2.1).
+taken (it decreases the exact F without a line search, section 2.2.1); if
+the evaluated F rises beyond rounding (1e-13 relative) all the same,
+LineSearchError is raised and the generators stay where they were.
 """
 import numpy as np
 
@@ -98,6 +100,16 @@ def two_loop(g, h, hist):
     return q
 
 
+class LineSearchError(RuntimeError):
+    """No sufficient decrease along the direction, and the Lloyd step did
+    not lower F either (beyond the evaluation's rounding)."""
+
+
+# relative rise of F the Lloyd fallback may show and still count as a
+# decrease (the evaluation's rounding in FP64)
+LLOYD_ALLOWANCE = 1e-13
+
+
 class Solver:
     """Lloyd-preconditioned LBFGS (state machine written out plainly).
 
@@ -173,6 +185,11 @@ class Solver:
             q = -cur.h[:, None] * cur.g
             ev = evaluate(normalize_rows(cur.Z + q), self.density, self.levels, self.rule)
             self.n_evals += 1
+            # section 2.2.1: Lloyd's step lowers the exact energy; a rise of
+            # the evaluated energy (coarse quadrature of very large cells)
+            # ends the iteration, the generators staying where they are
+            if not ev.F <= cur.F + LLOYD_ALLOWANCE * abs(cur.F):
+                raise LineSearchError("Lloyd step raised F from %.17g to %.17g" % (cur.F, ev.F))
             alpha = 1.0
             self.n_lloyd_fallback += 1
         s = ev.Z - cur.Z

@@ -47,10 +47,14 @@ struct scvt_handle {
   GridBufs grid{};
   double *Z = nullptr, *Zt = nullptr, *q = nullptr, *R = nullptr;
   EvalSet cur, trial;
-  double *S = nullptr, *Y = nullptr;  // (M+1) slots of 3n
+  // history slots: M + 2 of 3n each -- the M stored pairs, a pair whose
+  // curvature test is pending, and the slot the next trial's early push
+  // writes (never one that undoing the pending pair would restore)
+  int nslots = 0;
+  double *S = nullptr, *Y = nullptr;
   double* dscal = nullptr;            // device scalars
   double* partials = nullptr;
-  double* gram = nullptr;   // s_j . y_k (j older than k) by slot, (M+1)^2
+  double* gram = nullptr;   // s_j . y_k (j older than k) by slot, nslots^2
   double* hgam = nullptr;   // plain LBFGS: gamma_n on every generator
   double* hpart = nullptr;  // block partials of the history passes
   int32_t* fb_list = nullptr;
@@ -192,6 +196,8 @@ DensityP to_dev(const scvt_density& d) {
 
 int validate(const scvt_config* c) {
   if (!c || c->n < 4 || c->n > (int64_t)1 << 28) return SCVT_E_INVALID;  // 3n < 2^31
+  // M + 2 history slots index the per-slot scalars (64 entries each)
+  static_assert(kYY + 62 <= kNScal && kR + 62 <= kGQ && kSG + 62 <= kYY, "slot scalars");
   if (c->m_hist < 0 || c->m_hist > 60) return SCVT_E_INVALID;
   if (c->method < SCVT_METHOD_PLBFGS || c->method > SCVT_METHOD_LBFGS) return SCVT_E_INVALID;
   if (c->precision != SCVT_FP64 && c->precision != SCVT_MIXED) return SCVT_E_INVALID;
@@ -424,7 +430,7 @@ int direction_fused(scvt_handle* h, const double* hv, double* gq) {
   f.partials = h->hpart;
   f.nblocks = hist_grid(n3);
   f.c = c;
-  f.stride = h->M + 1;
+  f.stride = h->nslots;
   f.dscal = D;
   f.gram = h->gram;
   HistPassArgs p{};
@@ -471,7 +477,7 @@ int hist_rebuild(scvt_handle* h) {
   if (h->M > kHmax || c == 0) return SCVT_OK;
   hipStream_t st = h->stream;
   const int64_t n3 = 3 * h->n;
-  const int stride = h->M + 1;
+  const int stride = h->nslots;
   auto S = [&](int j) { return h->S + (size_t)h->ring[j] * n3; };
   for (int k = 0; k <= c; k++) {  // k = c: against g; else against y_k
     const int cnt = k == c ? c : k;
@@ -625,6 +631,11 @@ int lloyd_direction(scvt_handle* h, double* gq) {
   return h->M <= kHmax ? direction_fused(h, h->cur.h, gq) : direction_passes(h, h->cur.h, gq);
 }
 
+// Relative rise of F the Lloyd fallback may show and still count as a
+// decrease: the evaluation's rounding (1e-13 relative in FP64; the mixed
+// path's FP32 noise allowance when larger)
+double lloyd_allowance(const scvt_handle* h) { return h->ls_noise > 1e-13 ? h->ls_noise : 1e-13; }
+
 // Armijo's sufficient decrease for the trial just evaluated at step alpha
 bool armijo(const scvt_handle* h, double alpha, double gq) {
   return h->tF <= h->F + h->cfg.ls_c1 * alpha * gq + h->ls_noise * fabs(h->F);
@@ -671,9 +682,19 @@ hipError_t launch_push_ext_now(scvt_handle* h, int slot) {
 }
 
 // the trial's push, ahead of its acceptance (a rejected trial's slot stays
-// free and its partials are overwritten)
+// free and its partials are overwritten).  While the last pair's curvature
+// test is pending, the slot must not be one the history held before that
+// push: undoing the push restores that history, vectors included.
 int launch_push_pre(scvt_handle* h) {
-  const int slot = h->free_slots.back();
+  int slot = -1;
+  for (int k = (int)h->free_slots.size() - 1; k >= 0 && slot < 0; k--) {
+    const int c = h->free_slots[k];
+    bool held = false;
+    if (h->push_pending)
+      for (int r : h->ring_prev) held = held || r == c;
+    if (!held) slot = c;
+  }
+  if (slot < 0) return SCVT_OK;  // no such slot: push_pair launches the push
   HIPCK(launch_push_ext_now(h, slot));
   h->pre_valid = true;
   h->pre_slot = slot;
@@ -683,7 +704,13 @@ int launch_push_pre(scvt_handle* h) {
 
 int push_pair(scvt_handle* h) {
   if (h->M == 0) return SCVT_OK;
-  const int slot = h->free_slots.back();
+  // the slot of the push launched behind the trial's evaluation, if it was
+  // launched for this history; else any free slot
+  int slot_pos = (int)h->free_slots.size() - 1;
+  if (h->pre_valid && h->pre_ring == h->ring)
+    for (int k = 0; k < (int)h->free_slots.size(); k++)
+      if (h->free_slots[k] == h->pre_slot) slot_pos = k;
+  const int slot = h->free_slots[slot_pos];
   const int64_t n3 = 3 * h->n;
   // the history the pair joins (decided at the next host sync, resolve_push)
   std::vector<int> ring_next = h->ring;
@@ -699,7 +726,7 @@ int push_pair(scvt_handle* h) {
     f.nvals = 4 + 2 * c;
     f.c = c;
     f.p = slot;
-    f.stride = h->M + 1;
+    f.stride = h->nslots;
     f.dscal = h->dscal;
     f.gram = h->gram;
     for (int j = 0; j < c; j++) f.slot[j] = h->ring[j];
@@ -747,7 +774,7 @@ int push_pair(scvt_handle* h) {
   // resolve_push restores the history if it fails.
   h->ring_prev = h->ring;
   h->free_prev = h->free_slots;
-  h->free_slots.pop_back();
+  h->free_slots.erase(h->free_slots.begin() + slot_pos);
   h->ring.push_back(slot);
   if ((int)h->ring.size() > h->M) {
     h->free_slots.push_back(h->ring.front());
@@ -852,6 +879,11 @@ int quasi_newton_step(scvt_handle* h) {
     rc = evaluate(h, h->Zt, h->trial, true);
     h->n_evals++;
     if (rc < 0) return rc;
+    // Lloyd's step lowers the exact energy (section 2.2.1); if the evaluated
+    // energy rose beyond its rounding allowance (the quadrature of very
+    // large cells can do that), stop here: the generators stay where they
+    // are, with the history cleared
+    if (!(h->tF <= h->F + lloyd_allowance(h) * fabs(h->F))) return SCVT_E_LINESEARCH;
     alpha = 1.0;
     h->n_lloyd_fallback++;
   }
@@ -914,14 +946,15 @@ int alloc_device_state(scvt_handle* h) {
   if (rc) return rc;
   rc = alloc_set(h, h->trial);
   if (rc) return rc;
+  h->nslots = M > 0 ? M + 2 : 0;
   if (M > 0) {
-    ALLOC(h->S, (size_t)(M + 1) * 3 * n);
-    ALLOC(h->Y, (size_t)(M + 1) * 3 * n);
+    ALLOC(h->S, (size_t)h->nslots * 3 * n);
+    ALLOC(h->Y, (size_t)h->nslots * 3 * n);
   }
   ALLOC(h->dscal, kNScal);
   h->ctr = reinterpret_cast<Counters*>(h->dscal + kCtr);
   ALLOC(h->partials, kPartTotal * reduce_grid_max());
-  ALLOC(h->gram, (size_t)(M + 1) * (M + 1));
+  ALLOC(h->gram, (size_t)h->nslots * h->nslots);
   if (h->cfg.method == SCVT_METHOD_LBFGS) ALLOC(h->hgam, n);
   ALLOC(h->hpart, hist_grid_max());
   ALLOC(h->fb_list, n);
@@ -974,7 +1007,7 @@ int init_device_state(scvt_handle* h) {
   HIPCK(launch_fill_i32((int32_t*)h->q, 0, 6 * n, st));
   HIPCK(launch_poly_table(h->rho, const_cast<RhoPoly*>(h->rho.poly_tab),
                           const_cast<RhoPoly*>(h->rho.polyx_tab), st));
-  for (int s = M; s >= 0 && M > 0; s--) h->free_slots.push_back(s);
+  for (int s = h->nslots - 1; s >= 0; s--) h->free_slots.push_back(s);
   h->main_path = n > 256 ? 1 : 0;
   h->r_default = 2.0 * sqrt(4.0 * 3.141592653589793 / (double)n);
   return SCVT_OK;

@@ -88,7 +88,7 @@ struct HistFinArgs {
   int c;
   int slot[kHmax];  // ring slots, oldest first
   int p;            // push: slot of the new pair
-  int stride;       // row stride of the s.y table (M + 1)
+  int stride;       // row stride of the s.y table (the handle's slot count)
   double* dscal;
   double* gram;     // s_j.y_k at [slot_j * stride + slot_k]
   double* dst[kHmax];

@@ -340,3 +340,47 @@ def test_lloyd_fallback_matches_oracle(scvt):
         O.step()
     assert info["n_lloyd_fallback"] == O.n_lloyd_fallback >= 1
     assert np.max(np.abs(S.generators() - O.Z)) < 1e-10
+
+
+def test_curvature_rejection_with_full_history_in_solve(scvt):
+    """scvt_solve decides a pushed pair's curvature test one iteration late
+    and launches the next trial's push before it; with M = 2 and
+    curv_eps = 0.2 the oracle's trajectory accepts four pairs (the ring is
+    full from the second) and rejects every pair from the fifth iteration on
+    (cos(y, s) 0.18 and below, far from the threshold).  Each rejection must
+    restore the history with its vectors intact: the trajectory, the
+    evaluation count and the history length match the oracle's."""
+    n = 2000
+    d = I.density_tanh(I.latlon(30, 90), math.pi / 6, 0.2, 8)
+    Z0 = I.uniform_sphere(n, 17)
+    S = scvt.Solver(Z0, d, m_hist=2, curv_eps=0.2)
+    O = oracle.Solver(S.generators(), d, m_hist=2, curv_eps=0.2)
+    info = S.solve(12, 0.0)
+    for _ in range(12):
+        O.step()
+    assert info["iter"] == O.iter == 12
+    assert info["n_evals"] == O.n_evals
+    assert info["hist_len"] == len(O.hist) == 2
+    assert np.max(np.abs(S.generators() - O.Z)) < 1e-10
+    assert abs(info["F"] - O.cur.F) <= 1e-10 * O.cur.F
+
+
+def test_linesearch_error_when_lloyd_step_raises_energy(scvt):
+    """The case of the oracle's pin: eight generators, X64, 4-point rule
+    without subdivision.  No trial of the line search decreases the
+    evaluated F and the Lloyd step raises it by a third: scvt_step returns
+    SCVT_E_LINESEARCH after 1 + 10 + 1 evaluations, as the oracle raises,
+    and the generators and F stay where they were."""
+    d = I.density_x64()
+    Z0 = I.uniform_sphere(8, 205)
+    S = scvt.Solver(Z0, d, m_hist=7, quad_levels=0, quad_rule=4)
+    Z, F = S.generators(), S.energy()[0]
+    O = oracle.Solver(Z, d, m_hist=7, levels=0, rule=4)
+    assert abs(F - O.cur.F) <= 1e-12 * F
+    with pytest.raises(oracle.LineSearchError):
+        O.step()
+    with pytest.raises(scvt.ScvtError) as e:
+        S.step()
+    assert e.value.code == -5
+    assert np.array_equal(S.generators(), Z) and S.energy()[0] == F
+    assert S.info.n_evals == O.n_evals == 12 and S.info.iter == 0

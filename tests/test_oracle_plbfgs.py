@@ -224,3 +224,23 @@ def test_solve_rel_stopping_tests():
     assert S.iter == 3
     S = oracle.Solver(Z, d, method="lloyd")
     assert S.solve_rel(50, step_tol=1.0) and S.iter == 0
+
+
+def test_lloyd_fallback_that_raises_energy_is_an_error():
+    """Lloyd's step lowers the exact energy (section 2.2.1), not necessarily
+    a coarse quadrature of it: eight generators under the X64 density with
+    the 4-point rule and no subdivision (cells a quarter of the sphere wide)
+    find no decrease along the first direction in ten evaluations, and the
+    Lloyd step raises the evaluated F by a third.  The iteration ends with
+    LineSearchError, the generators and F where they were."""
+    d = I.density_x64()
+    O = oracle.Solver(I.uniform_sphere(8, 205), d, m_hist=7, levels=0, rule=4)
+    Z, F = O.Z.copy(), O.cur.F
+    with pytest.raises(oracle.LineSearchError):
+        O.step()
+    assert np.array_equal(O.Z, Z) and O.cur.F == F and O.iter == 0
+    assert O.n_evals == 1 + 10 + 1 and O.hist == []
+    # the same start with the default rule (7 points, 2 levels) descends
+    P = oracle.Solver(I.uniform_sphere(8, 205), d, m_hist=7)
+    P.step()
+    assert P.cur.F < P.history_F[0]
