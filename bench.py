@@ -8,9 +8,12 @@ density with 16x spacing ratio (x_c at lat 30 lon 90, beta = pi/9,
 alpha = 0.15), M = 10.  Generators start resident in HBM; the timed region is
 K iterations from the seeded start, bracketed by device synchronisation.
 
-Prints one JSON line.  Options: --steps K (default 200, the workload's
-iteration count), --warmup W, --precision fp64|mixed|both (default both:
-`value` is the FP64 path, the "mixed" object the mixed-precision path),
+Prints one JSON line.  Options: --config C1|C2|C3|C5 (default C3, the
+workload above; C1 n=2,562 rho=1 to 1e-10, C2 n=163,842 8x tanh to 1e-8,
+C5 n=4,194,304 two-centre density, 100 iterations), --steps K (iteration cap,
+default the workload's: 200 for C3), --warmup W, --precision fp64|mixed|both
+(default both: `value` is the FP64 path, the "mixed" object the
+mixed-precision path),
 --no-cpu-baseline, --copy-calibration (only run a plain 256 MiB device copy,
 used to scale the profiler's FETCH_SIZE / WRITE_SIZE counters).
 """
@@ -112,7 +115,7 @@ def valu_rates():
     return out
 
 
-def run_gpu(args, precision, Z0_dev, cfg, stream):
+def run_gpu(args, precision, Z0_dev, cfg, stream, max_iter, tol):
     import torch
 
     from paper_1709_06924_amd import scvt
@@ -127,16 +130,18 @@ def run_gpu(args, precision, Z0_dev, cfg, stream):
     S.set_timing(True, quad_only=True)  # two events per evaluation, around k_quad
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    info = S.solve(args.steps, 0.0)  # exactly `steps` iterations (no step is below 0)
+    # max_iter iterations, or fewer when the Lloyd step falls below tol (tol 0:
+    # exactly max_iter)
+    info = S.solve(max_iter, tol)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    out = {"elapsed_s": t1 - t0, "info": info, "F0": F0}
+    out = {"elapsed_s": t1 - t0, "info": info, "F0": F0, "iters": info["iter"]}
     ms, cnt = S.kernel_time(scvt.KERNEL_QUAD)
     out["quad"] = {"total_ms": ms, "launches": cnt}
     # the other kernels' times: every timer on, over the next iterations
     # (outside the timed region)
     S.set_timing(True)
-    S.solve(args.steps + args.breakdown_steps, 0.0)
+    S.solve(info["iter"] + args.breakdown_steps, 0.0)
     for name, k in (("geom", scvt.KERNEL_CELLS), ("fallback", scvt.KERNEL_FALLBACK),
                     ("grid", scvt.KERNEL_GRID), ("lbfgs", scvt.KERNEL_LBFGS),
                     ("eval", scvt.KERNEL_EVAL), ("wide", scvt.KERNEL_CELLS_WIDE)):
@@ -177,24 +182,103 @@ def mixed_errors(cfg, Z0_dev, stream, checkpoints=(0, 50, 100, 200)):
     return out
 
 
-def cpu_baseline(cfg, Z0):
+def host_description():
+    """nproc and the CPU model of the machine the oracle runs on."""
+    import subprocess
+    model = ""
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline(cfg, Z0, iters):
+    """The oracle as it stands, on the host: `iters` P-LBFGS iterations from
+    the workload's start on all its threads; then the same evaluation's cell
+    integrals re-timed on one thread over a sample of cells and scaled to the
+    whole set (the hull and the vector algebra run on one thread anyway)."""
     import oracle
     from oracle import _clib
+    L = _clib.lib()
+    threads = int(L.oracle_num_threads())
     S = oracle.Solver(Z0, cfg["density"], m_hist=cfg["m_hist"])  # initial evaluation, untimed
+    cells = S.cur.cells
     t0 = time.perf_counter()
-    S.step()
+    for _ in range(iters):
+        S.step()
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "iterations/s", "cores": int(_clib.lib().oracle_num_threads()),
+    evals = S.n_evals - 1
+    n = len(Z0)
+    t0 = time.perf_counter()
+    oracle.cell_integrals(cells, cfg["density"])
+    t_all = time.perf_counter() - t0
+    sample = min(n, 131072)
+    sub = type(cells).__new__(type(cells))
+    sub.Z = cells.Z[:sample]
+    sub.ptr = cells.ptr[:sample + 1]
+    sub.verts = cells.verts
+    L.oracle_set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.cell_integrals(sub, cfg["density"])
+        t_one = (time.perf_counter() - t0) * n / sample
+    finally:
+        L.oracle_set_num_threads(threads)
+    dt1 = dt + evals * (t_one - t_all)
+    return {"value": iters / dt, "unit": "iterations/s", "cores": threads, "kind": "oracle",
+            "sample": "%d FP64 oracle P-LBFGS iteration(s) (Qhull hull, C cell integrals on %d "
+                      "threads, numpy two-loop) at n=%d from the seeded start; %d evaluation(s), "
+                      "%.1f s" % (iters, threads, n, evals, dt),
+            "single_thread": {"value": iters / dt1, "unit": "iterations/s", "cores": 1,
+                              "sample": "the same iterations with their cell integrals re-timed "
+                                        "on one thread over %d cells (%.2f s per evaluation "
+                                        "against %.2f s on %d threads)"
+                                        % (sample, t_one, t_all, threads)},
+            "host": host_description()}
+
+
+def cpu_baseline_sampled(cfg, Z0, every=16):
+    """For sizes whose global hull is too slow to time within a benchmark
+    run: one oracle evaluation (hull, cells, integrals on all threads) of
+    every `every`-th generator of the seeded start -- a uniform random set
+    of n/every points under the same density, so the same structure --
+    scaled by `every` to n cells."""
+    import oracle
+    from oracle import _clib
+    n = len(Z0)
+    Zs = Z0[::every].copy()
+    t0 = time.perf_counter()
+    oracle.evaluate(Zs, cfg["density"])
+    dt = (time.perf_counter() - t0) * n / len(Zs)
+    return {"value": 1.0 / dt, "unit": "evaluations/s", "cores": int(_clib.lib().oracle_num_threads()),
             "kind": "oracle",
-            "sample": "one FP64 oracle P-LBFGS iteration (Qhull hull, C cell integrals, numpy "
-                      "two-loop) at n=1,048,576 from the seeded start; %d evaluation(s), %.1f s"
-                      % (S.n_evals - 1, dt)}
+            "sample": "one FP64 oracle evaluation (Qhull hull, C cell integrals) of every %dth "
+                      "generator of the seeded start (%d points), scaled to %d: %.1f s per "
+                      "evaluation" % (every, len(Zs), n, dt),
+            "host": host_description()}
+
+
+WORKLOADS = {
+    "C1": "n=2562 uniform start (seed 1), rho = 1, M=7, 100 iterations or max |l| < 1e-10",
+    "C2": "n=163842 uniform start (seed 2), tanh density 8x (lat 30 lon 90, beta pi/6, "
+          "alpha 0.2), M=7, solved to max |l| < 1e-8 (cap 20000)",
+    "C3": "n=1048576 uniform start (seed 3), tanh density 16x (lat 30 lon 90, beta pi/9, "
+          "alpha 0.15), M=10, 200 iterations",
+    "C5": "n=4194304 uniform start (seed 5), two-centre tanh density (lat +-45 lon 0, 16x and "
+          "8x), M=10, 100 iterations",
+}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--config", default="C3", choices=sorted(WORKLOADS),
+                    help="workload (default C3, the 1M-generator benchmark)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="iteration cap (default: the workload's, 200 for C3)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -202,7 +286,7 @@ def main():
     ap.add_argument("--valu-rates", action="store_true",
                     help="only measure vector-ALU instruction rates (libscvt_calib.so)")
     ap.add_argument("--no-mixed-errors", action="store_true",
-                    help="skip the mixed-vs-FP64 evaluation errors at iterations 0/50/100/200")
+                    help="skip the mixed-vs-FP64 evaluation errors at the FP64 iterates")
     ap.add_argument("--source-hash", action="store_true",
                     help="print the hash of the quadrature kernel's sources and exit")
     ap.add_argument("--breakdown-steps", type=int, default=20,
@@ -235,36 +319,42 @@ def main():
     import torch
 
     import paper_1709_06924_amd.inputs as I
-    cfg = I.CONFIGS["C3"]
+    cfg = I.CONFIGS[args.config]
     n = cfg["n"]
+    max_iter = args.steps if args.steps is not None else cfg["max_iter"]
+    tol = cfg["tol"]
     Z0 = I.uniform_sphere(n, cfg["seed"])
     torch.cuda.set_device(0)
     Z0_dev = torch.from_numpy(Z0).to("cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
-    print("bench: n=%d steps=%d warmup=%d" % (n, args.steps, args.warmup), file=sys.stderr,
-          flush=True)
+    print("bench: %s n=%d max_iter=%d tol=%g warmup=%d" % (args.config, n, max_iter, tol, args.warmup),
+          file=sys.stderr, flush=True)
 
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    if args.config in ("C1", "C2") and args.precision == "both":
+        precisions = ["fp64"]  # FP64 workloads
     runs = {}
     for p in precisions:
-        runs[p] = run_gpu(args, p, Z0_dev, cfg, stream)
+        runs[p] = run_gpu(args, p, Z0_dev, cfg, stream, max_iter, tol)
         r = runs[p]
-        print("bench: %s %.3f it/s (%d evals)" % (p, args.steps / r["elapsed_s"], r["info"]["n_evals"]),
+        print("bench: %s %.3f it/s (%d iterations, %d evals)"
+              % (p, r["iters"] / r["elapsed_s"], r["iters"], r["info"]["n_evals"]),
               file=sys.stderr, flush=True)
 
     main_p = precisions[0]
     r = runs[main_p]
-    value = args.steps / r["elapsed_s"]
+    value = r["iters"] / r["elapsed_s"]
     quad = r["quad"]
     avg_ms = quad["total_ms"] / max(quad["launches"], 1)
     flops = cell_flops(r["mean_degree"]) * n
     achieved = flops / (avg_ms * 1e-3) / 1e12
+    traffic = recorded_traffic() if args.config == "C3" and main_p == "fp64" else None
     line = {
         "metric": METRIC,
         "value": value,
         "unit": "iterations/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": r["iters"],
         "warmup": args.warmup,
         "ms_per_step": 1000.0 / value,
         "higher_is_better": True,
@@ -272,10 +362,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_p == "fp64" else "f32-quadrature/f64-geometry",
         "data": "synthetic",
-        "config": {"workload": "n=1048576 uniform start (seed 3), tanh density 16x "
-                               "(lat 30 lon 90, beta pi/9, alpha 0.15), M=10, %s" % main_p,
+        "config": {"workload": "%s: %s, %s" % (args.config, WORKLOADS[args.config], main_p),
                    "n": n, "m_hist": cfg["m_hist"], "quad": "7-point, 2 levels",
-                   "evals": r["info"]["n_evals"] - 1, "F_start": r["F0"],
+                   "iterations": r["iters"], "converged": bool(r["info"].get("converged")),
+                   "tol": tol, "evals": r["info"]["n_evals"] - 1, "F_start": r["F0"],
                    "F_end": r["info"]["F"], "step_inf_end": r["info"]["step_inf"]},
         "kernels_ms_per_eval": {k: r[k]["total_ms"] / max(r[k]["launches"], 1)
                                 for k in ("geom", "wide", "fallback", "quad", "grid", "eval")},
@@ -283,17 +373,19 @@ def main():
         "kernels_timed": "quad: HIP events around k_quad over the timed iterations; the others: "
                          "every timer on over the %d iterations after them" % args.breakdown_steps,
         "roofline": {"kernel": "k_quad", "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": recorded_traffic(),
-                     "flops_per_launch": flops, "avg_launch_ms": avg_ms,
+                     "peak": PEAK_FP64_VECTOR_TFLOPS if main_p == "fp64" else PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": achieved / (PEAK_FP64_VECTOR_TFLOPS if main_p == "fp64"
+                                         else PEAK_FP32_VECTOR_TFLOPS),
+                     "traffic": traffic, "flops_per_launch": flops, "avg_launch_ms": avg_ms,
                      "mean_degree": r["mean_degree"]},
     }
     for p in precisions[1:]:
         rr = runs[p]
         qms = rr["quad"]["total_ms"] / max(rr["quad"]["launches"], 1)
         qfl = cell_flops(rr["mean_degree"]) * n
-        line[p] = {"value": args.steps / rr["elapsed_s"], "unit": "iterations/s",
-                   "ms_per_step": 1000.0 * rr["elapsed_s"] / args.steps,
+        line[p] = {"value": rr["iters"] / rr["elapsed_s"], "unit": "iterations/s",
+                   "ms_per_step": 1000.0 * rr["elapsed_s"] / rr["iters"],
                    "dtype": "f32 quadrature points, f64 geometry/accumulation/LBFGS",
                    "kernels_ms_per_eval": {k: rr[k]["total_ms"] / max(rr[k]["launches"], 1)
                                            for k in ("geom", "wide", "fallback", "quad", "grid", "eval")},
@@ -306,8 +398,9 @@ def main():
     if "mixed" in line and not args.no_mixed_errors:
         print("bench: mixed-vs-FP64 evaluation errors at the FP64 iterates", file=sys.stderr,
               flush=True)
-        line["mixed"]["errors_vs_fp64"] = mixed_errors(cfg, Z0_dev, stream)
-    if args.serving_requests > 0:
+        cps = tuple(k for k in (0, 50, 100, 200) if k <= max_iter)
+        line["mixed"]["errors_vs_fp64"] = mixed_errors(cfg, Z0_dev, stream, cps)
+    if args.serving_requests > 0 and args.config == "C3":
         from paper_1709_06924_amd import serving
         stream = I.serving_stream(seed=4, rate=args.serving_rate, count=args.serving_requests)
         print("bench: serving %d requests at %.0f req/s" % (len(stream), args.serving_rate),
@@ -323,9 +416,12 @@ def main():
                      "max_slots": args.serving_slots, "hbm_budget_bytes": 64 << 30})
         line["serving"] = summ
     if not args.no_cpu_baseline:
-        print("bench: timing the oracle on the host (one iteration at n=%d)" % n,
-              file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(cfg, Z0)
+        print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
+        if args.config == "C5":
+            line["cpu_baseline"] = cpu_baseline_sampled(cfg, Z0)
+        else:
+            iters = {"C1": 20, "C2": 2, "C3": 1}[args.config]
+            line["cpu_baseline"] = cpu_baseline(cfg, Z0, iters)
     print(json.dumps(line), flush=True)
 
 

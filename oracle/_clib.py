@@ -81,6 +81,8 @@ def lib():
                                             ctypes.POINTER(CRule), dp, dp, dp]
         L.oracle_cell_integrals.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 

@@ -286,6 +286,17 @@ void oracle_rho_many(const oracle_density *D, int64_t npts, const double *Y, dou
   for (int64_t k = 0; k < npts; k++) out[k] = oracle_rho(D, Y + 3 * k);
 }
 
+/* Threads the integrals use from now on (the benchmark's single-thread
+ * baseline); values below 1 are ignored. */
+void oracle_set_num_threads(int t) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (t >= 1) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
+
 /* Number of OpenMP threads the integrals use (reported by the benchmark). */
 int oracle_num_threads(void) {
   int t = 1;

@@ -179,8 +179,10 @@ SCVT_HD Pred det_cached(const CrossCache& k, V3 l) {
 // increasing index order so that every cell that meets at the vertex gets the
 // same bits: normalize((p_b - p_a) x (p_c - p_a)), signed so that v . p_a > 0.
 // The cross product is evaluated without fused multiply-adds (one rounding
-// per operation, as the plain formula); the normalisation multiplies by the
-// refined reciprocal square root (within about one ulp of the division).
+// per operation, as the plain formula), and the normalisation is the IEEE
+// square root of ((w_x^2 + w_y^2) + w_z^2) and three IEEE divisions: the
+// vertex is the correctly rounded value of that expression, as anywhere else
+// it is evaluated in this order.
 SCVT_HD V3 circumcentre(int ia, V3 pa, int ib, V3 pb, int ic, V3 pc) {
 #pragma clang fp contract(off)
   if (ia > ib) {
@@ -200,10 +202,10 @@ SCVT_HD V3 circumcentre(int ia, V3 pa, int ib, V3 pb, int ic, V3 pc) {
   double wx = uy * vz - uz * vy;
   double wy = uz * vx - ux * vz;
   double wz = ux * vy - uy * vx;
-  const double ri = rsq_pos(wx * wx + wy * wy + wz * wz);
-  wx = wx * ri;
-  wy = wy * ri;
-  wz = wz * ri;
+  const double r = sqrt(wx * wx + wy * wy + wz * wz);
+  wx = wx / r;
+  wy = wy / r;
+  wz = wz / r;
   if (wx * pa.x + wy * pa.y + wz * pa.z < 0.0) {
     wx = -wx;
     wy = -wy;

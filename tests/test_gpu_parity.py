@@ -2,11 +2,11 @@
 
 Tolerance (FP64 path): 1e-12 relative on m, mu, e, F, g, h, Lloyd step and
 the search direction q; neighbour sets bit-exact away from edges flagged
-near-degenerate by either side.  A cell's second moment e also moves by
-about 4 dv / R relative when its vertices move by dv (R its circumradius),
-and the two sides round each Voronoi vertex's normalisation independently
-(dv up to two ulps): e is compared at 1e-12 + 16 eps / R, which matters only
-for the smallest cells (R ~ 2e-3 gives 1.8e-12).
+near-degenerate by either side.  Both sides evaluate every Voronoi vertex as
+the correctly rounded normalize((z_b - z_a) x (z_c - z_a)) of the sorted
+triple, so the cells' vertices agree to the bit; the generators compared are
+the library's own renormalised rows (a one-ulp change of a generator moves a
+few ill-conditioned cells by ~4e-12).
 """
 import math
 from collections import defaultdict
@@ -48,13 +48,10 @@ def compare_eval(S, ev, n, check_cells=True):
     rel = np.abs(m - ev.m) / ev.m
     k = int(np.argmax(rel))
     assert rel[k] <= RTOL, (k, rel[k], ev.cells.deg()[k])
-    R = np.zeros(len(ev.e))
-    np.maximum.at(R, np.repeat(np.arange(len(ev.e)), ev.cells.deg()),
-                  np.linalg.norm(ev.cells.verts - np.repeat(ev.Z, ev.cells.deg(), axis=0), axis=1))
-    etol = RTOL + 16 * np.finfo(np.float64).eps / R
     erel = np.abs(e - ev.e) / ev.e
-    k = int(np.argmax(erel / etol))
-    assert erel[k] <= etol[k], (k, erel[k], etol[k], R[k])
+    k = int(np.argmax(erel))
+    print("worst relative differences: m %.2e, e %.2e" % (rel.max(), erel[k]))
+    assert erel[k] <= RTOL, (k, erel[k], ev.cells.deg()[k])
     scale = np.linalg.norm(ev.mu, axis=1)
     assert np.max(np.linalg.norm(mu - ev.mu, axis=1) / scale) <= RTOL
     assert np.max(np.linalg.norm(cen - ev.centroid, axis=1)) <= 1e-12
