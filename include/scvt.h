@@ -227,6 +227,19 @@ int scvt_refine(scvt_handle* h, double* z_out, int on_device, int64_t* n_out);
 int scvt_multilevel(const scvt_config* cfg0, const double* z0, int z0_on_device, int levels,
                     int64_t max_iter, double tol, scvt_info* infos, scvt_handle** out);
 
+/* scvt_refine for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same result, written to the device buffer z_out (n_out x 3; NULL to query
+ * *n_out only), with no hipMalloc or hipFree.  Its temporary buffers live in
+ * one static device array per GPU (96 MiB, held by every GPU the library
+ * runs on until the process ends), enough for SCVT_REFINE_NOALLOC_MAX_N
+ * generators (the paper's largest bisection input, section 4.3); larger
+ * handles return SCVT_E_OOM.  Calls on one GPU share the array: calls that
+ * overlap in time on one GPU race (serialise them); nothing in it has to
+ * start cleared.  Uses the handle's own buffers and stream otherwise. */
+#define SCVT_REFINE_NOALLOC_MAX_N 655362
+int scvt_refine_noalloc(scvt_handle* h, double* z_out, int64_t* n_out);
+
 /* Mesh export and quality (sections 3.3 and 4) at the current generators:
  * the Delaunay triangles, each once as (i, j, k) with i its smallest index,
  * counter-clockwise seen from outside, ordered by i then j (2n - 4 of them

@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -1249,6 +1250,100 @@ int scvt_refine(scvt_handle* h, double* z_out, int on_device, int64_t* n_out) {
   HIPCK(launch_refine_emit(h->Z, h->trial.deg, nbr, off, n, dst, st));
   if (!on_device)
     HIPCK(hipMemcpyAsync(z_out, dst, 3 * m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  return SCVT_OK;
+}
+
+}  // extern "C"
+
+// ---- refinement without allocation ----------------------------------------
+// scvt_refine's temporary buffers (neighbour lists, per-cell edge counts and
+// their scan) live in one static device array per GPU, sized for
+// SCVT_REFINE_NOALLOC_MAX_N generators.  Host code never passes the array's
+// name to a kernel or a copy: it stands for a device symbol, whose address
+// on each device comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[(size_t)96 << 20];
+
+namespace {
+
+struct NoAllocLayout {
+  size_t nbr, cnt, off, junk, tmp, bytes;  // byte offsets, total
+};
+
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+NoAllocLayout noalloc_layout(int64_t n) {
+  NoAllocLayout L{};
+  size_t o = 0;
+  L.nbr = o;
+  o += align256((size_t)n * kVmax * sizeof(int32_t));
+  L.cnt = o;
+  o += align256((size_t)n * sizeof(int32_t));
+  L.off = o;
+  o += align256((size_t)(n + 1) * sizeof(int32_t));
+  L.junk = o;
+  o += align256((size_t)(n + 1) * sizeof(int32_t));
+  L.tmp = o;
+  o += align256((size_t)scan_tmp_ints(n) * sizeof(int32_t));
+  L.bytes = o;
+  return L;
+}
+
+constexpr size_t kNoAllocScratchBytes = sizeof(scratch);
+constexpr int kNoAllocMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// the current device's copy of the scratch array (looked up once per device)
+int scratch_ptr(void** out) {
+  int dev = -1;
+  HIPCK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return SCVT_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SCVT_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SCVT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int scvt_refine_noalloc(scvt_handle* h, double* z_out, int64_t* n_out) {
+  if (!h || !n_out) return SCVT_E_INVALID;
+  const int64_t n = h->n;
+  if (n > SCVT_REFINE_NOALLOC_MAX_N) return SCVT_E_OOM;
+  const NoAllocLayout L = noalloc_layout(n);
+  if (L.bytes > kNoAllocScratchBytes) return SCVT_E_OOM;
+  void* base = nullptr;
+  int rc = scratch_ptr(&base);
+  if (rc) return rc;
+  unsigned char* b = (unsigned char*)base;
+  int32_t* nbr = (int32_t*)(b + L.nbr);
+  int32_t* cnt = (int32_t*)(b + L.cnt);
+  int32_t* off = (int32_t*)(b + L.off);
+  int32_t* junk = (int32_t*)(b + L.junk);
+  int32_t* tmp = (int32_t*)(b + L.tmp);
+  hipStream_t st = h->stream;
+  // every scratch word read below is written first in this call (neighbour
+  // lists and counts per cell, the scan's tiles), so nothing is cleared
+  rc = geometry_with_neighbours(h, h->Z, nbr);
+  if (rc) return rc;
+  HIPCK(launch_refine_count(h->trial.deg, nbr, n, cnt, st));
+  HIPCK(launch_scan_pair(cnt, cnt, n, tmp, off, junk, st));
+  int32_t* edges = (int32_t*)(h->pinned + kPinWords);  // the handle's pinned words
+  HIPCK(hipMemcpyAsync(edges, off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  const int64_t m = n + *edges;
+  *n_out = m;
+  if (!z_out) return SCVT_OK;
+  HIPCK(launch_refine_emit(h->Z, h->trial.deg, nbr, off, n, z_out, st));
   HIPCK(hipStreamSynchronize(st));
   return SCVT_OK;
 }

@@ -23,6 +23,7 @@ FP64, MIXED = 0, 1
 KIND = {"const": 0, "tanh": 1, "x3": 2, "x16": 3}
 KERNEL_CELLS, KERNEL_FALLBACK, KERNEL_GRID, KERNEL_LBFGS, KERNEL_EVAL, KERNEL_QUAD = 0, 1, 2, 3, 4, 5
 KERNEL_CELLS_WIDE = 6
+REFINE_NOALLOC_MAX_N = 655362  # scvt.h SCVT_REFINE_NOALLOC_MAX_N
 VMAX = 32
 
 
@@ -80,6 +81,7 @@ _sig = {
     "scvt_num_generators": (ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_int64)]),
     "scvt_refine": (ctypes.c_int, [_H, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     "scvt_mesh": (ctypes.c_int, [_H, _vp, ctypes.POINTER(ctypes.c_int64), _vp, _vp]),
+    "scvt_refine_noalloc": (ctypes.c_int, [_H, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "scvt_multilevel": (ctypes.c_int, [ctypes.POINTER(Config), _vp, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int64, ctypes.c_double, ctypes.POINTER(Info),
                                        ctypes.POINTER(_H)]),
