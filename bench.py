@@ -152,16 +152,27 @@ def run_gpu(args, precision, Z0_dev, cfg, stream, max_iter, tol):
     return out
 
 
+def mean_spacing(Z, nbr, deg):
+    """h_i: mean chord distance from z_i to its Voronoi neighbours."""
+    import numpy as np
+    n = len(Z)
+    rows = np.repeat(np.arange(n), deg)
+    cols = nbr[np.arange(nbr.shape[1])[None, :] < deg[:, None]]
+    dist = np.linalg.norm(Z[rows] - Z[cols], axis=1)
+    return np.bincount(rows, dist, n) / np.maximum(deg, 1)
+
+
 def mixed_errors(cfg, Z0_dev, stream, checkpoints=(0, 50, 100, 200)):
     """The mixed path's evaluation against the FP64 one at the FP64 iterates
     Z_0, Z_50, Z_100, Z_200 of the workload (both on the device): |dF|/F,
-    max |dm|/m and max |d centroid| / R_i (R_i the cell's circumradius)."""
+    max |dm|/m and max |d centroid| / h_i (h_i the mean distance to the
+    cell's neighbours; also / R_i, the cell's circumradius)."""
     import numpy as np
     import torch
 
     from paper_1709_06924_amd import scvt
     kw = dict(m_hist=cfg["m_hist"], stream=stream)
-    S = scvt.Solver(Z0_dev, cfg["density"], precision="fp64", **kw)
+    S = scvt.Solver(Z0_dev, cfg["density"], precision="fp64", keep_cells=True, **kw)
     out = []
     it = 0
     for k in checkpoints:
@@ -172,12 +183,17 @@ def mixed_errors(cfg, Z0_dev, stream, checkpoints=(0, 50, 100, 200)):
         S.generators(Z)
         F64, m64, c64, _ = S.energy()
         R = S.vector("R")
+        nbr, deg = S.neighbours()
+        h = mean_spacing(S.generators(), nbr, deg)
         M = scvt.Solver(Z, cfg["density"], precision="mixed", **kw)
         Fmx, mmx, cmx, _ = M.energy()
         M.close()
+        err = np.linalg.norm(cmx - c64, axis=1)
         out.append({"iteration": k, "dF_over_F": abs(Fmx - F64) / F64,
                     "max_dm_over_m": float(np.max(np.abs(mmx - m64) / m64)),
-                    "max_dcentroid_over_R": float(np.max(np.linalg.norm(cmx - c64, axis=1) / R))})
+                    "max_dcentroid_over_h": float(np.max(err / h)),
+                    "p99_dcentroid_over_h": float(np.percentile(err / h, 99)),
+                    "max_dcentroid_over_R": float(np.max(err / R))})
     S.close()
     return out
 

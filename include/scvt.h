@@ -120,7 +120,10 @@ typedef struct {
   int32_t quad_rule;    /* points of the triangle rule: 7 (Radon, degree 5; default), or the
                            conical product rules of the sizes section 4.1 uses: 4 (degree 3),
                            9 (degree 5) */
-  int32_t reserved;
+  int32_t k_max;        /* > 0: at most k_max candidates per cell in the certified passes
+                           (16, 32 and 64 otherwise); cells needing more go on to the next
+                           pass and finally to the sequential clipper, which builds the same
+                           cell (a test knob for the fallback path; 0 = default) */
   void* hip_stream;     /* hipStream_t to order work on, or NULL */
 } scvt_config;
 
@@ -142,20 +145,23 @@ typedef struct {
                            and that pass to the 64-lane one, last evaluation */
 } scvt_info;
 
-/* Fill *cfg with defaults for n generators: M = 7, FP64, rho = 1,
+/* Fill *cfg with defaults for n generators (section 4's settings: M = 7,
+ * ten energy evaluations per line search): FP64, rho = 1,
  * 2 subdivision levels, 10 evaluations per line search, c1 = 1e-4,
  * curv_eps = 1e-10, automatic ls_noise, no cell copy, NULL stream. */
 int scvt_config_init(scvt_config* cfg, int64_t n);
 
-/* Create a solver.  z0: n x 3 (host, or device if z0_on_device); rows are
- * normalised to the unit sphere.  Allocates all device state, builds the
+/* Create a solver for the problem of section 2.1 (generators on the unit
+ * sphere, density rho, CCVT energy).  z0: n x 3 (host, or device if
+ * z0_on_device); rows are normalised to the unit sphere.  Allocates all device state, builds the
  * cells of z0 and evaluates F, g, h and the Lloyd step (iteration 0 ready).
  * Errors: SCVT_E_INVALID (n < 4, bad config, non-finite z0), SCVT_E_OOM,
  * SCVT_E_DEGENERATE (zero row), SCVT_E_CERT, SCVT_E_NUMERIC, SCVT_E_HIP.
  * *out is NULL on error. */
 int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt_handle** out);
 
-/* One iteration of the configured method.  P-LBFGS and LBFGS: two-loop
+/* One iteration of the configured method (section 3.1 with the two-loop
+ * recursion of section 2.2.2).  P-LBFGS and LBFGS: two-loop
  * direction, descent check with reset to the history-free direction, Armijo
  * line search, history update; if the line search finds no sufficient
  * decrease in ls_max_evals evaluations, the history is cleared and the Lloyd
@@ -164,7 +170,8 @@ int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt
  * evaluation.  info may be NULL. */
 int scvt_step(scvt_handle* h, scvt_info* info);
 
-/* Iterate until step_inf < tol_step_inf or max_iter iterations in total.
+/* Iterate until step_inf < tol_step_inf or max_iter iterations in total
+ * (the stopping test on the generators' movement, section 3.3).
  * Returns SCVT_OK when converged, SCVT_NOT_CONVERGED at the cap, or an error. */
 int scvt_solve(scvt_handle* h, int64_t max_iter, double tol_step_inf, scvt_info* info);
 
@@ -176,26 +183,31 @@ int scvt_solve(scvt_handle* h, int64_t max_iter, double tol_step_inf, scvt_info*
 int scvt_solve_rel(scvt_handle* h, int64_t max_iter, double step_tol, double grad_rel_tol,
                    double f_rel_tol, scvt_info* info);
 
-/* Cached results at the current generators (no recomputation): F, and
+/* Cached results at the current generators (no recomputation): the CCVT
+ * energy F and the mass centroids of section 2.1: F, and
  * optionally per cell mass (n), centroid mu_i/m_i (n x 3) and energy e_i (n).
  * Any output pointer may be NULL. */
 int scvt_energy(scvt_handle* h, double* F, double* mass, double* centroid, double* e_cell,
                 int out_on_device);
 
-/* Current generators, n x 3. */
+/* Current generators, n x 3 (the iterate z of section 3.1). */
 int scvt_get_generators(scvt_handle* h, double* z, int on_device);
 
-/* Per-generator vectors at the current generators (parity and debugging):
+/* Per-generator vectors at the current generators (section 3.1's gradient,
+ * preconditioner and Lloyd step; parity and debugging):
  * which = 0 gradient g (n x 3), 1 preconditioner h (n), 2 Lloyd step l
  * (n x 3), 3 first moment mu (n x 3), 4 the last search direction q (n x 3),
  * 5 cell circumradius (n). */
 int scvt_get_vectors(scvt_handle* h, int which, double* out, int on_device);
 
-/* Compute the P-LBFGS direction at the current state into out (n x 3),
+/* Compute the P-LBFGS direction (the two-loop recursion of section 2.2.2
+ * with the initial inverse Hessian of section 3.1) at the current state into
+ * out (n x 3),
  * without stepping; *gq receives g . q (may be NULL). */
 int scvt_direction(scvt_handle* h, double* out, int on_device, double* gq);
 
-/* Voronoi cells at the current generators (requires keep_cells = 1).
+/* Voronoi cells at the current generators (eq. viInS of section 2.1;
+ * requires keep_cells = 1).
  * max_deg must be 32.  nbr: n x 32 neighbour ids sorted ascending, -1 padded;
  * deg: n; verts: n x 32 x 6, edge k of cell i runs counter-clockwise (seen
  * from outside) from verts[i][k][0:3] to verts[i][k][3:6] on the bisector of
@@ -204,7 +216,7 @@ int scvt_direction(scvt_handle* h, double* out, int on_device, double* gq);
 int scvt_get_cells(scvt_handle* h, int32_t max_deg, int32_t* nbr, int32_t* deg, double* verts,
                    uint8_t* flags);
 
-/* Number of generators of a handle. */
+/* Number of generators of a handle (n of section 2.1). */
 int scvt_num_generators(scvt_handle* h, int64_t* n);
 
 /* Bisection step of the optimisation-bisection initialisation (section 3.3;
@@ -251,13 +263,16 @@ int scvt_refine_noalloc(scvt_handle* h, double* z_out, int64_t* n_out);
  * memory; the handle's state is unchanged. */
 int scvt_mesh(scvt_handle* h, int32_t* tri, int64_t* ntri, double* cell_q, double* tri_q);
 
-/* Checkpoint: serialise (Z, history ring, counters) into buf.  With buf ==
+/* Checkpoint of the iteration of section 3.1 (its state is the generators
+ * and the LBFGS pairs of section 2.2.2): serialise (Z, history ring,
+ * counters) into buf.  With buf ==
  * NULL, *bytes receives the size needed.  scvt_set_state restores a state
  * produced by a handle with the same n and M and re-evaluates at Z. */
 int scvt_get_state(scvt_handle* h, void* buf, size_t* bytes);
 int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes);
 
-/* Kernel timing (HIP events on the handle's stream, enabled by
+/* Kernel timing of the iteration's steps (section 3.1's evaluation and
+ * direction; HIP events on the handle's stream, enabled by
  * scvt_set_timing: 0 off, 1 every timer below, 2 only the quadrature
  * kernel's, two events per evaluation): kernel 0 = certified cell geometry
  * kernel, 1 = fallback
@@ -268,26 +283,39 @@ int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes);
 int scvt_set_timing(scvt_handle* h, int enable);
 int scvt_kernel_time(scvt_handle* h, int kernel, double* total_ms, int64_t* launches);
 
+/* Release a handle and all its device state (NULL is ignored). */
 void scvt_destroy(scvt_handle* h);
+/* Text of a status code (the SCVT_* values above). */
 const char* scvt_strerror(int code);
 
-/* Device memory a handle with this configuration allocates (bytes). */
+/* Device memory a handle with this configuration allocates (bytes): the
+ * generators, cells and LBFGS history of section 3.1 for n and M. */
 int scvt_footprint(const scvt_config* cfg, size_t* bytes);
 
 /* ------------------------------------------------------------- serving --
- * A persistent request loop (north of the per-iteration path): requests of
- * any size and density are submitted while others run.  A request is
- * admitted when one of max_slots slots is free and its footprint
- * (scvt_footprint) fits in what hbm_budget has left, first come first
- * served; it then runs on its own HIP stream with its generators, cells and
- * LBFGS history resident in HBM, concurrently with the other admitted
- * requests, until step_inf < tol or max_iter iterations.  Results do not
- * depend on the other requests (all kernels are deterministic).
- * The server uses the device current at creation.  Submit copies z0 (host,
- * n x 3); cfg->hip_stream is ignored.  Errors: SCVT_E_INVALID,
- * SCVT_E_OOM (footprint above the whole budget). */
+ * Continuous batching of solves (north of the per-iteration path of
+ * section 3.1; the paper has no serving): requests of any size and tanh or
+ * other density are submitted at any time.  A request is admitted when one
+ * of max_slots slots is free and its footprint (scvt_footprint) fits in a
+ * free range of the server's device arena of hbm_budget bytes, first come
+ * first served; its generators, cells and LBFGS history then live in that
+ * range until it finishes.  One driver thread runs rounds on `stream`: every
+ * admitted request's next evaluation (with its direction passes and trial
+ * point) is issued as one segmented launch per kernel over all of them,
+ * followed by one gather of their scalars and one synchronisation; each
+ * request then takes its own line-search and history decisions (those of
+ * scvt_solve), until step_inf < tol or max_iter iterations.  Requests join
+ * and leave at round boundaries.  A request's result does not depend on the
+ * other requests (every kernel computes a request's cells and reductions as
+ * its own launch would).
+ * Served: P-LBFGS with m_hist <= 16 (other methods: SCVT_E_INVALID).  All
+ * device and pinned memory is allocated by scvt_server_create; nothing is
+ * allocated per request.  The server uses the device current at creation;
+ * stream NULL: its own.  Submit copies z0 (host, n x 3); cfg->hip_stream is
+ * ignored.  Errors: SCVT_E_INVALID, SCVT_E_OOM (footprint above the whole
+ * budget, or the budget cannot be allocated). */
 typedef struct scvt_server scvt_server;
-int scvt_server_create(size_t hbm_budget, int max_slots, scvt_server** out);
+int scvt_server_create(size_t hbm_budget, int max_slots, void* stream, scvt_server** out);
 int scvt_server_submit(scvt_server* s, const scvt_config* cfg, const double* z0, double tol,
                        int64_t max_iter, int64_t* req_id);
 /* SCVT_PENDING while waiting or running; otherwise the request's final

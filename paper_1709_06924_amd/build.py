@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libscvt.so")
 CALIB_LIB = os.path.join(HERE, "libscvt_calib.so")  # measurement only (bench.py --valu-rates)
-SOURCES = ["grid.hip", "cells.hip", "lbfgs.hip", "mesh.hip", "engine.cpp", "serve.cpp"]
+SOURCES = ["grid.hip", "cells.hip", "lbfgs.hip", "mesh.hip", "round.hip", "engine.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
           "-Xclang", "-packed-fp32-ops", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,

@@ -790,15 +790,13 @@ SCVT_HD void quad_tri(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc, int 
 
 // ------------------------------------------------ mixed-precision quadrature
 // The same rule with the point arithmetic in FP32, in a frame local to the
-// generator z: every quantity is a small offset from z, so FP32 keeps its
-// relative precision on the cell scale h instead of on the unit sphere.
-//   d  = p - z = sum_q lambda_q (X_q - z)      (vertex offsets formed in FP64)
-//   s  = |p|^2 - 1 = 2 z.d + |d|^2,  r = (1 + s)^(-1/2),  Jacobian r^3
-//   y - z = r d + (r - 1) z,  r - 1 = -s r^2 / (1 + r)   (no cancellation)
-//   rho at y from (z - x_c) + (y - z), with (z - x_c) formed in FP64.
-// Each sub-triangle's 7-point sums are added to FP64 accumulators (the
-// compensation for the FP32 point values); the first moment is accumulated
-// as int rho (y - z) and mu = m z + int rho (y - z) is formed in FP64.
+// generator z: every per-point quantity is a small offset from z (or from
+// the cell's own value of the density's argument), so FP32 keeps its
+// relative precision on the cell scale h instead of on the unit sphere.  The
+// subdivision grid, each leaf's Jacobian determinant and the accumulation
+// stay FP64; each leaf's 7-point sums are formed in FP32 and scaled into the
+// FP64 accumulators (quad_leaf_mixed).  The first moment is accumulated as
+// int rho (y - z), and mu = m z + int rho (y - z) is formed in FP64.
 struct F3 {
   float x, y, z;
 };
@@ -843,24 +841,6 @@ SCVT_HD float rm1_series(float s) {
   constexpr float c1 = -0.5f, c2 = 0.375f, c3 = -0.3125f, c4 = 0.2734375f, c5 = -0.24609375f,
                   c6 = 0.2255859375f;
   return s * fmaf(s, fmaf(s, fmaf(s, fmaf(s, fmaf(s, c6, c5), c4), c3), c2), c1);
-}
-
-// Midpoint of the arc between the unit vectors z + dP and z + dQ, as an
-// offset from z in FP32: with D = dP + dQ, |P + Q|^2 = 4 - |dP - dQ|^2 =
-// 4 (1 + s), and the midpoint is z + D/2 + r1 (z + D/2), r1 = (1 + s)^(-1/2)
-// - 1 (series for small s, else the hardware rsqrt with the cancellation-
-// free form -s r^2 / (1 + r)).
-SCVT_HD F3 arc_midpoint_local(F3 dP, F3 dQ, F3 zf) {
-  const F3 h = 0.5f * (dP + dQ), dd = dP - dQ;
-  const float s = -0.25f * dotf(dd, dd);
-  float r1;
-  if (s >= -0x1p-5f) {
-    r1 = rm1_series(s);
-  } else {
-    const float r = rsqf(1.0f + s);
-    r1 = -s * r * r * rcpf(1.0f + r);
-  }
-  return F3{fmaf(r1, zf.x + h.x, h.x), fmaf(r1, zf.y + h.y, h.y), fmaf(r1, zf.z + h.z, h.z)};
 }
 
 struct DensityF {  // FP32 density parameters
@@ -928,45 +908,182 @@ SCVT_HD float rho_kind_f(const DensityF& D, const F3* zc, F3 zf, F3 dyz, const D
   return bumpf(D.amp[0], D.beta[0], D.k2l[0], d) + D.gamma;
 }
 
-// sub-triangle with vertex offsets dA, dB, dC from z; accumulates m,
-// int rho (y - z) (in mx, my, mz) and e into the FP64 accumulator
+// ---- the mixed path's leaf: FP64 leaf, FP32 points ------------------------
+// Per cell: z = zf + zl as a pair of floats (so that 2 z.d keeps its
+// precision where d is small), and for every chord tanh bump the logistic
+// taken apart about the cell's own distance d_z = |z - x_c|:
+//   sigma(u_z + du) = sigma_z / (1 + q (2^du - 1)),  q = 1 - sigma_z,
+//   du = K2 (d - d_z) = K2 (d^2 - d_z^2) / (d + d_z),
+//   d^2 - d_z^2 = 2 (z - x_c).(y - z) + |y - z|^2
+// (K2 = 2 log2(e) / alpha, sigma in base 2).  Every per-point quantity is
+// then a small offset: in FP32 the bump's argument u = K2 (d - beta) itself
+// (|u| up to ~20 at the far side of the sphere) would carry ~1e-6 absolute
+// rounding into every point's density, and the distance d (~1) ~6e-8, which
+// the factor K2 (~19 at alpha = 0.15) turns into ~1e-6 relative noise in rho
+// point to point; as offsets they carry ~6e-8 of |y - z| ~ R.
+// With the geodesic distance theta = 2 asin(c/2) of the chord c, the offset
+// is taken from sin(asin a - asin b) = (a^2 - b^2) / (a sqrt(1 - b^2) +
+// b sqrt(1 - a^2)) with a = c/2, b = c_z/2 (a^2 - b^2 = (c^2 - c_z^2)/4, no
+// cancellation): theta - theta_z = 2 asin(X).
+// A cell within the FP64 expansion in x = d^2/2 (single chord bump, the
+// table entry about x*) takes its first six coefficients in FP32 instead:
+// rho = sum_k c_k D^k with D = x(y) - x* = (x(z) - x*) - (y - z).x_c, the
+// per-cell part formed in FP64.  Inside the entry's radius (chosen for the
+// degree-9 truncation below 1e-15, |D|/r <= ~0.025 of the series' radius r)
+// the degree-5 truncation is below ~1e-8 relative, and no special function
+// is left at the point.
+// The per-cell constants share one array (a cell takes one of the two
+// forms), so that the kernel holds one set of registers for them: bump k
+// at k[8k..8k+7] = z - x_c (3), amp sigma(d_z), 1 - sigma(d_z), c_z, c_z^2,
+// sqrt(1 - c_z^2/4) (geodesic); the expansion in x at k[0..9] = the six
+// coefficients, x(z) - x*, x_c (3).  Densities other than tanh bumps use
+// z - x_c at k[0..2] (and k[8..10]).
+struct CellF {
+  F3 zf, zl;
+  float k[16];
+  SCVT_HD F3 v3(int o) const { return F3{k[o], k[o + 1], k[o + 2]}; }
+  SCVT_HD void set3(int o, F3 v) {
+    k[o] = v.x;
+    k[o + 1] = v.y;
+    k[o + 2] = v.z;
+  }
+};
+
 template <int KIND>
-SCVT_HD void quad_tri_mixed(F3 dA, F3 dB, F3 dC, F3 zf, const F3* zc, const DensityF& D,
-                            const DensityP& Dd, Acc5& acc, int nq = 7) {
+SCVT_HD CellF cell_f32(const DensityP& D, V3 z, const double* tab = SCVT_EXP2_TAB) {
+  CellF c{};
+  c.zf = to_f3(z);
+  c.zl = to_f3(z - V3{(double)c.zf.x, (double)c.zf.y, (double)c.zf.z});
+  constexpr int NB = (KIND & kVarTwo) ? 2 : 1;
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const V3 t = z - V3{D.xc[b][0], D.xc[b][1], D.xc[b][2]};
+    c.set3(8 * b, to_f3(t));
+    if ((KIND & 7) == kRhoTanh) {
+      const double dz2 = dot(t, t), dz = sqrt(dz2);
+      const double sig = logistic(D.bK[b], D.K[b], (KIND & kVarGeo) ? chord_to_angle(dz) : dz, tab);
+      c.k[8 * b + 3] = (float)(D.amp[b] * sig);
+      c.k[8 * b + 4] = (float)(1.0 - sig);
+      c.k[8 * b + 5] = (float)dz;
+      c.k[8 * b + 6] = (float)dz2;
+      c.k[8 * b + 7] = (float)sqrt(fmax(1.0 - 0.25 * dz2, 0.0));
+    }
+  }
+  return c;
+}
+
+// A cell within the FP64 expansion in x = d^2/2 (single chord bump, the
+// table entry about x*) takes its first six coefficients in FP32 instead:
+// rho = sum_k c_k D^k with D = x(y) - x* = (x(z) - x*) - (y - z).x_c, the
+// per-cell part formed in FP64.  Inside the entry's radius (chosen for the
+// degree-9 truncation below 1e-15, |D|/r <= ~0.025 of the series' radius r)
+// the degree-5 truncation is below ~1e-8 relative, and no special function
+// is left at the point.
+SCVT_HD CellF cell_f32_poly(const DensityP& D, const RhoPoly& P, V3 z) {
+  CellF c{};
+  c.zf = to_f3(z);
+  c.zl = to_f3(z - V3{(double)c.zf.x, (double)c.zf.y, (double)c.zf.z});
+  const V3 xc = V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]};
+  for (int k = 0; k < 6; k++) c.k[k] = (float)P.c[k];
+  c.k[6] = (float)(P.off - dot(z, xc));
+  c.set3(7, to_f3(xc));
+  return c;
+}
+
+// rho at y = z + dyz (|dyz|^2 = dyz2): tanh bumps in the split form above,
+// every other density directly
+template <int KIND>
+SCVT_HD float rho_cell_f(const DensityF& D, const CellF& c, F3 dyz, float dyz2,
+                         const DensityP& Dd) {
+  if ((KIND & 7) == kRhoTanh) {
+    constexpr int NB = (KIND & kVarTwo) ? 2 : 1;
+    float rho = D.gamma;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const float* kb = c.k + 8 * b;
+      const float dd2 = fmaf(2.0f, dotf(c.v3(8 * b), dyz), dyz2);  // c^2 - c_z^2
+      const float t2 = fmaxf(kb[6] + dd2, 1e-30f);
+      const float ch = t2 * rsqf(t2);  // c
+      float dd;                        // d - d_z
+      if (KIND & kVarGeo) {
+        const float u = fmaxf(fmaf(-0.25f, t2, 1.0f), 1e-30f);
+        const float den = fmaxf(0.5f * fmaf(ch, kb[7], kb[5] * (u * rsqf(u))), 1e-30f);
+        const float X = 0.25f * dd2 * rcpf(den);  // sin((theta - theta_z)/2)
+        const float X2 = X * X;
+        // asin X by its series to X^5 (next term below 3e-10 of X for
+        // |X| <= 2^-4), else the library's
+        const float as = fabsf(X) <= 0.0625f ? X * fmaf(X2, fmaf(X2, 0.075f, 0.16666667f), 1.0f)
+                                             : asinf(X);
+        dd = 2.0f * as;
+      } else {
+        dd = dd2 * rcpf(fmaxf(ch + kb[5], 1e-30f));  // (c^2 - c_z^2) / (c + c_z)
+      }
+      const float du = -D.k2l[b] * dd;
+      rho = fmaf(kb[3], rcpf(fmaf(kb[4], exp2_hw(du) - 1.0f, 1.0f)), rho);
+    }
+    return rho;
+  }
+  const F3 zc[2] = {c.v3(0), c.v3(8)};
+  return rho_kind_f<KIND>(D, zc, c.zf, dyz, Dd);
+}
+
+// One leaf (A, B, C on the sphere, FP64) of a cell of z in the mixed
+// precision: the leaf's Jacobian determinant in FP64 (its rounding in FP32
+// would be a per-leaf relative error of ~1e-7, and the cell boundary's
+// corners rounded to FP32 would move the cell's edges by ~6e-8 R), the
+// points in FP32 offsets d = p - z from the rounded corner offsets:
+//   s = |z + d|^2 - 1 = 2 z.d + |d|^2,  r - 1 = (1 + s)^(-1/2) - 1,
+//   y - z = d + (r - 1)(z + d),  Jacobian r^3 = 1 + (r - 1)(3 + (r - 1)(3 + (r - 1)))
+// (no "1 +" rounded away at any point); the 7 weighted points summed in FP32
+// and scaled by the FP64 determinant into the FP64 accumulators.
+// Accumulates m, int rho (y - z) (mx, my, mz) and e.
+template <int KIND, bool XP = false>
+SCVT_HD void quad_leaf_mixed(V3 A, V3 B, V3 C, V3 z, const CellF& cf, const DensityF& D,
+                             const DensityP& Dd, Acc5& acc, int nq = 7) {
   const float(*R)[4] = SCVT_RULE_TABLE_F(nq);
-  const F3 A = zf + dA;
-  const F3 dBA = dB - dA, dCA = dC - dA;
-  const float hd = 0.5f * dotf(A, crossf(dBA, dCA));
+  const V3 BA = B - A, CA = C - A;
+  const double hd = 0.5 * dot(A, cross(BA, CA));
+  const F3 dA = to_f3(A - z), dBA = to_f3(BA), dCA = to_f3(CA);
   float sm = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, se = 0.f;
 #pragma unroll 1
   for (int q = 0; q < nq; q++) {
-    // d = l0 dA + l1 dB + l2 dC with l0 = 1 - l1 - l2
     const float l1 = R[q][1], l2 = R[q][2];
     const F3 d = F3{fmaf(l2, dCA.x, fmaf(l1, dBA.x, dA.x)), fmaf(l2, dCA.y, fmaf(l1, dBA.y, dA.y)),
                     fmaf(l2, dCA.z, fmaf(l1, dBA.z, dA.z))};
-    float s = 2.0f * dotf(zf, d) + dotf(d, d);
-    float r, rm1;
+    const float s = fmaf(2.0f, dotf(cf.zf, d) + dotf(cf.zl, d), dotf(d, d));
+    float rm1;
     if (fabsf(s) <= 0x1p-5f) {  // all but very large cells: no special functions
       rm1 = rm1_series(s);
-      r = 1.0f + rm1;
     } else {
-      r = rsqf(1.0f + s);
+      const float r = rsqf(1.0f + s);
       rm1 = -s * r * r * rcpf(1.0f + r);
     }
-    F3 dyz = r * d + rm1 * zf;
-    float jac = r * r * r;
-    float wt = hd * R[q][3] * jac * rho_kind_f<KIND>(D, zc, zf, dyz, Dd);
+    const F3 p = cf.zf + d;
+    const F3 dyz = F3{fmaf(rm1, p.x, d.x), fmaf(rm1, p.y, d.y), fmaf(rm1, p.z, d.z)};
+    const float jm1 = rm1 * fmaf(rm1, rm1 + 3.0f, 3.0f);
+    const float dyz2 = dotf(dyz, dyz);
+    float rho;
+    if (XP) {
+      const float Dx = fmaf(-dyz.z, cf.k[9], fmaf(-dyz.y, cf.k[8], fmaf(-dyz.x, cf.k[7], cf.k[6])));
+      rho = cf.k[5];
+#pragma unroll
+      for (int k = 4; k >= 0; k--) rho = fmaf(rho, Dx, cf.k[k]);
+    } else {
+      rho = rho_cell_f<KIND>(D, cf, dyz, dyz2, Dd);
+    }
+    const float b = R[q][3] * rho;
+    const float wt = fmaf(b, jm1, b);
     sm += wt;
-    sx += wt * dyz.x;
-    sy += wt * dyz.y;
-    sz += wt * dyz.z;
-    se += wt * dotf(dyz, dyz);
+    sx = fmaf(wt, dyz.x, sx);
+    sy = fmaf(wt, dyz.y, sy);
+    sz = fmaf(wt, dyz.z, sz);
+    se = fmaf(wt, dyz2, se);
   }
-  acc.m += (double)sm;
-  acc.mx += (double)sx;
-  acc.my += (double)sy;
-  acc.mz += (double)sz;
-  acc.e += (double)se;
+  acc.m = fma(hd, (double)sm, acc.m);
+  acc.mx = fma(hd, (double)sx, acc.mx);
+  acc.my = fma(hd, (double)sy, acc.my);
+  acc.mz = fma(hd, (double)sz, acc.mz);
+  acc.e = fma(hd, (double)se, acc.e);
 }
 
 // a / |a| through the reciprocal square root (quadrature only; the shared

@@ -225,9 +225,11 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
     const double rc = rt < w.D ? rt : w.D;
     const int ns = gather<GS, CAP, ROWS>(a, L, w, i, z, rc * rc, active, G);
     bool go = active;
-    if (go && ns > CAP) {
+    // the configured cap (a test knob) can only lower the pass's own
+    const int cap = a.kmax > 0 && a.kmax < CAP ? a.kmax : CAP;
+    if (go && ns > cap) {
       rc_over = rc;
-      rt = rc * sqrt_fast(0.75 * CAP / (double)ns);
+      rt = rc * sqrt_fast(0.75 * cap / (double)ns);
       if (rt <= r_small) active = false;
       go = false;
     }
@@ -271,7 +273,7 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
     r2 = group_max<GS>(r2);
     bool store = false;
     if (go) {
-      R = sqrt_fast(r2);
+      R = sqrt(r2);  // as the fallback clipper's, so that R does not depend on the path
       if (4.0 * r2 * (1.0 + 1e-12) <= rc * rc && En >= 3 && En <= kVmax) {
         outcome = kCellOk;
         active = false;
@@ -342,12 +344,15 @@ __device__ inline void hand_on(const CellArgs& a, int64_t i, int oc, int next_ti
 }
 
 // Main certified pass: eight cells per wave in cube-map order.
-__global__ __launch_bounds__(256, 4) void k_cells_geom(CellArgs a) {
+template <class P>
+__global__ __launch_bounds__(256, 4) void k_cells_geom(P p) {
+  if (p.idle()) return;
+  const CellArgs& a = p.args();
   constexpr int GS = 8, GPW = 64 / GS;
   __shared__ CandLds<GS, 16, 15> lds[4 * GPW];
   const GroupPos G = group_pos<GS>();
   const int wv = threadIdx.x >> 6;
-  const int64_t pos = (xcd_block(blockIdx.x) * 4 + wv) * GPW + G.gid;
+  const int64_t pos = (xcd_block(p.bx()) * 4 + wv) * GPW + G.gid;
   const bool valid = pos < a.n;
   if (!__ballot(valid)) return;
   const int64_t i = valid ? a.grid.order[pos] : 0;
@@ -357,15 +362,17 @@ __global__ __launch_bounds__(256, 4) void k_cells_geom(CellArgs a) {
 
 // List passes: the cells of tier list T, GS lanes each; what stays open
 // goes to list T + 1 (or, after the last pass, to the fallback).
-template <int T, int GS, int CAP, int ROWS>
-__global__ __launch_bounds__(256, 2) void k_cells_tier(CellArgs a) {
+template <int T, int GS, int CAP, int ROWS, class P>
+__global__ __launch_bounds__(256, 2) void k_cells_tier(P p) {
+  if (p.idle()) return;
+  const CellArgs& a = p.args();
   constexpr int GPW = 64 / GS;
   __shared__ CandLds<GS, CAP, ROWS> lds[4 * GPW];
   const GroupPos G = group_pos<GS>();
   const int wv = threadIdx.x >> 6;
   const int count = a.ctr->tier_count[T];
-  const int stride = gridDim.x * 4 * GPW;
-  for (int base = (blockIdx.x * 4 + wv) * GPW; base < count; base += stride) {
+  const int stride = p.gx() * 4 * GPW;
+  for (int base = (p.bx() * 4 + wv) * GPW; base < count; base += stride) {
     const int w = base + G.gid;
     const bool valid = w < count;
     const int64_t i = valid ? a.tier_list[T][w] : 0;
@@ -418,11 +425,14 @@ __device__ void fb_offer(FbLds& F, const double* Z, V3 z, int64_t self, int64_t 
   }
 }
 
-__global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
+template <class P>
+__global__ __launch_bounds__(64) void k_fallback(P p) {
+  if (p.idle()) return;
+  const CellArgs& a = p.args();
   __shared__ FbLds F;
   const int ln = lane_id();
   const int count = a.ctr->fb_count;
-  for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
+  for (int64_t w = p.bx(); w < count; w += p.gx()) {
     const int64_t i = a.fb_list[w];
     const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
     if (ln == 0) {
@@ -497,8 +507,8 @@ __global__ __launch_bounds__(64) void k_fallback(CellArgs a) {
 // each into one accumulator per lane, and sums its 32 lanes in a fixed
 // butterfly order: a cell's result depends neither on its partner nor on
 // the sort nor on the schedule.  MIXED: FP32 points in the generator's local
-// frame (quad_tri_mixed), FP64 sub-triangle vertices, accumulation and
-// epilogue.  Writes m, mu, e of the cell (g, h and the Lloyd step follow in
+// frame (quad_leaf_mixed), FP64 subdivision grid, leaf determinants,
+// accumulation and epilogue.  Writes m, mu, e of the cell (g, h and the Lloyd step follow in
 // k_eval_reduce).
 template <bool MIXED>
 __device__ inline void cell_epilogue(const EvalOut& o, int64_t i, V3 z, Acc5 acc) {
@@ -518,17 +528,12 @@ __device__ inline double half_sum(double v) {
 }
 
 template <int KIND, bool MIXED>
-__device__ inline void quad_item(const CellArgs& a, V3 A, V3 B, V3 C, V3 z, const DensityF& Df,
-                                 const double* tab, Acc5& acc) {
-  if (MIXED) {
-    F3 zc[2];
-    for (int k = 0; k < 2; k++)
-      zc[k] = to_f3(z - V3{a.rho.xc[k][0], a.rho.xc[k][1], a.rho.xc[k][2]});
-    quad_tri_mixed<KIND>(to_f3(A - z), to_f3(B - z), to_f3(C - z), to_f3(z), zc, Df, a.rho, acc,
-                         a.quad_rule);
-  } else {
+__device__ inline void quad_item(const CellArgs& a, V3 A, V3 B, V3 C, V3 z, const CellF& cf,
+                                 const DensityF& Df, const double* tab, Acc5& acc) {
+  if (MIXED)
+    quad_leaf_mixed<KIND>(A, B, C, z, cf, Df, a.rho, acc, a.quad_rule);
+  else
     quad_tri_k<KIND>(A, B, C, z, a.rho, acc, tab, a.quad_rule);
-  }
 }
 
 // Two subdivision levels (the configured rule): the 32 lanes of a half-wave
@@ -544,20 +549,23 @@ struct QuadLds {
 };
 constexpr int kQuadCells = 64;  // cells per block: eight pairs per wave
 
-template <int KIND, bool MIXED>
-__global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
+template <int KIND, bool MIXED, class P>
+__global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(P p) {
+  if (p.idle()) return;
+  const CellArgs& a = p.args();
   __shared__ QuadLds lds[4];
   __shared__ double tab[kExpN];  // the exponential's 2^(j/N) table
   // FP64 single chord tanh bump: cells whose fan lies within the density
   // polynomial's radius take it (RhoPoly); they are sorted ahead of the
   // others so that the two halves of a wave mostly take the same path
-  constexpr bool POLY = !MIXED && KIND == kRhoTanh;
+  // (MIXED: the expansion in x only, as FP32 coefficients)
+  constexpr bool POLY = KIND == kRhoTanh;
   constexpr int kBins = (POLY ? 3 : 1) * (kVmax + 1);
   __shared__ int bin[kBins];
   __shared__ int list[kQuadCells];
   const int tid = threadIdx.x;
   const EvalOut& o = a.out;
-  const int64_t base = (int64_t)blockIdx.x * kQuadCells;
+  const int64_t base = (int64_t)p.bx() * kQuadCells;
   const int ncell = a.n - base < kQuadCells ? (int)(a.n - base) : kQuadCells;
   if (tid < kExpN) tab[tid] = kExp2Tab[tid];
   if (tid < kBins) bin[tid] = 0;
@@ -583,7 +591,8 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
         const double delta = fabs(xz - (double)j * kPolyDx) + r * (dz + 0.5 * r);
         xmode = delta <= a.rho.polyx_tab[j].lim;
       }
-      key = xmode ? dm : (poly_qualifies(a.rho, z, r * r) ? kVmax + 1 + dm : 2 * (kVmax + 1) + dm);
+      key = xmode ? dm
+                  : (!MIXED && poly_qualifies(a.rho, z, r * r) ? kVmax + 1 + dm : 2 * (kVmax + 1) + dm);
     }
   }
   if (lead) atomicAdd(&bin[key], 1);
@@ -607,12 +616,14 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
 
   const int ln = lane_id(), w = tid >> 6, hl = ln & 31;
   const int lv = a.levels, per = 1 << (2 * lv);
-  CellArgs ar = a;  // density constants held in vector registers
-  pin_v(ar.rho.gamma);
-  for (int k = 0; k < 2; k++) {
-    pin_v(ar.rho.K[k]);
-    pin_v(ar.rho.bK[k]);
-    pin_v(ar.rho.amp[k]);
+  CellArgs ar = a;  // FP64 density constants held in vector registers
+  if (!MIXED) {
+    pin_v(ar.rho.gamma);
+    for (int k = 0; k < 2; k++) {
+      pin_v(ar.rho.K[k]);
+      pin_v(ar.rho.bK[k]);
+      pin_v(ar.rho.amp[k]);
+    }
   }
   DensityF Df{};
   if (MIXED) Df = density_f32(a.rho);
@@ -630,23 +641,19 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
     const int both = max(items, __shfl_xor(items, 32, 64));
     if (both == 0) continue;  // wave-uniform
     Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const bool use_poly = POLY && (ent & 256), xmode = POLY && (ent & 512);
+    // (the mixed path has no expansion in t: its cells take x or nothing)
+    const bool xmode = POLY && (ent & 512), use_poly = POLY && (MIXED ? xmode : (ent & 256));
     RhoPoly rp{};
     if (use_poly) {
       double xz;
       rp = xmode ? ar.rho.polyx_tab[polyx_index(ar.rho, z, &xz)]
                  : ar.rho.poly_tab[poly_index(ar.rho, z)];
     }
+    CellF cf{};
+    if (MIXED) cf = xmode ? cell_f32_poly(ar.rho, rp, z) : cell_f32<KIND>(ar.rho, z, tab);
     if (lv == 2) {
       // the whole cell's grids (up to kGridEdges edges at a time), then its
-      // leaves; the mixed path keeps FP32 offsets from z (its local frame)
-      float(*Gf)[15][3] = reinterpret_cast<float(*)[15][3]>(&G[0][0][0]);
-      F3 zc[2] = {}, zf = {};
-      if (MIXED) {
-        for (int k = 0; k < 2; k++)
-          zc[k] = to_f3(z - V3{ar.rho.xc[k][0], ar.rho.xc[k][1], ar.rho.xc[k][2]});
-        zf = to_f3(z);
-      }
+      // leaves (FP64 grid points on both paths)
       const int dboth = max(d, __shfl_xor(d, 32, 64));
       for (int e0 = 0; e0 < dboth; e0 += kGridEdges) {
         const int ne = min(max(d - e0, 0), kGridEdges);
@@ -658,18 +665,11 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
           const bool vert = hl < 2 * ne;
           const int e = vert ? hl >> 1 : hl - 2 * ne, k = vert ? ((hl & 1) ? 0 : 4) : 14;
           const double* ed = eb + (e0 + e) * 6 + ((hl & 1) ? 3 : 0);
-          const V3 P = vert ? V3{__builtin_nontemporal_load(ed), __builtin_nontemporal_load(ed + 1),
+          const V3 X = vert ? V3{__builtin_nontemporal_load(ed), __builtin_nontemporal_load(ed + 1),
                                     __builtin_nontemporal_load(ed + 2)} : z;
-          if (MIXED) {
-            const F3 q = vert ? to_f3(P - z) : F3{0.0f, 0.0f, 0.0f};
-            Gf[e][k][0] = q.x;
-            Gf[e][k][1] = q.y;
-            Gf[e][k][2] = q.z;
-          } else {
-            G[e][k][0] = P.x;
-            G[e][k][1] = P.y;
-            G[e][k][2] = P.z;
-          }
+          G[e][k][0] = X.x;
+          G[e][k][1] = X.y;
+          G[e][k][2] = X.z;
         }
         wave_sync();
         // level-1 midpoints (3 per edge), then level-2 (9 per edge)
@@ -681,19 +681,11 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
               const int e = (int)(q / (unsigned)per_e);
               const int task = (int)q - per_e * e + (level == 0 ? 0 : 3);
               const int kp = nib(kG2TaskP, task), kq = nib(kG2TaskQ, task), km = nib(kG2TaskPt, task);
-              if (MIXED) {
-                const F3 m = arc_midpoint_local(F3{Gf[e][kp][0], Gf[e][kp][1], Gf[e][kp][2]},
-                                                F3{Gf[e][kq][0], Gf[e][kq][1], Gf[e][kq][2]}, zf);
-                Gf[e][km][0] = m.x;
-                Gf[e][km][1] = m.y;
-                Gf[e][km][2] = m.z;
-              } else {
-                const V3 m = normalized_fast(V3{G[e][kp][0], G[e][kp][1], G[e][kp][2]} +
-                                             V3{G[e][kq][0], G[e][kq][1], G[e][kq][2]});
-                G[e][km][0] = m.x;
-                G[e][km][1] = m.y;
-                G[e][km][2] = m.z;
-              }
+              const V3 m = normalized_fast(V3{G[e][kp][0], G[e][kp][1], G[e][kp][2]} +
+                                           V3{G[e][kq][0], G[e][kq][1], G[e][kq][2]});
+              G[e][km][0] = m.x;
+              G[e][km][1] = m.y;
+              G[e][km][2] = m.z;
             }
           }
           wave_sync();
@@ -703,22 +695,17 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
           if (t < 16 * ne) {
             const int e = t >> 4;
             const int ka = nib(kG2LeafA, s), kb = nib(kG2LeafB, s), kc = nib(kG2LeafC, s);
-            if (MIXED) {
-              quad_tri_mixed<KIND>(F3{Gf[e][ka][0], Gf[e][ka][1], Gf[e][ka][2]},
-                                   F3{Gf[e][kb][0], Gf[e][kb][1], Gf[e][kb][2]},
-                                   F3{Gf[e][kc][0], Gf[e][kc][1], Gf[e][kc][2]}, zf, zc, Df,
-                                   ar.rho, acc, ar.quad_rule);
-            } else {
-              const V3 A = V3{G[e][ka][0], G[e][ka][1], G[e][ka][2]};
-              const V3 B = V3{G[e][kb][0], G[e][kb][1], G[e][kb][2]};
-              const V3 C = V3{G[e][kc][0], G[e][kc][1], G[e][kc][2]};
-              if (xmode)
-                quad_tri_poly<true>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
-              else if (use_poly)
-                quad_tri_poly<false>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
-              else
-                quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
-            }
+            const V3 A = V3{G[e][ka][0], G[e][ka][1], G[e][ka][2]};
+            const V3 B = V3{G[e][kb][0], G[e][kb][1], G[e][kb][2]};
+            const V3 C = V3{G[e][kc][0], G[e][kc][1], G[e][kc][2]};
+            if (MIXED && xmode)
+              quad_leaf_mixed<KIND, true>(A, B, C, z, cf, Df, ar.rho, acc, ar.quad_rule);
+            else if (xmode)
+              quad_tri_poly<true>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+            else if (use_poly)
+              quad_tri_poly<false>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+            else
+              quad_item<KIND, MIXED>(ar, A, B, C, z, cf, Df, tab, acc);
           }
         }
         wave_sync();  // the next chunk or cell rewrites the grids
@@ -731,12 +718,14 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
         V3 B = V3{ed[0], ed[1], ed[2]};
         V3 C = V3{ed[3], ed[4], ed[5]};
         subtriangle(A, B, C, sub, lv);
-        if (xmode)
+        if (MIXED && xmode)
+          quad_leaf_mixed<KIND, true>(A, B, C, z, cf, Df, ar.rho, acc, ar.quad_rule);
+        else if (xmode)
           quad_tri_poly<true>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
         else if (use_poly)
           quad_tri_poly<false>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
         else
-          quad_item<KIND, MIXED>(ar, A, B, C, z, Df, tab, acc);
+          quad_item<KIND, MIXED>(ar, A, B, C, z, cf, Df, tab, acc);
       }
     }
     const Acc5 tot = {half_sum(acc.m), half_sum(acc.mx), half_sum(acc.my), half_sum(acc.mz),
@@ -746,36 +735,69 @@ __global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(CellArgs a) {
 }
 
 // small problems: every cell goes through the fallback clipper
-__global__ void k_fb_all(int32_t* fb_list, Counters* ctr, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) fb_list[i] = (int32_t)i;
-  if (i == 0) ctr->fb_count = (int32_t)n;
+template <class P>
+__global__ void k_fb_all(P p) {
+  if (p.idle()) return;
+  const CellArgs& a = p.args();
+  int64_t i = (int64_t)p.bx() * blockDim.x + threadIdx.x;
+  if (i < a.n) a.fb_list[i] = (int32_t)i;
+  if (i == 0) a.ctr->fb_count = (int32_t)a.n;
 }
 
-hipError_t launch_cells_main(const CellArgs& a, hipStream_t s) {
-  const int64_t nb = (a.n + 31) / 32;  // eight cells per wave, four waves per block
+// grid sizes of the cell kernels for a problem (the segmented launches use
+// the same ones per problem)
+int cells_main_grid(int64_t n) {
+  const int64_t nb = (n + 31) / 32;  // eight cells per wave, four waves per block
   const int64_t pad = 8 * kXcdChunk;
-  k_cells_geom<<<(unsigned)((nb + pad - 1) / pad * pad), 256, 0, s>>>(a);
+  return (int)((nb + pad - 1) / pad * pad);
+}
+// list lengths are only known on the device: fixed grids, large enough for
+// a long list (a random start hands on a few percent of the cells) to run
+// at several waves per SIMD; idle blocks exit at once.  The second list
+// holds what the first could not certify: far shorter
+int cells_tier_grid(int64_t n, int tier) {
+  const int64_t nb = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
+  return (int)(tier == 0 ? nb : (nb < 512 ? nb : 512));
+}
+// one cell per block; after the certified passes the list is short
+int cells_fallback_grid(int64_t n, int all) {
+  const int64_t cap = all ? 8192 : 1024;
+  return (int)(n < cap ? n : cap);
+}
+int fb_all_grid(int64_t n) { return (int)((n + 255) / 256); }
+int quad_grid(int64_t n) { return (int)((n + kQuadCells - 1) / kQuadCells); }
+
+hipError_t launch_cells_main(const CellArgs& a, hipStream_t s) {
+  k_cells_geom<<<(unsigned)cells_main_grid(a.n), 256, 0, s>>>(One<CellArgs>{a});
   return hipGetLastError();
 }
 
 hipError_t launch_cells_tiers(const CellArgs& a, hipStream_t s) {
-  // list lengths are only known on the device: fixed grids, large enough
-  // for a long list (a random start hands on a few percent of the cells)
-  // to run at several waves per SIMD; idle blocks exit at once
-  const int64_t nb = (a.n + 255) / 256 < 2048 ? (a.n + 255) / 256 : 2048;
-  k_cells_tier<0, 32, 32, 31><<<(unsigned)nb, 256, 0, s>>>(a);
-  // the second list holds what the first could not certify: far shorter
-  k_cells_tier<1, 64, 64, kWinMax><<<(unsigned)(nb < 512 ? nb : 512), 256, 0, s>>>(a);
+  k_cells_tier<0, 32, 32, 31><<<(unsigned)cells_tier_grid(a.n, 0), 256, 0, s>>>(One<CellArgs>{a});
+  k_cells_tier<1, 64, 64, kWinMax><<<(unsigned)cells_tier_grid(a.n, 1), 256, 0, s>>>(One<CellArgs>{a});
   return hipGetLastError();
 }
 
 hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s) {
-  if (all) k_fb_all<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a.fb_list, a.ctr, a.n);
-  // one cell per block; after the certified passes the list is short
-  const int64_t cap = all ? 8192 : 1024;
-  const int64_t fb_blocks = a.n < cap ? a.n : cap;
-  k_fallback<<<(unsigned)fb_blocks, 64, 0, s>>>(a);
+  if (all) k_fb_all<<<(unsigned)fb_all_grid(a.n), 256, 0, s>>>(One<CellArgs>{a});
+  k_fallback<<<(unsigned)cells_fallback_grid(a.n, all), 64, 0, s>>>(One<CellArgs>{a});
+  return hipGetLastError();
+}
+
+// segmented: main pass, list passes and fallback of a batch (tabs[k]: the
+// batch's table of kernel k's grids, all on one args table)
+hipError_t launch_cells_many(const CellArgs* tab, const int32_t* nb_main, int max_main,
+                             const int32_t* nb_t0, int max_t0, const int32_t* nb_t1, int max_t1,
+                             const int32_t* nb_all, int max_all, const int32_t* nb_fb, int max_fb,
+                             int nseg, hipStream_t s) {
+  if (max_main > 0)
+    k_cells_geom<<<dim3(max_main, nseg), 256, 0, s>>>(Many<CellArgs>{tab, nb_main});
+  if (max_t0 > 0)
+    k_cells_tier<0, 32, 32, 31><<<dim3(max_t0, nseg), 256, 0, s>>>(Many<CellArgs>{tab, nb_t0});
+  if (max_t1 > 0)
+    k_cells_tier<1, 64, 64, kWinMax><<<dim3(max_t1, nseg), 256, 0, s>>>(Many<CellArgs>{tab, nb_t1});
+  if (max_all > 0) k_fb_all<<<dim3(max_all, nseg), 256, 0, s>>>(Many<CellArgs>{tab, nb_all});
+  k_fallback<<<dim3(max_fb, nseg), 64, 0, s>>>(Many<CellArgs>{tab, nb_fb});
   return hipGetLastError();
 }
 
@@ -795,16 +817,32 @@ hipError_t launch_poly_table(const DensityP& D, RhoPoly* out, RhoPoly* outx, hip
 }
 
 hipError_t launch_quad(const CellArgs& a, hipStream_t s) {
-  const unsigned nb = (unsigned)((a.n + kQuadCells - 1) / kQuadCells);
+  const unsigned nb = (unsigned)quad_grid(a.n);
 #define SCVT_LAUNCH_QUAD(V)                                  \
   do {                                                       \
     if (a.mixed)                                             \
-      k_quad<V, true><<<nb, 256, 0, s>>>(a);                 \
+      k_quad<V, true><<<nb, 256, 0, s>>>(One<CellArgs>{a});  \
     else                                                     \
-      k_quad<V, false><<<nb, 256, 0, s>>>(a);                \
+      k_quad<V, false><<<nb, 256, 0, s>>>(One<CellArgs>{a}); \
   } while (0)
   SCVT_RHO_DISPATCH(rho_variant(a.rho), SCVT_LAUNCH_QUAD)
 #undef SCVT_LAUNCH_QUAD
+  return hipGetLastError();
+}
+
+// segmented: every problem of the batch has density variant `var` and
+// precision `mixed`
+hipError_t launch_quad_many(const Seg<CellArgs>& g, int var, int mixed, hipStream_t s) {
+  const dim3 grid(g.maxnb, g.nseg);
+#define SCVT_LAUNCH_QUAD_MANY(V)                                          \
+  do {                                                                    \
+    if (mixed)                                                            \
+      k_quad<V, true><<<grid, 256, 0, s>>>(Many<CellArgs>{g.tab, g.nb});  \
+    else                                                                  \
+      k_quad<V, false><<<grid, 256, 0, s>>>(Many<CellArgs>{g.tab, g.nb}); \
+  } while (0)
+  SCVT_RHO_DISPATCH(var, SCVT_LAUNCH_QUAD_MANY)
+#undef SCVT_LAUNCH_QUAD_MANY
   return hipGetLastError();
 }
 

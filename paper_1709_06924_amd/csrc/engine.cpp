@@ -12,8 +12,10 @@
 #include <vector>
 
 #include "../../include/scvt.h"
+#include "engine_batch.h"
 #include "kernels.h"
 #include "lbfgs.h"
+#include "round.h"
 
 using namespace scvt;
 
@@ -97,6 +99,18 @@ struct scvt_handle {
   // a_j of the backward recursion for the current history already computed
   // (by the last push's chained fin steps)
   bool backward_ready = false;
+  // ---- batched (serving) mode: device memory from a caller's arena, the
+  // pinned scalars and stream from the server, launches recorded into a
+  // round instead of issued (rec), and the P-LBFGS iteration as a state
+  // machine advanced once per round
+  bool batched = false;
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
+  Round* rec = nullptr;
+  int bstate = 0, bk = 0;
+  double balpha = 1.0, bgq = 0.0;
+  int64_t bmax_iter = 0;
+  double btol = 0.0;
 };
 
 namespace {
@@ -127,6 +141,13 @@ int dalloc(scvt_handle* h, T** p, size_t count) {
   if (h->dry_run) {  // footprint only: count the bytes, allocate nothing
     h->dry_bytes += (count * sizeof(T) + 255) / 256 * 256;
     *p = (T*)(uintptr_t)256;
+    return SCVT_OK;
+  }
+  if (h->arena) {  // the caller's memory, laid out as the dry run counts it
+    const size_t bytes = (count * sizeof(T) + 255) / 256 * 256;
+    if (h->arena_used + bytes > h->arena_bytes) return SCVT_E_OOM;
+    *p = (T*)(h->arena + h->arena_used);
+    h->arena_used += bytes;
     return SCVT_OK;
   }
   if (hipMalloc(&v, count * sizeof(T)) != hipSuccess) return SCVT_E_OOM;
@@ -206,6 +227,7 @@ int validate(const scvt_config* c) {
   if (c->quad_rule != 4 && c->quad_rule != 7 && c->quad_rule != 9) return SCVT_E_INVALID;
   if (c->ls_max_evals < 1 || !(c->ls_c1 > 0.0 && c->ls_c1 < 1.0)) return SCVT_E_INVALID;
   if (!(c->curv_eps >= 0.0)) return SCVT_E_INVALID;
+  if (c->k_max < 0) return SCVT_E_INVALID;
   const scvt_density& d = c->rho;
   if (d.kind < 0 || d.kind > 3) return SCVT_E_INVALID;
   if (d.kind == SCVT_RHO_TANH) {
@@ -245,6 +267,7 @@ CellArgs cell_args(scvt_handle* h, const double* Zsrc, EvalSet& s) {
   a.tier_list[1] = h->tier_list[1];
   a.ctr = h->ctr;
   a.r_default = h->r_default;
+  a.kmax = h->cfg.k_max;
   return a;
 }
 
@@ -257,6 +280,89 @@ void timer_add(scvt_handle* h, int k, hipEvent_t a, hipEvent_t b) {
 }
 
 int launch_push_pre(scvt_handle* h);
+
+// Launches of the iteration's steps: issued on the handle's stream, or, in
+// batched mode, recorded into the round (the same arguments).
+int vw_of(int64_t n3) { return n3 % 2 == 0 ? 2 : 1; }
+hipError_t L_hist_fin(scvt_handle* h, const HistFinArgs& f) {
+  if (!h->rec) return launch_hist_fin(f, h->stream);
+  if (f.mode == kFinBackward) h->rec->fin_back.push_back(f);
+  else if (f.mode == kFinForward) h->rec->fin_fwd.push_back(f);
+  else if (f.mode == kFinGQ) h->rec->fin_gq.push_back(f);
+  else return hipErrorInvalidValue;  // no other step runs in a round
+  return hipSuccess;
+}
+hipError_t L_hist_q0(scvt_handle* h, const HistPassArgs& p) {
+  if (!h->rec) return launch_hist_q0(p, h->stream);
+  h->rec->q0[vw_of(p.n3) - 1].push_back(p);
+  return hipSuccess;
+}
+hipError_t L_hist_dir(scvt_handle* h, const HistPassArgs& p) {
+  if (!h->rec) return launch_hist_dir(p, h->stream);
+  h->rec->dir[vw_of(p.n3) - 1].push_back(p);
+  return hipSuccess;
+}
+hipError_t L_push_ext(scvt_handle* h, const PushExtArgs& p) {
+  if (!h->rec) return launch_push_ext(p, h->stream);
+  h->rec->push_ext[vw_of(p.n3) - 1].push_back(p);
+  return hipSuccess;
+}
+hipError_t L_fin_chain(scvt_handle* h, const FinChain& f) {
+  if (!h->rec) return launch_fin_chain(f, h->stream);
+  h->rec->fin_chain.push_back(f);
+  return hipSuccess;
+}
+hipError_t L_normalize(scvt_handle* h, const double* Z, const double* q, double alpha, double* Zt) {
+  if (!h->rec) return launch_normalize_trial(Z, q, alpha, Zt, h->n, h->stream);
+  h->rec->norm.push_back(NormArgs{Z, q, alpha, Zt, h->n});
+  return hipSuccess;
+}
+
+// per generator g, h, l and the block partials of the evaluation's scalars;
+// then their fixed-order finish into the device scalars
+EvalRedArgs eval_red_args(scvt_handle* h, const double* Zsrc, EvalSet& s) {
+  EvalRedArgs r{};
+  r.n = h->n;
+  r.e = s.e;
+  r.mu = s.mu;
+  r.Z = Zsrc;
+  r.g = s.g;
+  r.h = s.h;
+  r.lloyd = s.lloyd;
+  r.partials = h->partials + kPartEval * reduce_grid_max();
+  return r;
+}
+FinalizeArgs eval_fin_args(scvt_handle* h, const EvalRedArgs& r) {
+  FinalizeArgs fa{};
+  fa.partials = r.partials;
+  fa.nblocks = reduce_grid(h->n);
+  fa.nvals = 4;
+  fa.op[0] = 0;
+  fa.op[1] = 1;
+  fa.op[2] = 0;
+  fa.op[3] = 2;
+  fa.out = h->dscal + kEval;
+  return fa;
+}
+int evaluate_complete(scvt_handle* h);
+
+// An evaluation at Zsrc into set s recorded into the handle's round (batched
+// mode): the same launches as evaluate(), and the same scalars gathered into
+// the pinned mirror at the round's end (evaluate_complete then reads them).
+int record_evaluation(scvt_handle* h, const double* Zsrc, EvalSet& s) {
+  Round* R = h->rec;
+  std::swap(h->grid.order, h->grid.order_prev);  // last build's order drives this one
+  R->grid.push_back(GridBuildArgs{Zsrc, h->n, h->grid, (int32_t*)h->ctr});  // also clears ctr
+  const CellArgs a = cell_args(h, Zsrc, s);
+  (h->main_path ? R->cells : R->cells_all).push_back(a);
+  R->quad[{rho_variant(a.rho), a.mixed}].push_back(a);
+  const EvalRedArgs r = eval_red_args(h, Zsrc, s);
+  R->reduce.push_back(r);
+  R->fin.push_back(eval_fin_args(h, r));
+  R->out.push_back(Round::Out{h->dscal + kGQ, kPinWords, h->pinned + kPinGQ});
+  h->pre_valid = false;
+  return SCVT_OK;
+}
 
 // Evaluate at Zsrc into set s: grid, cells, reductions; one host sync.
 // prepush (a trial of the P-LBFGS loop): the push of the trial as the next
@@ -278,26 +384,9 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s, bool prepush = fals
   if (tq) HIPCK(hipEventRecord(h->ev[3], st));
   HIPCK(launch_quad(a, st));
   if (tq) HIPCK(hipEventRecord(h->ev[7], st));
-  EvalRedArgs r{};
-  r.n = h->n;
-  r.e = s.e;
-  r.mu = s.mu;
-  r.Z = Zsrc;
-  r.g = s.g;
-  r.h = s.h;
-  r.lloyd = s.lloyd;
-  r.partials = h->partials + kPartEval * reduce_grid_max();
+  const EvalRedArgs r = eval_red_args(h, Zsrc, s);
   HIPCK(launch_eval_reduce(r, st));
-  FinalizeArgs fa{};
-  fa.partials = r.partials;
-  fa.nblocks = reduce_grid(h->n);
-  fa.nvals = 4;
-  fa.op[0] = 0;
-  fa.op[1] = 1;
-  fa.op[2] = 0;
-  fa.op[3] = 2;
-  fa.out = h->dscal + kEval;
-  HIPCK(launch_finalize(fa, st));
+  HIPCK(launch_finalize(eval_fin_args(h, r), st));
   if (tm) HIPCK(hipEventRecord(h->ev[4], st));
   // one copy brings g.q, the last push's curvature scalars, this
   // evaluation's scalars and its counters (adjacent device scalars)
@@ -324,6 +413,11 @@ int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s, bool prepush = fals
     timer_add(h, 4, h->ev[0], h->ev[4]);
   }
   if (tq) timer_add(h, 5, h->ev[3], h->ev[7]);
+  return evaluate_complete(h);
+}
+
+// the evaluation's scalars, once they are in the pinned mirror
+int evaluate_complete(scvt_handle* h) {
   Counters c;
   memcpy(&c, h->pinned + kPinCtr, sizeof(Counters));
   h->tF = h->pinned[kPinEval];
@@ -448,24 +542,24 @@ int direction_fused(scvt_handle* h, const double* hv, double* gq) {
   if (c > 0 && !h->backward_ready) {
     f.mode = kFinBackward;
     f.nvals = 0;
-    HIPCK(launch_hist_fin(f, st));
+    HIPCK(L_hist_fin(h, f));
   }
   h->backward_ready = false;
   p.coef = D + kA;
   p.q = h->q;
-  HIPCK(launch_hist_q0(p, st));
+  HIPCK(L_hist_q0(h, p));
   if (c > 0) {
     f.mode = kFinForward;
     f.nvals = c;
-    HIPCK(launch_hist_fin(f, st));
+    HIPCK(L_hist_fin(h, f));
   }
   p.coef = D + kCoef;
   p.qin = h->q;
   p.q = h->q;
-  HIPCK(launch_hist_dir(p, st));
+  HIPCK(L_hist_dir(h, p));
   f.mode = kFinGQ;
   f.nvals = 1;
-  HIPCK(launch_hist_fin(f, st));
+  HIPCK(L_hist_fin(h, f));
   if (h->timing) HIPCK(hipEventRecord(h->ev[6], st));
   return finish_direction(h, gq);
 }
@@ -679,7 +773,7 @@ hipError_t launch_push_ext_now(scvt_handle* h, int slot) {
   p.c = (int)h->ring.size();
   p.partials = h->hpart;
   for (int j = 0; j < p.c; j++) p.S[j] = h->S + (size_t)h->ring[j] * n3;
-  return launch_push_ext(p, h->stream);
+  return L_push_ext(h, p);
 }
 
 // the trial's push, ahead of its acceptance (a rejected trial's slot stays
@@ -747,7 +841,7 @@ int push_pair(scvt_handle* h) {
     if (!(h->pre_valid && h->pre_slot == slot && h->pre_ring == h->ring))
       HIPCK(launch_push_ext_now(h, slot));
     h->pre_valid = false;
-    HIPCK(launch_fin_chain(fc, h->stream));
+    HIPCK(L_fin_chain(h, fc));
     h->backward_ready = true;
   } else {
     PushArgs p{};
@@ -926,7 +1020,7 @@ void destroy(scvt_handle* h) {
   if (!h) return;
   if (h->stream) hipStreamSynchronize(h->stream);
   for (void* p : h->allocs) hipFree(p);
-  if (h->pinned) hipHostFree(h->pinned);
+  if (h->pinned && !h->batched) hipHostFree(h->pinned);
   for (auto& e : h->ev)
     if (e) hipEventDestroy(e);
   if (h->ev_copy) hipEventDestroy(h->ev_copy);
@@ -991,13 +1085,16 @@ int init_device_state(scvt_handle* h) {
   const int64_t n = h->n;
   const int M = h->M;
   const int64_t nc = h->grid.g.ncells;
-  if (hipHostMalloc((void**)&h->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-    return SCVT_E_OOM;
-  if (hipEventCreateWithFlags(&h->ev_copy, hipEventDisableTiming) != hipSuccess) return SCVT_E_HIP;
-  // timing only, read after a stream synchronisation: no system-scope fence
-  // (which writes back and invalidates caches at every record)
-  for (auto& e : h->ev)
-    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return SCVT_E_HIP;
+  if (!h->batched) {  // batched: the server's pinned scalars, no events (no timing)
+    static_assert(64 * sizeof(double) == kBatchPinnedBytes, "pinned scalars");
+    if (hipHostMalloc((void**)&h->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      return SCVT_E_OOM;
+    if (hipEventCreateWithFlags(&h->ev_copy, hipEventDisableTiming) != hipSuccess) return SCVT_E_HIP;
+    // timing only, read after a stream synchronisation: no system-scope fence
+    // (which writes back and invalidates caches at every record)
+    for (auto& e : h->ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return SCVT_E_HIP;
+  }
   hipStream_t st = h->stream;
   HIPCK(launch_fill_i32(h->grid.cnt_tot, 0, nc + 1, st));
   HIPCK(launch_fill_i32(h->grid.cnt_home, 0, nc + 1, st));
@@ -1015,6 +1112,189 @@ int init_device_state(scvt_handle* h) {
 }
 
 }  // namespace
+
+// ============================================================ batched mode
+// The P-LBFGS iteration of quasi_newton_step (with scvt_solve's late
+// curvature decision) as a state machine: each state records the launches
+// of one evaluation (and what precedes it) into a round, and batch_finish
+// takes the decision quasi_newton_step takes after that evaluation's host
+// sync.  The evaluations, their order and their results are those of
+// scvt_solve (the trial's early push aside, which only moves work earlier).
+namespace scvt {
+
+enum BatchState : int {
+  kBEval0 = 0,  // the initial evaluation
+  kBIter,       // direction and the first trial (alpha = 1)
+  kBRestart,    // not a descent direction: history cleared, Lloyd direction, alpha = 1
+  kBSearch,     // backtracking: trial at balpha
+  kBLloyd,      // no sufficient decrease: the Lloyd step
+  kBDone
+};
+
+int batch_create(const scvt_config* cfg, const double* z0, void* arena, size_t arena_bytes,
+                 double* pinned, void* stream, int64_t max_iter, double tol, scvt_handle** out) {
+  if (!out || !z0 || !arena || !pinned || !stream) return SCVT_E_INVALID;
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (cfg->method != SCVT_METHOD_PLBFGS || cfg->m_hist > kHmax) return SCVT_E_INVALID;
+  const int64_t n = cfg->n;
+  for (int64_t k = 0; k < 3 * n; k++)
+    if (!isfinite(z0[k])) return SCVT_E_INVALID;
+  for (int64_t i = 0; i < n; i++)
+    if (z0[3 * i] == 0.0 && z0[3 * i + 1] == 0.0 && z0[3 * i + 2] == 0.0) return SCVT_E_DEGENERATE;
+  scvt_handle* h = new (std::nothrow) scvt_handle();
+  if (!h) return SCVT_E_OOM;
+  h->cfg = *cfg;
+  h->cfg.hip_stream = stream;
+  h->n = n;
+  h->M = cfg->m_hist;
+  h->rho = to_dev(cfg->rho);
+  h->ls_noise = cfg->ls_noise >= 0.0 ? cfg->ls_noise : (cfg->precision == SCVT_MIXED ? 1e-8 : 0.0);
+  h->stream = (hipStream_t)stream;
+  h->batched = true;
+  h->arena = (char*)arena;
+  h->arena_bytes = arena_bytes;
+  h->pinned = pinned;
+  h->bmax_iter = max_iter;
+  h->btol = tol;
+  h->bstate = kBEval0;
+  rc = init_device_state(h);
+  if (!rc)
+    rc = hip_err(hipMemcpyAsync(h->Zt, z0, 3 * n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  if (rc) {
+    destroy(h);
+    return rc;
+  }
+  *out = h;
+  return SCVT_OK;
+}
+
+int batch_plan(scvt_handle* h, Round& r) {
+  h->rec = &r;
+  int rc = SCVT_OK;
+  switch (h->bstate) {
+    case kBEval0:  // rows normalised to the sphere, then evaluated
+      rc = hip_err(L_normalize(h, h->Zt, nullptr, 0.0, h->Z));
+      if (!rc) rc = record_evaluation(h, h->Z, h->cur);
+      break;
+    case kBIter:
+    case kBRestart:
+    case kBLloyd:  // (the history is already cleared for the last two)
+      rc = direction(h, nullptr);
+      if (!rc) rc = hip_err(L_normalize(h, h->Z, h->q, 1.0, h->Zt));
+      if (!rc) rc = record_evaluation(h, h->Zt, h->trial);
+      break;
+    case kBSearch:
+      rc = hip_err(L_normalize(h, h->Z, h->q, h->balpha, h->Zt));
+      if (!rc) rc = record_evaluation(h, h->Zt, h->trial);
+      break;
+    default:
+      rc = SCVT_E_INVALID;
+  }
+  h->rec = nullptr;
+  return rc;
+}
+
+namespace {
+
+// the solve's status once an iterate is adopted: SCVT_PENDING to go on
+int batch_status(scvt_handle* h) {
+  if (h->step_inf < h->btol) return SCVT_OK;
+  if (h->iter >= h->bmax_iter) return SCVT_NOT_CONVERGED;
+  return SCVT_PENDING;
+}
+
+// the trial is the next iterate (quasi_newton_step's tail): the history push
+// goes into the next round unless the solve stops here
+int batch_accept(scvt_handle* h, double alpha, Round& next) {
+  const bool last = h->tstep < h->btol || h->iter + 1 >= h->bmax_iter;
+  if (!last) {
+    h->rec = &next;
+    const int rc = push_pair(h);
+    h->rec = nullptr;
+    if (rc) return rc;
+  }
+  swap_sets(h);
+  adopt_trial_scalars(h);
+  h->alpha = alpha;
+  h->iter++;
+  h->bstate = kBIter;
+  return batch_status(h);
+}
+
+// Armijo failed at the k-th trial of the line search along the direction
+int batch_backtrack(scvt_handle* h, int k) {
+  if (k + 1 < h->cfg.ls_max_evals) {
+    h->bk = k + 1;
+    h->balpha = ldexp(1.0, -(k + 1));
+    h->bstate = kBSearch;
+  } else {
+    clear_history(h);
+    h->bstate = kBLloyd;
+  }
+  return SCVT_PENDING;
+}
+
+}  // namespace
+
+int batch_finish(scvt_handle* h, Round& next) {
+  const int st = h->bstate;
+  int rc = evaluate_complete(h);
+  if (rc < 0) {
+    h->bstate = kBDone;
+    return rc;
+  }
+  switch (st) {
+    case kBEval0:
+      h->n_evals = 1;
+      adopt_trial_scalars(h);
+      h->bstate = kBIter;
+      return batch_status(h);
+    case kBIter: {
+      bool undone = false;
+      rc = resolve_push(h, true, &undone);
+      if (rc) return rc;
+      if (undone) return SCVT_PENDING;  // the direction used a pair the history does not hold
+      const double gq = h->pinned[kPinGQ];
+      if (!(gq < 0.0)) {  // not a descent direction: back to the Lloyd direction
+        clear_history(h);
+        h->bstate = kBRestart;
+        return SCVT_PENDING;
+      }
+      h->n_evals++;
+      h->bgq = gq;
+      if (armijo(h, 1.0, gq)) return batch_accept(h, 1.0, next);
+      return batch_backtrack(h, 0);
+    }
+    case kBRestart: {  // the first trial of the line search along the Lloyd direction
+      h->bgq = h->pinned[kPinGQ];
+      h->n_evals++;
+      if (armijo(h, 1.0, h->bgq)) return batch_accept(h, 1.0, next);
+      return batch_backtrack(h, 0);
+    }
+    case kBSearch:
+      h->n_evals++;
+      if (armijo(h, h->balpha, h->bgq)) return batch_accept(h, h->balpha, next);
+      return batch_backtrack(h, h->bk);
+    case kBLloyd:
+      h->n_evals++;
+      if (!(h->tF <= h->F + lloyd_allowance(h) * fabs(h->F))) {
+        h->bstate = kBDone;
+        return SCVT_E_LINESEARCH;
+      }
+      h->n_lloyd_fallback++;
+      return batch_accept(h, 1.0, next);
+    default:
+      return SCVT_E_INVALID;
+  }
+}
+
+void batch_info(scvt_handle* h, scvt_info* info, int status) { fill_info(h, info, status); }
+
+void batch_destroy(scvt_handle* h) { destroy(h); }
+
+}  // namespace scvt
 
 // =============================================================== C ABI ====
 extern "C" {

@@ -40,11 +40,17 @@ hipError_t launch_fill_gamma(double* p, int64_t count, const double* dscal, int 
 }
 
 // trial point: Zt = normalize(Z + alpha q) (q == nullptr: normalize Z)
-__global__ void k_normalize_trial(const double* __restrict__ Z, const double* __restrict__ q,
-                                  double alpha, double* __restrict__ Zt, int64_t n) {
+template <class P>
+__global__ void k_normalize_trial(P p) {
 #pragma clang fp contract(off)
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (p.idle()) return;
+  const NormArgs& a = p.args();
+  const double* __restrict__ Z = a.Z;
+  const double* __restrict__ q = a.q;
+  double* __restrict__ Zt = a.Zt;
+  const double alpha = a.alpha;
+  int64_t i = (int64_t)p.bx() * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
   V3 z = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
   // z + alpha q with one rounding per operation, then z / |z|
   if (q) z = z + alpha * V3{q[3 * i], q[3 * i + 1], q[3 * i + 2]};
@@ -54,9 +60,17 @@ __global__ void k_normalize_trial(const double* __restrict__ Z, const double* __
   Zt[3 * i + 2] = w.z;
 }
 
+int normalize_grid(int64_t n) { return (int)((n + 255) / 256); }
+
 hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha, double* Zt,
                                   int64_t n, hipStream_t s) {
-  k_normalize_trial<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Z, q, alpha, Zt, n);
+  const NormArgs a = {Z, q, alpha, Zt, n};
+  k_normalize_trial<<<(unsigned)normalize_grid(n), 256, 0, s>>>(One<NormArgs>{a});
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize_trial_many(const Seg<NormArgs>& g, hipStream_t s) {
+  k_normalize_trial<<<dim3(g.maxnb, g.nseg), 256, 0, s>>>(Many<NormArgs>{g.tab, g.nb});
   return hipGetLastError();
 }
 
@@ -129,14 +143,22 @@ __device__ inline void generator_cells(const double* __restrict__ Z, int64_t i, 
   for (; k < 3; k++) out[k] = -1;
 }
 
-__global__ __launch_bounds__(kBucketBlock) void k_grid_count(
-    const double* __restrict__ Z, int64_t n, GridP g, const int32_t* __restrict__ order_prev,
-    int32_t* __restrict__ cnt_tot, int32_t* __restrict__ cnt_home, int32_t* __restrict__ cell3,
-    int32_t* __restrict__ clear) {
+template <class P>
+__global__ __launch_bounds__(kBucketBlock) void k_grid_count(P p) {
+  if (p.idle()) return;
+  const GridBuildArgs& a = p.args();
+  const double* __restrict__ Z = a.Z;
+  const int64_t n = a.n;
+  const GridP& g = a.gb.g;
+  const int32_t* __restrict__ order_prev = a.gb.order_prev;
+  int32_t* __restrict__ cnt_tot = a.gb.cnt_tot;
+  int32_t* __restrict__ cnt_home = a.gb.cnt_home;
+  int32_t* __restrict__ cell3 = a.gb.cell3;
+  int32_t* __restrict__ clear = a.clear;
   __shared__ BucketLds L;
-  if (clear && blockIdx.x == 0 && threadIdx.x < 8) clear[threadIdx.x] = 0;
+  if (clear && p.bx() == 0 && threadIdx.x < 8) clear[threadIdx.x] = 0;
   bucket_init(L);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)p.bx() * blockDim.x + threadIdx.x;
   if (t < n) {
     const int64_t i = order_prev[t];
     int32_t c[3];
@@ -181,10 +203,16 @@ __device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
 }
 
 // pass 1: per-tile sums of both arrays
-__global__ void k_scan_tiles(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
-                             int64_t m, int32_t* __restrict__ sums) {
+template <class P>
+__global__ void k_scan_tiles(P p) {
+  if (p.idle()) return;
+  const ScanArgs& A = p.args();
+  const int32_t* __restrict__ a = A.a;
+  const int32_t* __restrict__ b = A.b;
+  const int64_t m = A.m;
+  int32_t* __restrict__ sums = A.sums;
   __shared__ int sh[kScanBlock];
-  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t base = (int64_t)p.bx() * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int sa = 0, sb = 0;
   for (int k = 0; k < kScanItems; k++) {
     int64_t t = base + k;
@@ -195,13 +223,17 @@ __global__ void k_scan_tiles(const int32_t* __restrict__ a, const int32_t* __res
   }
   int tot;
   block_exclusive_scan(sa, sh, tot);
-  if (threadIdx.x == 0) sums[2 * blockIdx.x] = tot;
+  if (threadIdx.x == 0) sums[2 * p.bx()] = tot;
   block_exclusive_scan(sb, sh, tot);
-  if (threadIdx.x == 0) sums[2 * blockIdx.x + 1] = tot;
+  if (threadIdx.x == 0) sums[2 * p.bx() + 1] = tot;
 }
 
 // pass 2: exclusive scan of the tile sums by one block (loops over chunks)
-__global__ void k_scan_sums(int32_t* sums, int64_t ntiles) {
+template <class P>
+__global__ void k_scan_sums(P p) {
+  if (p.idle()) return;
+  int32_t* sums = p.args().sums;
+  const int64_t ntiles = p.args().ntiles;
   __shared__ int sh[kScanBlock];
   int carry_a = 0, carry_b = 0;
   for (int64_t c0 = 0; c0 < ntiles; c0 += kScanBlock) {
@@ -221,11 +253,18 @@ __global__ void k_scan_sums(int32_t* sums, int64_t ntiles) {
 }
 
 // pass 3: scan inside each tile, add the tile offset; element m gets the total
-__global__ void k_scan_apply(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
-                             int64_t m, const int32_t* __restrict__ sums,
-                             int32_t* __restrict__ oa, int32_t* __restrict__ ob) {
+template <class P>
+__global__ void k_scan_apply(P p) {
+  if (p.idle()) return;
+  const ScanArgs& A = p.args();
+  const int32_t* __restrict__ a = A.a;
+  const int32_t* __restrict__ b = A.b;
+  const int64_t m = A.m;
+  const int32_t* __restrict__ sums = A.sums;
+  int32_t* __restrict__ oa = A.oa;
+  int32_t* __restrict__ ob = A.ob;
   __shared__ int sh[kScanBlock];
-  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t base = (int64_t)p.bx() * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int va[kScanItems], vb[kScanItems];
   int sa = 0, sb = 0;
   for (int k = 0; k < kScanItems; k++) {
@@ -236,8 +275,8 @@ __global__ void k_scan_apply(const int32_t* __restrict__ a, const int32_t* __res
     sb += vb[k];
   }
   int tot;
-  int ea = block_exclusive_scan(sa, sh, tot) + sums[2 * blockIdx.x];
-  int eb = block_exclusive_scan(sb, sh, tot) + sums[2 * blockIdx.x + 1];
+  int ea = block_exclusive_scan(sa, sh, tot) + sums[2 * p.bx()];
+  int eb = block_exclusive_scan(sb, sh, tot) + sums[2 * p.bx() + 1];
   for (int k = 0; k < kScanItems; k++) {
     int64_t t = base + k;
     if (t <= m) {
@@ -249,15 +288,25 @@ __global__ void k_scan_apply(const int32_t* __restrict__ a, const int32_t* __res
   }
 }
 
-__global__ __launch_bounds__(kBucketBlock) void k_grid_scatter(
-    const double* __restrict__ Z, int64_t n, const int32_t* __restrict__ order_prev,
-    const int32_t* __restrict__ cell3, const int32_t* __restrict__ start_tot,
-    const int32_t* __restrict__ start_home, int32_t* cnt_tot, int32_t* cnt_home,
-    Entry* __restrict__ entries, int64_t cap, int32_t* __restrict__ order,
-    int32_t* overflow) {
+template <class P>
+__global__ __launch_bounds__(kBucketBlock) void k_grid_scatter(P p) {
+  if (p.idle()) return;
+  const GridBuildArgs& a = p.args();
+  const double* __restrict__ Z = a.Z;
+  const int64_t n = a.n;
+  const int32_t* __restrict__ order_prev = a.gb.order_prev;
+  const int32_t* __restrict__ cell3 = a.gb.cell3;
+  const int32_t* __restrict__ start_tot = a.gb.start_tot;
+  const int32_t* __restrict__ start_home = a.gb.start_home;
+  int32_t* cnt_tot = a.gb.cnt_tot;
+  int32_t* cnt_home = a.gb.cnt_home;
+  Entry* __restrict__ entries = a.gb.entries;
+  const int64_t cap = a.gb.cap_entries;
+  int32_t* __restrict__ order = a.gb.order;
+  int32_t* overflow = a.gb.overflow;
   __shared__ BucketLds L;
   bucket_init(L);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)p.bx() * blockDim.x + threadIdx.x;
   const bool valid = t < n;
   const int64_t i = valid ? order_prev[t] : 0;
   int32_t c[3] = {-1, -1, -1};
@@ -328,31 +377,50 @@ hipError_t launch_centroid(const double* mu, const double* m, double* out, int64
   return hipGetLastError();
 }
 
+int64_t scan_tiles(int64_t m) { return (m + 1 + kScanTile - 1) / kScanTile; }
+
 hipError_t launch_scan_pair(const int32_t* a, const int32_t* b, int64_t m, int32_t* tmp,
                             int32_t* oa, int32_t* ob, hipStream_t s) {
-  int64_t ntiles = (m + 1 + kScanTile - 1) / kScanTile;
-  k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, s>>>(a, b, m, tmp);
-  k_scan_sums<<<1, kScanBlock, 0, s>>>(tmp, ntiles);
-  k_scan_apply<<<(unsigned)ntiles, kScanBlock, 0, s>>>(a, b, m, tmp, oa, ob);
+  const int64_t ntiles = scan_tiles(m);
+  const ScanArgs sa = {a, b, m, tmp, oa, ob, ntiles};
+  k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, s>>>(One<ScanArgs>{sa});
+  k_scan_sums<<<1, kScanBlock, 0, s>>>(One<ScanArgs>{sa});
+  k_scan_apply<<<(unsigned)ntiles, kScanBlock, 0, s>>>(One<ScanArgs>{sa});
   return hipGetLastError();
 }
 
 int64_t scan_tmp_ints(int64_t m) { return 2 * ((m + 1 + kScanTile - 1) / kScanTile + 1); }
 
+int bucket_grid(int64_t n) { return (int)((n + kBucketBlock - 1) / kBucketBlock); }
+
+ScanArgs grid_scan_args(const GridBufs& gb) {
+  const int64_t m = gb.g.ncells;
+  return ScanArgs{gb.cnt_tot, gb.cnt_home, m, gb.scan_tmp, gb.start_tot, gb.start_home,
+                  scan_tiles(m)};
+}
+
 hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, int32_t* clear,
                              hipStream_t s) {
-  const int64_t m = gb.g.ncells;
-  unsigned nb = (unsigned)((n + kBucketBlock - 1) / kBucketBlock);
-  k_grid_count<<<nb, kBucketBlock, 0, s>>>(Z, n, gb.g, gb.order_prev, gb.cnt_tot, gb.cnt_home,
-                                           gb.cell3, clear);
-  int64_t ntiles = (m + 1 + kScanTile - 1) / kScanTile;
-  k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, s>>>(gb.cnt_tot, gb.cnt_home, m, gb.scan_tmp);
-  k_scan_sums<<<1, kScanBlock, 0, s>>>(gb.scan_tmp, ntiles);
-  k_scan_apply<<<(unsigned)ntiles, kScanBlock, 0, s>>>(gb.cnt_tot, gb.cnt_home, m, gb.scan_tmp,
-                                                      gb.start_tot, gb.start_home);
-  k_grid_scatter<<<nb, kBucketBlock, 0, s>>>(Z, n, gb.order_prev, gb.cell3, gb.start_tot,
-                                             gb.start_home, gb.cnt_tot, gb.cnt_home, gb.entries,
-                                             gb.cap_entries, gb.order, gb.overflow);
+  const GridBuildArgs a = {Z, n, gb, clear};
+  const ScanArgs sa = grid_scan_args(gb);
+  const unsigned nb = (unsigned)bucket_grid(n);
+  k_grid_count<<<nb, kBucketBlock, 0, s>>>(One<GridBuildArgs>{a});
+  k_scan_tiles<<<(unsigned)sa.ntiles, kScanBlock, 0, s>>>(One<ScanArgs>{sa});
+  k_scan_sums<<<1, kScanBlock, 0, s>>>(One<ScanArgs>{sa});
+  k_scan_apply<<<(unsigned)sa.ntiles, kScanBlock, 0, s>>>(One<ScanArgs>{sa});
+  k_grid_scatter<<<nb, kBucketBlock, 0, s>>>(One<GridBuildArgs>{a});
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_build_many(const Seg<GridBuildArgs>& g, const Seg<ScanArgs>& tiles,
+                                  const Seg<ScanArgs>& one, hipStream_t s) {
+  k_grid_count<<<dim3(g.maxnb, g.nseg), kBucketBlock, 0, s>>>(Many<GridBuildArgs>{g.tab, g.nb});
+  k_scan_tiles<<<dim3(tiles.maxnb, tiles.nseg), kScanBlock, 0, s>>>(
+      Many<ScanArgs>{tiles.tab, tiles.nb});
+  k_scan_sums<<<dim3(one.maxnb, one.nseg), kScanBlock, 0, s>>>(Many<ScanArgs>{one.tab, one.nb});
+  k_scan_apply<<<dim3(tiles.maxnb, tiles.nseg), kScanBlock, 0, s>>>(
+      Many<ScanArgs>{tiles.tab, tiles.nb});
+  k_grid_scatter<<<dim3(g.maxnb, g.nseg), kBucketBlock, 0, s>>>(Many<GridBuildArgs>{g.tab, g.nb});
   return hipGetLastError();
 }
 

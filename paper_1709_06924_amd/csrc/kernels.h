@@ -7,6 +7,39 @@
 
 namespace scvt {
 
+// Where a kernel takes its arguments and block numbers from.  One: one
+// problem per launch, the arguments by value.  Many: one launch for a batch
+// of problems (the serving loop's segmented launches): blockIdx.y picks the
+// problem, whose arguments and own grid size sit in device tables; blocks
+// beyond that problem's grid exit at once.  A kernel body sees the same
+// arguments and block numbers either way, so a problem's results do not
+// depend on the batch it runs in.
+template <class A>
+struct One {
+  A a;
+  __device__ const A& args() const { return a; }
+  __device__ int bx() const { return (int)blockIdx.x; }
+  __device__ int gx() const { return (int)gridDim.x; }
+  __device__ bool idle() const { return false; }
+};
+template <class A>
+struct Many {
+  const A* tab;       // per problem
+  const int32_t* nb;  // each problem's own grid size
+  __device__ const A& args() const { return tab[blockIdx.y]; }
+  __device__ int bx() const { return (int)blockIdx.x; }
+  __device__ int gx() const { return nb[blockIdx.y]; }
+  __device__ bool idle() const { return (int)blockIdx.x >= nb[blockIdx.y]; }
+};
+
+// A segmented launch's device tables: nseg problems, the largest grid maxnb.
+template <class A>
+struct Seg {
+  const A* tab;
+  const int32_t* nb;
+  int nseg, maxnb;
+};
+
 constexpr int kVmax = 32;          // max Voronoi edges per cell kept in debug output
 constexpr int kWinMax = 63;        // max window side in cells
 constexpr int kFbPolyMax = 64;     // polygon capacity of the fallback clipper
@@ -72,7 +105,34 @@ struct CellArgs {
   int32_t* tier_list[2];  // n each: cells for the list passes of the certified path
   Counters* ctr;
   double r_default;  // initial search radius when no previous one is known
+  int kmax;          // > 0: at most kmax candidates per cell in the certified passes
 };
+
+// arguments of the trial normalisation, the grid build and the scans
+struct NormArgs {
+  const double* Z;
+  const double* q;  // null: normalise Z itself
+  double alpha;
+  double* Zt;
+  int64_t n;
+};
+struct GridBuildArgs {
+  const double* Z;
+  int64_t n;
+  GridBufs gb;
+  int32_t* clear;  // 8 ints zeroed by the first kernel, or null
+};
+struct ScanArgs {  // exclusive scans of a and b (m entries) into oa, ob
+  const int32_t *a, *b;
+  int64_t m;
+  int32_t* sums;  // tile sums (scratch)
+  int32_t *oa, *ob;
+  int64_t ntiles;
+};
+int normalize_grid(int64_t n);
+int bucket_grid(int64_t n);
+int64_t scan_tiles(int64_t m);
+ScanArgs grid_scan_args(const GridBufs& gb);
 
 // ---- launch wrappers (return hipError_t) ----
 hipError_t launch_normalize_trial(const double* Z, const double* q, double alpha, double* Zt,
@@ -115,5 +175,26 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
 // pair), or 1 when r_at < 0
 hipError_t launch_fill_gamma(double* p, int64_t count, const double* dscal, int r_at, int yy_at,
                              hipStream_t s);
+
+// ---- segmented launches: the same kernels over a batch of problems ----
+// grid sizes of a single problem's launches (a batch uses them per problem)
+int cells_main_grid(int64_t n);
+int cells_tier_grid(int64_t n, int tier);
+int cells_fallback_grid(int64_t n, int all);
+int fb_all_grid(int64_t n);
+int quad_grid(int64_t n);
+hipError_t launch_normalize_trial_many(const Seg<NormArgs>& g, hipStream_t s);
+// grid build: count and scatter over g, the scans' tiles over `tiles`, one
+// block per problem over `one` (the same ScanArgs table)
+hipError_t launch_grid_build_many(const Seg<GridBuildArgs>& g, const Seg<ScanArgs>& tiles,
+                                  const Seg<ScanArgs>& one, hipStream_t s);
+// main pass, the two list passes, the small problems' full lists (max_all 0:
+// none) and the fallback clipper, each with its own per-problem grid sizes
+hipError_t launch_cells_many(const CellArgs* tab, const int32_t* nb_main, int max_main,
+                             const int32_t* nb_t0, int max_t0, const int32_t* nb_t1, int max_t1,
+                             const int32_t* nb_all, int max_all, const int32_t* nb_fb, int max_fb,
+                             int nseg, hipStream_t s);
+// every problem of the batch with density variant var and precision mixed
+hipError_t launch_quad_many(const Seg<CellArgs>& g, int var, int mixed, hipStream_t s);
 
 }  // namespace scvt

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kernels.h"
+
 namespace scvt {
 
 // One two-loop pass: optionally finish the previous pass's dot product
@@ -150,5 +152,15 @@ hipError_t launch_eval_reduce(const EvalRedArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 int reduce_grid(int64_t count);  // blocks the streaming kernels use for count items
 int reduce_grid_max();
+
+// segmented launches: the same kernels over a batch of problems (vw: 2 when
+// the problems' 3n is even, as the single launch chooses)
+hipError_t launch_push_ext_many(const Seg<PushExtArgs>& g, int vw, hipStream_t s);
+hipError_t launch_hist_q0_many(const Seg<HistPassArgs>& g, int vw, hipStream_t s);
+hipError_t launch_hist_dir_many(const Seg<HistPassArgs>& g, int vw, hipStream_t s);
+hipError_t launch_hist_fin_many(const Seg<HistFinArgs>& g, hipStream_t s);
+hipError_t launch_fin_chain_many(const Seg<FinChain>& g, hipStream_t s);
+hipError_t launch_eval_reduce_many(const Seg<EvalRedArgs>& g, hipStream_t s);
+hipError_t launch_finalize_many(const Seg<FinalizeArgs>& g, hipStream_t s);
 
 }  // namespace scvt

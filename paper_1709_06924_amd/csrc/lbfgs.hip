@@ -116,11 +116,14 @@ __global__ __launch_bounds__(kRedBlock) void k_push(PushArgs a) {
 // ------------------------------------------------------ evaluation reduce
 // Per generator the gradient, preconditioner and Lloyd step from mu (section
 // 3.1), then partials of F = sum e_i, max |l_ik|, sum |g_i|^2, min mu_i . z_i
-__global__ __launch_bounds__(kRedBlock) void k_eval_reduce(EvalRedArgs a) {
+template <class P>
+__global__ __launch_bounds__(kRedBlock) void k_eval_reduce(P p) {
+  if (p.idle()) return;
+  const EvalRedArgs& a = p.args();
   __shared__ double sh[kRedBlock];
   double F = 0.0, lmax = 0.0, gg = 0.0, mzmin = 1e300;
   const int n = (int)a.n;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int i = p.bx() * blockDim.x + threadIdx.x; i < n; i += p.gx() * blockDim.x) {
     const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
     const V3 mu = V3{a.mu[3 * i], a.mu[3 * i + 1], a.mu[3 * i + 2]};
     const double e = a.e[i];
@@ -143,14 +146,17 @@ __global__ __launch_bounds__(kRedBlock) void k_eval_reduce(EvalRedArgs a) {
   double b0 = block_sum(F, sh), b1 = block_max(lmax, sh), b2 = block_sum(gg, sh),
          b3 = block_min(mzmin, sh);
   if (threadIdx.x == 0) {
-    a.partials[4 * blockIdx.x] = b0;
-    a.partials[4 * blockIdx.x + 1] = b1;
-    a.partials[4 * blockIdx.x + 2] = b2;
-    a.partials[4 * blockIdx.x + 3] = b3;
+    a.partials[4 * p.bx()] = b0;
+    a.partials[4 * p.bx() + 1] = b1;
+    a.partials[4 * p.bx() + 2] = b2;
+    a.partials[4 * p.bx() + 3] = b3;
   }
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_finalize(FinalizeArgs a) {
+template <class P>
+__global__ __launch_bounds__(kRedBlock) void k_finalize(P p) {
+  if (p.idle()) return;
+  const FinalizeArgs& a = p.args();
   __shared__ double sh[kRedBlock];
   for (int v = 0; v < a.nvals; v++) {
     const int op = a.op[v];
@@ -215,14 +221,16 @@ __device__ inline void st(double* __restrict__ p, int u, const double (&o)[VW]) 
   }
 }
 
-template <int VW>
-__global__ __launch_bounds__(kRedBlock) void k_push_ext(PushExtArgs a) {
+template <int VW, class P>
+__global__ __launch_bounds__(kRedBlock) void k_push_ext(P p) {
+  if (p.idle()) return;
+  const PushExtArgs& a = p.args();
   double acc[kHVals];
 #pragma unroll
   for (int v = 0; v < kHVals; v++) acc[v] = 0.0;
   const int c = a.c;
   const int nu = (int)(a.n3 / VW);
-  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+  for (int u = p.bx() * blockDim.x + threadIdx.x; u < nu; u += p.gx() * blockDim.x) {
     double gt[VW], zt[VW], z[VW], g[VW], s[VW], y[VW];
     ld<VW>(a.gt, u, gt);
     ld<VW>(a.Zt, u, zt);
@@ -255,7 +263,7 @@ __global__ __launch_bounds__(kRedBlock) void k_push_ext(PushExtArgs a) {
       }
     }
   }
-  block_partials<kHVals>(acc, 4 + 2 * c, a.partials + (size_t)blockIdx.x * (4 + 2 * c));
+  block_partials<kHVals>(acc, 4 + 2 * c, a.partials + (size_t)p.bx() * (4 + 2 * c));
 }
 
 // the same sums as k_push_ext forms for s_j . g and s_j . y (same element
@@ -285,8 +293,10 @@ __global__ __launch_bounds__(kRedBlock) void k_multi_dot(MultiDotArgs a) {
 
 // r = h (.) (-g - sum_k a_k y_k), newest pair first as in the backward loop;
 // partials of y_j . r
-template <int VW>
-__global__ __launch_bounds__(kRedBlock) void k_hist_q0(HistPassArgs a) {
+template <int VW, class P>
+__global__ __launch_bounds__(kRedBlock) void k_hist_q0(P p) {
+  if (p.idle()) return;
+  const HistPassArgs& a = p.args();
   const int c = a.c;
   double coef[kHmax], acc[kHmax];
 #pragma unroll
@@ -295,7 +305,7 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_q0(HistPassArgs a) {
     acc[j] = 0.0;
   }
   const int nu = (int)(a.n3 / VW);
-  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+  for (int u = p.bx() * blockDim.x + threadIdx.x; u < nu; u += p.gx() * blockDim.x) {
     double yv[kHmax][VW];
     double q[VW];
     ld<VW>(a.g, u, q);
@@ -320,20 +330,22 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_q0(HistPassArgs a) {
         for (int e = 0; e < VW; e++) acc[j] = fma(yv[j][e], r[e], acc[j]);
       }
   }
-  if (c > 0) block_partials<kHmax>(acc, c, a.partials + (size_t)blockIdx.x * c);
+  if (c > 0) block_partials<kHmax>(acc, c, a.partials + (size_t)p.bx() * c);
 }
 
 // q = r + sum_k c_k s_k, oldest pair first as in the forward loop; partials
 // of g . q
-template <int VW>
-__global__ __launch_bounds__(kRedBlock) void k_hist_dir(HistPassArgs a) {
+template <int VW, class P>
+__global__ __launch_bounds__(kRedBlock) void k_hist_dir(P p) {
+  if (p.idle()) return;
+  const HistPassArgs& a = p.args();
   const int c = a.c;
   double coef[kHmax];
 #pragma unroll
   for (int j = 0; j < kHmax; j++) coef[j] = j < c ? a.coef[j] : 0.0;
   double acc[1] = {0.0};
   const int nu = (int)(a.n3 / VW);
-  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+  for (int u = p.bx() * blockDim.x + threadIdx.x; u < nu; u += p.gx() * blockDim.x) {
     double q[VW], g[VW];
     ld<VW>(a.qin, u, q);
     ld<VW>(a.g, u, g);
@@ -349,7 +361,7 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_dir(HistPassArgs a) {
 #pragma unroll
     for (int e = 0; e < VW; e++) acc[0] = fma(g[e], q[e], acc[0]);
   }
-  block_partials<1>(acc, 1, a.partials + blockIdx.x);
+  block_partials<1>(acc, 1, a.partials + p.bx());
 }
 
 // One block: sums the block partials of each value in block order (wave w
@@ -433,11 +445,17 @@ __device__ void hist_fin(const HistFinArgs& a) {
   }
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_hist_fin(HistFinArgs a) { hist_fin(a); }
+template <class P>
+__global__ __launch_bounds__(kRedBlock) void k_hist_fin(P p) {
+  if (!p.idle()) hist_fin(p.args());
+}
 
 // several fin steps in one launch, in order (e.g. a push's scalars, then the
 // next direction's backward recursion, which reads them)
-__global__ __launch_bounds__(kRedBlock) void k_fin_chain(FinChain f) {
+template <class P>
+__global__ __launch_bounds__(kRedBlock) void k_fin_chain(P p) {
+  if (p.idle()) return;
+  const FinChain& f = p.args();
   for (int k = 0; k < f.n; k++) {
     hist_fin(f.step[k]);
     __syncthreads();
@@ -455,9 +473,9 @@ int hist_grid_max() { return kHGrid * kHVals; }
 hipError_t launch_push_ext(const PushExtArgs& a, hipStream_t s) {
   const int nb = hist_grid(a.n3);
   if (a.n3 % 2 == 0)
-    k_push_ext<2><<<nb, kRedBlock, 0, s>>>(a);
+    k_push_ext<2><<<nb, kRedBlock, 0, s>>>(One<PushExtArgs>{a});
   else
-    k_push_ext<1><<<nb, kRedBlock, 0, s>>>(a);
+    k_push_ext<1><<<nb, kRedBlock, 0, s>>>(One<PushExtArgs>{a});
   return hipGetLastError();
 }
 hipError_t launch_multi_dot(const MultiDotArgs& a, hipStream_t s) {
@@ -471,25 +489,25 @@ hipError_t launch_multi_dot(const MultiDotArgs& a, hipStream_t s) {
 hipError_t launch_hist_q0(const HistPassArgs& a, hipStream_t s) {
   const int nb = hist_grid(a.n3);
   if (a.n3 % 2 == 0)
-    k_hist_q0<2><<<nb, kRedBlock, 0, s>>>(a);
+    k_hist_q0<2><<<nb, kRedBlock, 0, s>>>(One<HistPassArgs>{a});
   else
-    k_hist_q0<1><<<nb, kRedBlock, 0, s>>>(a);
+    k_hist_q0<1><<<nb, kRedBlock, 0, s>>>(One<HistPassArgs>{a});
   return hipGetLastError();
 }
 hipError_t launch_hist_dir(const HistPassArgs& a, hipStream_t s) {
   const int nb = hist_grid(a.n3);
   if (a.n3 % 2 == 0)
-    k_hist_dir<2><<<nb, kRedBlock, 0, s>>>(a);
+    k_hist_dir<2><<<nb, kRedBlock, 0, s>>>(One<HistPassArgs>{a});
   else
-    k_hist_dir<1><<<nb, kRedBlock, 0, s>>>(a);
+    k_hist_dir<1><<<nb, kRedBlock, 0, s>>>(One<HistPassArgs>{a});
   return hipGetLastError();
 }
 hipError_t launch_hist_fin(const HistFinArgs& a, hipStream_t s) {
-  k_hist_fin<<<1, kRedBlock, 0, s>>>(a);
+  k_hist_fin<<<1, kRedBlock, 0, s>>>(One<HistFinArgs>{a});
   return hipGetLastError();
 }
 hipError_t launch_fin_chain(const FinChain& f, hipStream_t s) {
-  k_fin_chain<<<1, kRedBlock, 0, s>>>(f);
+  k_fin_chain<<<1, kRedBlock, 0, s>>>(One<FinChain>{f});
   return hipGetLastError();
 }
 
@@ -509,13 +527,52 @@ hipError_t launch_push(const PushArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_eval_reduce(const EvalRedArgs& a, hipStream_t s) {
-  k_eval_reduce<<<reduce_grid(a.n), kRedBlock, 0, s>>>(a);
+  k_eval_reduce<<<reduce_grid(a.n), kRedBlock, 0, s>>>(One<EvalRedArgs>{a});
   return hipGetLastError();
 }
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
-  k_finalize<<<1, kRedBlock, 0, s>>>(a);
+  k_finalize<<<1, kRedBlock, 0, s>>>(One<FinalizeArgs>{a});
   return hipGetLastError();
 }
 int reduce_grid_max() { return kRedGrid; }
+
+// ---- segmented launches (one per kernel for a batch of problems) ----
+hipError_t launch_push_ext_many(const Seg<PushExtArgs>& g, int vw, hipStream_t s) {
+  if (vw == 2)
+    k_push_ext<2><<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<PushExtArgs>{g.tab, g.nb});
+  else
+    k_push_ext<1><<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<PushExtArgs>{g.tab, g.nb});
+  return hipGetLastError();
+}
+hipError_t launch_hist_q0_many(const Seg<HistPassArgs>& g, int vw, hipStream_t s) {
+  if (vw == 2)
+    k_hist_q0<2><<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<HistPassArgs>{g.tab, g.nb});
+  else
+    k_hist_q0<1><<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<HistPassArgs>{g.tab, g.nb});
+  return hipGetLastError();
+}
+hipError_t launch_hist_dir_many(const Seg<HistPassArgs>& g, int vw, hipStream_t s) {
+  if (vw == 2)
+    k_hist_dir<2><<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<HistPassArgs>{g.tab, g.nb});
+  else
+    k_hist_dir<1><<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<HistPassArgs>{g.tab, g.nb});
+  return hipGetLastError();
+}
+hipError_t launch_hist_fin_many(const Seg<HistFinArgs>& g, hipStream_t s) {
+  k_hist_fin<<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<HistFinArgs>{g.tab, g.nb});
+  return hipGetLastError();
+}
+hipError_t launch_fin_chain_many(const Seg<FinChain>& g, hipStream_t s) {
+  k_fin_chain<<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<FinChain>{g.tab, g.nb});
+  return hipGetLastError();
+}
+hipError_t launch_eval_reduce_many(const Seg<EvalRedArgs>& g, hipStream_t s) {
+  k_eval_reduce<<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<EvalRedArgs>{g.tab, g.nb});
+  return hipGetLastError();
+}
+hipError_t launch_finalize_many(const Seg<FinalizeArgs>& g, hipStream_t s) {
+  k_finalize<<<dim3(g.maxnb, g.nseg), kRedBlock, 0, s>>>(Many<FinalizeArgs>{g.tab, g.nb});
+  return hipGetLastError();
+}
 
 }  // namespace scvt

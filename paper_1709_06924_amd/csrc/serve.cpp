@@ -1,17 +1,26 @@
-// Serving engine: a persistent request loop over the solver.
+// Serving engine: continuous batching of SCVT solves with segmented launches.
 //
 // Requests (generators, density, tolerance, iteration cap) are submitted at
-// any time.  Admission: a request enters when a slot is free and its device
-// footprint fits in what the budget has left (first come, first served; a
-// request larger than the whole budget is rejected at submission).  Every
-// admitted request gets its own HIP stream and handle -- generators, cells
-// and LBFGS history stay resident in HBM until it finishes -- and is driven
-// by one of the server's host threads, so the kernels of all admitted
-// requests are in flight together on the device.  Finished requests release
-// their slot and memory at once and the next waiting request is admitted:
-// continuous batching at iteration granularity.  All kernels are
-// deterministic, so a request's result does not depend on what else runs.
+// any time.  Admission: a request enters when one of max_slots slots is free
+// and its exact device footprint (scvt_footprint) fits in a free range of
+// the server's arena -- one device allocation of hbm_budget bytes made at
+// creation -- first come, first served; a request larger than the budget is
+// rejected at submission.  An admitted request's generators, cells and LBFGS
+// history live in its arena range until it finishes; nothing is allocated
+// or freed per request.
+//
+// One driver thread runs rounds: every admitted request records the
+// launches of its next evaluation (direction passes, trial point, grid,
+// cells, quadrature, reductions) into the round, and the round issues one
+// launch per kernel for all of them (blockIdx.y = request, round.h), gathers
+// every request's scalars with one copy and synchronises once.  Then each
+// request takes its own decision (Armijo test, history update, stopping
+// test) and the next round begins, with newly admitted requests joining and
+// finished ones leaving at round boundaries: continuous batching at the
+// granularity of one evaluation.  A request's blocks compute exactly what
+// its own single launches would, so its result does not depend on the mix.
 #include <hip/hip_runtime.h>
+#include <string.h>
 
 #include <chrono>
 #include <condition_variable>
@@ -23,6 +32,10 @@
 #include <vector>
 
 #include "../../include/scvt.h"
+#include "engine_batch.h"
+#include "round.h"
+
+using namespace scvt;
 
 namespace {
 
@@ -44,44 +57,83 @@ struct Request {
   int rc = 0;
   scvt_info info{};
   double t_submit = 0, t_start = 0, t_done = 0;
+  // while admitted (driver thread only)
+  size_t off = 0;     // arena range
+  int slot = -1;      // pinned scalars
+  scvt_handle* h = nullptr;
 };
+
+// First-fit ranges of the arena (offsets in bytes, 256-byte aligned).
+struct Arena {
+  std::map<size_t, size_t> free;  // offset -> size
+  bool take(size_t bytes, size_t* off) {
+    for (auto it = free.begin(); it != free.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes, at = it->first + bytes;
+      free.erase(it);
+      if (rest) free[at] = rest;
+      return true;
+    }
+    return false;
+  }
+  void give(size_t off, size_t bytes) {
+    auto it = free.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free.erase(nx);
+    }
+    if (it != free.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free.erase(it);
+      }
+    }
+  }
+};
+
+constexpr size_t kRoundTableBytes = (size_t)4 << 20;  // argument tables of one round
+constexpr int kScalarsPerRequest = 16;                // gathered doubles per request and round
 
 }  // namespace
 
 struct scvt_server {
   size_t budget = 0, used = 0;
-  int max_slots = 1, running = 0;
+  int max_slots = 1;
   int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
   int64_t next_id = 1;
   bool stop = false;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request*> queue;
   std::map<int64_t, Request*> reqs;
-  std::vector<std::thread> workers;
+  std::vector<Request*> active;  // admitted (driver thread; membership under mu)
+  int running = 0;
+  Arena arena;
+  char* arena_base = nullptr;
+  double* pinned = nullptr;  // kBatchPinnedBytes per slot
+  std::vector<int> free_slots;
+  RoundBuffers rb;
+  std::thread driver;
 };
 
 namespace {
 
-void run_request(scvt_server* s, Request* r) {
-  hipSetDevice(s->device);
-  hipStream_t st = nullptr;
-  int rc = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess ? SCVT_OK : SCVT_E_HIP;
-  scvt_handle* h = nullptr;
-  if (!rc) {
-    r->cfg.hip_stream = st;
-    rc = scvt_create(&r->cfg, r->z0.data(), 0, &h);
-  }
-  if (!rc) {
-    rc = scvt_solve(h, r->max_iter, r->tol, &r->info);
+void finish_request(scvt_server* s, Request* r, int rc) {
+  if (r->h) {
+    batch_info(r->h, &r->info, rc);
     if (rc >= 0) {
-      r->z.assign(r->z0.size(), 0.0);
-      int rc2 = scvt_get_generators(h, r->z.data(), 0);
+      r->z.assign(3 * (size_t)r->cfg.n, 0.0);
+      const int rc2 = scvt_get_generators(r->h, r->z.data(), 0);
       if (rc2) rc = rc2;
     }
+    batch_destroy(r->h);
+    r->h = nullptr;
   }
-  if (h) scvt_destroy(h);
-  if (st) hipStreamDestroy(st);
   std::lock_guard<std::mutex> lk(s->mu);
   r->rc = rc;
   r->info.status = rc;
@@ -89,58 +141,150 @@ void run_request(scvt_server* s, Request* r) {
   r->t_done = now_s();
   r->z0.clear();
   r->z0.shrink_to_fit();
+  s->arena.give(r->off, r->footprint);
   s->used -= r->footprint;
+  s->free_slots.push_back(r->slot);
   s->running--;
   s->cv.notify_all();
 }
 
-void worker(scvt_server* s) {
+// admit waiting requests in order while a slot and an arena range are free
+// (called with mu held); returns the admitted ones
+std::vector<Request*> admit(scvt_server* s) {
+  std::vector<Request*> in;
+  while (!s->queue.empty() && !s->free_slots.empty()) {
+    Request* r = s->queue.front();
+    size_t off = 0;
+    if (!s->arena.take(r->footprint, &off)) break;  // first come, first served
+    s->queue.pop_front();
+    r->off = off;
+    r->slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    s->used += r->footprint;
+    s->running++;
+    r->state = kRunning;
+    r->t_start = now_s();
+    in.push_back(r);
+  }
+  return in;
+}
+
+void driver(scvt_server* s) {
+  hipSetDevice(s->device);
+  Round round, next;  // next: launches one round leaves for the following one
   for (;;) {
-    Request* r = nullptr;
+    std::vector<Request*> in;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv.wait(lk, [&] {
-        if (s->stop) return true;
-        if (s->queue.empty() || s->running >= s->max_slots) return false;
-        return s->used + s->queue.front()->footprint <= s->budget;
+        return s->stop || !s->active.empty() || (!s->queue.empty() && !s->free_slots.empty());
       });
-      if (s->stop) return;
-      r = s->queue.front();
-      s->queue.pop_front();
-      s->used += r->footprint;
-      s->running++;
-      r->state = kRunning;
-      r->t_start = now_s();
+      if (s->stop && s->active.empty()) return;
+      if (!s->stop) in = admit(s);
     }
-    run_request(s, r);
+    for (Request* r : in) {
+      const int rc = batch_create(&r->cfg, r->z0.data(), s->arena_base + r->off, r->footprint,
+                                  s->pinned + (size_t)r->slot * (kBatchPinnedBytes / sizeof(double)),
+                                  s->stream, r->max_iter, r->tol, &r->h);
+      if (rc) {
+        if (r->h) batch_destroy(r->h);
+        r->h = nullptr;
+        finish_request(s, r, rc);
+      } else {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->active.push_back(r);
+      }
+    }
+    if (s->active.empty()) continue;
+    // one round: the history pushes the last one left, then every admitted
+    // request's next evaluation
+    std::swap(round, next);
+    next.clear();
+    std::vector<int> plan_rc(s->active.size(), SCVT_OK);
+    for (size_t k = 0; k < s->active.size(); k++) plan_rc[k] = batch_plan(s->active[k]->h, round);
+    const hipError_t e = round_run(round, s->rb, s->stream);
+    round.clear();
+    std::vector<Request*> keep, done;
+    std::vector<int> codes;
+    for (size_t k = 0; k < s->active.size(); k++) {
+      Request* r = s->active[k];
+      const int rc = e != hipSuccess ? SCVT_E_HIP : (plan_rc[k] ? plan_rc[k] : batch_finish(r->h, next));
+      if (rc == SCVT_PENDING) {
+        keep.push_back(r);
+      } else {
+        done.push_back(r);
+        codes.push_back(rc);
+      }
+    }
+    // (a request records launches for the next round only when it goes on:
+    // its last iteration pushes no pair)
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->active = keep;
+    }
+    for (size_t k = 0; k < done.size(); k++) finish_request(s, done[k], codes[k]);
   }
+}
+
+void free_server(scvt_server* s) {
+  if (s->rb.dev) hipFree(s->rb.dev);
+  if (s->rb.host) hipHostFree(s->rb.host);
+  if (s->rb.dscal) hipFree(s->rb.dscal);
+  if (s->rb.hscal) hipHostFree(s->rb.hscal);
+  if (s->pinned) hipHostFree(s->pinned);
+  if (s->arena_base) hipFree(s->arena_base);
+  if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+  delete s;
 }
 
 }  // namespace
 
 extern "C" {
 
-int scvt_server_create(size_t hbm_budget, int max_slots, scvt_server** out) {
-  if (!out || max_slots < 1 || max_slots > 64 || hbm_budget == 0) return SCVT_E_INVALID;
+int scvt_server_create(size_t hbm_budget, int max_slots, void* stream, scvt_server** out) {
+  if (!out || max_slots < 1 || max_slots > 64 || hbm_budget < 256) return SCVT_E_INVALID;
   *out = nullptr;
   scvt_server* s = new (std::nothrow) scvt_server();
   if (!s) return SCVT_E_OOM;
-  s->budget = hbm_budget;
+  s->budget = hbm_budget / 256 * 256;
   s->max_slots = max_slots;
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return SCVT_E_HIP;
   }
+  int rc = SCVT_OK;
+  if (stream) {
+    s->stream = (hipStream_t)stream;
+  } else if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess) {
+    s->own_stream = true;
+  } else {
+    rc = SCVT_E_HIP;
+  }
+  // everything the server will ever use, allocated here
+  if (!rc && hipMalloc((void**)&s->arena_base, s->budget) != hipSuccess) rc = SCVT_E_OOM;
+  if (!rc && hipHostMalloc((void**)&s->pinned, max_slots * kBatchPinnedBytes, hipHostMallocDefault) !=
+                 hipSuccess)
+    rc = SCVT_E_OOM;
+  s->rb.bytes = kRoundTableBytes;
+  s->rb.max_scal = max_slots * kScalarsPerRequest;
+  if (!rc && hipMalloc(&s->rb.dev, s->rb.bytes) != hipSuccess) rc = SCVT_E_OOM;
+  if (!rc && hipHostMalloc(&s->rb.host, s->rb.bytes, hipHostMallocDefault) != hipSuccess)
+    rc = SCVT_E_OOM;
+  if (!rc && hipMalloc((void**)&s->rb.dscal, s->rb.max_scal * sizeof(double)) != hipSuccess)
+    rc = SCVT_E_OOM;
+  if (!rc && hipHostMalloc((void**)&s->rb.hscal, s->rb.max_scal * sizeof(double),
+                           hipHostMallocDefault) != hipSuccess)
+    rc = SCVT_E_OOM;
+  if (rc) {
+    free_server(s);
+    return rc;
+  }
+  s->arena.free[0] = s->budget;
+  for (int k = max_slots - 1; k >= 0; k--) s->free_slots.push_back(k);
   try {
-    for (int k = 0; k < max_slots; k++) s->workers.emplace_back(worker, s);
+    s->driver = std::thread(driver, s);
   } catch (...) {
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->stop = true;
-    }
-    s->cv.notify_all();
-    for (auto& t : s->workers) t.join();
-    delete s;
+    free_server(s);
     return SCVT_E_OOM;
   }
   *out = s;
@@ -150,8 +294,11 @@ int scvt_server_create(size_t hbm_budget, int max_slots, scvt_server** out) {
 int scvt_server_submit(scvt_server* s, const scvt_config* cfg, const double* z0, double tol,
                        int64_t max_iter, int64_t* req_id) {
   if (!s || !cfg || !z0 || !req_id || cfg->n < 4 || max_iter < 0) return SCVT_E_INVALID;
+  if (cfg->method != SCVT_METHOD_PLBFGS || cfg->m_hist > 16) return SCVT_E_INVALID;
+  scvt_config c = *cfg;
+  c.keep_cells = 0;
   size_t fp = 0;
-  int rc = scvt_footprint(cfg, &fp);
+  int rc = scvt_footprint(&c, &fp);
   if (rc) return rc;
   if (fp > s->budget) return SCVT_E_OOM;
   Request* r = new (std::nothrow) Request();
@@ -162,8 +309,7 @@ int scvt_server_submit(scvt_server* s, const scvt_config* cfg, const double* z0,
     delete r;
     return SCVT_E_OOM;
   }
-  r->cfg = *cfg;
-  r->cfg.keep_cells = 0;
+  r->cfg = c;
   r->tol = tol;
   r->max_iter = max_iter;
   r->footprint = fp;
@@ -193,8 +339,7 @@ int scvt_server_poll(scvt_server* s, int64_t req_id, double* z_out, scvt_info* i
     times[1] = r->t_start;
     times[2] = r->t_done;
   }
-  if (z_out && r->state == kDone)
-    for (size_t k = 0; k < r->z.size(); k++) z_out[k] = r->z[k];
+  if (z_out && r->state == kDone) memcpy(z_out, r->z.data(), r->z.size() * sizeof(double));
   return r->rc;
 }
 
@@ -222,17 +367,17 @@ int scvt_server_stats(scvt_server* s, int64_t* waiting, int64_t* running, size_t
 void scvt_server_destroy(scvt_server* s) {
   if (!s) return;
   {
-    std::unique_lock<std::mutex> lk(s->mu);
+    std::lock_guard<std::mutex> lk(s->mu);
     // waiting requests are dropped; running ones finish first
     for (Request* r : s->queue) r->state = kFailed;
     s->queue.clear();
-    s->cv.wait(lk, [&] { return s->running == 0; });
     s->stop = true;
   }
   s->cv.notify_all();
-  for (auto& t : s->workers) t.join();
+  if (s->driver.joinable()) s->driver.join();
+  hipStreamSynchronize(s->stream);
   for (auto& kv : s->reqs) delete kv.second;
-  delete s;
+  free_server(s);
 }
 
 }  // extern "C"

@@ -132,7 +132,8 @@ def serving_stream(seed=4, rate=20.0, count=200, n_lo=10242, n_hi=655362):
 
 
 def platonic(name):
-    """Vertices of the tetrahedron, octahedron or icosahedron on the sphere."""
+    """Vertices of a Platonic solid (tetra, octa, icosa, cube, dodeca) or of
+    the icosidodecahedron, on the unit sphere."""
     if name == "tetra":
         P = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=float)
     elif name == "octa":
@@ -147,6 +148,23 @@ def platonic(name):
         P = np.array(P, dtype=float)
     elif name == "cube":
         P = np.array([[a, b, c] for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)], dtype=float)
+    elif name == "dodeca":  # 20 vertices; its pentagonal faces put 5 points on a circle
+        p = (1 + 5 ** 0.5) / 2
+        P = [[a, b, c] for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)]
+        for a in (-1, 1):
+            for b in (-1, 1):
+                P += [[0, a / p, b * p], [a / p, b * p, 0], [b * p, 0, a / p]]
+        P = np.array(P, dtype=float)
+    elif name == "icosidodeca":  # 30 vertices (edge midpoints of the icosahedron)
+        p = (1 + 5 ** 0.5) / 2
+        P = []
+        for a in (-1, 1):
+            P += [[0, 0, a * p], [0, a * p, 0], [a * p, 0, 0]]
+            for b in (-1, 1):
+                for c in (-1, 1):
+                    v = [a * 0.5, b * p / 2, c * p * p / 2]
+                    P += [v, [v[2], v[0], v[1]], [v[1], v[2], v[0]]]
+        P = np.array(P, dtype=float)
     else:
         raise ValueError(name)
     return np.ascontiguousarray(P / np.linalg.norm(P, axis=1)[:, None])

@@ -42,7 +42,7 @@ class Config(ctypes.Structure):
                 ("curv_eps", ctypes.c_double), ("ls_noise", ctypes.c_double),
                 ("keep_cells", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("quad_rule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+                ("k_max", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -87,7 +87,7 @@ _sig = {
                                        ctypes.POINTER(_H)]),
     "scvt_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "scvt_footprint": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]),
-    "scvt_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_H)]),
+    "scvt_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, _vp, ctypes.POINTER(_H)]),
     "scvt_server_submit": (ctypes.c_int, [_H, ctypes.POINTER(Config), _vp, ctypes.c_double,
                                           ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "scvt_server_poll": (ctypes.c_int, [_H, ctypes.c_int64, _vp, ctypes.POINTER(Info), _dp]),
@@ -142,7 +142,7 @@ METHODS = {"plbfgs": 0, "lloyd": 1, "lbfgs": 2}
 
 def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_max_evals=10,
                 ls_c1=1e-4, curv_eps=1e-10, keep_cells=False, stream=None, ls_noise=-1.0,
-                method="plbfgs", quad_rule=7):
+                method="plbfgs", quad_rule=7, k_max=0):
     c = Config()
     _check(_lib.scvt_config_init(ctypes.byref(c), int(n)), "scvt_config_init")
     c.m_hist = int(m_hist)
@@ -156,6 +156,7 @@ def make_config(n, density=None, m_hist=7, precision="fp64", quad_levels=2, ls_m
     c.keep_cells = 1 if keep_cells else 0
     c.method = METHODS[method] if isinstance(method, str) else int(method)
     c.quad_rule = int(quad_rule)
+    c.k_max = int(k_max)
     c.hip_stream = stream
     return c
 
@@ -312,6 +313,16 @@ class Solver:
                                    flags.ctypes.data_as(ctypes.c_void_p)), "scvt_get_cells")
         return nbr, deg, verts, flags
 
+    def neighbours(self):
+        """Neighbour lists (n, 32; -1 padded) and degrees of the current
+        cells (scvt_get_cells without vertices; needs keep_cells)."""
+        nbr = np.zeros((self.n, VMAX), np.int32)
+        deg = np.zeros(self.n, np.int32)
+        _check(_lib.scvt_get_cells(self.h, VMAX, nbr.ctypes.data_as(ctypes.c_void_p),
+                                   deg.ctypes.data_as(ctypes.c_void_p), None, None),
+               "scvt_get_cells")
+        return nbr, deg
+
     def degrees(self):
         """Voronoi degree of every cell at the current generators."""
         deg = np.zeros(self.n, np.int32)
@@ -353,12 +364,14 @@ def footprint(n, density=None, **kw):
 
 
 class Server:
-    """Persistent request loop (scvt_server): submit requests at any time,
-    poll for results.  Admission by slots and HBM footprint."""
+    """Continuous-batching request loop (scvt_server): submit requests at any
+    time, poll for results.  Admission by slots and HBM footprint; all
+    admitted requests advance together in rounds of segmented launches on
+    `stream` (a hipStream_t as an int, or None for the server's own)."""
 
-    def __init__(self, hbm_budget, max_slots=8):
+    def __init__(self, hbm_budget, max_slots=8, stream=None):
         h = _H()
-        _check(_lib.scvt_server_create(int(hbm_budget), int(max_slots), ctypes.byref(h)),
+        _check(_lib.scvt_server_create(int(hbm_budget), int(max_slots), stream, ctypes.byref(h)),
                "scvt_server_create")
         self.h = h
         self.n_of = {}

@@ -219,16 +219,14 @@ int hc_rho_poly(const double* z3, const DensityP* D, int64_t n, const double* y,
 }
 
 // Mixed-precision cell integrals as the kernel computes them (FP64
-// sub-triangles, FP32 local-frame points, FP64 accumulation, mu = m z + ...)
+// subdivision and leaf determinants, FP32 local-frame points, FP64
+// accumulation, mu = m z + ...)
 int hc_quad_mixed(const double* z3, int E, const double* verts, const DensityP* D, int levels,
                   int nq, double* out5) {
   Acc5 acc = {0, 0, 0, 0, 0};
   DensityP Dp = density_prepare(*D);
   V3 z = V3{z3[0], z3[1], z3[2]};
-  F3 zf = to_f3(z);
   DensityF Df = density_f32(Dp);
-  F3 zc[2];
-  for (int k = 0; k < 2; k++) zc[k] = to_f3(z - V3{Dp.xc[k][0], Dp.xc[k][1], Dp.xc[k][2]});
   const int per = 1 << (2 * levels);
   const int var = rho_variant(Dp);
   for (int t = 0; t < E * per; t++) {
@@ -236,8 +234,7 @@ int hc_quad_mixed(const double* z3, int E, const double* verts, const DensityP* 
     V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
        C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
     subtriangle(A, B, C, s, levels);
-#define HC_MIXED(V) \
-  quad_tri_mixed<V>(to_f3(A - z), to_f3(B - z), to_f3(C - z), zf, zc, Df, Dp, acc, nq)
+#define HC_MIXED(V) quad_leaf_mixed<V>(A, B, C, z, cell_f32<V>(Dp, z), Df, Dp, acc, nq)
     SCVT_RHO_DISPATCH(var, HC_MIXED)
 #undef HC_MIXED
   }
@@ -340,40 +337,3 @@ int hc_leaves2(const double* abc, double* out) {
 }
 }
 
-extern "C" {
-// The mixed-precision cell integrals as k_quad<MIXED> computes them with two
-// subdivision levels: the 15-point grid of each fan triangle in FP32 offsets
-// from z (corners rounded from FP64, arc midpoints in the local frame), then
-// the 16 leaves through quad_tri_mixed, FP64 accumulation.
-int hc_quad_mixed_grid(const double* z3, int E, const double* verts, const DensityP* D, int nq,
-                       double* out5) {
-  Acc5 acc = {0, 0, 0, 0, 0};
-  DensityP Dp = density_prepare(*D);
-  V3 z = V3{z3[0], z3[1], z3[2]};
-  F3 zf = to_f3(z);
-  DensityF Df = density_f32(Dp);
-  F3 zc[2];
-  for (int k = 0; k < 2; k++) zc[k] = to_f3(z - V3{Dp.xc[k][0], Dp.xc[k][1], Dp.xc[k][2]});
-  const int var = rho_variant(Dp);
-  for (int e = 0; e < E; e++) {
-    F3 G[15];
-    G[4] = to_f3(V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]} - z);
-    G[0] = to_f3(V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]} - z);
-    G[14] = F3{0.0f, 0.0f, 0.0f};
-    for (int task = 0; task < 12; task++)
-      G[nib(kG2TaskPt, task)] = arc_midpoint_local(G[nib(kG2TaskP, task)], G[nib(kG2TaskQ, task)], zf);
-    for (int s = 0; s < 16; s++) {
-      const F3 a = G[nib(kG2LeafA, s)], b = G[nib(kG2LeafB, s)], c = G[nib(kG2LeafC, s)];
-#define HC_MIXED2(V) quad_tri_mixed<V>(a, b, c, zf, zc, Df, Dp, acc, nq)
-      SCVT_RHO_DISPATCH(var, HC_MIXED2)
-#undef HC_MIXED2
-    }
-  }
-  out5[0] = acc.m;
-  out5[1] = acc.m * z.x + acc.mx;
-  out5[2] = acc.m * z.y + acc.my;
-  out5[3] = acc.m * z.z + acc.mz;
-  out5[4] = acc.e;
-  return 0;
-}
-}

@@ -146,17 +146,6 @@ def quad_mixed(z, E, verts, density, levels=2, rule=7):
     return out
 
 
-def quad_mixed_grid(z, E, verts, density, rule=7):
-    """k_quad's mixed path with two levels: FP32 grid in the local frame."""
-    z = np.ascontiguousarray(z, dtype=np.float64)
-    verts = np.ascontiguousarray(verts, dtype=np.float64)
-    out = np.zeros(5)
-    D = cdensity(density)
-    lib().hc_quad_mixed_grid(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D), ctypes.c_int(rule),
-                             P(out))
-    return out
-
-
 def grid(n):
     GBW = np.zeros(3, np.int32)
     dd = np.zeros(3)

@@ -237,3 +237,26 @@ def test_x16_density_closed_forms(centre):
         assert abs(r_lon - exact) < 1e-15 and abs(r_lat - exact) < 1e-15
         assert abs(_x16_at(d, 0.0, 0.0) - (d["gamma"] + d["amp"][0] * 0.5 * (
             math.tanh(d["beta"][0] / d["alpha"][0]) + 1))) < 1e-15
+
+
+def test_oracle_c_under_address_and_ub_sanitizers(tmp_path):
+    """The oracle's C integrals built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (gcc, host code) run every density kind, both
+    rule kinds and several subdivision levels without a report."""
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path / "oracle_sanitize")
+    subprocess.check_call(["gcc", "-O1", "-g", "-fopenmp", "-ffp-contract=off",
+                           "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", "-o", exe,
+                           os.path.join(here, "host", "oracle_sanitize.c"), "-lm"])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    p = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
+    assert p.returncode == 0, p.stdout + p.stderr
+    assert "runtime error" not in p.stderr and "AddressSanitizer" not in p.stderr
+    assert "0 failures" in p.stdout
