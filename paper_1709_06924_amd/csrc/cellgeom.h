@@ -559,25 +559,28 @@ SCVT_HD double rho_eval(const DensityP& D, V3 y) {
 // Triangle rules (rules.h, weights summing to 1): Radon's 7-point degree-5
 // rule (the configured one) and the 4- and 9-point conical product rules of
 // degrees 3 and 5 (the sizes the paper uses, section 4.1).  The FP32 copies
-// serve the mixed-precision points.
-#define SCVT_RULE_F(T, r) {(float)T[r][0], (float)T[r][1], (float)T[r][2], (float)T[r][3]}
-__device__ constexpr float kRule7f[7][4] = {
+// serve the mixed-precision points: (l0, l1, l2, w, l0 l1, l0 l2, l1 l2, 0),
+// the products formed in FP64 and rounded once.
+#define SCVT_RULE_F(T, r)                                                                  \
+  {(float)T[r][0], (float)T[r][1], (float)T[r][2], (float)T[r][3], (float)(T[r][0] * T[r][1]), \
+   (float)(T[r][0] * T[r][2]), (float)(T[r][1] * T[r][2]), 0.0f}
+__device__ constexpr float kRule7f[7][8] = {
     SCVT_RULE_F(kRule7, 0), SCVT_RULE_F(kRule7, 1), SCVT_RULE_F(kRule7, 2),
     SCVT_RULE_F(kRule7, 3), SCVT_RULE_F(kRule7, 4), SCVT_RULE_F(kRule7, 5),
     SCVT_RULE_F(kRule7, 6)};
-__device__ constexpr float kRule4f[4][4] = {SCVT_RULE_F(kRule4, 0), SCVT_RULE_F(kRule4, 1),
+__device__ constexpr float kRule4f[4][8] = {SCVT_RULE_F(kRule4, 0), SCVT_RULE_F(kRule4, 1),
                                             SCVT_RULE_F(kRule4, 2), SCVT_RULE_F(kRule4, 3)};
-__device__ constexpr float kRule9f[9][4] = {
+__device__ constexpr float kRule9f[9][8] = {
     SCVT_RULE_F(kRule9, 0), SCVT_RULE_F(kRule9, 1), SCVT_RULE_F(kRule9, 2),
     SCVT_RULE_F(kRule9, 3), SCVT_RULE_F(kRule9, 4), SCVT_RULE_F(kRule9, 5),
     SCVT_RULE_F(kRule9, 6), SCVT_RULE_F(kRule9, 7), SCVT_RULE_F(kRule9, 8)};
-constexpr float kRule7fHost[7][4] = {
+constexpr float kRule7fHost[7][8] = {
     SCVT_RULE_F(kRule7Host, 0), SCVT_RULE_F(kRule7Host, 1), SCVT_RULE_F(kRule7Host, 2),
     SCVT_RULE_F(kRule7Host, 3), SCVT_RULE_F(kRule7Host, 4), SCVT_RULE_F(kRule7Host, 5),
     SCVT_RULE_F(kRule7Host, 6)};
-constexpr float kRule4fHost[4][4] = {SCVT_RULE_F(kRule4Host, 0), SCVT_RULE_F(kRule4Host, 1),
+constexpr float kRule4fHost[4][8] = {SCVT_RULE_F(kRule4Host, 0), SCVT_RULE_F(kRule4Host, 1),
                                      SCVT_RULE_F(kRule4Host, 2), SCVT_RULE_F(kRule4Host, 3)};
-constexpr float kRule9fHost[9][4] = {
+constexpr float kRule9fHost[9][8] = {
     SCVT_RULE_F(kRule9Host, 0), SCVT_RULE_F(kRule9Host, 1), SCVT_RULE_F(kRule9Host, 2),
     SCVT_RULE_F(kRule9Host, 3), SCVT_RULE_F(kRule9Host, 4), SCVT_RULE_F(kRule9Host, 5),
     SCVT_RULE_F(kRule9Host, 6), SCVT_RULE_F(kRule9Host, 7), SCVT_RULE_F(kRule9Host, 8)};
@@ -1031,36 +1034,50 @@ SCVT_HD float rho_cell_f(const DensityF& D, const CellF& c, F3 dyz, float dyz2,
 // precision: the leaf's Jacobian determinant in FP64 (its rounding in FP32
 // would be a per-leaf relative error of ~1e-7, and the cell boundary's
 // corners rounded to FP32 would move the cell's edges by ~6e-8 R), the
-// points in FP32 offsets d = p - z from the rounded corner offsets:
-//   s = |z + d|^2 - 1 = 2 z.d + |d|^2,  r - 1 = (1 + s)^(-1/2) - 1,
-//   y - z = d + (r - 1)(z + d),  Jacobian r^3 = 1 + (r - 1)(3 + (r - 1)(3 + (r - 1)))
-// (no "1 +" rounded away at any point); the 7 weighted points summed in FP32
-// and scaled by the FP64 determinant into the FP64 accumulators.
+// points in FP32 offsets d = p - z from the rounded corner offsets.  For a
+// point p = sum l_k V_k of a flat triangle with unit corners,
+//   s = |p|^2 - 1 = -(l0 l1 |V0 - V1|^2 + l0 l2 |V0 - V2|^2 + l1 l2 |V1 - V2|^2)
+// (no cancellation: from the leaf's edge lengths, |s| <= max edge^2 / 3),
+// r - 1 = (1 + s)^(-1/2) - 1 from its binomial series (two terms when the
+// leaf bounds |s| by 2^-16: the rest is below 1e-15 absolute; six up to
+// 2^-5; else the hardware rsqrt), y - z = d + (r - 1)(z + d) and the
+// Jacobian r^3 = 1 + 3(r - 1) + 3(r - 1)^2 (+ (r - 1)^3 beyond two terms)
+// (no "1 +" rounded away at any point); the 7 weighted points summed in
+// FP32 and scaled by the FP64 determinant into the FP64 accumulators.
 // Accumulates m, int rho (y - z) (mx, my, mz) and e.
 template <int KIND, bool XP = false>
 SCVT_HD void quad_leaf_mixed(V3 A, V3 B, V3 C, V3 z, const CellF& cf, const DensityF& D,
                              const DensityP& Dd, Acc5& acc, int nq = 7) {
-  const float(*R)[4] = SCVT_RULE_TABLE_F(nq);
+  const float(*R)[8] = SCVT_RULE_TABLE_F(nq);
   const V3 BA = B - A, CA = C - A;
   const double hd = 0.5 * dot(A, cross(BA, CA));
   const F3 dA = to_f3(A - z), dBA = to_f3(BA), dCA = to_f3(CA);
+  const F3 dCB = dCA - dBA;
+  const float eAB = dotf(dBA, dBA), eAC = dotf(dCA, dCA), eBC = dotf(dCB, dCB);
+  const float smax = fmaxf(eAB, fmaxf(eAC, eBC)) * (1.0f / 3.0f);
+  const int form = smax <= 0x1p-16f ? 0 : (smax <= 0x1p-5f ? 1 : 2);  // uniform over the leaf
   float sm = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, se = 0.f;
 #pragma unroll 1
   for (int q = 0; q < nq; q++) {
     const float l1 = R[q][1], l2 = R[q][2];
     const F3 d = F3{fmaf(l2, dCA.x, fmaf(l1, dBA.x, dA.x)), fmaf(l2, dCA.y, fmaf(l1, dBA.y, dA.y)),
                     fmaf(l2, dCA.z, fmaf(l1, dBA.z, dA.z))};
-    const float s = fmaf(2.0f, dotf(cf.zf, d) + dotf(cf.zl, d), dotf(d, d));
-    float rm1;
-    if (fabsf(s) <= 0x1p-5f) {  // all but very large cells: no special functions
-      rm1 = rm1_series(s);
+    const float s = -fmaf(R[q][6], eBC, fmaf(R[q][5], eAC, R[q][4] * eAB));
+    float rm1, jm1;
+    if (form == 0) {  // tiny leaves: two terms
+      rm1 = s * fmaf(s, 0.375f, -0.5f);
+      jm1 = rm1 * fmaf(rm1, 3.0f, 3.0f);
     } else {
-      const float r = rsqf(1.0f + s);
-      rm1 = -s * r * r * rcpf(1.0f + r);
+      if (form == 1) {
+        rm1 = rm1_series(s);
+      } else {
+        const float r = rsqf(1.0f + s);
+        rm1 = -s * r * r * rcpf(1.0f + r);
+      }
+      jm1 = rm1 * fmaf(rm1, rm1 + 3.0f, 3.0f);
     }
     const F3 p = cf.zf + d;
     const F3 dyz = F3{fmaf(rm1, p.x, d.x), fmaf(rm1, p.y, d.y), fmaf(rm1, p.z, d.z)};
-    const float jm1 = rm1 * fmaf(rm1, rm1 + 3.0f, 3.0f);
     const float dyz2 = dotf(dyz, dyz);
     float rho;
     if (XP) {

@@ -550,7 +550,7 @@ struct QuadLds {
 constexpr int kQuadCells = 64;  // cells per block: eight pairs per wave
 
 template <int KIND, bool MIXED, class P>
-__global__ __launch_bounds__(256, MIXED ? 6 : 4) void k_quad(P p) {
+__global__ __launch_bounds__(256, 4) void k_quad(P p) {
   if (p.idle()) return;
   const CellArgs& a = p.args();
   __shared__ QuadLds lds[4];
