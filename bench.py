@@ -8,8 +8,14 @@ density with 16x spacing ratio (x_c at lat 30 lon 90, beta = pi/9,
 alpha = 0.15), M = 10.  Generators start resident in HBM; the timed region is
 K iterations from the seeded start, bracketed by device synchronisation.
 
-Prints one JSON line.  Options: --config C1|C2|C3|C5 (default C3, the
+The run ends with a serving leg at the stated accuracy: the first 16
+requests of the seeded Poisson stream (20 req/s, n log-uniform in
+[10,242, 655,362], each with its own tanh density) solved in mixed precision
+to max |l| < 1e-8 with a 5,000-iteration cap; p50/p99 latency and throughput.
+
+Prints one JSON line.  Options: --config C1|C2|C3|C4|C5 (default C3, the
 workload above; C1 n=2,562 rho=1 to 1e-10, C2 n=163,842 8x tanh to 1e-8,
+C4 the serving stream alone, 200 requests at each rate of --serving-rates,
 C5 n=4,194,304 two-centre density, 100 iterations), --steps K (iteration cap,
 default the workload's: 200 for C3), --warmup W, --precision fp64|mixed|both
 (default both: `value` is the FP64 path, the "mixed" object the
@@ -283,9 +289,53 @@ WORKLOADS = {
           "alpha 0.2), M=7, solved to max |l| < 1e-8 (cap 20000)",
     "C3": "n=1048576 uniform start (seed 3), tanh density 16x (lat 30 lon 90, beta pi/9, "
           "alpha 0.15), M=10, 200 iterations",
+    "C4": "Poisson stream (seed 4), n log-uniform in [10242, 655362], per-request tanh density "
+          "(centre uniform on the sphere, beta in [pi/12, pi/4], alpha in [0.1, 0.3], ratio 4-16x), "
+          "mixed precision, M=10, max |l| < 1e-8 with a 5000-iteration cap",
     "C5": "n=4194304 uniform start (seed 5), two-centre tanh density (lat +-45 lon 0, 16x and "
           "8x), M=10, 100 iterations",
 }
+
+
+def serve(rate, count, max_iter, slots):
+    """The first `count` requests of the seeded stream at `rate` req/s,
+    served to max |l| < 1e-8; per-request records and the summary."""
+    import paper_1709_06924_amd.inputs as I
+    from paper_1709_06924_amd import serving
+    stream = I.serving_stream(seed=4, rate=rate, count=count)
+    print("bench: serving %d requests at %g req/s" % (len(stream), rate), file=sys.stderr,
+          flush=True)
+    records, summ = serving.run_stream(
+        stream, tol=1e-8, max_iter=max_iter, max_slots=slots, hbm_budget=64 << 30,
+        precision="mixed", m_hist=10, log=lambda m: print(m, file=sys.stderr, flush=True))
+    summ.update({"rate_rps": rate, "max_iter": max_iter, "max_slots": slots,
+                 "hbm_budget_bytes": 64 << 30,
+                 "n_total": sum(r["n"] for r in stream),
+                 "iterations_total": sum(r["iters"] for r in records)})
+    print("bench: %g req/s: %d/%d converged, p50 %.2f s, p99 %.2f s, %.3g generator-iterations/s"
+          % (rate, summ["converged"], summ["requests"], summ["p50_s"], summ["p99_s"],
+             summ["generator_iterations_per_s"]), file=sys.stderr, flush=True)
+    return records, summ
+
+
+def bench_serving(args):
+    """C4: the serving stream alone at each rate; `value` is the p50 latency
+    at the last rate (the stream's own 20 req/s by default)."""
+    rates = [float(x) for x in args.serving_rates.split(",")]
+    out = []
+    for rate in rates:
+        out.append(serve(rate, args.serving_requests, args.serving_max_iter, args.serving_slots)[1])
+    last = out[-1]
+    line = {"metric": "SCVT serving p50 solve latency at max |l| < 1e-8 (mixed)",
+            "value": last["p50_s"], "unit": "s", "n_gpus": 1, "steps": last["requests"],
+            "warmup": 0, "ms_per_step": 1000.0 * last["wall_s"] / max(last["requests"], 1),
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32-quadrature/f64-geometry", "data": "synthetic",
+            "config": {"workload": "C4: " + WORKLOADS["C4"], "requests": args.serving_requests,
+                       "rates_rps": rates, "max_iter": args.serving_max_iter,
+                       "max_slots": args.serving_slots},
+            "serving": out}
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -307,9 +357,12 @@ def main():
                     help="print the hash of the quadrature kernel's sources and exit")
     ap.add_argument("--breakdown-steps", type=int, default=20,
                     help="iterations after the timed ones with every kernel timer on")
-    ap.add_argument("--serving-requests", type=int, default=24)
+    ap.add_argument("--serving-requests", type=int, default=None,
+                    help="requests of the serving stream (default 16 after C3, 200 for C4; "
+                         "0 skips the serving leg)")
     ap.add_argument("--serving-rate", type=float, default=20.0)
-    ap.add_argument("--serving-max-iter", type=int, default=200)
+    ap.add_argument("--serving-rates", default="5,10,20", help="C4: arrival rates (req/s)")
+    ap.add_argument("--serving-max-iter", type=int, default=5000)
     ap.add_argument("--serving-slots", type=int, default=8)
     args = ap.parse_args()
     if args.source_hash:
@@ -331,6 +384,12 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
               "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.serving_requests is None:
+        args.serving_requests = 200 if args.config == "C4" else 16
+    if args.config == "C4":
+        bench_serving(args)
+        return
 
     import torch
 
@@ -417,20 +476,11 @@ def main():
         cps = tuple(k for k in (0, 50, 100, 200) if k <= max_iter)
         line["mixed"]["errors_vs_fp64"] = mixed_errors(cfg, Z0_dev, stream, cps)
     if args.serving_requests > 0 and args.config == "C3":
-        from paper_1709_06924_amd import serving
-        stream = I.serving_stream(seed=4, rate=args.serving_rate, count=args.serving_requests)
-        print("bench: serving %d requests at %.0f req/s" % (len(stream), args.serving_rate),
-              file=sys.stderr, flush=True)
-        records, summ = serving.run_stream(
-            stream, tol=1e-8, max_iter=args.serving_max_iter, max_slots=args.serving_slots,
-            hbm_budget=64 << 30, precision="mixed", m_hist=10,
-            log=lambda m: print(m, file=sys.stderr, flush=True))
-        summ.update({"workload": "Poisson %.0f req/s (seed 4), first %d requests, n log-uniform "
-                                 "in [10242, 655362], per-request tanh density, mixed precision, "
-                                 "M=10, tol 1e-8 with an iteration cap of %d"
-                                 % (args.serving_rate, len(stream), args.serving_max_iter),
-                     "max_slots": args.serving_slots, "hbm_budget_bytes": 64 << 30})
-        line["serving"] = summ
+        line["serving"] = serve(args.serving_rate, args.serving_requests, args.serving_max_iter,
+                                args.serving_slots)[1]
+        line["serving"]["workload"] = ("Poisson %g req/s (seed 4), first %d requests: %s"
+                                       % (args.serving_rate, args.serving_requests,
+                                          WORKLOADS["C4"]))
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
         if args.config == "C5":

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "../../include/scvt.h"
+#include "arena.h"
 #include "engine_batch.h"
 #include "round.h"
 
@@ -61,37 +62,6 @@ struct Request {
   size_t off = 0;     // arena range
   int slot = -1;      // pinned scalars
   scvt_handle* h = nullptr;
-};
-
-// First-fit ranges of the arena (offsets in bytes, 256-byte aligned).
-struct Arena {
-  std::map<size_t, size_t> free;  // offset -> size
-  bool take(size_t bytes, size_t* off) {
-    for (auto it = free.begin(); it != free.end(); ++it) {
-      if (it->second < bytes) continue;
-      *off = it->first;
-      const size_t rest = it->second - bytes, at = it->first + bytes;
-      free.erase(it);
-      if (rest) free[at] = rest;
-      return true;
-    }
-    return false;
-  }
-  void give(size_t off, size_t bytes) {
-    auto it = free.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free.erase(nx);
-    }
-    if (it != free.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free.erase(it);
-      }
-    }
-  }
 };
 
 constexpr size_t kRoundTableBytes = (size_t)4 << 20;  // argument tables of one round

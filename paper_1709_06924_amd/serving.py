@@ -10,8 +10,22 @@ from . import inputs
 from . import scvt
 
 
+def depth_series(depth, step_s):
+    """(time, waiting, running) samples thinned to one per step_s seconds:
+    the largest queue depth and running count seen in each interval."""
+    out = []
+    for t, w, r in depth:
+        b = int(t // step_s)
+        if out and out[-1][0] == b * step_s:
+            out[-1][1] = max(out[-1][1], w)
+            out[-1][2] = max(out[-1][2], r)
+        else:
+            out.append([b * step_s, w, r])
+    return out
+
+
 def run_stream(requests, tol=1e-8, max_iter=5000, max_slots=8, hbm_budget=64 << 30,
-               precision="mixed", m_hist=10, poll_s=0.002, log=None):
+               precision="mixed", m_hist=10, poll_s=0.002, log=None, series_step_s=1.0):
     """Submit each request at its arrival time (seconds from start), wait for
     all to finish.  Returns per-request records and a summary."""
     srv = scvt.Server(hbm_budget, max_slots)
@@ -65,5 +79,6 @@ def run_stream(requests, tol=1e-8, max_iter=5000, max_slots=8, hbm_budget=64 << 
         "generator_iterations_per_s": gen_it / wall,
         "max_queue_depth": max((d[1] for d in depth), default=0),
         "max_running": max((d[2] for d in depth), default=0),
+        "depth_over_time": depth_series(depth, series_step_s),
     }
     return records, summary
