@@ -1057,25 +1057,11 @@ SCVT_HD void quad_leaf_mixed(V3 A, V3 B, V3 C, V3 z, const CellF& cf, const Dens
   const float smax = fmaxf(eAB, fmaxf(eAC, eBC)) * (1.0f / 3.0f);
   const int form = smax <= 0x1p-16f ? 0 : (smax <= 0x1p-5f ? 1 : 2);  // uniform over the leaf
   float sm = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, se = 0.f;
-#pragma unroll 1
-  for (int q = 0; q < nq; q++) {
-    const float l1 = R[q][1], l2 = R[q][2];
+  // point q of the rule with r - 1 and the Jacobian's r^3 - 1 given
+  auto point = [&](const float* Rq, float rm1, float jm1) {
+    const float l1 = Rq[1], l2 = Rq[2];
     const F3 d = F3{fmaf(l2, dCA.x, fmaf(l1, dBA.x, dA.x)), fmaf(l2, dCA.y, fmaf(l1, dBA.y, dA.y)),
                     fmaf(l2, dCA.z, fmaf(l1, dBA.z, dA.z))};
-    const float s = -fmaf(R[q][6], eBC, fmaf(R[q][5], eAC, R[q][4] * eAB));
-    float rm1, jm1;
-    if (form == 0) {  // tiny leaves: two terms
-      rm1 = s * fmaf(s, 0.375f, -0.5f);
-      jm1 = rm1 * fmaf(rm1, 3.0f, 3.0f);
-    } else {
-      if (form == 1) {
-        rm1 = rm1_series(s);
-      } else {
-        const float r = rsqf(1.0f + s);
-        rm1 = -s * r * r * rcpf(1.0f + r);
-      }
-      jm1 = rm1 * fmaf(rm1, rm1 + 3.0f, 3.0f);
-    }
     const F3 p = cf.zf + d;
     const F3 dyz = F3{fmaf(rm1, p.x, d.x), fmaf(rm1, p.y, d.y), fmaf(rm1, p.z, d.z)};
     const float dyz2 = dotf(dyz, dyz);
@@ -1088,13 +1074,43 @@ SCVT_HD void quad_leaf_mixed(V3 A, V3 B, V3 C, V3 z, const CellF& cf, const Dens
     } else {
       rho = rho_cell_f<KIND>(D, cf, dyz, dyz2, Dd);
     }
-    const float b = R[q][3] * rho;
+    const float b = Rq[3] * rho;
     const float wt = fmaf(b, jm1, b);
     sm += wt;
     sx = fmaf(wt, dyz.x, sx);
     sy = fmaf(wt, dyz.y, sy);
     sz = fmaf(wt, dyz.z, sz);
     se = fmaf(wt, dyz2, se);
+  };
+  // s at point q (no cancellation: the leaf's squared edge lengths)
+  auto sq = [&](const float* Rq) { return -fmaf(Rq[6], eBC, fmaf(Rq[5], eAC, Rq[4] * eAB)); };
+  // one loop per form: the common one (every leaf of a cell at n >~ 10^4)
+  // runs without a branch per point
+  auto tiny = [&](const float* Rq) {  // tiny leaves: two terms
+    const float s = sq(Rq);
+    const float rm1 = s * fmaf(s, 0.375f, -0.5f);
+    point(Rq, rm1, rm1 * fmaf(rm1, 3.0f, 3.0f));
+  };
+  if (form == 0 && nq == 7) {  // the rule's constants as immediates
+    const float(*R7)[8] = SCVT_RULE_TABLE_F(7);
+#pragma unroll
+    for (int q = 0; q < 7; q++) tiny(R7[q]);
+  } else if (form == 0) {
+#pragma unroll 1
+    for (int q = 0; q < nq; q++) tiny(R[q]);
+  } else {
+#pragma unroll 1
+    for (int q = 0; q < nq; q++) {
+      const float s = sq(R[q]);
+      float rm1;
+      if (form == 1) {
+        rm1 = rm1_series(s);
+      } else {
+        const float r = rsqf(1.0f + s);
+        rm1 = -s * r * r * rcpf(1.0f + r);
+      }
+      point(R[q], rm1, rm1 * fmaf(rm1, rm1 + 3.0f, 3.0f));
+    }
   }
   acc.m = fma(hd, (double)sm, acc.m);
   acc.mx = fma(hd, (double)sx, acc.mx);
