@@ -326,7 +326,7 @@ struct DensityP {
   // x = d^2/2 (polyx_*)
   const RhoPoly* poly_tab;
   int64_t poly_n;
-  const RhoPoly* polyx_tab;
+  const RhoPoly* polyx_tab[2];  // one per bump (chord tanh bumps, one or two)
   int64_t polyx_n;
 };
 
@@ -395,13 +395,17 @@ SCVT_HD DensityP density_prepare(DensityP d) {
     d.poly_r2[k] = d.alpha[k] > 0.0 ? rl * rl : 0.0;
     d.poly_near2[k] = (kPolyNear + rl) * (kPolyNear + rl);
   }
-  // t spans [t(0), t(2)] = [-2 beta/alpha, -2 beta/alpha + 4/alpha]
-  const bool single = d.kind == kRhoTanh && d.nbumps == 1 && !d.geodesic && d.alpha[0] > 0.0;
-  const double span = single ? 4.0 / d.alpha[0] * kPolyPerT : 0.0;
-  d.poly_n = single && span < (double)(kPolyMax - 2) ? (int64_t)span + 2 : 0;
+  // t spans [t(0), t(2)] = [-2 beta/alpha, -2 beta/alpha + 4/alpha]; the
+  // tables serve chord tanh bumps with alpha in the t table's range: the
+  // expansion in t a single bump, the one in x each of one or two bumps
+  const bool chord = d.kind == kRhoTanh && !d.geodesic && (d.nbumps == 1 || d.nbumps == 2);
+  bool in_range = chord;
+  for (int k = 0; k < d.nbumps && k < 2; k++)
+    in_range = in_range && d.alpha[k] > 0.0 && 4.0 / d.alpha[k] * kPolyPerT < (double)(kPolyMax - 2);
+  d.poly_n = in_range && d.nbumps == 1 ? (int64_t)(4.0 / d.alpha[0] * kPolyPerT) + 2 : 0;
   d.poly_tab = nullptr;
-  d.polyx_n = d.poly_n > 0 ? (int64_t)(2.0 / kPolyDx) + 2 : 0;
-  d.polyx_tab = nullptr;
+  d.polyx_n = in_range ? (int64_t)(2.0 / kPolyDx) + 2 : 0;
+  d.polyx_tab[0] = d.polyx_tab[1] = nullptr;
   return d;
 }
 
@@ -673,19 +677,22 @@ SCVT_HD int64_t poly_index(const DensityP& D, V3 z) {
   return min(max(j, 0), (int)D.poly_n - 1);
 }
 
-// Table entry j of the expansion in x about x* = j kPolyDx: the t-series
+// Table entry j of the expansion in x about x* = j kPolyDx of bump `bump` (gamma
+// added to bump 0's constant term; the bound above is relative to the bump's
+// own term, so to rho as well): the t-series
 // (poly_entry's b_n about t* = t(x*)) composed with the binomial series of
 // t(x* + D) - t* = Kt sqrt(x*) sum_{k>=1} binom(1/2, k) (D/x*)^k, both
 // truncated at degree 9; lim from the bound above (bisection).
-SCVT_HD RhoPoly polyx_entry(const DensityP& D, int64_t j, const double* tab = SCVT_EXP2_TAB) {
+SCVT_HD RhoPoly polyx_entry(const DensityP& D, int64_t j, int bump = 0,
+                            const double* tab = SCVT_EXP2_TAB) {
   constexpr int K = kPolyDeg;
   RhoPoly P{};
   const double xs = (double)j * kPolyDx;
-  P.off = D.cc[0] - xs;
+  P.off = D.cc[bump] - xs;
   P.lim = 0.0;
   if (j < 1) return P;
-  const double ss = sqrt(xs), ks = D.Kt[0] * ss;
-  const double ts = D.k2[0] * D.beta[0] + ks;  // t(x*) = Kt sqrt(x*) - 2 beta/alpha
+  const double ss = sqrt(xs), ks = D.Kt[bump] * ss;
+  const double ts = D.k2[bump] * D.beta[bump] + ks;  // t(x*) = Kt sqrt(x*) - 2 beta/alpha
   const double s0 = rcp_nr(1.0 + exp2_n(fmin(ts * kExpInvLn, kUMax), tab));
   const double q = 1.0 - s0;
   double b[K + 1], a[K + 1], pw[K + 1], nw[K + 1], r[K + 1];
@@ -720,9 +727,9 @@ SCVT_HD RhoPoly polyx_entry(const DensityP& D, int64_t j, const double* tab = SC
       r[m] = fma(b[n], pw[m], r[m]);
     }
   }
-  const double as = D.amp[0] * s0;
+  const double as = D.amp[bump] * s0;
   for (int m = 0; m <= K; m++) P.c[m] = as * r[m];
-  P.c[0] += D.gamma;
+  if (bump == 0) P.c[0] += D.gamma;  // two bumps: the first entry carries gamma
   // the bound: w for |Im t| <= 2.5 (at most 0.8), then the largest delta
   const double y = 2.5 / ks;
   const double w = y >= 0.5528 ? 0.8 : 2.0 * y - y * y;
@@ -740,12 +747,22 @@ SCVT_HD RhoPoly polyx_entry(const DensityP& D, int64_t j, const double* tab = SC
   return P;
 }
 
-// the x table's entry of generator z, and x(z) = d(z)^2 / 2
-SCVT_HD int64_t polyx_index(const DensityP& D, V3 z, double* xz) {
-  const double x = fmax(D.cc[0] - dot(z, V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]}), 0.0);
+// bump b's x table entry of generator z, and x(z) = d(z)^2 / 2
+SCVT_HD int64_t polyx_index(const DensityP& D, V3 z, double* xz, int b = 0) {
+  const double x = fmax(D.cc[b] - dot(z, V3{D.xc[b][0], D.xc[b][1], D.xc[b][2]}), 0.0);
   *xz = x;
   const int j = (int)fmin(rint(x * (1.0 / kPolyDx)), 2e9);
   return min(max(j, 1), (int)D.polyx_n - 1);
+}
+
+// whether the fan of z (vertices within chord r of z) lies inside the radius
+// of its entry of bump b's x table: |x - x*| <= |x(z) - x*| + r (d(z) + r/2)
+SCVT_HD bool polyx_qualifies(const DensityP& D, V3 z, double r, int b) {
+  double xz = 0.0;
+  const int64_t j = polyx_index(D, z, &xz, b);
+  const double dz = sqrt_nr_pos(fmax(2.0 * xz, 1e-300));
+  const double delta = fabs(xz - (double)j * kPolyDx) + r * (dz + 0.5 * r);
+  return delta <= D.polyx_tab[b][j].lim;
 }
 
 // quad_tri_k with rho from the cell's polynomial (single chord tanh bump)
@@ -775,6 +792,40 @@ SCVT_HD void quad_tri_poly(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const RhoP
     for (int n = kPolyDeg - 1; n >= 0; n--) rho = fma(rho, dl, P.c[n]);
     const V3 y = ri * p;
     const double wt = hd * R[q][3] * (ri * ri * ri) * rho;
+    const V3 dy = y - z;
+    acc.m += wt;
+    const double wr = wt * ri;
+    acc.mx += wr * p.x;
+    acc.my += wr * p.y;
+    acc.mz += wr * p.z;
+    acc.e += wt * dot(dy, dy);
+  }
+}
+
+// quad_tri_k for two chord tanh bumps, rho = P0(x_0 - x_0*) + P1(x_1 - x_1*)
+// from both bumps' x tables (the fan inside both entries' radii)
+SCVT_HD void quad_tri_poly2(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const RhoPoly& P0,
+                            const RhoPoly& P1, Acc5& acc, int nq = 7) {
+  const double(*R)[4] = SCVT_RULE_TABLE(nq);
+  const V3 BA = B - A, CA = C - A;
+  const double hd = 0.5 * dot(A, cross(BA, CA));
+  const V3 x0 = V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]};
+  const V3 x1 = V3{D.xc[1][0], D.xc[1][1], D.xc[1][2]};
+#pragma unroll 1
+  for (int q = 0; q < nq; q++) {
+    const double l1 = R[q][1], l2 = R[q][2];
+    const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
+                    fma(l2, CA.z, fma(l1, BA.z, A.z))};
+    const double ri = rsq_near1(dot(p, p));
+    const double d0 = fma(-ri, dot(p, x0), P0.off), d1 = fma(-ri, dot(p, x1), P1.off);
+    double r0 = P0.c[kPolyDeg], r1 = P1.c[kPolyDeg];
+#pragma unroll
+    for (int n = kPolyDeg - 1; n >= 0; n--) {
+      r0 = fma(r0, d0, P0.c[n]);
+      r1 = fma(r1, d1, P1.c[n]);
+    }
+    const V3 y = ri * p;
+    const double wt = hd * R[q][3] * (ri * ri * ri) * (r0 + r1);
     const V3 dy = y - z;
     acc.m += wt;
     const double wr = wt * ri;
@@ -938,12 +989,12 @@ SCVT_HD float rho_kind_f(const DensityF& D, const F3* zc, F3 zf, F3 dyz, const D
 // The per-cell constants share one array (a cell takes one of the two
 // forms), so that the kernel holds one set of registers for them: bump k
 // at k[8k..8k+7] = z - x_c (3), amp sigma(d_z), 1 - sigma(d_z), c_z, c_z^2,
-// sqrt(1 - c_z^2/4) (geodesic); the expansion in x at k[0..9] = the six
-// coefficients, x(z) - x*, x_c (3).  Densities other than tanh bumps use
-// z - x_c at k[0..2] (and k[8..10]).
+// sqrt(1 - c_z^2/4) (geodesic); the expansion in x of bump k at
+// k[10k..10k+9] = the six coefficients, x(z) - x*, x_c (3).  Densities other
+// than tanh bumps use z - x_c at k[0..2] (and k[8..10]).
 struct CellF {
   F3 zf, zl;
-  float k[16];
+  float k[20];
   SCVT_HD F3 v3(int o) const { return F3{k[o], k[o + 1], k[o + 2]}; }
   SCVT_HD void set3(int o, F3 v) {
     k[o] = v.x;
@@ -982,14 +1033,17 @@ SCVT_HD CellF cell_f32(const DensityP& D, V3 z, const double* tab = SCVT_EXP2_TA
 // degree-9 truncation below 1e-15, |D|/r <= ~0.025 of the series' radius r)
 // the degree-5 truncation is below ~1e-8 relative, and no special function
 // is left at the point.
-SCVT_HD CellF cell_f32_poly(const DensityP& D, const RhoPoly& P, V3 z) {
+// the expansions in x of the first nb bumps (entries P[0..nb-1])
+SCVT_HD CellF cell_f32_poly(const DensityP& D, const RhoPoly* P, int nb, V3 z) {
   CellF c{};
   c.zf = to_f3(z);
   c.zl = to_f3(z - V3{(double)c.zf.x, (double)c.zf.y, (double)c.zf.z});
-  const V3 xc = V3{D.xc[0][0], D.xc[0][1], D.xc[0][2]};
-  for (int k = 0; k < 6; k++) c.k[k] = (float)P.c[k];
-  c.k[6] = (float)(P.off - dot(z, xc));
-  c.set3(7, to_f3(xc));
+  for (int b = 0; b < nb; b++) {
+    const V3 xc = V3{D.xc[b][0], D.xc[b][1], D.xc[b][2]};
+    for (int k = 0; k < 6; k++) c.k[10 * b + k] = (float)P[b].c[k];
+    c.k[10 * b + 6] = (float)(P[b].off - dot(z, xc));
+    c.set3(10 * b + 7, to_f3(xc));
+  }
   return c;
 }
 
@@ -1045,7 +1099,7 @@ SCVT_HD float rho_cell_f(const DensityF& D, const CellF& c, F3 dyz, float dyz2,
 // (no "1 +" rounded away at any point); the 7 weighted points summed in
 // FP32 and scaled by the FP64 determinant into the FP64 accumulators.
 // Accumulates m, int rho (y - z) (mx, my, mz) and e.
-template <int KIND, bool XP = false>
+template <int KIND, int XP = 0>
 SCVT_HD void quad_leaf_mixed(V3 A, V3 B, V3 C, V3 z, const CellF& cf, const DensityF& D,
                              const DensityP& Dd, Acc5& acc, int nq = 7) {
   const float(*R)[8] = SCVT_RULE_TABLE_F(nq);
@@ -1066,11 +1120,17 @@ SCVT_HD void quad_leaf_mixed(V3 A, V3 B, V3 C, V3 z, const CellF& cf, const Dens
     const F3 dyz = F3{fmaf(rm1, p.x, d.x), fmaf(rm1, p.y, d.y), fmaf(rm1, p.z, d.z)};
     const float dyz2 = dotf(dyz, dyz);
     float rho;
-    if (XP) {
-      const float Dx = fmaf(-dyz.z, cf.k[9], fmaf(-dyz.y, cf.k[8], fmaf(-dyz.x, cf.k[7], cf.k[6])));
-      rho = cf.k[5];
+    if (XP > 0) {  // the expansions in x of XP bumps
+      rho = 0.0f;
 #pragma unroll
-      for (int k = 4; k >= 0; k--) rho = fmaf(rho, Dx, cf.k[k]);
+      for (int b = 0; b < XP; b++) {
+        const float* kb = cf.k + 10 * b;
+        const float Dx = fmaf(-dyz.z, kb[9], fmaf(-dyz.y, kb[8], fmaf(-dyz.x, kb[7], kb[6])));
+        float rb = kb[5];
+#pragma unroll
+        for (int k = 4; k >= 0; k--) rb = fmaf(rb, Dx, kb[k]);
+        rho += rb;
+      }
     } else {
       rho = rho_cell_f<KIND>(D, cf, dyz, dyz2, Dd);
     }

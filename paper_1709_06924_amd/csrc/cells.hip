@@ -255,20 +255,48 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
     }
     uint64_t em[PER];
     V3 vlo[PER], vhi[PER];
+    bool has[PER];
     double r2 = 0.0;
     int En = 0;
+    // every vertex once per cell: edge j ends at (j, hi) and starts at
+    // (j, lo), the end of edge lo (the same sorted triple, so the same bits)
     for (int k = 0; k < PER; k++) {
       const int j = G.gl + k * GS;
-      const bool has = go && er[k].status == kEdgeYes;
-      em[k] = __ballot(has) & G.gm;
+      has[k] = go && er[k].status == kEdgeYes;
+      em[k] = __ballot(has[k]) & G.gm;
       En += __popcll(em[k]);
-      vlo[k] = vhi[k] = V3{0.0, 0.0, 0.0};
-      if (has) {
-        vlo[k] = circumcentre((int)i, z, L.idx[j], S.p(j), L.idx[er[k].lo], S.p(er[k].lo));
+      vhi[k] = V3{0.0, 0.0, 0.0};
+      if (has[k]) {
         vhi[k] = circumcentre((int)i, z, L.idx[j], S.p(j), L.idx[er[k].hi], S.p(er[k].hi));
-        const V3 q0 = vlo[k] - z, q1 = vhi[k] - z;
-        r2 = fmax(r2, fmax(dot(q0, q0), dot(q1, q1)));
+        const V3 q1 = vhi[k] - z;
+        r2 = fmax(r2, dot(q1, q1));
       }
+    }
+    wave_sync();  // the candidates' differences and norms are read no more
+    for (int k = 0; k < PER; k++) {
+      const int j = G.gl + k * GS;
+      if (go && j < ns) {  // edge ends by candidate, and whose end it is
+        L.dx[j] = vhi[k].x;
+        L.dy[j] = vhi[k].y;
+        L.dz[j] = vhi[k].z;
+        L.nrm[j] = has[k] ? (double)er[k].hi : -1.0;
+      }
+    }
+    wave_sync();
+    bool broken = false;
+    for (int k = 0; k < PER; k++) {
+      const int j = G.gl + k * GS;
+      vlo[k] = V3{0.0, 0.0, 0.0};
+      if (has[k]) {
+        const int lo = er[k].lo;
+        vlo[k] = V3{L.dx[lo], L.dy[lo], L.dz[lo]};
+        broken |= L.nrm[lo] != (double)j;  // certified predicates make this impossible
+      }
+    }
+    if (go && (__ballot(broken) & G.gm)) {
+      outcome = kCellDegenerate;
+      active = false;
+      go = false;
     }
     r2 = group_max<GS>(r2);
     bool store = false;
@@ -560,7 +588,10 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
   // others so that the two halves of a wave mostly take the same path
   // (MIXED: the expansion in x only, as FP32 coefficients)
   constexpr bool POLY = KIND == kRhoTanh;
-  constexpr int kBins = (POLY ? 3 : 1) * (kVmax + 1);
+  // two chord tanh bumps: the expansion in x of each (both or nothing)
+  constexpr bool POLY2 = KIND == kRhoTanh + kVarTwo;
+  constexpr bool XPOLY = POLY || POLY2;
+  constexpr int kBins = (XPOLY ? 3 : 1) * (kVmax + 1);
   __shared__ int bin[kBins];
   __shared__ int list[kQuadCells];
   const int tid = threadIdx.x;
@@ -580,19 +611,17 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
     const int64_t i = base + tid;
     dm = min(max(o.deg[i], 0), kVmax);
     key = dm;
-    if (POLY) {
+    if (XPOLY) {
       const V3 z = V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]};
       const double r = o.R[i] * (1.0 + 1e-9);
-      double xz = 0.0;
       bool xmode = false;
       if (a.rho.polyx_n > 0) {
-        const int64_t j = polyx_index(a.rho, z, &xz);
-        const double dz = sqrt_nr_pos(fmax(2.0 * xz, 1e-300));
-        const double delta = fabs(xz - (double)j * kPolyDx) + r * (dz + 0.5 * r);
-        xmode = delta <= a.rho.polyx_tab[j].lim;
+        xmode = polyx_qualifies(a.rho, z, r, 0);
+        if (POLY2) xmode = xmode && polyx_qualifies(a.rho, z, r, 1);
       }
       key = xmode ? dm
-                  : (!MIXED && poly_qualifies(a.rho, z, r * r) ? kVmax + 1 + dm : 2 * (kVmax + 1) + dm);
+                  : (POLY && !MIXED && poly_qualifies(a.rho, z, r * r) ? kVmax + 1 + dm
+                                                                       : 2 * (kVmax + 1) + dm);
     }
   }
   if (lead) atomicAdd(&bin[key], 1);
@@ -609,7 +638,7 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
   // entries: the cell's place in the block, +256 if it takes a polynomial,
   // +512 if that is the one in x, its degree from bit 10 on
   if (lead) {
-    const int cls = POLY ? key / (kVmax + 1) : 2;
+    const int cls = XPOLY ? key / (kVmax + 1) : 2;
     list[atomicAdd(&bin[key], 1)] = tid + (cls < 2 ? 256 : 0) + (cls == 0 ? 512 : 0) + (dm << 10);
   }
   __syncthreads();
@@ -617,7 +646,7 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
   const int ln = lane_id(), w = tid >> 6, hl = ln & 31;
   const int lv = a.levels, per = 1 << (2 * lv);
   CellArgs ar = a;  // FP64 density constants held in vector registers
-  if (!MIXED) {
+  if (!MIXED && !POLY2) {  // (two bumps: the registers hold both expansions instead)
     pin_v(ar.rho.gamma);
     for (int k = 0; k < 2; k++) {
       pin_v(ar.rho.K[k]);
@@ -641,16 +670,19 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
     const int both = max(items, __shfl_xor(items, 32, 64));
     if (both == 0) continue;  // wave-uniform
     Acc5 acc = {0.0, 0.0, 0.0, 0.0, 0.0};
-    // (the mixed path has no expansion in t: its cells take x or nothing)
-    const bool xmode = POLY && (ent & 512), use_poly = POLY && (MIXED ? xmode : (ent & 256));
-    RhoPoly rp{};
+    // (the mixed path and two bumps have no expansion in t: their cells
+    // take x or nothing)
+    const bool xmode = XPOLY && (ent & 512);
+    const bool use_poly = XPOLY && (MIXED || POLY2 ? xmode : (ent & 256));
+    RhoPoly rp[POLY2 ? 2 : 1] = {};
     if (use_poly) {
       double xz;
-      rp = xmode ? ar.rho.polyx_tab[polyx_index(ar.rho, z, &xz)]
-                 : ar.rho.poly_tab[poly_index(ar.rho, z)];
+      rp[0] = xmode ? ar.rho.polyx_tab[0][polyx_index(ar.rho, z, &xz, 0)]
+                    : ar.rho.poly_tab[poly_index(ar.rho, z)];
+      if (POLY2) rp[POLY2 ? 1 : 0] = ar.rho.polyx_tab[1][polyx_index(ar.rho, z, &xz, 1)];
     }
     CellF cf{};
-    if (MIXED) cf = xmode ? cell_f32_poly(ar.rho, rp, z) : cell_f32<KIND>(ar.rho, z, tab);
+    if (MIXED) cf = xmode ? cell_f32_poly(ar.rho, rp, POLY2 ? 2 : 1, z) : cell_f32<KIND>(ar.rho, z, tab);
     if (lv == 2) {
       // the whole cell's grids (up to kGridEdges edges at a time), then its
       // leaves (FP64 grid points on both paths)
@@ -699,11 +731,13 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
             const V3 B = V3{G[e][kb][0], G[e][kb][1], G[e][kb][2]};
             const V3 C = V3{G[e][kc][0], G[e][kc][1], G[e][kc][2]};
             if (MIXED && xmode)
-              quad_leaf_mixed<KIND, true>(A, B, C, z, cf, Df, ar.rho, acc, ar.quad_rule);
-            else if (xmode)
-              quad_tri_poly<true>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
-            else if (use_poly)
-              quad_tri_poly<false>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+              quad_leaf_mixed<KIND, POLY2 ? 2 : 1>(A, B, C, z, cf, Df, ar.rho, acc, ar.quad_rule);
+            else if (POLY2 && xmode)
+              quad_tri_poly2(A, B, C, z, ar.rho, rp[0], rp[POLY2 ? 1 : 0], acc, ar.quad_rule);
+            else if (POLY && xmode)
+              quad_tri_poly<true>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
+            else if (POLY && use_poly)
+              quad_tri_poly<false>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
             else
               quad_item<KIND, MIXED>(ar, A, B, C, z, cf, Df, tab, acc);
           }
@@ -719,11 +753,13 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
         V3 C = V3{ed[3], ed[4], ed[5]};
         subtriangle(A, B, C, sub, lv);
         if (MIXED && xmode)
-          quad_leaf_mixed<KIND, true>(A, B, C, z, cf, Df, ar.rho, acc, ar.quad_rule);
-        else if (xmode)
-          quad_tri_poly<true>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
-        else if (use_poly)
-          quad_tri_poly<false>(A, B, C, z, ar.rho, rp, acc, ar.quad_rule);
+          quad_leaf_mixed<KIND, POLY2 ? 2 : 1>(A, B, C, z, cf, Df, ar.rho, acc, ar.quad_rule);
+        else if (POLY2 && xmode)
+          quad_tri_poly2(A, B, C, z, ar.rho, rp[0], rp[POLY2 ? 1 : 0], acc, ar.quad_rule);
+        else if (POLY && xmode)
+          quad_tri_poly<true>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
+        else if (POLY && use_poly)
+          quad_tri_poly<false>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
         else
           quad_item<KIND, MIXED>(ar, A, B, C, z, cf, Df, tab, acc);
       }
@@ -803,16 +839,23 @@ hipError_t launch_cells_many(const CellArgs* tab, const int32_t* nb_main, int ma
 
 // the density polynomials' tables (single chord tanh bump): entry j per
 // thread, of the expansion in t (X = false) or in x
+// the tables' entries, one per thread (x tables: blockIdx.y = bump)
 template <bool X>
-__global__ void k_poly_table(DensityP D, RhoPoly* out) {
+__global__ void k_poly_table(DensityP D, RhoPoly* out, RhoPoly* out2) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < (X ? D.polyx_n : D.poly_n)) out[j] = X ? polyx_entry(D, j, kExp2Tab) : poly_entry(D, j, kExp2Tab);
+  const int b = (int)blockIdx.y;
+  if (j < (X ? D.polyx_n : D.poly_n))
+    (b ? out2 : out)[j] = X ? polyx_entry(D, j, b, kExp2Tab) : poly_entry(D, j, kExp2Tab);
 }
 
-hipError_t launch_poly_table(const DensityP& D, RhoPoly* out, RhoPoly* outx, hipStream_t s) {
-  if (D.poly_n > 0) k_poly_table<false><<<(unsigned)((D.poly_n + 255) / 256), 256, 0, s>>>(D, out);
-  if (D.polyx_n > 0)
-    k_poly_table<true><<<(unsigned)((D.polyx_n + 255) / 256), 256, 0, s>>>(D, outx);
+hipError_t launch_poly_table(const DensityP& D, RhoPoly* out, RhoPoly* outx0, RhoPoly* outx1,
+                             hipStream_t s) {
+  if (D.poly_n > 0)
+    k_poly_table<false><<<(unsigned)((D.poly_n + 255) / 256), 256, 0, s>>>(D, out, out);
+  if (D.polyx_n > 0) {
+    const dim3 g((unsigned)((D.polyx_n + 255) / 256), D.nbumps == 2 ? 2 : 1);
+    k_poly_table<true><<<g, 256, 0, s>>>(D, outx0, outx1);
+  }
   return hipGetLastError();
 }
 

@@ -1071,10 +1071,10 @@ int alloc_device_state(scvt_handle* h) {
     ALLOC(t, h->rho.poly_n);
     h->rho.poly_tab = t;
   }
-  if (h->rho.polyx_n > 0) {
+  for (int b = 0; h->rho.polyx_n > 0 && b < (h->rho.nbumps == 2 ? 2 : 1); b++) {
     RhoPoly* t = nullptr;
     ALLOC(t, h->rho.polyx_n);
-    h->rho.polyx_tab = t;
+    h->rho.polyx_tab[b] = t;
   }
   return SCVT_OK;
 }
@@ -1104,7 +1104,8 @@ int init_device_state(scvt_handle* h) {
   HIPCK(launch_fill_i32((int32_t*)h->dscal, 0, 2 * kNScal, st));
   HIPCK(launch_fill_i32((int32_t*)h->q, 0, 6 * n, st));
   HIPCK(launch_poly_table(h->rho, const_cast<RhoPoly*>(h->rho.poly_tab),
-                          const_cast<RhoPoly*>(h->rho.polyx_tab), st));
+                          const_cast<RhoPoly*>(h->rho.polyx_tab[0]),
+                          const_cast<RhoPoly*>(h->rho.polyx_tab[1]), st));
   for (int s = h->nslots - 1; s >= 0; s--) h->free_slots.push_back(s);
   h->main_path = n > 256 ? 1 : 0;
   h->r_default = 2.0 * sqrt(4.0 * 3.141592653589793 / (double)n);

@@ -166,7 +166,8 @@ hipError_t launch_refine_emit(const double* Z, const int32_t* deg, const int32_t
 hipError_t launch_cells_main(const CellArgs& a, hipStream_t s);
 hipError_t launch_cells_tiers(const CellArgs& a, hipStream_t s);
 hipError_t launch_cells_fallback(const CellArgs& a, int all, hipStream_t s);
-hipError_t launch_poly_table(const DensityP& D, RhoPoly* out, RhoPoly* outx, hipStream_t s);
+hipError_t launch_poly_table(const DensityP& D, RhoPoly* out, RhoPoly* outx0, RhoPoly* outx1,
+                             hipStream_t s);
 hipError_t launch_quad(const CellArgs& a, hipStream_t s);
 hipError_t launch_centroid(const double* mu, const double* m, double* out, int64_t n,
                            hipStream_t s);

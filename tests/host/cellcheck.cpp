@@ -155,7 +155,8 @@ int hc_quad_poly(const double* z3, int E, const double* verts, const DensityP* D
                  int nq, double* out5, int force) {
   Acc5 acc = {0, 0, 0, 0, 0};
   DensityP Dp = density_prepare(*D);
-  if (Dp.kind != kRhoTanh || Dp.nbumps != 1 || Dp.geodesic) return 0;
+  if (Dp.kind != kRhoTanh || Dp.geodesic || Dp.polyx_n == 0) return 0;
+  const int nb = Dp.nbumps;
   V3 z = V3{z3[0], z3[1], z3[2]};
   double r2 = 0.0;
   for (int e = 0; e < E; e++)
@@ -164,24 +165,32 @@ int hc_quad_poly(const double* z3, int E, const double* verts, const DensityP* D
       r2 = fmax(r2, dot(v, v));
     }
   const double r = sqrt(r2);
-  double xz = 0.0;
-  const int64_t jx = polyx_index(Dp, z, &xz);
-  const RhoPoly PX = polyx_entry(Dp, jx);
-  const double delta = fabs(xz - (double)jx * kPolyDx) + r * (sqrt(2.0 * xz) + 0.5 * r);
-  const bool xq = delta <= PX.lim, tq = poly_qualifies(Dp, z, r2);
+  // the x entries of every bump, and whether the fan lies inside each radius
+  RhoPoly PX[2];
+  bool xq = true;
+  for (int b = 0; b < nb; b++) {
+    double xz = 0.0;
+    const int64_t jx = polyx_index(Dp, z, &xz, b);
+    PX[b] = polyx_entry(Dp, jx, b);
+    const double delta = fabs(xz - (double)jx * kPolyDx) + r * (sqrt(2.0 * xz) + 0.5 * r);
+    xq = xq && delta <= PX[b].lim;
+  }
+  const bool tq = nb == 1 && poly_qualifies(Dp, z, r2);
   int mode = 0;
   if (force == 2) mode = xq ? 2 : 0;
   else if (force == 1) mode = tq ? 1 : 0;
   else mode = xq ? 2 : (tq ? 1 : 0);
   if (mode == 0) return 0;
-  const RhoPoly P = mode == 2 ? PX : poly_entry(Dp, poly_index(Dp, z));
+  const RhoPoly P = mode == 2 ? PX[0] : poly_entry(Dp, poly_index(Dp, z));
   const int per = 1 << (2 * levels);
   for (int t = 0; t < E * per; t++) {
     int e = t >> (2 * levels), s = t & (per - 1);
     V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
        C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
     subtriangle(A, B, C, s, levels);
-    if (mode == 2)
+    if (mode == 2 && nb == 2)
+      quad_tri_poly2(A, B, C, z, Dp, PX[0], PX[1], acc, nq);
+    else if (mode == 2)
       quad_tri_poly<true>(A, B, C, z, Dp, P, acc, nq);
     else
       quad_tri_poly<false>(A, B, C, z, Dp, P, acc, nq);
@@ -194,6 +203,52 @@ int hc_quad_poly(const double* z3, int E, const double* verts, const DensityP* D
   return mode;
 }
 
+// Mixed-precision cell integrals through the FP32 copies of the expansions
+// in x (one or two chord tanh bumps), as the mixed kernel takes a qualifying
+// cell; returns 0 (nothing computed) if the fan is not inside every entry's
+// radius.
+int hc_quad_mixed_poly(const double* z3, int E, const double* verts, const DensityP* D,
+                       int levels, int nq, double* out5) {
+  Acc5 acc = {0, 0, 0, 0, 0};
+  DensityP Dp = density_prepare(*D);
+  if (Dp.kind != kRhoTanh || Dp.geodesic || Dp.polyx_n == 0) return 0;
+  const int nb = Dp.nbumps;
+  const V3 z = V3{z3[0], z3[1], z3[2]};
+  double r2 = 0.0;
+  for (int e = 0; e < E; e++)
+    for (int c = 0; c < 2; c++) {
+      const V3 v = V3{verts[6 * e + 3 * c], verts[6 * e + 3 * c + 1], verts[6 * e + 3 * c + 2]} - z;
+      r2 = fmax(r2, dot(v, v));
+    }
+  const double r = sqrt(r2);
+  RhoPoly PX[2];
+  for (int b = 0; b < nb; b++) {
+    double xz = 0.0;
+    const int64_t jx = polyx_index(Dp, z, &xz, b);
+    PX[b] = polyx_entry(Dp, jx, b);
+    if (fabs(xz - (double)jx * kPolyDx) + r * (sqrt(2.0 * xz) + 0.5 * r) > PX[b].lim) return 0;
+  }
+  const CellF cf = cell_f32_poly(Dp, PX, nb, z);
+  const DensityF Df = density_f32(Dp);
+  const int per = 1 << (2 * levels);
+  for (int t = 0; t < E * per; t++) {
+    int e = t >> (2 * levels), s = t & (per - 1);
+    V3 A = z, B = V3{verts[6 * e], verts[6 * e + 1], verts[6 * e + 2]},
+       C = V3{verts[6 * e + 3], verts[6 * e + 4], verts[6 * e + 5]};
+    subtriangle(A, B, C, s, levels);
+    if (nb == 2)
+      quad_leaf_mixed<kRhoTanh + kVarTwo, 2>(A, B, C, z, cf, Df, Dp, acc, nq);
+    else
+      quad_leaf_mixed<kRhoTanh, 1>(A, B, C, z, cf, Df, Dp, acc, nq);
+  }
+  out5[0] = acc.m;  // mu = m z + int rho (y - z)
+  out5[1] = acc.m * z.x + acc.mx;
+  out5[2] = acc.m * z.y + acc.my;
+  out5[3] = acc.m * z.z + acc.mz;
+  out5[4] = acc.e;
+  return 1;
+}
+
 // rho at the unit points y (n x 3) from the polynomial table's entry of
 // generator z (mode 0: in t, 1: in x), and from the exact evaluation; lim
 // receives the x entry's radius
@@ -201,18 +256,28 @@ int hc_rho_poly(const double* z3, const DensityP* D, int64_t n, const double* y,
                 double* exact, int mode, double* lim) {
   DensityP Dp = density_prepare(*D);
   V3 z = V3{z3[0], z3[1], z3[2]};
-  double xz = 0.0;
-  const RhoPoly P = mode == 1 ? polyx_entry(Dp, polyx_index(Dp, z, &xz))
-                              : poly_entry(Dp, poly_index(Dp, z));
-  *lim = P.lim;
+  // two bumps (x only): the sum of both entries' polynomials, lim the smaller radius
+  const int nb = mode == 1 ? Dp.nbumps : 1;
+  RhoPoly P[2];
+  *lim = 1e300;
+  for (int b = 0; b < nb; b++) {
+    double xz = 0.0;
+    P[b] = mode == 1 ? polyx_entry(Dp, polyx_index(Dp, z, &xz, b), b)
+                     : poly_entry(Dp, poly_index(Dp, z));
+    *lim = fmin(*lim, P[b].lim);
+  }
   for (int64_t k = 0; k < n; k++) {
     const V3 p = V3{y[3 * k], y[3 * k + 1], y[3 * k + 2]};
-    const double u = fma(-1.0, dot(p, V3{Dp.xc[0][0], Dp.xc[0][1], Dp.xc[0][2]}),
-                         mode == 1 ? P.off : Dp.cc[0]);
-    const double dl = mode == 1 ? u : fma(sqrt_nr_pos(fmax(u, 1e-300)), Dp.Kt[0], P.off);
-    double r = P.c[kPolyDeg];
-    for (int j = kPolyDeg - 1; j >= 0; j--) r = fma(r, dl, P.c[j]);
-    poly[k] = r;
+    double sum = 0.0;
+    for (int b = 0; b < nb; b++) {
+      const double u = fma(-1.0, dot(p, V3{Dp.xc[b][0], Dp.xc[b][1], Dp.xc[b][2]}),
+                           mode == 1 ? P[b].off : Dp.cc[0]);
+      const double dl = mode == 1 ? u : fma(sqrt_nr_pos(fmax(u, 1e-300)), Dp.Kt[0], P[b].off);
+      double r = P[b].c[kPolyDeg];
+      for (int j = kPolyDeg - 1; j >= 0; j--) r = fma(r, dl, P[b].c[j]);
+      sum += r;
+    }
+    poly[k] = sum;
     exact[k] = rho_eval(Dp, p);
   }
   return 0;

@@ -74,7 +74,7 @@ class CDensity(ctypes.Structure):
                 ("cc", ctypes.c_double * 2), ("Kt", ctypes.c_double * 2),
                 ("poly_r2", ctypes.c_double * 2), ("poly_near2", ctypes.c_double * 2),
                 ("poly_tab", ctypes.c_void_p), ("poly_n", ctypes.c_int64),
-                ("polyx_tab", ctypes.c_void_p), ("polyx_n", ctypes.c_int64)]
+                ("polyx_tab", ctypes.c_void_p * 2), ("polyx_n", ctypes.c_int64)]
 
 
 KIND = {"const": 0, "tanh": 1, "x3": 2, "x16": 3}
@@ -134,6 +134,18 @@ def rho_poly(z, density, Y, mode=0):
     lib().hc_rho_poly(P(z), ctypes.byref(D), ctypes.c_int64(len(Y)), P(Y), P(poly), P(exact),
                       ctypes.c_int(mode), P(lim))
     return poly, exact, float(lim[0])
+
+
+def quad_mixed_poly(z, E, verts, density, levels=2, rule=7):
+    """Mixed-precision cell integrals through the FP32 expansions in x (one
+    or two bumps), or None if the cell does not qualify."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    out = np.zeros(5)
+    D = cdensity(density)
+    ok = lib().hc_quad_mixed_poly(P(z), ctypes.c_int(E), P(verts), ctypes.byref(D),
+                                  ctypes.c_int(levels), ctypes.c_int(rule), P(out))
+    return out if ok else None
 
 
 def quad_mixed(z, E, verts, density, levels=2, rule=7):

@@ -86,11 +86,24 @@ def clustered_c3():
     return Z, d
 
 
+def clustered_two_centre():
+    """20,011 uniform generators of the two-centre density plus dense
+    clusters at chord 0.35 from each bump's centre (30,000 and 20,000, cells
+    inside both bumps' expansions in x) and 1,200 at the first centre (small
+    cells that must not take them)."""
+    d = I.density_two_centre()
+    x0, x1 = np.array(d["xc"][0]), np.array(d["xc"][1])
+    Z = np.concatenate([I.uniform_sphere(20011, 17), I.cap_points(I.toward(x0, 0.35, 18), 0.25, 30000, 19),
+                        I.cap_points(I.toward(x1, 0.35, 20), 0.25, 20000, 21),
+                        I.cap_points(x0, 0.05, 1200, 22)])
+    return Z, d
+
+
 @pytest.mark.parametrize("case", ["c1_const", "tanh_ragged", "x3", "two_centre", "geodesic",
-                                  "tanh16_clustered"])
+                                  "tanh16_clustered", "two_centre_clustered"])
 def test_evaluation_parity(scvt, case):
-    if case == "tanh16_clustered":
-        Z, d = clustered_c3()
+    if case in ("tanh16_clustered", "two_centre_clustered"):
+        Z, d = clustered_c3() if case == "tanh16_clustered" else clustered_two_centre()
         n = len(Z)
     else:
         n, d, seed = {

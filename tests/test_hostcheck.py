@@ -395,3 +395,109 @@ def test_density_polynomial_in_x_within_bound(chord):
         Yf = I.cap_points(z, 4 * rcap, 20000, 5)
         pf, ef, _ = hc.rho_poly(z, d, Yf, mode=1)
         assert (np.abs(pf - ef) / ef).max() > 10 * rel.max()
+
+
+def two_centre_point(bump, chord, seed):
+    d = I.density_two_centre()
+    return d, I.toward(np.array(d["xc"][bump]), chord, seed)
+
+
+@pytest.mark.parametrize("bump,chord", [(0, 0.45), (0, 1.0), (1, 0.3), (1, 0.8)])
+def test_two_bump_expansion_in_x_within_bound(bump, chord):
+    """Two chord tanh bumps: the sum of both bumps' expansions in x (each
+    from its own table, gamma carried by the first) agrees with the direct
+    density wherever both entries' radii cover the point's |x - x*| (the
+    smaller radius taken for both), and the radius covers the cells of the
+    first bump at n = 4,194,304 (R ~ 3e-4) at these distances."""
+    d, z = two_centre_point(bump, chord, 3)
+    _, _, lim = hc.rho_poly(z, d, z[None, :], mode=1)
+    slack = lim
+    for b in range(2):
+        xc = np.array(d["xc"][b])
+        xz = 0.5 * float(np.sum((z - xc) ** 2))
+        slack_b = lim - abs(xz - round(xz / 1e-4) * 1e-4)
+        slack = min(slack, slack_b / (math.sqrt(2 * xz) + slack_b))
+    assert slack >= 5e-4, slack
+    Y = I.cap_points(z, 0.999 * slack, 20000, 4)
+    poly, exact, _ = hc.rho_poly(z, d, Y, mode=1)
+    rel = np.abs(poly - exact) / exact
+    assert rel.max() < 1.5e-14, rel.max()
+
+
+def two_centre_clusters():
+    """Generators of the two-centre density: dense clusters at chord 0.35
+    from each bump's centre (cells small enough for both expansions in x),
+    one at the first centre (too close to it), and a uniform background."""
+    d = I.density_two_centre()
+    x0, x1 = np.array(d["xc"][0]), np.array(d["xc"][1])
+    Z = np.concatenate([I.cap_points(I.toward(x0, 0.35, 7), 0.012, 600, 8),
+                        I.cap_points(I.toward(x1, 0.35, 9), 0.012, 400, 10),
+                        I.cap_points(x0, 0.004, 100, 11), I.uniform_sphere(300, 12)])
+    rad = np.concatenate([np.full(1000, 4 * 0.012 / math.sqrt(400)), np.full(100, 4e-3),
+                          np.full(300, 4 * math.sqrt(4 * math.pi / 300))])
+    return d, Z, rad
+
+
+def test_two_bump_polynomial_quadrature_matches_oracle():
+    """Cells of the two-centre density inside both bumps' expansion radii:
+    their integrals through the two expansions in x agree with the direct
+    FP64 path on the same vertices to 2e-14 and with the oracle to 1e-12 on
+    m and mu and 3e-12 on e (as for one bump); cells at the first bump's
+    centre do not qualify."""
+    d, Z, rad = two_centre_clusters()
+    ev = oracle.evaluate(Z, d)
+    st, deg, nbr, verts, R = hc.cells(Z, rad)
+    used = 0
+    worst = [0.0, 0.0, 0.0, 0.0]
+    for k in np.where(st == 0)[0]:
+        res = hc.quad_poly(Z[k], deg[k], verts[k], d, force=2)
+        if 1000 <= k < 1100:
+            assert res is None  # at the centre: the entry radius shrinks to nothing
+        if res is None:
+            continue
+        out = res[0]
+        used += 1
+        ref = hc.quad(Z[k], deg[k], verts[k], d)
+        worst[0] = max(worst[0], abs(out[0] - ev.m[k]) / ev.m[k])
+        worst[1] = max(worst[1], np.linalg.norm(out[1:4] - ev.mu[k]) / np.linalg.norm(ev.mu[k]))
+        worst[2] = max(worst[2], abs(out[4] - ev.e[k]) / ev.e[k])
+        worst[3] = max(worst[3], abs(out[0] - ref[0]) / ref[0], abs(out[4] - ref[4]) / ref[4])
+    assert used >= 700, used
+    assert max(worst[:2]) < 1e-12 and worst[2] < 3e-12, worst
+    assert worst[3] < 2e-14, worst
+
+
+@pytest.mark.parametrize("density", ["tanh16", "two"])
+def test_mixed_expansion_in_x_error(density):
+    """The mixed path's FP32 copies of the expansions in x (degree 5, one or
+    two bumps) on cells inside the entries' radii, against the FP64 oracle:
+    per cell |dm|/m and |de|/e <= 1e-5 and centroid error <= 1e-7 h_i."""
+    if density == "two":
+        d, Z, rad = two_centre_clusters()
+    else:
+        d = I.CONFIGS["C3"]["density"]
+        xc = np.array(d["xc"][0])
+        Z = np.concatenate([I.cap_points(I.toward(xc, 0.349, 7), 0.012, 600, 8),
+                            I.uniform_sphere(200, 9)])
+        rad = np.concatenate([np.full(600, 4 * 0.012 / math.sqrt(600)),
+                              np.full(200, 4 * math.sqrt(4 * math.pi / 200))])
+    n = len(Z)
+    ev = oracle.evaluate(Z, d)
+    i, j, _ = oracle.neighbour_sets(Z, ev.cells)
+    dist = np.linalg.norm(Z[i] - Z[j], axis=1)
+    hi = (np.bincount(i, dist, n) + np.bincount(j, dist, n)) / (
+        np.bincount(i, minlength=n) + np.bincount(j, minlength=n))
+    st, deg, nbr, verts, R = hc.cells(Z, rad)
+    used = 0
+    worst = 0.0
+    for k in np.where(st == 0)[0]:
+        out = hc.quad_mixed_poly(Z[k], deg[k], verts[k], d)
+        if out is None:
+            continue
+        used += 1
+        assert abs(out[0] - ev.m[k]) <= 1e-5 * ev.m[k]
+        assert abs(out[4] - ev.e[k]) <= 1e-5 * ev.e[k]
+        worst = max(worst, np.linalg.norm(out[1:4] / out[0] - ev.centroid[k]) / hi[k])
+    print("mixed expansion in x, %s: %d cells, max centroid error / h = %.2e" % (density, used, worst))
+    assert used >= 400, used
+    assert worst <= 1e-7
