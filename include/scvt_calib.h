@@ -9,6 +9,8 @@
 #ifndef SCVT_CALIB_H
 #define SCVT_CALIB_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -26,6 +28,16 @@ int scvt_calib_count(void);
  * allocates (and frees) a 4 MiB output buffer.  Returns 0, or -1 on any HIP
  * error. */
 int scvt_calib_valu(double* ns, int reps);
+
+/* Checking only: the device values of the solver's refined special
+ * functions, whose error bounds the host build cannot test.  x: host array
+ * of n doubles; out: host array of n x 9 doubles, owned by the caller; row i
+ * receives rsq_pos, rcp_fast, sqrt_fast, rcp_nr, sqrt_nr, rsq_near1 of x[i]
+ * (FP64) and the FP32 hardware reciprocal square root, reciprocal and 2^x
+ * of (float)x[i], as the kernels evaluate them.  Allocates and frees its own
+ * device buffers on the current device.  Returns 0, or -1 on a HIP error or
+ * n < 0. */
+int scvt_calib_math(int64_t n, const double* x, double* out);
 
 #ifdef __cplusplus
 }

@@ -5,10 +5,15 @@
 // denominators (FP64 and FP32 FMA rates) and prices the special functions
 // (rsqrt, reciprocal, exp) that the quadrature's points use.
 //
-// Built into libscvt_calib.so; called by `bench.py --valu-rates`.
+// Built into libscvt_calib.so; called by `bench.py --valu-rates`.  It also
+// evaluates the solver's refined special functions on the device
+// (scvt_calib_math), whose error bounds the host build cannot check: there
+// they are exact divisions and square roots.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+
+#include "cellgeom.h"
 
 namespace {
 
@@ -73,9 +78,51 @@ hipError_t launch_rate(int k, double* out, hipStream_t s) {
   return hipGetLastError();
 }
 
+// the device values of the refined special functions, one x per thread
+constexpr int kMathOut = 9;
+__global__ void k_math(const double* x, double* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = x[i];
+  double* o = out + i * kMathOut;
+  o[0] = scvt::rsq_pos(v);
+  o[1] = scvt::rcp_fast(v);
+  o[2] = scvt::sqrt_fast(v);
+  o[3] = scvt::rcp_nr(v);
+  o[4] = scvt::sqrt_nr(v);
+  o[5] = scvt::rsq_near1(v);
+  o[6] = (double)scvt::rsqf((float)v);
+  o[7] = (double)scvt::rcpf((float)v);
+  o[8] = (double)scvt::exp2_hw((float)v);
+}
+
 }  // namespace
 
 extern "C" {
+
+// out (host, n x 9, caller-owned): for each x[i] (host) the device's
+// rsq_pos, rcp_fast, sqrt_fast, rcp_nr, sqrt_nr, rsq_near1 (FP64) and the
+// FP32 hardware rsqrt, reciprocal and 2^x of (float)x.  Allocates and frees
+// its own device buffers.  Returns 0, or -1 on a HIP error or n < 0.
+int scvt_calib_math(int64_t n, const double* x, double* out) {
+  if (n < 0) return -1;
+  if (n == 0) return 0;
+  double *dx = nullptr, *dout = nullptr;
+  int rc = 0;
+  if (hipMalloc(&dx, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&dout, sizeof(double) * n * kMathOut) != hipSuccess)
+    rc = -1;
+  if (!rc && hipMemcpy(dx, x, sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess) rc = -1;
+  if (!rc) {
+    k_math<<<(unsigned)((n + 255) / 256), 256>>>(dx, dout, n);
+    if (hipGetLastError() != hipSuccess) rc = -1;
+  }
+  if (!rc && hipMemcpy(out, dout, sizeof(double) * n * kMathOut, hipMemcpyDeviceToHost) != hipSuccess)
+    rc = -1;
+  if (dx) hipFree(dx);
+  if (dout) hipFree(dout);
+  return rc;
+}
 
 // Number of measured instruction kinds.
 int scvt_calib_count() { return kOps; }

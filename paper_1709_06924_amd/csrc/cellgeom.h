@@ -215,96 +215,94 @@ SCVT_HD V3 circumcentre(int ia, V3 pa, int ib, V3 pb, int ic, V3 pc) {
 }
 
 // ------------------------------------------ edge of the cell on one bisector
-// Candidate set S (positions p_l and differences d_l = p_l - z).  In the
-// gnomonic chart at z every bisector is a straight line and the cell is the
-// convex polygon of the half-planes containing z.  For the line of candidate
-// j, every other candidate l bounds it from one side; the sign of
-// sigma_jl = det(z, d_j, d_l) says which (> 0: an upper bound in the
-// counter-clockwise direction).  Two bounds l, m of the same kind are ordered
-// by the in-circle determinant det(d_j, d_l, d_m) (its sign says whether the
-// vertex (j,l) lies inside the half-space of m).  The edge on line j runs from
-// the tightest lower bound `lo` to the tightest upper bound `hi`, counter-
-// clockwise seen from outside the sphere, and exists if lo < hi.
+// Candidate set S (positions p_l and differences d_l = p_l - z).  Every
+// bisector is the plane through the origin with normal d_l, and the cell is
+// the part of the sphere on z's side of all of them, y . d_l <= 0.  The plane
+// of candidate j holds the great circle y(t) = m_j + t b_j with m_j = z - c_j
+// d_j, c_j = z.d_j / |d_j|^2 (z projected onto the plane) and b_j = z x d_j
+// (t increasing counter-clockwise seen from outside the sphere); candidate l
+// bounds it by num_l + t sg_l <= 0 with
+//   sg_l = b_j . d_l = det(z, d_j, d_l),  num_l = m_j . d_l = z.d_l - c_j d_j.d_l,
+// an upper bound t <= -num_l/sg_l when sg_l > 0, a lower bound when sg_l < 0.
+// Bound l is tighter than bound a of the same kind when
+//   cmp = num_l sg_a - num_a sg_l
+// is positive (upper) or negative (lower): the vertex (j, a) violates l, the
+// sign of det(d_j, d_a, d_l) (scalars only, so the scan over l keeps two
+// numbers per side instead of a cross product).  The edge runs from the
+// tightest lower bound `lo` to the tightest upper bound `hi` and exists if
+// num_hi sg_lo - num_lo sg_hi > 0.
+//
+// Certification: with E = max |d_l| over the candidates (nm) and u = 2^-53,
+// the computed sg_l, num_l err by at most 96u |d_j||d_l| and 16u E (z.d_l and
+// d_j.d_l from rounded differences, c_j's rounding), and are bounded by
+// |d_j| E and E (E + |d_j|)/2; a comparison of two bounds then errs by at
+// most B = 1.1 (2 (16u E Sb + Nb 96u |d_j| E) + 4u Nb Sb) with Sb, Nb those
+// bounds.  A comparison within B, or a line (nearly) parallel to j in the
+// chart (|sg_l| within its error), settles nothing by itself: the latter is
+// decided at the foot of line j, the former makes the cell degenerate (it
+// goes to the sequential clipper).  B / |cmp| is ~u/h for cells of size h.
 enum EdgeStatus { kEdgeNone = 0, kEdgeYes = 1, kEdgeUnbounded = 2, kEdgeDegenerate = 3 };
 struct EdgeRes {
   int status, lo, hi;
 };
 
 struct CandView {  // structure-of-arrays view (LDS on the device)
-  const double *px, *py, *pz, *dx, *dy, *dz, *nrm;  // nrm[l] = |d_l|
+  const double *px, *py, *pz, *dx, *dy, *dz, *nrm, *zd;  // nrm[l] = |d_l|, zd[l] = z . d_l
   SCVT_HD V3 p(int l) const { return V3{px[l], py[l], pz[l]}; }
   SCVT_HD V3 d(int l) const { return V3{dx[l], dy[l], dz[l]}; }
 };
 
 // Error bound for det(a, b, c) of rounded difference vectors: 16u times the
-// permanent (see det_pred), and the permanent's six terms are each at most
-// |a||b||c|, so 96u |a||b||c| bounds the error from the norms alone.
+// permanent, whose six terms are each at most |a||b||c|: 96u |a||b||c|.
 constexpr double kDetBound = 96.0 * kU;
 
-SCVT_HD EdgeRes edge_on_bisector(int j, int ns, V3 z, const CandView& S) {
+// nm: the largest |d_l| of the candidate set (at least |d_j|)
+SCVT_HD EdgeRes edge_on_bisector(int j, int ns, V3 z, const CandView& S, double nm) {
   const V3 dj = S.d(j), pj = S.p(j);
   const double nj = S.nrm[j];
-  // sigma_jl = det(z, d_j, d_l) = d_l . (z x d_j), |z| = 1
   const V3 wj = cross(z, dj);
-  const double ebj = kDetBound * nj;
+  const double cj = S.zd[j] / dot(dj, dj);
+  const double ebj = kDetBound * nj;  // |sg_l| error bound / |d_l|
+  const double Sb = 1.01 * nj * nm, Nb = 0.5 * nm * (nm + nj) + 16.0 * kU * nm;
+  const double B = 1.1 * (2.0 * (16.0 * kU * nm * Sb + Nb * kDetBound * nj * nm) + 4.0 * kU * Nb * Sb);
+  // the tightest bounds so far; (-1, 0) stands for none (t = +-inf)
   int lo = -1, hi = -1;
-  V3 clo = V3{0, 0, 0}, chi = V3{0, 0, 0};  // d_j x d_lo, d_j x d_hi
-  double elo = 0.0, ehi = 0.0;              // kDetBound |d_j| |d_lo| (|d_hi|)
-  bool degenerate = false;
-  for (int l = 0; l < ns; l++) {
-    if (l == j) continue;
+  double nlo = -1.0, slo = 0.0, nhi = -1.0, shi = 0.0;
+  bool degenerate = false, none = false;
+  for (int l = 0; l < ns; l++) {  // straight-line but for the rare parallel case
     const V3 dl = S.d(l);
-    const double nl = S.nrm[l];
     const double sg = dot(dl, wj);
-    if (fabs(sg) <= ebj * nl) {
+    const double num = fma(-cj, dot(dj, dl), S.zd[l]);
+    const bool self = l == j;
+    const bool par = !self && fabs(sg) <= ebj * S.nrm[l];
+    if (par) {
       // lines (nearly) parallel in the chart: line l either leaves all of
       // line j feasible or none of it; decided at the foot of line j by the
       // sign of d_l . (p_l - p_j)
-      V3 pl = S.p(l), dd = pl - pj;
-      double s = dot(dl, dd);
-      double se = 16.0 * kU * (fabs(dl.x * dd.x) + fabs(dl.y * dd.y) + fabs(dl.z * dd.z));
-      if (s > se) continue;
-      if (s < -se) return EdgeRes{kEdgeNone, -1, -1};
-      degenerate = true;
-      continue;
+      const V3 dd = S.p(l) - pj;
+      const double t = dot(dl, dd);
+      const double te = 16.0 * kU * (fabs(dl.x * dd.x) + fabs(dl.y * dd.y) + fabs(dl.z * dd.z));
+      none |= t < -te;
+      degenerate |= fabs(t) <= te;
     }
-    if (sg > 0.0) {
-      if (hi < 0) {
-        hi = l;
-        chi = cross(dj, dl);
-        ehi = ebj * nl;
-      } else {
-        const double o = dot(dl, chi);  // det(d_j, d_hi, d_l)
-        if (fabs(o) <= ehi * nl) {
-          degenerate = true;
-        } else if (o > 0.0) {  // vertex (j,hi) violates l: l is tighter
-          hi = l;
-          chi = cross(dj, dl);
-          ehi = ebj * nl;
-        }
-      }
-    } else {
-      if (lo < 0) {
-        lo = l;
-        clo = cross(dj, dl);
-        elo = ebj * nl;
-      } else {
-        const double o = dot(dl, clo);  // det(d_j, d_lo, d_l)
-        if (fabs(o) <= elo * nl) {
-          degenerate = true;
-        } else if (o < 0.0) {
-          lo = l;
-          clo = cross(dj, dl);
-          elo = ebj * nl;
-        }
-      }
-    }
+    const bool up = sg > 0.0, use = !self && !par;
+    // > 0: l is tighter than the side's current bound
+    const double c = up ? fma(num, shi, -nhi * sg) : -fma(num, slo, -nlo * sg);
+    degenerate |= use && (up ? hi : lo) >= 0 && fabs(c) <= B;
+    const bool th = use && up && c > 0.0, tl = use && !up && c > 0.0;
+    hi = th ? l : hi;
+    nhi = th ? num : nhi;
+    shi = th ? sg : shi;
+    lo = tl ? l : lo;
+    nlo = tl ? num : nlo;
+    slo = tl ? sg : slo;
   }
+  if (none) return EdgeRes{kEdgeNone, -1, -1};  // excluded by a parallel line
   if (degenerate) return EdgeRes{kEdgeDegenerate, lo, hi};
   if (lo < 0 || hi < 0) return EdgeRes{kEdgeUnbounded, lo, hi};
-  const double o = dot(S.d(hi), clo);  // det(d_j, d_lo, d_hi) > 0  <=>  lo < hi
-  if (fabs(o) <= elo * S.nrm[hi]) return EdgeRes{kEdgeDegenerate, lo, hi};
-  return EdgeRes{o > 0.0 ? kEdgeYes : kEdgeNone, lo, hi};
+  const double x = fma(nhi, slo, -nlo * shi);
+  if (fabs(x) <= B) return EdgeRes{kEdgeDegenerate, lo, hi};
+  return EdgeRes{x > 0.0 ? kEdgeYes : kEdgeNone, lo, hi};
 }
 
 // ------------------------------------------------------------- densities
@@ -1121,7 +1119,6 @@ SCVT_HD void quad_leaf_mixed(V3 A, V3 B, V3 C, V3 z, const CellF& cf, const Dens
     const float dyz2 = dotf(dyz, dyz);
     float rho;
     if (XP > 0) {  // the expansions in x of XP bumps
-      rho = 0.0f;
 #pragma unroll
       for (int b = 0; b < XP; b++) {
         const float* kb = cf.k + 10 * b;
@@ -1129,7 +1126,7 @@ SCVT_HD void quad_leaf_mixed(V3 A, V3 B, V3 C, V3 z, const CellF& cf, const Dens
         float rb = kb[5];
 #pragma unroll
         for (int k = 4; k >= 0; k--) rb = fmaf(rb, Dx, kb[k]);
-        rho += rb;
+        rho = b == 0 ? rb : rho + rb;
       }
     } else {
       rho = rho_cell_f<KIND>(D, cf, dyz, dyz2, Dd);
@@ -1151,7 +1148,10 @@ SCVT_HD void quad_leaf_mixed(V3 A, V3 B, V3 C, V3 z, const CellF& cf, const Dens
     const float rm1 = s * fmaf(s, 0.375f, -0.5f);
     point(Rq, rm1, rm1 * fmaf(rm1, 3.0f, 3.0f));
   };
-  if (form == 0 && nq == 7) {  // the rule's constants as immediates
+  // the polynomial points and the single bump's direct ones with the rule's
+  // constants as immediates (unrolled, the other densities run out of
+  // registers)
+  if ((XP > 0 || KIND == kRhoTanh) && form == 0 && nq == 7) {
     const float(*R7)[8] = SCVT_RULE_TABLE_F(7);
 #pragma unroll
     for (int q = 0; q < 7; q++) tiny(R7[q]);

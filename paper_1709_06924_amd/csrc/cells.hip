@@ -89,7 +89,7 @@ __device__ inline void store_edge(const EvalOut& o, int64_t i, int k, V3 v0, V3 
 // certify to the fallback clipper.
 template <int GS, int CAP, int ROWS>
 struct CandLds {
-  double px[CAP], py[CAP], pz[CAP], dx[CAP], dy[CAP], dz[CAP], nrm[CAP];
+  double px[CAP], py[CAP], pz[CAP], dx[CAP], dy[CAP], dz[CAP], nrm[CAP], zd[CAP];
   int32_t idx[CAP];
   int32_t rowoff[ROWS + 1];
   int32_t rowstart[ROWS];
@@ -187,6 +187,7 @@ __device__ int gather(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, const Window
       L.dy[slot] = d.y;
       L.dz[slot] = d.z;
       L.nrm[slot] = sqrt_fast(dot(d, d));
+      L.zd[slot] = dot(z, d);
       L.idx[slot] = en.idx;
     }
     kept += __popcll(m);
@@ -211,7 +212,7 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
   static_assert(PER * GS == CAP && PER >= 1 && PER <= 2, "one or two candidates per lane");
   const V3 z = valid ? V3{a.Z[3 * i], a.Z[3 * i + 1], a.Z[3 * i + 2]} : V3{0.0, 0.0, 1.0};
   const int f = home_face(z);
-  const CandView S = {L.px, L.py, L.pz, L.dx, L.dy, L.dz, L.nrm};
+  const CandView S = {L.px, L.py, L.pz, L.dx, L.dy, L.dz, L.nrm, L.zd};
   const double Rg = valid ? a.out.R[i] : 0.0;
   double rt = Rg > 0.0 ? 2.3 * Rg : a.r_default;
   double r_small = 0.0;  // largest radius found too small
@@ -235,10 +236,16 @@ __device__ int build_cell(const CellArgs& a, CandLds<GS, CAP, ROWS>& L, bool val
     }
     EdgeRes er[PER];
     bool anydeg = false, anyunb = false;
+    double nm = 0.0;  // the largest |d_l| of the cell's candidates
+    for (int k = 0; k < PER; k++) {
+      const int j = G.gl + k * GS;
+      if (go && j < ns) nm = fmax(nm, L.nrm[j]);
+    }
+    nm = group_max<GS>(nm);
     for (int k = 0; k < PER; k++) {
       const int j = G.gl + k * GS;
       er[k] = EdgeRes{kEdgeNone, -1, -1};
-      if (go && j < ns) er[k] = edge_on_bisector(j, ns, z, S);
+      if (go && j < ns) er[k] = edge_on_bisector(j, ns, z, S, nm);
       anydeg |= er[k].status == kEdgeDegenerate;
       anyunb |= er[k].status == kEdgeUnbounded;
     }
@@ -730,16 +737,17 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
             const V3 A = V3{G[e][ka][0], G[e][ka][1], G[e][ka][2]};
             const V3 B = V3{G[e][kb][0], G[e][kb][1], G[e][kb][2]};
             const V3 C = V3{G[e][kc][0], G[e][kc][1], G[e][kc][2]};
-            if (MIXED && xmode)
+            if (MIXED && xmode) {
               quad_leaf_mixed<KIND, POLY2 ? 2 : 1>(A, B, C, z, cf, Df, ar.rho, acc, ar.quad_rule);
-            else if (POLY2 && xmode)
+            } else if (POLY2 && xmode) {
               quad_tri_poly2(A, B, C, z, ar.rho, rp[0], rp[POLY2 ? 1 : 0], acc, ar.quad_rule);
-            else if (POLY && xmode)
+            } else if (POLY && xmode) {
               quad_tri_poly<true>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
-            else if (POLY && use_poly)
+            } else if (POLY && use_poly) {
               quad_tri_poly<false>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
-            else
+            } else {
               quad_item<KIND, MIXED>(ar, A, B, C, z, cf, Df, tab, acc);
+            }
           }
         }
         wave_sync();  // the next chunk or cell rewrites the grids

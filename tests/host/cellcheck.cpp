@@ -24,7 +24,7 @@ extern "C" {
 int hc_cells(int64_t n, const double* Z, const double* rad, int32_t* status, int32_t* deg,
              int32_t* nbr, double* verts, double* Rout, int cap) {
   if (cap < 1 || cap > 64) return -1;
-  std::vector<double> px(64), py(64), pz(64), dx(64), dy(64), dz(64), nr(64);
+  std::vector<double> px(64), py(64), pz(64), dx(64), dy(64), dz(64), nr(64), zd(64);
   std::vector<int> idx(64);
   for (int64_t i = 0; i < n; i++) {
     V3 z = V3{Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
@@ -38,6 +38,7 @@ int hc_cells(int64_t n, const double* Z, const double* rad, int32_t* status, int
         px[ns] = p.x; py[ns] = p.y; pz[ns] = p.z;
         dx[ns] = d.x; dy[ns] = d.y; dz[ns] = d.z;
         nr[ns] = sqrt(dot(d, d));
+        zd[ns] = dot(z, d);
         idx[ns] = (int)j;
         ns++;
       }
@@ -49,11 +50,14 @@ int hc_cells(int64_t n, const double* Z, const double* rad, int32_t* status, int
       Rout[i] = (double)total;
       continue;
     }
-    CandView S = {px.data(), py.data(), pz.data(), dx.data(), dy.data(), dz.data(), nr.data()};
+    CandView S = {px.data(), py.data(), pz.data(), dx.data(), dy.data(), dz.data(), nr.data(),
+                  zd.data()};
+    double nm = 0.0;
+    for (int l = 0; l < ns; l++) nm = fmax(nm, nr[l]);
     std::vector<EdgeRes> er(ns);
     int st = 0;
     for (int l = 0; l < ns; l++) {
-      er[l] = edge_on_bisector(l, ns, z, S);
+      er[l] = edge_on_bisector(l, ns, z, S, nm);
       if (er[l].status == kEdgeDegenerate) st = 1;
       if (er[l].status == kEdgeUnbounded && st == 0) st = 2;
     }

@@ -41,7 +41,7 @@ def test_calibration_library_exports_its_header():
     text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "scvt_calib.h")).read(),
                   flags=re.S)
     names = sorted(set(re.findall(r"\b(scvt_[a-z_]+)\s*\(", text)))
-    assert names == ["scvt_calib_count", "scvt_calib_valu"]
+    assert names == ["scvt_calib_count", "scvt_calib_math", "scvt_calib_valu"]
     lib = ctypes.CDLL(build.CALIB_LIB)
     for name in names:
         assert hasattr(lib, name), name
