@@ -486,7 +486,7 @@ def main():
         if args.config == "C5":
             line["cpu_baseline"] = cpu_baseline_sampled(cfg, Z0)
         else:
-            iters = {"C1": 20, "C2": 2, "C3": 1}[args.config]
+            iters = {"C1": 100, "C2": 2, "C3": 1}[args.config]  # C1: the whole solve
             line["cpu_baseline"] = cpu_baseline(cfg, Z0, iters)
     print(json.dumps(line), flush=True)
 

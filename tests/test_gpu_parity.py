@@ -232,6 +232,28 @@ def test_first_step_is_lloyd_and_trajectory(scvt):
     assert max(dev) < 1e-9
 
 
+def test_c1_full_solve_matches_oracle(scvt):
+    """The small workload solved as specified (n = 2,562, rho = 1, M = 7, 100
+    iterations or max |l| < 1e-10) by scvt_solve and by the oracle: the same
+    stopping iteration, energies to 1e-10 and generators within 1e-8 at the
+    end (the two trajectories take the same line-search decisions; their
+    per-evaluation parity of 1e-12 accumulates over the iterations)."""
+    n = 2562
+    d = {"kind": "const"}
+    Z0 = I.uniform_sphere(n, 1)
+    S = scvt.Solver(Z0, d, m_hist=7)
+    O = oracle.Solver(Z0, d, m_hist=7)
+    info = S.solve(100, 1e-10)
+    O.solve(100, 1e-10)
+    dz = np.max(np.abs(S.generators() - O.Z))
+    print("C1 solve: %d iterations (oracle %d), F %.15e (oracle %.15e), step %.3e, max |dz| %.2e"
+          % (info["iter"], O.iter, info["F"], O.cur.F, info["step_inf"], dz), flush=True)
+    assert info["iter"] == O.iter
+    assert info["converged"] == (O.cur.step_inf < 1e-10)
+    assert abs(info["F"] - O.cur.F) <= 1e-10 * O.cur.F
+    assert dz < 1e-8
+
+
 def test_m0_is_lloyd_iteration(scvt):
     n = 1500
     d = I.density_x3()
