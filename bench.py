@@ -381,8 +381,9 @@ def main():
         print(json.dumps(valu_rates()))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
-              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (its work would "
+              "shard by cells, with halo exchange and one small allreduce per LBFGS pass); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.serving_requests is None:
