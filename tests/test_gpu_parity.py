@@ -311,6 +311,54 @@ def test_run_to_run_bitwise(scvt):
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
 
 
+def two_bump_mass(d):
+    """Total mass of a sum of chord tanh bumps by linearity: 4 pi gamma plus,
+    per bump (axially symmetric about its own centre), 2 pi amp_k times the
+    1-D integral of its logistic against sin(theta)."""
+    from scipy import integrate
+    M = 4 * math.pi * d["gamma"]
+    for k in range(len(d["xc"])):
+        a, b, amp = d["alpha"][k], d["beta"][k], d["amp"][k]
+        f = lambda t: amp * 0.5 * (math.tanh((b - 2 * math.sin(t / 2)) / a) + 1) * math.sin(t)
+        M += 2 * math.pi * integrate.quad(f, 0, math.pi, epsabs=0, epsrel=1e-13, limit=400)[0]
+    return M
+
+
+def test_two_centre_full_size_sampled(scvt):
+    """n = 4,194,304 with the two-centre density (the large workload, whose
+    cells take both bumps' expansions in x): total mass against the per-bump
+    1-D integrals, Euler count, and sampled cells -- half of them in the
+    second bump -- against the oracle's neighbourhood-only cells, at the
+    random start and after 10 iterations."""
+    cfg = I.CONFIGS["C5"]
+    n, d = cfg["n"], cfg["density"]
+    S = scvt.Solver(I.uniform_sphere(n, cfg["seed"]), d, m_hist=cfg["m_hist"], keep_cells=True)
+    M = two_bump_mass(d)
+    h = math.sqrt(4 * math.pi / n)
+    rng = np.random.default_rng(1)
+    x1 = np.array(d["xc"][1])
+    for it in (0, 10):
+        for _ in range(it):
+            info = S.step()
+        Z = S.generators()
+        F, m, cen, e = S.energy()
+        mu = S.vector("mu")
+        nbr, deg = S.neighbours()
+        print("two-centre n=%d after %d iterations: F %.10e, mass error %.2e"
+              % (n, it, F, abs(m.sum() - M) / M), flush=True)
+        assert deg.sum() == 6 * n - 12
+        assert abs(m.sum() - M) / M < 1e-10
+        near2 = np.where(np.linalg.norm(Z - x1, axis=1) < 0.5)[0]
+        sample = np.concatenate([rng.choice(n, 24, replace=False), rng.choice(near2, 24, replace=False)])
+        for i in sample:
+            nb, vv, om, omu, oe = oracle.local_cell(Z, i, d, 8 * h)
+            assert set(nb) == set(nbr[i][:deg[i]].tolist())
+            assert abs(m[i] - om) <= RTOL * om
+            assert np.linalg.norm(mu[i] - omu) <= RTOL * np.linalg.norm(omu)
+            assert abs(e[i] - oe) <= RTOL * oe
+    S.close()
+
+
 def test_full_size_sampled(scvt):
     """n = 1,048,576 with the 16x tanh density, in the configuration the
     benchmark times: totals against 1-D quadrature, Euler counts, symmetric
