@@ -261,7 +261,7 @@ SCVT_HD EdgeRes edge_on_bisector(int j, int ns, V3 z, const CandView& S, double 
   const V3 dj = S.d(j), pj = S.p(j);
   const double nj = S.nrm[j];
   const V3 wj = cross(z, dj);
-  const double cj = S.zd[j] / dot(dj, dj);
+  const double cj = div_fast(S.zd[j], dot(dj, dj));  // ~1 ulp: inside the bound below
   const double ebj = kDetBound * nj;  // |sg_l| error bound / |d_l|
   const double Sb = 1.01 * nj * nm, Nb = 0.5 * nm * (nm + nj) + 16.0 * kU * nm;
   const double B = 1.1 * (2.0 * (16.0 * kU * nm * Sb + Nb * kDetBound * nj * nm) + 4.0 * kU * Nb * Sb);
