@@ -145,6 +145,16 @@ typedef struct {
                            and that pass to the 64-lane one, last evaluation */
 } scvt_info;
 
+/* The per-iteration records: a handle keeps the last SCVT_RECORD_RING of
+ * them -- the initial evaluation's (iter 0) and one after every iteration, as
+ * scvt_step would return them (status SCVT_OK) -- the columns of the paper's
+ * iteration histories (section 4: F and |grad F| against iterations).  out:
+ * host array of max records (caller-owned), filled oldest first with the last
+ * min(max, kept) records; *count (optional) receives how many.  Errors:
+ * SCVT_E_INVALID (NULL handle, max < 0, or out NULL with max > 0). */
+#define SCVT_RECORD_RING 4096
+int scvt_get_records(scvt_handle* h, int64_t max, scvt_info* out, int64_t* count);
+
 /* Fill *cfg with defaults for n generators (section 4's settings: M = 7,
  * ten energy evaluations per line search): FP64, rho = 1,
  * 2 subdivision levels, 10 evaluations per line search, c1 = 1e-4,

@@ -47,7 +47,8 @@ def build(verbose=False, jobs=4):
     if failed:
         raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + \
+          ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     tmp = CALIB_LIB + ".tmp%d" % os.getpid()

@@ -3,6 +3,7 @@
 // search with projection, history ring).
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -78,6 +79,10 @@ struct scvt_handle {
   // current state
   double F = 0, step_inf = 0, gnorm2 = 0, min_mz = 0, alpha = 0;
   int64_t iter = 0, n_evals = 0, n_fb = 0, n_deg = 0, n_lloyd_fallback = 0, n_wide[2] = {0, 0};
+  // the last SCVT_RECORD_RING per-iteration records (the initial
+  // evaluation's and one after every iteration), a ring once full
+  std::vector<scvt_info> records;
+  int64_t rec_total = 0;
   // evaluation results of the last trial
   double tF = 0, tstep = 0, tg2 = 0, tmz = 0;
   int64_t tfb = 0, tdeg = 0, twide[2] = {0, 0};
@@ -128,6 +133,28 @@ constexpr int kPinWords = kPinCtr + 4;  // doubles of one evaluation's copy
 enum : int { kPartPass = 0, kPartPush = 2, kPartEval = 5, kPartTotal = 9 };
 
 int hip_err(hipError_t e) { return e == hipSuccess ? SCVT_OK : SCVT_E_HIP; }
+
+// a roctx range over a scope (visible to rocprofv3 --marker-trace; the
+// calls cost a few nanoseconds when no tool is attached)
+struct Range {
+  explicit Range(const char* what) { roctxRangePushA(what); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
+void fill_info(scvt_handle* h, scvt_info* info, int status);
+
+// the state after an evaluation or iteration, into the record ring
+void record(scvt_handle* h) {
+  scvt_info r;
+  fill_info(h, &r, SCVT_OK);
+  if ((int64_t)h->records.size() < SCVT_RECORD_RING)
+    h->records.push_back(r);
+  else
+    h->records[(size_t)(h->rec_total % SCVT_RECORD_RING)] = r;
+  h->rec_total++;
+}
 #define HIPCK(x)                          \
   do {                                    \
     hipError_t _e = (x);                  \
@@ -369,6 +396,7 @@ int record_evaluation(scvt_handle* h, const double* Zsrc, EvalSet& s) {
 // pair is launched behind the evaluation, and the host waits for the
 // scalars' copy only, so the push runs while the host decides.
 int evaluate(scvt_handle* h, const double* Zsrc, EvalSet& s, bool prepush = false) {
+  Range range("scvt evaluation");  // the launches and the wait for their scalars
   hipStream_t st = h->stream;
   const bool tm = h->timing, tq = h->timing_quad;
   if (tm) HIPCK(hipEventRecord(h->ev[0], st));
@@ -715,6 +743,7 @@ const double* initial_diag(scvt_handle* h) {
 }
 
 int direction(scvt_handle* h, double* gq) {
+  Range range("scvt direction");
   const double* hv = initial_diag(h);
   if (!hv) return SCVT_E_HIP;
   return h->M <= kHmax ? direction_fused(h, hv, gq) : direction_passes(h, hv, gq);
@@ -922,6 +951,7 @@ int lloyd_step(scvt_handle* h) {
   adopt_trial_scalars(h);
   h->alpha = 1.0;
   h->iter++;
+  record(h);
   return SCVT_OK;
 }
 
@@ -988,6 +1018,7 @@ int quasi_newton_step(scvt_handle* h) {
   adopt_trial_scalars(h);
   h->alpha = alpha;
   h->iter++;
+  record(h);
   return SCVT_OK;
 }
 
@@ -1220,6 +1251,7 @@ int batch_accept(scvt_handle* h, double alpha, Round& next) {
   adopt_trial_scalars(h);
   h->alpha = alpha;
   h->iter++;
+  record(h);
   h->bstate = kBIter;
   return batch_status(h);
 }
@@ -1250,6 +1282,7 @@ int batch_finish(scvt_handle* h, Round& next) {
     case kBEval0:
       h->n_evals = 1;
       adopt_trial_scalars(h);
+      record(h);
       h->bstate = kBIter;
       return batch_status(h);
     case kBIter: {
@@ -1379,7 +1412,10 @@ int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt
   if (!rc) {
     rc = evaluate(h, h->Z, h->cur);
     h->n_evals = 1;
-    if (!rc) adopt_trial_scalars(h);
+    if (!rc) {
+      adopt_trial_scalars(h);
+      record(h);
+    }
   }
   if (rc) {
     destroy(h);
@@ -1389,8 +1425,22 @@ int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt
   return SCVT_OK;
 }
 
+int scvt_get_records(scvt_handle* h, int64_t max, scvt_info* out, int64_t* count) {
+  if (!h || max < 0 || (max > 0 && !out)) return SCVT_E_INVALID;
+  const int64_t kept = (int64_t)h->records.size();
+  const int64_t m = max < kept ? max : kept;
+  // the last m records, oldest first: record k of the run sits at k mod ring
+  for (int64_t t = 0; t < m; t++) {
+    const int64_t k = h->rec_total - m + t;
+    out[t] = h->records[(size_t)(k % SCVT_RECORD_RING)];
+  }
+  if (count) *count = m;
+  return SCVT_OK;
+}
+
 int scvt_step(scvt_handle* h, scvt_info* info) {
   if (!h) return SCVT_E_INVALID;
+  Range range("scvt_step");
   int rc = settle(h);
   if (!rc) rc = do_step(h, false);
   fill_info(h, info, rc);
@@ -1399,6 +1449,7 @@ int scvt_step(scvt_handle* h, scvt_info* info) {
 
 int scvt_solve(scvt_handle* h, int64_t max_iter, double tol, scvt_info* info) {
   if (!h) return SCVT_E_INVALID;
+  Range range("scvt_solve");
   int rc = SCVT_OK;
   while (!(h->step_inf < tol) && h->iter < max_iter) {
     rc = do_step(h, true);
@@ -1414,6 +1465,7 @@ int scvt_solve(scvt_handle* h, int64_t max_iter, double tol, scvt_info* info) {
 int scvt_solve_rel(scvt_handle* h, int64_t max_iter, double step_tol, double grad_rel_tol,
                    double f_rel_tol, scvt_info* info) {
   if (!h) return SCVT_E_INVALID;
+  Range range("scvt_solve_rel");
   const bool qn = h->cfg.method != SCVT_METHOD_LLOYD;
   int rc = SCVT_OK;
   bool done = false;

@@ -20,6 +20,7 @@
 // granularity of one evaluation.  A request's blocks compute exactly what
 // its own single launches would, so its result does not depend on the mix.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <string.h>
 
 #include <chrono>
@@ -172,7 +173,9 @@ void driver(scvt_server* s) {
     next.clear();
     std::vector<int> plan_rc(s->active.size(), SCVT_OK);
     for (size_t k = 0; k < s->active.size(); k++) plan_rc[k] = batch_plan(s->active[k]->h, round);
+    roctxRangePushA("scvt serving round");  // planning is host work; this is the round itself
     const hipError_t e = round_run(round, s->rb, s->stream);
+    roctxRangePop();
     round.clear();
     std::vector<Request*> keep, done;
     std::vector<int> codes;

@@ -24,6 +24,7 @@ KIND = {"const": 0, "tanh": 1, "x3": 2, "x16": 3}
 KERNEL_CELLS, KERNEL_FALLBACK, KERNEL_GRID, KERNEL_LBFGS, KERNEL_EVAL, KERNEL_QUAD = 0, 1, 2, 3, 4, 5
 KERNEL_CELLS_WIDE = 6
 REFINE_NOALLOC_MAX_N = 655362  # scvt.h SCVT_REFINE_NOALLOC_MAX_N
+RECORD_RING = 4096  # scvt.h SCVT_RECORD_RING
 VMAX = 32
 
 
@@ -65,6 +66,8 @@ _sig = {
     "scvt_config_init": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_int64]),
     "scvt_create": (ctypes.c_int, [ctypes.POINTER(Config), _vp, ctypes.c_int, ctypes.POINTER(_H)]),
     "scvt_step": (ctypes.c_int, [_H, ctypes.POINTER(Info)]),
+    "scvt_get_records": (ctypes.c_int, [_H, ctypes.c_int64, ctypes.POINTER(Info),
+                                        ctypes.POINTER(ctypes.c_int64)]),
     "scvt_solve": (ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(Info)]),
     "scvt_solve_rel": (ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.POINTER(Info)]),
@@ -253,6 +256,15 @@ class Solver:
     def step(self):
         _check(_lib.scvt_step(self.h, ctypes.byref(self.info)), "scvt_step")
         return self.info.as_dict()
+
+    def records(self, max_records=RECORD_RING):
+        """The last per-iteration records (the initial evaluation's and one
+        after every iteration, at most RECORD_RING), oldest first, as dicts."""
+        buf = (Info * max_records)()
+        cnt = ctypes.c_int64()
+        _check(_lib.scvt_get_records(self.h, int(max_records), buf, ctypes.byref(cnt)),
+               "scvt_get_records")
+        return [buf[k].as_dict() for k in range(cnt.value)]
 
     def solve(self, max_iter, tol):
         rc = _check(_lib.scvt_solve(self.h, int(max_iter), float(tol), ctypes.byref(self.info)),

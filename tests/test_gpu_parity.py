@@ -254,6 +254,35 @@ def test_c1_full_solve_matches_oracle(scvt):
     assert dz < 1e-8
 
 
+def test_iteration_records(scvt):
+    """The per-iteration record ring: the initial evaluation's record and one
+    per iteration, the energies on the oracle's trajectory (1e-10), F
+    decreasing; after more iterations than the ring holds (Lloyd's method,
+    which never fails), the last SCVT_RECORD_RING of them, oldest first."""
+    n = 2562
+    d = {"kind": "const"}
+    Z0 = I.uniform_sphere(n, 1)
+    S = scvt.Solver(Z0, d, m_hist=7)
+    O = oracle.Solver(S.generators(), d, m_hist=7)
+    S.solve(30, 0.0)
+    for _ in range(30):
+        O.step()
+    rec = S.records()
+    assert [r["iter"] for r in rec] == list(range(31))
+    F = np.array([r["F"] for r in rec])
+    assert np.all(np.diff(F) < 0)
+    assert np.max(np.abs(F - np.array(O.history_F)) / F) <= 1e-10
+    assert rec[-1]["n_evals"] == S.info.n_evals and rec[-1]["F"] == S.info.F
+    assert len(S.records(5)) == 5 and S.records(5)[-1]["iter"] == 30
+    S.close()
+    L = scvt.Solver(I.uniform_sphere(300, 2), d, method="lloyd")
+    L.solve(scvt.RECORD_RING + 100, 0.0)
+    rec = L.records()
+    assert len(rec) == scvt.RECORD_RING
+    assert [r["iter"] for r in rec] == list(range(101, scvt.RECORD_RING + 101))
+    L.close()
+
+
 def test_m0_is_lloyd_iteration(scvt):
     n = 1500
     d = I.density_x3()
