@@ -1300,48 +1300,62 @@ struct Window {
 // sin(theta) = st: z sits at angle phi_z = atan(c_z) about the other face
 // axis, at radius rho = sqrt(n^2 + w^2) from it, so the planes must be at
 // phi_z -+ delta with sin(delta) = st / rho; tan(phi_z -+ delta) in closed form.
-SCVT_HD void coord_bounds(double cz, double rho, double st, double& lo, double& hi) {
-  double s = div_fast(st, rho);
-  if (s >= 1.0) {
-    lo = -1e300;
-    hi = 1e300;
+// FP32: the bounds only choose the window's columns (the radius the window
+// certifies is computed from the columns taken, below).
+SCVT_HD void coord_bounds(float cz, float rho, float st, float& lo, float& hi) {
+  const float s = st * rcpf(rho);
+  if (!(s < 1.0f)) {
+    lo = -1e30f;
+    hi = 1e30f;
     return;
   }
-  double t = div_fast(s, sqrt_fast(1.0 - s * s));  // tan(delta)
-  double dl = 1.0 + cz * t, dh = 1.0 - cz * t;
-  lo = dl > 0.0 ? div_fast(cz - t, dl) : -1e300;
-  hi = dh > 0.0 ? div_fast(cz + t, dh) : 1e300;
+  const float t = s * rsqf(fmaxf(1.0f - s * s, 1e-30f));  // tan(delta)
+  const float dl = fmaf(cz, t, 1.0f), dh = fmaf(-cz, t, 1.0f);
+  lo = dl > 0.0f ? (cz - t) * rcpf(dl) : -1e30f;
+  hi = dh > 0.0f ? (cz + t) * rcpf(dh) : 1e30f;
 }
 
-// sine of the angular distance from z (depth n, coordinate w) to the plane
-// c = cc through the face's other axis, signed positive on z's side (sgn)
+// A lower bound on the sine of the angular distance from z (depth n,
+// coordinate w) to the plane c = cc through the face's other axis, signed
+// positive on z's side (sgn): the offset in FP64, 1/sqrt(1 + cc^2) from the
+// FP32 estimate (within a few 1e-7) lowered by 4e-6.
 SCVT_HD double plane_sine(double n, double w, double cc, double sgn) {
-  return sgn * (w - cc * n) * rsq_pos(1.0 + cc * cc);
+  const float q = (float)fma(cc, cc, 1.0);
+  return sgn * (w - cc * n) * (double)(rsqf(q) * (1.0f - 4e-6f));
 }
 
-// Smallest window around z (face f = home face) that covers the chord
-// radius rt (clamped to the grid and to at most maxw cells a side), and the
-// certified radius D of the window actually chosen: the distance from z to
-// the nearest window side, or to the face's horizon (points behind the face
-// are not in its grid).
+// Window around z (face f = home face) that covers the chord radius rt
+// (clamped to the grid and to at most maxw cells a side), and the radius D
+// that the window actually chosen certifies: every generator within chord D
+// of z is stored in its cells.  D is the least sine of the angular distance
+// from z to a window side or to the face's horizon (points behind the face
+// are not in its grid): a chord is never shorter than the sine of its angle,
+// 2 sin(a/2) >= sin a.  The columns are chosen in FP32, widened by 1% of a
+// cell so that the window covers rt despite the rounding; z's own cell is
+// found in FP64 as the binning finds it.
 SCVT_HD Window make_window(const GridP& g, V3 z, int f, double rt, int maxw) {
   double n, u, v;
   face_local(z, f, n, u, v);
   const double ni = rcp_fast(n);
   const double uz = u * ni, vz = v * ni;
-  double r = rt > 2.0 ? 2.0 : rt;
-  double st = r * sqrt_fast(fmax(0.0, 1.0 - 0.25 * r * r));  // sin of the angular radius
-  if (rt >= 1.4142135623730951) st = 1.0;                   // beyond 90 degrees: everything
-  double ulo, uhi, vlo, vhi;
-  coord_bounds(uz, sqrt_fast(n * n + u * u), st, ulo, uhi);
-  coord_bounds(vz, sqrt_fast(n * n + v * v), st, vlo, vhi);
   int ca = (int)floor((uz + g.U) * g.inv_du), cb = (int)floor((vz + g.U) * g.inv_du);
   ca = ca < 0 ? 0 : (ca >= g.W ? g.W - 1 : ca);
   cb = cb < 0 ? 0 : (cb >= g.W ? g.W - 1 : cb);
+  const float r = rt > 2.0 ? 2.0f : (float)rt;
+  const float q = fmaxf(1.0f - 0.25f * r * r, 1e-30f);
+  float st = r * q * rsqf(q);                 // sin of the angular radius
+  if (rt >= 1.4142135623730951) st = 1.0f;   // beyond 90 degrees: everything
+  const float nf = (float)n, uf = (float)u, vf = (float)v;
+  const float nif = rcpf(nf);
+  float ulo, uhi, vlo, vhi;
+  const float ru = fmaf(nf, nf, uf * uf), rv = fmaf(nf, nf, vf * vf);
+  coord_bounds(uf * nif, ru * rsqf(ru), st, ulo, uhi);
+  coord_bounds(vf * nif, rv * rsqf(rv), st, vlo, vhi);
   const int half_max = (maxw - 1) / 2;
-  auto col = [&](double c, int centre, int dir) {
-    double x = floor((c + g.U) * g.inv_du);
-    double lim = (double)(centre + dir * half_max);
+  const float sc = (float)g.inv_du, of = (float)(g.U * g.inv_du);
+  auto col = [&](float c, int centre, int dir) {
+    const float x = floorf(fmaf(c, sc, of) + (float)dir * 0.01f);
+    const float lim = (float)(centre + dir * half_max);
     if (dir < 0) return x < lim ? (int)lim : (int)x;
     return x > lim ? (int)lim : (int)x;
   };
@@ -1368,16 +1382,8 @@ SCVT_HD Window make_window(const GridP& g, V3 z, int f, double rt, int maxw) {
   w.ia_hi = ia_hi;
   w.ib_lo = ib_lo;
   w.ib_hi = ib_hi;
-  if (sm <= 0.0) {
-    w.D = 0.0;
-  } else {
-    sm = fmin(sm, 1.0);
-    // chord of the angle asin(sm): 2 sin(asin(sm)/2), cancellation-free;
-    // shrunk to cover points binned across a side by rounding
-    double D = sm * sqrt_fast(div_fast(2.0, 1.0 + sqrt_fast(1.0 - sm * sm)));
-    w.D = D * (1.0 - 1e-10) - 1e-14;
-    if (w.D < 0.0) w.D = 0.0;
-  }
+  // shrunk to cover points binned across a side by rounding
+  w.D = sm > 0.0 ? fmax(fmin(sm, 1.0) * (1.0 - 1e-10) - 1e-14, 0.0) : 0.0;
   return w;
 }
 
