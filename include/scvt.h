@@ -52,7 +52,8 @@ extern "C" {
 #define SCVT_NOT_CONVERGED 1   /* scvt_solve stopped at max_iter */
 #define SCVT_PENDING 2         /* serving: request not finished yet */
 #define SCVT_E_INVALID -1      /* bad argument (n < 4, non-finite input, ...) */
-#define SCVT_E_OOM -2          /* device allocation failed or over budget */
+#define SCVT_E_OOM -2          /* device allocation failed or over budget, or a host
+                                  allocation failed (no C++ exception leaves a call) */
 #define SCVT_E_DEGENERATE -3   /* duplicate or zero generators */
 #define SCVT_E_CERT -4         /* a Voronoi cell could not be built */
 #define SCVT_E_LINESEARCH -5   /* no sufficient decrease along the direction, and the
@@ -323,7 +324,9 @@ int scvt_footprint(const scvt_config* cfg, size_t* bytes);
  * allocated per request.  The server uses the device current at creation;
  * stream NULL: its own.  Submit copies z0 (host, n x 3); cfg->hip_stream is
  * ignored.  Errors: SCVT_E_INVALID, SCVT_E_OOM (footprint above the whole
- * budget, or the budget cannot be allocated). */
+ * budget, or the budget cannot be allocated; also a failed host allocation:
+ * in the driver thread it fails every admitted and waiting request and
+ * every later submission with SCVT_E_OOM). */
 typedef struct scvt_server scvt_server;
 int scvt_server_create(size_t hbm_budget, int max_slots, void* stream, scvt_server** out);
 int scvt_server_submit(scvt_server* s, const scvt_config* cfg, const double* z0, double tol,

@@ -1333,7 +1333,7 @@ void batch_destroy(scvt_handle* h) { destroy(h); }
 // =============================================================== C ABI ====
 extern "C" {
 
-int scvt_footprint(const scvt_config* cfg, size_t* bytes) {
+int scvt_footprint(const scvt_config* cfg, size_t* bytes) try {
   if (!bytes) return SCVT_E_INVALID;
   int rc = validate(cfg);
   if (rc) return rc;
@@ -1348,9 +1348,11 @@ int scvt_footprint(const scvt_config* cfg, size_t* bytes) {
   *bytes = h->dry_bytes;
   delete h;
   return rc;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_config_init(scvt_config* c, int64_t n) {
+int scvt_config_init(scvt_config* c, int64_t n) try {
   if (!c) return SCVT_E_INVALID;
   memset(c, 0, sizeof(*c));
   c->n = n;
@@ -1369,9 +1371,11 @@ int scvt_config_init(scvt_config* c, int64_t n) {
   c->keep_cells = 0;
   c->hip_stream = nullptr;
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt_handle** out) {
+int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt_handle** out) try {
   if (!out) return SCVT_E_INVALID;
   *out = nullptr;
   int rc = validate(cfg);
@@ -1423,9 +1427,11 @@ int scvt_create(const scvt_config* cfg, const double* z0, int z0_on_device, scvt
   }
   *out = h;
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_get_records(scvt_handle* h, int64_t max, scvt_info* out, int64_t* count) {
+int scvt_get_records(scvt_handle* h, int64_t max, scvt_info* out, int64_t* count) try {
   if (!h || max < 0 || (max > 0 && !out)) return SCVT_E_INVALID;
   const int64_t kept = (int64_t)h->records.size();
   const int64_t m = max < kept ? max : kept;
@@ -1436,18 +1442,22 @@ int scvt_get_records(scvt_handle* h, int64_t max, scvt_info* out, int64_t* count
   }
   if (count) *count = m;
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_step(scvt_handle* h, scvt_info* info) {
+int scvt_step(scvt_handle* h, scvt_info* info) try {
   if (!h) return SCVT_E_INVALID;
   Range range("scvt_step");
   int rc = settle(h);
   if (!rc) rc = do_step(h, false);
   fill_info(h, info, rc);
   return rc;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_solve(scvt_handle* h, int64_t max_iter, double tol, scvt_info* info) {
+int scvt_solve(scvt_handle* h, int64_t max_iter, double tol, scvt_info* info) try {
   if (!h) return SCVT_E_INVALID;
   Range range("scvt_solve");
   int rc = SCVT_OK;
@@ -1460,10 +1470,12 @@ int scvt_solve(scvt_handle* h, int64_t max_iter, double tol, scvt_info* info) {
   if (!rc && !(h->step_inf < tol)) rc = SCVT_NOT_CONVERGED;
   fill_info(h, info, rc);
   return rc;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
 int scvt_solve_rel(scvt_handle* h, int64_t max_iter, double step_tol, double grad_rel_tol,
-                   double f_rel_tol, scvt_info* info) {
+                   double f_rel_tol, scvt_info* info) try {
   if (!h) return SCVT_E_INVALID;
   Range range("scvt_solve_rel");
   const bool qn = h->cfg.method != SCVT_METHOD_LLOYD;
@@ -1487,10 +1499,12 @@ int scvt_solve_rel(scvt_handle* h, int64_t max_iter, double step_tol, double gra
   if (!rc && !done) rc = SCVT_NOT_CONVERGED;
   fill_info(h, info, rc);
   return rc;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
 int scvt_energy(scvt_handle* h, double* F, double* mass, double* centroid, double* e_cell,
-                int on_dev) {
+                int on_dev) try {
   if (!h) return SCVT_E_INVALID;
   const int64_t n = h->n;
   const hipMemcpyKind k = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1507,17 +1521,21 @@ int scvt_energy(scvt_handle* h, double* F, double* mass, double* centroid, doubl
   }
   HIPCK(hipStreamSynchronize(h->stream));
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_get_generators(scvt_handle* h, double* z, int on_dev) {
+int scvt_get_generators(scvt_handle* h, double* z, int on_dev) try {
   if (!h || !z) return SCVT_E_INVALID;
   HIPCK(hipMemcpyAsync(z, h->Z, 3 * h->n * sizeof(double),
                        on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
   HIPCK(hipStreamSynchronize(h->stream));
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_get_vectors(scvt_handle* h, int which, double* out, int on_dev) {
+int scvt_get_vectors(scvt_handle* h, int which, double* out, int on_dev) try {
   if (!h || !out) return SCVT_E_INVALID;
   const int64_t n = h->n;
   const double* src = nullptr;
@@ -1535,9 +1553,11 @@ int scvt_get_vectors(scvt_handle* h, int which, double* out, int on_dev) {
                        on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
   HIPCK(hipStreamSynchronize(h->stream));
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_direction(scvt_handle* h, double* out, int on_dev, double* gq) {
+int scvt_direction(scvt_handle* h, double* out, int on_dev, double* gq) try {
   if (!h) return SCVT_E_INVALID;
   double v = 0.0;
   int rc = settle(h);
@@ -1546,15 +1566,19 @@ int scvt_direction(scvt_handle* h, double* out, int on_dev, double* gq) {
   if (gq) *gq = v;
   if (out) return scvt_get_vectors(h, 4, out, on_dev);
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_num_generators(scvt_handle* h, int64_t* n) {
+int scvt_num_generators(scvt_handle* h, int64_t* n) try {
   if (!h || !n) return SCVT_E_INVALID;
   *n = h->n;
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_refine(scvt_handle* h, double* z_out, int on_device, int64_t* n_out) {
+int scvt_refine(scvt_handle* h, double* z_out, int on_device, int64_t* n_out) try {
   if (!h || !n_out) return SCVT_E_INVALID;
   const int64_t n = h->n;
   hipStream_t st = h->stream;
@@ -1585,6 +1609,8 @@ int scvt_refine(scvt_handle* h, double* z_out, int on_device, int64_t* n_out) {
     HIPCK(hipMemcpyAsync(z_out, dst, 3 * m * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
 }  // extern "C"
@@ -1648,7 +1674,7 @@ int scratch_ptr(void** out) {
 
 extern "C" {
 
-int scvt_refine_noalloc(scvt_handle* h, double* z_out, int64_t* n_out) {
+int scvt_refine_noalloc(scvt_handle* h, double* z_out, int64_t* n_out) try {
   if (!h || !n_out) return SCVT_E_INVALID;
   const int64_t n = h->n;
   if (n > SCVT_REFINE_NOALLOC_MAX_N) return SCVT_E_OOM;
@@ -1679,9 +1705,11 @@ int scvt_refine_noalloc(scvt_handle* h, double* z_out, int64_t* n_out) {
   HIPCK(launch_refine_emit(h->Z, h->trial.deg, nbr, off, n, z_out, st));
   HIPCK(hipStreamSynchronize(st));
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_mesh(scvt_handle* h, int32_t* tri, int64_t* ntri, double* cell_q, double* tri_q) {
+int scvt_mesh(scvt_handle* h, int32_t* tri, int64_t* ntri, double* cell_q, double* tri_q) try {
   if (!h || !ntri) return SCVT_E_INVALID;
   const int64_t n = h->n;
   hipStream_t st = h->stream;
@@ -1721,10 +1749,12 @@ int scvt_mesh(scvt_handle* h, int32_t* tri, int64_t* ntri, double* cell_q, doubl
   }
   HIPCK(hipStreamSynchronize(st));
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
 int scvt_multilevel(const scvt_config* cfg0, const double* z0, int z0_on_device, int levels,
-                    int64_t max_iter, double tol, scvt_info* infos, scvt_handle** out) {
+                    int64_t max_iter, double tol, scvt_info* infos, scvt_handle** out) try {
   if (!cfg0 || !z0 || !out || levels < 0 || max_iter < 0) return SCVT_E_INVALID;
   *out = nullptr;
   scvt_handle* h = nullptr;
@@ -1764,10 +1794,12 @@ int scvt_multilevel(const scvt_config* cfg0, const double* z0, int z0_on_device,
   }
   *out = h;
   return rc;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
 int scvt_get_cells(scvt_handle* h, int32_t max_deg, int32_t* nbr, int32_t* deg, double* verts,
-                   uint8_t* flags) {
+                   uint8_t* flags) try {
   if (!h || max_deg != kVmax) return SCVT_E_INVALID;
   const int64_t n = h->n;
   hipStream_t st = h->stream;
@@ -1781,11 +1813,13 @@ int scvt_get_cells(scvt_handle* h, int32_t max_deg, int32_t* nbr, int32_t* deg, 
   if (flags) HIPCK(hipMemcpyAsync(flags, h->cur.flags, n, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
 // state blob: int64 header[8] = {magic, n, M, ring size, iter, n_evals, 0, 0},
 // double alpha, then Z (3n), then per ring entry oldest first: r, s (3n), y (3n)
-int scvt_get_state(scvt_handle* h, void* buf, size_t* bytes) {
+int scvt_get_state(scvt_handle* h, void* buf, size_t* bytes) try {
   if (!h || !bytes) return SCVT_E_INVALID;
   const int rs = settle(h);
   if (rs) return rs;
@@ -1824,9 +1858,11 @@ int scvt_get_state(scvt_handle* h, void* buf, size_t* bytes) {
   }
   *bytes = need;
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes) {
+int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes) try {
   if (!h || !buf || bytes < 8 * sizeof(int64_t) + sizeof(double)) return SCVT_E_INVALID;
   const char* p = (const char*)buf;
   int64_t hdr[8];
@@ -1869,21 +1905,27 @@ int scvt_set_state(scvt_handle* h, const void* buf, size_t bytes) {
   if (!rc) rc = hist_rebuild(h);
   if (!rc && h->cfg.method == SCVT_METHOD_LBFGS) rc = yy_rebuild(h);
   return rc;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_set_timing(scvt_handle* h, int enable) {
+int scvt_set_timing(scvt_handle* h, int enable) try {
   if (!h) return SCVT_E_INVALID;
   h->timing = enable == 1;
   h->timing_quad = enable == 1 || enable == 2;
   for (auto& t : h->timers) t = Timer{};
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_kernel_time(scvt_handle* h, int kernel, double* total_ms, int64_t* launches) {
+int scvt_kernel_time(scvt_handle* h, int kernel, double* total_ms, int64_t* launches) try {
   if (!h || kernel < 0 || kernel >= kTimers) return SCVT_E_INVALID;
   if (total_ms) *total_ms = h->timers[kernel].ms;
   if (launches) *launches = h->timers[kernel].launches;
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
 void scvt_destroy(scvt_handle* h) { destroy(h); }

@@ -78,6 +78,7 @@ struct scvt_server {
   bool own_stream = false;
   int64_t next_id = 1;
   bool stop = false;
+  bool dead = false;  // the driver thread ended on a failed host allocation
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request*> queue;
@@ -140,7 +141,7 @@ std::vector<Request*> admit(scvt_server* s) {
   return in;
 }
 
-void driver(scvt_server* s) {
+void driver_loop(scvt_server* s) {
   hipSetDevice(s->device);
   Round round, next;  // next: launches one round leaves for the following one
   for (;;) {
@@ -199,6 +200,31 @@ void driver(scvt_server* s) {
   }
 }
 
+// The driver thread: a failed host allocation ends it, and every request
+// still admitted or waiting then fails with SCVT_E_OOM (as do later
+// submissions) instead of the exception ending the process.
+void driver(scvt_server* s) {
+  try {
+    driver_loop(s);
+  } catch (...) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (Request* r : s->active) {
+      if (r->h) batch_destroy(r->h);
+      r->h = nullptr;
+      r->rc = r->info.status = SCVT_E_OOM;
+      r->state = kFailed;
+    }
+    for (Request* r : s->queue) {
+      r->rc = r->info.status = SCVT_E_OOM;
+      r->state = kFailed;
+    }
+    s->active.clear();
+    s->queue.clear();
+    s->dead = true;
+    s->cv.notify_all();
+  }
+}
+
 void free_server(scvt_server* s) {
   if (s->rb.dev) hipFree(s->rb.dev);
   if (s->rb.host) hipHostFree(s->rb.host);
@@ -214,7 +240,7 @@ void free_server(scvt_server* s) {
 
 extern "C" {
 
-int scvt_server_create(size_t hbm_budget, int max_slots, void* stream, scvt_server** out) {
+int scvt_server_create(size_t hbm_budget, int max_slots, void* stream, scvt_server** out) try {
   if (!out || max_slots < 1 || max_slots > 64 || hbm_budget < 256) return SCVT_E_INVALID;
   *out = nullptr;
   scvt_server* s = new (std::nothrow) scvt_server();
@@ -262,10 +288,12 @@ int scvt_server_create(size_t hbm_budget, int max_slots, void* stream, scvt_serv
   }
   *out = s;
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
 int scvt_server_submit(scvt_server* s, const scvt_config* cfg, const double* z0, double tol,
-                       int64_t max_iter, int64_t* req_id) {
+                       int64_t max_iter, int64_t* req_id) try {
   if (!s || !cfg || !z0 || !req_id || cfg->n < 4 || max_iter < 0) return SCVT_E_INVALID;
   if (cfg->method != SCVT_METHOD_PLBFGS || cfg->m_hist > 16) return SCVT_E_INVALID;
   scvt_config c = *cfg;
@@ -289,17 +317,29 @@ int scvt_server_submit(scvt_server* s, const scvt_config* cfg, const double* z0,
   r->t_submit = now_s();
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->dead) {
+      delete r;
+      return SCVT_E_OOM;
+    }
     r->id = s->next_id++;
-    s->reqs[r->id] = r;
-    s->queue.push_back(r);
+    try {
+      s->reqs[r->id] = r;
+      s->queue.push_back(r);
+    } catch (...) {
+      s->reqs.erase(r->id);
+      delete r;
+      return SCVT_E_OOM;
+    }
   }
   s->cv.notify_all();
   *req_id = r->id;
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
 int scvt_server_poll(scvt_server* s, int64_t req_id, double* z_out, scvt_info* info,
-                     double* times) {
+                     double* times) try {
   if (!s) return SCVT_E_INVALID;
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->reqs.find(req_id);
@@ -314,9 +354,11 @@ int scvt_server_poll(scvt_server* s, int64_t req_id, double* z_out, scvt_info* i
   }
   if (z_out && r->state == kDone) memcpy(z_out, r->z.data(), r->z.size() * sizeof(double));
   return r->rc;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_server_release(scvt_server* s, int64_t req_id) {
+int scvt_server_release(scvt_server* s, int64_t req_id) try {
   if (!s) return SCVT_E_INVALID;
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->reqs.find(req_id);
@@ -326,18 +368,22 @@ int scvt_server_release(scvt_server* s, int64_t req_id) {
   delete r;
   s->reqs.erase(it);
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-int scvt_server_stats(scvt_server* s, int64_t* waiting, int64_t* running, size_t* bytes_used) {
+int scvt_server_stats(scvt_server* s, int64_t* waiting, int64_t* running, size_t* bytes_used) try {
   if (!s) return SCVT_E_INVALID;
   std::lock_guard<std::mutex> lk(s->mu);
   if (waiting) *waiting = (int64_t)s->queue.size();
   if (running) *running = s->running;
   if (bytes_used) *bytes_used = s->used;
   return SCVT_OK;
+} catch (...) {  // host allocation (no exception leaves the C ABI)
+  return SCVT_E_OOM;
 }
 
-void scvt_server_destroy(scvt_server* s) {
+void scvt_server_destroy(scvt_server* s) try {
   if (!s) return;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -351,6 +397,7 @@ void scvt_server_destroy(scvt_server* s) {
   hipStreamSynchronize(s->stream);
   for (auto& kv : s->reqs) delete kv.second;
   free_server(s);
+} catch (...) {
 }
 
 }  // extern "C"
