@@ -83,11 +83,29 @@ SCVT_HD double rsq_pos(double x) {
 // on the sphere (x <= 1): when e = 1 - x (exact) is at most 1e-4 -- leaves
 // below ~0.03 rad across, all but very coarse meshes -- the binomial series
 // 1 + e/2 + 3e^2/8 + 5e^3/16 (next term below 3e-17), otherwise rsq_pos.
-SCVT_HD double rsq_near1(double x) {
+SCVT_HD double rsq_series(double x) {
   const double e = 1.0 - x;
-  if (fabs(e) <= 1e-4) return fma(e, fma(e, fma3(e, 0.3125, 0.375), 0.5), 1.0);
+  return fma(e, fma(e, fma3(e, 0.3125, 0.375), 0.5), 1.0);
+}
+SCVT_HD double rsq_near1(double x) {
+  if (fabs(1.0 - x) <= 1e-4) return rsq_series(x);
   return rsq_pos(x);
 }
+// NEAR1: the caller knows |1 - |p|^2| <= 1e-4 at every point of the leaf, so
+// every point takes the series (the same bits as rsq_near1 would give).
+template <bool NEAR1>
+SCVT_HD double rsq_leaf(double x) {
+  if constexpr (NEAR1) return rsq_series(x);
+  else return rsq_near1(x);
+}
+
+// Whether every quadrature point of a cell of radius R (all its vertices
+// within chord R of the generator) is near the sphere in the sense of
+// rsq_near1: a point p = sum l_k V_k of a flat triangle with unit corners
+// has 1 - |p|^2 = sum_{j<k} l_j l_k |V_j - V_k|^2 <= max |V_j - V_k|^2 / 3,
+// and the corners of every leaf lie within 2R of each other, so
+// 1 - |p|^2 <= 4 R^2 / 3 (and >= minus a few roundings of the corners' norms).
+SCVT_HD bool cell_near1(double R) { return R <= 8e-3; }  // 4 R^2 / 3 <= 8.6e-5
 
 // a / b and sqrt(x) where the geometry needs neither IEEE rounding nor
 // special values: the window and grid arithmetic (whose certified radius is
@@ -601,7 +619,10 @@ struct Acc5 {
 // Radial projection of the flat triangle (A,B,C) onto the sphere has Jacobian
 // (n.p)/|p|^3 with n.p constant = det(A,B,C)/(2 area), so
 //   int_sph f dsigma = det(A,B,C)/2 * sum_q w_q f(p_q/|p_q|) / |p_q|^3.
-template <int KIND>
+// The first moment is accumulated relative to the generator, as int rho (y - z)
+// (mu = m z + that, formed once per cell), which takes one product fewer per
+// point than int rho y and keeps the sum small.
+template <int KIND, bool NEAR1 = false>
 SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
                         const double* tab = SCVT_EXP2_TAB, int nq = 7) {
   const double(*R)[4] = SCVT_RULE_TABLE(nq);
@@ -616,17 +637,16 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
     const double l1 = R[q][1], l2 = R[q][2];
     const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
                     fma(l2, CA.z, fma(l1, BA.z, A.z))};
-    double ri = rsq_near1(dot(p, p));
-    V3 y = ri * p;
-    double jac = ri * ri * ri;
-    double wt = hd * R[q][3] * jac * rho_kind<KIND>(D, y, tab);
-    V3 dy = y - z;
+    const double ri = rsq_leaf<NEAR1>(dot(p, p));
+    const V3 y = ri * p;
+    const double jac = ri * ri * ri;
+    const double wt = hd * R[q][3] * jac * rho_kind<KIND>(D, y, tab);
+    const V3 dy = V3{fma(ri, p.x, -z.x), fma(ri, p.y, -z.y), fma(ri, p.z, -z.z)};  // y - z
     acc.m += wt;
-    const double wr = wt * ri;  // first moment: wt y = (wt ri) p
-    acc.mx += wr * p.x;
-    acc.my += wr * p.y;
-    acc.mz += wr * p.z;
-    acc.e += wt * dot(dy, dy);
+    acc.mx = fma(wt, dy.x, acc.mx);
+    acc.my = fma(wt, dy.y, acc.my);
+    acc.mz = fma(wt, dy.z, acc.mz);
+    acc.e = fma(wt, dot(dy, dy), acc.e);
   }
 }
 
@@ -763,9 +783,20 @@ SCVT_HD bool polyx_qualifies(const DensityP& D, V3 z, double r, int b) {
   return delta <= D.polyx_tab[b][j].lim;
 }
 
+// The x table's entry of bump b taken at the cell of z: as x(y) = cc - y.x_c,
+// its offset off = cc - x* becomes off - z.x_c = x(z) - x*, and the argument
+// at a point y is x(y) - x* = (x(z) - x*) - (y - z).x_c, the cell's part
+// formed once.
+SCVT_HD RhoPoly polyx_at(const RhoPoly& P, const DensityP& D, V3 z, int b) {
+  RhoPoly Q = P;
+  Q.off = P.off - dot(z, V3{D.xc[b][0], D.xc[b][1], D.xc[b][2]});
+  return Q;
+}
+
 // quad_tri_k with rho from the cell's polynomial (single chord tanh bump)
-// (X: the expansion in x, else in t)
-template <bool X>
+// (X: the expansion in x, its entry taken at the cell by polyx_at; else the
+// one in t)
+template <bool X, bool NEAR1 = false>
 SCVT_HD void quad_tri_poly(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const RhoPoly& P,
                            Acc5& acc, int nq = 7) {
   const double(*R)[4] = SCVT_RULE_TABLE(nq);
@@ -777,10 +808,11 @@ SCVT_HD void quad_tri_poly(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const RhoP
     const double l1 = R[q][1], l2 = R[q][2];
     const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
                     fma(l2, CA.z, fma(l1, BA.z, A.z))};
-    const double ri = rsq_near1(dot(p, p));
+    const double ri = rsq_leaf<NEAR1>(dot(p, p));
+    const V3 dy = V3{fma(ri, p.x, -z.x), fma(ri, p.y, -z.y), fma(ri, p.z, -z.z)};  // y - z
     double dl;
     if constexpr (X) {
-      dl = fma(-ri, dot(p, xc), P.off);
+      dl = fma(-dy.z, xc.z, fma(-dy.y, xc.y, fma(-dy.x, xc.x, P.off)));
     } else {
       const double h = sqrt_nr_pos(fmax(fma(-ri, dot(p, xc), D.cc[0]), 1e-300));
       dl = fma(h, D.Kt[0], P.off);
@@ -788,20 +820,19 @@ SCVT_HD void quad_tri_poly(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const RhoP
     double rho = P.c[kPolyDeg];
 #pragma unroll
     for (int n = kPolyDeg - 1; n >= 0; n--) rho = fma(rho, dl, P.c[n]);
-    const V3 y = ri * p;
     const double wt = hd * R[q][3] * (ri * ri * ri) * rho;
-    const V3 dy = y - z;
     acc.m += wt;
-    const double wr = wt * ri;
-    acc.mx += wr * p.x;
-    acc.my += wr * p.y;
-    acc.mz += wr * p.z;
-    acc.e += wt * dot(dy, dy);
+    acc.mx = fma(wt, dy.x, acc.mx);
+    acc.my = fma(wt, dy.y, acc.my);
+    acc.mz = fma(wt, dy.z, acc.mz);
+    acc.e = fma(wt, dot(dy, dy), acc.e);
   }
 }
 
 // quad_tri_k for two chord tanh bumps, rho = P0(x_0 - x_0*) + P1(x_1 - x_1*)
-// from both bumps' x tables (the fan inside both entries' radii)
+// from both bumps' x tables (the fan inside both entries' radii; both
+// entries taken at the cell by polyx_at)
+template <bool NEAR1 = false>
 SCVT_HD void quad_tri_poly2(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const RhoPoly& P0,
                             const RhoPoly& P1, Acc5& acc, int nq = 7) {
   const double(*R)[4] = SCVT_RULE_TABLE(nq);
@@ -814,23 +845,22 @@ SCVT_HD void quad_tri_poly2(V3 A, V3 B, V3 C, V3 z, const DensityP& D, const Rho
     const double l1 = R[q][1], l2 = R[q][2];
     const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
                     fma(l2, CA.z, fma(l1, BA.z, A.z))};
-    const double ri = rsq_near1(dot(p, p));
-    const double d0 = fma(-ri, dot(p, x0), P0.off), d1 = fma(-ri, dot(p, x1), P1.off);
+    const double ri = rsq_leaf<NEAR1>(dot(p, p));
+    const V3 dy = V3{fma(ri, p.x, -z.x), fma(ri, p.y, -z.y), fma(ri, p.z, -z.z)};  // y - z
+    const double d0 = fma(-dy.z, x0.z, fma(-dy.y, x0.y, fma(-dy.x, x0.x, P0.off)));
+    const double d1 = fma(-dy.z, x1.z, fma(-dy.y, x1.y, fma(-dy.x, x1.x, P1.off)));
     double r0 = P0.c[kPolyDeg], r1 = P1.c[kPolyDeg];
 #pragma unroll
     for (int n = kPolyDeg - 1; n >= 0; n--) {
       r0 = fma(r0, d0, P0.c[n]);
       r1 = fma(r1, d1, P1.c[n]);
     }
-    const V3 y = ri * p;
     const double wt = hd * R[q][3] * (ri * ri * ri) * (r0 + r1);
-    const V3 dy = y - z;
     acc.m += wt;
-    const double wr = wt * ri;
-    acc.mx += wr * p.x;
-    acc.my += wr * p.y;
-    acc.mz += wr * p.z;
-    acc.e += wt * dot(dy, dy);
+    acc.mx = fma(wt, dy.x, acc.mx);
+    acc.my = fma(wt, dy.y, acc.my);
+    acc.mz = fma(wt, dy.z, acc.mz);
+    acc.e = fma(wt, dot(dy, dy), acc.e);
   }
 }
 
@@ -1031,7 +1061,8 @@ SCVT_HD CellF cell_f32(const DensityP& D, V3 z, const double* tab = SCVT_EXP2_TA
 // degree-9 truncation below 1e-15, |D|/r <= ~0.025 of the series' radius r)
 // the degree-5 truncation is below ~1e-8 relative, and no special function
 // is left at the point.
-// the expansions in x of the first nb bumps (entries P[0..nb-1])
+// the expansions in x of the first nb bumps (entries P[0..nb-1], taken at
+// the cell by polyx_at)
 SCVT_HD CellF cell_f32_poly(const DensityP& D, const RhoPoly* P, int nb, V3 z) {
   CellF c{};
   c.zf = to_f3(z);
@@ -1039,7 +1070,7 @@ SCVT_HD CellF cell_f32_poly(const DensityP& D, const RhoPoly* P, int nb, V3 z) {
   for (int b = 0; b < nb; b++) {
     const V3 xc = V3{D.xc[b][0], D.xc[b][1], D.xc[b][2]};
     for (int k = 0; k < 6; k++) c.k[10 * b + k] = (float)P[b].c[k];
-    c.k[10 * b + 6] = (float)(P[b].off - dot(z, xc));
+    c.k[10 * b + 6] = (float)P[b].off;  // x(z) - x*: the entry taken at the cell (polyx_at)
     c.set3(10 * b + 7, to_f3(xc));
   }
   return c;

@@ -547,8 +547,7 @@ __global__ __launch_bounds__(64) void k_fallback(P p) {
 // k_eval_reduce).
 template <bool MIXED>
 __device__ inline void cell_epilogue(const EvalOut& o, int64_t i, V3 z, Acc5 acc) {
-  V3 mu = V3{acc.mx, acc.my, acc.mz};
-  if (MIXED) mu = acc.m * z + mu;  // first moment from int rho (y - z)
+  const V3 mu = acc.m * z + V3{acc.mx, acc.my, acc.mz};  // first moment from int rho (y - z)
   o.m[i] = acc.m;
   o.e[i] = acc.e;
   o.mu[3 * i] = mu.x;
@@ -564,11 +563,14 @@ __device__ inline double half_sum(double v) {
 
 template <int KIND, bool MIXED>
 __device__ inline void quad_item(const CellArgs& a, V3 A, V3 B, V3 C, V3 z, const CellF& cf,
-                                 const DensityF& Df, const double* tab, Acc5& acc) {
+                                 const DensityF& Df, const double* tab, Acc5& acc,
+                                 bool near1 = false) {
   if (MIXED)
     quad_leaf_mixed<KIND>(A, B, C, z, cf, Df, a.rho, acc, a.quad_rule);
+  else if (near1)
+    quad_tri_k<KIND, true>(A, B, C, z, a.rho, acc, tab, a.quad_rule);
   else
-    quad_tri_k<KIND>(A, B, C, z, a.rho, acc, tab, a.quad_rule);
+    quad_tri_k<KIND, false>(A, B, C, z, a.rho, acc, tab, a.quad_rule);
 }
 
 // Two subdivision levels (the configured rule): the 32 lanes of a half-wave
@@ -687,7 +689,14 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
       rp[0] = xmode ? ar.rho.polyx_tab[0][polyx_index(ar.rho, z, &xz, 0)]
                     : ar.rho.poly_tab[poly_index(ar.rho, z)];
       if (POLY2) rp[POLY2 ? 1 : 0] = ar.rho.polyx_tab[1][polyx_index(ar.rho, z, &xz, 1)];
+      if (xmode) {
+        rp[0] = polyx_at(rp[0], ar.rho, z, 0);
+        if (POLY2) rp[POLY2 ? 1 : 0] = polyx_at(rp[POLY2 ? 1 : 0], ar.rho, z, 1);
+      }
     }
+    // every point of the cell near the sphere: the FP64 paths skip the
+    // per-point test of the reciprocal square root's series (same bits)
+    const bool near1 = !MIXED && has && cell_near1(o.R[i]);
     CellF cf{};
     if (MIXED) cf = xmode ? cell_f32_poly(ar.rho, rp, POLY2 ? 2 : 1, z) : cell_f32<KIND>(ar.rho, z, tab);
     if (lv == 2) {
@@ -740,13 +749,19 @@ __global__ __launch_bounds__(256, 4) void k_quad(P p) {
             if (MIXED && xmode) {
               quad_leaf_mixed<KIND, POLY2 ? 2 : 1>(A, B, C, z, cf, Df, ar.rho, acc, ar.quad_rule);
             } else if (POLY2 && xmode) {
-              quad_tri_poly2(A, B, C, z, ar.rho, rp[0], rp[POLY2 ? 1 : 0], acc, ar.quad_rule);
+              if (near1)
+                quad_tri_poly2<true>(A, B, C, z, ar.rho, rp[0], rp[POLY2 ? 1 : 0], acc, ar.quad_rule);
+              else
+                quad_tri_poly2<false>(A, B, C, z, ar.rho, rp[0], rp[POLY2 ? 1 : 0], acc, ar.quad_rule);
             } else if (POLY && xmode) {
-              quad_tri_poly<true>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
+              if (near1)
+                quad_tri_poly<true, true>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
+              else
+                quad_tri_poly<true, false>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
             } else if (POLY && use_poly) {
               quad_tri_poly<false>(A, B, C, z, ar.rho, rp[0], acc, ar.quad_rule);
             } else {
-              quad_item<KIND, MIXED>(ar, A, B, C, z, cf, Df, tab, acc);
+              quad_item<KIND, MIXED>(ar, A, B, C, z, cf, Df, tab, acc, near1);
             }
           }
         }

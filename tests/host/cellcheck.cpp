@@ -142,10 +142,10 @@ int hc_quad(const double* z3, int E, const double* verts, const DensityP* D, int
     subtriangle(A, B, C, s, levels);
     quad_tri(A, B, C, z, Dp, acc, nq);
   }
-  out5[0] = acc.m;
-  out5[1] = acc.mx;
-  out5[2] = acc.my;
-  out5[3] = acc.mz;
+  out5[0] = acc.m;  // mu = m z + int rho (y - z), as the kernels' epilogue
+  out5[1] = acc.m * z.x + acc.mx;
+  out5[2] = acc.m * z.y + acc.my;
+  out5[3] = acc.m * z.z + acc.mz;
   out5[4] = acc.e;
   return 0;
 }
@@ -185,6 +185,8 @@ int hc_quad_poly(const double* z3, int E, const double* verts, const DensityP* D
   else if (force == 1) mode = tq ? 1 : 0;
   else mode = xq ? 2 : (tq ? 1 : 0);
   if (mode == 0) return 0;
+  if (mode == 2)  // the x entries taken at the cell, as the kernel takes them
+    for (int b = 0; b < nb; b++) PX[b] = polyx_at(PX[b], Dp, z, b);
   const RhoPoly P = mode == 2 ? PX[0] : poly_entry(Dp, poly_index(Dp, z));
   const int per = 1 << (2 * levels);
   for (int t = 0; t < E * per; t++) {
@@ -199,10 +201,10 @@ int hc_quad_poly(const double* z3, int E, const double* verts, const DensityP* D
     else
       quad_tri_poly<false>(A, B, C, z, Dp, P, acc, nq);
   }
-  out5[0] = acc.m;
-  out5[1] = acc.mx;
-  out5[2] = acc.my;
-  out5[3] = acc.mz;
+  out5[0] = acc.m;  // mu = m z + int rho (y - z)
+  out5[1] = acc.m * z.x + acc.mx;
+  out5[2] = acc.m * z.y + acc.my;
+  out5[3] = acc.m * z.z + acc.mz;
   out5[4] = acc.e;
   return mode;
 }
@@ -231,6 +233,7 @@ int hc_quad_mixed_poly(const double* z3, int E, const double* verts, const Densi
     const int64_t jx = polyx_index(Dp, z, &xz, b);
     PX[b] = polyx_entry(Dp, jx, b);
     if (fabs(xz - (double)jx * kPolyDx) + r * (sqrt(2.0 * xz) + 0.5 * r) > PX[b].lim) return 0;
+    PX[b] = polyx_at(PX[b], Dp, z, b);
   }
   const CellF cf = cell_f32_poly(Dp, PX, nb, z);
   const DensityF Df = density_f32(Dp);
