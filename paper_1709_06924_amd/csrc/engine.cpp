@@ -1086,8 +1086,7 @@ int alloc_device_state(scvt_handle* h) {
   ALLOC(h->fb_list, n);
   ALLOC(h->tier_list[0], n);
   ALLOC(h->tier_list[1], n);
-  ALLOC(h->grid.cnt_tot, nc + 1);
-  ALLOC(h->grid.cnt_home, nc + 1);
+  ALLOC(h->grid.cnt2, 2 * (nc + 1));
   ALLOC(h->grid.start_tot, nc + 1);
   ALLOC(h->grid.start_home, nc + 1);
   ALLOC(h->grid.cell3, 3 * n);
@@ -1127,8 +1126,7 @@ int init_device_state(scvt_handle* h) {
       if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return SCVT_E_HIP;
   }
   hipStream_t st = h->stream;
-  HIPCK(launch_fill_i32(h->grid.cnt_tot, 0, nc + 1, st));
-  HIPCK(launch_fill_i32(h->grid.cnt_home, 0, nc + 1, st));
+  HIPCK(launch_fill_i32(h->grid.cnt2, 0, 2 * (nc + 1), st));
   HIPCK(launch_fill_i32(h->grid.overflow, 0, 1, st));
   HIPCK(launch_iota(h->grid.order, n, st));  // first build: generator order
   HIPCK(launch_fill_i32((int32_t*)h->R, 0, 2 * n, st));

@@ -143,6 +143,13 @@ __device__ inline void generator_cells(const double* __restrict__ Z, int64_t i, 
   for (; k < 3; k++) out[k] = -1;
 }
 
+// a cell's two counts as one 64-bit word (entries in the low half, home
+// entries in the high half; neither exceeds 2^31, so no carry or borrow
+// crosses the halves)
+__device__ inline unsigned long long pack2(int32_t tot, int32_t home) {
+  return (unsigned long long)(uint32_t)tot | ((unsigned long long)(uint32_t)home << 32);
+}
+
 template <class P>
 __global__ __launch_bounds__(kBucketBlock) void k_grid_count(P p) {
   if (p.idle()) return;
@@ -151,8 +158,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_grid_count(P p) {
   const int64_t n = a.n;
   const GridP& g = a.gb.g;
   const int32_t* __restrict__ order_prev = a.gb.order_prev;
-  int32_t* __restrict__ cnt_tot = a.gb.cnt_tot;
-  int32_t* __restrict__ cnt_home = a.gb.cnt_home;
+  unsigned long long* __restrict__ cnt2 = reinterpret_cast<unsigned long long*>(a.gb.cnt2);
   int32_t* __restrict__ cell3 = a.gb.cell3;
   int32_t* __restrict__ clear = a.clear;
   __shared__ BucketLds L;
@@ -175,8 +181,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_grid_count(P p) {
   for (int s = threadIdx.x; s < kHashSize; s += blockDim.x) {
     const int32_t c = L.key[s];
     if (c < 0) continue;
-    atomicAdd(&cnt_tot[c], L.ntot[s]);
-    if (L.nhome[s]) atomicAdd(&cnt_home[c], L.nhome[s]);
+    atomicAdd(&cnt2[c], pack2(L.ntot[s], L.nhome[s]));
   }
 }
 
@@ -214,11 +219,12 @@ __global__ void k_scan_tiles(P p) {
   __shared__ int sh[kScanBlock];
   int64_t base = (int64_t)p.bx() * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int sa = 0, sb = 0;
+  const int64_t st = A.stride;
   for (int k = 0; k < kScanItems; k++) {
     int64_t t = base + k;
     if (t < m) {
-      sa += a[t];
-      sb += b[t];
+      sa += a[t * st];
+      sb += b[t * st];
     }
   }
   int tot;
@@ -267,10 +273,11 @@ __global__ void k_scan_apply(P p) {
   int64_t base = (int64_t)p.bx() * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int va[kScanItems], vb[kScanItems];
   int sa = 0, sb = 0;
+  const int64_t st = A.stride;
   for (int k = 0; k < kScanItems; k++) {
     int64_t t = base + k;
-    va[k] = t < m ? a[t] : 0;
-    vb[k] = t < m ? b[t] : 0;
+    va[k] = t < m ? a[t * st] : 0;
+    vb[k] = t < m ? b[t * st] : 0;
     sa += va[k];
     sb += vb[k];
   }
@@ -298,8 +305,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_grid_scatter(P p) {
   const int32_t* __restrict__ cell3 = a.gb.cell3;
   const int32_t* __restrict__ start_tot = a.gb.start_tot;
   const int32_t* __restrict__ start_home = a.gb.start_home;
-  int32_t* cnt_tot = a.gb.cnt_tot;
-  int32_t* cnt_home = a.gb.cnt_home;
+  unsigned long long* cnt2 = reinterpret_cast<unsigned long long*>(a.gb.cnt2);
   Entry* __restrict__ entries = a.gb.entries;
   const int64_t cap = a.gb.cap_entries;
   int32_t* __restrict__ order = a.gb.order;
@@ -328,8 +334,10 @@ __global__ __launch_bounds__(kBucketBlock) void k_grid_scatter(P p) {
   for (int s = threadIdx.x; s < kHashSize; s += blockDim.x) {
     const int32_t cs = L.key[s];
     if (cs < 0) continue;
-    L.btot[s] = atomicSub(&cnt_tot[cs], L.ntot[s]) - L.ntot[s];
-    if (L.nhome[s]) L.bhome[s] = atomicSub(&cnt_home[cs], L.nhome[s]) - L.nhome[s];
+    const unsigned long long v = pack2(L.ntot[s], L.nhome[s]);
+    const unsigned long long old = atomicAdd(&cnt2[cs], 0ull - v);  // both counts down at once
+    L.btot[s] = (int32_t)(uint32_t)old - L.ntot[s];
+    L.bhome[s] = (int32_t)(uint32_t)(old >> 32) - L.nhome[s];
     L.ntot[s] = 0;  // reused as the in-block rank counters
     L.nhome[s] = 0;
   }
@@ -382,7 +390,7 @@ int64_t scan_tiles(int64_t m) { return (m + 1 + kScanTile - 1) / kScanTile; }
 hipError_t launch_scan_pair(const int32_t* a, const int32_t* b, int64_t m, int32_t* tmp,
                             int32_t* oa, int32_t* ob, hipStream_t s) {
   const int64_t ntiles = scan_tiles(m);
-  const ScanArgs sa = {a, b, m, tmp, oa, ob, ntiles};
+  const ScanArgs sa = {a, b, m, tmp, oa, ob, ntiles, 1};
   k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, s>>>(One<ScanArgs>{sa});
   k_scan_sums<<<1, kScanBlock, 0, s>>>(One<ScanArgs>{sa});
   k_scan_apply<<<(unsigned)ntiles, kScanBlock, 0, s>>>(One<ScanArgs>{sa});
@@ -395,8 +403,8 @@ int bucket_grid(int64_t n) { return (int)((n + kBucketBlock - 1) / kBucketBlock)
 
 ScanArgs grid_scan_args(const GridBufs& gb) {
   const int64_t m = gb.g.ncells;
-  return ScanArgs{gb.cnt_tot, gb.cnt_home, m, gb.scan_tmp, gb.start_tot, gb.start_home,
-                  scan_tiles(m)};
+  return ScanArgs{gb.cnt2, gb.cnt2 + 1, m, gb.scan_tmp, gb.start_tot, gb.start_home,
+                  scan_tiles(m), 2};
 }
 
 hipError_t launch_grid_build(const double* Z, int64_t n, GridBufs& gb, int32_t* clear,

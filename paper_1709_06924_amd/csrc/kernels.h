@@ -70,8 +70,10 @@ struct EvalOut {  // per-generator results of one evaluation
 
 struct GridBufs {
   GridP g;
-  int32_t* cnt_tot;    // ncells (+1)
-  int32_t* cnt_home;   // ncells (+1)
+  // per cell the pair (entries, home entries), one 64-bit word (total in the
+  // low half), so that a block adds or takes both counts with one atomic;
+  // ncells (+1) pairs
+  int32_t* cnt2;
   int32_t* start_tot;  // ncells + 1 (exclusive scan)
   int32_t* start_home; // ncells + 1
   int32_t* cell3;      // n x 3 cells (home, ghosts, -1) of the generator at each position of order_prev
@@ -123,11 +125,12 @@ struct GridBuildArgs {
   int32_t* clear;  // 8 ints zeroed by the first kernel, or null
 };
 struct ScanArgs {  // exclusive scans of a and b (m entries) into oa, ob
-  const int32_t *a, *b;
+  const int32_t *a, *b;  // entry t at a[t * stride], b[t * stride]
   int64_t m;
   int32_t* sums;  // tile sums (scratch)
   int32_t *oa, *ob;
   int64_t ntiles;
+  int stride;
 };
 int normalize_grid(int64_t n);
 int bucket_grid(int64_t n);
