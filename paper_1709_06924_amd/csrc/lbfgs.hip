@@ -183,9 +183,11 @@ __device__ inline double wave_sum64(double v) {
 __device__ void hist_fin(const HistFinArgs& a);
 
 // Block partials of K (<= KMAX) per-thread values: a butterfly within each
-// wave, then the four waves in order; written to out[0..K).
+// wave, then the four waves in order; value v written to out[v * stride]
+// (value-major over the grid: out = partials + block, stride = blocks, so
+// that the one-block fin reads each value's partials contiguously).
 template <int KMAX>
-__device__ inline void block_partials(const double* acc, int K, double* out) {
+__device__ inline void block_partials(const double* acc, int K, double* out, int stride) {
   __shared__ double sh[4][KMAX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -197,7 +199,7 @@ __device__ inline void block_partials(const double* acc, int K, double* out) {
   }
   __syncthreads();
   for (int v = threadIdx.x; v < K; v += blockDim.x)
-    out[v] = ((sh[0][v] + sh[1][v]) + sh[2][v]) + sh[3][v];
+    out[(size_t)v * stride] = ((sh[0][v] + sh[1][v]) + sh[2][v]) + sh[3][v];
 }
 
 // The streaming passes read VW consecutive elements per thread and step (16-
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(kRedBlock) void k_push_ext(P p) {
       }
     }
   }
-  block_partials<kHVals>(acc, 4 + 2 * c, a.partials + (size_t)p.bx() * (4 + 2 * c));
+  block_partials<kHVals>(acc, 4 + 2 * c, a.partials + p.bx(), p.gx());
 }
 
 // the same sums as k_push_ext forms for s_j . g and s_j . y (same element
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(kRedBlock) void k_multi_dot(MultiDotArgs a) {
       }
     }
   }
-  block_partials<kHmax>(acc, c, a.partials + (size_t)blockIdx.x * c);
+  block_partials<kHmax>(acc, c, a.partials + blockIdx.x, (int)gridDim.x);
 }
 
 // r = h (.) (-g - sum_k a_k y_k), newest pair first as in the backward loop;
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_q0(P p) {
         for (int e = 0; e < VW; e++) acc[j] = fma(yv[j][e], r[e], acc[j]);
       }
   }
-  if (c > 0) block_partials<kHmax>(acc, c, a.partials + (size_t)p.bx() * c);
+  if (c > 0) block_partials<kHmax>(acc, c, a.partials + p.bx(), p.gx());
 }
 
 // q = r + sum_k c_k s_k, oldest pair first as in the forward loop; partials
@@ -374,7 +376,7 @@ __global__ __launch_bounds__(kRedBlock) void k_hist_dir(P p) {
 #pragma unroll
     for (int e = 0; e < VW; e++) acc[0] = fma(g[e], q[e], acc[0]);
   }
-  block_partials<1>(acc, 1, a.partials + p.bx());
+  block_partials<1>(acc, 1, a.partials + p.bx(), p.gx());
 }
 
 // One block: sums the block partials of each value in block order (wave w
@@ -394,7 +396,7 @@ __device__ void hist_fin(const HistFinArgs& a) {
 #pragma unroll
     for (int k = 0; k < kPer; k++) {
       const int b = lane + 64 * k;
-      xs[k] = b < a.nblocks ? a.partials[(size_t)b * a.nvals + v] : 0.0;
+      xs[k] = b < a.nblocks ? a.partials[(size_t)v * a.nblocks + b] : 0.0;
     }
 #pragma unroll
     for (int w = kPer / 2; w > 0; w >>= 1)
