@@ -622,7 +622,7 @@ struct Acc5 {
 // The first moment is accumulated relative to the generator, as int rho (y - z)
 // (mu = m z + that, formed once per cell), which takes one product fewer per
 // point than int rho y and keeps the sum small.
-template <int KIND, bool NEAR1 = false>
+template <int KIND>
 SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
                         const double* tab = SCVT_EXP2_TAB, int nq = 7) {
   const double(*R)[4] = SCVT_RULE_TABLE(nq);
@@ -637,7 +637,7 @@ SCVT_HD void quad_tri_k(V3 A, V3 B, V3 C, V3 z, const DensityP& D, Acc5& acc,
     const double l1 = R[q][1], l2 = R[q][2];
     const V3 p = V3{fma(l2, CA.x, fma(l1, BA.x, A.x)), fma(l2, CA.y, fma(l1, BA.y, A.y)),
                     fma(l2, CA.z, fma(l1, BA.z, A.z))};
-    const double ri = rsq_leaf<NEAR1>(dot(p, p));
+    const double ri = rsq_near1(dot(p, p));
     const V3 y = ri * p;
     const double jac = ri * ri * ri;
     const double wt = hd * R[q][3] * jac * rho_kind<KIND>(D, y, tab);
