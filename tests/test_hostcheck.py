@@ -203,6 +203,36 @@ def test_window_certificate_covers_ball(n):
             assert np.all((ia >= alo) & (ia <= ahi) & (ib >= blo) & (ib <= bhi))
 
 
+@pytest.mark.parametrize("n", [10**6, 10**8, 10**9])
+def test_window_certificate_covers_ball_large_grids(n):
+    """The same at the grids of large n, with points sampled in a cap around
+    each z (uniform points would leave the small balls empty): the columns
+    are chosen in FP32 (at n = 10^9 the column coordinate reaches ~10^4),
+    and the certified radius, computed from the columns taken, still bounds
+    every stored point; the window also reaches the radius asked for where
+    the face allows it."""
+    GBW, dd = hc.grid(n)
+    W = GBW[2]
+    Z = I.uniform_sphere(200, 5)
+    h = math.sqrt(4 * math.pi / n)
+    reached = 0
+    for k, z in enumerate(Z):
+        for rt in (2.0 * h, 6.0 * h):
+            (f, alo, ahi, blo, bhi), D = hc.window(GBW, dd, z, rt)
+            if D <= 0:
+                continue
+            reached += D >= rt
+            X = I.cap_points(z, 1.2 * D, 400, 100 + k)
+            near = X[np.linalg.norm(X - z, axis=1) < D]
+            assert len(near) > 100
+            c = hc.cell_on_face(GBW, dd, near, f)
+            assert np.all(c >= 0)
+            loc = c - f * W * W
+            ia, ib = loc % W, loc // W
+            assert np.all((ia >= alo) & (ia <= ahi) & (ib >= blo) & (ib <= bhi))
+    assert reached >= 0.95 * 2 * len(Z), reached
+
+
 def test_home_face_inside_its_grid():
     GBW, dd = hc.grid(100000)
     X = I.uniform_sphere(50000, 3)
