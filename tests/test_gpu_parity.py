@@ -388,6 +388,46 @@ def test_two_centre_full_size_sampled(scvt):
     S.close()
 
 
+def test_16m_sampled(scvt):
+    """n = 16,777,216 (the 1M workload's density, M = 10: a grid of 9.1M
+    buckets, 1,182 per face side): total mass against 1-D quadrature, Euler
+    count, and sampled cells against the oracle's neighbourhood-only cells,
+    at the random start and after 3 iterations."""
+    from scipy import integrate
+    cfg = I.CONFIGS["C3"]
+    n, d = 1 << 24, cfg["density"]
+    S = scvt.Solver(I.uniform_sphere(n, 11), d, m_hist=cfg["m_hist"], keep_cells=True)
+    g, a, b, amp = d["gamma"], d["alpha"][0], d["beta"][0], d["amp"][0]
+    rho = lambda t: g + amp * 0.5 * (math.tanh((b - 2 * math.sin(t / 2)) / a) + 1)
+    M = 2 * math.pi * integrate.quad(lambda t: rho(t) * math.sin(t), 0, math.pi, epsabs=0,
+                                     epsrel=1e-13, limit=400)[0]
+    h = math.sqrt(4 * math.pi / n)
+    rng = np.random.default_rng(2)
+    F0 = None
+    for it in (0, 3):
+        for _ in range(it):
+            info = S.step()
+        Z = S.generators()
+        F, m, cen, e = S.energy()
+        mu = S.vector("mu")
+        nbr, deg = S.neighbours()
+        print("n=%d after %d iterations: F %.10e, mass error %.2e"
+              % (n, it, F, abs(m.sum() - M) / M), flush=True)
+        if F0 is None:
+            F0 = F
+        else:
+            assert F < F0
+        assert deg.sum() == 6 * n - 12
+        assert abs(m.sum() - M) / M < 1e-10
+        for i in rng.choice(n, 24, replace=False):
+            nb, vv, om, omu, oe = oracle.local_cell(Z, i, d, 8 * h)
+            assert set(nb) == set(nbr[i][:deg[i]].tolist())
+            assert abs(m[i] - om) <= RTOL * om
+            assert np.linalg.norm(mu[i] - omu) <= RTOL * np.linalg.norm(omu)
+            assert abs(e[i] - oe) <= RTOL * oe
+    S.close()
+
+
 def test_full_size_sampled(scvt):
     """n = 1,048,576 with the 16x tanh density, in the configuration the
     benchmark times: totals against 1-D quadrature, Euler counts, symmetric
