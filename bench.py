@@ -21,7 +21,8 @@ default the workload's: 200 for C3), --warmup W, --precision fp64|mixed|both
 (default both: `value` is the FP64 path, the "mixed" object the
 mixed-precision path),
 --no-cpu-baseline, --copy-calibration (only run a plain 256 MiB device copy,
-used to scale the profiler's FETCH_SIZE / WRITE_SIZE counters).
+used to scale the profiler's FETCH_SIZE / WRITE_SIZE counters), --copy-bandwidth
+(only time a plain 1 GiB device copy: the practical HBM rate).
 """
 import argparse
 import json
@@ -349,6 +350,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--copy-bandwidth", action="store_true",
+                    help="only time a plain 1 GiB device copy (GB/s)")
     ap.add_argument("--valu-rates", action="store_true",
                     help="only measure vector-ALU instruction rates (libscvt_calib.so)")
     ap.add_argument("--no-mixed-errors", action="store_true",
@@ -376,6 +379,28 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
+        return
+    if args.copy_bandwidth:
+        # a STREAM-like copy (torch's device copy of 1 GiB, beyond the 256 MB MALL):
+        # the practical HBM rate beside the 8 TB/s of the specification
+        import torch
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        moved = 2 * src.numel() * 8
+        print(json.dumps({"copy_bytes": src.numel() * 8, "bytes_moved_per_copy": moved,
+                          "ms_per_copy": round(ms, 4), "GB_per_s": round(moved / ms / 1e6, 1),
+                          "fraction_of_8TBps": round(moved / ms / 1e6 / PEAK_HBM_GBS, 3)}))
         return
     if args.valu_rates:
         print(json.dumps(valu_rates()))
